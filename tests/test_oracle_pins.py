@@ -1,0 +1,397 @@
+"""Pins of the FP64 CPU oracle to facts other than itself.
+
+Each test checks the oracle against something the paper or the mathematics
+fixes: exact integer arithmetic, a library routine, a closed form, a theorem
+(the rounding bound behind the threshold), brute force on tiny inputs, or a
+published test vector.  A dropped term, a wrong sign or index or a transposed
+operand in the oracle fails at least one of them.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_0806_3121_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def int_problem(m, n, k, lo=-8, hi=8, seed=7):
+    A = synth.uniform_ints(seed, synth.STREAM_A, m, k, lo, hi)
+    B = synth.uniform_ints(seed, synth.STREAM_B, k, n, lo, hi)
+    return A, B
+
+
+# ---------------------------------------------------------------- generator
+def test_splitmix64_published_vector():
+    lines = [ln for ln in open(os.path.join(GOLDEN, "splitmix64.txt")) if ln.strip() and not ln.startswith("#")]
+    seed = int(lines[0].split()[1])
+    expect = [int(x) for x in lines[1:]]
+    state, got = seed, []
+    for _ in expect:
+        state = (state + int(synth.GAMMA)) & synth.MASK64
+        got.append(synth.mix64_int(state))
+    assert got == expect
+    # the counter form used for matrices is the same sequence
+    key = 1234567
+    z = [synth.mix64_int((key + (i + 1) * int(synth.GAMMA)) & synth.MASK64) for i in range(5)]
+    assert z == expect
+
+
+def test_uniform_range_and_exactness():
+    x = synth.uniform(3, 0, 64, 64)
+    assert x.min() >= -1.0 and x.max() < 1.0
+    # every value is an integer multiple of 2^-52 (exact map)
+    assert np.all((x + 1.0) * 2.0 ** 52 == np.floor((x + 1.0) * 2.0 ** 52))
+    y = synth.uniform(3, 0, 64, 64, np.float32)
+    assert y.dtype == np.float32 and y.min() >= -1 and y.max() < 1
+
+
+# ---------------------------------------------------------------- product
+def test_gemm_integer_exact(orc):
+    # integer inputs: every partial sum is an integer < 2^53, so the FP64
+    # product must equal the exact integer product in any order
+    A, B = int_problem(37, 29, 53)
+    Cm = orc.gemm(A, B)
+    exact = A.astype(np.int64) @ B.astype(np.int64)
+    assert np.array_equal(Cm, exact.astype(np.float64))
+
+
+def test_gemm_matches_library_within_gamma_bound(orc):
+    A = synth.uniform(11, 0, 40, 300)
+    B = synth.uniform(11, 1, 300, 33)
+    Cm = orc.gemm(A, B)
+    ref = A @ B
+    g = orc.lib().orc_gamma(300.0, orc.U64)
+    bound = 2 * g * (np.abs(A) @ np.abs(B))
+    assert np.all(np.abs(Cm - ref) <= bound)
+    # and the dot entry point is the same ascending-order sum, bit for bit
+    for (i, j) in [(0, 0), (5, 17), (39, 32)]:
+        assert orc.dot(A[i], B[:, j]) == Cm[i, j]
+
+
+def test_gemm_not_transposed(orc):
+    A = np.arange(6, dtype=np.float64).reshape(2, 3)
+    B = np.arange(12, dtype=np.float64).reshape(3, 4)
+    assert np.array_equal(orc.gemm(A, B), np.array([[20, 23, 26, 29], [56, 68, 80, 92]], dtype=np.float64))
+
+
+# ---------------------------------------------------------------- encoding
+@pytest.mark.parametrize("br,bc", [(1, 1), (2, 3), (4, 1), (1, 6), (12, 6)])
+def test_encoding_block_sums_exact(orc, br, bc):
+    m, n, k = 24, 18, 10
+    A, B = int_problem(m, n, k)
+    Af, Bf = orc.encode(A, B, br, bc)
+    Ai = A.astype(np.int64)
+    Bi = B.astype(np.int64)
+    # C_C^T A: rows of block g at residue r summed over g
+    want_rows = sum(Ai[g * br:(g + 1) * br] for g in range(m // br))
+    want_cols = sum(Bi[:, h * bc:(h + 1) * bc] for h in range(n // bc))
+    assert np.array_equal(Af[:m], A) and np.array_equal(Bf[:, :n], B)
+    assert np.array_equal(Af[m:], want_rows.astype(np.float64))
+    assert np.array_equal(Bf[:, n:], want_cols.astype(np.float64))
+
+
+@pytest.mark.parametrize("br,bc", [(1, 1), (3, 2), (6, 6)])
+def test_eq_abft_gemm_consistency_exact(orc, br, bc):
+    """Eq. ABFT-GEMM: C_C^T(AB) = (C_C^T A)B, (AB)C_R = A(BC_R), and the
+    corner agrees both ways; exact for integer inputs."""
+    m, n, k = 18, 12, 30
+    A, B = int_problem(m, n, k, seed=3)
+    Af, Bf, Cf = orc.protected_product(A, B, br, bc)
+    Ci = (A.astype(np.int64) @ B.astype(np.int64))
+    assert np.array_equal(Cf[:m, :n], Ci.astype(np.float64))
+    col_sum = sum(Cf[g * br:(g + 1) * br] for g in range(m // br))   # C_C^T C_f over data rows
+    row_sum = sum(Cf[:, h * bc:(h + 1) * bc] for h in range(n // bc))
+    assert np.array_equal(col_sum, Cf[m:])          # carried row block (incl. corner)
+    assert np.array_equal(row_sum, Cf[:, n:])       # carried column block (incl. corner)
+    tc = np.zeros((br, n + bc))
+    tr = np.zeros((m + br, bc))
+    Dc, Dr, rep = orc.verify(Cf, m, n, br, bc, tc, tr)
+    assert rep.n_flag_c == 0 and rep.n_flag_r == 0
+    assert not Dc.any() and not Dr.any()
+
+
+# ---------------------------------------------------------------- thresholds
+@pytest.mark.parametrize("br,bc", [(1, 1), (16, 16), (64, 1), (128, 128)])
+def test_det_threshold_bounds_clean_residual(orc, br, bc):
+    """|D| <= tau_det on clean FP64 data is a theorem (rounding-error bound)."""
+    m = n = 128
+    k = 200
+    A = synth.uniform(5, 0, m, k)
+    B = synth.uniform(5, 1, k, n)
+    Af, Bf, Cf = orc.protected_product(A, B, br, bc)
+    tc, tr = orc.tau_det(Af, Bf, m, n, br, bc)
+    Dc, Dr, rep = orc.verify(Cf, m, n, br, bc, tc, tr)
+    assert rep.n_flag_c == 0 and rep.n_flag_r == 0
+    assert rep.max_ratio_c < 1.0 and rep.max_ratio_r < 1.0
+    assert np.all(np.abs(Dc) <= tc) and np.all(np.abs(Dr) <= tr)
+
+
+def test_norms_bound_the_tight_sum(orc):
+    """Cauchy-Schwarz: (C_C^T|A|)|B_f| <= na_abs * nb and |A_f|(|B|C_R) <= na * nb_abs,
+    with the tight sums computed by the library matmul; the norms themselves
+    match numpy's."""
+    m, n, k, br, bc = 32, 24, 50, 8, 4
+    A = synth.uniform(9, 0, m, k)
+    B = synth.uniform(9, 1, k, n)
+    Af, Bf = orc.encode(A, B, br, bc)
+    na, na_abs, nb, nb_abs = orc.norms(Af, Bf, m, n, br, bc)
+    assert np.allclose(na, np.linalg.norm(Af, axis=1), rtol=1e-14)
+    assert np.allclose(nb, np.linalg.norm(Bf, axis=0), rtol=1e-14)
+    cabsA = sum(np.abs(A[g * br:(g + 1) * br]) for g in range(m // br))
+    absBcr = sum(np.abs(B[:, h * bc:(h + 1) * bc]) for h in range(n // bc))
+    assert np.allclose(na_abs, np.linalg.norm(cabsA, axis=1), rtol=1e-14)
+    assert np.allclose(nb_abs, np.linalg.norm(absBcr, axis=0), rtol=1e-14)
+    tight_c = cabsA @ np.abs(Bf)
+    tight_r = np.abs(Af) @ absBcr
+    assert np.all(tight_c <= np.outer(na_abs, nb) * (1 + 1e-12))
+    assert np.all(tight_r <= np.outer(na, nb_abs) * (1 + 1e-12))
+
+
+def test_det_threshold_is_not_vacuous(orc):
+    """A mantissa flip in the top 12 bits of a unit-size FP64 value must exceed
+    tau_det by orders of magnitude at the paper's nb=64 scale."""
+    m = n = k = 256
+    A = synth.uniform(1, 0, m, k)
+    B = synth.uniform(1, 1, k, n)
+    Af, Bf = orc.encode(A, B, 1, 1)
+    tc, tr = orc.tau_det(Af, Bf, m, n, 1, 1)
+    assert tc.max() < 1e-6 and tr.max() < 1e-6
+    assert 2.0 ** (40 - 52) > 1e3 * max(tc.max(), tr.max())
+
+
+def test_stat_q_matches_library_gemv(orc):
+    """For br = bc = 1 the stat threshold's Q is an exact GEMV:
+    Q_c = v (B_f o B_f), v = colsum(A o A) + A_cs o A_cs, Q_r = (A_f o A_f) w."""
+    m, n, k = 40, 30, 64
+    A = synth.uniform(2, 0, m, k)
+    B = synth.uniform(2, 1, k, n)
+    Af, Bf = orc.encode(A, B, 1, 1)
+    T, lam, u = 16.0, 10.0, orc.U32
+    tc, tr = orc.tau_stat(Af, Bf, m, n, 1, 1, u_acc=u, T=T, s_store=1.0, lam=lam)
+    v = (Af ** 2).sum(axis=0)                       # includes the checksum row
+    w = (Bf ** 2).sum(axis=1)                       # includes the checksum column
+    coef = u * u / 3 * (T / 2 + 1)
+    assert np.allclose(tc[0], lam * np.sqrt(coef * (v @ Bf ** 2)), rtol=1e-12)
+    assert np.allclose(tr[:, 0], lam * np.sqrt(coef * ((Af ** 2) @ w)), rtol=1e-12)
+
+
+def test_stat_model_matches_simulated_fp32_accumulation(orc):
+    """The stat sigma (tau/lambda) predicts the spread of D when every member
+    of a relation is accumulated in binary32 with one rounding per step of
+    4 products (simulated with numpy float32); rms(D/sigma) must come out
+    near the model's ~0.6-1, not off by the sqrt(T/2) factor a dropped term
+    would cause."""
+    rng_seed = 13
+    m, n, k = 64, 48, 1024
+    A = synth.uniform(rng_seed, 0, m, k, np.float32).astype(np.float64)
+    B = synth.uniform(rng_seed, 1, k, n, np.float32).astype(np.float64)
+    Af, Bf = orc.encode(A, B, 1, 1, store_f32=True)
+    step = 4
+    T = k / step
+    # binary32 accumulation: exact block of 4 products, one rounding per step
+    prods = Af[:, None, :] * Bf.T[None, :, :]                       # (M, N, k) float64, exact
+    blocks = prods.reshape(m + 1, n + 1, k // step, step).sum(axis=3)  # exact in f64 for these sizes
+    acc = np.zeros((m + 1, n + 1), dtype=np.float32)
+    for t in range(blocks.shape[2]):
+        acc = (acc.astype(np.float64) + blocks[:, :, t]).astype(np.float32)
+    Cf = acc.astype(np.float64)
+    tc, tr = orc.tau_stat(Af, Bf, m, n, 1, 1, u_acc=orc.U32, T=T, s_store=1.0, lam=1.0)
+    Dc, Dr, _ = orc.verify(Cf, m, n, 1, 1, tc, tr)
+    z = np.concatenate([(Dc / tc).ravel(), (Dr / tr).ravel()])
+    rms = np.sqrt(np.mean(z ** 2))
+    assert 0.3 < rms < 1.5, rms
+    assert np.abs(z).max() < 6.0
+
+
+# ---------------------------------------------------------------- locate / correct (brute force)
+@pytest.mark.parametrize("m,n,k,br,bc", [(4, 4, 4, 1, 1), (4, 4, 6, 2, 2), (8, 8, 5, 4, 2), (3, 2, 4, 1, 1),
+                                         (8, 4, 3, 2, 4)])
+def test_every_element_every_bit_located_and_restored(orc, m, n, k, br, bc):
+    """Brute force: integer inputs, exact mode (tau = 0).  Every element of C_f
+    (data, carried checksums and corner) under every bit flip 40..62 is located
+    at its exact (i, j) and rebuilt bit-exactly."""
+    A, B = int_problem(m, n, k, seed=m * 100 + n)
+    Af, Bf, Cf = orc.protected_product(A, B, br, bc)
+    tc = np.zeros((br, n + bc))
+    tr = np.zeros((m + br, bc))
+    bits = Cf.view(np.uint64)
+    for i in range(m + br):
+        for j in range(n + bc):
+            for beta in range(40, 63):
+                Cx = Cf.copy()
+                Cx.view(np.uint64)[i, j] = bits[i, j] ^ np.uint64(1 << beta)
+                _, _, rep = orc.verify(Cx, m, n, br, bc, tc, tr)
+                cls, li, lj, d = orc.classify(rep, m, n, br, bc)
+                assert (li, lj) == (i, j), (i, j, beta, cls)
+                assert cls == (orc.DATA if (i < m and j < n) else orc.CHECKSUM)
+                v = orc.rebuild_value(Cx, m, n, br, bc, li, lj, d)
+                assert v == Cf[i, j]
+
+
+def test_flip_residual_equals_delta(orc):
+    """The flagged residuals equal delta = value(flipped) - value with the
+    sign rule (+ for a summand, - for a stored total)."""
+    m, n, k, br, bc = 16, 12, 20, 4, 3
+    A = synth.uniform(4, 0, m, k)
+    B = synth.uniform(4, 1, k, n)
+    Af, Bf, Cf = orc.protected_product(A, B, br, bc)
+    tc, tr = orc.tau_det(Af, Bf, m, n, br, bc)
+    for (i, j) in [(3, 5), (m + 1, 7), (9, n + 2), (m + 3, n + 1)]:
+        Cx = Cf.copy()
+        Cx.view(np.uint64)[i, j] ^= np.uint64(1 << 50)
+        delta = Cx[i, j] - Cf[i, j]
+        _, _, rep = orc.verify(Cx, m, n, br, bc, tc, tr)
+        (r, jj, dc, tcq), = rep.flags_c()
+        (ii, c, dr, trq), = rep.flags_r()
+        assert (r, jj, ii, c) == (i % br, j, i, j % bc)
+        sc = 1 if i < m else -1
+        sr = 1 if j < n else -1
+        assert abs(dc - sc * delta) <= tcq and abs(dr - sr * delta) <= trq
+
+
+def test_two_errors_are_not_miscorrected(orc):
+    m, n, k = 8, 8, 6
+    A, B = int_problem(m, n, k)
+    Af, Bf, Cf = orc.protected_product(A, B, 1, 1)
+    Cx = Cf.copy()
+    Cx[1, 2] += 3
+    Cx[5, 6] -= 2
+    _, _, rep = orc.verify(Cx, m, n, 1, 1, np.zeros((1, n + 1)), np.zeros((m + 1, 1)))
+    assert orc.classify(rep, m, n, 1, 1)[0] == orc.MULTI
+
+
+# ---------------------------------------------------------------- erasure recovery (Sec. 2.1)
+@pytest.mark.parametrize("br,bc,bh,bw", [(4, 4, 4, 4), (2, 4, 2, 4), (4, 2, 4, 2), (8, 8, 8, 8)])
+def test_every_block_position_rebuilt_exactly(orc, br, bc, bh, bw):
+    m, n, k = 16, 16, 7
+    A, B = int_problem(m, n, k, seed=br * 10 + bc)
+    Af, Bf, Cf = orc.protected_product(A, B, br, bc)
+    for use_rows in (False, True):
+        if (not use_rows and bh > br) or (use_rows and bw > bc):
+            continue
+        for i0 in range(0, m + br - bh + 1, bh):
+            for j0 in range(0, n + bc - bw + 1, bw):
+                Cx = Cf.copy()
+                Cx[i0:i0 + bh, j0:j0 + bw] = np.nan
+                assert orc.recover(Cx, m, n, br, bc, (i0, j0, bh, bw), use_rows=use_rows) == 0
+                assert np.array_equal(Cx, Cf), (i0, j0, use_rows)
+
+
+def test_recovery_formula_single_checksum(orc):
+    """Sec. 2.1 with unit weights: x_i = y - sum_{k != i} x_k, on a 1-row C."""
+    m, n, k = 1, 5, 1
+    A = np.array([[2.0]])
+    B = np.array([[1.0, -3.0, 4.0, 0.5, 7.0]])
+    Af, Bf, Cf = orc.protected_product(A, B, 1, 1)
+    y = Cf[0, n]
+    assert y == 2 * (1 - 3 + 4 + 0.5 + 7)
+    assert orc.rebuild_value(Cf, m, n, 1, 1, 0, 2, orc.DIR_ROW) == y - (2 - 6 + 1 + 14)
+
+
+def test_taller_than_checksum_block_is_unrecoverable(orc):
+    """A b x b hole with b > br has more unknowns than column relations
+    (C1's 64x64 erasure under the (n+1) encoding)."""
+    m = n = 16
+    A, B = int_problem(m, n, 5)
+    Af, Bf, Cf = orc.protected_product(A, B, 1, 1)
+    Cx = Cf.copy()
+    Cx[0:4, 0:4] = 0
+    assert orc.recover(Cx, m, n, 1, 1, (0, 0, 4, 4)) == -4
+    assert orc.recover(Cx, m, n, 1, 1, (0, 0, 4, 4), use_rows=True) == -4
+    assert np.array_equal(Cx[0:4, 0:4], np.zeros((4, 4)))   # untouched
+    _, _, rep = orc.verify(Cx, m, n, 1, 1, np.zeros((1, n + 1)), np.zeros((m + 1, 1)))
+    assert rep.n_flag_c == 4 and rep.n_flag_r == 4
+    assert orc.classify(rep, m, n, 1, 1)[0] == orc.MULTI
+
+
+@pytest.mark.parametrize("share", ["col_band", "row_band", "neither"])
+def test_flip_with_known_erasure(orc, share):
+    """A flip and an erased block in one run: the erasure is passed as known,
+    the flip is located and corrected first, then the block is rebuilt."""
+    m = n = 32
+    b = 8
+    A, B = int_problem(m, n, 9, seed=21)
+    Af, Bf, Cf = orc.protected_product(A, B, b, b)
+    rect = (8, 16, 8, 8)
+    fi, fj = {"col_band": (27, 19), "row_band": (10, 3), "neither": (30, 2)}[share]
+    Cx = Cf.copy()
+    Cx[fi, fj] += 5
+    Cx[8:16, 16:24] = 0
+    tc = np.zeros((b, n + b))
+    tr = np.zeros((m + b, b))
+    _, _, rep = orc.verify(Cx, m, n, b, b, tc, tr, erasures=[rect])
+    cls, i, j, d = orc.classify(rep, m, n, b, b, erasures=[rect])
+    assert (cls, i, j) == (orc.DATA, fi, fj)
+    if share == "col_band":
+        assert d == orc.DIR_ROW
+    Cx[i, j] = orc.rebuild_value(Cx, m, n, b, b, i, j, d)
+    assert orc.recover(Cx, m, n, b, b, rect) == 0
+    assert np.array_equal(Cx, Cf)
+
+
+# ---------------------------------------------------------------- residual check (Sec. 4.3)
+def test_residual_check(orc):
+    m, n, k = 64, 48, 80
+    A = synth.uniform(6, 0, m, k)
+    B = synth.uniform(6, 1, k, n)
+    x = synth.uniform(6, synth.STREAM_X, 1, n)[0]
+    Cm = orc.gemm(A, B)
+    rho = orc.residual(A, B, Cm, x)
+    assert rho < 10.0
+    Cm[3, 7] += 1e-6
+    assert orc.residual(A, B, Cm, x) > 1e3
+
+
+# ---------------------------------------------------------------- quantizers
+def _bit_patterns(count, seed=17):
+    raw = synth.raw_u64(seed, 0, np.arange(count, dtype=np.uint64)).astype(np.uint64)
+    u32 = (raw >> np.uint64(32)).astype(np.uint32)
+    edge = np.array([0, 0x80000000, 0x3F800000, 0x3F808000, 0x3F818000, 0x3F80FFFF, 0x7F7FFFFF, 0x00000001,
+                     0x007FFFFF, 0x00800000, 0x7F800000, 0xFF800000, 0x477FE000, 0x477FF000], dtype=np.uint32)
+    return np.concatenate([u32, edge])
+
+
+def test_bf16_rne_matches_torch(orc):
+    import torch
+    pats = _bit_patterns(1 << 20)
+    x = pats.view(np.float32)
+    x = x[~np.isnan(x)]
+    ours = orc.to_bf16_bits(x)
+    ref = torch.from_numpy(x.copy()).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(ours, ref)
+
+
+def test_e4m3_decode_table_matches_torch(orc):
+    import torch
+    codes = np.arange(256, dtype=np.uint8)
+    ref = torch.from_numpy(codes.copy()).view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    ours = orc.e4m3_values(codes)
+    finite = ~np.isnan(ref)
+    assert np.array_equal(np.isnan(ours), ~finite)
+    assert np.array_equal(ours[finite], ref[finite])
+    assert ours[finite].max() == 448.0
+
+
+def test_e4m3_rne_matches_torch_in_range(orc):
+    import torch
+    pats = _bit_patterns(1 << 20, seed=23)
+    x = pats.view(np.float32)
+    x = x[np.isfinite(x) & (np.abs(x) <= 464.0)]
+    # add exact ties of the e4m3 grid
+    grid = orc.e4m3_values(np.arange(0, 126, dtype=np.uint8))
+    ties = ((grid[1:] + grid[:-1]) / 2).astype(np.float32)
+    x = np.concatenate([x, ties, -ties])
+    ours = orc.e4m3_values(orc.to_e4m3_codes(x))
+    ref = torch.from_numpy(x.copy()).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(ours, ref)
+
+
+def test_e4m3_scale_is_largest_power_of_two(orc):
+    for amax in [1.0, 0.999, 3.5, 448.0, 449.0, 1e-3, 7e5]:
+        x = np.array([0.25, -amax, 0.0], dtype=np.float32)
+        e = orc.e4m3_scale_exp(x)
+        a = max(0.25, float(np.float32(amax)))
+        assert a * 2.0 ** e <= 448.0 < a * 2.0 ** (e + 1)
+    assert orc.e4m3_scale_exp(np.zeros(4, dtype=np.float32)) == 0
