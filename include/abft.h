@@ -1,0 +1,240 @@
+/*
+ * abft.h -- C ABI of libabft: checksum-encoded matrix multiplication with
+ * error detection, location, correction and erased-block rebuild, on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: Bosilca, Delmas, Dongarra, Langou, "Algorithmic Based Fault
+ * Tolerance Applied to High Performance Computing" (2008), Sec. 2.1 (the
+ * single-checksum recovery y = a_1 x_1 + ... + a_p x_p, here with unit
+ * weights) and Sec. 2.2, Eq. ABFT-GEMM:
+ *
+ *     [ A       ]                 [ AB         AB C_R       ]
+ *     [ C_C^T A ] [ B   B C_R ] = [ C_C^T AB   C_C^T AB C_R ] = (AB)_F
+ *
+ * whose result is "consistent": it keeps the checksum relations of its
+ * operands, which lets errors in it be detected, located and corrected, and
+ * lost parts be rebuilt.  C_C (m x br) stacks m/br identity blocks and C_R
+ * (n x bc) stacks n/bc identity blocks, so C_C^T A sums the row blocks of A
+ * and B C_R sums the column blocks of B.  br = bc = 1 is the classic
+ * all-ones checksum; br = bc = nloc is the paper's per-process block scheme
+ * (Sec. 3.2, the (n+nloc)-by-n-by-(n+nloc) product).
+ *
+ * Relations checked in C_f (the encoded product):
+ *   column relation (r, j), r < br, j < N:  sum_{g<m/br} C_f[g*br + r, j] = T_c(r, j)
+ *   row relation    (i, c), i < M, c < bc:  sum_{h<n/bc} C_f[i, h*bc + c] = T_r(i, c)
+ * where T_c(r, j) = sum_{s<S} C_f[m + s*br + r, j] and T_r(i, c) =
+ * sum_{s<S} C_f[i, n + s*bc + c] are the carried checksums, stored as S
+ * "split" parts (S = 1 for binary64 and binary32 inputs; S = 3 for bfloat16,
+ * see abft_split_count), M = m + S*br and N = n + S*bc.
+ *
+ * Conventions
+ *  - Every pointer named *_f, ws or dst is DEVICE memory owned by the caller;
+ *    the library never allocates or frees.  Host pointers are marked "host".
+ *  - stream is a hipStream_t (passed as void*); every call that launches work
+ *    is asynchronous on it and returns as soon as the work is queued.
+ *  - Return values: 0 = ABFT_OK, > 0 informative, < 0 error.  Errors in the
+ *    arguments are reported before anything is launched; no C++ exception or
+ *    abort crosses this boundary.  After ABFT_E_HIP, abft_last_hip_error()
+ *    gives the hipError_t.
+ *  - Calls on distinct buffers are independent and reentrant; the library
+ *    keeps no state besides the last HIP error (thread-local).
+ */
+#ifndef ABFT_H
+#define ABFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Element type of A_f and B_f.  C_f is binary64 for ABFT_F64 and binary32
+ * (FP32 accumulation) for every other input type. */
+typedef enum {
+    ABFT_F64 = 0,
+    ABFT_F32 = 1,
+    ABFT_BF16 = 2,
+    ABFT_FP8_E4M3 = 3
+} abft_dtype;
+
+typedef enum {
+    ABFT_OK = 0,
+    ABFT_FAULT_DETECTED = 1,     /* abft_verify: at least one relation failed */
+    ABFT_E_ARG = -1,             /* invalid sizes, leading dimensions, alignment or pointers */
+    ABFT_E_HIP = -2,             /* a HIP runtime call failed (see abft_last_hip_error) */
+    ABFT_E_UNCORRECTABLE = -3,   /* abft_correct: the flags do not name one element */
+    ABFT_E_UNRECOVERABLE = -4,   /* abft_recover_block: more unknowns than relations */
+    ABFT_E_WORKSPACE = -5,       /* workspace pointer missing */
+    ABFT_E_UNSUPPORTED = -6      /* combination not implemented (e.g. dtype, tau mode) */
+} abft_status;
+
+/* Detection threshold tau per relation (a relation fails when !(|D| <= tau),
+ * so NaN residuals always fail).  The paper fixes no threshold: it only
+ * notes that checksum rounding is of the order of the method's own
+ * (Sec. 2.1).
+ *  ABFT_TAU_DET   rigorous rounding bound, (2 gamma_k + 2 gamma_{G+1} + u_st) S
+ *                 with S bounded by Cauchy-Schwarz from per-row/column norms
+ *                 (binary64 paths);
+ *  ABFT_TAU_STAT  lambda times the standard deviation of the rounding error of
+ *                 a T-step binary32 accumulation (FP32-accumulated paths);
+ *  ABFT_TAU_EXACT tau = 0, for integer-valued inputs whose sums are exact. */
+typedef enum { ABFT_TAU_DET = 0, ABFT_TAU_STAT = 1, ABFT_TAU_EXACT = 2 } abft_tau_mode;
+
+/* abft_gemm flags */
+#define ABFT_PLAIN 1u   /* multiply only the data part (C = A B, m x n): the
+                           unprotected baseline the overhead is measured against */
+
+/*
+ * Problem descriptor.  Layouts (elements of the dtype, not bytes):
+ *   A_f  row-major (m + S*br) x k, row i at A_f + i*lda, lda >= k.
+ *        Rows [0, m) are the caller's A; abft_encode writes rows [m, m+S*br).
+ *   B_f  column-major k x (n + S*bc), column j at B_f + j*ldb, ldb >= k
+ *        (equivalently, B_f^T is row-major).  Columns [0, n) are the caller's
+ *        B; abft_encode writes columns [n, n+S*bc).
+ *   C_f  row-major (m + S*br) x (n + S*bc), ldc >= n + S*bc.
+ * Requirements: m % br == 0, n % bc == 0, k >= 1, and rows of A_f / columns
+ * of B_f start on 16-byte boundaries (lda*size and ldb*size multiples of 16,
+ * base pointers 16-byte aligned); k is a multiple of 16/size.  C_f only
+ * needs its natural alignment (any ldc >= its minimum, e.g. n+1).
+ */
+typedef struct {
+    int32_t dtype;     /* abft_dtype */
+    int32_t tau_mode;  /* abft_tau_mode */
+    int64_t m, n, k;   /* data sizes: A is m x k, B is k x n */
+    int64_t br, bc;    /* checksum block height (divides m) and width (divides n) */
+    int64_t lda, ldb, ldc;
+    double lambda;     /* ABFT_TAU_STAT multiplier (0 selects 10) */
+    double kappa;      /* ABFT_TAU_DET safety factor >= 1 (0 selects 1 + 2^-20) */
+} abft_problem;
+
+/* A rectangle of C_f: rows [i0, i0+h), columns [j0, j0+w). */
+typedef struct {
+    int64_t i0, j0, h, w;
+} abft_rect;
+
+#define ABFT_MAX_FLAGS 64
+
+/* One failed relation: column relation (a = r, b = j) or row relation
+ * (a = i, b = c), its residual d and threshold tau. */
+typedef struct {
+    int64_t a, b;
+    double d, tau;
+} abft_flag;
+
+/* Result of abft_verify.  The flag lists hold the first ABFT_MAX_FLAGS failed
+ * relations of each direction in no particular order (counts are exact). */
+typedef struct {
+    int64_t n_flag_c, n_flag_r;       /* failed column / row relations */
+    int64_t n_excl_c, n_excl_r;       /* relations skipped: they hold a known erased element */
+    int64_t n_nonfinite;              /* failed relations with a NaN/Inf residual */
+    double max_ratio_c, max_ratio_r;  /* max |D|/tau over finite, checked relations */
+    abft_flag flag_c[ABFT_MAX_FLAGS];
+    abft_flag flag_r[ABFT_MAX_FLAGS];
+} abft_report;
+
+typedef enum { ABFT_CLS_CLEAN = 0, ABFT_CLS_DATA = 1, ABFT_CLS_CHECKSUM = 2, ABFT_CLS_MULTI = 3 } abft_class;
+typedef enum { ABFT_DIR_COL = 0, ABFT_DIR_ROW = 1 } abft_direction;
+
+/* Result of abft_classify: the class, the element (i, j) of C_f and the
+ * direction of the relation it is rebuilt from. */
+typedef struct {
+    int32_t cls;   /* abft_class */
+    int32_t dir;   /* abft_direction */
+    int64_t i, j;
+} abft_location;
+
+/* Number S of split parts a carried checksum is stored in for this dtype:
+ * 1 for F64 and F32; 3 for BF16 (a binary32 checksum c = hi + mid + lo,
+ * each part a bfloat16, so the bfloat16 matrix cores carry it exactly). */
+int abft_split_count(int32_t dtype);
+
+/* Bytes of device workspace the calls below need for problem p (threshold
+ * statistics, verification partials and the device report). */
+size_t abft_workspace_size(const abft_problem *p);
+
+/*
+ * Encode (Eq. ABFT-GEMM, the checkpointed operands A_F and B_F): writes
+ * C_C^T A into rows [m, m+S*br) of A_f and B C_R into columns [n, n+S*bc) of
+ * B_f, summing in binary64 and rounding once to the dtype (then splitting,
+ * when S > 1); and writes the per-row / per-column statistics the thresholds
+ * are built from into ws.  Reads A and B once or twice (HBM-bound).
+ */
+int abft_encode(const abft_problem *p, void *A_f, void *B_f, void *ws, void *stream);
+
+/*
+ * Protected product (Eq. ABFT-GEMM): C_f = A_f B_f over all (m+S*br) x
+ * (n+S*bc) entries, on the matrix cores with binary64 (F64) or binary32
+ * (other dtypes) accumulation.  With flags & ABFT_PLAIN only C = A B (m x n)
+ * is computed.  A_f and B_f must have been encoded (unless ABFT_PLAIN).
+ */
+int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, void *stream);
+
+/*
+ * Verify (consistency, Sec. 2.2): recomputes every column and row relation of
+ * C_f from C_f in binary64, compares each residual with its threshold and
+ * records the failures.  Relations that hold an element of a known erased
+ * rectangle (host array `known`, n_known <= 4) are skipped.  The report is
+ * built in ws; if host_out is not NULL it is also copied there (asynchronous
+ * on stream: pass pinned memory and synchronise the stream before reading).
+ * Returns ABFT_OK once queued; the outcome is in the report.
+ */
+int abft_verify(const abft_problem *p, const void *C_f, const abft_rect *known, int n_known,
+                void *ws, abft_report *host_out, void *stream);
+
+/*
+ * Classify a report (host only, no device work; single-error model):
+ *  no failed relation                                   -> CLEAN
+ *  one failed column relation (r, j) and one failed row relation (i, c) with
+ *  i mod br = r, j mod bc = c and consistent residuals  -> DATA (i < m, j < n)
+ *                                                          or CHECKSUM (a carried entry)
+ *  with known erasures, a lone failed relation whose partner relation is
+ *  skipped and names exactly one element                -> DATA / CHECKSUM
+ *  anything else                                        -> MULTI
+ * The rebuild direction is the column relation unless that relation holds an
+ * erased element.  report and out are host pointers.
+ */
+int abft_classify(const abft_problem *p, const abft_report *report, const abft_rect *known, int n_known,
+                  abft_location *out);
+
+/*
+ * Correct one located element (Sec. 2.1 recovery with unit weights): the
+ * element is rebuilt from the other members of its relation in binary64,
+ * without reading its (possibly non-finite) value, and rounded once to C's
+ * type.  loc is a host pointer from abft_classify.  CLEAN: nothing is queued,
+ * returns ABFT_OK.  MULTI: returns ABFT_E_UNCORRECTABLE, C_f untouched.
+ */
+int abft_correct(const abft_problem *p, void *C_f, const abft_location *loc, void *stream);
+
+/*
+ * Rebuild an erased rectangle of C_f (the one-GPU image of the lost process,
+ * Sec. 3.3's checksum step): each element is solved from its column relation
+ * (use_rows == 0; needs e.h <= br) or its row relation (use_rows != 0; needs
+ * e.w <= bc), which then hold exactly one unknown each.  Otherwise returns
+ * ABFT_E_UNRECOVERABLE and queues nothing.  HBM-bound.
+ */
+int abft_recover_block(const abft_problem *p, void *C_f, abft_rect e, int use_rows, void *stream);
+
+/* Test-only fault injectors.  abft_inject_flip XORs bit `bit` of element
+ * (i, j) of C_f (bit < 64 for binary64 C, < 32 for binary32 C).
+ * abft_inject_erase overwrites a rectangle with zeros (nan_fill == 0) or NaN. */
+int abft_inject_flip(const abft_problem *p, void *C_f, int64_t i, int64_t j, int bit, void *stream);
+int abft_inject_erase(const abft_problem *p, void *C_f, abft_rect e, int nan_fill, void *stream);
+
+/* Synthetic inputs: splitmix64 counter stream (seed, stream_id); logical
+ * element (r, c) of a rows x cols matrix uses counter r*cols + c and maps to
+ * uniform [-1, 1) (binary64: 2*((x>>11)*2^-53)-1; binary32: 2*((x>>40)*2^-24)-1).
+ * It is stored at dst[r*ld + c] (transpose == 0) or dst[c*ld + r]
+ * (transpose != 0).  dtype ABFT_F64 or ABFT_F32. */
+int abft_fill_uniform(int32_t dtype, int64_t rows, int64_t cols, int64_t ld, int transpose, uint64_t seed,
+                      int32_t stream_id, void *dst, void *stream);
+
+/* Last hipError_t seen by this thread (0 if none), and a status message. */
+int abft_last_hip_error(void);
+const char *abft_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ABFT_H */

@@ -569,3 +569,11 @@ int orc_e4m3_scale_exp(int64_t count, const float *x)
     while (ldexp(amax, e) > 448.0) --e;
     return e;
 }
+
+/* Threads the OpenMP loops of this library run on (1 without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+int orc_num_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_num_threads(void) { return 1; }
+#endif

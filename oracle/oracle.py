@@ -89,6 +89,7 @@ def lib():
             "orc_e4m3_value": (_D, [C.c_uint8]),
             "orc_to_e4m3": (None, [_I, _P, _P]),
             "orc_e4m3_scale_exp": (C.c_int, [_I, _P]),
+            "orc_num_threads": (C.c_int, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -136,6 +137,10 @@ def gemm(A: np.ndarray, B: np.ndarray) -> np.ndarray:
     Cm = np.empty((M, N))
     lib().orc_gemm(M, N, K, _p(A), K, _p(B), N, _p(Cm), N)
     return Cm
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
 
 
 def dot(a: np.ndarray, b: np.ndarray) -> float:

@@ -1,0 +1,234 @@
+"""Thin ctypes binding of libabft (include/abft.h): same names, argument
+marshalling only.  Device buffers are torch tensors on a ROCm device; every
+computation runs in the library's HIP kernels.  There is no CPU fallback: if
+the library is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libabft.so")
+
+ABFT_F64, ABFT_F32, ABFT_BF16, ABFT_FP8_E4M3 = 0, 1, 2, 3
+ABFT_OK, ABFT_FAULT_DETECTED = 0, 1
+ABFT_E_ARG, ABFT_E_HIP, ABFT_E_UNCORRECTABLE, ABFT_E_UNRECOVERABLE, ABFT_E_WORKSPACE, ABFT_E_UNSUPPORTED = \
+    -1, -2, -3, -4, -5, -6
+ABFT_TAU_DET, ABFT_TAU_STAT, ABFT_TAU_EXACT = 0, 1, 2
+ABFT_PLAIN = 1
+ABFT_CLS_CLEAN, ABFT_CLS_DATA, ABFT_CLS_CHECKSUM, ABFT_CLS_MULTI = 0, 1, 2, 3
+ABFT_DIR_COL, ABFT_DIR_ROW = 0, 1
+ABFT_MAX_FLAGS = 64
+
+
+class AbftError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn}: {msg} (status {status})")
+        self.status = status
+
+
+class abft_problem(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("tau_mode", C.c_int32),
+                ("m", C.c_int64), ("n", C.c_int64), ("k", C.c_int64),
+                ("br", C.c_int64), ("bc", C.c_int64),
+                ("lda", C.c_int64), ("ldb", C.c_int64), ("ldc", C.c_int64),
+                ("lambda_", C.c_double), ("kappa", C.c_double)]
+
+
+class abft_rect(C.Structure):
+    _fields_ = [("i0", C.c_int64), ("j0", C.c_int64), ("h", C.c_int64), ("w", C.c_int64)]
+
+
+class abft_flag(C.Structure):
+    _fields_ = [("a", C.c_int64), ("b", C.c_int64), ("d", C.c_double), ("tau", C.c_double)]
+
+
+class abft_report(C.Structure):
+    _fields_ = [("n_flag_c", C.c_int64), ("n_flag_r", C.c_int64),
+                ("n_excl_c", C.c_int64), ("n_excl_r", C.c_int64),
+                ("n_nonfinite", C.c_int64),
+                ("max_ratio_c", C.c_double), ("max_ratio_r", C.c_double),
+                ("flag_c", abft_flag * ABFT_MAX_FLAGS), ("flag_r", abft_flag * ABFT_MAX_FLAGS)]
+
+    def flags_c(self):
+        return sorted((f.a, f.b, f.d, f.tau) for f in self.flag_c[:min(self.n_flag_c, ABFT_MAX_FLAGS)])
+
+    def flags_r(self):
+        return sorted((f.a, f.b, f.d, f.tau) for f in self.flag_r[:min(self.n_flag_r, ABFT_MAX_FLAGS)])
+
+
+class abft_location(C.Structure):
+    _fields_ = [("cls", C.c_int32), ("dir", C.c_int32), ("i", C.c_int64), ("j", C.c_int64)]
+
+
+_lib = None
+_V = C.c_void_p
+_P = C.POINTER
+
+
+def lib():
+    """Load libabft.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_0806_3121_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        sig = {
+            "abft_split_count": (C.c_int, [C.c_int32]),
+            "abft_workspace_size": (C.c_size_t, [_P(abft_problem)]),
+            "abft_encode": (C.c_int, [_P(abft_problem), _V, _V, _V, _V]),
+            "abft_gemm": (C.c_int, [_P(abft_problem), _V, _V, _V, C.c_uint32, _V]),
+            "abft_verify": (C.c_int, [_P(abft_problem), _V, _P(abft_rect), C.c_int, _V, _V, _V]),
+            "abft_classify": (C.c_int, [_P(abft_problem), _P(abft_report), _P(abft_rect), C.c_int,
+                                        _P(abft_location)]),
+            "abft_correct": (C.c_int, [_P(abft_problem), _V, _P(abft_location), _V]),
+            "abft_recover_block": (C.c_int, [_P(abft_problem), _V, abft_rect, C.c_int, _V]),
+            "abft_inject_flip": (C.c_int, [_P(abft_problem), _V, C.c_int64, C.c_int64, C.c_int, _V]),
+            "abft_inject_erase": (C.c_int, [_P(abft_problem), _V, abft_rect, C.c_int, _V]),
+            "abft_fill_uniform": (C.c_int, [C.c_int32, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_uint64,
+                                            C.c_int32, _V, _V]),
+            "abft_last_hip_error": (C.c_int, []),
+            "abft_status_string": (C.c_char_p, [C.c_int]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(fn, st, ok=(ABFT_OK,)):
+    if st not in ok:
+        msg = lib().abft_status_string(st).decode()
+        if st == ABFT_E_HIP:
+            msg += f" (hipError {lib().abft_last_hip_error()})"
+        raise AbftError(fn, st, msg)
+    return st
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def problem(dtype, m, n, k, br, bc, lda=None, ldb=None, ldc=None, tau_mode=None, lam=0.0, kappa=0.0):
+    S = lib().abft_split_count(dtype)
+    if tau_mode is None:
+        tau_mode = ABFT_TAU_DET if dtype == ABFT_F64 else ABFT_TAU_STAT
+    return abft_problem(dtype, tau_mode, m, n, k, br, bc,
+                        lda if lda is not None else k, ldb if ldb is not None else k,
+                        ldc if ldc is not None else n + S * bc, lam, kappa)
+
+
+def split_count(dtype) -> int:
+    return lib().abft_split_count(dtype)
+
+
+def workspace_size(p: abft_problem) -> int:
+    return lib().abft_workspace_size(C.byref(p))
+
+
+def encode(p, A_f, B_f, ws, stream=None):
+    return _check("abft_encode", lib().abft_encode(C.byref(p), _ptr(A_f), _ptr(B_f), _ptr(ws), _stream(stream)))
+
+
+def gemm(p, A_f, B_f, C_f, flags=0, stream=None):
+    return _check("abft_gemm", lib().abft_gemm(C.byref(p), _ptr(A_f), _ptr(B_f), _ptr(C_f), flags, _stream(stream)))
+
+
+def _rects(known):
+    known = list(known or [])
+    arr = (abft_rect * max(1, len(known)))(*[abft_rect(*r) for r in known])
+    return arr, len(known)
+
+
+def verify(p, C_f, ws, known=None, host_out=None, stream=None):
+    """host_out: a pinned uint8 CPU tensor of sizeof(abft_report) bytes, or None."""
+    arr, nk = _rects(known)
+    hp = C.c_void_p(host_out.data_ptr()) if host_out is not None else None
+    return _check("abft_verify", lib().abft_verify(C.byref(p), _ptr(C_f), arr, nk, _ptr(ws), hp, _stream(stream)))
+
+
+def new_report_buffer():
+    import torch
+    return torch.empty(C.sizeof(abft_report), dtype=torch.uint8, pin_memory=True)
+
+
+def read_report(host_buf) -> abft_report:
+    """Copy the report out of a pinned buffer (synchronise the stream first)."""
+    return abft_report.from_buffer_copy(host_buf.numpy().tobytes())
+
+
+def classify(p, rep: abft_report, known=None) -> abft_location:
+    arr, nk = _rects(known)
+    loc = abft_location()
+    _check("abft_classify", lib().abft_classify(C.byref(p), C.byref(rep), arr, nk, C.byref(loc)))
+    return loc
+
+
+def correct(p, C_f, loc: abft_location, stream=None):
+    return _check("abft_correct", lib().abft_correct(C.byref(p), _ptr(C_f), C.byref(loc), _stream(stream)))
+
+
+def recover_block(p, C_f, rect, use_rows=False, stream=None):
+    return _check("abft_recover_block",
+                  lib().abft_recover_block(C.byref(p), _ptr(C_f), abft_rect(*rect), int(use_rows), _stream(stream)))
+
+
+def inject_flip(p, C_f, i, j, bit, stream=None):
+    return _check("abft_inject_flip", lib().abft_inject_flip(C.byref(p), _ptr(C_f), i, j, bit, _stream(stream)))
+
+
+def inject_erase(p, C_f, rect, nan_fill=False, stream=None):
+    return _check("abft_inject_erase",
+                  lib().abft_inject_erase(C.byref(p), _ptr(C_f), abft_rect(*rect), int(nan_fill), _stream(stream)))
+
+
+def fill_uniform(dtype, rows, cols, ld, transpose, seed, stream_id, dst, stream=None):
+    return _check("abft_fill_uniform", lib().abft_fill_uniform(dtype, rows, cols, ld, int(transpose), seed, stream_id,
+                                                               _ptr(dst), _stream(stream)))
+
+
+# ---------------------------------------------------------------- conveniences
+class Protected:
+    """Device buffers of one protected product (A_f, B_f, C_f, workspace),
+    allocated with torch.  B_f is stored column-major: the tensor Bt is
+    B_f^T, (n + S*bc) x k row-major."""
+
+    def __init__(self, dtype, m, n, k, br, bc, device="cuda", tau_mode=None, lam=0.0):
+        import torch
+        tdt = {ABFT_F64: torch.float64, ABFT_F32: torch.float32, ABFT_BF16: torch.bfloat16,
+               ABFT_FP8_E4M3: torch.uint8}[dtype]
+        cdt = torch.float64 if dtype == ABFT_F64 else torch.float32
+        self.S = split_count(dtype)
+        self.p = problem(dtype, m, n, k, br, bc, tau_mode=tau_mode, lam=lam)
+        self.M, self.N = m + self.S * br, n + self.S * bc
+        self.A = torch.zeros(self.M, k, dtype=tdt, device=device)
+        self.Bt = torch.zeros(self.N, k, dtype=tdt, device=device)
+        self.C = torch.zeros(self.M, self.N, dtype=cdt, device=device)
+        self.ws = torch.zeros(workspace_size(self.p), dtype=torch.uint8, device=device)
+        self.rep_host = new_report_buffer()
+
+    def encode(self):
+        encode(self.p, self.A, self.Bt, self.ws)
+
+    def gemm(self, flags=0):
+        gemm(self.p, self.A, self.Bt, self.C, flags)
+
+    def verify(self, known=None) -> abft_report:
+        import torch
+        verify(self.p, self.C, self.ws, known=known, host_out=self.rep_host)
+        torch.cuda.current_stream().synchronize()
+        return read_report(self.rep_host)

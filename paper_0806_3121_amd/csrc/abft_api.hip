@@ -1,0 +1,333 @@
+// libabft C ABI: argument checks, workspace layout, host-side classification
+// and dispatch to the gfx950 kernels.  See include/abft.h for the contract.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace abft {
+
+static thread_local int g_last_hip_error = 0;
+void set_hip_error(hipError_t e) { g_last_hip_error = (int)e; }
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int64_t group_partitions(int64_t G, int64_t b, int64_t cols) {
+    // Enough independent sums to fill 256 CUs with ~2K threads each; each
+    // partition sums a contiguous run of groups in ascending order.
+    const int64_t target = int64_t(1) << 19;
+    int64_t rel = b * cols;
+    int64_t P = (target + rel - 1) / rel;
+    if (P > G) P = G;
+    if (P < 1) P = 1;
+    return P;
+}
+
+WsLayout ws_layout(const abft_problem *p) {
+    Geom g = geom_of(p);
+    WsLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    L.na = take(sizeof(double) * g.M);
+    L.na_abs = take(sizeof(double) * g.br);
+    L.nb = take(sizeof(double) * g.N);
+    L.nb_abs = take(sizeof(double) * g.bc);
+    L.qr = take(sizeof(double) * g.M);
+    L.qc = take(sizeof(double) * g.N);
+    L.nv = take(sizeof(double) * g.br);
+    L.nw = take(sizeof(double) * g.bc);
+    L.grpA = take(sizeof(double) * g.br * g.k);
+    L.grpB = take(sizeof(double) * g.bc * g.k);
+    // partial sums: encode A (2 stats), encode B (2 stats), verify columns (1)
+    int64_t pa = group_partitions(g.Gr, g.br, g.k);
+    int64_t pb = group_partitions(g.Gc, g.bc, g.k);
+    int64_t pc = group_partitions(g.Gr, g.br, g.N);
+    size_t need = 0;
+    if (pa > 1) need = std::max(need, (size_t)(pa * g.br * g.k * 2));
+    if (pb > 1) need = std::max(need, (size_t)(pb * g.bc * g.k * 2));
+    if (pc > 1) need = std::max(need, (size_t)(pc * g.br * g.N));
+    L.partial_bytes = sizeof(double) * need;
+    L.partial = take(L.partial_bytes > 0 ? L.partial_bytes : 8);
+    L.report = take(sizeof(abft_report));
+    L.total = off;
+    return L;
+}
+
+static double gamma_n(double n, double u) { return n * u / (1.0 - n * u); }
+
+TauCoef tau_coef(const abft_problem *p) {
+    Geom g = geom_of(p);
+    TauCoef t;
+    t.mode = p->tau_mode;
+    t.lambda = p->lambda > 0 ? p->lambda : 10.0;
+    const double u64 = std::ldexp(1.0, -53);
+    const double u32 = std::ldexp(1.0, -24);
+    if (p->tau_mode == ABFT_TAU_DET) {
+        double kappa = p->kappa >= 1.0 ? p->kappa : 1.0 + std::ldexp(1.0, -20);
+        double u_acc = p->dtype == ABFT_F64 ? u64 : u32;
+        double u_st = p->dtype == ABFT_F64 ? 0.0 : u32;
+        t.cc = kappa * (2 * gamma_n((double)g.k, u_acc) + 2 * gamma_n((double)(g.Gr + g.S), u64) + u_st);
+        t.cr = kappa * (2 * gamma_n((double)g.k, u_acc) + 2 * gamma_n((double)(g.Gc + g.S), u64) + u_st);
+    } else {
+        t.cc = t.cr = 0.0;
+    }
+    return t;
+}
+
+// ------------------------------------------------------------------ checks
+static int check_problem(const abft_problem *p) {
+    if (!p) return ABFT_E_ARG;
+    if (p->dtype < ABFT_F64 || p->dtype > ABFT_FP8_E4M3) return ABFT_E_ARG;
+    if (p->m < 1 || p->n < 1 || p->k < 1 || p->br < 1 || p->bc < 1) return ABFT_E_ARG;
+    if (p->br > p->m || p->bc > p->n) return ABFT_E_ARG;
+    if (p->m % p->br || p->n % p->bc) return ABFT_E_ARG;
+    if (p->tau_mode < ABFT_TAU_DET || p->tau_mode > ABFT_TAU_EXACT) return ABFT_E_ARG;
+    if (p->dtype != ABFT_F64) return ABFT_E_UNSUPPORTED;
+    if (p->tau_mode == ABFT_TAU_STAT) return ABFT_E_UNSUPPORTED;
+    return ABFT_OK;
+}
+
+static bool aligned16(const void *q) { return ((uintptr_t)q & 15u) == 0; }
+
+static int check_operands(const abft_problem *p, const void *A_f, const void *B_f) {
+    size_t es = dtype_size(p->dtype);
+    if (!A_f || !B_f) return ABFT_E_ARG;
+    if (p->lda < p->k || p->ldb < p->k) return ABFT_E_ARG;
+    if ((p->lda * es) % 16 || (p->ldb * es) % 16 || (p->k * es) % 16) return ABFT_E_ARG;
+    if (!aligned16(A_f) || !aligned16(B_f)) return ABFT_E_ARG;
+    return ABFT_OK;
+}
+
+static int check_c(const abft_problem *p, const void *C_f, bool plain) {
+    Geom g = geom_of(p);
+    if (!C_f) return ABFT_E_ARG;
+    if (p->ldc < (plain ? g.n : g.N)) return ABFT_E_ARG;
+    if (((uintptr_t)C_f % c_size(p->dtype)) != 0) return ABFT_E_ARG;
+    return ABFT_OK;
+}
+
+static int check_rect(const Geom &g, const abft_rect &e) {
+    if (e.h < 1 || e.w < 1 || e.i0 < 0 || e.j0 < 0) return ABFT_E_ARG;
+    if (e.i0 + e.h > g.M || e.j0 + e.w > g.N) return ABFT_E_ARG;
+    return ABFT_OK;
+}
+
+// ------------------------------------------------------------------ classification (host)
+static bool col_erased_h(const abft_rect *kn, int nk, int64_t r, int64_t j, int64_t br) {
+    for (int q = 0; q < nk; ++q) {
+        const abft_rect &e = kn[q];
+        if (j < e.j0 || j >= e.j0 + e.w) continue;
+        if (e.h >= br) return true;
+        int64_t off = ((r - e.i0) % br + br) % br;
+        if (off < e.h) return true;
+    }
+    return false;
+}
+static bool row_erased_h(const abft_rect *kn, int nk, int64_t i, int64_t c, int64_t bc) {
+    for (int q = 0; q < nk; ++q) {
+        const abft_rect &e = kn[q];
+        if (i < e.i0 || i >= e.i0 + e.h) continue;
+        if (e.w >= bc) return true;
+        int64_t off = ((c - e.j0) % bc + bc) % bc;
+        if (off < e.w) return true;
+    }
+    return false;
+}
+
+static int classify(const abft_problem *p, const abft_report *rep, const abft_rect *kn, int nk, abft_location *out) {
+    Geom g = geom_of(p);
+    out->cls = ABFT_CLS_MULTI;
+    out->dir = ABFT_DIR_COL;
+    out->i = out->j = -1;
+    int64_t nc = rep->n_flag_c, nr = rep->n_flag_r;
+    if (nc == 0 && nr == 0) { out->cls = ABFT_CLS_CLEAN; return ABFT_OK; }
+    // A carried entry is "stored total" of its relation: its residual sign is
+    // negative; a data entry is a summand.  Split parts all count as totals.
+    auto is_data_row = [&](int64_t i) { return i < g.m; };
+    auto is_data_col = [&](int64_t j) { return j < g.n; };
+    auto kind = [&](int64_t i, int64_t j) {
+        return (is_data_row(i) && is_data_col(j)) ? ABFT_CLS_DATA : ABFT_CLS_CHECKSUM;
+    };
+    if (nc == 1 && nr == 1) {
+        const abft_flag &fc = rep->flag_c[0], &fr = rep->flag_r[0];
+        int64_t r = fc.a, j = fc.b, i = fr.a, c = fr.b;
+        int64_t ri = is_data_row(i) ? i % g.br : (i - g.m) % g.br;
+        int64_t cj = is_data_col(j) ? j % g.bc : (j - g.n) % g.bc;
+        if (ri != r || cj != c) return ABFT_OK;  // MULTI
+        if (std::isfinite(fc.d) && std::isfinite(fr.d)) {
+            double sc = is_data_row(i) ? 1.0 : -1.0, sr = is_data_col(j) ? 1.0 : -1.0;
+            if (!(std::fabs(sc * fc.d - sr * fr.d) <= fc.tau + fr.tau)) return ABFT_OK;  // MULTI
+        }
+        out->cls = kind(i, j); out->i = i; out->j = j; out->dir = ABFT_DIR_COL;
+        return ABFT_OK;
+    }
+    if (nk > 0 && nc == 0 && nr == 1) {
+        const abft_flag &fr = rep->flag_r[0];
+        int64_t i = fr.a, c = fr.b, found = -1, cnt = 0;
+        int64_t r = is_data_row(i) ? i % g.br : (i - g.m) % g.br;
+        for (int64_t j = c; j < g.N; j += g.bc)
+            if (col_erased_h(kn, nk, r, j, g.br)) { found = j; ++cnt; }
+        if (cnt != 1) return ABFT_OK;
+        out->cls = kind(i, found); out->i = i; out->j = found; out->dir = ABFT_DIR_ROW;
+        return ABFT_OK;
+    }
+    if (nk > 0 && nc == 1 && nr == 0) {
+        const abft_flag &fc = rep->flag_c[0];
+        int64_t r = fc.a, j = fc.b, found = -1, cnt = 0;
+        int64_t c = is_data_col(j) ? j % g.bc : (j - g.n) % g.bc;
+        for (int64_t i = r; i < g.M; i += g.br)
+            if (row_erased_h(kn, nk, i, c, g.bc)) { found = i; ++cnt; }
+        if (cnt != 1) return ABFT_OK;
+        out->cls = kind(found, j); out->i = found; out->j = j; out->dir = ABFT_DIR_COL;
+        return ABFT_OK;
+    }
+    return ABFT_OK;  // MULTI
+}
+
+static int to_erasures(const Geom &g, const abft_rect *known, int n_known, Erasures *er) {
+    if (n_known < 0 || n_known > 4 || (n_known > 0 && !known)) return ABFT_E_ARG;
+    er->n = n_known;
+    for (int q = 0; q < n_known; ++q) {
+        if (check_rect(g, known[q])) return ABFT_E_ARG;
+        er->i0[q] = known[q].i0; er->j0[q] = known[q].j0; er->h[q] = known[q].h; er->w[q] = known[q].w;
+    }
+    return ABFT_OK;
+}
+
+}  // namespace abft
+
+using namespace abft;
+
+extern "C" {
+
+int abft_split_count(int32_t dtype) { return dtype == ABFT_BF16 ? 3 : 1; }
+
+size_t abft_workspace_size(const abft_problem *p) {
+    if (check_problem(p) != ABFT_OK) return 0;
+    return ws_layout(p).total;
+}
+
+int abft_encode(const abft_problem *p, void *A_f, void *B_f, void *ws, void *stream) {
+    int st = check_problem(p);
+    if (st) return st;
+    if ((st = check_operands(p, A_f, B_f))) return st;
+    if (!ws) return ABFT_E_WORKSPACE;
+    return launch_encode(p, A_f, B_f, (char *)ws, (hipStream_t)stream);
+}
+
+int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, void *stream) {
+    int st = check_problem(p);
+    if (st) return st;
+    if (flags & ~ABFT_PLAIN) return ABFT_E_ARG;
+    if ((st = check_operands(p, A_f, B_f))) return st;
+    if ((st = check_c(p, C_f, flags & ABFT_PLAIN))) return st;
+    return launch_gemm(p, A_f, B_f, C_f, flags, (hipStream_t)stream);
+}
+
+int abft_verify(const abft_problem *p, const void *C_f, const abft_rect *known, int n_known, void *ws,
+                abft_report *host_out, void *stream) {
+    int st = check_problem(p);
+    if (st) return st;
+    if ((st = check_c(p, C_f, false))) return st;
+    if (!ws) return ABFT_E_WORKSPACE;
+    Geom g = geom_of(p);
+    Erasures er;
+    if ((st = to_erasures(g, known, n_known, &er))) return st;
+    if ((st = launch_verify(p, C_f, er, (char *)ws, (hipStream_t)stream))) return st;
+    if (host_out) {
+        WsLayout L = ws_layout(p);
+        ABFT_HIP(hipMemcpyAsync(host_out, (char *)ws + L.report, sizeof(abft_report), hipMemcpyDeviceToHost,
+                                (hipStream_t)stream));
+    }
+    return ABFT_OK;
+}
+
+int abft_classify(const abft_problem *p, const abft_report *report, const abft_rect *known, int n_known,
+                  abft_location *out) {
+    int st = check_problem(p);
+    if (st) return st;
+    if (!report || !out) return ABFT_E_ARG;
+    Geom g = geom_of(p);
+    Erasures er;
+    if ((st = to_erasures(g, known, n_known, &er))) return st;
+    // The device writes flags in arrival order; classify a sorted copy so the
+    // outcome does not depend on it.
+    abft_report rep = *report;
+    int64_t kc = std::min<int64_t>(rep.n_flag_c, ABFT_MAX_FLAGS), kr = std::min<int64_t>(rep.n_flag_r, ABFT_MAX_FLAGS);
+    auto less = [](const abft_flag &x, const abft_flag &y) { return x.a < y.a || (x.a == y.a && x.b < y.b); };
+    std::sort(rep.flag_c, rep.flag_c + kc, less);
+    std::sort(rep.flag_r, rep.flag_r + kr, less);
+    return classify(p, &rep, known, n_known, out);
+}
+
+int abft_correct(const abft_problem *p, void *C_f, const abft_location *loc, void *stream) {
+    int st = check_problem(p);
+    if (st) return st;
+    if ((st = check_c(p, C_f, false))) return st;
+    if (!loc) return ABFT_E_ARG;
+    if (loc->cls == ABFT_CLS_CLEAN) return ABFT_OK;
+    if (loc->cls == ABFT_CLS_MULTI) return ABFT_E_UNCORRECTABLE;
+    if (loc->cls != ABFT_CLS_DATA && loc->cls != ABFT_CLS_CHECKSUM) return ABFT_E_ARG;
+    Geom g = geom_of(p);
+    if (loc->i < 0 || loc->i >= g.M || loc->j < 0 || loc->j >= g.N) return ABFT_E_ARG;
+    if (loc->dir != ABFT_DIR_COL && loc->dir != ABFT_DIR_ROW) return ABFT_E_ARG;
+    return launch_correct(p, C_f, loc->i, loc->j, loc->dir, (hipStream_t)stream);
+}
+
+int abft_recover_block(const abft_problem *p, void *C_f, abft_rect e, int use_rows, void *stream) {
+    int st = check_problem(p);
+    if (st) return st;
+    if ((st = check_c(p, C_f, false))) return st;
+    Geom g = geom_of(p);
+    if ((st = check_rect(g, e))) return st;
+    if (!use_rows && e.h > g.br) return ABFT_E_UNRECOVERABLE;
+    if (use_rows && e.w > g.bc) return ABFT_E_UNRECOVERABLE;
+    return launch_recover(p, C_f, e, use_rows, (hipStream_t)stream);
+}
+
+int abft_inject_flip(const abft_problem *p, void *C_f, int64_t i, int64_t j, int bit, void *stream) {
+    int st = check_problem(p);
+    if (st) return st;
+    if ((st = check_c(p, C_f, false))) return st;
+    Geom g = geom_of(p);
+    if (i < 0 || i >= g.M || j < 0 || j >= g.N) return ABFT_E_ARG;
+    if (bit < 0 || bit >= (int)(8 * c_size(p->dtype))) return ABFT_E_ARG;
+    return launch_inject_flip(p, C_f, i, j, bit, (hipStream_t)stream);
+}
+
+int abft_inject_erase(const abft_problem *p, void *C_f, abft_rect e, int nan_fill, void *stream) {
+    int st = check_problem(p);
+    if (st) return st;
+    if ((st = check_c(p, C_f, false))) return st;
+    Geom g = geom_of(p);
+    if ((st = check_rect(g, e))) return st;
+    return launch_inject_erase(p, C_f, e, nan_fill, (hipStream_t)stream);
+}
+
+int abft_fill_uniform(int32_t dtype, int64_t rows, int64_t cols, int64_t ld, int transpose, uint64_t seed,
+                      int32_t stream_id, void *dst, void *stream) {
+    if (dtype != ABFT_F64 && dtype != ABFT_F32) return ABFT_E_ARG;
+    if (rows < 1 || cols < 1 || !dst) return ABFT_E_ARG;
+    if (ld < (transpose ? rows : cols)) return ABFT_E_ARG;
+    return launch_fill_uniform(dtype, rows, cols, ld, transpose, seed, stream_id, dst, (hipStream_t)stream);
+}
+
+int abft_last_hip_error(void) { return g_last_hip_error; }
+
+const char *abft_status_string(int s) {
+    switch (s) {
+    case ABFT_OK: return "ok";
+    case ABFT_FAULT_DETECTED: return "fault detected";
+    case ABFT_E_ARG: return "invalid argument";
+    case ABFT_E_HIP: return "HIP runtime error";
+    case ABFT_E_UNCORRECTABLE: return "uncorrectable: the failed relations do not name one element";
+    case ABFT_E_UNRECOVERABLE: return "unrecoverable: more unknowns than checksum relations";
+    case ABFT_E_WORKSPACE: return "workspace missing";
+    case ABFT_E_UNSUPPORTED: return "unsupported combination";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

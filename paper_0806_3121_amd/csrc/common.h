@@ -1,0 +1,143 @@
+// Internal declarations shared by the libabft HIP sources (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "abft.h"
+
+namespace abft {
+
+// ------------------------------------------------------------------ types
+struct bf16 { uint16_t bits; };
+
+__host__ __device__ inline float bf16_to_f32(uint16_t b) {
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+// Round-to-nearest-even binary32 -> bfloat16 bits (NaN stays NaN).
+__host__ __device__ inline uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40u);
+    uint32_t rounding = 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)((u + rounding) >> 16);
+}
+
+template <typename T> struct elem;
+template <> struct elem<double> {
+    __device__ static double load(const double *p) { return *p; }
+};
+template <> struct elem<float> {
+    __device__ static double load(const float *p) { return (double)*p; }
+};
+template <> struct elem<uint16_t> {   // bfloat16 storage
+    __device__ static double load(const uint16_t *p) { return (double)bf16_to_f32(*p); }
+};
+
+inline size_t dtype_size(int dt) {
+    switch (dt) {
+    case ABFT_F64: return 8;
+    case ABFT_F32: return 4;
+    case ABFT_BF16: return 2;
+    case ABFT_FP8_E4M3: return 1;
+    default: return 0;
+    }
+}
+inline size_t c_size(int dt) { return dt == ABFT_F64 ? 8 : 4; }
+
+// ------------------------------------------------------------------ geometry
+struct Geom {
+    int64_t m, n, k, br, bc, S;
+    int64_t M, N;        // encoded sizes m + S*br, n + S*bc
+    int64_t Gr, Gc;      // m / br, n / bc
+};
+inline Geom geom_of(const abft_problem *p) {
+    Geom g;
+    g.m = p->m; g.n = p->n; g.k = p->k; g.br = p->br; g.bc = p->bc;
+    g.S = abft_split_count(p->dtype);
+    g.M = g.m + g.S * g.br;
+    g.N = g.n + g.S * g.bc;
+    g.Gr = g.m / g.br;
+    g.Gc = g.n / g.bc;
+    return g;
+}
+
+// Up to 4 known erased rectangles, passed to kernels by value.
+struct Erasures {
+    int n;
+    int64_t i0[4], j0[4], h[4], w[4];
+};
+
+// Does column relation (r, j) (members: rows i == r mod br, column j) hold an erased element?
+__device__ inline bool col_rel_erased(const Erasures &e, int64_t r, int64_t j, int64_t br) {
+    for (int q = 0; q < e.n; ++q) {
+        if (j < e.j0[q] || j >= e.j0[q] + e.w[q]) continue;
+        if (e.h[q] >= br) return true;
+        int64_t off = ((r - e.i0[q]) % br + br) % br;   // first row >= i0 with residue r is i0 + off
+        if (off < e.h[q]) return true;
+    }
+    return false;
+}
+__device__ inline bool row_rel_erased(const Erasures &e, int64_t i, int64_t c, int64_t bc) {
+    for (int q = 0; q < e.n; ++q) {
+        if (i < e.i0[q] || i >= e.i0[q] + e.h[q]) continue;
+        if (e.w[q] >= bc) return true;
+        int64_t off = ((c - e.j0[q]) % bc + bc) % bc;
+        if (off < e.w[q]) return true;
+    }
+    return false;
+}
+
+// ------------------------------------------------------------------ workspace
+// All offsets in bytes from ws, 256-byte aligned.
+struct WsLayout {
+    size_t na, na_abs, nb, nb_abs;   // det statistics (double)
+    size_t qr, qc, nv, nw;           // stat statistics (double)
+    size_t grpA, grpB;               // per-residue group sums of |A| (or A^2) and of |B| (double, br*k / bc*k)
+    size_t partial;                  // two-level reduction partials (double)
+    size_t report;                   // abft_report
+    size_t total;
+    size_t partial_bytes;
+};
+WsLayout ws_layout(const abft_problem *p);
+
+// Number of partitions used for the row-group sums of a (G groups, b residues, cols) sum.
+int64_t group_partitions(int64_t G, int64_t b, int64_t cols);
+
+// ------------------------------------------------------------------ error plumbing
+void set_hip_error(hipError_t e);
+#define ABFT_HIP(call)                                        \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) { ::abft::set_hip_error(e_); return ABFT_E_HIP; } \
+    } while (0)
+#define ABFT_LAUNCHED()                                       \
+    do {                                                      \
+        hipError_t e_ = hipGetLastError();                    \
+        if (e_ != hipSuccess) { ::abft::set_hip_error(e_); return ABFT_E_HIP; } \
+    } while (0)
+
+// ------------------------------------------------------------------ launchers (return abft_status)
+int launch_encode(const abft_problem *p, void *A_f, void *B_f, char *ws, hipStream_t s);
+int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, hipStream_t s);
+int launch_verify(const abft_problem *p, const void *C_f, const Erasures &er, char *ws, hipStream_t s);
+int launch_correct(const abft_problem *p, void *C_f, int64_t i, int64_t j, int dir, hipStream_t s);
+int launch_recover(const abft_problem *p, void *C_f, abft_rect e, int use_rows, hipStream_t s);
+int launch_inject_flip(const abft_problem *p, void *C_f, int64_t i, int64_t j, int bit, hipStream_t s);
+int launch_inject_erase(const abft_problem *p, void *C_f, abft_rect e, int nan_fill, hipStream_t s);
+int launch_fill_uniform(int32_t dtype, int64_t rows, int64_t cols, int64_t ld, int transpose, uint64_t seed,
+                        int32_t stream_id, void *dst, hipStream_t s);
+
+// Threshold coefficients shared by encode (statistics) and verify.
+struct TauCoef {
+    int mode;
+    double cc, cr;       // det: tau_c = cc*na_abs[r]*nb[j], tau_r = cr*na[i]*nb_abs[c]; stat: coef*lambda^2
+    double lambda;
+};
+TauCoef tau_coef(const abft_problem *p);
+
+}  // namespace abft

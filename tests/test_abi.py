@@ -1,0 +1,135 @@
+"""CPU tests of the C-ABI library: it loads without a GPU, exports every
+symbol include/abft.h declares, rejects bad arguments before any launch, and
+its host-side classification takes the oracle's decisions on the same reports."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_0806_3121_amd import abft, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+NULL_STREAM = None
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "abft.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(abft_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = abft.lib()
+    names = header_functions()
+    assert len(names) >= 13
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_struct_sizes_match_header_layout():
+    assert C.sizeof(abft.abft_problem) == 4 + 4 + 8 * 8 + 8 * 2
+    assert C.sizeof(abft.abft_flag) == 32
+    assert C.sizeof(abft.abft_report) == 8 * 5 + 8 * 2 + 2 * 64 * 32
+    assert C.sizeof(abft.abft_location) == 24
+
+
+def test_split_counts():
+    assert abft.split_count(abft.ABFT_F64) == 1
+    assert abft.split_count(abft.ABFT_F32) == 1
+    assert abft.split_count(abft.ABFT_BF16) == 3
+
+
+def _call(name, *args):
+    return getattr(abft.lib(), name)(*args)
+
+
+@pytest.mark.parametrize("field,value", [("m", 0), ("br", 3), ("bc", 7), ("k", -1), ("dtype", 9), ("tau_mode", 5),
+                                         ("br", 512)])
+def test_bad_problem_rejected_before_launch(field, value):
+    p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1)
+    setattr(p, field, value)
+    fake = C.c_void_p(256)     # never dereferenced: the checks fail first
+    assert abft.workspace_size(p) == 0
+    assert _call("abft_gemm", C.byref(p), fake, fake, fake, 0, NULL_STREAM) == abft.ABFT_E_ARG
+
+
+def test_layout_and_alignment_rejected():
+    fake = C.c_void_p(256)
+    p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1, lda=255)
+    assert _call("abft_encode", C.byref(p), fake, fake, fake, NULL_STREAM) == abft.ABFT_E_ARG
+    p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1, ldc=256)          # < n + bc
+    assert _call("abft_gemm", C.byref(p), fake, fake, fake, 0, NULL_STREAM) == abft.ABFT_E_ARG
+    p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1)
+    assert _call("abft_gemm", C.byref(p), C.c_void_p(8), fake, fake, 0, NULL_STREAM) == abft.ABFT_E_ARG
+    assert _call("abft_gemm", C.byref(p), fake, fake, fake, 8, NULL_STREAM) == abft.ABFT_E_ARG   # unknown flag
+    assert _call("abft_encode", C.byref(p), fake, fake, None, NULL_STREAM) == abft.ABFT_E_WORKSPACE
+    p = abft.problem(abft.ABFT_F64, 256, 256, 251, 1, 1, lda=252, ldb=252)  # k*8 not a multiple of 16
+    assert _call("abft_encode", C.byref(p), fake, fake, fake, NULL_STREAM) == abft.ABFT_E_ARG
+
+
+def test_unrecoverable_and_bad_rects_rejected():
+    fake = C.c_void_p(256)
+    p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1)
+    r = abft.abft_rect(0, 0, 64, 64)
+    assert _call("abft_recover_block", C.byref(p), fake, r, 0, NULL_STREAM) == abft.ABFT_E_UNRECOVERABLE
+    assert _call("abft_recover_block", C.byref(p), fake, r, 1, NULL_STREAM) == abft.ABFT_E_UNRECOVERABLE
+    p = abft.problem(abft.ABFT_F64, 256, 256, 256, 64, 64)
+    assert _call("abft_recover_block", C.byref(p), fake, abft.abft_rect(300, 0, 64, 64), 0, NULL_STREAM) == abft.ABFT_E_ARG
+    assert _call("abft_inject_flip", C.byref(p), fake, 0, 0, 64, NULL_STREAM) == abft.ABFT_E_ARG
+    assert _call("abft_inject_flip", C.byref(p), fake, 320, 0, 3, NULL_STREAM) == abft.ABFT_E_ARG
+
+
+def test_correct_refuses_multi_and_ignores_clean():
+    fake = C.c_void_p(256)
+    p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1)
+    loc = abft.abft_location(abft.ABFT_CLS_MULTI, 0, 0, 0)
+    assert _call("abft_correct", C.byref(p), fake, C.byref(loc), NULL_STREAM) == abft.ABFT_E_UNCORRECTABLE
+    loc = abft.abft_location(abft.ABFT_CLS_CLEAN, 0, -1, -1)
+    assert _call("abft_correct", C.byref(p), fake, C.byref(loc), NULL_STREAM) == abft.ABFT_OK
+
+
+# ---------------------------------------------------------------- classification vs the oracle
+def _to_lib_report(orep):
+    rep = abft.abft_report()
+    rep.n_flag_c, rep.n_flag_r = orep.n_flag_c, orep.n_flag_r
+    fc, fr = orep.flags_c(), orep.flags_r()
+    # the device writes flags in arbitrary order: feed them reversed
+    for q, (a, b, d, t) in enumerate(reversed(fc)):
+        rep.flag_c[q] = abft.abft_flag(a, b, d, t)
+    for q, (a, b, d, t) in enumerate(reversed(fr)):
+        rep.flag_r[q] = abft.abft_flag(a, b, d, t)
+    return rep
+
+
+@pytest.mark.parametrize("m,n,br,bc", [(8, 8, 1, 1), (8, 12, 2, 3), (16, 16, 4, 4)])
+def test_classification_matches_oracle(orc, m, n, br, bc):
+    k = 5
+    A = synth.uniform_ints(1, 0, m, k, -4, 4)
+    B = synth.uniform_ints(1, 1, k, n, -4, 4)
+    Af, Bf, Cf = orc.protected_product(A, B, br, bc)
+    p = abft.problem(abft.ABFT_F64, m, n, k, br, bc, tau_mode=abft.ABFT_TAU_EXACT)
+    tc = np.zeros((br, n + bc))
+    tr = np.zeros((m + br, bc))
+    cases = []
+    for i in range(m + br):
+        for j in range(n + bc):
+            cases.append(([(i, j, 3.0)], None))
+    cases.append(([(0, 0, 1.0), (1, 1, 1.0)], None))
+    cases.append(([(0, 0, 1.0), (0, 1, 2.0)], None))
+    rect = (0, 0, br, bc)
+    cases.append(([(br, bc, 1.0)], [rect]))
+    cases.append(([(m - 1, 0, 1.0)], [rect]))
+    cases.append(([(0, n - 1, 1.0)], [rect]))
+    for errs, known in cases:
+        Cx = Cf.copy()
+        for (i, j, d) in errs:
+            Cx[i, j] += d
+        if known:
+            i0, j0, h, w = known[0]
+            Cx[i0:i0 + h, j0:j0 + w] = 0
+        _, _, orep = orc.verify(Cx, m, n, br, bc, tc, tr, erasures=known)
+        ocls, oi, oj, od = orc.classify(orep, m, n, br, bc, erasures=known)
+        loc = abft.classify(p, _to_lib_report(orep), known=known)
+        assert (loc.cls, loc.i, loc.j, loc.dir) == (ocls, oi, oj, od), (errs, known)
