@@ -369,7 +369,9 @@ enum { ORC_DIR_COL = 0, ORC_DIR_ROW = 1 };
  * (i mod br, j) and one row relation (i, j mod bc).  Its residuals are
  * +delta where it is a summand and -delta where it is the stored total, so
  * sc*Dc and sr*Dr (sc = +1 for i < m, else -1; sr = +1 for j < n, else -1)
- * agree to within tau_c + tau_r when both are finite.
+ * agree to within tau_c + tau_r plus the rounding of the two residual sums,
+ * which both hold the bad value (gamma_{G+2} |delta| each), when both are
+ * finite.
  * With known erasures, the relation through the erased rectangle is not
  * checked; a lone flag on one side then names the element when exactly one
  * candidate lies on an excluded relation of the other side.
@@ -386,8 +388,15 @@ int orc_classify(int64_t m, int64_t n, int64_t br, int64_t bc, const orc_report 
         if (i % br != r || j % bc != c) return ORC_MULTI;
         double dc = rep->fc_d[0], dr = rep->fr_d[0];
         if (isfinite(dc) && isfinite(dr)) {
+            /* each residual also carries the rounding of its own sum, which
+             * holds the bad value: up to gamma_{G+2} |delta| (large when an
+             * exponent bit flipped) */
+            const double u64 = ldexp(1.0, -53);
+            double big = fmax(fabs(dc), fabs(dr));
+            double tol = rep->fc_t[0] + rep->fr_t[0] +
+                         (orc_gamma((double)(m / br + 2), u64) + orc_gamma((double)(n / bc + 2), u64)) * big;
             double sc = (i < m) ? 1.0 : -1.0, sr = (j < n) ? 1.0 : -1.0;
-            if (!(fabs(sc * dc - sr * dr) <= rep->fc_t[0] + rep->fr_t[0])) return ORC_MULTI;
+            if (!(fabs(sc * dc - sr * dr) <= tol)) return ORC_MULTI;
         }
         *oi = i; *oj = j; *odir = ORC_DIR_COL;
         return (i < m && j < n) ? ORC_DATA : ORC_CHECKSUM;

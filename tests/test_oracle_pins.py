@@ -395,3 +395,29 @@ def test_e4m3_scale_is_largest_power_of_two(orc):
         a = max(0.25, float(np.float32(amax)))
         assert a * 2.0 ** e <= 448.0 < a * 2.0 ** (e + 1)
     assert orc.e4m3_scale_exp(np.zeros(4, dtype=np.float32)) == 0
+
+
+def test_exponent_bit_flip_located_on_real_data(orc):
+    """An exponent-bit flip makes |delta| huge, so both residuals also carry
+    the rounding of a sum that holds the bad value; the single error must
+    still be located (and the element rebuilt within tau)."""
+    m, n, k, br, bc = 64, 48, 96, 8, 4
+    A = synth.uniform(31, 0, m, k)
+    B = synth.uniform(31, 1, k, n)
+    Af, Bf, Cf = orc.protected_product(A, B, br, bc)
+    tc, tr = orc.tau_det(Af, Bf, m, n, br, bc)
+    found = 0
+    for t, (i, j) in enumerate([(5, 7), (63, 0), (m + 2, 9), (17, n + 3), (m + 7, n + 1), (30, 30)]):
+        for beta in range(52, 62):
+            Cx = Cf.copy()
+            Cx.view(np.uint64)[i, j] ^= np.uint64(1 << beta)
+            if abs(Cx[i, j] - Cf[i, j]) <= 2 * max(tc[i % br, j], tr[i, j % bc]):
+                continue
+            _, _, rep = orc.verify(Cx, m, n, br, bc, tc, tr)
+            cls, li, lj, d = orc.classify(rep, m, n, br, bc)
+            assert (li, lj) == (i, j), (i, j, beta, cls)
+            if np.isfinite(Cx[i, j]):
+                v = orc.rebuild_value(Cx, m, n, br, bc, i, j, d)
+                assert abs(v - Cf[i, j]) <= tc[i % br, j]
+            found += 1
+    assert found >= 50
