@@ -157,8 +157,13 @@ static int classify(const abft_problem *p, const abft_report *rep, const abft_re
         int64_t cj = is_data_col(j) ? j % g.bc : (j - g.n) % g.bc;
         if (ri != r || cj != c) return ABFT_OK;  // MULTI
         if (std::isfinite(fc.d) && std::isfinite(fr.d)) {
+            // Both residual sums contain the bad value, so each is also off by
+            // up to gamma_{G+S+1} |delta| (large after an exponent-bit flip).
+            const double u64 = std::ldexp(1.0, -53);
+            double big = std::max(std::fabs(fc.d), std::fabs(fr.d));
+            double tol = fc.tau + fr.tau + (gamma_n((double)(g.Gr + g.S + 1), u64) + gamma_n((double)(g.Gc + g.S + 1), u64)) * big;
             double sc = is_data_row(i) ? 1.0 : -1.0, sr = is_data_col(j) ? 1.0 : -1.0;
-            if (!(std::fabs(sc * fc.d - sr * fr.d) <= fc.tau + fr.tau)) return ABFT_OK;  // MULTI
+            if (!(std::fabs(sc * fc.d - sr * fr.d) <= tol)) return ABFT_OK;  // MULTI
         }
         out->cls = kind(i, j); out->i = i; out->j = j; out->dir = ABFT_DIR_COL;
         return ABFT_OK;

@@ -11,7 +11,7 @@
 //
 // MFMA 16x16x4 f64 operand layout (lane l of 64): A[l % 16][l / 16],
 // B[l / 16][l % 16]; the 4 accumulator values of lane l are
-// C[4 * (l / 16) + v][l % 16], v = 0..3.
+// C[l / 16 + 4 * v][l % 16], v = 0..3.
 #include "common.h"
 
 namespace abft {
@@ -128,8 +128,8 @@ __global__ __launch_bounds__(f64gemm::THREADS, 1) void k_gemm_f64(const double *
         }
     }
 
-    // epilogue: lane holds C[4*(lane/16) + v][lane % 16] of each 16 x 16 tile
-    const int crow = 4 * (lane / 16), ccol = lane % 16;
+    // epilogue: lane holds C[lane/16 + 4*v][lane % 16] of each 16 x 16 tile
+    const int crow = lane / 16, ccol = lane % 16;
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
 #pragma unroll
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(f64gemm::THREADS, 1) void k_gemm_f64(const double *
             int64_t gc = col0 + wn * (BN / WN) + b * 16 + ccol;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int64_t gr = row0 + wm * (BM / WM) + a * 16 + crow + v;
+                int64_t gr = row0 + wm * (BM / WM) + a * 16 + crow + 4 * v;
                 if (gr < M && gc < N) C[gr * ldc + gc] = acc[a][b][v];
             }
         }
