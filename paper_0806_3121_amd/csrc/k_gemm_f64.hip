@@ -1,167 +1,80 @@
-// Protected product C_f = A_f B_f in binary64 on the gfx950 matrix cores
-// (v_mfma_f64_16x16x4_f64).  A_f is row-major (k contiguous) and B_f is
-// column-major (k contiguous), so both operands stream k-contiguous rows.
+// Protected product C_f = A_f B_f (Eq. ABFT-GEMM) dispatch.
 //
-// Block tile BM x BN with 256 threads (4 waves in a 2 x 2 grid, 64 x 64 per
-// wave = 4 x 4 MFMA tiles of 16 x 16).  K advances in BK-wide slabs staged in
-// LDS; the next slab is loaded into registers while the current one feeds the
-// matrix cores.  Inside a 16-wide k group each lane reads four consecutive k
-// of its row (one 32-byte LDS read) and feeds them to four MFMAs; A and B use
-// the same k permutation, so every product a_il * b_lj is formed exactly once.
-//
-// MFMA 16x16x4 f64 operand layout (lane l of 64): A[l % 16][l / 16],
-// B[l / 16][l % 16]; the 4 accumulator values of lane l are
-// C[l / 16 + 4 * v][l % 16], v = 0..3.
-#include "common.h"
+// The data part and any thick checksum block (b > kSliverMaxB) run on the
+// matrix cores (gemm_f64_kernel.h).  A thin checksum block (b <= kSliverMaxB,
+// e.g. the classic b = 1) would occupy a whole row or column of tiles for a
+// few useful rows, so it is computed instead by the skinny-product kernel
+// (k_sliver.hip), which streams the other operand once.
+#include "gemm_f64_kernel.h"
 
 namespace abft {
 
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef double v2d __attribute__((ext_vector_type(2)));
+int launch_sliver_rows_f64(const Geom &g, const double *Acs, int64_t ldacs, const double *Bt, int64_t ldb, double *C,
+                           int64_t ldc, hipStream_t s);
+int launch_sliver_cols_f64(const Geom &g, int64_t rows, const double *A, int64_t lda, const double *Bcs, int64_t ldbcs,
+                           double *C, int64_t ldc, hipStream_t s);
 
-namespace f64gemm {
-constexpr int BM = 128, BN = 128, BK = 32, PAD = 2;
-constexpr int LDSROW = BK + PAD;               // doubles per LDS row
-constexpr int THREADS = 256;
-constexpr int WM = 2, WN = 2;                  // wave grid
-constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
-constexpr int VPR = BK / 2;                    // 16-byte vectors per tile row
-constexpr int ROWS_PER_PASS = THREADS / VPR;   // tile rows loaded per pass
-constexpr int PASSES_A = BM / ROWS_PER_PASS, PASSES_B = BN / ROWS_PER_PASS;
-constexpr int GROUP_M = 8;                     // tile-row grouping for L2 reuse
-}  // namespace f64gemm
+constexpr int64_t kSliverMaxB = 8;
 
-// Map the linear workgroup id to a C tile: ids are first spread back from the
-// round-robin XCD dispatch (workgroup w runs on XCD w mod 8) so each XCD owns a
-// contiguous range, then ranges are walked in GROUP_M-row bands so that the
-// tiles an XCD runs together share A rows and B columns in its L2.
-__device__ inline void tile_of(int64_t wg, int64_t nwg, int64_t tiles_m, int64_t tiles_n, int64_t &tm, int64_t &tn) {
-    const int64_t nxcd = 8;
-    int64_t id = wg;
-    if (nwg % nxcd == 0) id = (wg % nxcd) * (nwg / nxcd) + wg / nxcd;
-    const int64_t G = f64gemm::GROUP_M;
-    int64_t band = id / (G * tiles_n);
-    int64_t first_m = band * G;
-    int64_t gm = min(tiles_m - first_m, G);
-    int64_t in = id - band * G * tiles_n;
-    tm = first_m + in % gm;
-    tn = in / gm;
+// Tile candidates: per-tile efficiency measured on MI355X at 8192^3 / 9216^2 x 8192,
+// and resident blocks per CU (LDS- and register-limited).
+using F64_256x128 = F64Tile<256, 128, 16, 4, 2>;
+using F64_128x128 = F64Tile<128, 128, 16, 2, 2>;
+using F64_128x96 = F64Tile<128, 96, 16, 2, 2, 8, 2>;
+using F64_96x96 = F64Tile<96, 96, 16, 2, 2, 8, 2>;
+
+struct TileChoice { int id; int bm, bn, per_cu; double eff; };
+static const TileChoice kF64Tiles[] = {
+    {0, 256, 128, 1, 0.818}, {1, 128, 128, 2, 0.787}, {2, 128, 96, 2, 0.80}, {3, 96, 96, 2, 0.76},
+};
+
+// Estimated time ~ rounds of resident blocks x time per round (tile flops x
+// blocks per CU / efficiency); the smallest wins.  256 CUs.
+static int choose_f64_tile(int64_t M, int64_t N) {
+    double best = 0;
+    int pick = 0;
+    for (const TileChoice &t : kF64Tiles) {
+        int64_t tiles = ((M + t.bm - 1) / t.bm) * ((N + t.bn - 1) / t.bn);
+        int64_t slots = 256 * t.per_cu;
+        double rounds = (double)((tiles + slots - 1) / slots);
+        double cost = rounds * (double)t.bm * t.bn * t.per_cu / t.eff;
+        if (best == 0 || cost < best) { best = cost; pick = t.id; }
+    }
+    return pick;
 }
 
-__global__ __launch_bounds__(f64gemm::THREADS, 1) void k_gemm_f64(const double *__restrict__ A, int64_t lda,
-                                                                  const double *__restrict__ Bt, int64_t ldb,
-                                                                  double *__restrict__ C, int64_t ldc, int64_t M,
-                                                                  int64_t N, int64_t K) {
-    using namespace f64gemm;
-    __shared__ double As[BM * LDSROW];
-    __shared__ double Bs[BN * LDSROW];
-
-    const int64_t tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
-    int64_t tm, tn;
-    tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
-    const int64_t row0 = tm * BM, col0 = tn * BN;
-
-    const int tid = threadIdx.x;
-    const int lane = tid % 64, wave = tid / 64;
-    const int wm = wave / WN, wn = wave % WN;
-
-    // global -> register staging: thread loads vector v of tile rows rr + p*ROWS_PER_PASS
-    const int lr = tid / VPR, lv = tid % VPR;
-    v2d ra[PASSES_A], rb[PASSES_B];
-
-    auto load_tiles = [&](int64_t k0) {
-#pragma unroll
-        for (int p = 0; p < PASSES_A; ++p) {
-            int64_t gr = row0 + lr + p * ROWS_PER_PASS, gk = k0 + 2 * lv;
-            if (gr < M && gk < K) ra[p] = *(const v2d *)(A + gr * lda + gk);
-            else ra[p] = v2d{0.0, 0.0};
-        }
-#pragma unroll
-        for (int p = 0; p < PASSES_B; ++p) {
-            int64_t gc = col0 + lr + p * ROWS_PER_PASS, gk = k0 + 2 * lv;
-            if (gc < N && gk < K) rb[p] = *(const v2d *)(Bt + gc * ldb + gk);
-            else rb[p] = v2d{0.0, 0.0};
-        }
-    };
-    auto store_tiles = [&]() {
-#pragma unroll
-        for (int p = 0; p < PASSES_A; ++p) *(v2d *)(As + (lr + p * ROWS_PER_PASS) * LDSROW + 2 * lv) = ra[p];
-#pragma unroll
-        for (int p = 0; p < PASSES_B; ++p) *(v2d *)(Bs + (lr + p * ROWS_PER_PASS) * LDSROW + 2 * lv) = rb[p];
-    };
-
-    v4d acc[TM][TN];
-#pragma unroll
-    for (int a = 0; a < TM; ++a)
-#pragma unroll
-        for (int b = 0; b < TN; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-
-    const int lrow = lane % 16, lk = 4 * (lane / 16);
-    const double *Aw = As + (wm * (BM / WM) + lrow) * LDSROW + lk;
-    const double *Bw = Bs + (wn * (BN / WN) + lrow) * LDSROW + lk;
-
-    const int64_t nk = (K + BK - 1) / BK;
-    load_tiles(0);
-    store_tiles();
-    __syncthreads();
-    for (int64_t kt = 0; kt < nk; ++kt) {
-        if (kt + 1 < nk) load_tiles((kt + 1) * BK);
-#pragma unroll
-        for (int kg = 0; kg < BK; kg += 16) {
-            v4d fa[TM], fb[TN];
-#pragma unroll
-            for (int a = 0; a < TM; ++a) fa[a] = *(const v4d *)(Aw + a * 16 * LDSROW + kg);
-#pragma unroll
-            for (int b = 0; b < TN; ++b) fb[b] = *(const v4d *)(Bw + b * 16 * LDSROW + kg);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int a = 0; a < TM; ++a)
-#pragma unroll
-                    for (int b = 0; b < TN; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a][q], fb[b][q], acc[a][b], 0, 0, 0);
-        }
-        __syncthreads();
-        if (kt + 1 < nk) {
-            store_tiles();
-            __syncthreads();
-        }
+static int gemm_f64_main(const double *A, int64_t lda, const double *Bt, int64_t ldb, double *C, int64_t ldc,
+                         int64_t M, int64_t N, int64_t K, hipStream_t s) {
+    switch (choose_f64_tile(M, N)) {
+    case 0: return launch_gemm_f64_tile<F64_256x128>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
+    case 1: return launch_gemm_f64_tile<F64_128x128>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
+    case 2: return launch_gemm_f64_tile<F64_128x96>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
+    default: return launch_gemm_f64_tile<F64_96x96>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
     }
-
-    // epilogue: lane holds C[lane/16 + 4*v][lane % 16] of each 16 x 16 tile
-    const int crow = lane / 16, ccol = lane % 16;
-#pragma unroll
-    for (int a = 0; a < TM; ++a) {
-#pragma unroll
-        for (int b = 0; b < TN; ++b) {
-            int64_t gc = col0 + wn * (BN / WN) + b * 16 + ccol;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                int64_t gr = row0 + wm * (BM / WM) + a * 16 + crow + 4 * v;
-                if (gr < M && gc < N) C[gr * ldc + gc] = acc[a][b][v];
-            }
-        }
-    }
-}
-
-int launch_gemm_f64(const double *A, int64_t lda, const double *Bt, int64_t ldb, double *C, int64_t ldc, int64_t M,
-                    int64_t N, int64_t K, hipStream_t s) {
-    using namespace f64gemm;
-    int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-    if (tiles > INT32_MAX) return ABFT_E_ARG;
-    k_gemm_f64<<<(unsigned)tiles, THREADS, 0, s>>>(A, lda, Bt, ldb, C, ldc, M, N, K);
-    ABFT_LAUNCHED();
-    return ABFT_OK;
 }
 
 int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, hipStream_t s) {
     Geom g = geom_of(p);
-    int64_t M = (flags & ABFT_PLAIN) ? g.m : g.M;
-    int64_t N = (flags & ABFT_PLAIN) ? g.n : g.N;
+    const bool plain = flags & ABFT_PLAIN;
+    const bool thin_r = !plain && g.S * g.br <= kSliverMaxB;
+    const bool thin_c = !plain && g.S * g.bc <= kSliverMaxB;
+    int64_t Mm = (plain || thin_r) ? g.m : g.M;
+    int64_t Nm = (plain || thin_c) ? g.n : g.N;
+    int st;
     switch (p->dtype) {
-    case ABFT_F64:
-        return launch_gemm_f64((const double *)A_f, p->lda, (const double *)B_f, p->ldb, (double *)C_f, p->ldc, M, N,
-                               g.k, s);
+    case ABFT_F64: {
+        const double *A = (const double *)A_f, *Bt = (const double *)B_f;
+        double *C = (double *)C_f;
+        st = gemm_f64_main(A, p->lda, Bt, p->ldb, C, p->ldc, Mm, Nm, g.k, s);
+        if (st) return st;
+        ABFT_LAUNCHED();
+        // carried row block over all N columns (corner included), then the
+        // carried column block over the rows the main product covered
+        if (thin_r && (st = launch_sliver_rows_f64(g, A + g.m * p->lda, p->lda, Bt, p->ldb, C, p->ldc, s))) return st;
+        if (thin_c && (st = launch_sliver_cols_f64(g, Mm, A, p->lda, Bt + g.n * p->ldb, p->ldb, C, p->ldc, s)))
+            return st;
+        return ABFT_OK;
+    }
     default:
         return ABFT_E_UNSUPPORTED;
     }

@@ -1,0 +1,116 @@
+// Carried checksum blocks of C_f computed as skinny products with binary64
+// accumulation (the "sliver" path, used when a checksum block is thinner than
+// a matrix-core tile):
+//   carried row block    C_f[m + r, j] = sum_l (C_C^T A)[r, l] B_f[l, j]   (r < br, j < N)
+//   carried column block C_f[i, n + c] = sum_l A_f[i, l] (B C_R)[l, c]     (i < rows, c < bc)
+// Both have the form out[u, s] = sum_l X[u, l] Y[s, l] with many rows u (a
+// whole operand, streamed once from HBM) and few rows s (the checksum rows,
+// L2-resident).  One wave owns one u at a time; lanes stride k with 16-byte
+// loads; the few partial sums are folded with wavefront shuffles.
+#include "common.h"
+
+namespace abft {
+
+constexpr int kSliverThreads = 256;
+constexpr int kSliverR = 8;   // few rows per pass
+
+template <typename T> struct vec16;                  // one 16-byte load, widened to double
+template <> struct vec16<double> {
+    static constexpr int N = 2;
+    __device__ static void load(const double *p, double *o) {
+        typedef double v2 __attribute__((ext_vector_type(2)));
+        v2 v = *(const v2 *)p;
+        o[0] = v[0]; o[1] = v[1];
+    }
+};
+template <> struct vec16<float> {
+    static constexpr int N = 4;
+    __device__ static void load(const float *p, double *o) {
+        typedef float v4 __attribute__((ext_vector_type(4)));
+        v4 v = *(const v4 *)p;
+        o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+    }
+};
+template <> struct vec16<uint16_t> {                 // bfloat16
+    static constexpr int N = 8;
+    __device__ static void load(const uint16_t *p, double *o) {
+        typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+        v4u v = *(const v4u *)p;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            o[2 * q] = (double)bf16_to_f32((uint16_t)(v[q] & 0xFFFFu));
+            o[2 * q + 1] = (double)bf16_to_f32((uint16_t)(v[q] >> 16));
+        }
+    }
+};
+
+template <typename T> __device__ inline void store_out(T *p, double v);
+template <> __device__ inline void store_out<double>(double *p, double v) { *p = v; }
+template <> __device__ inline void store_out<float>(float *p, double v) { *p = (float)v; }
+
+// X: U rows of type TX (ldx); Y: R rows of type TY (ldy), R <= kSliverR per launch.
+// out[u*ou + s*os] = scale * sum_l X[u,l] Y[s,l].  K is a multiple of both vector widths.
+template <typename TX, typename TY, typename TC>
+__global__ __launch_bounds__(kSliverThreads) void k_sliver(const TX *__restrict__ X, int64_t ldx, int64_t U,
+                                                          const TY *__restrict__ Y, int64_t ldy, int R, int64_t K,
+                                                          TC *__restrict__ out, int64_t ou, int64_t os, double scale) {
+    constexpr int VX = vec16<TX>::N, VY = vec16<TY>::N;
+    constexpr int V = VX > VY ? VX : VY;             // k per lane per step
+    const int lane = threadIdx.x % 64;
+    const int64_t wave = ((int64_t)blockIdx.x * kSliverThreads + threadIdx.x) / 64;
+    const int64_t nwaves = (int64_t)gridDim.x * kSliverThreads / 64;
+    for (int64_t u = wave; u < U; u += nwaves) {
+        double acc[kSliverR];
+#pragma unroll
+        for (int s = 0; s < kSliverR; ++s) acc[s] = 0.0;
+        const TX *xr = X + u * ldx;
+        for (int64_t k0 = (int64_t)lane * V; k0 < K; k0 += 64 * V) {
+            double xv[V];
+#pragma unroll
+            for (int q = 0; q < V; q += VX) vec16<TX>::load(xr + k0 + q, xv + q);
+#pragma unroll
+            for (int s = 0; s < kSliverR; ++s) {
+                if (s < R) {
+                    double yv[V];
+#pragma unroll
+                    for (int q = 0; q < V; q += VY) vec16<TY>::load(Y + s * ldy + k0 + q, yv + q);
+#pragma unroll
+                    for (int q = 0; q < V; ++q) acc[s] = fma(xv[q], yv[q], acc[s]);
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < kSliverR; ++s) {
+            double v = acc[s];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0 && s < R) store_out<TC>(out + u * ou + s * os, scale * v);
+        }
+    }
+}
+
+template <typename TX, typename TY, typename TC>
+static int sliver(const TX *X, int64_t ldx, int64_t U, const TY *Y, int64_t ldy, int64_t R, int64_t K, TC *out,
+                  int64_t ou, int64_t os, double scale, hipStream_t s) {
+    const int64_t waves_per_block = kSliverThreads / 64;
+    unsigned blocks = (unsigned)std::min<int64_t>((U + waves_per_block - 1) / waves_per_block, 4096);
+    for (int64_t r0 = 0; r0 < R; r0 += kSliverR) {
+        int rr = (int)std::min<int64_t>(kSliverR, R - r0);
+        k_sliver<TX, TY, TC><<<blocks, kSliverThreads, 0, s>>>(X, ldx, U, Y + r0 * ldy, ldy, rr, K, out + r0 * os, ou,
+                                                               os, scale);
+    }
+    ABFT_LAUNCHED();
+    return ABFT_OK;
+}
+
+// Carried row block: C_f[m + r, 0:N) from checksum rows Acs (br x k).
+int launch_sliver_rows_f64(const Geom &g, const double *Acs, int64_t ldacs, const double *Bt, int64_t ldb, double *C,
+                           int64_t ldc, hipStream_t s) {
+    return sliver<double, double, double>(Bt, ldb, g.N, Acs, ldacs, g.br, g.k, C + g.m * ldc, 1, ldc, 1.0, s);
+}
+// Carried column block: C_f[0:rows, n + c) from checksum columns Bcs (bc rows of length k).
+int launch_sliver_cols_f64(const Geom &g, int64_t rows, const double *A, int64_t lda, const double *Bcs, int64_t ldbcs,
+                           double *C, int64_t ldc, hipStream_t s) {
+    return sliver<double, double, double>(A, lda, rows, Bcs, ldbcs, g.bc, g.k, C + g.n, ldc, 1, 1.0, s);
+}
+
+}  // namespace abft
