@@ -19,13 +19,11 @@
  * all-ones checksum; br = bc = nloc is the paper's per-process block scheme
  * (Sec. 3.2, the (n+nloc)-by-n-by-(n+nloc) product).
  *
- * Relations checked in C_f (the encoded product):
- *   column relation (r, j), r < br, j < N:  sum_{g<m/br} C_f[g*br + r, j] = T_c(r, j)
- *   row relation    (i, c), i < M, c < bc:  sum_{h<n/bc} C_f[i, h*bc + c] = T_r(i, c)
- * where T_c(r, j) = sum_{s<S} C_f[m + s*br + r, j] and T_r(i, c) =
- * sum_{s<S} C_f[i, n + s*bc + c] are the carried checksums, stored as S
- * "split" parts (S = 1 for binary64 and binary32 inputs; S = 3 for bfloat16,
- * see abft_split_count), M = m + S*br and N = n + S*bc.
+ * Relations checked in C_f (the encoded product, M = m + br rows, N = n + bc
+ * columns):
+ *   column relation (r, j), r < br, j < N:  sum_{g<m/br} C_f[g*br + r, j] = C_f[m + r, j]
+ *   row relation    (i, c), i < M, c < bc:  sum_{h<n/bc} C_f[i, h*bc + c] = C_f[i, n + c]
+ * (the right-hand sides are the carried checksums).
  *
  * Conventions
  *  - Every pointer named *_f, ws or dst is DEVICE memory owned by the caller;
@@ -76,8 +74,12 @@ typedef enum {
  *  ABFT_TAU_DET   rigorous rounding bound, (2 gamma_k + 2 gamma_{G+1} + u_st) S
  *                 with S bounded by Cauchy-Schwarz from per-row/column norms
  *                 (binary64 paths);
- *  ABFT_TAU_STAT  lambda times the standard deviation of the rounding error of
- *                 a T-step binary32 accumulation (FP32-accumulated paths);
+ *  ABFT_TAU_STAT  lambda times the standard deviation of the rounding error:
+ *                 sigma^2 = (u^2/3)(T/2 + 2) Q, u = 2^-24, T = k (one rounding
+ *                 per product, an upper bound for any matrix-core order), Q
+ *                 the sum of the squared products of the relation (exact for
+ *                 b = 1, a Cauchy-Schwarz bound otherwise); for binary32
+ *                 accumulation, where the rigorous bound is far too loose;
  *  ABFT_TAU_EXACT tau = 0, for integer-valued inputs whose sums are exact. */
 typedef enum { ABFT_TAU_DET = 0, ABFT_TAU_STAT = 1, ABFT_TAU_EXACT = 2 } abft_tau_mode;
 
@@ -87,12 +89,12 @@ typedef enum { ABFT_TAU_DET = 0, ABFT_TAU_STAT = 1, ABFT_TAU_EXACT = 2 } abft_ta
 
 /*
  * Problem descriptor.  Layouts (elements of the dtype, not bytes):
- *   A_f  row-major (m + S*br) x k, row i at A_f + i*lda, lda >= k.
- *        Rows [0, m) are the caller's A; abft_encode writes rows [m, m+S*br).
- *   B_f  column-major k x (n + S*bc), column j at B_f + j*ldb, ldb >= k
+ *   A_f  row-major (m + br) x k, row i at A_f + i*lda, lda >= k.
+ *        Rows [0, m) are the caller's A; abft_encode writes rows [m, m+br).
+ *   B_f  column-major k x (n + bc), column j at B_f + j*ldb, ldb >= k
  *        (equivalently, B_f^T is row-major).  Columns [0, n) are the caller's
- *        B; abft_encode writes columns [n, n+S*bc).
- *   C_f  row-major (m + S*br) x (n + S*bc), ldc >= n + S*bc.
+ *        B; abft_encode writes columns [n, n+bc).
+ *   C_f  row-major (m + br) x (n + bc), ldc >= n + bc.
  * Requirements: m % br == 0, n % bc == 0, k >= 1, and rows of A_f / columns
  * of B_f start on 16-byte boundaries (lda*size and ldb*size multiples of 16,
  * base pointers 16-byte aligned); k is a multiple of 16/size.  C_f only
@@ -144,29 +146,27 @@ typedef struct {
     int64_t i, j;
 } abft_location;
 
-/* Number S of split parts a carried checksum is stored in for this dtype:
- * 1 for F64 and F32; 3 for BF16 (a binary32 checksum c = hi + mid + lo,
- * each part a bfloat16, so the bfloat16 matrix cores carry it exactly). */
-int abft_split_count(int32_t dtype);
-
 /* Bytes of device workspace the calls below need for problem p (threshold
  * statistics, verification partials and the device report). */
 size_t abft_workspace_size(const abft_problem *p);
 
 /*
  * Encode (Eq. ABFT-GEMM, the checkpointed operands A_F and B_F): writes
- * C_C^T A into rows [m, m+S*br) of A_f and B C_R into columns [n, n+S*bc) of
- * B_f, summing in binary64 and rounding once to the dtype (then splitting,
- * when S > 1); and writes the per-row / per-column statistics the thresholds
- * are built from into ws.  Reads A and B once or twice (HBM-bound).
+ * C_C^T A into rows [m, m+br) of A_f and B C_R into columns [n, n+bc) of
+ * B_f, summing in binary64 and rounding once to the dtype, and writes the
+ * per-row / per-column statistics the thresholds are built from into ws.
+ * Reads A and B twice each (HBM-bound).
  */
 int abft_encode(const abft_problem *p, void *A_f, void *B_f, void *ws, void *stream);
 
 /*
- * Protected product (Eq. ABFT-GEMM): C_f = A_f B_f over all (m+S*br) x
- * (n+S*bc) entries, on the matrix cores with binary64 (F64) or binary32
- * (other dtypes) accumulation.  With flags & ABFT_PLAIN only C = A B (m x n)
- * is computed.  A_f and B_f must have been encoded (unless ABFT_PLAIN).
+ * Protected product (Eq. ABFT-GEMM): C_f = A_f B_f over all (m+br) x (n+bc)
+ * entries.  The data part and checksum blocks wider than 8 run on the matrix
+ * cores with binary64 (F64) or binary32 (other dtypes) accumulation;
+ * checksum blocks of width <= 8 are computed by a streaming kernel with
+ * binary64 accumulation.  With flags & ABFT_PLAIN only C = A B (m x n) is
+ * computed, on the matrix cores.  A_f and B_f must have been encoded (unless
+ * ABFT_PLAIN).
  */
 int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, void *stream);
 

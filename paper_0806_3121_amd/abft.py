@@ -75,7 +75,6 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_0806_3121_amd.build`")
         L = C.CDLL(LIB_PATH)
         sig = {
-            "abft_split_count": (C.c_int, [C.c_int32]),
             "abft_workspace_size": (C.c_size_t, [_P(abft_problem)]),
             "abft_encode": (C.c_int, [_P(abft_problem), _V, _V, _V, _V]),
             "abft_gemm": (C.c_int, [_P(abft_problem), _V, _V, _V, C.c_uint32, _V]),
@@ -124,16 +123,11 @@ def _ptr(t):
 
 
 def problem(dtype, m, n, k, br, bc, lda=None, ldb=None, ldc=None, tau_mode=None, lam=0.0, kappa=0.0):
-    S = lib().abft_split_count(dtype)
     if tau_mode is None:
         tau_mode = ABFT_TAU_DET if dtype == ABFT_F64 else ABFT_TAU_STAT
     return abft_problem(dtype, tau_mode, m, n, k, br, bc,
                         lda if lda is not None else k, ldb if ldb is not None else k,
-                        ldc if ldc is not None else n + S * bc, lam, kappa)
-
-
-def split_count(dtype) -> int:
-    return lib().abft_split_count(dtype)
+                        ldc if ldc is not None else n + bc, lam, kappa)
 
 
 def workspace_size(p: abft_problem) -> int:
@@ -205,16 +199,15 @@ def fill_uniform(dtype, rows, cols, ld, transpose, seed, stream_id, dst, stream=
 class Protected:
     """Device buffers of one protected product (A_f, B_f, C_f, workspace),
     allocated with torch.  B_f is stored column-major: the tensor Bt is
-    B_f^T, (n + S*bc) x k row-major."""
+    B_f^T, (n + bc) x k row-major."""
 
     def __init__(self, dtype, m, n, k, br, bc, device="cuda", tau_mode=None, lam=0.0):
         import torch
         tdt = {ABFT_F64: torch.float64, ABFT_F32: torch.float32, ABFT_BF16: torch.bfloat16,
                ABFT_FP8_E4M3: torch.uint8}[dtype]
         cdt = torch.float64 if dtype == ABFT_F64 else torch.float32
-        self.S = split_count(dtype)
         self.p = problem(dtype, m, n, k, br, bc, tau_mode=tau_mode, lam=lam)
-        self.M, self.N = m + self.S * br, n + self.S * bc
+        self.M, self.N = m + br, n + bc
         self.A = torch.zeros(self.M, k, dtype=tdt, device=device)
         self.Bt = torch.zeros(self.N, k, dtype=tdt, device=device)
         self.C = torch.zeros(self.M, self.N, dtype=cdt, device=device)

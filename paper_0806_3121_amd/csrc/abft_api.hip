@@ -70,6 +70,13 @@ TauCoef tau_coef(const abft_problem *p) {
         double u_st = p->dtype == ABFT_F64 ? 0.0 : u32;
         t.cc = kappa * (2 * gamma_n((double)g.k, u_acc) + 2 * gamma_n((double)(g.Gr + g.S), u64) + u_st);
         t.cr = kappa * (2 * gamma_n((double)g.k, u_acc) + 2 * gamma_n((double)(g.Gc + g.S), u64) + u_st);
+    } else if (p->tau_mode == ABFT_TAU_STAT) {
+        // sigma^2 = (u^2/3)(T/2 + s) Q with T = k accumulation steps (one
+        // rounding per product bounds every matrix-core order) and s = 2 for
+        // the binary32 storage of the checksum row and of the carried total
+        double u = p->dtype == ABFT_F64 ? u64 : u32;
+        double T = (double)g.k;
+        t.cc = t.cr = t.lambda * t.lambda * (u * u / 3.0) * (T / 2.0 + 2.0);
     } else {
         t.cc = t.cr = 0.0;
     }
@@ -84,8 +91,7 @@ static int check_problem(const abft_problem *p) {
     if (p->br > p->m || p->bc > p->n) return ABFT_E_ARG;
     if (p->m % p->br || p->n % p->bc) return ABFT_E_ARG;
     if (p->tau_mode < ABFT_TAU_DET || p->tau_mode > ABFT_TAU_EXACT) return ABFT_E_ARG;
-    if (p->dtype != ABFT_F64) return ABFT_E_UNSUPPORTED;
-    if (p->tau_mode == ABFT_TAU_STAT) return ABFT_E_UNSUPPORTED;
+    if (p->dtype != ABFT_F64 && p->dtype != ABFT_F32) return ABFT_E_UNSUPPORTED;
     return ABFT_OK;
 }
 
@@ -206,8 +212,6 @@ static int to_erasures(const Geom &g, const abft_rect *known, int n_known, Erasu
 using namespace abft;
 
 extern "C" {
-
-int abft_split_count(int32_t dtype) { return dtype == ABFT_BF16 ? 3 : 1; }
 
 size_t abft_workspace_size(const abft_problem *p) {
     if (check_problem(p) != ABFT_OK) return 0;

@@ -51,14 +51,15 @@ inline size_t c_size(int dt) { return dt == ABFT_F64 ? 8 : 4; }
 
 // ------------------------------------------------------------------ geometry
 struct Geom {
-    int64_t m, n, k, br, bc, S;
-    int64_t M, N;        // encoded sizes m + S*br, n + S*bc
+    int64_t m, n, k, br, bc;
+    int64_t S;           // entries per carried checksum (1: every carried value is one entry of C_f)
+    int64_t M, N;        // encoded sizes m + br, n + bc
     int64_t Gr, Gc;      // m / br, n / bc
 };
 inline Geom geom_of(const abft_problem *p) {
     Geom g;
     g.m = p->m; g.n = p->n; g.k = p->k; g.br = p->br; g.bc = p->bc;
-    g.S = abft_split_count(p->dtype);
+    g.S = 1;
     g.M = g.m + g.S * g.br;
     g.N = g.n + g.S * g.bc;
     g.Gr = g.m / g.br;
@@ -135,7 +136,8 @@ int launch_fill_uniform(int32_t dtype, int64_t rows, int64_t cols, int64_t ld, i
 // Threshold coefficients shared by encode (statistics) and verify.
 struct TauCoef {
     int mode;
-    double cc, cr;       // det: tau_c = cc*na_abs[r]*nb[j], tau_r = cr*na[i]*nb_abs[c]; stat: coef*lambda^2
+    double cc, cr;       // det: tau_c = cc*na_abs[r]*nb[j], tau_r = cr*na[i]*nb_abs[c];
+                         // stat: tau = sqrt(cc * Q), cc = lambda^2 (u^2/3)(T/2 + s)
     double lambda;
 };
 TauCoef tau_coef(const abft_problem *p);

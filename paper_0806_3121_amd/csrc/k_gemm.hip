@@ -1,0 +1,92 @@
+// Protected product C_f = A_f B_f (Eq. ABFT-GEMM) dispatch.
+//
+// The data part and any thick checksum block (b > kSliverMaxB) run on the
+// matrix cores (gemm_mfma_kernel.h).  A thin checksum block (b <= kSliverMaxB,
+// e.g. the classic b = 1) would occupy a whole row or column of tiles for a
+// few useful rows, so it is computed instead by the skinny-product kernel
+// (sliver_kernel.h), which streams the other operand once with binary64
+// accumulation.
+#include "gemm_mfma_kernel.h"
+#include "sliver_kernel.h"
+
+namespace abft {
+
+constexpr int64_t kSliverMaxB = 8;
+
+struct TileChoice { int id; int bm, bn, per_cu; double eff; };
+
+// Estimated time ~ rounds of resident blocks x time per round (tile flops x
+// blocks per CU / per-tile efficiency); the smallest wins.  256 CUs.
+static int choose_tile(const TileChoice *tab, int n, int64_t M, int64_t N) {
+    double best = 0;
+    int pick = tab[0].id;
+    for (int q = 0; q < n; ++q) {
+        const TileChoice &t = tab[q];
+        int64_t tiles = ((M + t.bm - 1) / t.bm) * ((N + t.bn - 1) / t.bn);
+        int64_t slots = 256 * t.per_cu;
+        double rounds = (double)((tiles + slots - 1) / slots);
+        double cost = rounds * (double)t.bm * t.bn * t.per_cu / t.eff;
+        if (best == 0 || cost < best) { best = cost; pick = t.id; }
+    }
+    return pick;
+}
+
+// binary64 candidates; efficiencies measured on MI355X at 8192^3 and 9216^2 x 8192.
+static const TileChoice kF64Tiles[] = {
+    {0, 256, 128, 1, 0.818}, {1, 128, 128, 2, 0.787}, {2, 128, 96, 2, 0.80}, {3, 96, 96, 2, 0.76},
+};
+static int gemm_main(const double *A, int64_t lda, const double *Bt, int64_t ldb, double *C, int64_t ldc, int64_t M,
+                     int64_t N, int64_t K, hipStream_t s) {
+    switch (choose_tile(kF64Tiles, 4, M, N)) {
+    case 0: return launch_gemm_tile<MfmaTile<double, 256, 128, 16, 4, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
+    case 1: return launch_gemm_tile<MfmaTile<double, 128, 128, 16, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
+    case 2: return launch_gemm_tile<MfmaTile<double, 128, 96, 16, 2, 2, 8, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
+    default: return launch_gemm_tile<MfmaTile<double, 96, 96, 16, 2, 2, 8, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
+    }
+}
+
+// binary32 candidates (same shapes; the f32 matrix core is twice as fast per instruction).
+static const TileChoice kF32Tiles[] = {
+    {0, 256, 128, 1, 0.80}, {1, 128, 128, 2, 0.78},
+};
+static int gemm_main(const float *A, int64_t lda, const float *Bt, int64_t ldb, float *C, int64_t ldc, int64_t M,
+                     int64_t N, int64_t K, hipStream_t s) {
+    switch (choose_tile(kF32Tiles, 2, M, N)) {
+    case 0: return launch_gemm_tile<MfmaTile<float, 256, 128, 32, 4, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
+    default: return launch_gemm_tile<MfmaTile<float, 128, 128, 32, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
+    }
+}
+
+template <typename E>
+static int protected_product(const abft_problem *p, const Geom &g, const E *A, const E *Bt, E *C, bool plain,
+                             hipStream_t s) {
+    const bool thin_r = !plain && g.S * g.br <= kSliverMaxB;
+    const bool thin_c = !plain && g.S * g.bc <= kSliverMaxB;
+    int64_t Mm = (plain || thin_r) ? g.m : g.M;
+    int64_t Nm = (plain || thin_c) ? g.n : g.N;
+    int st = gemm_main(A, p->lda, Bt, p->ldb, C, p->ldc, Mm, Nm, g.k, s);
+    if (st) return st;
+    ABFT_LAUNCHED();
+    // carried row block over all N columns (corner included), then the carried
+    // column block over the rows the main product covered
+    if (thin_r && (st = launch_sliver_rows<E, E, E>(g, A + g.m * p->lda, p->lda, Bt, p->ldb, C, p->ldc, 1.0, s)))
+        return st;
+    if (thin_c && (st = launch_sliver_cols<E, E, E>(g, Mm, A, p->lda, Bt + g.n * p->ldb, p->ldb, C, p->ldc, 1.0, s)))
+        return st;
+    return ABFT_OK;
+}
+
+int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, hipStream_t s) {
+    Geom g = geom_of(p);
+    const bool plain = flags & ABFT_PLAIN;
+    switch (p->dtype) {
+    case ABFT_F64:
+        return protected_product<double>(p, g, (const double *)A_f, (const double *)B_f, (double *)C_f, plain, s);
+    case ABFT_F32:
+        return protected_product<float>(p, g, (const float *)A_f, (const float *)B_f, (float *)C_f, plain, s);
+    default:
+        return ABFT_E_UNSUPPORTED;
+    }
+}
+
+}  // namespace abft

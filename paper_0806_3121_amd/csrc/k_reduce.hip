@@ -69,88 +69,85 @@ __global__ void k_report_init(abft_report *rep) {
     for (int q = threadIdx.x; q < nw; q += blockDim.x) w[q] = 0;
 }
 
-// ------------------------------------------------------------------ store helpers
-template <typename T> __device__ inline void store_checksum(T *row0, int64_t stride_s, int64_t l, double s, int S);
-template <> __device__ inline void store_checksum<double>(double *row0, int64_t, int64_t l, double s, int) { row0[l] = s; }
-template <> __device__ inline void store_checksum<float>(float *row0, int64_t, int64_t l, double s, int) { row0[l] = (float)s; }
-template <> __device__ inline void store_checksum<uint16_t>(uint16_t *row0, int64_t stride_s, int64_t l, double s, int S) {
-    // binary32 checksum split into S bfloat16 parts whose sum is exact (S = 3)
-    float c = (float)s;
-    for (int q = 0; q < S; ++q) {
-        uint16_t h = f32_to_bf16_rne(c);
-        row0[q * stride_s + l] = h;
-        c = c - bf16_to_f32(h);
-    }
+// ------------------------------------------------------------------ encode
+// Checksum rows of an operand X (R data rows, row-major, ld; the B operand is
+// passed as its transpose, so both sides are the same row-group sum):
+//   CS[r, l] = sum_{g<G} X[g*b + r, l]       (binary64 sum, rounded once to TC)
+// and the per-residue statistic grp[r, l] of the threshold:
+//   det:  sum_g |X[g*b + r, l]|               (row r of C_C^T |X|)
+//   stat: sum_g X[g*b + r, l]^2 + CS[r, l]^2  (the squares of every member of the relation)
+template <typename T, typename TC> __device__ inline void finish_encode(double s, double ss, bool stat, TC *cs, double *grp) {
+    TC c = (TC)s;
+    *cs = c;
+    *grp = stat ? ss + (double)c * (double)c : ss;
 }
 
-// ------------------------------------------------------------------ encode
-// Operand X (rows >= R + S*b, row-major, ld): the checksum rows
-// X[R + s*b + r, l] receive sum_{g<G} X[g*b + r, l] (s = split part), and
-// grp[r*k + l] = sum_g |X[g*b + r, l]| (det statistics).
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_encode_direct(T *X, int64_t ld, int64_t R, int64_t b, int64_t G,
-                                                            int64_t k, int S, double *grp) {
+template <typename T, typename TC>
+__global__ __launch_bounds__(kThreads) void k_encode_direct(const T *X, int64_t ld, int64_t b, int64_t G, int64_t k,
+                                                            TC *CS, int64_t ldcs, bool stat, double *grp) {
     const int64_t total = b * k;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
         int64_t r = t / k, l = t - r * k;
-        double s = 0.0, sa = 0.0;
+        double s = 0.0, ss = 0.0;
         const T *p = X + r * ld + l;
         for (int64_t g = 0; g < G; ++g) {
             double v = elem<T>::load(p + g * b * ld);
             s += v;
-            sa += fabs(v);
+            ss += stat ? v * v : fabs(v);
         }
-        store_checksum<T>(X + (R + r) * ld, b * ld, l, s, S);
-        grp[t] = sa;
+        finish_encode<T, TC>(s, ss, stat, CS + r * ldcs + l, grp + t);
     }
 }
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_encode_partial(const T *X, int64_t ld, int64_t b, int64_t G, int64_t k,
-                                                             int64_t P, int64_t chunk, double *part) {
+                                                             int64_t P, int64_t chunk, bool stat, double *part) {
     const int64_t rel = b * k, total = P * rel;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
         int64_t p = t / rel, q = t - p * rel;
         int64_t r = q / k, l = q - r * k;
         int64_t g0 = p * chunk, g1 = min(G, g0 + chunk);
-        double s = 0.0, sa = 0.0;
+        double s = 0.0, ss = 0.0;
         const T *src = X + r * ld + l;
         for (int64_t g = g0; g < g1; ++g) {
             double v = elem<T>::load(src + g * b * ld);
             s += v;
-            sa += fabs(v);
+            ss += stat ? v * v : fabs(v);
         }
         part[(2 * p) * rel + q] = s;
-        part[(2 * p + 1) * rel + q] = sa;
+        part[(2 * p + 1) * rel + q] = ss;
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_encode_finish(T *X, int64_t ld, int64_t R, int64_t b, int64_t k, int S,
+template <typename T, typename TC>
+__global__ __launch_bounds__(kThreads) void k_encode_finish(int64_t b, int64_t k, TC *CS, int64_t ldcs, bool stat,
                                                             int64_t P, const double *part, double *grp) {
     const int64_t rel = b * k;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < rel; t += (int64_t)gridDim.x * kThreads) {
         int64_t r = t / k, l = t - r * k;
-        double s = 0.0, sa = 0.0;
+        double s = 0.0, ss = 0.0;
         for (int64_t p = 0; p < P; ++p) {
             s += part[(2 * p) * rel + t];
-            sa += part[(2 * p + 1) * rel + t];
+            ss += part[(2 * p + 1) * rel + t];
         }
-        store_checksum<T>(X + (R + r) * ld, b * ld, l, s, S);
-        grp[t] = sa;
+        finish_encode<T, TC>(s, ss, stat, CS + r * ldcs + l, grp + t);
     }
 }
 
-// out[i] = || X[i, 0:k] ||_2, one block per row (grid-stride over rows).
+// Per-row statistic of X[i, 0:k), one block per row (grid-stride over rows):
+//   ROW_L2:  ||x||_2              ROW_W: sum_l x_l^2 w_l          ROW_L4SQ: ||x||_4^2
+enum { ROW_L2 = 0, ROW_W = 1, ROW_L4SQ = 2 };
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_row_norms(const T *X, int64_t ld, int64_t rows, int64_t k, double *out) {
+__global__ __launch_bounds__(kThreads) void k_row_stats(const T *X, int64_t ld, int64_t rows, int64_t k, int mode,
+                                                        const double *w, double *out) {
     __shared__ double sh[kThreads / kWave];
     for (int64_t i = blockIdx.x; i < rows; i += gridDim.x) {
         const T *row = X + i * ld;
         double s = 0.0;
         for (int64_t l = threadIdx.x; l < k; l += kThreads) {
             double v = elem<T>::load(row + l);
-            s += v * v;
+            double v2 = v * v;
+            s += mode == ROW_W ? v2 * w[l] : (mode == ROW_L4SQ ? v2 * v2 : v2);
         }
         s = wave_sum(s);
         if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = s;
@@ -158,45 +155,75 @@ __global__ __launch_bounds__(kThreads) void k_row_norms(const T *X, int64_t ld, 
         if (threadIdx.x == 0) {
             double t = 0.0;
             for (int q = 0; q < kThreads / kWave; ++q) t += sh[q];
-            out[i] = sqrt(t);
+            out[i] = mode == ROW_W ? t : sqrt(t);
         }
         __syncthreads();
     }
 }
 
-template <typename T>
-static int encode_operand(T *X, int64_t ld, int64_t R, int64_t b, int64_t k, int S, int64_t rows_total,
-                          double *grp, double *norms_rows, double *norms_grp, double *part, hipStream_t s) {
+static unsigned grid_for(int64_t work) { return (unsigned)std::min<int64_t>((work + kThreads - 1) / kThreads, 65536); }
+static unsigned rows_grid(int64_t rows) { return (unsigned)std::min<int64_t>(std::max<int64_t>(rows, 1), 65536); }
+
+// Pass 1 over one operand: checksum rows CS (ldcs) and grp.
+template <typename T, typename TC>
+static void encode_pass1(const T *X, int64_t ld, int64_t R, int64_t b, int64_t k, TC *CS, int64_t ldcs, bool stat,
+                         double *grp, double *part, hipStream_t s) {
     int64_t G = R / b;
     int64_t P = group_partitions(G, b, k);
-    auto blocks = [](int64_t work) { return (unsigned)std::min<int64_t>((work + kThreads - 1) / kThreads, 65536); };
     if (P == 1) {
-        k_encode_direct<T><<<blocks(b * k), kThreads, 0, s>>>(X, ld, R, b, G, k, S, grp);
+        k_encode_direct<T, TC><<<grid_for(b * k), kThreads, 0, s>>>(X, ld, b, G, k, CS, ldcs, stat, grp);
     } else {
         int64_t chunk = (G + P - 1) / P;
         P = (G + chunk - 1) / chunk;
-        k_encode_partial<T><<<blocks(P * b * k), kThreads, 0, s>>>(X, ld, b, G, k, P, chunk, part);
-        k_encode_finish<T><<<blocks(b * k), kThreads, 0, s>>>(X, ld, R, b, k, S, P, part, grp);
+        k_encode_partial<T><<<grid_for(P * b * k), kThreads, 0, s>>>(X, ld, b, G, k, P, chunk, stat, part);
+        k_encode_finish<T, TC><<<grid_for(b * k), kThreads, 0, s>>>(b, k, CS, ldcs, stat, P, part, grp);
     }
-    ABFT_LAUNCHED();
-    k_row_norms<T><<<(unsigned)std::min<int64_t>(rows_total, 65536), kThreads, 0, s>>>(X, ld, rows_total, k, norms_rows);
-    k_row_norms<double><<<(unsigned)std::min<int64_t>(b, 65536), kThreads, 0, s>>>(grp, k, b, k, norms_grp);
+}
+
+// Pass 2 over one operand: a statistic per row of the data rows and of the
+// checksum rows.  det: ||row||_2; stat with the other side thin (b_other == 1):
+// sum_l row_l^2 w_l (w = the other side's grp); stat otherwise: ||row||_4^2.
+template <typename T, typename TC>
+static void encode_pass2(const T *X, int64_t ld, int64_t R, const TC *CS, int64_t ldcs, int64_t b, int64_t k,
+                         bool stat, int64_t b_other, const double *w_other, double *out, hipStream_t s) {
+    int mode = !stat ? ROW_L2 : (b_other == 1 ? ROW_W : ROW_L4SQ);
+    k_row_stats<T><<<rows_grid(R), kThreads, 0, s>>>(X, ld, R, k, mode, w_other, out);
+    k_row_stats<TC><<<rows_grid(b), kThreads, 0, s>>>(CS, ldcs, b, k, mode, w_other, out + R);
+}
+
+template <typename T, typename TC>
+static int encode_typed(const abft_problem *p, T *A, T *Bt, TC *Acs, int64_t ldacs, TC *Bcs, int64_t ldbcs, char *ws,
+                        hipStream_t s) {
+    Geom g = geom_of(p);
+    WsLayout L = ws_layout(p);
+    double *part = (double *)(ws + L.partial);
+    double *grpA = (double *)(ws + L.grpA), *grpB = (double *)(ws + L.grpB);
+    const bool stat = p->tau_mode == ABFT_TAU_STAT;
+    encode_pass1<T, TC>(A, p->lda, g.m, g.br, g.k, Acs, ldacs, stat, grpA, part, s);
+    encode_pass1<T, TC>(Bt, p->ldb, g.n, g.bc, g.k, Bcs, ldbcs, stat, grpB, part, s);
+    // row statistics (det: na, nb; stat: qr, qc) and the norms of the grp rows
+    // (det: na_abs, nb_abs; stat: nv, nw)
+    double *ra = (double *)(ws + (stat ? L.qr : L.na)), *rb = (double *)(ws + (stat ? L.qc : L.nb));
+    encode_pass2<T, TC>(A, p->lda, g.m, Acs, ldacs, g.br, g.k, stat, g.bc, grpB, ra, s);
+    encode_pass2<T, TC>(Bt, p->ldb, g.n, Bcs, ldbcs, g.bc, g.k, stat, g.br, grpA, rb, s);
+    double *ga = (double *)(ws + (stat ? L.nv : L.na_abs)), *gb = (double *)(ws + (stat ? L.nw : L.nb_abs));
+    k_row_stats<double><<<rows_grid(g.br), kThreads, 0, s>>>(grpA, g.k, g.br, g.k, ROW_L2, nullptr, ga);
+    k_row_stats<double><<<rows_grid(g.bc), kThreads, 0, s>>>(grpB, g.k, g.bc, g.k, ROW_L2, nullptr, gb);
     ABFT_LAUNCHED();
     return ABFT_OK;
 }
 
 int launch_encode(const abft_problem *p, void *A_f, void *B_f, char *ws, hipStream_t s) {
     Geom g = geom_of(p);
-    WsLayout L = ws_layout(p);
-    double *part = (double *)(ws + L.partial);
-    int st;
     switch (p->dtype) {
-    case ABFT_F64:
-        st = encode_operand<double>((double *)A_f, p->lda, g.m, g.br, g.k, (int)g.S, g.M, (double *)(ws + L.grpA),
-                                    (double *)(ws + L.na), (double *)(ws + L.na_abs), part, s);
-        if (st) return st;
-        return encode_operand<double>((double *)B_f, p->ldb, g.n, g.bc, g.k, (int)g.S, g.N, (double *)(ws + L.grpB),
-                                      (double *)(ws + L.nb), (double *)(ws + L.nb_abs), part, s);
+    case ABFT_F64: {
+        double *A = (double *)A_f, *Bt = (double *)B_f;
+        return encode_typed<double, double>(p, A, Bt, A + g.m * p->lda, p->lda, Bt + g.n * p->ldb, p->ldb, ws, s);
+    }
+    case ABFT_F32: {
+        float *A = (float *)A_f, *Bt = (float *)B_f;
+        return encode_typed<float, float>(p, A, Bt, A + g.m * p->lda, p->lda, Bt + g.n * p->ldb, p->ldb, ws, s);
+    }
     default:
         return ABFT_E_UNSUPPORTED;
     }
@@ -206,17 +233,24 @@ int launch_encode(const abft_problem *p, void *A_f, void *B_f, char *ws, hipStre
 struct VerifyArgs {
     int64_t m, n, br, bc, S, Gr, Gc, M, N, ldc;
     int mode;
-    double cc, cr;
+    double cc, cr;                  // det coefficients; stat: cc = lambda^2 (u^2/3)(T/2 + s)
     const double *na, *na_abs, *nb, *nb_abs;
+    const double *qr, *qc, *nv, *nw;
     abft_report *rep;
     Erasures er;
 };
 
+// det:  tau_c = cc ||(C_C^T|A|)[r,:]||_2 ||B_f[:,j]||_2
+// stat: tau_c = sqrt(cc Q_c[r,j]),  Q_c = qc[j] (br = 1, exact) or nv[r] qc[j] (Cauchy-Schwarz bound)
 __device__ inline double tau_col(const VerifyArgs &a, int64_t r, int64_t j) {
-    return a.mode == ABFT_TAU_DET ? a.cc * a.na_abs[r] * a.nb[j] : 0.0;
+    if (a.mode == ABFT_TAU_DET) return a.cc * a.na_abs[r] * a.nb[j];
+    if (a.mode == ABFT_TAU_STAT) return sqrt(a.cc * (a.br == 1 ? a.qc[j] : a.nv[r] * a.qc[j]));
+    return 0.0;
 }
 __device__ inline double tau_row(const VerifyArgs &a, int64_t i, int64_t c) {
-    return a.mode == ABFT_TAU_DET ? a.cr * a.na[i] * a.nb_abs[c] : 0.0;
+    if (a.mode == ABFT_TAU_DET) return a.cr * a.na[i] * a.nb_abs[c];
+    if (a.mode == ABFT_TAU_STAT) return sqrt(a.cr * (a.bc == 1 ? a.qr[i] : a.qr[i] * a.nw[c]));
+    return 0.0;
 }
 
 // Column relation (r, j): sum_{g<Gr} C[g*br + r, j] - sum_{s<S} C[m + s*br + r, j]
@@ -338,6 +372,8 @@ static int verify_typed(const abft_problem *p, const T *C, const Erasures &er, c
     a.mode = tc.mode; a.cc = tc.cc; a.cr = tc.cr;
     a.na = (const double *)(ws + L.na); a.na_abs = (const double *)(ws + L.na_abs);
     a.nb = (const double *)(ws + L.nb); a.nb_abs = (const double *)(ws + L.nb_abs);
+    a.qr = (const double *)(ws + L.qr); a.qc = (const double *)(ws + L.qc);
+    a.nv = (const double *)(ws + L.nv); a.nw = (const double *)(ws + L.nw);
     a.rep = (abft_report *)(ws + L.report);
     a.er = er;
     k_report_init<<<1, kThreads, 0, s>>>(a.rep);

@@ -7,6 +7,8 @@
 // whole operand, streamed once from HBM) and few rows s (the checksum rows,
 // L2-resident).  One wave owns one u at a time; lanes stride k with 16-byte
 // loads; the few partial sums are folded with wavefront shuffles.
+#pragma once
+
 #include "common.h"
 
 namespace abft {
@@ -89,7 +91,7 @@ __global__ __launch_bounds__(kSliverThreads) void k_sliver(const TX *__restrict_
 }
 
 template <typename TX, typename TY, typename TC>
-static int sliver(const TX *X, int64_t ldx, int64_t U, const TY *Y, int64_t ldy, int64_t R, int64_t K, TC *out,
+inline int sliver(const TX *X, int64_t ldx, int64_t U, const TY *Y, int64_t ldy, int64_t R, int64_t K, TC *out,
                   int64_t ou, int64_t os, double scale, hipStream_t s) {
     const int64_t waves_per_block = kSliverThreads / 64;
     unsigned blocks = (unsigned)std::min<int64_t>((U + waves_per_block - 1) / waves_per_block, 4096);
@@ -102,15 +104,17 @@ static int sliver(const TX *X, int64_t ldx, int64_t U, const TY *Y, int64_t ldy,
     return ABFT_OK;
 }
 
-// Carried row block: C_f[m + r, 0:N) from checksum rows Acs (br x k).
-int launch_sliver_rows_f64(const Geom &g, const double *Acs, int64_t ldacs, const double *Bt, int64_t ldb, double *C,
-                           int64_t ldc, hipStream_t s) {
-    return sliver<double, double, double>(Bt, ldb, g.N, Acs, ldacs, g.br, g.k, C + g.m * ldc, 1, ldc, 1.0, s);
+// Carried row block: C_f[m + r, 0:N) = sum_l Acs[r, l] Bt[j, l] (checksum rows Acs, br x k).
+template <typename TA, typename TB, typename TC>
+inline int launch_sliver_rows(const Geom &g, const TA *Acs, int64_t ldacs, const TB *Bt, int64_t ldb, TC *C,
+                              int64_t ldc, double scale, hipStream_t s) {
+    return sliver<TB, TA, TC>(Bt, ldb, g.N, Acs, ldacs, g.br, g.k, C + g.m * ldc, 1, ldc, scale, s);
 }
-// Carried column block: C_f[0:rows, n + c) from checksum columns Bcs (bc rows of length k).
-int launch_sliver_cols_f64(const Geom &g, int64_t rows, const double *A, int64_t lda, const double *Bcs, int64_t ldbcs,
-                           double *C, int64_t ldc, hipStream_t s) {
-    return sliver<double, double, double>(A, lda, rows, Bcs, ldbcs, g.bc, g.k, C + g.n, ldc, 1, 1.0, s);
+// Carried column block: C_f[0:rows, n + c) = sum_l A[i, l] Bcs[c, l] (checksum columns Bcs, bc x k).
+template <typename TA, typename TB, typename TC>
+inline int launch_sliver_cols(const Geom &g, int64_t rows, const TA *A, int64_t lda, const TB *Bcs, int64_t ldbcs,
+                              TC *C, int64_t ldc, double scale, hipStream_t s) {
+    return sliver<TA, TB, TC>(A, lda, rows, Bcs, ldbcs, g.bc, g.k, C + g.n, ldc, 1, scale, s);
 }
 
 }  // namespace abft
