@@ -26,14 +26,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "protected-GEMM TFLOP/s and % MFMA peak; ABFT overhead vs plain GEMM"
-PEAK_F64 = 78.6  # TFLOP/s, MI355X dense FP64 matrix
+PEAK = {"f64": 78.6, "f32": 157.3}  # TFLOP/s, MI355X dense matrix-core peaks
 WORKLOADS = {
-    # name: (m, n, k, b, erase)
-    "c2": (8192, 8192, 8192, 1024, True),
-    "c2b1": (8192, 8192, 8192, 1, False),
-    "c1": (256, 256, 256, 1, False),
-    "c1b64": (256, 256, 256, 64, True),
+    # name: (dtype, m, n, k, b, erase)
+    "c2": ("f64", 8192, 8192, 8192, 1024, True),
+    "c2b1": ("f64", 8192, 8192, 8192, 1, False),
+    "c1": ("f64", 256, 256, 256, 1, False),
+    "c1b64": ("f64", 256, 256, 256, 64, True),
+    "c3": ("f32", 16384, 8192, 32768, 1, False),
 }
+# flip bits per C type: binary64 40..62; binary32 24..29 (exponent bits and the
+# top fraction bit: always above the statistical threshold, so every step's
+# flip is located)
+FLIP_BITS = {"f64": (40, 62), "f32": (24, 29)}
 SEED = 20080523
 
 
@@ -41,23 +46,33 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(m, n, k, b, rows):
-    """Oracle (FP64 i-l-j loops, all host threads) on rows [0, rows) of the
-    same encoded product; returns (TFLOP/s, threads, seconds)."""
+def cpu_baseline(dt_name, m, n, k, b, target_s=12.0):
+    """Oracle (FP64 i-l-j loops, all host threads) on leading rows of the same
+    encoded product, sized to about target_s seconds; returns (TFLOP/s,
+    threads, seconds, rows)."""
     import numpy as np
 
     from oracle import oracle as orc
     from paper_0806_3121_amd import synth
 
-    A = synth.uniform_rows(SEED, synth.STREAM_A, np.arange(m), k)
-    B = synth.uniform(SEED, synth.STREAM_B, k, n)
-    Af, Bf = orc.encode(A, B, b, b)
-    del A, B
+    ndt = np.float64 if dt_name == "f64" else np.float32
+    B = synth.uniform(SEED, synth.STREAM_B, k, n, ndt).astype(np.float64)
+    probe = 32
+    A0 = synth.uniform_rows(SEED, synth.STREAM_A, np.arange(probe), k, ndt).astype(np.float64)
+    Bf = np.zeros((k, n + b))
+    Bf[:, :n] = B
+    del B
+    orc.lib().orc_encode_cols(k, n, b, orc._p(Bf), n + b, int(dt_name != "f64"))
     t0 = time.perf_counter()
-    orc.gemm(Af[:rows], Bf)
+    orc.gemm(A0, Bf)
+    t_probe = time.perf_counter() - t0
+    rows = int(min(m, max(probe, probe * target_s / max(t_probe, 1e-3))))
+    A = synth.uniform_rows(SEED, synth.STREAM_A, np.arange(rows), k, ndt).astype(np.float64)
+    t0 = time.perf_counter()
+    orc.gemm(A, Bf)
     dt = time.perf_counter() - t0
     flops = 2.0 * rows * (n + b) * k
-    return flops / dt / 1e12, orc.num_threads(), dt
+    return flops / dt / 1e12, orc.num_threads(), dt, rows
 
 
 def main():
@@ -67,7 +82,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=96)
+    ap.add_argument("--no-plain", action="store_true", help="skip the unprotected-kernel timing (profiling runs)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the path is built and measured on one "
@@ -82,15 +98,18 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    m, n, k, b, erase = WORKLOADS[args.workload]
+    dt_name, m, n, k, b, erase = WORKLOADS[args.workload]
+    adt = {"f64": abft.ABFT_F64, "f32": abft.ABFT_F32}[dt_name]
+    tdt = {"f64": torch.float64, "f32": torch.float32}[dt_name]
+    bit_lo, bit_hi = FLIP_BITS[dt_name]
 
-    log(f"workload {args.workload}: m={m} n={n} k={k} b={b}")
-    P = abft.Protected(abft.ABFT_F64, m, n, k, b, b, device=dev)
-    abft.fill_uniform(abft.ABFT_F64, m, k, k, 0, SEED, synth.STREAM_A, P.A)
+    log(f"workload {args.workload}: {dt_name} m={m} n={n} k={k} b={b}")
+    P = abft.Protected(adt, m, n, k, b, b, device=dev)
+    abft.fill_uniform(adt, m, k, k, 0, SEED, synth.STREAM_A, P.A)
     # B (k x n) stored column-major: the Bt tensor holds B^T row-major
-    abft.fill_uniform(abft.ABFT_F64, k, n, k, 1, SEED, synth.STREAM_B, P.Bt)
-    Cplain = torch.empty(m, n, dtype=torch.float64, device=dev)
-    pplain = abft.problem(abft.ABFT_F64, m, n, k, b, b, ldc=n)
+    abft.fill_uniform(adt, k, n, k, 1, SEED, synth.STREAM_B, P.Bt)
+    Cplain = torch.empty(m, n, dtype=tdt, device=dev)
+    pplain = abft.problem(adt, m, n, k, b, b, ldc=n)
     torch.cuda.synchronize()
 
     g_events = []
@@ -107,7 +126,7 @@ def main():
         if erase:
             I, J = synth.erase_block(SEED, s, m // b, n // b)
             rect = (I * b, J * b, b, b)
-        i, j, bit = synth.flip_site(SEED, s, m, n, 40, 62, avoid=rect)
+        i, j, bit = synth.flip_site(SEED, s, m, n, bit_lo, bit_hi, avoid=rect)
         abft.inject_flip(P.p, P.C, i, j, bit)
         known = [rect] if rect else None
         if rect:
@@ -137,7 +156,7 @@ def main():
 
     # plain product of the same kernel (no checksum rows/columns)
     pe = []
-    for s in range(max(3, min(args.steps, 10))):
+    for s in range(0 if args.no_plain else max(3, min(args.steps, 10))):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -145,7 +164,8 @@ def main():
         e1.record(stream)
         pe.append((e0, e1))
     torch.cuda.synchronize()
-    plain_ms = sum(a.elapsed_time(c) for a, c in pe[1:]) / len(pe[1:])
+    plain_ms = sum(a.elapsed_time(c) for a, c in pe[1:]) / len(pe[1:]) if pe else None
+    peak = PEAK[dt_name]
 
     useful = 2.0 * m * n * k
     executed = 2.0 * (m + b) * (n + b) * k
@@ -163,25 +183,25 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": dt_name,
         "data": "synthetic",
-        "config": {"workload": f"FP64 protected GEMM {args.workload}: m=n=k={n}, checksum blocks {b}x{b} "
-                               f"({'8x8 grid, one erased block + one flip per step' if erase else 'one flip per step'})",
+        "config": {"workload": f"{dt_name.upper()} protected GEMM {args.workload}: m={m} n={n} k={k}, checksum blocks "
+                               f"{b}x{b} ({f'{m // b}x{n // b} grid, one erased block + one flip per step' if erase else 'one flip per step'})",
                    "m": m, "n": n, "k": k, "br": b, "bc": b, "global_batch": 1, "seq_len": 0,
                    "parallelism": "single-gpu"},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_F64, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_F64, 4), "traffic": None,
-                     "kernel": "k_gemm_f64", "flops_per_launch": executed, "avg_launch_ms": round(gemm_ms, 4)},
-        "pct_mfma_peak_useful": round(100 * value / PEAK_F64, 2),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "k_gemm_mfma (+ k_sliver for b <= 8)", "flops_per_launch": executed,
+                     "avg_launch_ms": round(gemm_ms, 4)},
+        "pct_mfma_peak_useful": round(100 * value / peak, 2),
         "gemm_protected_ms": round(gemm_ms, 4),
-        "gemm_plain_ms": round(plain_ms, 4),
-        "abft_overhead_pct": round(100 * (gemm_ms / plain_ms - 1), 2),
+        "gemm_plain_ms": round(plain_ms, 4) if plain_ms else None,
+        "abft_overhead_pct": round(100 * (gemm_ms / plain_ms - 1), 2) if plain_ms else None,
         "abft_floor_pct": round(100 * (executed / useful - 1), 2),
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        rows = args.cpu_rows
-        tf, thr, sec = cpu_baseline(m, n, k, b, rows)
+        tf, thr, sec, rows = cpu_baseline(dt_name, m, n, k, b, args.cpu_seconds)
         out["cpu_baseline"] = {"value": round(tf, 6), "unit": "TFLOP/s", "cores": thr, "kind": "oracle",
                                "sample": f"rows 0..{rows - 1} of the encoded product C_f = A_f B_f "
                                          f"({rows} x {n + b} x {k}, FP64 i-l-j loops), {sec:.1f} s"}

@@ -95,6 +95,9 @@ typedef enum { ABFT_TAU_DET = 0, ABFT_TAU_STAT = 1, ABFT_TAU_EXACT = 2 } abft_ta
  *        (equivalently, B_f^T is row-major).  Columns [0, n) are the caller's
  *        B; abft_encode writes columns [n, n+bc).
  *   C_f  row-major (m + br) x (n + bc), ldc >= n + bc.
+ * For ABFT_BF16 (and ABFT_FP8_E4M3) A_f holds only the m data rows and B_f
+ * only the n data columns: their checksums are binary32 values that the
+ * element type cannot hold, so abft_encode keeps them in the workspace.
  * Requirements: m % br == 0, n % bc == 0, k >= 1, and rows of A_f / columns
  * of B_f start on 16-byte boundaries (lda*size and ldb*size multiples of 16,
  * base pointers 16-byte aligned); k is a multiple of 16/size.  C_f only
@@ -151,9 +154,20 @@ typedef struct {
 size_t abft_workspace_size(const abft_problem *p);
 
 /*
+ * Quantize a binary32 operand into the problem's element type (a step of the
+ * low-precision workloads, not of the paper's method).  which == 0: X is A
+ * (m x k, row-major, ldx) and dst receives the data rows of A_f (lda);
+ * which == 1: X is B^T (n x k, row-major, ldx) and dst receives the data
+ * columns of the column-major B_f (ldb).  ABFT_BF16: round to nearest even.
+ * X and dst 16-byte aligned, ldx*4 a multiple of 16.  Asynchronous.
+ */
+int abft_quantize(const abft_problem *p, int which, const float *X, int64_t ldx, void *dst, void *ws, void *stream);
+
+/*
  * Encode (Eq. ABFT-GEMM, the checkpointed operands A_F and B_F): writes
  * C_C^T A into rows [m, m+br) of A_f and B C_R into columns [n, n+bc) of
- * B_f, summing in binary64 and rounding once to the dtype, and writes the
+ * B_f (F64, F32; for BF16 / FP8 into ws, in binary32), summing in binary64
+ * and rounding once, and writes the
  * per-row / per-column statistics the thresholds are built from into ws.
  * Reads A and B twice each (HBM-bound).
  */
@@ -163,12 +177,15 @@ int abft_encode(const abft_problem *p, void *A_f, void *B_f, void *ws, void *str
  * Protected product (Eq. ABFT-GEMM): C_f = A_f B_f over all (m+br) x (n+bc)
  * entries.  The data part and checksum blocks wider than 8 run on the matrix
  * cores with binary64 (F64) or binary32 (other dtypes) accumulation;
- * checksum blocks of width <= 8 are computed by a streaming kernel with
- * binary64 accumulation.  With flags & ABFT_PLAIN only C = A B (m x n) is
- * computed, on the matrix cores.  A_f and B_f must have been encoded (unless
- * ABFT_PLAIN).
+ * checksum blocks of width <= 8, and every checksum block of a bfloat16 / FP8
+ * problem (whose binary32 checksum rows live in ws), are computed by a
+ * streaming kernel with binary64 accumulation.  With flags & ABFT_PLAIN only
+ * C = A B (m x n) is computed, on the matrix cores, and ws may be NULL.
+ * A_f and B_f must have been encoded (unless ABFT_PLAIN); ws is the one
+ * abft_encode filled (required for BF16 / FP8, unused for F64 / F32).
  */
-int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, void *stream);
+int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, void *ws, uint32_t flags,
+              void *stream);
 
 /*
  * Verify (consistency, Sec. 2.2): recomputes every column and row relation of

@@ -77,7 +77,8 @@ def lib():
         sig = {
             "abft_workspace_size": (C.c_size_t, [_P(abft_problem)]),
             "abft_encode": (C.c_int, [_P(abft_problem), _V, _V, _V, _V]),
-            "abft_gemm": (C.c_int, [_P(abft_problem), _V, _V, _V, C.c_uint32, _V]),
+            "abft_gemm": (C.c_int, [_P(abft_problem), _V, _V, _V, _V, C.c_uint32, _V]),
+            "abft_quantize": (C.c_int, [_P(abft_problem), C.c_int, _V, C.c_int64, _V, _V, _V]),
             "abft_verify": (C.c_int, [_P(abft_problem), _V, _P(abft_rect), C.c_int, _V, _V, _V]),
             "abft_classify": (C.c_int, [_P(abft_problem), _P(abft_report), _P(abft_rect), C.c_int,
                                         _P(abft_location)]),
@@ -138,8 +139,15 @@ def encode(p, A_f, B_f, ws, stream=None):
     return _check("abft_encode", lib().abft_encode(C.byref(p), _ptr(A_f), _ptr(B_f), _ptr(ws), _stream(stream)))
 
 
-def gemm(p, A_f, B_f, C_f, flags=0, stream=None):
-    return _check("abft_gemm", lib().abft_gemm(C.byref(p), _ptr(A_f), _ptr(B_f), _ptr(C_f), flags, _stream(stream)))
+def gemm(p, A_f, B_f, C_f, ws=None, flags=0, stream=None):
+    return _check("abft_gemm", lib().abft_gemm(C.byref(p), _ptr(A_f), _ptr(B_f), _ptr(C_f), _ptr(ws), flags,
+                                               _stream(stream)))
+
+
+def quantize(p, which, X, dst, ws, stream=None):
+    """X: float32 device tensor (A: m x k, or B^T: n x k); dst: the A_f / Bt tensor."""
+    return _check("abft_quantize", lib().abft_quantize(C.byref(p), which, _ptr(X), X.stride(0), _ptr(dst), _ptr(ws),
+                                                       _stream(stream)))
 
 
 def _rects(known):
@@ -208,8 +216,9 @@ class Protected:
         cdt = torch.float64 if dtype == ABFT_F64 else torch.float32
         self.p = problem(dtype, m, n, k, br, bc, tau_mode=tau_mode, lam=lam)
         self.M, self.N = m + br, n + bc
-        self.A = torch.zeros(self.M, k, dtype=tdt, device=device)
-        self.Bt = torch.zeros(self.N, k, dtype=tdt, device=device)
+        lowp = dtype in (ABFT_BF16, ABFT_FP8_E4M3)      # checksum rows kept in the workspace
+        self.A = torch.zeros(m if lowp else self.M, k, dtype=tdt, device=device)
+        self.Bt = torch.zeros(n if lowp else self.N, k, dtype=tdt, device=device)
         self.C = torch.zeros(self.M, self.N, dtype=cdt, device=device)
         self.ws = torch.zeros(workspace_size(self.p), dtype=torch.uint8, device=device)
         self.rep_host = new_report_buffer()
@@ -218,7 +227,7 @@ class Protected:
         encode(self.p, self.A, self.Bt, self.ws)
 
     def gemm(self, flags=0):
-        gemm(self.p, self.A, self.Bt, self.C, flags)
+        gemm(self.p, self.A, self.Bt, self.C, self.ws, flags)
 
     def verify(self, known=None) -> abft_report:
         import torch

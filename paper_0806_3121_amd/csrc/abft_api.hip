@@ -40,6 +40,9 @@ WsLayout ws_layout(const abft_problem *p) {
     L.nw = take(sizeof(double) * g.bc);
     L.grpA = take(sizeof(double) * g.br * g.k);
     L.grpB = take(sizeof(double) * g.bc * g.k);
+    L.acs = take(cs_in_ws(p->dtype) ? sizeof(float) * g.br * g.k : 8);
+    L.bcs = take(cs_in_ws(p->dtype) ? sizeof(float) * g.bc * g.k : 8);
+    L.scale = take(16);
     // partial sums: encode A (2 stats), encode B (2 stats), verify columns (1)
     int64_t pa = group_partitions(g.Gr, g.br, g.k);
     int64_t pb = group_partitions(g.Gc, g.bc, g.k);
@@ -91,7 +94,7 @@ static int check_problem(const abft_problem *p) {
     if (p->br > p->m || p->bc > p->n) return ABFT_E_ARG;
     if (p->m % p->br || p->n % p->bc) return ABFT_E_ARG;
     if (p->tau_mode < ABFT_TAU_DET || p->tau_mode > ABFT_TAU_EXACT) return ABFT_E_ARG;
-    if (p->dtype != ABFT_F64 && p->dtype != ABFT_F32) return ABFT_E_UNSUPPORTED;
+    if (p->dtype == ABFT_FP8_E4M3) return ABFT_E_UNSUPPORTED;
     return ABFT_OK;
 }
 
@@ -226,13 +229,29 @@ int abft_encode(const abft_problem *p, void *A_f, void *B_f, void *ws, void *str
     return launch_encode(p, A_f, B_f, (char *)ws, (hipStream_t)stream);
 }
 
-int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, void *stream) {
+int abft_quantize(const abft_problem *p, int which, const float *X, int64_t ldx, void *dst, void *ws, void *stream) {
+    int st = check_problem(p);
+    if (st) return st;
+    if (!cs_in_ws(p->dtype)) return ABFT_E_ARG;
+    if (which != 0 && which != 1) return ABFT_E_ARG;
+    if (!X || !dst || ((uintptr_t)X & 15u) || ((uintptr_t)dst & 15u)) return ABFT_E_ARG;
+    if (ldx < p->k || (ldx * 4) % 16) return ABFT_E_ARG;
+    int64_t ldd = which == 0 ? p->lda : p->ldb;
+    size_t es = dtype_size(p->dtype);
+    if (ldd < p->k || (ldd * es) % 16 || (p->k * es) % 16) return ABFT_E_ARG;
+    if (!ws) return ABFT_E_WORKSPACE;
+    return launch_quantize(p, which, X, ldx, dst, (char *)ws, (hipStream_t)stream);
+}
+
+int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, void *ws, uint32_t flags,
+              void *stream) {
     int st = check_problem(p);
     if (st) return st;
     if (flags & ~ABFT_PLAIN) return ABFT_E_ARG;
     if ((st = check_operands(p, A_f, B_f))) return st;
     if ((st = check_c(p, C_f, flags & ABFT_PLAIN))) return st;
-    return launch_gemm(p, A_f, B_f, C_f, flags, (hipStream_t)stream);
+    if (cs_in_ws(p->dtype) && !(flags & ABFT_PLAIN) && !ws) return ABFT_E_WORKSPACE;
+    return launch_gemm(p, A_f, B_f, C_f, flags, ws, (hipStream_t)stream);
 }
 
 int abft_verify(const abft_problem *p, const void *C_f, const abft_rect *known, int n_known, void *ws,

@@ -48,6 +48,9 @@ inline size_t dtype_size(int dt) {
     }
 }
 inline size_t c_size(int dt) { return dt == ABFT_F64 ? 8 : 4; }
+// Low-precision inputs keep their checksum rows in binary32 in the workspace;
+// F64 and F32 keep them in the extra rows of A_f / B_f.
+inline bool cs_in_ws(int dt) { return dt == ABFT_BF16 || dt == ABFT_FP8_E4M3; }
 
 // ------------------------------------------------------------------ geometry
 struct Geom {
@@ -99,6 +102,8 @@ struct WsLayout {
     size_t na, na_abs, nb, nb_abs;   // det statistics (double)
     size_t qr, qc, nv, nw;           // stat statistics (double)
     size_t grpA, grpB;               // per-residue group sums of |A| (or A^2) and of |B| (double, br*k / bc*k)
+    size_t acs, bcs;                 // binary32 checksum rows of low-precision operands (float, br*k / bc*k)
+    size_t scale;                    // FP8 per-tensor scale exponents and amax scratch (4 x int32)
     size_t partial;                  // two-level reduction partials (double)
     size_t report;                   // abft_report
     size_t total;
@@ -124,7 +129,8 @@ void set_hip_error(hipError_t e);
 
 // ------------------------------------------------------------------ launchers (return abft_status)
 int launch_encode(const abft_problem *p, void *A_f, void *B_f, char *ws, hipStream_t s);
-int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, hipStream_t s);
+int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, void *ws,
+                hipStream_t s);
 int launch_verify(const abft_problem *p, const void *C_f, const Erasures &er, char *ws, hipStream_t s);
 int launch_correct(const abft_problem *p, void *C_f, int64_t i, int64_t j, int dir, hipStream_t s);
 int launch_recover(const abft_problem *p, void *C_f, abft_rect e, int use_rows, hipStream_t s);
@@ -132,6 +138,7 @@ int launch_inject_flip(const abft_problem *p, void *C_f, int64_t i, int64_t j, i
 int launch_inject_erase(const abft_problem *p, void *C_f, abft_rect e, int nan_fill, hipStream_t s);
 int launch_fill_uniform(int32_t dtype, int64_t rows, int64_t cols, int64_t ld, int transpose, uint64_t seed,
                         int32_t stream_id, void *dst, hipStream_t s);
+int launch_quantize(const abft_problem *p, int which, const float *X, int64_t ldx, void *dst, char *ws, hipStream_t s);
 
 // Threshold coefficients shared by encode (statistics) and verify.
 struct TauCoef {

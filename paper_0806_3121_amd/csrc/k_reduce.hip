@@ -224,9 +224,46 @@ int launch_encode(const abft_problem *p, void *A_f, void *B_f, char *ws, hipStre
         float *A = (float *)A_f, *Bt = (float *)B_f;
         return encode_typed<float, float>(p, A, Bt, A + g.m * p->lda, p->lda, Bt + g.n * p->ldb, p->ldb, ws, s);
     }
+    case ABFT_BF16: {
+        // bfloat16 data, binary32 checksum rows in the workspace
+        WsLayout L = ws_layout(p);
+        return encode_typed<uint16_t, float>(p, (uint16_t *)A_f, (uint16_t *)B_f, (float *)(ws + L.acs), g.k,
+                                             (float *)(ws + L.bcs), g.k, ws, s);
+    }
     default:
         return ABFT_E_UNSUPPORTED;
     }
+}
+
+// ------------------------------------------------------------------ quantize
+// binary32 -> bfloat16, round to nearest even; 8 values per thread and step.
+__global__ __launch_bounds__(kThreads) void k_quantize_bf16(const float *X, int64_t ldx, int64_t rows, int64_t k,
+                                                            uint16_t *Q, int64_t ldq) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    const int64_t per_row = k / 8, total = rows * per_row;
+    for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
+        int64_t i = t / per_row, c = (t - i * per_row) * 8;
+        v4 x0 = *(const v4 *)(X + i * ldx + c), x1 = *(const v4 *)(X + i * ldx + c + 4);
+        v4u o;
+        o[0] = f32_to_bf16_rne(x0[0]) | ((uint32_t)f32_to_bf16_rne(x0[1]) << 16);
+        o[1] = f32_to_bf16_rne(x0[2]) | ((uint32_t)f32_to_bf16_rne(x0[3]) << 16);
+        o[2] = f32_to_bf16_rne(x1[0]) | ((uint32_t)f32_to_bf16_rne(x1[1]) << 16);
+        o[3] = f32_to_bf16_rne(x1[2]) | ((uint32_t)f32_to_bf16_rne(x1[3]) << 16);
+        *(v4u *)(Q + i * ldq + c) = o;
+    }
+}
+
+int launch_quantize(const abft_problem *p, int which, const float *X, int64_t ldx, void *dst, char *ws, hipStream_t s) {
+    (void)ws;
+    int64_t rows = which == 0 ? p->m : p->n;
+    int64_t ldq = which == 0 ? p->lda : p->ldb;
+    if (p->dtype == ABFT_BF16) {
+        k_quantize_bf16<<<grid_for(rows * p->k / 8), kThreads, 0, s>>>(X, ldx, rows, p->k, (uint16_t *)dst, ldq);
+        ABFT_LAUNCHED();
+        return ABFT_OK;
+    }
+    return ABFT_E_UNSUPPORTED;
 }
 
 // ------------------------------------------------------------------ verify

@@ -46,7 +46,7 @@ def test_bad_problem_rejected_before_launch(field, value):
     setattr(p, field, value)
     fake = C.c_void_p(256)     # never dereferenced: the checks fail first
     assert abft.workspace_size(p) == 0
-    assert _call("abft_gemm", C.byref(p), fake, fake, fake, 0, NULL_STREAM) == abft.ABFT_E_ARG
+    assert _call("abft_gemm", C.byref(p), fake, fake, fake, None, 0, NULL_STREAM) == abft.ABFT_E_ARG
 
 
 def test_layout_and_alignment_rejected():
@@ -54,10 +54,10 @@ def test_layout_and_alignment_rejected():
     p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1, lda=255)
     assert _call("abft_encode", C.byref(p), fake, fake, fake, NULL_STREAM) == abft.ABFT_E_ARG
     p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1, ldc=256)          # < n + bc
-    assert _call("abft_gemm", C.byref(p), fake, fake, fake, 0, NULL_STREAM) == abft.ABFT_E_ARG
+    assert _call("abft_gemm", C.byref(p), fake, fake, fake, None, 0, NULL_STREAM) == abft.ABFT_E_ARG
     p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1)
-    assert _call("abft_gemm", C.byref(p), C.c_void_p(8), fake, fake, 0, NULL_STREAM) == abft.ABFT_E_ARG
-    assert _call("abft_gemm", C.byref(p), fake, fake, fake, 8, NULL_STREAM) == abft.ABFT_E_ARG   # unknown flag
+    assert _call("abft_gemm", C.byref(p), C.c_void_p(8), fake, fake, None, 0, NULL_STREAM) == abft.ABFT_E_ARG
+    assert _call("abft_gemm", C.byref(p), fake, fake, fake, None, 8, NULL_STREAM) == abft.ABFT_E_ARG   # unknown flag
     assert _call("abft_encode", C.byref(p), fake, fake, None, NULL_STREAM) == abft.ABFT_E_WORKSPACE
     p = abft.problem(abft.ABFT_F64, 256, 256, 251, 1, 1, lda=252, ldb=252)  # k*8 not a multiple of 16
     assert _call("abft_encode", C.byref(p), fake, fake, fake, NULL_STREAM) == abft.ABFT_E_ARG
