@@ -94,7 +94,6 @@ static int check_problem(const abft_problem *p) {
     if (p->br > p->m || p->bc > p->n) return ABFT_E_ARG;
     if (p->m % p->br || p->n % p->bc) return ABFT_E_ARG;
     if (p->tau_mode < ABFT_TAU_DET || p->tau_mode > ABFT_TAU_EXACT) return ABFT_E_ARG;
-    if (p->dtype == ABFT_FP8_E4M3) return ABFT_E_UNSUPPORTED;
     return ABFT_OK;
 }
 
@@ -250,7 +249,7 @@ int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f
     if (flags & ~ABFT_PLAIN) return ABFT_E_ARG;
     if ((st = check_operands(p, A_f, B_f))) return st;
     if ((st = check_c(p, C_f, flags & ABFT_PLAIN))) return st;
-    if (cs_in_ws(p->dtype) && !(flags & ABFT_PLAIN) && !ws) return ABFT_E_WORKSPACE;
+    if (!ws && (p->dtype == ABFT_FP8_E4M3 || (p->dtype == ABFT_BF16 && !(flags & ABFT_PLAIN)))) return ABFT_E_WORKSPACE;
     return launch_gemm(p, A_f, B_f, C_f, flags, ws, (hipStream_t)stream);
 }
 

@@ -27,6 +27,42 @@ __host__ __device__ inline uint16_t f32_to_bf16_rne(float f) {
     return (uint16_t)((u + rounding) >> 16);
 }
 
+// OCP FP8 E4M3 (e4m3fn): bias 7, 3 fraction bits, largest finite 448, no
+// infinities, S.1111.111 is NaN.  Decoding is exact in binary32.
+__host__ __device__ inline float e4m3_to_f32(uint8_t c) {
+    uint32_t e = (c >> 3) & 15u, f = c & 7u;
+    float v;
+    if (e == 0) {
+        v = (float)f * 0x1p-9f;
+    } else {
+        uint32_t u = ((e + 120u) << 23) | (f << 20);
+        __builtin_memcpy(&v, &u, 4);
+    }
+    return (c & 0x80u) ? -v : v;
+}
+
+// binary32 -> E4M3, round to nearest, ties to even fraction; |x| >= 464 (the
+// midpoint above 448 and beyond) saturates to +-448; NaN -> 0x7F.
+__host__ __device__ inline uint8_t f32_to_e4m3_rne(float x) {
+    uint32_t u;
+    __builtin_memcpy(&u, &x, 4);
+    uint8_t sign = (uint8_t)((u >> 24) & 0x80u);
+    uint32_t a = u & 0x7FFFFFFFu;
+    if (a > 0x7F800000u) return 0x7F;
+    float ax;
+    __builtin_memcpy(&ax, &a, 4);
+    if (ax >= 464.0f) return sign | 0x7E;
+    if (ax < 0x1p-6f) {                                   // subnormal grid: multiples of 2^-9
+        float q = __builtin_rintf(ax * 512.0f);          // exact scaling, ties to even
+        return sign | (uint8_t)q;                         // q == 8 is 2^-6, code 0x08
+    }
+    uint32_t r = (a + 0x7FFFFu + ((a >> 20) & 1u)) & 0xFFF00000u;   // round the fraction at bit 20
+    int E = (int)(r >> 23) - 127;
+    uint32_t code = ((uint32_t)(E + 7) << 3) | ((r >> 20) & 7u);
+    if (code > 0x7Eu) code = 0x7E;
+    return sign | (uint8_t)code;
+}
+
 template <typename T> struct elem;
 template <> struct elem<double> {
     __device__ static double load(const double *p) { return *p; }
@@ -36,6 +72,9 @@ template <> struct elem<float> {
 };
 template <> struct elem<uint16_t> {   // bfloat16 storage
     __device__ static double load(const uint16_t *p) { return (double)bf16_to_f32(*p); }
+};
+template <> struct elem<uint8_t> {    // FP8 E4M3 storage (values in the scaled domain)
+    __device__ static double load(const uint8_t *p) { return (double)e4m3_to_f32(*p); }
 };
 
 inline size_t dtype_size(int dt) {

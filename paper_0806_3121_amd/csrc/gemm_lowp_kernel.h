@@ -1,9 +1,16 @@
-// bfloat16 x bfloat16 -> binary32 product on the gfx950 matrix cores
-// (v_mfma_f32_16x16x32_bf16), templated on the tile shape.  A is row-major and
-// B column-major (Bt row-major), both k-contiguous, so every operand fragment
-// is one 16-byte LDS read: lane l of a 16 x 32 block holds row l % 16,
-// k = 8 * (l / 16) .. +7 (both operands); accumulator value v of lane l is
-// C[4 * (l / 16) + v][l % 16] (measured on gfx950).
+// Low-precision products with binary32 accumulation on the gfx950 matrix
+// cores, templated on the element type and the tile shape:
+//   bfloat16: v_mfma_f32_16x16x32_bf16 (16 x 16 x 32 per instruction)
+//   FP8 E4M3 (OCP e4m3fn): v_mfma_f32_16x16x32_fp8_fp8
+// A is row-major and B column-major (Bt row-major), both k-contiguous.  Each
+// lane reads one 16-byte fragment of its row per 64-byte k group: lane l of a
+// 16-row block holds row l % 16 and the 16 bytes at k-byte offset
+// 16 * (l / 16); bfloat16 feeds it to one MFMA (8 values), FP8 to two MFMAs
+// (8 values each).  A and B use the same k mapping, so every product is
+// formed exactly once.  Accumulator value v of lane l is
+// C[4 * (l / 16) + v][l % 16] (measured on gfx950).  FP8 products are scaled
+// back by 2^-(eA + eB), read from the device (the per-tensor scales of the
+// quantizer), in the epilogue: an exact power-of-two scaling.
 //
 // Block tile BM x BN, WM x WN waves; K advances in BK-wide slabs through a
 // double-buffered LDS (one barrier per slab, the next slab's global loads in
@@ -19,11 +26,34 @@ namespace abft {
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
-template <int BM_, int BN_, int BK_, int WM_, int WN_, int GROUP_M_ = 8, int MINB_ = 1>
-struct Bf16Tile {
+struct Bf16Ops {
+    typedef uint16_t E;
+    static constexpr int KG = 32;       // k per fragment read across the wave's four lane groups
+    __device__ static void mfma(const v4u &a, const v4u &b, v4f &c) {
+        v8bf x, y;
+        __builtin_memcpy(&x, &a, 16);
+        __builtin_memcpy(&y, &b, 16);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+    }
+};
+struct Fp8Ops {
+    typedef uint8_t E;
+    static constexpr int KG = 64;
+    __device__ static void mfma(const v4u &a, const v4u &b, v4f &c) {
+        long a0 = (long)(((uint64_t)a[1] << 32) | a[0]), a1 = (long)(((uint64_t)a[3] << 32) | a[2]);
+        long b0 = (long)(((uint64_t)b[1] << 32) | b[0]), b1 = (long)(((uint64_t)b[3] << 32) | b[2]);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, c, 0, 0, 0);
+    }
+};
+
+template <class Ops_, int BM_, int BN_, int BK_, int WM_, int WN_, int GROUP_M_ = 8, int MINB_ = 1>
+struct LowpTile {
+    typedef Ops_ Ops;
+    typedef typename Ops::E E;
     static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_, GROUP_M = GROUP_M_, MINB = MINB_;
-    static constexpr int VEC = 8;                           // bfloat16 per 16-byte load
-    static constexpr int LDSROW = BK + VEC;                 // elements per LDS row
+    static constexpr int VEC = 16 / (int)sizeof(E);        // elements per 16-byte load
+    static constexpr int LDSROW = BK + VEC;                 // elements per LDS row (16-byte skew)
     static constexpr int THREADS = 64 * WM * WN;
     static constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
     static constexpr int VPR = BK / VEC;
@@ -31,16 +61,17 @@ struct Bf16Tile {
     static constexpr int PASSES_A = BM / ROWS_PER_PASS, PASSES_B = BN / ROWS_PER_PASS;
     static constexpr int BUF = (BM + BN) * LDSROW;
     static_assert(BM % (WM * 16) == 0 && BN % (WN * 16) == 0, "wave tile");
-    static_assert(BK % 32 == 0, "k group");
+    static_assert(BK % Ops::KG == 0, "k group");
     static_assert(THREADS % VPR == 0 && BM % ROWS_PER_PASS == 0 && BN % ROWS_PER_PASS == 0, "load split");
 };
 
 template <class T>
-__global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_bf16(const uint16_t *__restrict__ A, int64_t lda,
-                                                             const uint16_t *__restrict__ Bt, int64_t ldb,
+__global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_lowp(const typename T::E *__restrict__ A, int64_t lda,
+                                                             const typename T::E *__restrict__ Bt, int64_t ldb,
                                                              float *__restrict__ C, int64_t ldc, int64_t M, int64_t N,
-                                                             int64_t K) {
-    __shared__ uint16_t lds[2 * T::BUF];
+                                                             int64_t K, const int *__restrict__ scale_exp) {
+    typedef typename T::E E;
+    __shared__ E lds[2 * T::BUF];
 
     const int64_t tiles_m = (M + T::BM - 1) / T::BM, tiles_n = (N + T::BN - 1) / T::BN;
     int64_t tm, tn;
@@ -53,8 +84,8 @@ __global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_bf16(const uint16_
 
     const int lr = tid / T::VPR, lv = tid % T::VPR;
     v4u ra[T::PASSES_A], rb[T::PASSES_B];
-    const uint16_t *pa[T::PASSES_A];
-    const uint16_t *pb[T::PASSES_B];
+    const E *pa[T::PASSES_A];
+    const E *pb[T::PASSES_B];
     bool oka[T::PASSES_A], okb[T::PASSES_B];
 #pragma unroll
     for (int p = 0; p < T::PASSES_A; ++p) {
@@ -79,8 +110,8 @@ __global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_bf16(const uint16_
         for (int p = 0; p < T::PASSES_B; ++p) rb[p] = *(const v4u *)(pb[p] + ko);
     };
     auto store_slab = [&](int buf) {
-        uint16_t *As = lds + buf * T::BUF;
-        uint16_t *Bs = As + T::BM * T::LDSROW;
+        E *As = lds + buf * T::BUF;
+        E *Bs = As + T::BM * T::LDSROW;
 #pragma unroll
         for (int p = 0; p < T::PASSES_A; ++p)
             *(v4u *)(As + (lr + p * T::ROWS_PER_PASS) * T::LDSROW + T::VEC * lv) = (oka[p] && kin) ? ra[p] : zero;
@@ -95,7 +126,7 @@ __global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_bf16(const uint16_
 #pragma unroll
         for (int b = 0; b < T::TN; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    const int lrow = lane % 16, lk = 8 * (lane / 16);
+    const int lrow = lane % 16, lk = T::VEC * (lane / 16);
     const int a_off = (wm * (T::BM / T::WM) + lrow) * T::LDSROW + lk;
     const int b_off = T::BM * T::LDSROW + (wn * (T::BN / T::WN) + lrow) * T::LDSROW + lk;
 
@@ -106,25 +137,25 @@ __global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_bf16(const uint16_
     for (int64_t kt = 0; kt < nk; ++kt) {
         const bool more = kt + 1 < nk;
         if (more) load_slab((kt + 1) * T::BK);
-        const uint16_t *Aw = lds + (kt & 1) * T::BUF + a_off;
-        const uint16_t *Bw = lds + (kt & 1) * T::BUF + b_off;
+        const E *Aw = lds + (kt & 1) * T::BUF + a_off;
+        const E *Bw = lds + (kt & 1) * T::BUF + b_off;
 #pragma unroll
-        for (int kg = 0; kg < T::BK; kg += 32) {
-            v8bf fa[T::TM], fb[T::TN];
+        for (int kg = 0; kg < T::BK; kg += T::Ops::KG) {
+            v4u fa[T::TM], fb[T::TN];
 #pragma unroll
-            for (int a = 0; a < T::TM; ++a) fa[a] = *(const v8bf *)(Aw + a * 16 * T::LDSROW + kg);
+            for (int a = 0; a < T::TM; ++a) fa[a] = *(const v4u *)(Aw + a * 16 * T::LDSROW + kg);
 #pragma unroll
-            for (int b = 0; b < T::TN; ++b) fb[b] = *(const v8bf *)(Bw + b * 16 * T::LDSROW + kg);
+            for (int b = 0; b < T::TN; ++b) fb[b] = *(const v4u *)(Bw + b * 16 * T::LDSROW + kg);
 #pragma unroll
             for (int a = 0; a < T::TM; ++a)
 #pragma unroll
-                for (int b = 0; b < T::TN; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+                for (int b = 0; b < T::TN; ++b) T::Ops::mfma(fa[a], fb[b], acc[a][b]);
         }
         if (more) store_slab((kt + 1) & 1);
         __syncthreads();
     }
 
+    const float sc = scale_exp ? __builtin_ldexpf(1.0f, -(scale_exp[0] + scale_exp[1])) : 1.0f;
     const int ccol = lane % 16;
 #pragma unroll
     for (int a = 0; a < T::TM; ++a) {
@@ -134,18 +165,18 @@ __global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_bf16(const uint16_
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 int64_t gr = row0 + wm * (T::BM / T::WM) + a * 16 + 4 * (lane / 16) + v;
-                if (gr < M && gc < N) C[gr * ldc + gc] = acc[a][b][v];
+                if (gr < M && gc < N) C[gr * ldc + gc] = acc[a][b][v] * sc;
             }
         }
     }
 }
 
 template <class T>
-inline int launch_gemm_bf16_tile(const uint16_t *A, int64_t lda, const uint16_t *Bt, int64_t ldb, float *C,
-                                 int64_t ldc, int64_t M, int64_t N, int64_t K, hipStream_t s) {
+inline int launch_gemm_lowp_tile(const typename T::E *A, int64_t lda, const typename T::E *Bt, int64_t ldb, float *C,
+                                 int64_t ldc, int64_t M, int64_t N, int64_t K, const int *scale_exp, hipStream_t s) {
     int64_t tiles = ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
     if (tiles > INT32_MAX) return ABFT_E_ARG;
-    k_gemm_bf16<T><<<(unsigned)tiles, T::THREADS, 0, s>>>(A, lda, Bt, ldb, C, ldc, M, N, K);
+    k_gemm_lowp<T><<<(unsigned)tiles, T::THREADS, 0, s>>>(A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp);
     return ABFT_OK;
 }
 

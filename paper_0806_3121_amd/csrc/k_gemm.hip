@@ -6,7 +6,7 @@
 // few useful rows, so it is computed instead by the skinny-product kernel
 // (sliver_kernel.h), which streams the other operand once with binary64
 // accumulation.
-#include "gemm_bf16_kernel.h"
+#include "gemm_lowp_kernel.h"
 #include "gemm_mfma_kernel.h"
 #include "sliver_kernel.h"
 
@@ -70,43 +70,50 @@ static int protected_product(const abft_problem *p, const Geom &g, const E *A, c
     ABFT_LAUNCHED();
     // carried row block over all N columns (corner included), then the carried
     // column block over the rows the main product covered
-    if (thin_r && (st = launch_sliver_rows<E, E, E>(g, A + g.m * p->lda, p->lda, Bt, p->ldb, C, p->ldc, 1.0, s)))
+    if (thin_r && (st = launch_sliver_rows<E, E, E>(g, A + g.m * p->lda, p->lda, Bt, p->ldb, C, p->ldc, s)))
         return st;
-    if (thin_c && (st = launch_sliver_cols<E, E, E>(g, Mm, A, p->lda, Bt + g.n * p->ldb, p->ldb, C, p->ldc, 1.0, s)))
+    if (thin_c && (st = launch_sliver_cols<E, E, E>(g, Mm, A, p->lda, Bt + g.n * p->ldb, p->ldb, C, p->ldc, s)))
         return st;
     return ABFT_OK;
 }
 
-// bfloat16 candidates; efficiencies measured on MI355X at 16384^3.
-static const TileChoice kBf16Tiles[] = {
+// bfloat16 / FP8 candidates; efficiencies measured on MI355X at 16384^3 (bfloat16).
+static const TileChoice kLowpTiles[] = {
     {0, 256, 256, 1, 0.411}, {1, 128, 128, 2, 0.303},
 };
-static int gemm_main_bf16(const uint16_t *A, int64_t lda, const uint16_t *Bt, int64_t ldb, float *C, int64_t ldc,
-                          int64_t M, int64_t N, int64_t K, hipStream_t s) {
-    switch (choose_tile(kBf16Tiles, 2, M, N)) {
-    case 0: return launch_gemm_bf16_tile<Bf16Tile<256, 256, 64, 4, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
-    default: return launch_gemm_bf16_tile<Bf16Tile<128, 128, 64, 2, 2, 8, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
+template <class Ops>
+static int gemm_main_lowp(const typename Ops::E *A, int64_t lda, const typename Ops::E *Bt, int64_t ldb, float *C,
+                          int64_t ldc, int64_t M, int64_t N, int64_t K, const int *scale_exp, hipStream_t s) {
+    switch (choose_tile(kLowpTiles, 2, M, N)) {
+    case 0:
+        return launch_gemm_lowp_tile<LowpTile<Ops, 256, 256, 64, 4, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp, s);
+    default:
+        return launch_gemm_lowp_tile<LowpTile<Ops, 128, 128, 64, 2, 2, 8, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K,
+                                                                              scale_exp, s);
     }
 }
 
 // Low-precision operands: the data part on the matrix cores, every carried
 // block from the binary32 checksum rows in the workspace (Acs: br x k,
-// Bcs: bc x k) with binary64 accumulation.
-template <typename E>
-static int protected_product_lowp(const abft_problem *p, const Geom &g, const E *A, const E *Bt, float *C,
-                                  const float *Acs, const float *Bcs, bool plain, hipStream_t s) {
-    int st = gemm_main_bf16(A, p->lda, Bt, p->ldb, C, p->ldc, g.m, g.n, g.k, s);
+// Bcs: bc x k) with binary64 accumulation; FP8 results are scaled back by
+// 2^-(eA + eB) on the device.
+template <class Ops>
+static int protected_product_lowp(const abft_problem *p, const Geom &g, const typename Ops::E *A,
+                                  const typename Ops::E *Bt, float *C, const float *Acs, const float *Bcs,
+                                  const int *scale_exp, bool plain, hipStream_t s) {
+    typedef typename Ops::E E;
+    int st = gemm_main_lowp<Ops>(A, p->lda, Bt, p->ldb, C, p->ldc, g.m, g.n, g.k, scale_exp, s);
     if (st) return st;
     ABFT_LAUNCHED();
     if (plain) return ABFT_OK;
     float *Crow = C + g.m * p->ldc;
     // C_f[m + r, j], j < n
-    if ((st = sliver<E, float, float>(Bt, p->ldb, g.n, Acs, g.k, g.br, g.k, Crow, 1, p->ldc, 1.0, s))) return st;
+    if ((st = sliver<E, float, float>(Bt, p->ldb, g.n, Acs, g.k, g.br, g.k, Crow, 1, p->ldc, scale_exp, s))) return st;
     // corner C_f[m + r, n + c]
-    if ((st = sliver<float, float, float>(Bcs, g.k, g.bc, Acs, g.k, g.br, g.k, Crow + g.n, 1, p->ldc, 1.0, s)))
+    if ((st = sliver<float, float, float>(Bcs, g.k, g.bc, Acs, g.k, g.br, g.k, Crow + g.n, 1, p->ldc, scale_exp, s)))
         return st;
     // C_f[i, n + c], i < m
-    return sliver<E, float, float>(A, p->lda, g.m, Bcs, g.k, g.bc, g.k, C + g.n, p->ldc, 1, 1.0, s);
+    return sliver<E, float, float>(A, p->lda, g.m, Bcs, g.k, g.bc, g.k, C + g.n, p->ldc, 1, scale_exp, s);
 }
 
 int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, void *ws,
@@ -118,11 +125,19 @@ int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C
         return protected_product<double>(p, g, (const double *)A_f, (const double *)B_f, (double *)C_f, plain, s);
     case ABFT_F32:
         return protected_product<float>(p, g, (const float *)A_f, (const float *)B_f, (float *)C_f, plain, s);
-    case ABFT_BF16: {
+    case ABFT_BF16:
+    case ABFT_FP8_E4M3: {
+        // ws may be NULL only for a plain bfloat16 product (no checksum is read)
         WsLayout L = ws_layout(p);
         const char *wsc = (const char *)ws;
-        return protected_product_lowp<uint16_t>(p, g, (const uint16_t *)A_f, (const uint16_t *)B_f, (float *)C_f,
-                                                (const float *)(wsc + L.acs), (const float *)(wsc + L.bcs), plain, s);
+        const float *Acs = ws ? (const float *)(wsc + L.acs) : nullptr;
+        const float *Bcs = ws ? (const float *)(wsc + L.bcs) : nullptr;
+        if (p->dtype == ABFT_BF16)
+            return protected_product_lowp<Bf16Ops>(p, g, (const uint16_t *)A_f, (const uint16_t *)B_f, (float *)C_f,
+                                                   Acs, Bcs, nullptr, plain, s);
+        const int *scale = ws ? (const int *)(wsc + L.scale) : nullptr;
+        return protected_product_lowp<Fp8Ops>(p, g, (const uint8_t *)A_f, (const uint8_t *)B_f, (float *)C_f, Acs,
+                                              Bcs, scale, plain, s);
     }
     default:
         return ABFT_E_UNSUPPORTED;

@@ -230,6 +230,12 @@ int launch_encode(const abft_problem *p, void *A_f, void *B_f, char *ws, hipStre
         return encode_typed<uint16_t, float>(p, (uint16_t *)A_f, (uint16_t *)B_f, (float *)(ws + L.acs), g.k,
                                              (float *)(ws + L.bcs), g.k, ws, s);
     }
+    case ABFT_FP8_E4M3: {
+        // E4M3 data (scaled domain), binary32 checksum rows in the workspace
+        WsLayout L = ws_layout(p);
+        return encode_typed<uint8_t, float>(p, (uint8_t *)A_f, (uint8_t *)B_f, (float *)(ws + L.acs), g.k,
+                                            (float *)(ws + L.bcs), g.k, ws, s);
+    }
     default:
         return ABFT_E_UNSUPPORTED;
     }
@@ -254,12 +260,72 @@ __global__ __launch_bounds__(kThreads) void k_quantize_bf16(const float *X, int6
     }
 }
 
+// FP8 per-tensor scaling, kept on the device (no host synchronisation):
+// amax = max |x| (binary32 bit patterns of non-negative values order like
+// unsigned integers), then the scale exponent e = the largest e with
+// amax * 2^e <= 448 (0 when amax is 0), then x * 2^e (exact) rounded to E4M3.
+// ws scale words: [0] = e_A, [1] = e_B, [2] = amax_A bits, [3] = amax_B bits.
+__global__ void k_amax_init(int *scale, int which) { scale[2 + which] = 0; }
+
+__global__ __launch_bounds__(kThreads) void k_amax(const float *X, int64_t ldx, int64_t rows, int64_t k, int *scale,
+                                                   int which) {
+    __shared__ float sh[kThreads / kWave];
+    float mx = 0.0f;
+    const int64_t total = rows * k;
+    for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
+        int64_t i = t / k, l = t - i * k;
+        mx = fmaxf(mx, fabsf(X[i * ldx + l]));
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, kWave));
+    if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < kThreads / kWave; ++q) mx = fmaxf(mx, sh[q]);
+        atomicMax((unsigned int *)&scale[2 + which], __float_as_uint(mx));
+    }
+}
+
+__global__ void k_scale_exp(int *scale, int which) {
+    double amax = (double)__uint_as_float((unsigned int)scale[2 + which]);
+    int e = 0;
+    if (amax > 0.0) {
+        while (ldexp(amax, e + 1) <= 448.0) ++e;
+        while (ldexp(amax, e) > 448.0) --e;
+    }
+    scale[which] = e;
+}
+
+__global__ __launch_bounds__(kThreads) void k_quantize_fp8(const float *X, int64_t ldx, int64_t rows, int64_t k,
+                                                           uint8_t *Q, int64_t ldq, const int *scale, int which) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const float f = __builtin_ldexpf(1.0f, scale[which]);
+    const int64_t per_row = k / 4, total = rows * per_row;
+    for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
+        int64_t i = t / per_row, c = (t - i * per_row) * 4;
+        v4 x = *(const v4 *)(X + i * ldx + c);
+        uint32_t o = (uint32_t)f32_to_e4m3_rne(x[0] * f) | ((uint32_t)f32_to_e4m3_rne(x[1] * f) << 8) |
+                     ((uint32_t)f32_to_e4m3_rne(x[2] * f) << 16) | ((uint32_t)f32_to_e4m3_rne(x[3] * f) << 24);
+        *(uint32_t *)(Q + i * ldq + c) = o;
+    }
+}
+
 int launch_quantize(const abft_problem *p, int which, const float *X, int64_t ldx, void *dst, char *ws, hipStream_t s) {
-    (void)ws;
     int64_t rows = which == 0 ? p->m : p->n;
     int64_t ldq = which == 0 ? p->lda : p->ldb;
     if (p->dtype == ABFT_BF16) {
         k_quantize_bf16<<<grid_for(rows * p->k / 8), kThreads, 0, s>>>(X, ldx, rows, p->k, (uint16_t *)dst, ldq);
+        ABFT_LAUNCHED();
+        return ABFT_OK;
+    }
+    if (p->dtype == ABFT_FP8_E4M3) {
+        WsLayout L = ws_layout(p);
+        int *scale = (int *)(ws + L.scale);
+        k_amax_init<<<1, 1, 0, s>>>(scale, which);
+        k_amax<<<(unsigned)std::min<int64_t>((rows * p->k + kThreads - 1) / kThreads, 4096), kThreads, 0, s>>>(
+            X, ldx, rows, p->k, scale, which);
+        k_scale_exp<<<1, 1, 0, s>>>(scale, which);
+        k_quantize_fp8<<<grid_for(rows * p->k / 4), kThreads, 0, s>>>(X, ldx, rows, p->k, (uint8_t *)dst, ldq, scale,
+                                                                      which);
         ABFT_LAUNCHED();
         return ABFT_OK;
     }
@@ -273,20 +339,24 @@ struct VerifyArgs {
     double cc, cr;                  // det coefficients; stat: cc = lambda^2 (u^2/3)(T/2 + s)
     const double *na, *na_abs, *nb, *nb_abs;
     const double *qr, *qc, *nv, *nw;
+    const int *scale_exp;           // FP8: statistics are in the scaled domain, C is not
     abft_report *rep;
     Erasures er;
 };
 
 // det:  tau_c = cc ||(C_C^T|A|)[r,:]||_2 ||B_f[:,j]||_2
 // stat: tau_c = sqrt(cc Q_c[r,j]),  Q_c = qc[j] (br = 1, exact) or nv[r] qc[j] (Cauchy-Schwarz bound)
+__device__ inline double tau_scale(const VerifyArgs &a) {
+    return a.scale_exp ? ldexp(1.0, -(a.scale_exp[0] + a.scale_exp[1])) : 1.0;
+}
 __device__ inline double tau_col(const VerifyArgs &a, int64_t r, int64_t j) {
-    if (a.mode == ABFT_TAU_DET) return a.cc * a.na_abs[r] * a.nb[j];
-    if (a.mode == ABFT_TAU_STAT) return sqrt(a.cc * (a.br == 1 ? a.qc[j] : a.nv[r] * a.qc[j]));
+    if (a.mode == ABFT_TAU_DET) return tau_scale(a) * a.cc * a.na_abs[r] * a.nb[j];
+    if (a.mode == ABFT_TAU_STAT) return tau_scale(a) * sqrt(a.cc * (a.br == 1 ? a.qc[j] : a.nv[r] * a.qc[j]));
     return 0.0;
 }
 __device__ inline double tau_row(const VerifyArgs &a, int64_t i, int64_t c) {
-    if (a.mode == ABFT_TAU_DET) return a.cr * a.na[i] * a.nb_abs[c];
-    if (a.mode == ABFT_TAU_STAT) return sqrt(a.cr * (a.bc == 1 ? a.qr[i] : a.qr[i] * a.nw[c]));
+    if (a.mode == ABFT_TAU_DET) return tau_scale(a) * a.cr * a.na[i] * a.nb_abs[c];
+    if (a.mode == ABFT_TAU_STAT) return tau_scale(a) * sqrt(a.cr * (a.bc == 1 ? a.qr[i] : a.qr[i] * a.nw[c]));
     return 0.0;
 }
 
@@ -411,6 +481,7 @@ static int verify_typed(const abft_problem *p, const T *C, const Erasures &er, c
     a.nb = (const double *)(ws + L.nb); a.nb_abs = (const double *)(ws + L.nb_abs);
     a.qr = (const double *)(ws + L.qr); a.qc = (const double *)(ws + L.qc);
     a.nv = (const double *)(ws + L.nv); a.nw = (const double *)(ws + L.nw);
+    a.scale_exp = p->dtype == ABFT_FP8_E4M3 ? (const int *)(ws + L.scale) : nullptr;
     a.rep = (abft_report *)(ws + L.report);
     a.er = er;
     k_report_init<<<1, kThreads, 0, s>>>(a.rep);

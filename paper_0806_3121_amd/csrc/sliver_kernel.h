@@ -16,6 +16,7 @@ namespace abft {
 constexpr int kSliverThreads = 256;
 constexpr int kSliverR = 8;   // few rows per pass
 
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
 template <typename T> struct vec16;                  // one 16-byte load, widened to double
 template <> struct vec16<double> {
     static constexpr int N = 2;
@@ -46,16 +47,29 @@ template <> struct vec16<uint16_t> {                 // bfloat16
     }
 };
 
+template <> struct vec16<uint8_t> {                  // FP8 E4M3
+    static constexpr int N = 16;
+    __device__ static void load(const uint8_t *p, double *o) {
+        v4u32 v = *(const v4u32 *)p;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) o[q] = (double)e4m3_to_f32((uint8_t)(v[q / 4] >> (8 * (q % 4))));
+    }
+};
+
 template <typename T> __device__ inline void store_out(T *p, double v);
 template <> __device__ inline void store_out<double>(double *p, double v) { *p = v; }
 template <> __device__ inline void store_out<float>(float *p, double v) { *p = (float)v; }
 
 // X: U rows of type TX (ldx); Y: R rows of type TY (ldy), R <= kSliverR per launch.
-// out[u*ou + s*os] = scale * sum_l X[u,l] Y[s,l].  K is a multiple of both vector widths.
+// out[u*ou + s*os] = scale * sum_l X[u,l] Y[s,l], scale = 2^-(e[0] + e[1]) when
+// the device scale exponents e are given (FP8), else 1.  K is a multiple of
+// both vector widths.
 template <typename TX, typename TY, typename TC>
 __global__ __launch_bounds__(kSliverThreads) void k_sliver(const TX *__restrict__ X, int64_t ldx, int64_t U,
                                                           const TY *__restrict__ Y, int64_t ldy, int R, int64_t K,
-                                                          TC *__restrict__ out, int64_t ou, int64_t os, double scale) {
+                                                          TC *__restrict__ out, int64_t ou, int64_t os,
+                                                          const int *__restrict__ scale_exp) {
+    const double scale = scale_exp ? ldexp(1.0, -(scale_exp[0] + scale_exp[1])) : 1.0;
     constexpr int VX = vec16<TX>::N, VY = vec16<TY>::N;
     constexpr int V = VX > VY ? VX : VY;             // k per lane per step
     const int lane = threadIdx.x % 64;
@@ -92,13 +106,13 @@ __global__ __launch_bounds__(kSliverThreads) void k_sliver(const TX *__restrict_
 
 template <typename TX, typename TY, typename TC>
 inline int sliver(const TX *X, int64_t ldx, int64_t U, const TY *Y, int64_t ldy, int64_t R, int64_t K, TC *out,
-                  int64_t ou, int64_t os, double scale, hipStream_t s) {
+                  int64_t ou, int64_t os, const int *scale_exp, hipStream_t s) {
     const int64_t waves_per_block = kSliverThreads / 64;
     unsigned blocks = (unsigned)std::min<int64_t>((U + waves_per_block - 1) / waves_per_block, 4096);
     for (int64_t r0 = 0; r0 < R; r0 += kSliverR) {
         int rr = (int)std::min<int64_t>(kSliverR, R - r0);
         k_sliver<TX, TY, TC><<<blocks, kSliverThreads, 0, s>>>(X, ldx, U, Y + r0 * ldy, ldy, rr, K, out + r0 * os, ou,
-                                                               os, scale);
+                                                               os, scale_exp);
     }
     ABFT_LAUNCHED();
     return ABFT_OK;
@@ -107,14 +121,14 @@ inline int sliver(const TX *X, int64_t ldx, int64_t U, const TY *Y, int64_t ldy,
 // Carried row block: C_f[m + r, 0:N) = sum_l Acs[r, l] Bt[j, l] (checksum rows Acs, br x k).
 template <typename TA, typename TB, typename TC>
 inline int launch_sliver_rows(const Geom &g, const TA *Acs, int64_t ldacs, const TB *Bt, int64_t ldb, TC *C,
-                              int64_t ldc, double scale, hipStream_t s) {
-    return sliver<TB, TA, TC>(Bt, ldb, g.N, Acs, ldacs, g.br, g.k, C + g.m * ldc, 1, ldc, scale, s);
+                              int64_t ldc, hipStream_t s) {
+    return sliver<TB, TA, TC>(Bt, ldb, g.N, Acs, ldacs, g.br, g.k, C + g.m * ldc, 1, ldc, nullptr, s);
 }
 // Carried column block: C_f[0:rows, n + c) = sum_l A[i, l] Bcs[c, l] (checksum columns Bcs, bc x k).
 template <typename TA, typename TB, typename TC>
 inline int launch_sliver_cols(const Geom &g, int64_t rows, const TA *A, int64_t lda, const TB *Bcs, int64_t ldbcs,
-                              TC *C, int64_t ldc, double scale, hipStream_t s) {
-    return sliver<TA, TB, TC>(A, lda, rows, Bcs, ldbcs, g.bc, g.k, C + g.n, ldc, 1, scale, s);
+                              TC *C, int64_t ldc, hipStream_t s) {
+    return sliver<TA, TB, TC>(A, lda, rows, Bcs, ldbcs, g.bc, g.k, C + g.n, ldc, 1, nullptr, s);
 }
 
 }  // namespace abft

@@ -1,9 +1,11 @@
-"""GPU parity of the bfloat16 path (binary32 inputs quantized to bfloat16 on
-the GPU, bfloat16 matrix cores with binary32 accumulation, binary32 checksum
-rows in the workspace, statistical thresholds) against the CPU oracle.
+"""GPU parity of the bfloat16 and FP8-E4M3 paths (binary32 inputs quantized on
+the GPU, low-precision matrix cores with binary32 accumulation, binary32
+checksum rows in the workspace, statistical thresholds) against the CPU oracle.
 
 The oracle quantizes the same binary32 inputs with its own round-to-nearest-
-even, works on the quantized values exactly in binary64, rounds its checksum
+even (FP8: after its own per-tensor power-of-two scale 2^e, the largest with
+amax * 2^e <= 448), works on the quantized values exactly in binary64 (FP8 in
+the scaled domain, the product scaled back by 2^-(eA+eB)), rounds its checksum
 rows once to binary32 and its product to binary32.
  - quantized operands: bit-exact;
  - values: per element |C_gpu - C_oracle| <= k u32 (|A_q||B_q|)_ij + u32 |C_ij|
@@ -36,39 +38,56 @@ def dev():
     return torch.device("cuda:0")
 
 
-def make(dev, orc, m, n, k, br, bc):
+DTYPES = {"bf16": abft.ABFT_BF16, "fp8": abft.ABFT_FP8_E4M3}
+
+
+def oracle_quantize(orc, dt, X32):
+    """-> (stored codes, values in the compute domain, scale exponent)."""
+    if dt == "bf16":
+        q = orc.to_bf16_bits(X32)
+        return q, orc.bf16_bits_to_f64(q), 0
+    e = orc.e4m3_scale_exp(X32)
+    q = orc.to_e4m3_codes(X32 * np.float32(2.0 ** e))
+    return q, orc.e4m3_values(q), e
+
+
+def stored_codes(t, dt):
+    return t.cpu().view(torch.int16).numpy().view(np.uint16) if dt == "bf16" else t.cpu().numpy()
+
+
+def make(dev, orc, m, n, k, br, bc, dt="bf16"):
     A32 = synth.uniform(SEED, synth.STREAM_A, m, k, np.float32)
     B32 = synth.uniform(SEED, synth.STREAM_B, k, n, np.float32)
-    P = abft.Protected(abft.ABFT_BF16, m, n, k, br, bc, device=dev, tau_mode=abft.ABFT_TAU_STAT, lam=LAMBDA)
+    P = abft.Protected(DTYPES[dt], m, n, k, br, bc, device=dev, tau_mode=abft.ABFT_TAU_STAT, lam=LAMBDA)
     abft.quantize(P.p, 0, torch.from_numpy(A32).to(dev), P.A, P.ws)
     abft.quantize(P.p, 1, torch.from_numpy(np.ascontiguousarray(B32.T)).to(dev), P.Bt, P.ws)
     torch.cuda.synchronize()
-    Aq = orc.to_bf16_bits(A32)
-    Bq = orc.to_bf16_bits(B32)
-    assert np.array_equal(P.A.cpu().view(torch.int16).numpy().view(np.uint16), Aq)
-    assert np.array_equal(P.Bt.cpu().view(torch.int16).numpy().view(np.uint16), np.ascontiguousarray(Bq.T))
-    A = orc.bf16_bits_to_f64(Aq)
-    B = orc.bf16_bits_to_f64(Bq)
+    Aq, A, eA = oracle_quantize(orc, dt, A32)
+    Bq, B, eB = oracle_quantize(orc, dt, B32)
+    assert np.array_equal(stored_codes(P.A, dt), Aq)
+    assert np.array_equal(stored_codes(P.Bt, dt), np.ascontiguousarray(Bq.T))
     Af, Bf = orc.encode(A, B, br, bc, store_f32=True)
-    C64 = orc.gemm(Af, Bf)
+    sc = 2.0 ** -(eA + eB)
+    C64 = orc.gemm(Af, Bf) * sc
     tc, tr = orc.tau_stat(Af, Bf, m, n, br, bc, u_acc=U32, T=float(k), s_store=2.0, lam=LAMBDA)
-    return P, A, B, Af, Bf, C64.astype(np.float32), tc, tr
+    return P, A * 2.0 ** -eA, B * 2.0 ** -eB, Af * 2.0 ** -eA, Bf * 2.0 ** -eB, C64.astype(np.float32), tc * sc, tr * sc
 
 
 SHAPES = [
     (256, 256, 256, 1, 1),
     (512, 384, 1024, 1, 1),
-    (200, 136, 72, 8, 4),
+    (200, 136, 80, 8, 4),
     (512, 512, 512, 32, 32),
     (1024, 1024, 4096, 1, 1),
-    (300, 260, 520, 3, 5),
+    (300, 260, 528, 3, 5),
 ]
 
 
+@pytest.mark.parametrize("dt", ["bf16", "fp8"])
 @pytest.mark.parametrize("m,n,k,br,bc", SHAPES)
-def test_bf16_product_and_clean_verify(dev, orc, m, n, k, br, bc):
-    note(f"bf16 m={m} n={n} k={k} br={br} bc={bc}")
-    P, A, B, Af, Bf, C32, tc, tr = make(dev, orc, m, n, k, br, bc)
+def test_lowp_product_and_clean_verify(dev, orc, m, n, k, br, bc, dt):
+    note(f"{dt} m={m} n={n} k={k} br={br} bc={bc}")
+    P, A, B, Af, Bf, C32, tc, tr = make(dev, orc, m, n, k, br, bc, dt)
     P.encode()
     P.gemm()
     torch.cuda.synchronize()
@@ -81,15 +100,16 @@ def test_bf16_product_and_clean_verify(dev, orc, m, n, k, br, bc):
          f"max rel err {np.abs(Cg - C32).max() / np.abs(C32).max():.2e}")
     # plain product = data part, bit for bit (same kernel, same k order)
     Cp = torch.zeros(m, n, dtype=torch.float32, device=dev)
-    p2 = abft.problem(abft.ABFT_BF16, m, n, k, br, bc, ldc=n, tau_mode=abft.ABFT_TAU_STAT)
-    abft.gemm(p2, P.A, P.Bt, Cp, flags=abft.ABFT_PLAIN)
+    p2 = abft.problem(DTYPES[dt], m, n, k, br, bc, ldc=n, tau_mode=abft.ABFT_TAU_STAT)
+    abft.gemm(p2, P.A, P.Bt, Cp, P.ws, flags=abft.ABFT_PLAIN)
     torch.cuda.synchronize()
     assert torch.equal(Cp, P.C[:m, :n])
 
 
+@pytest.mark.parametrize("dt", ["bf16", "fp8"])
 @pytest.mark.parametrize("m,n,k,br,bc,runs", [(256, 256, 256, 1, 1, 60), (512, 512, 512, 32, 32, 40)])
-def test_bf16_flip_decisions_match_oracle(dev, orc, m, n, k, br, bc, runs):
-    P, A, B, Af, Bf, C32, tc, tr = make(dev, orc, m, n, k, br, bc)
+def test_lowp_flip_decisions_match_oracle(dev, orc, m, n, k, br, bc, runs, dt):
+    P, A, B, Af, Bf, C32, tc, tr = make(dev, orc, m, n, k, br, bc, dt)
     P.encode()
     P.gemm()
     clean = P.C.clone()
@@ -97,7 +117,7 @@ def test_bf16_flip_decisions_match_oracle(dev, orc, m, n, k, br, bc, runs):
     located = compared = 0
     for run in range(runs):
         i, j, bit = synth.flip_site(SEED + 9, run, M, N, 11, 30)
-        note(f"bf16 flip run={run} ({i},{j}) bit {bit}")
+        note(f"{dt} flip run={run} ({i},{j}) bit {bit}")
         P.C.copy_(clean)
         abft.inject_flip(P.p, P.C, i, j, bit)
         rep = P.verify()
@@ -123,16 +143,17 @@ def test_bf16_flip_decisions_match_oracle(dev, orc, m, n, k, br, bc, runs):
     assert compared >= runs * 0.8 and located >= compared * 0.4
 
 
-def test_bf16_erasure_rebuild(dev, orc):
+@pytest.mark.parametrize("dt", ["bf16", "fp8"])
+def test_lowp_erasure_rebuild(dev, orc, dt):
     m = n = 512
     k, b = 256, 32
-    P, A, B, Af, Bf, C32, tc, tr = make(dev, orc, m, n, k, b, b)
+    P, A, B, Af, Bf, C32, tc, tr = make(dev, orc, m, n, k, b, b, dt)
     P.encode()
     P.gemm()
     clean = P.C.clone()
     for rect in [(64, 128, 32, 32), (512, 0, 32, 32), (5, 3, 20, 30), (64, 512, 32, 32)]:
         for use_rows in (False, True):
-            note(f"bf16 erase {rect} rows={use_rows}")
+            note(f"{dt} erase {rect} rows={use_rows}")
             P.C.copy_(clean)
             abft.inject_erase(P.p, P.C, rect, nan_fill=True)
             rep = P.verify(known=[rect])
