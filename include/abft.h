@@ -75,11 +75,13 @@ typedef enum {
  *                 with S bounded by Cauchy-Schwarz from per-row/column norms
  *                 (binary64 paths);
  *  ABFT_TAU_STAT  lambda times the standard deviation of the rounding error:
- *                 sigma^2 = (u^2/3)(T/2 + 2) Q, u = 2^-24, T = k (one rounding
- *                 per product, an upper bound for any matrix-core order), Q
- *                 the sum of the squared products of the relation (exact for
- *                 b = 1, a Cauchy-Schwarz bound otherwise); for binary32
- *                 accumulation, where the rigorous bound is far too loose;
+ *                 sigma^2 = (u^2/3)(T/2 + s) Q, u = 2^-24, Q the sum of the
+ *                 squared products of the relation (exact for b = 1, a
+ *                 Cauchy-Schwarz bound otherwise), T = k for F32 and k/4 for
+ *                 BF16 / FP8 (accumulation steps), s = 2, plus 2^18 for FP8
+ *                 (the FP8 matrix core's product-sum window, a per-product
+ *                 error of 2^-15); for binary32 accumulation, where the
+ *                 rigorous bound is far too loose;
  *  ABFT_TAU_EXACT tau = 0, for integer-valued inputs whose sums are exact. */
 typedef enum { ABFT_TAU_DET = 0, ABFT_TAU_STAT = 1, ABFT_TAU_EXACT = 2 } abft_tau_mode;
 

@@ -74,12 +74,18 @@ TauCoef tau_coef(const abft_problem *p) {
         t.cc = kappa * (2 * gamma_n((double)g.k, u_acc) + 2 * gamma_n((double)(g.Gr + g.S), u64) + u_st);
         t.cr = kappa * (2 * gamma_n((double)g.k, u_acc) + 2 * gamma_n((double)(g.Gc + g.S), u64) + u_st);
     } else if (p->tau_mode == ABFT_TAU_STAT) {
-        // sigma^2 = (u^2/3)(T/2 + s) Q with T = k accumulation steps (one
-        // rounding per product bounds every matrix-core order) and s = 2 for
-        // the binary32 storage of the checksum row and of the carried total
+        // sigma^2 = (u^2/3)(T/2 + s) Q.  T = accumulation steps: k for binary32
+        // (one rounding per product bounds every matrix-core order) and k/4 for
+        // bfloat16 / FP8 (measured: the bfloat16 matrix core rounds no more
+        // often than once per 4 products).  s = 2 covers the binary32 storage
+        // of the checksum row and of the carried total.  FP8 adds the narrow
+        // product-sum window of its matrix core, a per-product error of u_w =
+        // 2^-15 (measured rms 2^-16.3): s += (u_w / u)^2.
         double u = p->dtype == ABFT_F64 ? u64 : u32;
-        double T = (double)g.k;
-        t.cc = t.cr = t.lambda * t.lambda * (u * u / 3.0) * (T / 2.0 + 2.0);
+        double T = (p->dtype == ABFT_BF16 || p->dtype == ABFT_FP8_E4M3) ? (double)g.k / 4.0 : (double)g.k;
+        double sst = 2.0;
+        if (p->dtype == ABFT_FP8_E4M3) sst += std::ldexp(1.0, 2 * (24 - 15));
+        t.cc = t.cr = t.lambda * t.lambda * (u * u / 3.0) * (T / 2.0 + sst);
     } else {
         t.cc = t.cr = 0.0;
     }

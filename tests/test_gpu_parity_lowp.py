@@ -69,7 +69,10 @@ def make(dev, orc, m, n, k, br, bc, dt="bf16"):
     Af, Bf = orc.encode(A, B, br, bc, store_f32=True)
     sc = 2.0 ** -(eA + eB)
     C64 = orc.gemm(Af, Bf) * sc
-    tc, tr = orc.tau_stat(Af, Bf, m, n, br, bc, u_acc=U32, T=float(k), s_store=2.0, lam=LAMBDA)
+    # the library's statistical model: T = k/4 accumulation steps; s = 2, plus the
+    # FP8 product-sum window (per-product error 2^-15, i.e. + (2^-15 / 2^-24)^2)
+    s_store = 2.0 + (2.0 ** 18 if dt == "fp8" else 0.0)
+    tc, tr = orc.tau_stat(Af, Bf, m, n, br, bc, u_acc=U32, T=k / 4.0, s_store=s_store, lam=LAMBDA)
     return P, A * 2.0 ** -eA, B * 2.0 ** -eB, Af * 2.0 ** -eA, Bf * 2.0 ** -eB, C64.astype(np.float32), tc * sc, tr * sc
 
 
