@@ -12,7 +12,7 @@ per launch with events on the launch stream (the roofline object), the plain
 product of the same kernel gives the ABFT overhead, and the CPU oracle is
 timed on a bounded sample of the same product (rank 0, N = 1 only).
 
-    python bench.py [--steps K] [--warmup W] [--workload c2|c2b1|c1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload c2|c2b1|c1|c1b64|c3|c4|c4fp8] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "protected-GEMM TFLOP/s and % MFMA peak; ABFT overhead vs plain GEMM"
-PEAK = {"f64": 78.6, "f32": 157.3}  # TFLOP/s, MI355X dense matrix-core peaks
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6, "fp8": 5033.2}  # TFLOP/s, MI355X dense matrix-core peaks
 WORKLOADS = {
     # name: (dtype, m, n, k, b, erase)
     "c2": ("f64", 8192, 8192, 8192, 1024, True),
@@ -34,11 +34,13 @@ WORKLOADS = {
     "c1": ("f64", 256, 256, 256, 1, False),
     "c1b64": ("f64", 256, 256, 256, 64, True),
     "c3": ("f32", 16384, 8192, 32768, 1, False),
+    "c4": ("bf16", 16384, 16384, 16384, 1, False),
+    "c4fp8": ("fp8", 16384, 16384, 16384, 1, False),
 }
 # flip bits per C type: binary64 40..62; binary32 24..29 (exponent bits and the
 # top fraction bit: always above the statistical threshold, so every step's
 # flip is located)
-FLIP_BITS = {"f64": (40, 62), "f32": (24, 29)}
+FLIP_BITS = {"f64": (40, 62), "f32": (24, 29), "bf16": (24, 29), "fp8": (24, 29)}
 SEED = 20080523
 
 
@@ -56,9 +58,19 @@ def cpu_baseline(dt_name, m, n, k, b, target_s=12.0):
     from paper_0806_3121_amd import synth
 
     ndt = np.float64 if dt_name == "f64" else np.float32
-    B = synth.uniform(SEED, synth.STREAM_B, k, n, ndt).astype(np.float64)
+
+    def quant(X):
+        # the oracle's own quantizer (FP8: per-tensor scale of this sample)
+        if dt_name == "bf16":
+            return orc.bf16_bits_to_f64(orc.to_bf16_bits(X))
+        if dt_name == "fp8":
+            e = orc.e4m3_scale_exp(X)
+            return orc.e4m3_values(orc.to_e4m3_codes(X * np.float32(2.0 ** e))) * 2.0 ** -e
+        return X.astype(np.float64)
+
+    B = quant(synth.uniform(SEED, synth.STREAM_B, k, n, ndt))
     probe = 32
-    A0 = synth.uniform_rows(SEED, synth.STREAM_A, np.arange(probe), k, ndt).astype(np.float64)
+    A0 = quant(synth.uniform_rows(SEED, synth.STREAM_A, np.arange(probe), k, ndt).astype(ndt))
     Bf = np.zeros((k, n + b))
     Bf[:, :n] = B
     del B
@@ -67,8 +79,9 @@ def cpu_baseline(dt_name, m, n, k, b, target_s=12.0):
     orc.gemm(A0, Bf)
     t_probe = time.perf_counter() - t0
     rows = int(min(m, max(probe, probe * target_s / max(t_probe, 1e-3))))
-    A = synth.uniform_rows(SEED, synth.STREAM_A, np.arange(rows), k, ndt).astype(np.float64)
+    A = synth.uniform_rows(SEED, synth.STREAM_A, np.arange(rows), k, ndt).astype(ndt)
     t0 = time.perf_counter()
+    A = quant(A)
     orc.gemm(A, Bf)
     dt = time.perf_counter() - t0
     flops = 2.0 * rows * (n + b) * k
@@ -99,15 +112,23 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     dt_name, m, n, k, b, erase = WORKLOADS[args.workload]
-    adt = {"f64": abft.ABFT_F64, "f32": abft.ABFT_F32}[dt_name]
-    tdt = {"f64": torch.float64, "f32": torch.float32}[dt_name]
+    adt = {"f64": abft.ABFT_F64, "f32": abft.ABFT_F32, "bf16": abft.ABFT_BF16, "fp8": abft.ABFT_FP8_E4M3}[dt_name]
+    tdt = torch.float64 if dt_name == "f64" else torch.float32
+    lowp = dt_name in ("bf16", "fp8")
     bit_lo, bit_hi = FLIP_BITS[dt_name]
 
     log(f"workload {args.workload}: {dt_name} m={m} n={n} k={k} b={b}")
     P = abft.Protected(adt, m, n, k, b, b, device=dev)
-    abft.fill_uniform(adt, m, k, k, 0, SEED, synth.STREAM_A, P.A)
-    # B (k x n) stored column-major: the Bt tensor holds B^T row-major
-    abft.fill_uniform(adt, k, n, k, 1, SEED, synth.STREAM_B, P.Bt)
+    if lowp:
+        # binary32 inputs resident in HBM; each step quantizes them
+        A32 = torch.empty(m, k, dtype=torch.float32, device=dev)
+        Bt32 = torch.empty(n, k, dtype=torch.float32, device=dev)
+        abft.fill_uniform(abft.ABFT_F32, m, k, k, 0, SEED, synth.STREAM_A, A32)
+        abft.fill_uniform(abft.ABFT_F32, k, n, k, 1, SEED, synth.STREAM_B, Bt32)
+    else:
+        abft.fill_uniform(adt, m, k, k, 0, SEED, synth.STREAM_A, P.A)
+        # B (k x n) stored column-major: the Bt tensor holds B^T row-major
+        abft.fill_uniform(adt, k, n, k, 1, SEED, synth.STREAM_B, P.Bt)
     Cplain = torch.empty(m, n, dtype=tdt, device=dev)
     pplain = abft.problem(adt, m, n, k, b, b, ldc=n)
     torch.cuda.synchronize()
@@ -115,6 +136,9 @@ def main():
     g_events = []
 
     def step(s):
+        if lowp:
+            abft.quantize(P.p, 0, A32, P.A, P.ws)
+            abft.quantize(P.p, 1, Bt32, P.Bt, P.ws)
         P.encode()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -160,7 +184,7 @@ def main():
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        abft.gemm(pplain, P.A, P.Bt, Cplain, flags=abft.ABFT_PLAIN)
+        abft.gemm(pplain, P.A, P.Bt, Cplain, P.ws, flags=abft.ABFT_PLAIN)
         e1.record(stream)
         pe.append((e0, e1))
     torch.cuda.synchronize()
@@ -191,7 +215,8 @@ def main():
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": None,
-                     "kernel": "k_gemm_mfma (+ k_sliver for b <= 8)", "flops_per_launch": executed,
+                     "kernel": ("k_gemm_lowp" if lowp else "k_gemm_mfma") + " + k_sliver (thin checksum blocks)",
+                     "flops_per_launch": executed,
                      "avg_launch_ms": round(gemm_ms, 4)},
         "pct_mfma_peak_useful": round(100 * value / peak, 2),
         "gemm_protected_ms": round(gemm_ms, 4),
