@@ -75,12 +75,35 @@ __global__ __launch_bounds__(kSliverThreads) void k_sliver(const TX *__restrict_
     const int lane = threadIdx.x % 64;
     const int64_t wave = ((int64_t)blockIdx.x * kSliverThreads + threadIdx.x) / 64;
     const int64_t nwaves = (int64_t)gridDim.x * kSliverThreads / 64;
+    constexpr int UNR = 4;                           // 16-byte loads in flight per lane and operand row
     for (int64_t u = wave; u < U; u += nwaves) {
         double acc[kSliverR];
 #pragma unroll
         for (int s = 0; s < kSliverR; ++s) acc[s] = 0.0;
         const TX *xr = X + u * ldx;
-        for (int64_t k0 = (int64_t)lane * V; k0 < K; k0 += 64 * V) {
+        int64_t k0 = (int64_t)lane * V;
+        for (; k0 + (UNR - 1) * 64 * V < K; k0 += UNR * 64 * V) {
+            double xv[UNR][V];
+#pragma unroll
+            for (int w = 0; w < UNR; ++w)
+#pragma unroll
+                for (int q = 0; q < V; q += VX) vec16<TX>::load(xr + k0 + w * 64 * V + q, xv[w] + q);
+#pragma unroll
+            for (int s = 0; s < kSliverR; ++s) {
+                if (s < R) {
+                    double yv[UNR][V];
+#pragma unroll
+                    for (int w = 0; w < UNR; ++w)
+#pragma unroll
+                        for (int q = 0; q < V; q += VY) vec16<TY>::load(Y + s * ldy + k0 + w * 64 * V + q, yv[w] + q);
+#pragma unroll
+                    for (int w = 0; w < UNR; ++w)
+#pragma unroll
+                        for (int q = 0; q < V; ++q) acc[s] = fma(xv[w][q], yv[w][q], acc[s]);
+                }
+            }
+        }
+        for (; k0 < K; k0 += 64 * V) {
             double xv[V];
 #pragma unroll
             for (int q = 0; q < V; q += VX) vec16<TX>::load(xr + k0 + q, xv + q);
