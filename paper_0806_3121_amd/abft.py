@@ -214,12 +214,16 @@ class Protected:
         tdt = {ABFT_F64: torch.float64, ABFT_F32: torch.float32, ABFT_BF16: torch.bfloat16,
                ABFT_FP8_E4M3: torch.uint8}[dtype]
         cdt = torch.float64 if dtype == ABFT_F64 else torch.float32
-        self.p = problem(dtype, m, n, k, br, bc, tau_mode=tau_mode, lam=lam)
         self.M, self.N = m + br, n + bc
+        # rows of C_f padded to 16 bytes so the verification passes use 16-byte loads
+        vec = 16 // (8 if dtype == ABFT_F64 else 4)
+        self.ldc = (self.N + vec - 1) // vec * vec
+        self.p = problem(dtype, m, n, k, br, bc, ldc=self.ldc, tau_mode=tau_mode, lam=lam)
         lowp = dtype in (ABFT_BF16, ABFT_FP8_E4M3)      # checksum rows kept in the workspace
         self.A = torch.zeros(m if lowp else self.M, k, dtype=tdt, device=device)
         self.Bt = torch.zeros(n if lowp else self.N, k, dtype=tdt, device=device)
-        self.C = torch.zeros(self.M, self.N, dtype=cdt, device=device)
+        self.Cbuf = torch.zeros(self.M, self.ldc, dtype=cdt, device=device)
+        self.C = self.Cbuf[:, :self.N]          # view; the library sees ldc = self.ldc
         self.ws = torch.zeros(workspace_size(self.p), dtype=torch.uint8, device=device)
         self.rep_host = new_report_buffer()
 

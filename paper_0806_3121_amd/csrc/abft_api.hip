@@ -43,10 +43,13 @@ WsLayout ws_layout(const abft_problem *p) {
     L.acs = take(cs_in_ws(p->dtype) ? sizeof(float) * g.br * g.k : 8);
     L.bcs = take(cs_in_ws(p->dtype) ? sizeof(float) * g.bc * g.k : 8);
     L.scale = take(16);
-    // partial sums: encode A (2 stats), encode B (2 stats), verify columns (1)
-    int64_t pa = group_partitions(g.Gr, g.br, g.k);
-    int64_t pb = group_partitions(g.Gc, g.bc, g.k);
-    int64_t pc = group_partitions(g.Gr, g.br, g.N);
+    // partial sums: encode A (2 stats), encode B (2 stats), verify columns (1);
+    // encode threads own 16 bytes of a row each
+    int64_t vpe = 16 / (int64_t)dtype_size(p->dtype);
+    int64_t pa = group_partitions(g.Gr, g.br, g.k / vpe);
+    int64_t pb = group_partitions(g.Gc, g.bc, g.k / vpe);
+    int64_t pc = std::max(group_partitions(g.Gr, g.br, g.N), group_partitions(g.Gr, g.br, (g.N + 1) / 2));
+    pc = std::max(pc, group_partitions(g.Gr, g.br, (g.N + 3) / 4));
     size_t need = 0;
     if (pa > 1) need = std::max(need, (size_t)(pa * g.br * g.k * 2));
     if (pb > 1) need = std::max(need, (size_t)(pb * g.bc * g.k * 2));

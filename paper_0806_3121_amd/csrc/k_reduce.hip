@@ -76,81 +76,98 @@ __global__ void k_report_init(abft_report *rep) {
 // and the per-residue statistic grp[r, l] of the threshold:
 //   det:  sum_g |X[g*b + r, l]|               (row r of C_C^T |X|)
 //   stat: sum_g X[g*b + r, l]^2 + CS[r, l]^2  (the squares of every member of the relation)
-template <typename T, typename TC> __device__ inline void finish_encode(double s, double ss, bool stat, TC *cs, double *grp) {
-    TC c = (TC)s;
+template <typename TC> __device__ inline void finish_encode(double sv, double ssv, bool stat, TC *cs, double *grp) {
+    TC c = (TC)sv;
     *cs = c;
-    *grp = stat ? ss + (double)c * (double)c : ss;
+    *grp = stat ? ssv + (double)c * (double)c : ssv;
 }
 
+// Each thread owns V = 16/sizeof(T) consecutive columns l (one 16-byte load per
+// row); rows of X are 16-byte aligned and k is a multiple of V.
 template <typename T, typename TC>
 __global__ __launch_bounds__(kThreads) void k_encode_direct(const T *X, int64_t ld, int64_t b, int64_t G, int64_t k,
                                                             TC *CS, int64_t ldcs, bool stat, double *grp) {
-    const int64_t total = b * k;
+    constexpr int V = vec16<T>::N;
+    const int64_t kv = k / V, total = b * kv;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
-        int64_t r = t / k, l = t - r * k;
-        double s = 0.0, ss = 0.0;
-        const T *p = X + r * ld + l;
+        int64_t r = t / kv, l0 = (t - r * kv) * V;
+        double s[V], ss[V], v[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) s[q] = ss[q] = 0.0;
+        const T *p = X + r * ld + l0;
         for (int64_t g = 0; g < G; ++g) {
-            double v = elem<T>::load(p + g * b * ld);
-            s += v;
-            ss += stat ? v * v : fabs(v);
+            vec16<T>::load(p + g * b * ld, v);
+#pragma unroll
+            for (int q = 0; q < V; ++q) { s[q] += v[q]; ss[q] += stat ? v[q] * v[q] : fabs(v[q]); }
         }
-        finish_encode<T, TC>(s, ss, stat, CS + r * ldcs + l, grp + t);
+#pragma unroll
+        for (int q = 0; q < V; ++q) finish_encode<TC>(s[q], ss[q], stat, CS + r * ldcs + l0 + q, grp + r * k + l0 + q);
     }
 }
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_encode_partial(const T *X, int64_t ld, int64_t b, int64_t G, int64_t k,
                                                              int64_t P, int64_t chunk, bool stat, double *part) {
-    const int64_t rel = b * k, total = P * rel;
+    constexpr int V = vec16<T>::N;
+    const int64_t kv = k / V, rel = b * k, total = P * b * kv;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
-        int64_t p = t / rel, q = t - p * rel;
-        int64_t r = q / k, l = q - r * k;
+        int64_t p = t / (b * kv), q = t - p * (b * kv);
+        int64_t r = q / kv, l0 = (q - r * kv) * V;
         int64_t g0 = p * chunk, g1 = min(G, g0 + chunk);
-        double s = 0.0, ss = 0.0;
-        const T *src = X + r * ld + l;
+        double s[V], ss[V], v[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) s[e] = ss[e] = 0.0;
+        const T *src = X + r * ld + l0;
         for (int64_t g = g0; g < g1; ++g) {
-            double v = elem<T>::load(src + g * b * ld);
-            s += v;
-            ss += stat ? v * v : fabs(v);
+            vec16<T>::load(src + g * b * ld, v);
+#pragma unroll
+            for (int e = 0; e < V; ++e) { s[e] += v[e]; ss[e] += stat ? v[e] * v[e] : fabs(v[e]); }
         }
-        part[(2 * p) * rel + q] = s;
-        part[(2 * p + 1) * rel + q] = ss;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            part[(2 * p) * rel + r * k + l0 + e] = s[e];
+            part[(2 * p + 1) * rel + r * k + l0 + e] = ss[e];
+        }
     }
 }
 
-template <typename T, typename TC>
+template <typename TC>
 __global__ __launch_bounds__(kThreads) void k_encode_finish(int64_t b, int64_t k, TC *CS, int64_t ldcs, bool stat,
                                                             int64_t P, const double *part, double *grp) {
     const int64_t rel = b * k;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < rel; t += (int64_t)gridDim.x * kThreads) {
         int64_t r = t / k, l = t - r * k;
-        double s = 0.0, ss = 0.0;
+        double sv = 0.0, ssv = 0.0;
         for (int64_t p = 0; p < P; ++p) {
-            s += part[(2 * p) * rel + t];
-            ss += part[(2 * p + 1) * rel + t];
+            sv += part[(2 * p) * rel + t];
+            ssv += part[(2 * p + 1) * rel + t];
         }
-        finish_encode<T, TC>(s, ss, stat, CS + r * ldcs + l, grp + t);
+        finish_encode<TC>(sv, ssv, stat, CS + r * ldcs + l, grp + t);
     }
 }
 
-// Per-row statistic of X[i, 0:k), one block per row (grid-stride over rows):
+// Per-row statistic of X[i, 0:k), one block per row (grid-stride over rows),
+// 16-byte loads:
 //   ROW_L2:  ||x||_2              ROW_W: sum_l x_l^2 w_l          ROW_L4SQ: ||x||_4^2
 enum { ROW_L2 = 0, ROW_W = 1, ROW_L4SQ = 2 };
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_row_stats(const T *X, int64_t ld, int64_t rows, int64_t k, int mode,
                                                         const double *w, double *out) {
+    constexpr int V = vec16<T>::N;
     __shared__ double sh[kThreads / kWave];
     for (int64_t i = blockIdx.x; i < rows; i += gridDim.x) {
         const T *row = X + i * ld;
-        double s = 0.0;
-        for (int64_t l = threadIdx.x; l < k; l += kThreads) {
-            double v = elem<T>::load(row + l);
-            double v2 = v * v;
-            s += mode == ROW_W ? v2 * w[l] : (mode == ROW_L4SQ ? v2 * v2 : v2);
+        double acc = 0.0, v[V];
+        for (int64_t l0 = (int64_t)threadIdx.x * V; l0 < k; l0 += (int64_t)kThreads * V) {
+            vec16<T>::load(row + l0, v);
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                double v2 = v[q] * v[q];
+                acc += mode == ROW_W ? v2 * w[l0 + q] : (mode == ROW_L4SQ ? v2 * v2 : v2);
+            }
         }
-        s = wave_sum(s);
-        if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = s;
+        acc = wave_sum(acc);
+        if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = acc;
         __syncthreads();
         if (threadIdx.x == 0) {
             double t = 0.0;
@@ -168,15 +185,16 @@ static unsigned rows_grid(int64_t rows) { return (unsigned)std::min<int64_t>(std
 template <typename T, typename TC>
 static void encode_pass1(const T *X, int64_t ld, int64_t R, int64_t b, int64_t k, TC *CS, int64_t ldcs, bool stat,
                          double *grp, double *part, hipStream_t s) {
+    constexpr int V = vec16<T>::N;
     int64_t G = R / b;
-    int64_t P = group_partitions(G, b, k);
+    int64_t P = group_partitions(G, b, k / V);
     if (P == 1) {
-        k_encode_direct<T, TC><<<grid_for(b * k), kThreads, 0, s>>>(X, ld, b, G, k, CS, ldcs, stat, grp);
+        k_encode_direct<T, TC><<<grid_for(b * k / V), kThreads, 0, s>>>(X, ld, b, G, k, CS, ldcs, stat, grp);
     } else {
         int64_t chunk = (G + P - 1) / P;
         P = (G + chunk - 1) / chunk;
-        k_encode_partial<T><<<grid_for(P * b * k), kThreads, 0, s>>>(X, ld, b, G, k, P, chunk, stat, part);
-        k_encode_finish<T, TC><<<grid_for(b * k), kThreads, 0, s>>>(b, k, CS, ldcs, stat, P, part, grp);
+        k_encode_partial<T><<<grid_for(P * b * k / V), kThreads, 0, s>>>(X, ld, b, G, k, P, chunk, stat, part);
+        k_encode_finish<TC><<<grid_for(b * k), kThreads, 0, s>>>(b, k, CS, ldcs, stat, P, part, grp);
     }
 }
 
@@ -370,32 +388,58 @@ __device__ inline void finish_col(const VerifyArgs &a, const T *C, int64_t r, in
     ratio = fmax(ratio, record(a.rep, true, r, j, s - tot, tau_col(a, r, j)));
 }
 
-template <typename T>
+// V consecutive elements of a C row: one 16-byte load (V > 1, aligned rows) or one element.
+template <typename T, int V> __device__ inline void load_c(const T *p, double *v) {
+    if constexpr (V == 1) v[0] = elem<T>::load(p);
+    else vec16<T>::load(p, v);
+}
+
+// Column relations, one thread per residue r and V consecutive columns.  With
+// V > 1 the rows of C are 16-byte aligned and ldc is a multiple of V, so the
+// last vector of a row stays inside the row's ldc elements; columns >= N are
+// read but not used.
+template <typename T, int V>
 __global__ __launch_bounds__(kThreads) void k_vcol_direct(const T *C, VerifyArgs a) {
-    const int64_t total = a.br * a.N;
+    const int64_t nv = (a.N + V - 1) / V, total = a.br * nv;
     double ratio = 0.0;
     unsigned long long excl = 0;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
-        int64_t r = t / a.N, j = t - r * a.N;
-        const T *p = C + r * a.ldc + j;
-        double s = 0.0;
-        for (int64_t g = 0; g < a.Gr; ++g) s += elem<T>::load(p + g * a.br * a.ldc);
-        finish_col<T>(a, C, r, j, s, ratio, excl);
+        int64_t r = t / nv, j0 = (t - r * nv) * V;
+        const T *p = C + r * a.ldc + j0;
+        double s[V], v[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) s[q] = 0.0;
+        for (int64_t g = 0; g < a.Gr; ++g) {
+            load_c<T, V>(p + g * a.br * a.ldc, v);
+#pragma unroll
+            for (int q = 0; q < V; ++q) s[q] += v[q];
+        }
+#pragma unroll
+        for (int q = 0; q < V; ++q)
+            if (j0 + q < a.N) finish_col<T>(a, C, r, j0 + q, s[q], ratio, excl);
     }
     fold_block(ratio, excl, &a.rep->max_ratio_c, &a.rep->n_excl_c);
 }
 
-template <typename T>
+template <typename T, int V>
 __global__ __launch_bounds__(kThreads) void k_vcol_partial(const T *C, VerifyArgs a, int64_t P, int64_t chunk, double *part) {
-    const int64_t rel = a.br * a.N, total = P * rel;
+    const int64_t nv = (a.N + V - 1) / V, rel = a.br * a.N, total = P * a.br * nv;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
-        int64_t p = t / rel, q = t - p * rel;
-        int64_t r = q / a.N, j = q - r * a.N;
+        int64_t p = t / (a.br * nv), q = t - p * (a.br * nv);
+        int64_t r = q / nv, j0 = (q - r * nv) * V;
         int64_t g0 = p * chunk, g1 = min(a.Gr, g0 + chunk);
-        const T *src = C + r * a.ldc + j;
-        double s = 0.0;
-        for (int64_t g = g0; g < g1; ++g) s += elem<T>::load(src + g * a.br * a.ldc);
-        part[t] = s;
+        const T *src = C + r * a.ldc + j0;
+        double s[V], v[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) s[e] = 0.0;
+        for (int64_t g = g0; g < g1; ++g) {
+            load_c<T, V>(src + g * a.br * a.ldc, v);
+#pragma unroll
+            for (int e = 0; e < V; ++e) s[e] += v[e];
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            if (j0 + e < a.N) part[p * rel + r * a.N + j0 + e] = s[e];
     }
 }
 
@@ -441,25 +485,36 @@ __global__ __launch_bounds__(kThreads) void k_vrow_strided(const T *C, VerifyArg
 
 // One block per row for bc dividing 256: thread t sums the columns j = t mod 256,
 // all of residue t mod bc; a fixed-order tree then combines the 256/bc partial
-// sums of each residue.
-template <typename T>
+// sums of each residue.  With V > 1 (bc == 1 and 16-byte aligned rows) thread t
+// sums whole vectors t, t + 256, ... of the row.
+template <typename T, int V>
 __global__ __launch_bounds__(kThreads) void k_vrow_block(const T *C, VerifyArgs a) {
     __shared__ double sh[kThreads];
     double ratio = 0.0;
     unsigned long long excl = 0;
     for (int64_t i = blockIdx.x; i < a.M; i += gridDim.x) {
         const T *row = C + i * a.ldc;
-        double s0 = 0.0, s1 = 0.0;
-        int64_t j = threadIdx.x;
-        for (; j + kThreads < a.n; j += 2 * kThreads) {
-            s0 += elem<T>::load(row + j);
-            s1 += elem<T>::load(row + j + kThreads);
+        double s0 = 0.0, s1 = 0.0, v[V], w[V];
+        int64_t j = (int64_t)threadIdx.x * V;
+        for (; j + kThreads * V < a.n; j += 2 * kThreads * V) {
+            load_c<T, V>(row + j, v);
+            load_c<T, V>(row + j + kThreads * V, w);
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                if (j + q < a.n) s0 += v[q];
+                if (j + kThreads * V + q < a.n) s1 += w[q];
+            }
         }
-        if (j < a.n) s0 += elem<T>::load(row + j);
+        if (j < a.n) {
+            load_c<T, V>(row + j, v);
+#pragma unroll
+            for (int q = 0; q < V; ++q)
+                if (j + q < a.n) s0 += v[q];
+        }
         sh[threadIdx.x] = s0 + s1;
         __syncthreads();
-        for (int w = kThreads / 2; w >= a.bc; w >>= 1) {
-            if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        for (int wd = kThreads / 2; wd >= a.bc; wd >>= 1) {
+            if (threadIdx.x < wd) sh[threadIdx.x] += sh[threadIdx.x + wd];
             __syncthreads();
         }
         if (threadIdx.x < a.bc) finish_row<T>(a, C, i, threadIdx.x, sh[threadIdx.x], ratio, excl);
@@ -486,18 +541,26 @@ static int verify_typed(const abft_problem *p, const T *C, const Erasures &er, c
     a.er = er;
     k_report_init<<<1, kThreads, 0, s>>>(a.rep);
     auto blocks = [](int64_t work) { return (unsigned)std::min<int64_t>((work + kThreads - 1) / kThreads, 4096); };
-    int64_t P = group_partitions(g.Gr, g.br, g.N);
+    // 16-byte loads when every row of C starts on a 16-byte boundary
+    constexpr int VV = 16 / (int)sizeof(T);
+    const bool vec = ((uintptr_t)C % 16 == 0) && (p->ldc % VV == 0);
+    const int64_t V = vec ? VV : 1;
+    int64_t P = group_partitions(g.Gr, g.br, (g.N + V - 1) / V);
     if (P == 1) {
-        k_vcol_direct<T><<<blocks(g.br * g.N), kThreads, 0, s>>>(C, a);
+        if (vec) k_vcol_direct<T, VV><<<blocks(g.br * ((g.N + VV - 1) / VV)), kThreads, 0, s>>>(C, a);
+        else k_vcol_direct<T, 1><<<blocks(g.br * g.N), kThreads, 0, s>>>(C, a);
     } else {
         int64_t chunk = (g.Gr + P - 1) / P;
         P = (g.Gr + chunk - 1) / chunk;
         double *part = (double *)(ws + L.partial);
-        k_vcol_partial<T><<<blocks(P * g.br * g.N), kThreads, 0, s>>>(C, a, P, chunk, part);
+        if (vec) k_vcol_partial<T, VV><<<blocks(P * g.br * ((g.N + VV - 1) / VV)), kThreads, 0, s>>>(C, a, P, chunk, part);
+        else k_vcol_partial<T, 1><<<blocks(P * g.br * g.N), kThreads, 0, s>>>(C, a, P, chunk, part);
         k_vcol_finish<T><<<blocks(g.br * g.N), kThreads, 0, s>>>(C, a, P, part);
     }
-    if (g.bc < 64 && (kThreads % g.bc) == 0)
-        k_vrow_block<T><<<(unsigned)std::min<int64_t>(g.M, 8192), kThreads, 0, s>>>(C, a);
+    if (g.bc == 1 && vec)
+        k_vrow_block<T, VV><<<(unsigned)std::min<int64_t>(g.M, 8192), kThreads, 0, s>>>(C, a);
+    else if (g.bc < 64 && (kThreads % g.bc) == 0)
+        k_vrow_block<T, 1><<<(unsigned)std::min<int64_t>(g.M, 8192), kThreads, 0, s>>>(C, a);
     else
         k_vrow_strided<T><<<blocks(g.M * g.bc), kThreads, 0, s>>>(C, a);
     ABFT_LAUNCHED();

@@ -16,46 +16,6 @@ namespace abft {
 constexpr int kSliverThreads = 256;
 constexpr int kSliverR = 8;   // few rows per pass
 
-typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
-template <typename T> struct vec16;                  // one 16-byte load, widened to double
-template <> struct vec16<double> {
-    static constexpr int N = 2;
-    __device__ static void load(const double *p, double *o) {
-        typedef double v2 __attribute__((ext_vector_type(2)));
-        v2 v = *(const v2 *)p;
-        o[0] = v[0]; o[1] = v[1];
-    }
-};
-template <> struct vec16<float> {
-    static constexpr int N = 4;
-    __device__ static void load(const float *p, double *o) {
-        typedef float v4 __attribute__((ext_vector_type(4)));
-        v4 v = *(const v4 *)p;
-        o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
-    }
-};
-template <> struct vec16<uint16_t> {                 // bfloat16
-    static constexpr int N = 8;
-    __device__ static void load(const uint16_t *p, double *o) {
-        typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-        v4u v = *(const v4u *)p;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            o[2 * q] = (double)bf16_to_f32((uint16_t)(v[q] & 0xFFFFu));
-            o[2 * q + 1] = (double)bf16_to_f32((uint16_t)(v[q] >> 16));
-        }
-    }
-};
-
-template <> struct vec16<uint8_t> {                  // FP8 E4M3
-    static constexpr int N = 16;
-    __device__ static void load(const uint8_t *p, double *o) {
-        v4u32 v = *(const v4u32 *)p;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) o[q] = (double)e4m3_to_f32((uint8_t)(v[q / 4] >> (8 * (q % 4))));
-    }
-};
-
 template <typename T> __device__ inline void store_out(T *p, double v);
 template <> __device__ inline void store_out<double>(double *p, double v) { *p = v; }
 template <> __device__ inline void store_out<float>(float *p, double v) { *p = (float)v; }
