@@ -150,11 +150,18 @@ __global__ __launch_bounds__(kThreads) void k_encode_finish(int64_t b, int64_t k
 // 16-byte loads:
 //   ROW_L2:  ||x||_2              ROW_W: sum_l x_l^2 w_l          ROW_L4SQ: ||x||_4^2
 enum { ROW_L2 = 0, ROW_W = 1, ROW_L4SQ = 2 };
+constexpr int64_t kRowWMaxK = 16384;   // ROW_W keeps w (as binary32, 64 KB) in LDS up to this k
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_row_stats(const T *X, int64_t ld, int64_t rows, int64_t k, int mode,
                                                         const double *w, double *out) {
     constexpr int V = vec16<T>::N;
     __shared__ double sh[kThreads / kWave];
+    extern __shared__ float wsh[];                     // k floats when mode == ROW_W and k <= kRowWMaxK
+    const bool wlds = mode == ROW_W && k <= kRowWMaxK;
+    if (wlds) {
+        for (int64_t l = threadIdx.x; l < k; l += kThreads) wsh[l] = (float)w[l];
+        __syncthreads();
+    }
     for (int64_t i = blockIdx.x; i < rows; i += gridDim.x) {
         const T *row = X + i * ld;
         double acc = 0.0, v[V];
@@ -163,7 +170,8 @@ __global__ __launch_bounds__(kThreads) void k_row_stats(const T *X, int64_t ld, 
 #pragma unroll
             for (int q = 0; q < V; ++q) {
                 double v2 = v[q] * v[q];
-                acc += mode == ROW_W ? v2 * w[l0 + q] : (mode == ROW_L4SQ ? v2 * v2 : v2);
+                double wl = mode == ROW_W ? (wlds ? (double)wsh[l0 + q] : w[l0 + q]) : 0.0;
+                acc += mode == ROW_W ? v2 * wl : (mode == ROW_L4SQ ? v2 * v2 : v2);
             }
         }
         acc = wave_sum(acc);
@@ -176,6 +184,16 @@ __global__ __launch_bounds__(kThreads) void k_row_stats(const T *X, int64_t ld, 
         }
         __syncthreads();
     }
+}
+
+// Row statistics launch: with LDS-staged weights a block serves many rows.
+template <typename T>
+static void row_stats(const T *X, int64_t ld, int64_t rows, int64_t k, int mode, const double *w, double *out,
+                      hipStream_t s) {
+    if (rows <= 0) return;
+    size_t lds = (mode == ROW_W && k <= kRowWMaxK) ? sizeof(float) * (size_t)k : 0;
+    unsigned grid = (unsigned)std::min<int64_t>(rows, lds ? 1024 : 65536);
+    k_row_stats<T><<<grid, kThreads, lds, s>>>(X, ld, rows, k, mode, w, out);
 }
 
 static unsigned grid_for(int64_t work) { return (unsigned)std::min<int64_t>((work + kThreads - 1) / kThreads, 65536); }
@@ -205,8 +223,8 @@ template <typename T, typename TC>
 static void encode_pass2(const T *X, int64_t ld, int64_t R, const TC *CS, int64_t ldcs, int64_t b, int64_t k,
                          bool stat, int64_t b_other, const double *w_other, double *out, hipStream_t s) {
     int mode = !stat ? ROW_L2 : (b_other == 1 ? ROW_W : ROW_L4SQ);
-    k_row_stats<T><<<rows_grid(R), kThreads, 0, s>>>(X, ld, R, k, mode, w_other, out);
-    k_row_stats<TC><<<rows_grid(b), kThreads, 0, s>>>(CS, ldcs, b, k, mode, w_other, out + R);
+    row_stats<T>(X, ld, R, k, mode, w_other, out, s);
+    row_stats<TC>(CS, ldcs, b, k, mode, w_other, out + R, s);
 }
 
 template <typename T, typename TC>
@@ -225,8 +243,8 @@ static int encode_typed(const abft_problem *p, T *A, T *Bt, TC *Acs, int64_t lda
     encode_pass2<T, TC>(A, p->lda, g.m, Acs, ldacs, g.br, g.k, stat, g.bc, grpB, ra, s);
     encode_pass2<T, TC>(Bt, p->ldb, g.n, Bcs, ldbcs, g.bc, g.k, stat, g.br, grpA, rb, s);
     double *ga = (double *)(ws + (stat ? L.nv : L.na_abs)), *gb = (double *)(ws + (stat ? L.nw : L.nb_abs));
-    k_row_stats<double><<<rows_grid(g.br), kThreads, 0, s>>>(grpA, g.k, g.br, g.k, ROW_L2, nullptr, ga);
-    k_row_stats<double><<<rows_grid(g.bc), kThreads, 0, s>>>(grpB, g.k, g.bc, g.k, ROW_L2, nullptr, gb);
+    row_stats<double>(grpA, g.k, g.br, g.k, ROW_L2, nullptr, ga, s);
+    row_stats<double>(grpB, g.k, g.bc, g.k, ROW_L2, nullptr, gb, s);
     ABFT_LAUNCHED();
     return ABFT_OK;
 }
