@@ -1,0 +1,144 @@
+// Low-precision product, direct-to-LDS variant: 256 x 256 block, 2*WM waves
+// (WM = 4: eight waves of 64 x 128, two per SIMD; WM = 2: four waves of
+// 128 x 128).  Operand slabs of 128 bytes of k per row go global -> LDS
+// directly (global_load_lds_dwordx4: lane L of a wave writes 16 bytes at
+// base + 16 L; measured on gfx950), double-buffered, with no register staging
+// and no LDS write instructions.  An MFMA group takes CPM chunks per lane:
+// chunk kc = (4 g + lane / 16) CPM + c of the slab, identical for A and B.
+//
+// LDS layout per slab and operand: row r occupies 128 bytes = 8 chunks of 16
+// bytes; chunk kc of row r is stored at slot kc ^ ((r >> 1) & 7).  The 16 lanes
+// of a quarter-wave read chunk kc of 16 consecutive rows: (r & 1, slot) then
+// covers all 16 four-bank groups, so fragment reads are conflict-free.  The
+// swizzle is applied on the global side: lane L of a load instruction fetches
+// the chunk that belongs in slot L % 8 of row L / 8.
+//
+// Rows beyond M (columns beyond N) load a clamped valid row; they only feed
+// results that are not stored.  K must be a multiple of the slab (128 bytes);
+// other K use the padded-LDS kernel of gemm_lowp_kernel.h.
+#pragma once
+
+#include "gemm_lowp_kernel.h"
+
+namespace abft {
+
+template <class Ops, int WM = 2, int GROUP_M = 8>
+__global__ __launch_bounds__(128 * WM, 1) void k_gemm_lowp2(const typename Ops::E *__restrict__ A, int64_t lda,
+                                                       const typename Ops::E *__restrict__ Bt, int64_t ldb,
+                                                       float *__restrict__ C, int64_t ldc, int64_t M, int64_t N,
+                                                       int64_t K, const int *__restrict__ scale_exp) {
+    typedef typename Ops::E E;
+    constexpr int BM = 256, BN = 256;
+    constexpr int SLAB = 128;                          // bytes of k per row and slab
+    constexpr int BK = SLAB / (int)sizeof(E);          // elements of k per slab
+    constexpr int VEC = 16 / (int)sizeof(E);           // elements per 16-byte chunk
+    constexpr int STAGE = (BM + BN) * SLAB;            // 64 KB per slab of both operands
+    constexpr int HDR = 256;                           // keeps every LDS base address non-zero
+    __shared__ __attribute__((aligned(16))) uint8_t lds[HDR + 2 * STAGE];
+
+    const int64_t tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+    int64_t tm, tn;
+    tile_of<GROUP_M>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    const int64_t row0 = tm * BM, col0 = tn * BN;
+
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const int wm = wave / 2, wn = wave % 2;
+    constexpr int NW = 2 * WM;                         // waves per block
+    constexpr int LPW = 32 / NW;                       // load instructions per wave and operand
+    constexpr int TMW = 16 / WM;                       // 16-row MFMA tiles per wave along M (wave tile 256/WM x 128)
+
+    // global sources of this lane's A and B chunks per slab
+    const E *srcA[LPW], *srcB[LPW];
+#pragma unroll
+    for (int q = 0; q < LPW; ++q) {
+        int c = (wave * LPW + q) * 64 + lane;          // chunk index within the operand's slab
+        int r = c / 8, slot = c % 8;
+        int kc = slot ^ ((r >> 1) & 7);
+        int64_t ga = row0 + r < M ? row0 + r : M - 1;
+        int64_t gb = col0 + r < N ? col0 + r : N - 1;
+        srcA[q] = A + ga * lda + kc * VEC;
+        srcB[q] = Bt + gb * ldb + kc * VEC;
+    }
+    auto issue = [&](int buf, int64_t k0) {
+        uint8_t *base = lds + HDR + buf * STAGE + wave * LPW * 1024;
+#pragma unroll
+        for (int q = 0; q < LPW; ++q)
+            __builtin_amdgcn_global_load_lds((const void *)(srcA[q] + k0), (void *)(base + q * 1024), 16, 0, 0);
+#pragma unroll
+        for (int q = 0; q < LPW; ++q)
+            __builtin_amdgcn_global_load_lds((const void *)(srcB[q] + k0), (void *)(base + BM * SLAB + q * 1024), 16,
+                                             0, 0);
+    };
+
+    v4f acc[TMW][8];
+#pragma unroll
+    for (int a = 0; a < TMW; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    // fragment addresses: row r = wave-tile base + 16 a + lane % 16, chunk kc = 4 g + lane / 16
+    const int lr = lane % 16, lq = lane / 16;
+    const int arow = wm * (BM / WM) + lr, brow = wn * 128 + lr;
+
+    const int64_t nk = K / BK;
+    issue(0, 0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int buf = (int)(kt & 1);
+        if (kt + 1 < nk) issue(buf ^ 1, (kt + 1) * BK);
+        const uint8_t *As = lds + HDR + buf * STAGE;
+        const uint8_t *Bs = As + BM * SLAB;
+        constexpr int CPM = Ops::CPM;
+#pragma unroll
+        for (int g = 0; g < SLAB / (64 * CPM); ++g) {
+            v4u fa[TMW][CPM], fb[8][CPM];
+#pragma unroll
+            for (int c = 0; c < CPM; ++c) {
+                const int kc = (4 * g + lq) * CPM + c;
+#pragma unroll
+                for (int a = 0; a < TMW; ++a) {
+                    int r = arow + 16 * a;
+                    fa[a][c] = *(const v4u *)(As + r * SLAB + ((kc ^ ((r >> 1) & 7)) << 4));
+                }
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    int r = brow + 16 * b;
+                    fb[b][c] = *(const v4u *)(Bs + r * SLAB + ((kc ^ ((r >> 1) & 7)) << 4));
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < TMW; ++a)
+#pragma unroll
+                for (int b = 0; b < 8; ++b) Ops::mfma_chunks(fa[a], fb[b], acc[a][b]);
+        }
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // the next slab has landed in LDS
+        __syncthreads();
+    }
+
+    const float sc = scale_exp ? __builtin_ldexpf(1.0f, -(scale_exp[0] + scale_exp[1])) : 1.0f;
+    const int ccol = lane % 16;
+#pragma unroll
+    for (int a = 0; a < TMW; ++a) {
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            int64_t gc = col0 + wn * 128 + b * 16 + ccol;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int64_t gr = row0 + wm * (BM / WM) + a * 16 + 4 * (lane / 16) + v;
+                if (gr < M && gc < N) C[gr * ldc + gc] = acc[a][b][v] * sc;
+            }
+        }
+    }
+}
+
+template <class Ops, int WM = 2>
+inline int launch_gemm_lowp2(const typename Ops::E *A, int64_t lda, const typename Ops::E *Bt, int64_t ldb, float *C,
+                             int64_t ldc, int64_t M, int64_t N, int64_t K, const int *scale_exp, hipStream_t s) {
+    int64_t tiles = ((M + 255) / 256) * ((N + 255) / 256);
+    if (tiles > INT32_MAX) return ABFT_E_ARG;
+    k_gemm_lowp2<Ops, WM><<<(unsigned)tiles, 128 * WM, 0, s>>>(A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp);
+    return ABFT_OK;
+}
+
+}  // namespace abft

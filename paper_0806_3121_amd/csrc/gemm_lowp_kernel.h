@@ -26,24 +26,43 @@ namespace abft {
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
+// Each Ops feeds one MFMA group from CPM 16-byte chunks per lane (mfma_chunks).
 struct Bf16Ops {
     typedef uint16_t E;
     static constexpr int KG = 32;       // k per fragment read across the wave's four lane groups
+    static constexpr int CPM = 1;
     __device__ static void mfma(const v4u &a, const v4u &b, v4f &c) {
         v8bf x, y;
         __builtin_memcpy(&x, &a, 16);
         __builtin_memcpy(&y, &b, 16);
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
     }
+    __device__ static void mfma_chunks(const v4u *a, const v4u *b, v4f &c) { mfma(a[0], b[0], c); }
 };
 struct Fp8Ops {
     typedef uint8_t E;
     static constexpr int KG = 64;
+    static constexpr int CPM = 1;
     __device__ static void mfma(const v4u &a, const v4u &b, v4f &c) {
         long a0 = (long)(((uint64_t)a[1] << 32) | a[0]), a1 = (long)(((uint64_t)a[3] << 32) | a[2]);
         long b0 = (long)(((uint64_t)b[1] << 32) | b[0]), b1 = (long)(((uint64_t)b[3] << 32) | b[2]);
         c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, c, 0, 0, 0);
+    }
+    __device__ static void mfma_chunks(const v4u *a, const v4u *b, v4f &c) { mfma(a[0], b[0], c); }
+};
+
+// FP8 E4M3 through v_mfma_scale_f32_16x16x128_f8f6f4 (unit E8M0 scales, 127):
+// 32 bytes (two chunks) per lane and instruction, 128 products per output.
+struct Fp8x128Ops {
+    typedef uint8_t E;
+    static constexpr int CPM = 2;
+    typedef int v8i __attribute__((ext_vector_type(8)));
+    __device__ static void mfma_chunks(const v4u *a, const v4u *b, v4f &c) {
+        v8i x, y;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { x[q] = (int)a[0][q]; x[4 + q] = (int)a[1][q]; y[q] = (int)b[0][q]; y[4 + q] = (int)b[1][q]; }
+        c = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(x, y, c, 0, 0, 0, 127, 0, 127);
     }
 };
 

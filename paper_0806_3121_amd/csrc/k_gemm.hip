@@ -6,6 +6,7 @@
 // few useful rows, so it is computed instead by the skinny-product kernel
 // (sliver_kernel.h), which streams the other operand once with binary64
 // accumulation.
+#include "gemm_lowp2_kernel.h"
 #include "gemm_lowp_kernel.h"
 #include "gemm_mfma_kernel.h"
 #include "sliver_kernel.h"
@@ -77,16 +78,23 @@ static int protected_product(const abft_problem *p, const Geom &g, const E *A, c
     return ABFT_OK;
 }
 
-// bfloat16 / FP8 candidates; efficiencies measured on MI355X at 16384^3 (bfloat16).
+// bfloat16 / FP8 candidates.  When k is a multiple of the 128-byte slab the
+// direct-to-LDS kernel runs (measured at 16384^3: bfloat16 49%, FP8 via the
+// 16x16x128 instruction); otherwise the padded-LDS kernel, on a 256 x 256
+// or 128 x 128 tile (bfloat16 41% / 30% at 16384^3).
 static const TileChoice kLowpTiles[] = {
     {0, 256, 256, 1, 0.411}, {1, 128, 128, 2, 0.303},
 };
-template <class Ops>
+template <class Ops, class Ops2>
 static int gemm_main_lowp(const typename Ops::E *A, int64_t lda, const typename Ops::E *Bt, int64_t ldb, float *C,
                           int64_t ldc, int64_t M, int64_t N, int64_t K, const int *scale_exp, hipStream_t s) {
+    constexpr int64_t slab = 128 / (int64_t)sizeof(typename Ops::E);
+    if (K % slab == 0 && M * N >= (int64_t)256 * 256 * 256)
+        return launch_gemm_lowp2<Ops2, 4>(A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp, s);
     switch (choose_tile(kLowpTiles, 2, M, N)) {
     case 0:
-        return launch_gemm_lowp_tile<LowpTile<Ops, 256, 256, 64, 4, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp, s);
+        return launch_gemm_lowp_tile<LowpTile<Ops, 256, 256, 128 / sizeof(typename Ops::E), 4, 2>>(
+            A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp, s);
     default:
         return launch_gemm_lowp_tile<LowpTile<Ops, 128, 128, 64, 2, 2, 8, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K,
                                                                               scale_exp, s);
@@ -97,12 +105,12 @@ static int gemm_main_lowp(const typename Ops::E *A, int64_t lda, const typename 
 // block from the binary32 checksum rows in the workspace (Acs: br x k,
 // Bcs: bc x k) with binary64 accumulation; FP8 results are scaled back by
 // 2^-(eA + eB) on the device.
-template <class Ops>
+template <class Ops, class Ops2>
 static int protected_product_lowp(const abft_problem *p, const Geom &g, const typename Ops::E *A,
                                   const typename Ops::E *Bt, float *C, const float *Acs, const float *Bcs,
                                   const int *scale_exp, bool plain, hipStream_t s) {
     typedef typename Ops::E E;
-    int st = gemm_main_lowp<Ops>(A, p->lda, Bt, p->ldb, C, p->ldc, g.m, g.n, g.k, scale_exp, s);
+    int st = gemm_main_lowp<Ops, Ops2>(A, p->lda, Bt, p->ldb, C, p->ldc, g.m, g.n, g.k, scale_exp, s);
     if (st) return st;
     ABFT_LAUNCHED();
     if (plain) return ABFT_OK;
@@ -133,10 +141,10 @@ int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C
         const float *Acs = ws ? (const float *)(wsc + L.acs) : nullptr;
         const float *Bcs = ws ? (const float *)(wsc + L.bcs) : nullptr;
         if (p->dtype == ABFT_BF16)
-            return protected_product_lowp<Bf16Ops>(p, g, (const uint16_t *)A_f, (const uint16_t *)B_f, (float *)C_f,
+            return protected_product_lowp<Bf16Ops, Bf16Ops>(p, g, (const uint16_t *)A_f, (const uint16_t *)B_f, (float *)C_f,
                                                    Acs, Bcs, nullptr, plain, s);
         const int *scale = ws ? (const int *)(wsc + L.scale) : nullptr;
-        return protected_product_lowp<Fp8Ops>(p, g, (const uint8_t *)A_f, (const uint8_t *)B_f, (float *)C_f, Acs,
+        return protected_product_lowp<Fp8Ops, Fp8x128Ops>(p, g, (const uint8_t *)A_f, (const uint8_t *)B_f, (float *)C_f, Acs,
                                               Bcs, scale, plain, s);
     }
     default:

@@ -85,6 +85,8 @@ SHAPES = [
     (512, 512, 512, 32, 32),
     (1024, 1024, 4096, 1, 1),
     (300, 260, 528, 3, 5),
+    (4096, 4096, 256, 1, 1),      # large enough for the direct-to-LDS kernel
+    (4200, 4100, 384, 8, 4),      # same kernel, ragged tile edges
 ]
 
 
