@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kSliverThreads) void k_sliver(const TX *__restrict_
     const int lane = threadIdx.x % 64;
     const int64_t wave = ((int64_t)blockIdx.x * kSliverThreads + threadIdx.x) / 64;
     const int64_t nwaves = (int64_t)gridDim.x * kSliverThreads / 64;
-    constexpr int UNR = 4;                           // 16-byte loads in flight per lane and operand row
+    constexpr int UNR = V >= 16 ? 1 : (V >= 8 ? 2 : 4);   // 16-byte loads in flight per lane and operand row
     for (int64_t u = wave; u < U; u += nwaves) {
         double acc[kSliverR];
 #pragma unroll
