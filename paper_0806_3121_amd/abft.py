@@ -62,6 +62,19 @@ class abft_location(C.Structure):
     _fields_ = [("cls", C.c_int32), ("dir", C.c_int32), ("i", C.c_int64), ("j", C.c_int64)]
 
 
+class abft_batch_item(C.Structure):
+    _fields_ = [("A32", C.c_void_p), ("Bt32", C.c_void_p), ("A_f", C.c_void_p), ("B_f", C.c_void_p),
+                ("C_f", C.c_void_p)]
+
+
+class abft_batch_plan(C.Structure):
+    _fields_ = [("bws", C.c_void_p), ("count", C.c_int32), ("dtype", C.c_int32),
+                ("n_tiles", C.c_int64 * 2),
+                ("n_quant", C.c_int64), ("n_enc", C.c_int64), ("n_rows", C.c_int64),
+                ("n_many", C.c_int64), ("n_vcol", C.c_int64), ("n_vrow", C.c_int64),
+                ("bytes", C.c_size_t)]
+
+
 _lib = None
 _V = C.c_void_p
 _P = C.POINTER
@@ -88,6 +101,15 @@ def lib():
             "abft_inject_erase": (C.c_int, [_P(abft_problem), _V, abft_rect, C.c_int, _V]),
             "abft_fill_uniform": (C.c_int, [C.c_int32, C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_uint64,
                                             C.c_int32, _V, _V]),
+            "abft_batch_workspace_size": (C.c_size_t, [_P(abft_problem), C.c_int]),
+            "abft_batch_setup": (C.c_int, [_P(abft_problem), _P(abft_batch_item), C.c_int, _V, C.c_size_t,
+                                           _P(abft_batch_plan)]),
+            "abft_batch_quantize": (C.c_int, [_P(abft_batch_plan), _V]),
+            "abft_batch_encode": (C.c_int, [_P(abft_batch_plan), _V]),
+            "abft_batch_gemm": (C.c_int, [_P(abft_batch_plan), C.c_int, C.c_uint32, _V]),
+            "abft_batch_tune": (C.c_int, [_P(abft_batch_plan), _P(C.c_int), _V]),
+            "abft_batch_verify": (C.c_int, [_P(abft_batch_plan), _V]),
+            "abft_batch_reports": (C.c_int, [_P(abft_batch_plan), _V, _V]),
             "abft_last_hip_error": (C.c_int, []),
             "abft_status_string": (C.c_char_p, [C.c_int]),
         }
@@ -203,6 +225,48 @@ def fill_uniform(dtype, rows, cols, ld, transpose, seed, stream_id, dst, stream=
                                                                _ptr(dst), _stream(stream)))
 
 
+def batch_workspace_size(probs) -> int:
+    arr = (abft_problem * len(probs))(*probs)
+    return lib().abft_batch_workspace_size(arr, len(probs))
+
+
+def batch_setup(probs, items, bws) -> abft_batch_plan:
+    """probs: abft_problem list; items: abft_batch_item list; bws: device uint8 tensor."""
+    pa = (abft_problem * len(probs))(*probs)
+    ia = (abft_batch_item * len(items))(*items)
+    plan = abft_batch_plan()
+    _check("abft_batch_setup", lib().abft_batch_setup(pa, ia, len(probs), _ptr(bws), bws.numel(), C.byref(plan)))
+    return plan
+
+
+def batch_quantize(plan, stream=None):
+    return _check("abft_batch_quantize", lib().abft_batch_quantize(C.byref(plan), _stream(stream)))
+
+
+def batch_encode(plan, stream=None):
+    return _check("abft_batch_encode", lib().abft_batch_encode(C.byref(plan), _stream(stream)))
+
+
+def batch_gemm(plan, tile=0, flags=0, stream=None):
+    return _check("abft_batch_gemm", lib().abft_batch_gemm(C.byref(plan), tile, flags, _stream(stream)))
+
+
+def batch_tune(plan, stream=None) -> int:
+    best = C.c_int(-1)
+    _check("abft_batch_tune", lib().abft_batch_tune(C.byref(plan), C.byref(best), _stream(stream)))
+    return best.value
+
+
+def batch_verify(plan, stream=None):
+    return _check("abft_batch_verify", lib().abft_batch_verify(C.byref(plan), _stream(stream)))
+
+
+def batch_reports(plan, host_out, stream=None):
+    """host_out: pinned uint8 CPU tensor of count * sizeof(abft_report) bytes."""
+    return _check("abft_batch_reports",
+                  lib().abft_batch_reports(C.byref(plan), C.c_void_p(host_out.data_ptr()), _stream(stream)))
+
+
 # ---------------------------------------------------------------- conveniences
 class Protected:
     """Device buffers of one protected product (A_f, B_f, C_f, workspace),
@@ -238,3 +302,45 @@ class Protected:
         verify(self.p, self.C, self.ws, known=known, host_out=self.rep_host)
         torch.cuda.current_stream().synchronize()
         return read_report(self.rep_host)
+
+
+class Batch:
+    """Device buffers of a batch of bfloat16 protected products: per problem
+    binary32 inputs A32 (m x k) and Bt32 (n x k), their bfloat16 copies A and
+    Bt, and C_f with rows padded to 16 bytes; one batch workspace and a pinned
+    buffer for the reports.  shapes: list of (m, n, k, br, bc)."""
+
+    def __init__(self, shapes, device="cuda", tau_mode=ABFT_TAU_STAT, lam=0.0):
+        import torch
+        self.shapes = list(shapes)
+        self.probs, self.items = [], []
+        self.A32, self.Bt32, self.A, self.Bt, self.Cbuf, self.C = [], [], [], [], [], []
+        for (m, n, k, br, bc) in self.shapes:
+            N = n + bc
+            ldc = (N + 3) // 4 * 4
+            p = problem(ABFT_BF16, m, n, k, br, bc, ldc=ldc, tau_mode=tau_mode, lam=lam)
+            a32 = torch.zeros(m, k, dtype=torch.float32, device=device)
+            b32 = torch.zeros(n, k, dtype=torch.float32, device=device)
+            a = torch.zeros(m, k, dtype=torch.bfloat16, device=device)
+            b = torch.zeros(n, k, dtype=torch.bfloat16, device=device)
+            cb = torch.zeros(m + br, ldc, dtype=torch.float32, device=device)
+            self.probs.append(p)
+            self.items.append(abft_batch_item(a32.data_ptr(), b32.data_ptr(), a.data_ptr(), b.data_ptr(),
+                                              cb.data_ptr()))
+            self.A32.append(a32); self.Bt32.append(b32); self.A.append(a); self.Bt.append(b)
+            self.Cbuf.append(cb); self.C.append(cb[:, :N])
+        nbytes = batch_workspace_size(self.probs)
+        if nbytes == 0:
+            raise AbftError("abft_batch_workspace_size", ABFT_E_ARG, "invalid batch")
+        self.bws = torch.zeros(nbytes, dtype=torch.uint8, device=device)
+        self.plan = batch_setup(self.probs, self.items, self.bws)
+        self.rep_host = torch.empty(len(self.probs) * C.sizeof(abft_report), dtype=torch.uint8, pin_memory=True)
+
+    def reports(self, stream=None):
+        """Copy every report out (synchronises the current stream)."""
+        import torch
+        batch_reports(self.plan, self.rep_host, stream)
+        (stream or torch.cuda.current_stream()).synchronize()
+        raw = self.rep_host.numpy().tobytes()
+        sz = C.sizeof(abft_report)
+        return [abft_report.from_buffer_copy(raw[q * sz:(q + 1) * sz]) for q in range(len(self.probs))]

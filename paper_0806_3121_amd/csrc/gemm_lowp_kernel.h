@@ -84,19 +84,14 @@ struct LowpTile {
     static_assert(THREADS % VPR == 0 && BM % ROWS_PER_PASS == 0 && BN % ROWS_PER_PASS == 0, "load split");
 };
 
+// One BM x BN tile of C at (row0, col0): the whole k loop and the epilogue.
+// lds holds 2 * T::BUF elements; the function ends with a barrier, so a
+// persistent caller may reuse lds for its next tile.
 template <class T>
-__global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_lowp(const typename T::E *__restrict__ A, int64_t lda,
-                                                             const typename T::E *__restrict__ Bt, int64_t ldb,
-                                                             float *__restrict__ C, int64_t ldc, int64_t M, int64_t N,
-                                                             int64_t K, const int *__restrict__ scale_exp) {
+__device__ inline void lowp_tile(const typename T::E *__restrict__ A, int64_t lda, const typename T::E *__restrict__ Bt,
+                                 int64_t ldb, float *__restrict__ C, int64_t ldc, int64_t M, int64_t N, int64_t K,
+                                 float sc, int64_t row0, int64_t col0, typename T::E *lds) {
     typedef typename T::E E;
-    __shared__ E lds[2 * T::BUF];
-
-    const int64_t tiles_m = (M + T::BM - 1) / T::BM, tiles_n = (N + T::BN - 1) / T::BN;
-    int64_t tm, tn;
-    tile_of<T::GROUP_M>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
-    const int64_t row0 = tm * T::BM, col0 = tn * T::BN;
-
     const int tid = threadIdx.x;
     const int lane = tid % 64, wave = tid / 64;
     const int wm = wave / T::WN, wn = wave % T::WN;
@@ -174,7 +169,6 @@ __global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_lowp(const typenam
         __syncthreads();
     }
 
-    const float sc = scale_exp ? __builtin_ldexpf(1.0f, -(scale_exp[0] + scale_exp[1])) : 1.0f;
     const int ccol = lane % 16;
 #pragma unroll
     for (int a = 0; a < T::TM; ++a) {
@@ -188,6 +182,19 @@ __global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_lowp(const typenam
             }
         }
     }
+}
+
+template <class T>
+__global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_lowp(const typename T::E *__restrict__ A, int64_t lda,
+                                                             const typename T::E *__restrict__ Bt, int64_t ldb,
+                                                             float *__restrict__ C, int64_t ldc, int64_t M, int64_t N,
+                                                             int64_t K, const int *__restrict__ scale_exp) {
+    __shared__ typename T::E lds[2 * T::BUF];
+    const int64_t tiles_m = (M + T::BM - 1) / T::BM, tiles_n = (N + T::BN - 1) / T::BN;
+    int64_t tm, tn;
+    tile_of<T::GROUP_M>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    const float sc = scale_exp ? __builtin_ldexpf(1.0f, -(scale_exp[0] + scale_exp[1])) : 1.0f;
+    lowp_tile<T>(A, lda, Bt, ldb, C, ldc, M, N, K, sc, tm * T::BM, tn * T::BN, lds);
 }
 
 template <class T>

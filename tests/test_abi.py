@@ -127,3 +127,30 @@ def test_classification_matches_oracle(orc, m, n, br, bc):
         ocls, oi, oj, od = orc.classify(orep, m, n, br, bc, erasures=known)
         loc = abft.classify(p, _to_lib_report(orep), known=known)
         assert (loc.cls, loc.i, loc.j, loc.dir) == (ocls, oi, oj, od), (errs, known)
+
+
+def test_batch_setup_rejects_before_any_copy():
+    good = abft.problem(abft.ABFT_BF16, 64, 32, 16, 32, 1, ldc=36, tau_mode=abft.ABFT_TAU_STAT)
+    assert abft.batch_workspace_size([good]) > 0
+    bad = [
+        abft.problem(abft.ABFT_F64, 64, 32, 16, 32, 1, ldc=33),                                # dtype
+        abft.problem(abft.ABFT_BF16, 64, 32, 16, 32, 1, ldc=36, tau_mode=abft.ABFT_TAU_DET),   # tau mode
+        abft.problem(abft.ABFT_BF16, 64, 30, 16, 32, 3, ldc=36, tau_mode=abft.ABFT_TAU_STAT),  # bc does not divide 256
+        abft.problem(abft.ABFT_BF16, 64, 32, 12, 32, 1, ldc=36, tau_mode=abft.ABFT_TAU_STAT),  # k % 8
+        abft.problem(abft.ABFT_BF16, 64, 32, 16, 32, 1, ldc=32, tau_mode=abft.ABFT_TAU_STAT),  # ldc < n + bc
+    ]
+    for p in bad:
+        assert abft.batch_workspace_size([good, p]) == 0
+    # fake, never dereferenced device addresses: each call must fail on the host
+    fake = abft.abft_batch_item(None, None, 0x10000, 0x20000, 0x30000)
+    L = abft.lib()
+    plan = abft.abft_batch_plan()
+    probs = (abft.abft_problem * 1)(good)
+    items = (abft.abft_batch_item * 1)(fake)
+    need = abft.batch_workspace_size([good])
+    assert L.abft_batch_setup(probs, items, 1, C.c_void_p(0x40000), need - 1, C.byref(plan)) == abft.ABFT_E_WORKSPACE
+    assert L.abft_batch_setup(probs, items, 0, C.c_void_p(0x40000), need, C.byref(plan)) == abft.ABFT_E_ARG
+    misaligned = (abft.abft_batch_item * 1)(abft.abft_batch_item(None, None, 0x10008, 0x20000, 0x30000))
+    assert L.abft_batch_setup(probs, misaligned, 1, C.c_void_p(0x40000), need, C.byref(plan)) == abft.ABFT_E_ARG
+    assert L.abft_batch_gemm(None, 0, 0, None) == abft.ABFT_E_ARG
+    assert L.abft_batch_verify(None, None) == abft.ABFT_E_ARG

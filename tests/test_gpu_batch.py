@@ -1,0 +1,214 @@
+"""GPU parity of the batched bfloat16 path (many independent protected
+products of uneven shapes, flattened descriptors, persistent product kernel)
+against the CPU oracle, and of its hipGraph replay against eager launches.
+
+Per problem the oracle does what the single-problem bfloat16 test does: its
+own round-to-nearest-even of the binary32 inputs (bit-exact vs the device
+quantizer), binary32 checksum rows, the exact product in binary64 rounded to
+binary32, the statistical thresholds with T = k/4, s = 2 (Sec. 3 reading).
+ - values: |C_gpu - C_oracle| <= k u32 (|A_q||B_q|)_ij + u32 |C_ij|;
+ - both tile shapes give the same C bit for bit (same k order per element);
+ - flip decisions and locations equal the oracle's outside the gray zone;
+ - a graph replay equals the eager pass bit for bit, replay after replay.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_0806_3121_amd import abft, synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+SEED = synth.BASE_SEED + 40
+LAMBDA = 20.0
+U32 = 2.0 ** -24
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    abft.lib()
+    return torch.device("cuda:0")
+
+
+def batch_shapes():
+    # edge shapes (one group, minimal k, ragged tiles, one large problem) then seeded draws
+    shapes = [(32, 32, 8, 32, 1), (64, 40, 24, 32, 8), (96, 200, 72, 32, 1), (2048, 1056, 1024, 32, 32)]
+    for q, (m, n, k) in enumerate(synth.batched_shapes(SEED, 20, lo=64, hi=640, step=32)):
+        shapes.append((m, n, k, 32, 1 if q % 2 == 0 else 32))
+    return shapes
+
+
+class Case:
+    def __init__(self, dev, orc):
+        self.shapes = batch_shapes()
+        self.B = abft.Batch(self.shapes, device=dev, tau_mode=abft.ABFT_TAU_STAT, lam=LAMBDA)
+        self.ref = []
+        for q, (m, n, k, br, bc) in enumerate(self.shapes):
+            A32 = synth.uniform(SEED + q, synth.STREAM_A, m, k, np.float32)
+            B32 = synth.uniform(SEED + q, synth.STREAM_B, k, n, np.float32)
+            self.B.A32[q].copy_(torch.from_numpy(A32))
+            self.B.Bt32[q].copy_(torch.from_numpy(np.ascontiguousarray(B32.T)))
+            Aq = orc.to_bf16_bits(A32)
+            Bq = orc.to_bf16_bits(B32)
+            A = orc.bf16_bits_to_f64(Aq)
+            Bm = orc.bf16_bits_to_f64(Bq)
+            Af, Bf = orc.encode(A, Bm, br, bc, store_f32=True)
+            C32 = orc.gemm(Af, Bf).astype(np.float32)
+            tc, tr = orc.tau_stat(Af, Bf, m, n, br, bc, u_acc=U32, T=k / 4.0, s_store=2.0, lam=LAMBDA)
+            bound = k * U32 * (np.abs(Af) @ np.abs(Bf)) + U32 * np.abs(C32)
+            self.ref.append(dict(Aq=Aq, Bq=Bq, C32=C32, tc=tc, tr=tr, bound=bound))
+        torch.cuda.synchronize()
+
+    def run(self, tile):
+        abft.batch_quantize(self.B.plan)
+        abft.batch_encode(self.B.plan)
+        abft.batch_gemm(self.B.plan, tile)
+        abft.batch_verify(self.B.plan)
+        return self.B.reports()
+
+
+@pytest.fixture(scope="module")
+def case(dev, orc):
+    note(f"batch of {len(batch_shapes())} problems")
+    return Case(dev, orc)
+
+
+def test_batch_quantize_bit_exact(case):
+    abft.batch_quantize(case.B.plan)
+    torch.cuda.synchronize()
+    for q, r in enumerate(case.ref):
+        note(f"quantize problem {q} {case.shapes[q]}")
+        a = case.B.A[q].cpu().view(torch.int16).numpy().view(np.uint16)
+        b = case.B.Bt[q].cpu().view(torch.int16).numpy().view(np.uint16)
+        assert np.array_equal(a, r["Aq"])
+        assert np.array_equal(b, np.ascontiguousarray(r["Bq"].T))
+
+
+@pytest.mark.parametrize("tile", [0, 1])
+def test_batch_product_and_clean_verify(case, tile):
+    note(f"batch pass tile={tile}")
+    reps = case.run(tile)
+    for q, r in enumerate(case.ref):
+        Cg = case.B.C[q].cpu().numpy().astype(np.float64)
+        err = np.abs(Cg - r["C32"])
+        assert np.all(err <= r["bound"] * 1.01 + 1e-30), (q, case.shapes[q], err.max())
+        assert reps[q].n_flag_c == 0 and reps[q].n_flag_r == 0, (q, reps[q].max_ratio_c, reps[q].max_ratio_r)
+    note(f"  max |D|/tau {max(max(x.max_ratio_c, x.max_ratio_r) for x in reps):.4f}")
+
+
+def test_batch_tiles_agree_and_tune(case):
+    case.run(0)
+    C0 = [c.clone() for c in case.B.C]
+    case.run(1)
+    torch.cuda.synchronize()
+    for q in range(len(C0)):
+        assert torch.equal(C0[q], case.B.C[q]), q
+    best = abft.batch_tune(case.B.plan)
+    assert best in (0, 1)
+
+
+def test_batch_flips_match_oracle(case, orc):
+    case.run(0)
+    torch.cuda.synchronize()
+    clean = [c.clone() for c in case.B.C]
+    targets = synth.pick_distinct(SEED + 1, 6, len(case.shapes))
+    compared = located = 0
+    for run, q in enumerate(targets):
+        m, n, k, br, bc = case.shapes[q]
+        r = case.ref[q]
+        p = case.B.probs[q]
+        i, j, bit = synth.flip_site(SEED + 2, run, m + br, n + bc, 11, 30)
+        note(f"flip problem {q} {case.shapes[q]} at ({i},{j}) bit {bit}")
+        case.B.C[q].copy_(clean[q])
+        abft.inject_flip(p, case.B.C[q], i, j, bit)
+        abft.batch_verify(case.B.plan)
+        reps = case.B.reports()
+        for q2, rep in enumerate(reps):
+            if q2 != q:
+                assert rep.n_flag_c == 0 and rep.n_flag_r == 0, q2
+        rep = reps[q]
+        Cx = r["C32"].copy()
+        Cx.view(np.uint32)[i, j] ^= np.uint32(1 << bit)
+        delta = float(Cx[i, j]) - float(r["C32"][i, j])
+        t1, t2 = r["tc"][i % br, j], r["tr"][i, j % bc]
+        if np.isfinite(delta) and (t1 / 2 < abs(delta) < 2 * t1 or t2 / 2 < abs(delta) < 2 * t2):
+            case.B.C[q].copy_(clean[q])
+            continue
+        compared += 1
+        _, _, orep = orc.verify(Cx.astype(np.float64), m, n, br, bc, r["tc"], r["tr"])
+        ocls, oi, oj, _ = orc.classify(orep, m, n, br, bc)
+        assert (rep.n_flag_c, rep.n_flag_r) == (orep.n_flag_c, orep.n_flag_r)
+        loc = abft.classify(p, rep)
+        assert (loc.cls, loc.i, loc.j) == (ocls, oi, oj)
+        if loc.cls in (abft.ABFT_CLS_DATA, abft.ABFT_CLS_CHECKSUM):
+            located += 1
+            abft.correct(p, case.B.C[q], loc)
+            abft.batch_verify(case.B.plan)
+            rep2 = case.B.reports()[q]
+            assert rep2.n_flag_c == 0 and rep2.n_flag_r == 0
+            assert abs(case.B.C[q][i, j].item() - clean[q][i, j].item()) <= min(t1, t2)
+        case.B.C[q].copy_(clean[q])
+    note(f"  compared {compared}, located {located}")
+    assert compared >= 4 and located >= 2
+
+
+def test_batch_erasure_rebuild(case):
+    case.run(0)
+    torch.cuda.synchronize()
+    clean = [c.clone() for c in case.B.C]
+    for q in synth.pick_distinct(SEED + 3, 4, len(case.shapes)):
+        m, n, k, br, bc = case.shapes[q]
+        gi = synth.randint(SEED + 4, synth.STREAM_PICK, 2 * q, m // 32 + 1)
+        gj = synth.randint(SEED + 4, synth.STREAM_PICK, 2 * q + 1, n // 32)
+        rect = (gi * 32, gj * 32, 32, 32)
+        note(f"erase problem {q} {case.shapes[q]} rect {rect}")
+        p = case.B.probs[q]
+        abft.inject_erase(p, case.B.C[q], rect, nan_fill=True)
+        abft.recover_block(p, case.B.C[q], rect, use_rows=False)
+        abft.batch_verify(case.B.plan)
+        rep = case.B.reports()[q]
+        assert rep.n_flag_c == 0 and rep.n_flag_r == 0
+        i0, j0, h, w = rect
+        got = case.B.C[q][i0:i0 + h, j0:j0 + w].cpu().numpy().astype(np.float64)
+        want = case.ref[q]["C32"][i0:i0 + h, j0:j0 + w].astype(np.float64)
+        assert np.abs(got - want).max() <= np.abs(case.ref[q]["tc"]).max()
+        case.B.C[q].copy_(clean[q])
+
+
+def test_batch_graph_replay_matches_eager(case):
+    reps_eager = case.run(0)
+    torch.cuda.synchronize()
+    C_eager = [c.clone() for c in case.B.C]
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            abft.batch_quantize(case.B.plan)
+            abft.batch_encode(case.B.plan)
+            abft.batch_gemm(case.B.plan, 0)
+            abft.batch_verify(case.B.plan)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep_no in range(4):
+        note(f"graph replay {rep_no}")
+        # eager work between replays: wipe C and plant a flip the replay must overwrite
+        for c in case.B.C:
+            c.zero_()
+        abft.inject_flip(case.B.probs[0], case.B.C[0], 0, 0, 30)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        reps = case.B.reports()
+        for q in range(len(C_eager)):
+            assert torch.equal(case.B.C[q], C_eager[q]), (rep_no, q)
+            assert reps[q].n_flag_c == 0 and reps[q].n_flag_r == 0
+            assert reps[q].max_ratio_c == reps_eager[q].max_ratio_c
+            assert reps[q].max_ratio_r == reps_eager[q].max_ratio_r
+    del g
