@@ -12,7 +12,7 @@ per launch with events on the launch stream (the roofline object), the plain
 product of the same kernel gives the ABFT overhead, and the CPU oracle is
 timed on a bounded sample of the same product (rank 0, N = 1 only).
 
-    python bench.py [--steps K] [--warmup W] [--workload c2|c2b1|c1|c1b64|c3|c4|c4fp8] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload c2|c2b1|c1|c1b64|c3|c4|c4fp8|c5] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -36,7 +36,11 @@ WORKLOADS = {
     "c3": ("f32", 16384, 8192, 32768, 1, False),
     "c4": ("bf16", 16384, 16384, 16384, 1, False),
     "c4fp8": ("fp8", 16384, 16384, 16384, 1, False),
+    # batched: 512 bfloat16 problems, m, n, k uniform on multiples of 32 in [64, 2048]
+    "c5": ("bf16", 0, 0, 0, 32, True),
 }
+BATCH = {"count": 512, "lo": 64, "hi": 2048, "step": 32, "br": 32, "bc": 1, "lam": 20.0,
+         "flips": 5, "erasures": 3}
 # flip bits per C type: binary64 40..62; binary32 24..29 (exponent bits and the
 # top fraction bit: always above the statistical threshold, so every step's
 # flip is located)
@@ -88,6 +92,184 @@ def cpu_baseline(dt_name, m, n, k, b, target_s=12.0):
     return flops / dt / 1e12, orc.num_threads(), dt, rows
 
 
+def cpu_baseline_batched(shapes, br, bc, target_s=12.0):
+    """Oracle on whole problems of the batch, in order, until about target_s
+    seconds: quantize (its own RNE), encode, binary64 product of the encoded
+    operands.  Returns (TFLOP/s, threads, seconds, problems)."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    from paper_0806_3121_amd import synth
+
+    flops = 0.0
+    t0 = time.perf_counter()
+    q = 0
+    while q < len(shapes) and time.perf_counter() - t0 < target_s:
+        m, n, k = shapes[q]
+        A = orc.bf16_bits_to_f64(orc.to_bf16_bits(synth.uniform(SEED + q, synth.STREAM_A, m, k, np.float32)))
+        B = orc.bf16_bits_to_f64(orc.to_bf16_bits(synth.uniform(SEED + q, synth.STREAM_B, k, n, np.float32)))
+        Af, Bf = orc.encode(A, B, br, bc, store_f32=True)
+        orc.gemm(Af, Bf)
+        flops += 2.0 * (m + br) * (n + bc) * k
+        q += 1
+    dt = time.perf_counter() - t0
+    return flops / dt / 1e12, orc.num_threads(), dt, q
+
+
+def run_batched(args):
+    """The batched workload: per step one graph replay of quantize + encode,
+    one of the persistent product (timed with events), seeded flips and
+    erasures on distinct problems, block rebuilds, one graph replay of the
+    verification, host classification and correction of every flagged
+    problem, and a verification replay that must come back clean."""
+    import torch
+
+    from paper_0806_3121_amd import abft, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    cfg = BATCH
+    br, bc = cfg["br"], cfg["bc"]
+    shapes = synth.batched_shapes(SEED, cfg["count"], cfg["lo"], cfg["hi"], cfg["step"])
+    log(f"workload c5: {len(shapes)} bf16 problems, br={br} bc={bc}")
+    Bt = abft.Batch([(m, n, k, br, bc) for (m, n, k) in shapes], device=dev, tau_mode=abft.ABFT_TAU_STAT,
+                    lam=cfg["lam"])
+    for q, (m, n, k) in enumerate(shapes):
+        abft.fill_uniform(abft.ABFT_F32, m, k, k, 0, SEED + q, synth.STREAM_A, Bt.A32[q])
+        abft.fill_uniform(abft.ABFT_F32, k, n, k, 1, SEED + q, synth.STREAM_B, Bt.Bt32[q])
+    plan = Bt.plan
+    abft.batch_quantize(plan)
+    tile = abft.batch_tune(plan)
+    log(f"autotuned tile shape {tile}")
+    torch.cuda.synchronize()
+
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    graphs = {}
+    with torch.cuda.stream(side):
+        for name, fn in (("pre", lambda: (abft.batch_quantize(plan), abft.batch_encode(plan))),
+                         ("gemm", lambda: abft.batch_gemm(plan, tile)),
+                         ("verify", lambda: abft.batch_verify(plan))):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                fn()
+            graphs[name] = g
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+
+    ev = {"pre": [], "gemm": [], "verify": []}
+
+    def timed(name):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        graphs[name].replay()
+        e1.record(stream)
+        ev[name].append((e0, e1))
+
+    nf, ne = cfg["flips"], cfg["erasures"]
+
+    def step(s):
+        timed("pre")
+        timed("gemm")
+        picks = synth.pick_distinct(SEED + 7 + s, nf + ne, len(shapes))
+        flips = {}
+        for e, q in enumerate(picks[:nf]):
+            m, n, k = shapes[q]
+            i, j, bit = synth.flip_site(SEED, s * 16 + e, m + br, n + bc, 24, 29)
+            abft.inject_flip(Bt.probs[q], Bt.C[q], i, j, bit)
+            flips[q] = (i, j)
+        for e, q in enumerate(picks[nf:]):
+            m, n, k = shapes[q]
+            I, J = synth.erase_block(SEED, s * 16 + e, m // br + 1, n // 32)
+            rect = (I * br, J * 32, br, 32)
+            abft.inject_erase(Bt.probs[q], Bt.C[q], rect)
+            abft.recover_block(Bt.probs[q], Bt.C[q], rect, use_rows=False)
+        timed("verify")
+        flagged = Bt.fetch_reports()   # synchronises
+        if sorted(flagged) != sorted(flips):
+            raise RuntimeError(f"step {s}: flagged {flagged}, flipped {sorted(flips)}")
+        for q in flagged:
+            loc = abft.classify(Bt.probs[q], Bt.report(q))
+            if (loc.cls, loc.i, loc.j) != ((abft.ABFT_CLS_DATA if flips[q][0] < shapes[q][0] and flips[q][1] <
+                                            shapes[q][1] else abft.ABFT_CLS_CHECKSUM),) + flips[q]:
+                raise RuntimeError(f"step {s}: problem {q} flip {flips[q]} classified {loc.cls} ({loc.i},{loc.j})")
+            abft.correct(Bt.probs[q], Bt.C[q], loc)
+        timed("verify")
+        if Bt.fetch_reports():
+            raise RuntimeError(f"step {s}: not clean after repair")
+
+    for s in range(args.warmup):
+        step(1000 + s)
+    for v in ev.values():
+        v.clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(s)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"timed {args.steps} steps in {dt:.3f} s")
+    ms = {name: sum(a.elapsed_time(c) for a, c in v) / len(v) for name, v in ev.items()}
+
+    pe = []
+    for s in range(0 if args.no_plain else max(3, min(args.steps, 10))):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        abft.batch_gemm(plan, tile, abft.ABFT_PLAIN)
+        e1.record(stream)
+        pe.append((e0, e1))
+    torch.cuda.synchronize()
+    plain_ms = sum(a.elapsed_time(c) for a, c in pe[1:]) / len(pe[1:]) if pe else None
+
+    useful = sum(2.0 * m * n * k for (m, n, k) in shapes)
+    executed = sum(2.0 * (m + br) * (n + bc) * k for (m, n, k) in shapes)
+    ms_step = dt / args.steps * 1e3
+    value = useful / (ms_step * 1e-3) / 1e12
+    achieved = executed / (ms["gemm"] * 1e-3) / 1e12
+    peak = PEAK["bf16"]
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"batched BF16->FP32 protected GEMMs c5: {len(shapes)} problems, m, n, k uniform "
+                               f"on multiples of {cfg['step']} in [{cfg['lo']}, {cfg['hi']}], checksum blocks "
+                               f"{br}x{bc}; per step {nf} flips and {ne} erased {br}x32 blocks on distinct "
+                               f"problems; graph-captured passes",
+                   "problems": len(shapes), "br": br, "bc": bc, "tile": tile, "global_batch": len(shapes),
+                   "seq_len": 0, "parallelism": "single-gpu"},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "kb_gemm (persistent, all problems) + kb_sliver (carried checksums)",
+                     "flops_per_launch": executed, "avg_launch_ms": round(ms["gemm"], 4)},
+        "pct_mfma_peak_useful": round(100 * value / peak, 2),
+        "phase_ms": {"quantize_encode": round(ms["pre"], 4), "gemm_protected": round(ms["gemm"], 4),
+                     "verify": round(ms["verify"], 4)},
+        "gemm_protected_ms": round(ms["gemm"], 4),
+        "gemm_plain_ms": round(plain_ms, 4) if plain_ms else None,
+        "abft_overhead_pct": round(100 * (ms["gemm"] / plain_ms - 1), 2) if plain_ms else None,
+        "abft_floor_pct": round(100 * (executed / useful - 1), 2),
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        tf, thr, sec, nprob = cpu_baseline_batched(shapes, br, bc, args.cpu_seconds)
+        out["cpu_baseline"] = {"value": round(tf, 6), "unit": "TFLOP/s", "cores": thr, "kind": "oracle",
+                               "sample": f"problems 0..{nprob - 1} of the batch, whole (quantize, encode, FP64 "
+                                         f"i-l-j product of the encoded operands), {sec:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +284,9 @@ def main():
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the path is built and measured on one "
                                    "MI355X (see the sharding notes in DESIGN.md)", "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.workload == "c5":
+        return run_batched(args)
 
     import torch
 

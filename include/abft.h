@@ -250,13 +250,19 @@ int abft_fill_uniform(int32_t dtype, int64_t rows, int64_t cols, int64_t ld, int
 
 /*
  * Batched problems: many independent protected products of uneven shapes in
- * one pass (bfloat16 inputs, binary32 C, statistical thresholds).  Every step
- * is one or two launches over all problems (flattened per-problem
- * descriptors, persistent product kernel), takes no host synchronisation and
- * allocates nothing, so the pass quantize -> encode -> gemm -> verify can be
- * captured in one hipGraph and replayed.  Classification, correction and
- * block rebuild use the single-problem calls above (abft_classify,
- * abft_correct, abft_recover_block) with each problem's descriptor.
+ * one pass (bfloat16 inputs, binary32 C, statistical or exact thresholds).
+ * Every step is one or two launches over all problems (flattened
+ * per-problem descriptors; a persistent product kernel that takes tiles of
+ * all problems, largest k first, from a device counter), takes no host
+ * synchronisation and allocates nothing, so the pass quantize -> encode ->
+ * gemm -> verify can be captured in a hipGraph and replayed.  The binary32
+ * checksum rows are also stored as three bfloat16 rows whose sum is exact
+ * (hi + mid + lo), so the carried checksum blocks are products on the matrix
+ * cores like the data block; their three partial products are summed in
+ * binary64 and rounded once.  Classification, correction and block rebuild
+ * use the single-problem calls above (abft_classify, abft_correct,
+ * abft_recover_block) with each problem's descriptor.  The calls on one plan
+ * must be ordered on one stream: they share the workspace and its counters.
  */
 typedef struct {
     const float *A32;   /* binary32 A (m x k, row-major, leading dimension lda) for abft_batch_quantize, or NULL */
@@ -266,22 +272,29 @@ typedef struct {
     void *C_f;          /* binary32 C_f, (m+br) x (n+bc), ldc */
 } abft_batch_item;
 
+/* Product tile shapes of the batched kernel: 0 = 256 x 256, 1 = 256 x 128,
+ * 2 = 128 x 256, 3 = 128 x 128. */
+#define ABFT_BATCH_TILES 4
+
 /* Host-side plan filled by abft_batch_setup (caller-owned, plain data). */
 typedef struct {
-    void *bws;                 /* the device batch workspace */
+    void *bws;                                 /* the device batch workspace */
     int32_t count;
     int32_t dtype;
-    int64_t n_tiles[2];        /* product tiles for tile shape 0 (128 x 128) and 1 (64 x 64) */
-    int64_t n_quant, n_enc, n_rows, n_many, n_vcol, n_vrow;   /* flattened work counts */
+    int64_t n_tiles[ABFT_BATCH_TILES][2];      /* product tiles per shape: [.][0] protected, [.][1] ABFT_PLAIN */
+    int64_t n_work[8];                         /* flattened work sizes of the other steps */
     size_t bytes;
 } abft_batch_plan;
 
 /* Device bytes of the batch workspace for these problems (0 if invalid). */
 size_t abft_batch_workspace_size(const abft_problem *probs, int count);
 
-/* Validate every problem (dtype ABFT_BF16, tau mode STAT or EXACT, the
- * single-problem layout rules) and write the device descriptors into bws
- * (synchronous copy, not capturable).  probs, items and plan are host arrays. */
+/* Validate every problem (dtype ABFT_BF16; tau mode STAT or EXACT; k, lda,
+ * ldb multiples of 8; ldc >= n + bc; br divides m; bc divides n and 64) and
+ * write the descriptors and counters into bws (synchronous copy, not
+ * capturable).  probs, items and plan are host arrays; A_f and B_f 16-byte
+ * aligned, A32 and Bt32 16-byte aligned when set.  ABFT_E_ARG / ABFT_E_UNSUPPORTED
+ * on a bad problem, ABFT_E_WORKSPACE if bws_bytes is too small. */
 int abft_batch_setup(const abft_problem *probs, const abft_batch_item *items, int count, void *bws, size_t bws_bytes,
                      abft_batch_plan *plan);
 
@@ -290,21 +303,22 @@ int abft_batch_setup(const abft_problem *probs, const abft_batch_item *items, in
  *   abft_batch_quantize: A32 -> A_f and Bt32 -> B_f (round to nearest even)
  *     for the items whose binary32 pointers are set;
  *   abft_batch_encode: checksum rows C_C^T A and (B C_R)^T (Eq. ABFT-GEMM),
- *     kept in binary32 in bws, and the statistics of the thresholds (Sec. 3);
+ *     kept in binary32 and as three bfloat16 rows in bws, and the statistics
+ *     of the thresholds (Sec. 3);
  *   abft_batch_gemm: C_f = A_f B_f; flags 0 or ABFT_PLAIN (data block only);
- *     tile 0 = 128 x 128 product tiles, 1 = 64 x 64;
+ *     tile: one of the ABFT_BATCH_TILES shapes;
  *   abft_batch_verify: every column and row relation of every C_f (Sec. 2),
  *     into the problem's report in bws (no erased-element exclusion).
- * abft_batch_tune runs abft_batch_gemm(ABFT_PLAIN) with both tile shapes
- * (overwriting the data blocks of every C_f), synchronises the stream and
- * returns the faster in *best_tile.  All return ABFT_E_ARG on a NULL plan. */
+ * abft_batch_tune runs abft_batch_gemm with every tile shape (overwriting
+ * every C_f), synchronises the stream and returns the fastest in *best_tile.
+ * All return ABFT_E_ARG on a NULL plan or a bad tile. */
 int abft_batch_quantize(const abft_batch_plan *plan, void *stream);
 int abft_batch_encode(const abft_batch_plan *plan, void *stream);
 int abft_batch_gemm(const abft_batch_plan *plan, int tile, uint32_t flags, void *stream);
 int abft_batch_tune(const abft_batch_plan *plan, int *best_tile, void *stream);
 int abft_batch_verify(const abft_batch_plan *plan, void *stream);
-/* Copy the count reports (verify results, problem order) to host_out
- * (pinned; valid after a stream synchronisation). */
+/* Copy the count reports (verify results, in the caller's problem order) to
+ * host_out (pinned; valid after a stream synchronisation). */
 int abft_batch_reports(const abft_batch_plan *plan, abft_report *host_out, void *stream);
 
 /* Last hipError_t seen by this thread (0 if none), and a status message. */

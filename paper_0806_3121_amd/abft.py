@@ -67,11 +67,13 @@ class abft_batch_item(C.Structure):
                 ("C_f", C.c_void_p)]
 
 
+ABFT_BATCH_TILES = 4      # product tile shapes: 256x256, 256x128, 128x256, 128x128
+
+
 class abft_batch_plan(C.Structure):
     _fields_ = [("bws", C.c_void_p), ("count", C.c_int32), ("dtype", C.c_int32),
-                ("n_tiles", C.c_int64 * 2),
-                ("n_quant", C.c_int64), ("n_enc", C.c_int64), ("n_rows", C.c_int64),
-                ("n_many", C.c_int64), ("n_vcol", C.c_int64), ("n_vrow", C.c_int64),
+                ("n_tiles", (C.c_int64 * 2) * ABFT_BATCH_TILES),
+                ("n_work", C.c_int64 * 8),
                 ("bytes", C.c_size_t)]
 
 
@@ -335,6 +337,21 @@ class Batch:
         self.bws = torch.zeros(nbytes, dtype=torch.uint8, device=device)
         self.plan = batch_setup(self.probs, self.items, self.bws)
         self.rep_host = torch.empty(len(self.probs) * C.sizeof(abft_report), dtype=torch.uint8, pin_memory=True)
+
+    def fetch_reports(self, stream=None):
+        """Copy every report into the pinned buffer (synchronises the stream);
+        returns the indices of the problems with a failed relation."""
+        import numpy as np
+        import torch
+        batch_reports(self.plan, self.rep_host, stream)
+        (stream or torch.cuda.current_stream()).synchronize()
+        w = self.rep_host.numpy().view(np.int64).reshape(len(self.probs), C.sizeof(abft_report) // 8)
+        return [int(q) for q in np.nonzero(w[:, 0] + w[:, 1])[0]]
+
+    def report(self, q) -> abft_report:
+        """Problem q's report from the last fetch_reports."""
+        sz = C.sizeof(abft_report)
+        return abft_report.from_buffer_copy(self.rep_host.numpy()[q * sz:(q + 1) * sz].tobytes())
 
     def reports(self, stream=None):
         """Copy every report out (synchronises the current stream)."""

@@ -1,13 +1,21 @@
-// Batched protected products (the batched workload: many independent
-// bfloat16 products of uneven shapes).  Every step runs over flattened work
-// spaces: each problem's descriptor holds the start of its range in each
-// space, and a thread finds its problem by binary search.  The product is a
-// persistent kernel striding over all problems' tiles.  Nothing here
-// synchronises with the host or allocates, so the pass can be captured in a
-// hipGraph.  The arithmetic of every step is the single-problem one
-// (k_reduce.hip, gemm_lowp_kernel.h, sliver_kernel.h).
+// Batched protected products: many independent bfloat16 products of uneven
+// shapes.  Every step runs over flattened work spaces.  Each problem's range
+// in a space is padded to a whole number of block iterations, so a block
+// iteration belongs to one problem and finds it with one binary search on a
+// block-uniform index (scalar loads).  Nothing here synchronises with the
+// host or allocates, so the pass can be captured in a hipGraph.
+//
+// Per problem the arithmetic is that of the single-problem bfloat16 path
+// (binary64 checksum sums rounded once to binary32, statistics of Sec. 3),
+// except for the carried checksum blocks: the binary32 checksum rows are
+// split into three bfloat16 rows hi + mid + lo that add up to them exactly,
+// the product runs over the "virtual" operands [A; hi; mid; lo] and
+// [Bt; hi; mid; lo] on the matrix cores, and the three (nine, for the
+// corner) partial products are added in binary64 and rounded once.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <numeric>
 #include <vector>
 
 #include "gemm_lowp_kernel.h"
@@ -18,25 +26,48 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kW = 64;
+constexpr int kRowsPerIter = 64;        // row statistics: rows per block iteration (16 per wave)
+constexpr int kWLdsMax = 8192;          // row statistics: weights staged in LDS up to this k
 
 struct BatchDesc {
     int64_t m, n, k, br, bc, lda, ldb, ldc, M, N, Gr, Gc;
+    int64_t MV, NV;                   // virtual product rows m + 3 br, columns n + 3 bc
+    int64_t PA, PB;                   // encode partitions of the group sums (A side, B side)
     const float *A32, *Bt32;
     uint16_t *A, *Bt;
     float *C;
-    float *acs, *bcs;             // binary32 checksum rows (br x k), (bc x k)
-    double *grpA, *grpB;          // per-residue sums of squares v (br x k), w (bc x k)
-    double *qr, *qc, *nv, *nw;    // threshold statistics (M, N, br, bc)
+    float *acs, *bcs;                 // binary32 checksum rows (br x k), (bc x k)
+    uint16_t *asp, *bsp;              // the same split into bfloat16: (3 br x k), (3 bc x k), hi rows first
+    double *grpA, *grpB;              // per-residue sums of squares (br x k), (bc x k)
+    double *partA, *partB;            // encode partials [P][2][b][k] when P > 1
+    float *S1, *S2;                   // product staging: rows m.. of the virtual C (3 br x NV); columns n.. (m x 3 bc)
+    double *qr, *qc, *nv, *nw;        // threshold statistics (M, N, br, bc)
+    double *vpart;                    // verification row partials [M][ceil(N / 1024)][bc]
     abft_report *rep;
-    double cc, cr;                // stat coefficients (lambda^2 (u^2/3)(T/2 + s))
-    int mode;                     // ABFT_TAU_STAT or ABFT_TAU_EXACT
+    double cc, cr;                    // stat coefficients (lambda^2 (u^2/3)(T/2 + s))
+    int mode;                         // ABFT_TAU_STAT or ABFT_TAU_EXACT
+    int orig;                         // index in the caller's order
     // starts in the flattened work spaces
-    int64_t s_tiles[2], s_quant, s_enc, s_rows, s_many, s_vcol, s_vrow;
+    int64_t s_tiles[ABFT_BATCH_TILES][2];
+    int64_t s_quant, s_enc1, s_enc2, s_rows, s_comb, s_vcol, s_vrow;
 };
 
-// largest p with d[p].*F <= t  (starts are non-decreasing)
+enum { W_QUANT = 0, W_ENC1, W_ENC2, W_ROWS, W_COMB, W_VCOL, W_VROW };
+
+// A pointer read from a descriptor, typed as global memory: offsets are added
+// in the global address space, and the result is cast back to a generic
+// pointer only where it is dereferenced (G<T> * -> T *), so the compiler emits
+// global rather than flat memory instructions.
+template <typename T> using G = T __attribute__((address_space(1)));
+template <typename T>
+__device__ inline G<T> *gp(T *p) {
+    return (G<T> *)p;
+}
+
+
+// largest p with d[p].*F <= t (starts are non-decreasing; t block-uniform)
 template <int64_t BatchDesc::*F>
-__device__ inline int find_problem(const BatchDesc *d, int count, int64_t t) {
+__device__ inline int find_problem(const BatchDesc *__restrict__ d, int count, int64_t t) {
     int lo = 0, hi = count - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
@@ -45,294 +76,696 @@ __device__ inline int find_problem(const BatchDesc *d, int count, int64_t t) {
     }
     return lo;
 }
-__device__ inline int find_tile_problem(const BatchDesc *d, int count, int64_t t, int tile) {
+__device__ inline int find_tile_problem(const BatchDesc *__restrict__ d, int count, int64_t t, int cfg, int plain) {
     int lo = 0, hi = count - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (d[mid].s_tiles[tile] <= t) lo = mid;
+        if (d[mid].s_tiles[cfg][plain] <= t) lo = mid;
         else hi = mid - 1;
     }
     return lo;
 }
 
-__device__ inline double bf(uint16_t x) { return (double)bf16_to_f32(x); }
+// A block's walk over its contiguous share of a flattened space, PER units per
+// iteration: the problem is looked up again only when the walk crosses into
+// the next problem's range.
+template <int64_t BatchDesc::*F, int PER>
+struct Walk {
+    const BatchDesc *d;
+    int count, p;
+    int64_t end, first, last;
+    __device__ Walk(const BatchDesc *d_, int count_, int64_t total) : d(d_), count(count_), p(0), end(-1) {
+        const int64_t iters = (total + PER - 1) / PER, per = (iters + gridDim.x - 1) / gridDim.x;
+        first = (int64_t)blockIdx.x * per * PER;
+        last = min(total, first + per * PER);
+    }
+    __device__ const BatchDesc &at(int64_t t) {
+        if (t >= end) {
+            p = find_problem<F>(d, count, t);
+            end = p + 1 < count ? d[p + 1].*F : INT64_MAX;
+        }
+        return d[p];
+    }
+};
+
+typedef float v4f_ __attribute__((ext_vector_type(4)));
+typedef uint32_t v4u_ __attribute__((ext_vector_type(4)));
+typedef double v2d_ __attribute__((ext_vector_type(2)));
+
+__device__ inline uint32_t pack2(uint16_t a, uint16_t b) { return (uint32_t)a | ((uint32_t)b << 16); }
+
+// One 16-byte load from global memory, widened to binary64.
+template <typename T> struct gload;
+template <> struct gload<uint16_t> {
+    static constexpr int N = 8;
+    __device__ static void load(const G<uint16_t> *p, double *o) {
+        v4u_ v = *(const G<v4u_> *)p;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            o[2 * q] = (double)bf16_to_f32((uint16_t)(v[q] & 0xFFFFu));
+            o[2 * q + 1] = (double)bf16_to_f32((uint16_t)(v[q] >> 16));
+        }
+    }
+};
+template <> struct gload<float> {
+    static constexpr int N = 4;
+    __device__ static void load(const G<float> *p, double *o) {
+        v4f_ v = *(const G<v4f_> *)p;
+        o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+    }
+};
+template <> struct gload<double> {
+    static constexpr int N = 2;
+    __device__ static void load(const G<double> *p, double *o) {
+        v2d_ v = *(const G<v2d_> *)p;
+        o[0] = v[0]; o[1] = v[1];
+    }
+};
 
 // ------------------------------------------------------------------ quantize
-__global__ __launch_bounds__(kT) void kb_quantize(const BatchDesc *d, int count, int64_t total) {
-    typedef float v4 __attribute__((ext_vector_type(4)));
-    typedef uint32_t v4u_ __attribute__((ext_vector_type(4)));
-    for (int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x; t < total; t += (int64_t)gridDim.x * kT) {
-        int p = find_problem<&BatchDesc::s_quant>(d, count, t);
-        const BatchDesc &D = d[p];
-        int64_t q = t - D.s_quant, kv = D.k / 8;
-        bool isA = q < D.m * kv;
-        if (!isA) q -= D.m * kv;
-        int64_t i = q / kv, c = (q - i * kv) * 8;
-        const float *X0 = isA ? D.A32 : D.Bt32;
+// Unit = 8 consecutive elements of a row of A (first) or of Bt.
+__global__ __launch_bounds__(kT) void kb_quantize(const BatchDesc *__restrict__ d, int count, int64_t total) {
+    Walk<&BatchDesc::s_quant, kT> wk(d, count, total);
+    for (int64_t b0 = wk.first; b0 < wk.last; b0 += kT) {
+        const BatchDesc &D = wk.at(b0);
+        int64_t q = b0 - D.s_quant + threadIdx.x;
+        const int64_t kv = D.k / 8, na = D.m * kv;
+        if (q >= na + D.n * kv) continue;
+        const bool isA = q < na;
+        if (!isA) q -= na;
+        const G<const float> *X0 = isA ? gp(D.A32) : gp(D.Bt32);
         if (!X0) continue;                             // this operand is already bfloat16
-        const float *X = X0 + i * (isA ? D.lda : D.ldb) + c;
-        uint16_t *Q = isA ? D.A + i * D.lda + c : D.Bt + i * D.ldb + c;
-        v4 x0 = *(const v4 *)X, x1 = *(const v4 *)(X + 4);
+        const int64_t i = q / kv, c = (q - i * kv) * 8, ld = isA ? D.lda : D.ldb;
+        const G<const float> *X = X0 + i * ld + c;
+        v4f_ x0 = *(const G<v4f_> *)X, x1 = *(const G<v4f_> *)(X + 4);
         v4u_ o;
-        o[0] = f32_to_bf16_rne(x0[0]) | ((uint32_t)f32_to_bf16_rne(x0[1]) << 16);
-        o[1] = f32_to_bf16_rne(x0[2]) | ((uint32_t)f32_to_bf16_rne(x0[3]) << 16);
-        o[2] = f32_to_bf16_rne(x1[0]) | ((uint32_t)f32_to_bf16_rne(x1[1]) << 16);
-        o[3] = f32_to_bf16_rne(x1[2]) | ((uint32_t)f32_to_bf16_rne(x1[3]) << 16);
-        *(v4u_ *)Q = o;
+        o[0] = pack2(f32_to_bf16_rne(x0[0]), f32_to_bf16_rne(x0[1]));
+        o[1] = pack2(f32_to_bf16_rne(x0[2]), f32_to_bf16_rne(x0[3]));
+        o[2] = pack2(f32_to_bf16_rne(x1[0]), f32_to_bf16_rne(x1[1]));
+        o[3] = pack2(f32_to_bf16_rne(x1[2]), f32_to_bf16_rne(x1[3]));
+        *(G<v4u_> *)((isA ? gp(D.A) : gp(D.Bt)) + i * ld + c) = o;
     }
 }
 
-// ------------------------------------------------------------------ encode pass 1
-// Per problem: br*k/8 A relations then bc*k/8 B relations; thread = 8 columns.
-__global__ __launch_bounds__(kT) void kb_encode(const BatchDesc *d, int count, int64_t total) {
-    for (int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x; t < total; t += (int64_t)gridDim.x * kT) {
-        int p = find_problem<&BatchDesc::s_enc>(d, count, t);
-        const BatchDesc &D = d[p];
-        int64_t q = t - D.s_enc, kv = D.k / 8;
-        bool isA = q < D.br * kv;
-        if (!isA) q -= D.br * kv;
-        int64_t b = isA ? D.br : D.bc, G = isA ? D.Gr : D.Gc, ld = isA ? D.lda : D.ldb;
-        int64_t r = q / kv, l0 = (q - r * kv) * 8;
-        const uint16_t *X = (isA ? D.A : D.Bt) + r * ld + l0;
+// ------------------------------------------------------------------ encode
+// Final values of 8 consecutive checksum entries (r, l0..l0+7) of one side:
+// the binary32 row, its exact bfloat16 split hi + mid + lo, and grp.
+__device__ inline void enc_finish(G<float> *cs, G<uint16_t> *sp, G<double> *grp, int64_t b, int64_t k, int64_t r,
+                                  int64_t l0, const double *s, const double *ss) {
+    float c[8];
+    uint16_t h[3][8];
+    double g[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        c[e] = (float)s[e];
+        g[e] = ss[e] + (double)c[e] * (double)c[e];
+        uint16_t hi = f32_to_bf16_rne(c[e]);
+        float r1 = c[e] - bf16_to_f32(hi);             // exact
+        uint16_t mid = f32_to_bf16_rne(r1);
+        float r2 = r1 - bf16_to_f32(mid);              // exact, at most 8 significant bits
+        h[0][e] = hi;
+        h[1][e] = mid;
+        h[2][e] = f32_to_bf16_rne(r2);
+    }
+    G<float> *pc = cs + r * k + l0;
+    *(G<v4f_> *)pc = v4f_{c[0], c[1], c[2], c[3]};
+    *(G<v4f_> *)(pc + 4) = v4f_{c[4], c[5], c[6], c[7]};
+    G<double> *pg = grp + r * k + l0;
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) *(G<v2d_> *)(pg + e) = v2d_{g[e], g[e + 1]};
+#pragma unroll
+    for (int s3 = 0; s3 < 3; ++s3)
+        *(G<v4u_> *)(sp + (s3 * b + r) * k + l0) =
+            v4u_{pack2(h[s3][0], h[s3][1]), pack2(h[s3][2], h[s3][3]), pack2(h[s3][4], h[s3][5]),
+                 pack2(h[s3][6], h[s3][7])};
+}
+
+// Pass 1, unit = (side, partition, residue r, 8 columns): sums over the
+// partition's groups g of X[g*b + r, l] and of its square; final values when
+// the side has one partition, else partials.
+__global__ __launch_bounds__(kT) void kb_encode1(const BatchDesc *__restrict__ d, int count, int64_t total) {
+    Walk<&BatchDesc::s_enc1, kT> wk(d, count, total);
+    for (int64_t b0 = wk.first; b0 < wk.last; b0 += kT) {
+        const BatchDesc &D = wk.at(b0);
+        int64_t q = b0 - D.s_enc1 + threadIdx.x;
+        const int64_t kv = D.k / 8, ua = D.PA * D.br * kv;
+        if (q >= ua + D.PB * D.bc * kv) continue;
+        const bool isA = q < ua;
+        if (!isA) q -= ua;
+        const int64_t b = isA ? D.br : D.bc, NG = isA ? D.Gr : D.Gc, P = isA ? D.PA : D.PB;
+        const int64_t ld = isA ? D.lda : D.ldb;
+        const int64_t p = q / (b * kv), rem = q - p * (b * kv), r = rem / kv, l0 = (rem - r * kv) * 8;
+        const int64_t ch = (NG + P - 1) / P, g0 = p * ch, g1 = min(NG, g0 + ch);
+        const G<uint16_t> *X = (isA ? gp(D.A) : gp(D.Bt)) + r * ld + l0;
         double s[8], ss[8], v[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) s[e] = ss[e] = 0.0;
-        for (int64_t g = 0; g < G; ++g) {
-            vec16<uint16_t>::load(X + g * b * ld, v);
+#pragma unroll 4
+        for (int64_t g = g0; g < g1; ++g) {
+            gload<uint16_t>::load(X + g * b * ld, v);
 #pragma unroll
             for (int e = 0; e < 8; ++e) { s[e] += v[e]; ss[e] += v[e] * v[e]; }
         }
-        float *cs = (isA ? D.acs : D.bcs) + r * D.k + l0;
-        double *grp = (isA ? D.grpA : D.grpB) + r * D.k + l0;
+        if (P == 1) {
+            enc_finish(isA ? gp(D.acs) : gp(D.bcs), isA ? gp(D.asp) : gp(D.bsp), isA ? gp(D.grpA) : gp(D.grpB), b, D.k, r, l0, s, ss);
+        } else {
+            G<double> *part = isA ? gp(D.partA) : gp(D.partB);
+            G<double> *ps = part + ((2 * p) * b + r) * D.k + l0, *pq = part + ((2 * p + 1) * b + r) * D.k + l0;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            float c = (float)s[e];
-            cs[e] = c;
-            grp[e] = ss[e] + (double)c * (double)c;
+            for (int e = 0; e < 8; e += 2) {
+                *(G<v2d_> *)(ps + e) = v2d_{s[e], s[e + 1]};
+                *(G<v2d_> *)(pq + e) = v2d_{ss[e], ss[e + 1]};
+            }
         }
     }
 }
 
-// ------------------------------------------------------------------ encode pass 2 (row statistics)
-// Per problem, rows: [A m][Acs br][Bt n][Bcs bc][grpA br][grpB bc].  Data and
-// checksum rows: sum x^2 w (other side's b == 1) or ||x||_4^2; grp rows: ||.||_2.
-__global__ __launch_bounds__(kT) void kb_rowstats(const BatchDesc *d, int count, int64_t total) {
-    __shared__ double sh[kT / kW];
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int p = find_problem<&BatchDesc::s_rows>(d, count, t);
-        const BatchDesc &D = d[p];
-        int64_t q = t - D.s_rows;
-        int kind;                 // 0 bf16 row, 1 float row, 2 double row (L2)
-        const void *row;
-        const double *w = nullptr;
-        double *out;
-        bool use_w;
-        if (q < D.m) { kind = 0; row = D.A + q * D.lda; use_w = D.bc == 1; w = D.grpB; out = D.qr + q; }
-        else if ((q -= D.m) < D.br) { kind = 1; row = D.acs + q * D.k; use_w = D.bc == 1; w = D.grpB; out = D.qr + D.m + q; }
-        else if ((q -= D.br) < D.n) { kind = 0; row = D.Bt + q * D.ldb; use_w = D.br == 1; w = D.grpA; out = D.qc + q; }
-        else if ((q -= D.n) < D.bc) { kind = 1; row = D.bcs + q * D.k; use_w = D.br == 1; w = D.grpA; out = D.qc + D.n + q; }
-        else if ((q -= D.bc) < D.br) { kind = 2; row = D.grpA + q * D.k; use_w = false; out = D.nv + q; }
-        else { q -= D.br; kind = 2; row = D.grpB + q * D.k; use_w = false; out = D.nw + q; }
-        double acc = 0.0;
-        for (int64_t l = threadIdx.x; l < D.k; l += kT) {
-            double x = kind == 0 ? bf(((const uint16_t *)row)[l])
-                                 : (kind == 1 ? (double)((const float *)row)[l] : ((const double *)row)[l]);
-            double x2 = x * x;
-            acc += kind == 2 ? x2 : (use_w ? x2 * w[l] : x2 * x2);
+// Pass 1 finish for the sides with several partitions: partials added in
+// partition order.
+__global__ __launch_bounds__(kT) void kb_encode2(const BatchDesc *__restrict__ d, int count, int64_t total) {
+    Walk<&BatchDesc::s_enc2, kT> wk(d, count, total);
+    for (int64_t b0 = wk.first; b0 < wk.last; b0 += kT) {
+        const BatchDesc &D = wk.at(b0);
+        int64_t q = b0 - D.s_enc2 + threadIdx.x;
+        const int64_t kv = D.k / 8;
+        const int64_t ua = D.PA > 1 ? D.br * kv : 0, ub = D.PB > 1 ? D.bc * kv : 0;
+        if (q >= ua + ub) continue;
+        const bool isA = q < ua;
+        if (!isA) q -= ua;
+        const int64_t b = isA ? D.br : D.bc, P = isA ? D.PA : D.PB;
+        const int64_t r = q / kv, l0 = (q - r * kv) * 8;
+        const G<double> *part = isA ? gp(D.partA) : gp(D.partB);
+        double s[8], ss[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[e] = ss[e] = 0.0;
+        for (int64_t p = 0; p < P; ++p) {
+            const G<double> *ps = part + ((2 * p) * b + r) * D.k + l0, *pq = part + ((2 * p + 1) * b + r) * D.k + l0;
+#pragma unroll
+            for (int e = 0; e < 8; e += 2) {
+                v2d_ a = *(const G<v2d_> *)(ps + e), c = *(const G<v2d_> *)(pq + e);
+                s[e] += a[0]; s[e + 1] += a[1];
+                ss[e] += c[0]; ss[e + 1] += c[1];
+            }
         }
-        for (int off = kW / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kW);
-        if (threadIdx.x % kW == 0) sh[threadIdx.x / kW] = acc;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (int e = 0; e < kT / kW; ++e) s += sh[e];
-            *out = (kind != 2 && use_w) ? s : sqrt(s);
+        enc_finish(isA ? gp(D.acs) : gp(D.bcs), isA ? gp(D.asp) : gp(D.bsp), isA ? gp(D.grpA) : gp(D.grpB), b, D.k, r, l0, s, ss);
+    }
+}
+
+// ------------------------------------------------------------------ row statistics
+// Segments per problem, each padded to kRowsPerIter rows: [A rows m, acs rows br]
+// [Bt rows n, bcs rows bc] [grpA rows br, grpB rows bc].  Data and checksum rows:
+// sum x^2 w (the other side's b == 1, w = its grp) or ||x||_4^2; grp rows: ||.||_2.
+// Sixteen lanes per row, 16 rows per wave and block iteration.
+__device__ inline int64_t pad_to(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+// One row's statistic by a group of 16 lanes (lane16 = lane % 16).
+template <typename T, int MODE>   // MODE 0: sum x^4 -> sqrt; 1: sum x^2 w; 2: sum x^2 -> sqrt
+__device__ inline double row_stat(const G<T> *row, int64_t k, const float *wsh, const G<double> *wg, int lane16) {
+    constexpr int V = gload<T>::N;
+    double acc = 0.0, v[V];
+    for (int64_t l0 = (int64_t)lane16 * V; l0 < k; l0 += 16 * V) {
+        gload<T>::load(row + l0, v);
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            double x2 = v[e] * v[e];
+            if (MODE == 1) acc += x2 * (wsh ? (double)wsh[l0 + e] : wg[l0 + e]);
+            else if (MODE == 0) acc += x2 * x2;
+            else acc += x2;
         }
-        __syncthreads();
+    }
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kW);
+    return MODE == 1 ? acc : sqrt(acc);
+}
+
+// 64 rows per block iteration: 16 per wave, 4 at a time (16 lanes per row).
+__global__ __launch_bounds__(kT) void kb_rowstats(const BatchDesc *__restrict__ d, int count, int64_t total) {
+    __shared__ float wsh[kWLdsMax];
+    const int lane = threadIdx.x % kW, wave = threadIdx.x / kW, lane16 = lane % 16;
+    Walk<&BatchDesc::s_rows, kRowsPerIter> wk(d, count, total);
+    const G<double> *staged = nullptr;                 // the weights wsh holds
+    for (int64_t b0 = wk.first; b0 < wk.last; b0 += kRowsPerIter) {
+        const BatchDesc &D = wk.at(b0);
+        const int64_t q0 = b0 - D.s_rows;
+        const int64_t pa = pad_to(D.m + D.br, kRowsPerIter), pb = pad_to(D.n + D.bc, kRowsPerIter);
+        const int seg = q0 < pa ? 0 : (q0 < pa + pb ? 1 : 2);
+        const int64_t r0 = seg == 0 ? q0 : (seg == 1 ? q0 - pa : q0 - pa - pb);
+        const bool use_w = seg == 0 ? D.bc == 1 : (seg == 1 ? D.br == 1 : false);
+        const G<double> *wg = seg == 0 ? gp(D.grpB) : gp(D.grpA);
+        const bool wlds = use_w && D.k <= kWLdsMax;
+        if (wlds && staged != wg) {
+            __syncthreads();                           // every wave is done with the previous weights
+            for (int64_t l = threadIdx.x; l < D.k; l += kT) wsh[l] = (float)wg[l];
+            __syncthreads();
+            staged = wg;
+        }
+        const float *ws = wlds ? wsh : nullptr;
+#pragma unroll
+        for (int e = 0; e < kRowsPerIter / 16; ++e) {
+            const int64_t r = r0 + wave * (kRowsPerIter / 4) + e * 4 + lane / 16;
+            double out = 0.0;
+            G<double> *dst = nullptr;
+            if (seg == 0) {
+                if (r < D.m) {
+                    const G<uint16_t> *row = gp(D.A) + r * D.lda;
+                    out = use_w ? row_stat<uint16_t, 1>(row, D.k, ws, wg, lane16)
+                                : row_stat<uint16_t, 0>(row, D.k, ws, wg, lane16);
+                    dst = gp(D.qr) + r;
+                } else if (r < D.m + D.br) {
+                    const G<float> *row = gp(D.acs) + (r - D.m) * D.k;
+                    out = use_w ? row_stat<float, 1>(row, D.k, ws, wg, lane16)
+                                : row_stat<float, 0>(row, D.k, ws, wg, lane16);
+                    dst = gp(D.qr) + r;
+                }
+            } else if (seg == 1) {
+                if (r < D.n) {
+                    const G<uint16_t> *row = gp(D.Bt) + r * D.ldb;
+                    out = use_w ? row_stat<uint16_t, 1>(row, D.k, ws, wg, lane16)
+                                : row_stat<uint16_t, 0>(row, D.k, ws, wg, lane16);
+                    dst = gp(D.qc) + r;
+                } else if (r < D.n + D.bc) {
+                    const G<float> *row = gp(D.bcs) + (r - D.n) * D.k;
+                    out = use_w ? row_stat<float, 1>(row, D.k, ws, wg, lane16)
+                                : row_stat<float, 0>(row, D.k, ws, wg, lane16);
+                    dst = gp(D.qc) + r;
+                }
+            } else {
+                if (r < D.br) {
+                    out = row_stat<double, 2>(gp(D.grpA) + r * D.k, D.k, nullptr, nullptr, lane16);
+                    dst = gp(D.nv) + r;
+                } else if (r < D.br + D.bc) {
+                    out = row_stat<double, 2>(gp(D.grpB) + (r - D.br) * D.k, D.k, nullptr, nullptr, lane16);
+                    dst = gp(D.nw) + (r - D.br);
+                }
+            }
+            if (dst && lane16 == 0) *dst = out;
+        }
     }
 }
 
 // ------------------------------------------------------------------ product
-template <class T>
-__global__ __launch_bounds__(T::THREADS, T::MINB) void kb_gemm(const BatchDesc *d, int count, int64_t total, int tile) {
-    __shared__ uint16_t lds[2 * T::BUF];
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int p = find_tile_problem(d, count, t, tile);
-        const BatchDesc &D = d[p];
-        int64_t q = t - D.s_tiles[tile];
-        int64_t tn_count = (D.n + T::BN - 1) / T::BN;
-        int64_t tm = q / tn_count, tn = q - tm * tn_count;
-        lowp_tile<T>(D.A, D.lda, D.Bt, D.ldb, D.C, D.ldc, D.m, D.n, D.k, 1.0f, tm * T::BM, tn * T::BN, lds);
+// Direct-to-LDS tile (global_load_lds_dwordx4: lane L of a wave writes 16 bytes
+// at base + 16 L), NS-stage ring of LDS slabs with NS - 1 slabs in flight.  A
+// slab holds SLAB bytes of k per row: CPR = SLAB / 16 chunks.  Chunk kc of
+// combined row rr (A rows first, then B rows) sits in slot
+// kc ^ ((rr / RP) % CPR), RP = 256 / SLAB rows per 64-bank period, so the 16
+// lanes of a quarter-wave reading chunk kc of 16 consecutive rows hit all 64
+// banks once.  Chunks past K load a zero chunk.
+template <int BM_, int BN_, int WM_, int WN_, int BPC_, int SLAB_, int NS_>
+struct DCfg {
+    static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, BPC = BPC_, SLAB = SLAB_, NS = NS_;
+    static constexpr int NW = WM * WN, THREADS = 64 * NW;
+    static constexpr int BK = SLAB / 2;                // bfloat16 per row and slab
+    static constexpr int CPR = SLAB / 16, RP = 256 / SLAB, RPI = 1024 / SLAB;   // rows per load instruction
+    static constexpr int KGS = SLAB / 64;              // 32-wide k groups per slab
+    static constexpr int HDR = 256;
+    static constexpr int STAGE = (BM + BN) * SLAB;
+    static constexpr int LDS = HDR + NS * STAGE;
+    static constexpr int LPW = (BM + BN) / RPI / NW;   // load instructions per wave and slab
+    static constexpr int TMW = BM / WM / 16, TNW = BN / WN / 16;
+    // s_waitcnt with vmcnt = the loads of NS - 2 later slabs (expcnt, lgkmcnt not waited)
+    static constexpr int VM = LPW * (NS - 2);
+    static constexpr int WAIT_AHEAD = (VM & 15) | ((VM >> 4) << 14) | (7 << 4) | (15 << 8);
+    static_assert(VM < 64, "vmcnt range");
+    static_assert((BM + BN) % (RPI * NW) == 0 && BM % RPI == 0, "load split");
+    static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "wave tile");
+    static_assert(NS >= 2 && LDS <= 160 * 1024 / BPC, "LDS");
+};
+typedef DCfg<256, 256, 4, 2, 1, 128, 2> Cfg0;    // 128 KB
+typedef DCfg<256, 128, 4, 2, 1, 128, 3> Cfg1;    // 144 KB
+typedef DCfg<128, 256, 2, 4, 1, 128, 3> Cfg2;    // 144 KB
+typedef DCfg<128, 128, 2, 2, 2, 64, 4> Cfg3;     // 64 KB, two blocks per CU
+
+__device__ __align__(16) uint32_t kZeroChunk[4];      // never written: the source of chunks past K
+
+// Tile queues: one per XCD (8), each a contiguous range [qb[x], qe[x]) of the
+// flattened tiles, so the tiles an XCD runs together are neighbours and share
+// operand rows in its L2.  A block takes tiles from its own XCD's queue
+// (blockIdx.x % 8), then from the others in turn.  tmap (byte offset from the
+// workspace) gives each tile's problem.
+constexpr int kXcds = 8;
+struct TileQueues {
+    int64_t qb[ABFT_BATCH_TILES][2][kXcds], qe[ABFT_BATCH_TILES][2][kXcds];
+    int64_t tmap[ABFT_BATCH_TILES][2];
+};
+constexpr int kCtrWords = kXcds + 1;                   // queue counters, then the exit counter
+constexpr size_t kCtlBytes = 2048;                     // counters (256 bytes) + TileQueues
+static_assert(256 + sizeof(TileQueues) <= kCtlBytes, "control block");
+
+__device__ inline int64_t next_tile(unsigned *ctr, const int64_t *qb, const int64_t *qe, int home, int &qi) {
+    while (qi < kXcds) {
+        const int x = (home + qi) % kXcds;
+        const int64_t len = qe[x] - qb[x];
+        if (len > 0) {
+            const unsigned v = atomicAdd(ctr + x, 1u);
+            if ((int64_t)v < len) return qb[x] + v;
+        }
+        ++qi;
     }
+    return -1;
 }
 
-// ------------------------------------------------------------------ carried blocks
-// Per problem, "many" rows: [Bt n -> C[m+r, j]] [Bcs bc -> C[m+r, n+c]] [A m -> C[i, n+c]];
-// the few rows are Acs (first two) or Bcs (last).  One wave per many row,
-// binary64 accumulation, few rows in passes of 8.
-__global__ __launch_bounds__(kT) void kb_sliver(const BatchDesc *d, int count, int64_t total) {
-    const int lane = threadIdx.x % kW;
-    const int64_t wave = ((int64_t)blockIdx.x * kT + threadIdx.x) / kW;
-    const int64_t nwaves = (int64_t)gridDim.x * kT / kW;
-    for (int64_t u = wave; u < total; u += nwaves) {
-        int p = find_problem<&BatchDesc::s_many>(d, count, u);
-        const BatchDesc &D = d[p];
-        int64_t q = u - D.s_many;
-        int seg;
-        if (q < D.n) seg = 0;
-        else if ((q -= D.n) < D.bc) seg = 1;
-        else { q -= D.bc; seg = 2; }
-        const uint16_t *xb = seg == 0 ? D.Bt + q * D.ldb : (seg == 2 ? D.A + q * D.lda : nullptr);
-        const float *xf = seg == 1 ? D.bcs + q * D.k : nullptr;
-        const float *Y = seg == 2 ? D.bcs : D.acs;
-        int64_t R = seg == 2 ? D.bc : D.br;
-        for (int64_t r0 = 0; r0 < R; r0 += 8) {
-            double acc[8];
+// A block-uniform value read from LDS, made visibly uniform (scalar registers)
+// so that the descriptor loads it indexes are scalar loads.
+__device__ inline int64_t uniform64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <class CF>
+__global__ __launch_bounds__(CF::THREADS, 1) void kb_gemm(const BatchDesc *__restrict__ d, int cfg, int plain,
+                                                          unsigned *ctr, const TileQueues *__restrict__ tq) {
+    // One LDS object only: with a second one the compiler cannot tell the
+    // fragment reads from the in-flight direct-to-LDS loads and waits for them.
+    __shared__ __attribute__((aligned(16))) uint8_t lds[CF::LDS];
+    int64_t &sh_next = *(int64_t *)lds;               // the header holds the next tile index
+    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+    const int wm = wave / CF::WN, wn = wave % CF::WN;
+    const int lr = lane % 16, lq = lane / 16;
+    const int home = blockIdx.x % kXcds;
+    const int64_t *qb = tq->qb[cfg][plain], *qe = tq->qe[cfg][plain];
+    const int *tmap = (const int *)((const char *)d + tq->tmap[cfg][plain]);
+    int qi = 0;                                        // thread 0: queues tried so far
+    if (tid == 0) sh_next = next_tile(ctr, qb, qe, home, qi);
+    __syncthreads();
+    int64_t t = uniform64(sh_next);
+    while (t >= 0) {
+        int64_t nx = -1;
+        const BatchDesc &D = d[tmap[t]];
+        const int64_t MV = plain ? D.m : D.MV, NV = plain ? D.n : D.NV, K = D.k;
+        const int64_t local = t - D.s_tiles[cfg][plain];
+        // grouped order: bands of GM tile rows, column by column within a band,
+        // so the tiles running together share operand rows in L2
+        const int64_t tm_count = (MV + CF::BM - 1) / CF::BM, tn_count = (NV + CF::BN - 1) / CF::BN;
+        constexpr int GM = 1024 / CF::BM;
+        const int64_t band = local / (GM * tn_count), in_band = local - band * (GM * tn_count);
+        const int64_t gsz = min((int64_t)GM, tm_count - band * GM);
+        const int64_t tm = band * GM + in_band % gsz, tn = in_band / gsz;
+        const int64_t row0 = tm * CF::BM, col0 = tn * CF::BN;
+
+        const uint16_t *src[CF::LPW];
 #pragma unroll
-            for (int s = 0; s < 8; ++s) acc[s] = 0.0;
-            for (int64_t k0 = (int64_t)lane * 8; k0 < D.k; k0 += 64 * 8) {
-                double xv[8], yv[8];
-                if (xb) vec16<uint16_t>::load(xb + k0, xv);
-                else { vec16<float>::load(xf + k0, xv); vec16<float>::load(xf + k0 + 4, xv + 4); }
+        for (int q = 0; q < CF::LPW; ++q) {
+            const int c = (wave * CF::LPW + q) * 64 + lane;
+            const int rr = c / CF::CPR, kc = (c % CF::CPR) ^ ((rr / CF::RP) % CF::CPR);
+            const uint16_t *base;
+            if (rr < CF::BM) {
+                const int64_t gr = min(row0 + rr, MV - 1);
+                base = (const uint16_t *)(gr < D.m ? gp(D.A) + gr * D.lda : gp(D.asp) + (gr - D.m) * K);
+            } else {
+                const int64_t gc = min(col0 + (rr - CF::BM), NV - 1);
+                base = (const uint16_t *)(gc < D.n ? gp(D.Bt) + gc * D.ldb : gp(D.bsp) + (gc - D.n) * K);
+            }
+            src[q] = base + kc * 8;
+        }
+        const void *zero = (const void *)kZeroChunk;
+        auto issue = [&](int stage, int64_t k0) {
+            uint8_t *dst = lds + CF::HDR + stage * CF::STAGE + wave * CF::LPW * 1024;
+            const bool full = k0 + CF::BK <= K;
 #pragma unroll
-                for (int s = 0; s < 8; ++s) {
-                    if (r0 + s < R) {
-                        vec16<float>::load(Y + (r0 + s) * D.k + k0, yv);
-                        vec16<float>::load(Y + (r0 + s) * D.k + k0 + 4, yv + 4);
+            for (int q = 0; q < CF::LPW; ++q) {
+                const int c = (wave * CF::LPW + q) * 64 + lane;
+                const int rr = c / CF::CPR, kc = (c % CF::CPR) ^ ((rr / CF::RP) % CF::CPR);
+                const void *g = (full || k0 + kc * 8 < K) ? (const void *)(src[q] + k0) : zero;
+                __builtin_amdgcn_global_load_lds(g, (void *)(dst + q * 1024), 16, 0, 0);
+            }
+        };
+
+        v4f acc[CF::TMW][CF::TNW];
 #pragma unroll
-                        for (int e = 0; e < 8; ++e) acc[s] = fma(xv[e], yv[e], acc[s]);
+        for (int a = 0; a < CF::TMW; ++a)
+#pragma unroll
+            for (int b = 0; b < CF::TNW; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+        const int arow = wm * (CF::BM / CF::WM) + lr, brow = CF::BM + wn * (CF::BN / CF::WN) + lr;
+
+        const int64_t nk = (K + CF::BK - 1) / CF::BK;
+#pragma unroll
+        for (int s = 0; s < CF::NS - 1; ++s)
+            if (s < nk) issue(s, (int64_t)s * CF::BK);
+        for (int64_t kt = 0; kt < nk; ++kt) {
+            // slab kt has landed once at most the loads of the NS - 2 later slabs are pending
+            if (kt + CF::NS - 2 < nk) __builtin_amdgcn_s_waitcnt(CF::WAIT_AHEAD);
+            else __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+            // and every wave is done with slab kt - 1.  A bare barrier: the
+            // fence of __syncthreads would wait for every slab in flight.
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            if (kt + CF::NS - 1 < nk) issue((int)((kt + CF::NS - 1) % CF::NS), (kt + CF::NS - 1) * CF::BK);
+            // the next tile, taken during the last slab (taken earlier, it would
+            // sit reserved while idle blocks find the queues empty)
+            if (kt == nk - 1 && tid == 0) nx = next_tile(ctr, qb, qe, home, qi);
+            const uint8_t *S = lds + CF::HDR + (int)(kt % CF::NS) * CF::STAGE;
+#pragma unroll
+            for (int g = 0; g < CF::KGS; ++g) {
+                const int kc = 4 * g + lq;
+                v4u fa[CF::TMW], fb[CF::TNW];
+#pragma unroll
+                for (int a = 0; a < CF::TMW; ++a) {
+                    const int r = arow + 16 * a;
+                    fa[a] = *(const v4u *)(S + r * CF::SLAB + ((kc ^ ((r / CF::RP) % CF::CPR)) << 4));
+                }
+#pragma unroll
+                for (int b = 0; b < CF::TNW; ++b) {
+                    const int r = brow + 16 * b;
+                    fb[b] = *(const v4u *)(S + r * CF::SLAB + ((kc ^ ((r / CF::RP) % CF::CPR)) << 4));
+                }
+#pragma unroll
+                for (int a = 0; a < CF::TMW; ++a)
+#pragma unroll
+                    for (int b = 0; b < CF::TNW; ++b) Bf16Ops::mfma(fa[a], fb[b], acc[a][b]);
+            }
+        }
+
+        // epilogue: data block -> C; rows >= m -> S1; columns >= n of data rows -> S2
+        if (row0 + CF::BM <= D.m && col0 + CF::BN <= D.n) {
+            // interior tile: every element is a data element of C
+            G<float> *Ct = gp(D.C) + (row0 + wm * (CF::BM / CF::WM) + 4 * lq) * D.ldc + col0 + wn * (CF::BN / CF::WN) + lr;
+#pragma unroll
+            for (int a = 0; a < CF::TMW; ++a)
+#pragma unroll
+                for (int b = 0; b < CF::TNW; ++b)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) Ct[(16 * a + v) * D.ldc + 16 * b] = acc[a][b][v];
+        } else {
+#pragma unroll
+        for (int a = 0; a < CF::TMW; ++a) {
+#pragma unroll
+            for (int b = 0; b < CF::TNW; ++b) {
+                const int64_t gc = col0 + wn * (CF::BN / CF::WN) + 16 * b + lr;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t gr = row0 + wm * (CF::BM / CF::WM) + 16 * a + 4 * lq + v;
+                    if (gr < MV && gc < NV) {
+                        if (gr < D.m) {
+                            if (gc < D.n) gp(D.C)[gr * D.ldc + gc] = acc[a][b][v];
+                            else gp(D.S2)[gr * 3 * D.bc + (gc - D.n)] = acc[a][b][v];
+                        } else {
+                            gp(D.S1)[(gr - D.m) * D.NV + gc] = acc[a][b][v];
+                        }
                     }
                 }
             }
+        }
+        }
+        __syncthreads();                                // every wave is done with the last slab's stage
+        if (tid == 0) sh_next = nx;
+        __syncthreads();
+        t = uniform64(sh_next);
+    }
+    // the last block out resets the queue counters for the next launch
+    if (tid == 0) {
+        __threadfence();
+        if (atomicAdd(ctr + kXcds, 1u) == gridDim.x - 1) {
+            for (int x = 0; x < kCtrWords; ++x) atomicExch(ctr + x, 0u);
+        }
+    }
+}
+
+// Carried checksums from the staged partial products.  Unit per problem:
+// C[m+q, j] (br x n), C[i, n+c] (m x bc), corner C[m+q, n+c] (br x bc).
+__global__ __launch_bounds__(kT) void kb_combine(const BatchDesc *__restrict__ d, int count, int64_t total) {
+    Walk<&BatchDesc::s_comb, kT> wk(d, count, total);
+    for (int64_t b0 = wk.first; b0 < wk.last; b0 += kT) {
+        const BatchDesc &D = wk.at(b0);
+        int64_t u = b0 - D.s_comb + threadIdx.x;
+        const int64_t br = D.br, bc = D.bc, n = D.n, m = D.m, NV = D.NV;
+        if (u < br * n) {
+            const int64_t q = u / n, j = u - q * n;
+            double s = 0.0;
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                double v = acc[s];
-                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-                if (lane == 0 && r0 + s < R) {
-                    int64_t rr = r0 + s;
-                    float *o = seg == 0 ? D.C + (D.m + rr) * D.ldc + q
-                                        : (seg == 1 ? D.C + (D.m + rr) * D.ldc + D.n + q : D.C + q * D.ldc + D.n + rr);
-                    *o = (float)v;
-                }
-            }
+            for (int s3 = 0; s3 < 3; ++s3) s += (double)gp(D.S1)[(s3 * br + q) * NV + j];
+            gp(D.C)[(m + q) * D.ldc + j] = (float)s;
+            continue;
+        }
+        u -= br * n;
+        if (u < m * bc) {
+            const int64_t i = u / bc, c = u - i * bc;
+            double s = 0.0;
+#pragma unroll
+            for (int t3 = 0; t3 < 3; ++t3) s += (double)gp(D.S2)[i * 3 * bc + t3 * bc + c];
+            gp(D.C)[i * D.ldc + n + c] = (float)s;
+            continue;
+        }
+        u -= m * bc;
+        if (u < br * bc) {
+            const int64_t q = u / bc, c = u - q * bc;
+            double s = 0.0;
+#pragma unroll
+            for (int s3 = 0; s3 < 3; ++s3)
+#pragma unroll
+                for (int t3 = 0; t3 < 3; ++t3) s += (double)gp(D.S1)[(s3 * br + q) * NV + n + t3 * bc + c];
+            gp(D.C)[(m + q) * D.ldc + n + c] = (float)s;
         }
     }
 }
 
 // ------------------------------------------------------------------ verify
-__global__ void kb_report_init(const BatchDesc *d, int count) {
+__global__ void kb_report_init(const BatchDesc *__restrict__ d, int count) {
     for (int p = blockIdx.x; p < count; p += gridDim.x) {
         uint64_t *w = (uint64_t *)d[p].rep;
         for (int q = threadIdx.x; q < (int)(sizeof(abft_report) / 8); q += blockDim.x) w[q] = 0;
     }
 }
 
-__device__ inline void bflag(abft_report *rep, bool col, int64_t a, int64_t b, double dd, double tau) {
+__device__ inline void bflag(G<abft_report> *rep, bool col, int64_t a, int64_t b, double dd, double tau) {
     if (!(fabs(dd) <= tau)) {
         unsigned long long *cnt = (unsigned long long *)(col ? &rep->n_flag_c : &rep->n_flag_r);
         unsigned long long q = atomicAdd(cnt, 1ull);
         if (q < ABFT_MAX_FLAGS) {
-            abft_flag *f = col ? &rep->flag_c[q] : &rep->flag_r[q];
+            G<abft_flag> *f = col ? &rep->flag_c[q] : &rep->flag_r[q];
             f->a = a; f->b = b; f->d = dd; f->tau = tau;
         }
         if (!isfinite(dd)) atomicAdd((unsigned long long *)&rep->n_nonfinite, 1ull);
     }
 }
 
-// Fold the max ratio of a wave into its problem's report: one atomic per wave
-// when every lane of the wave is on the same problem, else one per lane.
-__device__ inline void bfold(int p, const BatchDesc *d, double ratio, bool col) {
-    int p0 = __shfl(p, 0, kW);
-    bool same = __all(p == p0);
-    if (same) {
-        for (int off = kW / 2; off > 0; off >>= 1) ratio = fmax(ratio, __shfl_xor(ratio, off, kW));
-        if (threadIdx.x % kW != 0) return;
-    }
-    if (ratio > 0 && p >= 0) {
+// Max ratio of a wave (all lanes on one problem) into the problem's report.
+__device__ inline void bfold(G<abft_report> *rep, double ratio, bool col) {
+    for (int off = kW / 2; off > 0; off >>= 1) ratio = fmax(ratio, __shfl_xor(ratio, off, kW));
+    if (threadIdx.x % kW == 0 && ratio > 0) {
         unsigned long long bits;
         __builtin_memcpy(&bits, &ratio, 8);
-        atomicMax((unsigned long long *)(col ? &d[p].rep->max_ratio_c : &d[p].rep->max_ratio_r), bits);
+        atomicMax((unsigned long long *)(col ? &rep->max_ratio_c : &rep->max_ratio_r), bits);
     }
 }
 
 __device__ inline double btau(const BatchDesc &D, bool col, int64_t a, int64_t b) {
     if (D.mode != ABFT_TAU_STAT) return 0.0;
-    if (col) return sqrt(D.cc * (D.br == 1 ? D.qc[b] : D.nv[a] * D.qc[b]));
-    return sqrt(D.cr * (D.bc == 1 ? D.qr[a] : D.qr[a] * D.nw[b]));
+    if (col) return sqrt(D.cc * (D.br == 1 ? gp(D.qc)[b] : gp(D.nv)[a] * gp(D.qc)[b]));
+    return sqrt(D.cr * (D.bc == 1 ? gp(D.qr)[a] : gp(D.qr)[a] * gp(D.nw)[b]));
 }
 
-// Column relations: thread per (problem, r, j).
-__global__ __launch_bounds__(kT) void kb_vcol(const BatchDesc *d, int count, int64_t total) {
-    const int64_t nthreads = (int64_t)gridDim.x * kT;
-    for (int64_t t0 = (int64_t)blockIdx.x * kT; t0 < total; t0 += nthreads) {
-        int64_t t = t0 + threadIdx.x;
-        int p = -1;
+// Verification pass 1, one read of C: one wave per (residue r, strip of
+// kVStrip columns).  The wave walks the rows i = g*br + r, g < Gr, then m + r;
+// lane l keeps the column sums of columns l, l + 64, ... of the strip in
+// registers, and each row's strip is folded once to its bc residues, into
+// part[i][strip][c].  Column relation (r, j): the sum against C[m + r, j].
+constexpr int kVCols = 16;                      // columns per lane and strip
+constexpr int kVStrip = kVCols * kW;            // 1024
+__global__ __launch_bounds__(kT) void kb_verify1(const BatchDesc *__restrict__ d, int count, int64_t total) {
+    const int lane = threadIdx.x % kW, wave = threadIdx.x / kW;
+    Walk<&BatchDesc::s_vcol, kT / kW> wk(d, count, total);
+    for (int64_t b0 = wk.first; b0 < wk.last; b0 += kT / kW) {
+        const BatchDesc &D = wk.at(b0);
+        const int64_t u = b0 - D.s_vcol + wave;
+        const int64_t nst = (D.N + kVStrip - 1) / kVStrip;
+        if (u >= D.br * nst) continue;                // wave-uniform
+        const int64_t r = u / nst, st = u - r * nst, j0 = st * kVStrip + lane;
+        const int bc = (int)D.bc;
+        double cs[kVCols];
+#pragma unroll
+        for (int e = 0; e < kVCols; ++e) cs[e] = 0.0;
+        auto do_row = [&](int64_t i, bool carried) {
+            const G<float> *row = gp(D.C) + i * D.ldc;
+            double x[kVCols], y = 0.0;
+            float xf[kVCols];
+#pragma unroll
+            for (int e = 0; e < kVCols; ++e)           // clamped, unconditional loads: all in flight at once
+                xf[e] = row[min(j0 + (int64_t)e * kW, D.N - 1)];
+#pragma unroll
+            for (int e = 0; e < kVCols; ++e) x[e] = j0 + (int64_t)e * kW < D.N ? (double)xf[e] : 0.0;
+#pragma unroll
+            for (int e = 0; e < kVCols; ++e) {
+                const int64_t j = j0 + (int64_t)e * kW;
+                if (!carried) cs[e] += x[e];
+                if (j < D.n) y += x[e];
+            }
+            for (int off = kW / 2; off >= bc; off >>= 1) y += __shfl_xor(y, off, kW);
+            if (lane < bc) gp(D.vpart)[(i * nst + st) * bc + lane] = y;
+            return 0;
+        };
+        for (int64_t g = 0; g < D.Gr; ++g) do_row(g * D.br + r, false);
+        do_row(D.m + r, true);
+        // column relations of the strip
+        const G<float> *crow = gp(D.C) + (D.m + r) * D.ldc;
         double ratio = 0.0;
-        if (t < total) {
-            p = find_problem<&BatchDesc::s_vcol>(d, count, t);
-            const BatchDesc &D = d[p];
-            int64_t q = t - D.s_vcol, r = q / D.N, j = q - r * D.N;
+#pragma unroll
+        for (int e = 0; e < kVCols; ++e) {
+            const int64_t j = j0 + (int64_t)e * kW;
+            if (j < D.N) {
+                const double dd = cs[e] - (double)crow[j];
+                const double tau = btau(D, true, r, j);
+                bflag(gp(D.rep), true, r, j, dd, tau);
+                if (isfinite(dd) && tau > 0) ratio = fmax(ratio, fabs(dd) / tau);
+            }
+        }
+        bfold(gp(D.rep), ratio, true);
+    }
+}
+
+// Verification pass 2: row relation (i, c) from the partials of pass 1, added
+// in column order, against C[i, n + c].
+__global__ __launch_bounds__(kT) void kb_verify2(const BatchDesc *__restrict__ d, int count, int64_t total) {
+    Walk<&BatchDesc::s_vrow, kT> wk(d, count, total);
+    for (int64_t b0 = wk.first; b0 < wk.last; b0 += kT) {
+        const BatchDesc &D = wk.at(b0);
+        const int64_t u = b0 - D.s_vrow + threadIdx.x;
+        double ratio = 0.0;
+        if (u < D.M * D.bc) {
+            const int64_t i = u / D.bc, c = u - i * D.bc, nst = (D.N + kVStrip - 1) / kVStrip;
             double s = 0.0;
-            for (int64_t g = 0; g < D.Gr; ++g) s += (double)D.C[(g * D.br + r) * D.ldc + j];
-            double dd = s - (double)D.C[(D.m + r) * D.ldc + j];
-            double tau = btau(D, true, r, j);
-            bflag(D.rep, true, r, j, dd, tau);
+            for (int64_t w = 0; w < nst; ++w) s += gp(D.vpart)[(i * nst + w) * D.bc + c];
+            const double dd = s - (double)gp(D.C)[i * D.ldc + D.n + c];
+            const double tau = btau(D, false, i, c);
+            bflag(gp(D.rep), false, i, c, dd, tau);
             if (isfinite(dd) && tau > 0) ratio = fabs(dd) / tau;
         }
-        bfold(p, d, ratio, true);
+        bfold(gp(D.rep), ratio, false);
     }
 }
 
-// Row relations: one block per (problem, row); bc divides 256.
-__global__ __launch_bounds__(kT) void kb_vrow(const BatchDesc *d, int count, int64_t total) {
-    __shared__ double sh[kT];
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int p = find_problem<&BatchDesc::s_vrow>(d, count, t);
-        const BatchDesc &D = d[p];
-        int64_t i = t - D.s_vrow;
-        const float *row = D.C + i * D.ldc;
-        double s = 0.0;
-        for (int64_t j = threadIdx.x; j < D.n; j += kT) s += (double)row[j];
-        sh[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = kT / 2; w >= D.bc; w >>= 1) {
-            if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-            __syncthreads();
-        }
-        double ratio = 0.0;
-        if (threadIdx.x < D.bc) {
-            int64_t c = threadIdx.x;
-            double dd = sh[c] - (double)row[D.n + c];
-            double tau = btau(D, false, i, c);
-            bflag(D.rep, false, i, c, dd, tau);
-            if (isfinite(dd) && tau > 0) ratio = fabs(dd) / tau;
-        }
-        if (threadIdx.x < kW) bfold(p, d, ratio, false);
-        __syncthreads();
-    }
-}
-
-unsigned grid_of(int64_t work, int64_t per) {
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + per - 1) / per, 65536));
-}
-
-// Batch workspace layout: [descriptors][reports][per-problem arrays...]
+// ------------------------------------------------------------------ host side
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+int64_t pad_h(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
-struct PerProblemBytes {
-    size_t acs, bcs, grpA, grpB, qr, qc, nv, nw;
-    size_t total() const { return acs + bcs + grpA + grpB + qr + qc + nv + nw; }
+struct Parts {
+    int64_t PA, PB;
+    size_t acs, bcs, asp, bsp, grpA, grpB, partA, partB, S1, S2, qr, qc, nv, nw, vpart;
+    size_t total() const {
+        return acs + bcs + asp + bsp + grpA + grpB + partA + partB + S1 + S2 + qr + qc + nv + nw + vpart;
+    }
 };
-PerProblemBytes per_problem_bytes(const abft_problem &q) {
-    PerProblemBytes b;
+Parts parts_of(const abft_problem &q) {
+    Parts b;
+    const int64_t Gr = q.m / q.br, Gc = q.n / q.bc;
+    b.PA = std::min<int64_t>(Gr, (32 + q.br - 1) / q.br);
+    b.PB = std::min<int64_t>(Gc, (32 + q.bc - 1) / q.bc);
     b.acs = align256(sizeof(float) * q.br * q.k);
     b.bcs = align256(sizeof(float) * q.bc * q.k);
+    b.asp = align256(sizeof(uint16_t) * 3 * q.br * q.k);
+    b.bsp = align256(sizeof(uint16_t) * 3 * q.bc * q.k);
     b.grpA = align256(sizeof(double) * q.br * q.k);
     b.grpB = align256(sizeof(double) * q.bc * q.k);
+    b.partA = b.PA > 1 ? align256(sizeof(double) * 2 * b.PA * q.br * q.k) : 0;
+    b.partB = b.PB > 1 ? align256(sizeof(double) * 2 * b.PB * q.bc * q.k) : 0;
+    b.S1 = align256(sizeof(float) * 3 * q.br * (q.n + 3 * q.bc));
+    b.S2 = align256(sizeof(float) * q.m * 3 * q.bc);
     b.qr = align256(sizeof(double) * (q.m + q.br));
     b.qc = align256(sizeof(double) * (q.n + q.bc));
     b.nv = align256(sizeof(double) * q.br);
     b.nw = align256(sizeof(double) * q.bc);
+    b.vpart = align256(sizeof(double) * (q.m + q.br) * ((q.n + q.bc + kVStrip - 1) / kVStrip) * q.bc);
     return b;
 }
 
@@ -342,21 +775,46 @@ int check_batch_problem(const abft_problem &q) {
     if (q.m < 1 || q.n < 1 || q.k < 8 || q.br < 1 || q.bc < 1 || q.m % q.br || q.n % q.bc) return ABFT_E_ARG;
     if (q.k % 8 || q.lda < q.k || q.ldb < q.k || q.lda % 8 || q.ldb % 8) return ABFT_E_ARG;
     if (q.ldc < q.n + q.bc) return ABFT_E_ARG;
-    if (256 % q.bc) return ABFT_E_UNSUPPORTED;     // row verification: one block per row
+    if (q.bc > 64 || 64 % q.bc) return ABFT_E_UNSUPPORTED;   // row verification folds lanes to bc residues
     return ABFT_OK;
 }
 
+size_t header_bytes(int count) {
+    return align256(sizeof(BatchDesc) * count) + kCtlBytes + align256(sizeof(abft_report) * count);
+}
+
+constexpr int kTileBM[ABFT_BATCH_TILES] = {Cfg0::BM, Cfg1::BM, Cfg2::BM, Cfg3::BM};
+constexpr int kTileBN[ABFT_BATCH_TILES] = {Cfg0::BN, Cfg1::BN, Cfg2::BN, Cfg3::BN};
+
 }  // namespace
 
+// Tiles of one problem for tile shape c: [0] protected (virtual rows and
+// columns), [1] data block only.
+static int64_t tiles_of(const abft_problem &q, int c, int plain) {
+    const int64_t R = plain ? q.m : q.m + 3 * q.br, Cn = plain ? q.n : q.n + 3 * q.bc;
+    return ((R + kTileBM[c] - 1) / kTileBM[c]) * ((Cn + kTileBN[c] - 1) / kTileBN[c]);
+}
+static size_t tmap_bytes(const abft_problem *probs, int count) {
+    size_t s = 0;
+    for (int c = 0; c < ABFT_BATCH_TILES; ++c)
+        for (int pl = 0; pl < 2; ++pl) {
+            int64_t n = 0;
+            for (int p = 0; p < count; ++p) n += tiles_of(probs[p], c, pl);
+            s += align256(sizeof(int) * n);
+        }
+    return s;
+}
+
 size_t batch_workspace_size(const abft_problem *probs, int count) {
-    size_t s = align256(sizeof(BatchDesc) * count) + align256(sizeof(abft_report) * count);
-    for (int p = 0; p < count; ++p) s += per_problem_bytes(probs[p]).total();
+    size_t s = header_bytes(count) + tmap_bytes(probs, count);
+    for (int p = 0; p < count; ++p) s += parts_of(probs[p]).total();
     return s;
 }
 
 int batch_setup(const abft_problem *probs, const abft_batch_item *items, int count, void *bws, size_t bytes,
                 abft_batch_plan *plan) {
     if (count < 1 || !probs || !items || !bws || !plan) return ABFT_E_ARG;
+    if ((uintptr_t)bws & 255u) return ABFT_E_ARG;
     for (int p = 0; p < count; ++p) {
         int st = check_batch_problem(probs[p]);
         if (st) return st;
@@ -364,90 +822,171 @@ int batch_setup(const abft_problem *probs, const abft_batch_item *items, int cou
         if (((uintptr_t)items[p].A_f | (uintptr_t)items[p].B_f) & 15u) return ABFT_E_ARG;
         if ((items[p].A32 && ((uintptr_t)items[p].A32 & 15u)) || (items[p].Bt32 && ((uintptr_t)items[p].Bt32 & 15u)))
             return ABFT_E_ARG;
+        if (((uintptr_t)items[p].C_f & 3u)) return ABFT_E_ARG;
     }
     size_t need = batch_workspace_size(probs, count);
     if (bytes < need) return ABFT_E_WORKSPACE;
+    // Problems in order of decreasing k; the flattened tiles are cut into 8
+    // contiguous queues of equal work (tiles x k), one per XCD, so each XCD
+    // runs a compact run of neighbouring tiles.
+    std::vector<int> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a].k > probs[b].k; });
+
     char *base = (char *)bws;
-    size_t off = align256(sizeof(BatchDesc) * count);
-    abft_report *reps = (abft_report *)(base + off);
-    off += align256(sizeof(abft_report) * count);
+    const size_t off_ctr = align256(sizeof(BatchDesc) * count);
+    abft_report *reps = (abft_report *)(base + off_ctr + kCtlBytes);
+    TileQueues tq;
+    for (int c = 0; c < ABFT_BATCH_TILES; ++c)
+        for (int pl = 0; pl < 2; ++pl)
+            for (int x = 0; x < kXcds; ++x) tq.qb[c][pl][x] = tq.qe[c][pl][x] = 0;
+    // per-tile problem maps, then the per-problem arrays
+    size_t off = header_bytes(count);
+    std::vector<int> tmaps[ABFT_BATCH_TILES][2];
+    size_t tmap_off[ABFT_BATCH_TILES][2];
+    for (int c = 0; c < ABFT_BATCH_TILES; ++c)
+        for (int pl = 0; pl < 2; ++pl) {
+            int64_t n = 0;
+            for (int p = 0; p < count; ++p) n += tiles_of(probs[p], c, pl);
+            if (n >= (int64_t)INT32_MAX) return ABFT_E_ARG;
+            tmaps[c][pl].reserve(n);
+            tmap_off[c][pl] = off;
+            tq.tmap[c][pl] = (int64_t)off;
+            off += align256(sizeof(int) * n);
+        }
     std::vector<BatchDesc> h(count);
-    int64_t tiles0 = 0, tiles1 = 0, quant = 0, enc = 0, rows = 0, many = 0, vcol = 0, vrow = 0;
-    for (int p = 0; p < count; ++p) {
+    int64_t tiles[ABFT_BATCH_TILES][2] = {};
+    int64_t w[8] = {};
+    for (int s = 0; s < count; ++s) {
+        const int p = order[s];
         const abft_problem &q = probs[p];
-        BatchDesc &D = h[p];
+        BatchDesc &D = h[s];
         D.m = q.m; D.n = q.n; D.k = q.k; D.br = q.br; D.bc = q.bc;
         D.lda = q.lda; D.ldb = q.ldb; D.ldc = q.ldc;
         D.M = q.m + q.br; D.N = q.n + q.bc; D.Gr = q.m / q.br; D.Gc = q.n / q.bc;
+        D.MV = q.m + 3 * q.br; D.NV = q.n + 3 * q.bc;
         D.A32 = items[p].A32; D.Bt32 = items[p].Bt32;
         D.A = (uint16_t *)items[p].A_f; D.Bt = (uint16_t *)items[p].B_f; D.C = (float *)items[p].C_f;
-        PerProblemBytes b = per_problem_bytes(q);
+        Parts b = parts_of(q);
+        D.PA = b.PA; D.PB = b.PB;
         D.acs = (float *)(base + off); off += b.acs;
         D.bcs = (float *)(base + off); off += b.bcs;
+        D.asp = (uint16_t *)(base + off); off += b.asp;
+        D.bsp = (uint16_t *)(base + off); off += b.bsp;
         D.grpA = (double *)(base + off); off += b.grpA;
         D.grpB = (double *)(base + off); off += b.grpB;
+        D.partA = (double *)(base + off); off += b.partA;
+        D.partB = (double *)(base + off); off += b.partB;
+        D.S1 = (float *)(base + off); off += b.S1;
+        D.S2 = (float *)(base + off); off += b.S2;
         D.qr = (double *)(base + off); off += b.qr;
         D.qc = (double *)(base + off); off += b.qc;
         D.nv = (double *)(base + off); off += b.nv;
         D.nw = (double *)(base + off); off += b.nw;
+        D.vpart = (double *)(base + off); off += b.vpart;
         D.rep = reps + p;
+        D.orig = p;
         TauCoef tc = tau_coef(&q);
         D.cc = tc.cc; D.cr = tc.cr; D.mode = q.tau_mode;
-        D.s_tiles[0] = tiles0; tiles0 += ((q.m + 127) / 128) * ((q.n + 127) / 128);
-        D.s_tiles[1] = tiles1; tiles1 += ((q.m + 63) / 64) * ((q.n + 63) / 64);
-        D.s_quant = quant; quant += (q.m + q.n) * (q.k / 8);
-        D.s_enc = enc; enc += (q.br + q.bc) * (q.k / 8);
-        D.s_rows = rows; rows += (q.m + q.br) + (q.n + q.bc) + q.br + q.bc;
-        D.s_many = many; many += q.n + q.bc + q.m;
-        D.s_vcol = vcol; vcol += q.br * (q.n + q.bc);
-        D.s_vrow = vrow; vrow += q.m + q.br;
+        for (int c = 0; c < ABFT_BATCH_TILES; ++c) {
+            for (int pl = 0; pl < 2; ++pl) {
+                D.s_tiles[c][pl] = tiles[c][pl];
+                const int64_t nt = tiles_of(q, c, pl);
+                tmaps[c][pl].insert(tmaps[c][pl].end(), (size_t)nt, s);
+                tiles[c][pl] += nt;
+            }
+        }
+        const int64_t kv = q.k / 8;
+        D.s_quant = w[W_QUANT]; w[W_QUANT] += pad_h((q.m + q.n) * kv, kT);
+        D.s_enc1 = w[W_ENC1]; w[W_ENC1] += pad_h((b.PA * q.br + b.PB * q.bc) * kv, kT);
+        D.s_enc2 = w[W_ENC2]; w[W_ENC2] += pad_h(((b.PA > 1 ? q.br : 0) + (b.PB > 1 ? q.bc : 0)) * kv, kT);
+        D.s_rows = w[W_ROWS];
+        w[W_ROWS] += pad_h(q.m + q.br, kRowsPerIter) + pad_h(q.n + q.bc, kRowsPerIter) +
+                     pad_h(q.br + q.bc, kRowsPerIter);
+        D.s_comb = w[W_COMB]; w[W_COMB] += pad_h(q.br * q.n + q.m * q.bc + q.br * q.bc, kT);
+        D.s_vcol = w[W_VCOL]; w[W_VCOL] += pad_h(q.br * ((q.n + q.bc + kVStrip - 1) / kVStrip), kT / kW);
+        D.s_vrow = w[W_VROW]; w[W_VROW] += pad_h((q.m + q.br) * q.bc, kT);
     }
+    // queue cuts: equal shares of the total tile work
+    for (int c = 0; c < ABFT_BATCH_TILES; ++c)
+        for (int pl = 0; pl < 2; ++pl) {
+            const std::vector<int> &tm = tmaps[c][pl];
+            double total = 0.0;
+            for (int v : tm) total += (double)h[v].k;
+            double acc = 0.0;
+            int64_t t = 0;
+            for (int x = 0; x < kXcds; ++x) {
+                tq.qb[c][pl][x] = t;
+                const double goal = total * (x + 1) / kXcds;
+                while (t < (int64_t)tm.size() && (x == kXcds - 1 || acc + 0.5 * (double)h[tm[t]].k <= goal))
+                    acc += (double)h[tm[t++]].k;
+                tq.qe[c][pl][x] = t;
+            }
+        }
     ABFT_HIP(hipMemcpy(bws, h.data(), sizeof(BatchDesc) * count, hipMemcpyHostToDevice));
+    for (int c = 0; c < ABFT_BATCH_TILES; ++c)
+        for (int pl = 0; pl < 2; ++pl)
+            ABFT_HIP(hipMemcpy(base + tmap_off[c][pl], tmaps[c][pl].data(), sizeof(int) * tmaps[c][pl].size(),
+                               hipMemcpyHostToDevice));
+    std::vector<char> ctl(kCtlBytes, 0);                // zero counters, then the queue table
+    std::memcpy(ctl.data() + 256, &tq, sizeof(tq));
+    ABFT_HIP(hipMemcpy(base + off_ctr, ctl.data(), kCtlBytes, hipMemcpyHostToDevice));
     plan->bws = bws;
     plan->count = count;
-    plan->dtype = probs[0].dtype;
-    plan->n_tiles[0] = tiles0;
-    plan->n_tiles[1] = tiles1;
-    plan->n_quant = quant;
-    plan->n_enc = enc;
-    plan->n_rows = rows;
-    plan->n_many = many;
-    plan->n_vcol = vcol;
-    plan->n_vrow = vrow;
+    plan->dtype = ABFT_BF16;
+    for (int c = 0; c < ABFT_BATCH_TILES; ++c) {
+        plan->n_tiles[c][0] = tiles[c][0];
+        plan->n_tiles[c][1] = tiles[c][1];
+    }
+    for (int e = 0; e < 8; ++e) plan->n_work[e] = w[e];
     plan->bytes = need;
     return ABFT_OK;
 }
 
 static const BatchDesc *descs(const abft_batch_plan *pl) { return (const BatchDesc *)pl->bws; }
+static unsigned *counters(const abft_batch_plan *pl) {
+    return (unsigned *)((char *)pl->bws + align256(sizeof(BatchDesc) * pl->count));
+}
+static unsigned blocks_for(int64_t work, int64_t per) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + per - 1) / per, 16384));
+}
 
 int batch_quantize(const abft_batch_plan *pl, hipStream_t s) {
-    kb_quantize<<<grid_of(pl->n_quant, kT), kT, 0, s>>>(descs(pl), pl->count, pl->n_quant);
+    const int64_t n = pl->n_work[W_QUANT];
+    kb_quantize<<<blocks_for(n, kT), kT, 0, s>>>(descs(pl), pl->count, n);
     ABFT_LAUNCHED();
     return ABFT_OK;
 }
 
 int batch_encode(const abft_batch_plan *pl, hipStream_t s) {
-    kb_encode<<<grid_of(pl->n_enc, kT), kT, 0, s>>>(descs(pl), pl->count, pl->n_enc);
-    kb_rowstats<<<(unsigned)std::min<int64_t>(pl->n_rows, 65536), kT, 0, s>>>(descs(pl), pl->count, pl->n_rows);
+    const int64_t n1 = pl->n_work[W_ENC1], n2 = pl->n_work[W_ENC2], nr = pl->n_work[W_ROWS];
+    kb_encode1<<<blocks_for(n1, kT), kT, 0, s>>>(descs(pl), pl->count, n1);
+    if (n2 > 0) kb_encode2<<<blocks_for(n2, kT), kT, 0, s>>>(descs(pl), pl->count, n2);
+    kb_rowstats<<<blocks_for(nr, kRowsPerIter), kT, 0, s>>>(descs(pl), pl->count, nr);
     ABFT_LAUNCHED();
     return ABFT_OK;
 }
 
-using BatchTile0 = LowpTile<Bf16Ops, 128, 128, 64, 2, 2, 8, 2>;
-using BatchTile1 = LowpTile<Bf16Ops, 64, 64, 64, 2, 2, 8, 4>;
+template <class CF>
+static void launch_cfg(const abft_batch_plan *pl, int cfg, int plain, hipStream_t s) {
+    // a whole number of blocks per XCD (256 CUs, BPC blocks each)
+    const TileQueues *tq = (const TileQueues *)((const char *)counters(pl) + 256);
+    kb_gemm<CF><<<256 * CF::BPC, CF::THREADS, 0, s>>>(descs(pl), cfg, plain, counters(pl), tq);
+}
 
 int batch_gemm(const abft_batch_plan *pl, int tile, uint32_t flags, hipStream_t s) {
-    if (tile != 0 && tile != 1) return ABFT_E_ARG;
-    const int64_t tiles = pl->n_tiles[tile];
-    if (tile == 0)
-        kb_gemm<BatchTile0><<<(unsigned)std::min<int64_t>(tiles, 256 * 2), BatchTile0::THREADS, 0, s>>>(
-            descs(pl), pl->count, tiles, 0);
-    else
-        kb_gemm<BatchTile1><<<(unsigned)std::min<int64_t>(tiles, 256 * 4), BatchTile1::THREADS, 0, s>>>(
-            descs(pl), pl->count, tiles, 1);
+    if (tile < 0 || tile >= ABFT_BATCH_TILES) return ABFT_E_ARG;
+    const int plain = (flags & ABFT_PLAIN) ? 1 : 0;
+    switch (tile) {
+    case 0: launch_cfg<Cfg0>(pl, 0, plain, s); break;
+    case 1: launch_cfg<Cfg1>(pl, 1, plain, s); break;
+    case 2: launch_cfg<Cfg2>(pl, 2, plain, s); break;
+    default: launch_cfg<Cfg3>(pl, 3, plain, s); break;
+    }
     ABFT_LAUNCHED();
-    if (!(flags & ABFT_PLAIN)) {
-        kb_sliver<<<grid_of(pl->n_many, kT / kW), kT, 0, s>>>(descs(pl), pl->count, pl->n_many);
+    if (!plain) {
+        const int64_t n = pl->n_work[W_COMB];
+        kb_combine<<<blocks_for(n, kT), kT, 0, s>>>(descs(pl), pl->count, n);
         ABFT_LAUNCHED();
     }
     return ABFT_OK;
@@ -455,36 +994,38 @@ int batch_gemm(const abft_batch_plan *pl, int tile, uint32_t flags, hipStream_t 
 
 int batch_verify(const abft_batch_plan *pl, hipStream_t s) {
     kb_report_init<<<(unsigned)std::min(pl->count, 1024), 64, 0, s>>>(descs(pl), pl->count);
-    kb_vcol<<<grid_of(pl->n_vcol, kT), kT, 0, s>>>(descs(pl), pl->count, pl->n_vcol);
-    kb_vrow<<<(unsigned)std::min<int64_t>(pl->n_vrow, 65536), kT, 0, s>>>(descs(pl), pl->count, pl->n_vrow);
+    const int64_t nc = pl->n_work[W_VCOL], nr = pl->n_work[W_VROW];
+    kb_verify1<<<blocks_for(nc, kT / kW), kT, 0, s>>>(descs(pl), pl->count, nc);
+    kb_verify2<<<blocks_for(nr, kT), kT, 0, s>>>(descs(pl), pl->count, nr);
     ABFT_LAUNCHED();
     return ABFT_OK;
 }
 
 int batch_reports(const abft_batch_plan *pl, abft_report *host, hipStream_t s) {
-    const char *base = (const char *)pl->bws + align256(sizeof(BatchDesc) * pl->count);
+    const char *base = (const char *)pl->bws + align256(sizeof(BatchDesc) * pl->count) + kCtlBytes;
     ABFT_HIP(hipMemcpyAsync(host, base, sizeof(abft_report) * pl->count, hipMemcpyDeviceToHost, s));
     return ABFT_OK;
 }
 
 int batch_tune(const abft_batch_plan *pl, int *best, hipStream_t s) {
-    float t[2];
+    float t[ABFT_BATCH_TILES];
     hipEvent_t e0, e1;
     ABFT_HIP(hipEventCreate(&e0));
     ABFT_HIP(hipEventCreate(&e1));
-    for (int tile = 0; tile < 2; ++tile) {
-        int st = batch_gemm(pl, tile, ABFT_PLAIN, s);          // warm-up
-        if (st) return st;
-        ABFT_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < 3; ++r)
-            if ((st = batch_gemm(pl, tile, ABFT_PLAIN, s))) return st;
-        ABFT_HIP(hipEventRecord(e1, s));
-        ABFT_HIP(hipEventSynchronize(e1));
-        ABFT_HIP(hipEventElapsedTime(&t[tile], e0, e1));
+    int st = ABFT_OK;
+    for (int tile = 0; tile < ABFT_BATCH_TILES && st == ABFT_OK; ++tile) {
+        if ((st = batch_gemm(pl, tile, 0, s))) break;           // warm-up
+        if (hipEventRecord(e0, s) != hipSuccess) { st = ABFT_E_HIP; break; }
+        for (int r = 0; r < 3 && st == ABFT_OK; ++r) st = batch_gemm(pl, tile, 0, s);
+        if (st) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t[tile], e0, e1) != hipSuccess)
+            st = ABFT_E_HIP;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    *best = t[1] < t[0] ? 1 : 0;
+    if (st) return st;
+    *best = (int)(std::min_element(t, t + ABFT_BATCH_TILES) - t);
     return ABFT_OK;
 }
 

@@ -91,7 +91,7 @@ def test_batch_quantize_bit_exact(case):
         assert np.array_equal(b, np.ascontiguousarray(r["Bq"].T))
 
 
-@pytest.mark.parametrize("tile", [0, 1])
+@pytest.mark.parametrize("tile", range(abft.ABFT_BATCH_TILES))
 def test_batch_product_and_clean_verify(case, tile):
     note(f"batch pass tile={tile}")
     reps = case.run(tile)
@@ -106,12 +106,27 @@ def test_batch_product_and_clean_verify(case, tile):
 def test_batch_tiles_agree_and_tune(case):
     case.run(0)
     C0 = [c.clone() for c in case.B.C]
-    case.run(1)
-    torch.cuda.synchronize()
-    for q in range(len(C0)):
-        assert torch.equal(C0[q], case.B.C[q]), q
+    for tile in range(1, abft.ABFT_BATCH_TILES):
+        note(f"tile {tile} vs tile 0")
+        case.run(tile)
+        torch.cuda.synchronize()
+        for q in range(len(C0)):
+            assert torch.equal(C0[q], case.B.C[q]), (tile, q)
     best = abft.batch_tune(case.B.plan)
-    assert best in (0, 1)
+    assert 0 <= best < abft.ABFT_BATCH_TILES
+
+
+def test_batch_plain_product_is_data_block(case):
+    case.run(0)
+    torch.cuda.synchronize()
+    C0 = [c[:m, :n].clone() for c, (m, n, k, br, bc) in zip(case.B.C, case.shapes)]
+    for c in case.B.Cbuf:
+        c.fill_(float("nan"))
+    abft.batch_gemm(case.B.plan, 3, abft.ABFT_PLAIN)
+    torch.cuda.synchronize()
+    for q, (m, n, k, br, bc) in enumerate(case.shapes):
+        assert torch.equal(case.B.C[q][:m, :n], C0[q]), q
+        assert torch.isnan(case.B.C[q][m:, :]).all() and torch.isnan(case.B.C[q][:, n:]).all()
 
 
 def test_batch_flips_match_oracle(case, orc):
