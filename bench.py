@@ -148,7 +148,7 @@ def run_batched(args):
     side.wait_stream(stream)
     graphs = {}
     with torch.cuda.stream(side):
-        for name, fn in (("pre", lambda: (abft.batch_quantize(plan), abft.batch_encode(plan))),
+        for name, fn in (("pre", lambda: abft.batch_quantize_encode(plan)),
                          ("gemm", lambda: abft.batch_gemm(plan, tile)),
                          ("verify", lambda: abft.batch_verify(plan))):
             g = torch.cuda.CUDAGraph()

@@ -314,6 +314,10 @@ int abft_batch_setup(const abft_problem *probs, const abft_batch_item *items, in
  * All return ABFT_E_ARG on a NULL plan or a bad tile. */
 int abft_batch_quantize(const abft_batch_plan *plan, void *stream);
 int abft_batch_encode(const abft_batch_plan *plan, void *stream);
+/* abft_batch_quantize then abft_batch_encode in one read of the binary32
+ * operands (same results, bit for bit); items without A32 / Bt32 are encoded
+ * from their bfloat16 operands as they are. */
+int abft_batch_quantize_encode(const abft_batch_plan *plan, void *stream);
 int abft_batch_gemm(const abft_batch_plan *plan, int tile, uint32_t flags, void *stream);
 int abft_batch_tune(const abft_batch_plan *plan, int *best_tile, void *stream);
 int abft_batch_verify(const abft_batch_plan *plan, void *stream);

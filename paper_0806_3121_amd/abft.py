@@ -108,6 +108,7 @@ def lib():
                                            _P(abft_batch_plan)]),
             "abft_batch_quantize": (C.c_int, [_P(abft_batch_plan), _V]),
             "abft_batch_encode": (C.c_int, [_P(abft_batch_plan), _V]),
+            "abft_batch_quantize_encode": (C.c_int, [_P(abft_batch_plan), _V]),
             "abft_batch_gemm": (C.c_int, [_P(abft_batch_plan), C.c_int, C.c_uint32, _V]),
             "abft_batch_tune": (C.c_int, [_P(abft_batch_plan), _P(C.c_int), _V]),
             "abft_batch_verify": (C.c_int, [_P(abft_batch_plan), _V]),
@@ -247,6 +248,10 @@ def batch_quantize(plan, stream=None):
 
 def batch_encode(plan, stream=None):
     return _check("abft_batch_encode", lib().abft_batch_encode(C.byref(plan), _stream(stream)))
+
+
+def batch_quantize_encode(plan, stream=None):
+    return _check("abft_batch_quantize_encode", lib().abft_batch_quantize_encode(C.byref(plan), _stream(stream)))
 
 
 def batch_gemm(plan, tile=0, flags=0, stream=None):

@@ -202,7 +202,11 @@ __device__ inline void enc_finish(G<float> *cs, G<uint16_t> *sp, G<double> *grp,
 
 // Pass 1, unit = (side, partition, residue r, 8 columns): sums over the
 // partition's groups g of X[g*b + r, l] and of its square; final values when
-// the side has one partition, else partials.
+// the side has one partition, else partials.  QUANT: the rows are read in
+// binary32 (for the items that have them), rounded to bfloat16 and stored,
+// and the sums are taken of the rounded values (quantize and pass 1 in one
+// read of the binary32 operand).
+template <bool QUANT>
 __global__ __launch_bounds__(kT) void kb_encode1(const BatchDesc *__restrict__ d, int count, int64_t total) {
     Walk<&BatchDesc::s_enc1, kT> wk(d, count, total);
     for (int64_t b0 = wk.first; b0 < wk.last; b0 += kT) {
@@ -216,15 +220,38 @@ __global__ __launch_bounds__(kT) void kb_encode1(const BatchDesc *__restrict__ d
         const int64_t ld = isA ? D.lda : D.ldb;
         const int64_t p = q / (b * kv), rem = q - p * (b * kv), r = rem / kv, l0 = (rem - r * kv) * 8;
         const int64_t ch = (NG + P - 1) / P, g0 = p * ch, g1 = min(NG, g0 + ch);
-        const G<uint16_t> *X = (isA ? gp(D.A) : gp(D.Bt)) + r * ld + l0;
+        G<uint16_t> *X = (isA ? gp(D.A) : gp(D.Bt)) + r * ld + l0;
         double s[8], ss[8], v[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) s[e] = ss[e] = 0.0;
+        const G<const float> *X32 = QUANT ? (isA ? gp(D.A32) : gp(D.Bt32)) : nullptr;
+        if (X32) {
+            X32 += r * ld + l0;
 #pragma unroll 4
-        for (int64_t g = g0; g < g1; ++g) {
-            gload<uint16_t>::load(X + g * b * ld, v);
+            for (int64_t g = g0; g < g1; ++g) {
+                const int64_t o = g * b * ld;
+                const v4f_ x0 = *(const G<v4f_> *)(X32 + o), x1 = *(const G<v4f_> *)(X32 + o + 4);
+                uint16_t h[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) { s[e] += v[e]; ss[e] += v[e] * v[e]; }
+                for (int e = 0; e < 4; ++e) {
+                    h[e] = f32_to_bf16_rne(x0[e]);
+                    h[4 + e] = f32_to_bf16_rne(x1[e]);
+                }
+                *(G<v4u_> *)(X + o) = v4u_{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const double x = (double)bf16_to_f32(h[e]);
+                    s[e] += x;
+                    ss[e] += x * x;
+                }
+            }
+        } else {
+#pragma unroll 4
+            for (int64_t g = g0; g < g1; ++g) {
+                gload<uint16_t>::load(X + g * b * ld, v);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) { s[e] += v[e]; ss[e] += v[e] * v[e]; }
+            }
         }
         if (P == 1) {
             enc_finish(isA ? gp(D.acs) : gp(D.bcs), isA ? gp(D.asp) : gp(D.bsp), isA ? gp(D.grpA) : gp(D.grpB), b, D.k, r, l0, s, ss);
@@ -958,9 +985,10 @@ int batch_quantize(const abft_batch_plan *pl, hipStream_t s) {
     return ABFT_OK;
 }
 
-int batch_encode(const abft_batch_plan *pl, hipStream_t s) {
+int batch_encode(const abft_batch_plan *pl, bool quantize, hipStream_t s) {
     const int64_t n1 = pl->n_work[W_ENC1], n2 = pl->n_work[W_ENC2], nr = pl->n_work[W_ROWS];
-    kb_encode1<<<blocks_for(n1, kT), kT, 0, s>>>(descs(pl), pl->count, n1);
+    if (quantize) kb_encode1<true><<<blocks_for(n1, kT), kT, 0, s>>>(descs(pl), pl->count, n1);
+    else kb_encode1<false><<<blocks_for(n1, kT), kT, 0, s>>>(descs(pl), pl->count, n1);
     if (n2 > 0) kb_encode2<<<blocks_for(n2, kT), kT, 0, s>>>(descs(pl), pl->count, n2);
     kb_rowstats<<<blocks_for(nr, kRowsPerIter), kT, 0, s>>>(descs(pl), pl->count, nr);
     ABFT_LAUNCHED();
@@ -1051,7 +1079,11 @@ int abft_batch_quantize(const abft_batch_plan *plan, void *stream) {
 }
 int abft_batch_encode(const abft_batch_plan *plan, void *stream) {
     if (!plan || !plan->bws) return ABFT_E_ARG;
-    return batch_encode(plan, (hipStream_t)stream);
+    return batch_encode(plan, false, (hipStream_t)stream);
+}
+int abft_batch_quantize_encode(const abft_batch_plan *plan, void *stream) {
+    if (!plan || !plan->bws) return ABFT_E_ARG;
+    return batch_encode(plan, true, (hipStream_t)stream);
 }
 int abft_batch_gemm(const abft_batch_plan *plan, int tile, uint32_t flags, void *stream) {
     if (!plan || !plan->bws || (flags & ~ABFT_PLAIN)) return ABFT_E_ARG;

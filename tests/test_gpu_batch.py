@@ -116,6 +116,25 @@ def test_batch_tiles_agree_and_tune(case):
     assert 0 <= best < abft.ABFT_BATCH_TILES
 
 
+def test_batch_fused_quantize_encode_matches_separate_steps(case):
+    reps0 = case.run(0)
+    torch.cuda.synchronize()
+    C0 = [c.clone() for c in case.B.C]
+    for a, b in zip(case.B.A, case.B.Bt):
+        a.zero_()
+        b.zero_()
+    abft.batch_quantize_encode(case.B.plan)
+    abft.batch_gemm(case.B.plan, 0)
+    abft.batch_verify(case.B.plan)
+    reps = case.B.reports()
+    for q, r in enumerate(case.ref):
+        note(f"fused quantize+encode problem {q}")
+        a = case.B.A[q].cpu().view(torch.int16).numpy().view(np.uint16)
+        assert np.array_equal(a, r["Aq"])
+        assert torch.equal(case.B.C[q], C0[q]), q
+        assert reps[q].max_ratio_c == reps0[q].max_ratio_c and reps[q].max_ratio_r == reps0[q].max_ratio_r
+
+
 def test_batch_plain_product_is_data_block(case):
     case.run(0)
     torch.cuda.synchronize()
