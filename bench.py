@@ -270,6 +270,96 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def run_campaign(args):
+    """Reliability campaign on one workload: args.campaign clean products on
+    fresh seeded inputs (every relation must pass: false positives are counted),
+    then args.campaign single flips on one product (every bit position of the
+    element type, sites seeded): detected, located exactly, corrected (re-verify
+    clean and the element back within the threshold).  Flips whose change is
+    below the relation's threshold cannot be detected by construction; they are
+    counted per class (|delta| > 2 tau, gray zone, below tau / 2)."""
+    import numpy as np
+    import torch
+
+    from paper_0806_3121_amd import abft, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    dt_name, m, n, k, b, _ = WORKLOADS[args.workload]
+    adt = {"f64": abft.ABFT_F64, "f32": abft.ABFT_F32, "bf16": abft.ABFT_BF16, "fp8": abft.ABFT_FP8_E4M3}[dt_name]
+    lowp = dt_name in ("bf16", "fp8")
+    nbits = 64 if dt_name == "f64" else 32
+    P = abft.Protected(adt, m, n, k, b, b, device=dev)
+    if lowp:
+        A32 = torch.empty(m, k, dtype=torch.float32, device=dev)
+        Bt32 = torch.empty(n, k, dtype=torch.float32, device=dev)
+
+    def product(seed):
+        if lowp:
+            abft.fill_uniform(abft.ABFT_F32, m, k, k, 0, seed, synth.STREAM_A, A32)
+            abft.fill_uniform(abft.ABFT_F32, k, n, k, 1, seed, synth.STREAM_B, Bt32)
+            abft.quantize(P.p, 0, A32, P.A, P.ws)
+            abft.quantize(P.p, 1, Bt32, P.Bt, P.ws)
+        else:
+            abft.fill_uniform(adt, m, k, k, 0, seed, synth.STREAM_A, P.A)
+            abft.fill_uniform(adt, k, n, k, 1, seed, synth.STREAM_B, P.Bt)
+        P.encode()
+        P.gemm()
+
+    t0 = time.perf_counter()
+    fp, worst = 0, 0.0
+    for r in range(args.campaign):
+        product(SEED + 1000 + r)
+        rep = P.verify()
+        if rep.n_flag_c or rep.n_flag_r:
+            fp += 1
+        worst = max(worst, rep.max_ratio_c, rep.max_ratio_r)
+        if r % 100 == 0:
+            log(f"clean run {r}: false positives so far {fp}, max |D|/tau {worst:.3f}")
+    t_clean = time.perf_counter() - t0
+
+    product(SEED)
+    clean = P.C.clone()
+    M, N = m + b, n + b
+    stats = {"detected": 0, "located": 0, "corrected": 0, "both_relations_flagged": 0,
+             "both_flagged_located": 0, "one_relation_flagged": 0, "none_flagged": 0}
+    t0 = time.perf_counter()
+    for r in range(args.campaign):
+        i, j, bit = synth.flip_site(SEED + 17, r, M, N, 0, nbits - 1)
+        P.C.copy_(clean)
+        abft.inject_flip(P.p, P.C, i, j, bit)
+        rep = P.verify()
+        old = clean[i, j].item()
+        col_flag = [f for f in rep.flags_c() if f[0] == i % b and f[1] == j]
+        row_flag = [f for f in rep.flags_r() if f[0] == i and f[1] == j % b]
+        detected = bool(rep.n_flag_c or rep.n_flag_r)
+        loc = abft.classify(P.p, rep)
+        ok_loc = (loc.i, loc.j) == (i, j) and loc.cls in (abft.ABFT_CLS_DATA, abft.ABFT_CLS_CHECKSUM)
+        stats["detected"] += detected
+        if ok_loc:
+            stats["located"] += 1
+            abft.correct(P.p, P.C, loc)
+            rep2 = P.verify()
+            tau_ij = min([f[3] for f in col_flag + row_flag] or [float("inf")])
+            if not (rep2.n_flag_c or rep2.n_flag_r) and abs(P.C[i, j].item() - old) <= tau_ij:
+                stats["corrected"] += 1
+        if col_flag and row_flag:
+            stats["both_relations_flagged"] += 1
+            stats["both_flagged_located"] += ok_loc
+        elif col_flag or row_flag:
+            stats["one_relation_flagged"] += 1
+        else:
+            stats["none_flagged"] += 1
+        if r % 100 == 0:
+            log(f"flip run {r}: {stats}")
+    t_flip = time.perf_counter() - t0
+    out = {"campaign": args.workload, "dtype": dt_name, "m": m, "n": n, "k": k, "b": b,
+           "clean_runs": args.campaign, "false_positives": fp, "max_ratio_clean": round(worst, 4),
+           "flip_runs": args.campaign, "flip_bits": f"0..{nbits - 1}", **stats,
+           "seconds": {"clean": round(t_clean, 1), "flips": round(t_flip, 1)}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -279,12 +369,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the unprotected-kernel timing (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--campaign", type=int, default=0,
+                    help="run N clean products and N single flips instead of the benchmark, print the tallies")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the path is built and measured on one "
                                    "MI355X (see the sharding notes in DESIGN.md)", "n_gpus": args.gpus}))
         sys.exit(2)
 
+    if args.campaign:
+        if args.workload == "c5":
+            raise SystemExit("the campaign runs on the single-problem workloads")
+        return run_campaign(args)
     if args.workload == "c5":
         return run_batched(args)
 
