@@ -45,6 +45,14 @@ BATCH = {"count": 512, "lo": 64, "hi": 2048, "step": 32, "br": 32, "bc": 1, "lam
 # top fraction bit: always above the statistical threshold, so every step's
 # flip is located)
 FLIP_BITS = {"f64": (40, 62), "f32": (24, 29), "bf16": (24, 29), "fp8": (24, 29)}
+# HBM bytes per protected-product call (read + write, all its launches), from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE on this benchmark, FETCH_SIZE scaled by 2 (a 1 GiB copy reads 0.5 GiB of FETCH_SIZE);
+# summarized in profiles/hbm_traffic_counters_c2_c4_c5.txt.  Re-measure when those kernels change.
+TRAFFIC = {
+    "c2": 28.956e9 + 0.679e9,                       # k_gemm_mfma (checksum blocks tiled with the data)
+    "c4": 12.942e9 + 1.122e9 + 2 * 0.539e9,         # k_gemm_lowp2 + two k_sliver launches
+    "c5": 5.185e9 + 2.664e9 + 0.226e9 + 0.087e9,    # kb_gemm (tuned tile) + kb_combine
+}
 SEED = 20080523
 
 
@@ -250,8 +258,8 @@ def run_batched(args):
                    "problems": len(shapes), "br": br, "bc": bc, "tile": tile, "global_batch": len(shapes),
                    "seq_len": 0, "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
-                     "kernel": "kb_gemm (persistent, all problems) + kb_sliver (carried checksums)",
+                     "frac": round(achieved / peak, 4), "traffic": TRAFFIC["c5"],
+                     "kernel": "kb_gemm (persistent, all problems) + kb_combine (carried checksums)",
                      "flops_per_launch": executed, "avg_launch_ms": round(ms["gemm"], 4)},
         "pct_mfma_peak_useful": round(100 * value / peak, 2),
         "phase_ms": {"quantize_encode": round(ms["pre"], 4), "gemm_protected": round(ms["gemm"], 4),
@@ -495,8 +503,8 @@ def main():
                    "m": m, "n": n, "k": k, "br": b, "bc": b, "global_batch": 1, "seq_len": 0,
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
-                     "kernel": ("k_gemm_lowp" if lowp else "k_gemm_mfma") + " + k_sliver (thin checksum blocks)",
+                     "frac": round(achieved / peak, 4), "traffic": TRAFFIC.get(args.workload),
+                     "kernel": ("k_gemm_lowp2" if lowp else "k_gemm_mfma") + " + k_sliver (thin checksum blocks)",
                      "flops_per_launch": executed,
                      "avg_launch_ms": round(gemm_ms, 4)},
         "pct_mfma_peak_useful": round(100 * value / peak, 2),
