@@ -146,43 +146,55 @@ __global__ __launch_bounds__(kThreads) void k_encode_finish(int64_t b, int64_t k
     }
 }
 
-// Per-row statistic of X[i, 0:k), one block per row (grid-stride over rows),
-// 16-byte loads:
+// Per-row statistic of X[i, 0:k), one wave per row (grid-stride over rows),
+// 16-byte loads, four in flight per lane:
 //   ROW_L2:  ||x||_2              ROW_W: sum_l x_l^2 w_l          ROW_L4SQ: ||x||_4^2
 enum { ROW_L2 = 0, ROW_W = 1, ROW_L4SQ = 2 };
 constexpr int64_t kRowWMaxK = 16384;   // ROW_W keeps w (as binary32, 64 KB) in LDS up to this k
+constexpr int kRowThreads = 512;       // 8 waves share one copy of w
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_row_stats(const T *X, int64_t ld, int64_t rows, int64_t k, int mode,
-                                                        const double *w, double *out) {
+__global__ __launch_bounds__(kRowThreads) void k_row_stats(const T *X, int64_t ld, int64_t rows, int64_t k, int mode,
+                                                           const double *w, double *out) {
     constexpr int V = vec16<T>::N;
-    __shared__ double sh[kThreads / kWave];
+    constexpr int NW = kRowThreads / kWave;
     extern __shared__ float wsh[];                     // k floats when mode == ROW_W and k <= kRowWMaxK
     const bool wlds = mode == ROW_W && k <= kRowWMaxK;
     if (wlds) {
-        for (int64_t l = threadIdx.x; l < k; l += kThreads) wsh[l] = (float)w[l];
+        for (int64_t l = threadIdx.x; l < k; l += kRowThreads) wsh[l] = (float)w[l];
         __syncthreads();
     }
-    for (int64_t i = blockIdx.x; i < rows; i += gridDim.x) {
-        const T *row = X + i * ld;
-        double acc = 0.0, v[V];
-        for (int64_t l0 = (int64_t)threadIdx.x * V; l0 < k; l0 += (int64_t)kThreads * V) {
-            vec16<T>::load(row + l0, v);
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    auto term = [&](const double *v, int64_t l0, double &acc) {
 #pragma unroll
-            for (int q = 0; q < V; ++q) {
-                double v2 = v[q] * v[q];
-                double wl = mode == ROW_W ? (wlds ? (double)wsh[l0 + q] : w[l0 + q]) : 0.0;
-                acc += mode == ROW_W ? v2 * wl : (mode == ROW_L4SQ ? v2 * v2 : v2);
-            }
+        for (int q = 0; q < V; ++q) {
+            const double v2 = v[q] * v[q];
+            const double wl = mode == ROW_W ? (wlds ? (double)wsh[l0 + q] : w[l0 + q]) : 0.0;
+            acc += mode == ROW_W ? v2 * wl : (mode == ROW_L4SQ ? v2 * v2 : v2);
+        }
+    };
+    for (int64_t i = (int64_t)blockIdx.x * NW + wave; i < rows; i += (int64_t)gridDim.x * NW) {
+        const T *row = X + i * ld;
+        double acc = 0.0;
+        constexpr int64_t step = (int64_t)kWave * V;
+        int64_t l0 = (int64_t)lane * V;
+        for (; l0 + 3 * step < k; l0 += 4 * step) {
+            double v0[V], v1[V], v2[V], v3[V];
+            vec16<T>::load(row + l0, v0);
+            vec16<T>::load(row + l0 + step, v1);
+            vec16<T>::load(row + l0 + 2 * step, v2);
+            vec16<T>::load(row + l0 + 3 * step, v3);
+            term(v0, l0, acc);
+            term(v1, l0 + step, acc);
+            term(v2, l0 + 2 * step, acc);
+            term(v3, l0 + 3 * step, acc);
+        }
+        for (; l0 < k; l0 += step) {
+            double v0[V];
+            vec16<T>::load(row + l0, v0);
+            term(v0, l0, acc);
         }
         acc = wave_sum(acc);
-        if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = acc;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int q = 0; q < kThreads / kWave; ++q) t += sh[q];
-            out[i] = mode == ROW_W ? t : sqrt(t);
-        }
-        __syncthreads();
+        if (lane == 0) out[i] = mode == ROW_W ? acc : sqrt(acc);
     }
 }
 
@@ -191,9 +203,10 @@ template <typename T>
 static void row_stats(const T *X, int64_t ld, int64_t rows, int64_t k, int mode, const double *w, double *out,
                       hipStream_t s) {
     if (rows <= 0) return;
+    constexpr int NW = kRowThreads / kWave;
     size_t lds = (mode == ROW_W && k <= kRowWMaxK) ? sizeof(float) * (size_t)k : 0;
-    unsigned grid = (unsigned)std::min<int64_t>(rows, lds ? 1024 : 65536);
-    k_row_stats<T><<<grid, kThreads, lds, s>>>(X, ld, rows, k, mode, w, out);
+    unsigned grid = (unsigned)std::min<int64_t>((rows + NW - 1) / NW, lds ? 512 : 65536);
+    k_row_stats<T><<<grid, kRowThreads, lds, s>>>(X, ld, rows, k, mode, w, out);
 }
 
 static unsigned grid_for(int64_t work) { return (unsigned)std::min<int64_t>((work + kThreads - 1) / kThreads, 65536); }
