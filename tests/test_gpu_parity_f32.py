@@ -158,3 +158,74 @@ def test_f32_erasure_rebuild(dev, orc):
             got = P.C[i0:i0 + h, j0:j0 + w].cpu().numpy().astype(np.float64)
             want = C32[i0:i0 + h, j0:j0 + w].astype(np.float64)
             assert np.abs(got - want).max() / np.abs(C32).max() <= TOL32
+
+
+# Heavy-tailed inputs: N(0,1) with 1 % of the entries scaled by 1e3 (the
+# second input set of the binary32 workload).  Same bars: values, clean verify
+# with the statistical thresholds, flip decisions equal the oracle's.
+HEAVY = [(512, 384, 2048, 1, 1), (384, 256, 1000, 8, 4)]
+
+
+def heavy_inputs(m, n, k):
+    A = synth.normal_with_outliers(SEED + 101, m, k)
+    B = synth.normal_with_outliers(SEED + 102, k, n)
+    return A, B
+
+
+@pytest.mark.parametrize("m,n,k,br,bc", HEAVY)
+def test_f32_heavy_tailed_product_and_clean_verify(dev, orc, m, n, k, br, bc):
+    note(f"f32 heavy-tailed m={m} n={n} k={k} br={br} bc={bc}")
+    A, B = heavy_inputs(m, n, k)
+    A, B, P = make(dev, m, n, k, br, bc, A, B)
+    P.encode()
+    P.gemm()
+    torch.cuda.synchronize()
+    Af, Bf, C32, tc, tr = oracle_side(orc, A, B, br, bc)
+    Cg = P.C.cpu().numpy()
+    # per element: k binary32 accumulations of the exact products, plus the rounding of C
+    bound = k * 2.0 ** -24 * (np.abs(Af) @ np.abs(Bf)) + 2.0 ** -24 * np.abs(C32)
+    assert np.all(np.abs(Cg.astype(np.float64) - C32) <= bound * 1.01)
+    rep = P.verify()
+    assert rep.n_flag_c == 0 and rep.n_flag_r == 0, (rep.max_ratio_c, rep.max_ratio_r)
+    Dc, Dr = residuals(Cg.astype(np.float64), m, n, br, bc)
+    z = np.concatenate([(Dc / (tc / LAMBDA)).ravel(), (Dr / (tr / LAMBDA)).ravel()])
+    note(f"  gpu |D|/sigma: rms {np.sqrt(np.mean(z * z)):.3f} max {np.abs(z).max():.3f}; max ratio "
+         f"{max(rep.max_ratio_c, rep.max_ratio_r):.4f}")
+    assert np.abs(z).max() < LAMBDA / 2
+
+
+def test_f32_heavy_tailed_flip_decisions_match_oracle(dev, orc):
+    m, n, k, br, bc, runs = 384, 256, 1000, 8, 4, 40
+    A, B = heavy_inputs(m, n, k)
+    A, B, P = make(dev, m, n, k, br, bc, A, B)
+    P.encode()
+    P.gemm()
+    clean = P.C.clone()
+    Af, Bf, C32, tc, tr = oracle_side(orc, A, B, br, bc)
+    M, N = m + br, n + bc
+    located = compared = 0
+    for run in range(runs):
+        i, j, bit = synth.flip_site(SEED + 9, run, M, N, 11, 30)
+        note(f"f32 heavy flip run={run} ({i},{j}) bit {bit}")
+        P.C.copy_(clean)
+        abft.inject_flip(P.p, P.C, i, j, bit)
+        rep = P.verify()
+        loc = abft.classify(P.p, rep)
+        Cx = C32.copy()
+        Cx.view(np.uint32)[i, j] ^= np.uint32(1 << bit)
+        delta = float(Cx[i, j]) - float(C32[i, j])
+        t1, t2 = tc[i % br, j], tr[i, j % bc]
+        if np.isfinite(delta) and (t1 / 2 < abs(delta) < 2 * t1 or t2 / 2 < abs(delta) < 2 * t2):
+            continue
+        compared += 1
+        _, _, orep = orc.verify(Cx.astype(np.float64), m, n, br, bc, tc, tr)
+        ocls, oi, oj, od = orc.classify(orep, m, n, br, bc)
+        assert (rep.n_flag_c, rep.n_flag_r) == (orep.n_flag_c, orep.n_flag_r), (i, j, bit, delta)
+        assert (loc.cls, loc.i, loc.j) == (ocls, oi, oj)
+        if loc.cls in (abft.ABFT_CLS_DATA, abft.ABFT_CLS_CHECKSUM):
+            located += 1
+            abft.correct(P.p, P.C, loc)
+            rep2 = P.verify()
+            assert rep2.n_flag_c == 0 and rep2.n_flag_r == 0
+    note(f"  compared {compared}, located {located}")
+    assert compared >= runs * 0.7 and located >= 1
