@@ -272,6 +272,20 @@ def e4m3_scale_exp(x: np.ndarray) -> int:
 
 
 # ---------------------------------------------------------------- whole pipeline
+def outer_update(Cf: np.ndarray, Af: np.ndarray, Bf: np.ndarray, k0: int, k1: int) -> np.ndarray:
+    """Outer-product form of the product (Sec. 2.2; the rank-nb updates of
+    Sec. 3.2): C_f += A_f[:, l] B_f[l, :] for l = k0 .. k1-1, one rank-1
+    update at a time, in place on a float64 C_f.  After the updates over
+    [0, k1) C_f is the encoded product of A[:, :k1] and B[:k1, :], so it is
+    consistent at every step of the loop."""
+    assert Cf.dtype == np.float64 and Cf.shape == (Af.shape[0], Bf.shape[1])
+    Af = _f64(Af)
+    Bf = _f64(Bf)
+    for l in range(k0, k1):
+        Cf += np.outer(Af[:, l], Bf[l, :])
+    return Cf
+
+
 def protected_product(A: np.ndarray, B: np.ndarray, br: int, bc: int):
     """Encode and multiply in FP64: returns (A_f, B_f, C_f)."""
     Af, Bf = encode(A, B, br, bc)

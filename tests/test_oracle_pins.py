@@ -279,6 +279,56 @@ def test_every_block_position_rebuilt_exactly(orc, br, bc, bh, bw):
                 assert np.array_equal(Cx, Cf), (i0, j0, use_rows)
 
 
+@pytest.mark.parametrize("br,bc", [(1, 1), (3, 2)])
+def test_outer_product_intermediates_consistent_exact(orc, br, bc):
+    """Sec. 2.2 outer-product loop: every intermediate C_k is the integer
+    partial product A[:, :k] B[:k, :] with its checksums, so every relation
+    holds exactly after every rank-1 update; the loop ends on the product."""
+    m, n, k = 12, 10, 9
+    A, B = int_problem(m, n, k, seed=br + 5 * bc)
+    Af, Bf = orc.encode(A, B, br, bc)
+    Ai, Bi = A.astype(np.int64), B.astype(np.int64)
+    Cf = np.zeros((m + br, n + bc))
+    tc, tr = np.zeros((br, n + bc)), np.zeros((m + br, bc))
+    for k1 in range(1, k + 1):
+        orc.outer_update(Cf, Af, Bf, k1 - 1, k1)
+        assert np.array_equal(Cf[:m, :n], (Ai[:, :k1] @ Bi[:k1]).astype(np.float64)), k1
+        rep = orc.verify(Cf, m, n, br, bc, tc, tr)[2]
+        assert rep.n_flag_c == 0 and rep.n_flag_r == 0, k1
+    assert np.array_equal(Cf, orc.gemm(Af, Bf))
+
+
+def test_outer_product_does_not_transpose_or_skip(orc):
+    """A rank-1 update on hand-sized operands, checked entry by entry."""
+    Af = np.array([[1.0, 2.0], [3.0, 4.0], [5.0, 6.0]])
+    Bf = np.array([[1.0, -1.0], [10.0, 20.0]])
+    Cf = np.zeros((3, 2))
+    orc.outer_update(Cf, Af, Bf, 1, 2)          # only l = 1
+    assert np.array_equal(Cf, [[20.0, 40.0], [40.0, 80.0], [60.0, 120.0]])
+    orc.outer_update(Cf, Af, Bf, 0, 1)
+    assert np.array_equal(Cf, Af @ Bf)
+
+
+@pytest.mark.parametrize("br,bc,rect,use_rows", [(4, 4, (4, 8, 4, 4), False), (2, 4, (6, 16, 2, 4), False),
+                                                 (4, 2, (0, 2, 4, 2), True)])
+def test_mid_loop_erasure_rebuilt_then_loop_goes_on(orc, br, bc, rect, use_rows):
+    """Sec. 2.2: a block lost between two updates of the outer-product loop
+    is rebuilt from the consistent intermediate (exactly, on integers), and
+    finishing the loop gives the product an uninterrupted loop gives."""
+    m, n, k = 16, 16, 11
+    A, B = int_problem(m, n, k, seed=31)
+    Af, Bf = orc.encode(A, B, br, bc)
+    Cf = np.zeros((m + br, n + bc))
+    orc.outer_update(Cf, Af, Bf, 0, 5)
+    want = Cf.copy()
+    i0, j0, h, w = rect
+    Cf[i0:i0 + h, j0:j0 + w] = np.nan
+    assert orc.recover(Cf, m, n, br, bc, rect, use_rows=use_rows) == 0
+    assert np.array_equal(Cf, want)
+    orc.outer_update(Cf, Af, Bf, 5, k)
+    assert np.array_equal(Cf, orc.gemm(Af, Bf))
+
+
 def test_recovery_formula_single_checksum(orc):
     """Sec. 2.1 with unit weights: x_i = y - sum_{k != i} x_k, on a 1-row C."""
     m, n, k = 1, 5, 1
