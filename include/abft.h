@@ -88,6 +88,8 @@ typedef enum { ABFT_TAU_DET = 0, ABFT_TAU_STAT = 1, ABFT_TAU_EXACT = 2 } abft_ta
 /* abft_gemm flags */
 #define ABFT_PLAIN 1u   /* multiply only the data part (C = A B, m x n): the
                            unprotected baseline the overhead is measured against */
+#define ABFT_ACCUMULATE 2u /* abft_gemm_panel only: add the panel product to C_f
+                              instead of overwriting it */
 
 /*
  * Problem descriptor.  Layouts (elements of the dtype, not bytes):
@@ -188,6 +190,26 @@ int abft_encode(const abft_problem *p, void *A_f, void *B_f, void *ws, void *str
  */
 int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, void *ws, uint32_t flags,
               void *stream);
+
+/*
+ * Panel update (outer-product form of the product, Sec. 2.2 and the rank-nb
+ * updates of Sec. 3.2): C_f = A_f[:, k0:k1) B_f[k0:k1, :), or with
+ * flags & ABFT_ACCUMULATE, C_f += A_f[:, k0:k1) B_f[k0:k1, :), over the same
+ * (m+br) x (n+bc) entries (m x n with ABFT_PLAIN) and on the same kernels as
+ * abft_gemm.  Every checksum relation is linear in the inner index, so after
+ * any sequence of panels covering [0, k1) C_f is the encoded product of
+ * A[:, 0:k1) and B[0:k1, :) and stays consistent: abft_verify may run and a
+ * lost block may be rebuilt (abft_recover) between panels, and the loop then
+ * goes on.  The thresholds are those of the whole product (an upper bound for
+ * every partial sum: partial row norms and step counts are no larger).
+ * Accumulation adds one rounding per panel to each entry.
+ * dtype ABFT_F64 or ABFT_F32 (ABFT_E_UNSUPPORTED otherwise); A_f and B_f must
+ * have been encoded; 0 <= k0 < k1 <= k with k0 and k1 multiples of 16/size
+ * (panels start and end on 16-byte boundaries).  No workspace.  flags:
+ * ABFT_PLAIN, ABFT_ACCUMULATE.
+ */
+int abft_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, int64_t k0, int64_t k1,
+                    uint32_t flags, void *stream);
 
 /*
  * Verify (consistency, Sec. 2.2): recomputes every column and row relation of

@@ -17,6 +17,7 @@ ABFT_E_ARG, ABFT_E_HIP, ABFT_E_UNCORRECTABLE, ABFT_E_UNRECOVERABLE, ABFT_E_WORKS
     -1, -2, -3, -4, -5, -6
 ABFT_TAU_DET, ABFT_TAU_STAT, ABFT_TAU_EXACT = 0, 1, 2
 ABFT_PLAIN = 1
+ABFT_ACCUMULATE = 2
 ABFT_CLS_CLEAN, ABFT_CLS_DATA, ABFT_CLS_CHECKSUM, ABFT_CLS_MULTI = 0, 1, 2, 3
 ABFT_DIR_COL, ABFT_DIR_ROW = 0, 1
 ABFT_MAX_FLAGS = 64
@@ -93,6 +94,7 @@ def lib():
             "abft_workspace_size": (C.c_size_t, [_P(abft_problem)]),
             "abft_encode": (C.c_int, [_P(abft_problem), _V, _V, _V, _V]),
             "abft_gemm": (C.c_int, [_P(abft_problem), _V, _V, _V, _V, C.c_uint32, _V]),
+            "abft_gemm_panel": (C.c_int, [_P(abft_problem), _V, _V, _V, C.c_int64, C.c_int64, C.c_uint32, _V]),
             "abft_quantize": (C.c_int, [_P(abft_problem), C.c_int, _V, C.c_int64, _V, _V, _V]),
             "abft_verify": (C.c_int, [_P(abft_problem), _V, _P(abft_rect), C.c_int, _V, _V, _V]),
             "abft_classify": (C.c_int, [_P(abft_problem), _P(abft_report), _P(abft_rect), C.c_int,
@@ -167,6 +169,12 @@ def encode(p, A_f, B_f, ws, stream=None):
 def gemm(p, A_f, B_f, C_f, ws=None, flags=0, stream=None):
     return _check("abft_gemm", lib().abft_gemm(C.byref(p), _ptr(A_f), _ptr(B_f), _ptr(C_f), _ptr(ws), flags,
                                                _stream(stream)))
+
+
+def gemm_panel(p, A_f, B_f, C_f, k0, k1, flags=0, stream=None):
+    """C_f (+)= A_f[:, k0:k1) B_f[k0:k1, :) (ABFT_ACCUMULATE in flags adds)."""
+    return _check("abft_gemm_panel", lib().abft_gemm_panel(C.byref(p), _ptr(A_f), _ptr(B_f), _ptr(C_f), k0, k1,
+                                                           flags, _stream(stream)))
 
 
 def quantize(p, which, X, dst, ws, stream=None):

@@ -262,6 +262,19 @@ int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f
     return launch_gemm(p, A_f, B_f, C_f, flags, ws, (hipStream_t)stream);
 }
 
+int abft_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, int64_t k0, int64_t k1,
+                    uint32_t flags, void *stream) {
+    int st = check_problem(p);
+    if (st) return st;
+    if (flags & ~(ABFT_PLAIN | ABFT_ACCUMULATE)) return ABFT_E_ARG;
+    if (p->dtype != ABFT_F64 && p->dtype != ABFT_F32) return ABFT_E_UNSUPPORTED;
+    if ((st = check_operands(p, A_f, B_f))) return st;
+    if ((st = check_c(p, C_f, flags & ABFT_PLAIN))) return st;
+    const int64_t align = 16 / (int64_t)dtype_size(p->dtype);
+    if (k0 < 0 || k1 <= k0 || k1 > p->k || k0 % align || k1 % align) return ABFT_E_ARG;
+    return launch_gemm_panel(p, A_f, B_f, C_f, k0, k1, flags, (hipStream_t)stream);
+}
+
 int abft_verify(const abft_problem *p, const void *C_f, const abft_rect *known, int n_known, void *ws,
                 abft_report *host_out, void *stream) {
     int st = check_problem(p);

@@ -210,6 +210,8 @@ void set_hip_error(hipError_t e);
 
 // ------------------------------------------------------------------ launchers (return abft_status)
 int launch_encode(const abft_problem *p, void *A_f, void *B_f, char *ws, hipStream_t s);
+int launch_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, int64_t k0, int64_t k1,
+                      uint32_t flags, hipStream_t s);
 int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, void *ws,
                 hipStream_t s);
 int launch_verify(const abft_problem *p, const void *C_f, const Erasures &er, char *ws, hipStream_t s);

@@ -84,7 +84,7 @@ template <class T>
 __global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_mfma(const typename T::E *__restrict__ A, int64_t lda,
                                                              const typename T::E *__restrict__ Bt, int64_t ldb,
                                                              typename T::E *__restrict__ C, int64_t ldc, int64_t M,
-                                                             int64_t N, int64_t K) {
+                                                             int64_t N, int64_t K, int accumulate) {
     typedef typename T::E E;
     typedef MfmaOps<E> Ops;
     typedef typename Ops::vec16 v16;
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_mfma(const typenam
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 int64_t gr = row0 + wm * (T::BM / T::WM) + a * 16 + Ops::crow(lane, v);
-                if (gr < M && gc < N) C[gr * ldc + gc] = acc[a][b][v];
+                if (gr < M && gc < N) C[gr * ldc + gc] = accumulate ? C[gr * ldc + gc] + acc[a][b][v] : acc[a][b][v];
             }
         }
     }
@@ -197,10 +197,11 @@ __global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_mfma(const typenam
 
 template <class T>
 inline int launch_gemm_tile(const typename T::E *A, int64_t lda, const typename T::E *Bt, int64_t ldb,
-                            typename T::E *C, int64_t ldc, int64_t M, int64_t N, int64_t K, hipStream_t s) {
+                            typename T::E *C, int64_t ldc, int64_t M, int64_t N, int64_t K, hipStream_t s,
+                            bool accumulate = false) {
     int64_t tiles = ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
     if (tiles > INT32_MAX) return ABFT_E_ARG;
-    k_gemm_mfma<T><<<(unsigned)tiles, T::THREADS, 0, s>>>(A, lda, Bt, ldb, C, ldc, M, N, K);
+    k_gemm_mfma<T><<<(unsigned)tiles, T::THREADS, 0, s>>>(A, lda, Bt, ldb, C, ldc, M, N, K, accumulate ? 1 : 0);
     return ABFT_OK;
 }
 

@@ -38,12 +38,14 @@ static const TileChoice kF64Tiles[] = {
     {0, 256, 128, 1, 0.818}, {1, 128, 128, 2, 0.787}, {2, 128, 96, 2, 0.80}, {3, 96, 96, 2, 0.76},
 };
 static int gemm_main(const double *A, int64_t lda, const double *Bt, int64_t ldb, double *C, int64_t ldc, int64_t M,
-                     int64_t N, int64_t K, hipStream_t s) {
+                     int64_t N, int64_t K, hipStream_t s, bool acc = false) {
     switch (choose_tile(kF64Tiles, 4, M, N)) {
-    case 0: return launch_gemm_tile<MfmaTile<double, 256, 128, 16, 4, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
-    case 1: return launch_gemm_tile<MfmaTile<double, 128, 128, 16, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
-    case 2: return launch_gemm_tile<MfmaTile<double, 128, 96, 16, 2, 2, 8, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
-    default: return launch_gemm_tile<MfmaTile<double, 96, 96, 16, 2, 2, 8, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
+    case 0: return launch_gemm_tile<MfmaTile<double, 256, 128, 16, 4, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc);
+    case 1: return launch_gemm_tile<MfmaTile<double, 128, 128, 16, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc);
+    case 2:
+        return launch_gemm_tile<MfmaTile<double, 128, 96, 16, 2, 2, 8, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc);
+    default:
+        return launch_gemm_tile<MfmaTile<double, 96, 96, 16, 2, 2, 8, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc);
     }
 }
 
@@ -52,28 +54,32 @@ static const TileChoice kF32Tiles[] = {
     {0, 256, 128, 1, 0.80}, {1, 128, 128, 2, 0.78},
 };
 static int gemm_main(const float *A, int64_t lda, const float *Bt, int64_t ldb, float *C, int64_t ldc, int64_t M,
-                     int64_t N, int64_t K, hipStream_t s) {
+                     int64_t N, int64_t K, hipStream_t s, bool acc = false) {
     switch (choose_tile(kF32Tiles, 2, M, N)) {
-    case 0: return launch_gemm_tile<MfmaTile<float, 256, 128, 32, 4, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
-    default: return launch_gemm_tile<MfmaTile<float, 128, 128, 32, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s);
+    case 0: return launch_gemm_tile<MfmaTile<float, 256, 128, 32, 4, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc);
+    default: return launch_gemm_tile<MfmaTile<float, 128, 128, 32, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc);
     }
 }
 
+// C_f = (acc ? C_f : 0) + A_f[:, k0:k0+K) B_f[k0:k0+K, :)  (the whole product: k0 = 0, K = k).
 template <typename E>
 static int protected_product(const abft_problem *p, const Geom &g, const E *A, const E *Bt, E *C, bool plain,
-                             hipStream_t s) {
+                             hipStream_t s, int64_t k0 = 0, int64_t K = -1, bool acc = false) {
+    if (K < 0) K = g.k;
     const bool thin_r = !plain && g.S * g.br <= kSliverMaxB;
     const bool thin_c = !plain && g.S * g.bc <= kSliverMaxB;
     int64_t Mm = (plain || thin_r) ? g.m : g.M;
     int64_t Nm = (plain || thin_c) ? g.n : g.N;
-    int st = gemm_main(A, p->lda, Bt, p->ldb, C, p->ldc, Mm, Nm, g.k, s);
+    const E *Ak = A + k0, *Bk = Bt + k0;
+    int st = gemm_main(Ak, p->lda, Bk, p->ldb, C, p->ldc, Mm, Nm, K, s, acc);
     if (st) return st;
     ABFT_LAUNCHED();
     // carried row block over all N columns (corner included), then the carried
     // column block over the rows the main product covered
-    if (thin_r && (st = launch_sliver_rows<E, E, E>(g, A + g.m * p->lda, p->lda, Bt, p->ldb, C, p->ldc, s)))
+    if (thin_r && (st = launch_sliver_rows<E, E, E>(g, Ak + g.m * p->lda, p->lda, Bk, p->ldb, C, p->ldc, K, acc, s)))
         return st;
-    if (thin_c && (st = launch_sliver_cols<E, E, E>(g, Mm, A, p->lda, Bt + g.n * p->ldb, p->ldb, C, p->ldc, s)))
+    if (thin_c &&
+        (st = launch_sliver_cols<E, E, E>(g, Mm, Ak, p->lda, Bk + g.n * p->ldb, p->ldb, C, p->ldc, K, acc, s)))
         return st;
     return ABFT_OK;
 }
@@ -122,6 +128,22 @@ static int protected_product_lowp(const abft_problem *p, const Geom &g, const ty
         return st;
     // C_f[i, n + c], i < m
     return sliver<E, float, float>(A, p->lda, g.m, Bcs, g.k, g.bc, g.k, C + g.n, p->ldc, 1, scale_exp, s);
+}
+
+int launch_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, int64_t k0, int64_t k1,
+                      uint32_t flags, hipStream_t s) {
+    Geom g = geom_of(p);
+    const bool plain = flags & ABFT_PLAIN, acc = flags & ABFT_ACCUMULATE;
+    switch (p->dtype) {
+    case ABFT_F64:
+        return protected_product<double>(p, g, (const double *)A_f, (const double *)B_f, (double *)C_f, plain, s, k0,
+                                         k1 - k0, acc);
+    case ABFT_F32:
+        return protected_product<float>(p, g, (const float *)A_f, (const float *)B_f, (float *)C_f, plain, s, k0,
+                                        k1 - k0, acc);
+    default:
+        return ABFT_E_UNSUPPORTED;
+    }
 }
 
 int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, void *ws,

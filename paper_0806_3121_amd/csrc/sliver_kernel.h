@@ -16,9 +16,14 @@ namespace abft {
 constexpr int kSliverThreads = 256;
 constexpr int kSliverR = 8;   // few rows per pass
 
-template <typename T> __device__ inline void store_out(T *p, double v);
-template <> __device__ inline void store_out<double>(double *p, double v) { *p = v; }
-template <> __device__ inline void store_out<float>(float *p, double v) { *p = (float)v; }
+// out = v, or out += v (accumulate: the sum is taken in binary64 and rounded once)
+template <typename T> __device__ inline void store_out(T *p, double v, bool accumulate);
+template <> __device__ inline void store_out<double>(double *p, double v, bool accumulate) {
+    *p = accumulate ? *p + v : v;
+}
+template <> __device__ inline void store_out<float>(float *p, double v, bool accumulate) {
+    *p = (float)(accumulate ? (double)*p + v : v);
+}
 
 // X: U rows of type TX (ldx); Y: R rows of type TY (ldy), R <= kSliverR per launch.
 // out[u*ou + s*os] = scale * sum_l X[u,l] Y[s,l], scale = 2^-(e[0] + e[1]) when
@@ -28,7 +33,7 @@ template <typename TX, typename TY, typename TC>
 __global__ __launch_bounds__(kSliverThreads) void k_sliver(const TX *__restrict__ X, int64_t ldx, int64_t U,
                                                           const TY *__restrict__ Y, int64_t ldy, int R, int64_t K,
                                                           TC *__restrict__ out, int64_t ou, int64_t os,
-                                                          const int *__restrict__ scale_exp) {
+                                                          const int *__restrict__ scale_exp, int accumulate) {
     const double scale = scale_exp ? ldexp(1.0, -(scale_exp[0] + scale_exp[1])) : 1.0;
     constexpr int VX = vec16<TX>::N, VY = vec16<TY>::N;
     constexpr int V = VX > VY ? VX : VY;             // k per lane per step
@@ -82,36 +87,37 @@ __global__ __launch_bounds__(kSliverThreads) void k_sliver(const TX *__restrict_
         for (int s = 0; s < kSliverR; ++s) {
             double v = acc[s];
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (lane == 0 && s < R) store_out<TC>(out + u * ou + s * os, scale * v);
+            if (lane == 0 && s < R) store_out<TC>(out + u * ou + s * os, scale * v, accumulate != 0);
         }
     }
 }
 
 template <typename TX, typename TY, typename TC>
 inline int sliver(const TX *X, int64_t ldx, int64_t U, const TY *Y, int64_t ldy, int64_t R, int64_t K, TC *out,
-                  int64_t ou, int64_t os, const int *scale_exp, hipStream_t s) {
+                  int64_t ou, int64_t os, const int *scale_exp, hipStream_t s, bool accumulate = false) {
     const int64_t waves_per_block = kSliverThreads / 64;
     unsigned blocks = (unsigned)std::min<int64_t>((U + waves_per_block - 1) / waves_per_block, 4096);
     for (int64_t r0 = 0; r0 < R; r0 += kSliverR) {
         int rr = (int)std::min<int64_t>(kSliverR, R - r0);
         k_sliver<TX, TY, TC><<<blocks, kSliverThreads, 0, s>>>(X, ldx, U, Y + r0 * ldy, ldy, rr, K, out + r0 * os, ou,
-                                                               os, scale_exp);
+                                                               os, scale_exp, accumulate ? 1 : 0);
     }
     ABFT_LAUNCHED();
     return ABFT_OK;
 }
 
-// Carried row block: C_f[m + r, 0:N) = sum_l Acs[r, l] Bt[j, l] (checksum rows Acs, br x k).
+// Carried row block: C_f[m + r, 0:N) = sum_l Acs[r, l] Bt[j, l] (checksum rows Acs, br x K; the
+// operands may start at a k offset, K is the panel depth).
 template <typename TA, typename TB, typename TC>
 inline int launch_sliver_rows(const Geom &g, const TA *Acs, int64_t ldacs, const TB *Bt, int64_t ldb, TC *C,
-                              int64_t ldc, hipStream_t s) {
-    return sliver<TB, TA, TC>(Bt, ldb, g.N, Acs, ldacs, g.br, g.k, C + g.m * ldc, 1, ldc, nullptr, s);
+                              int64_t ldc, int64_t K, bool accumulate, hipStream_t s) {
+    return sliver<TB, TA, TC>(Bt, ldb, g.N, Acs, ldacs, g.br, K, C + g.m * ldc, 1, ldc, nullptr, s, accumulate);
 }
-// Carried column block: C_f[0:rows, n + c) = sum_l A[i, l] Bcs[c, l] (checksum columns Bcs, bc x k).
+// Carried column block: C_f[0:rows, n + c) = sum_l A[i, l] Bcs[c, l] (checksum columns Bcs, bc x K).
 template <typename TA, typename TB, typename TC>
 inline int launch_sliver_cols(const Geom &g, int64_t rows, const TA *A, int64_t lda, const TB *Bcs, int64_t ldbcs,
-                              TC *C, int64_t ldc, hipStream_t s) {
-    return sliver<TA, TB, TC>(A, lda, rows, Bcs, ldbcs, g.bc, g.k, C + g.n, ldc, 1, nullptr, s);
+                              TC *C, int64_t ldc, int64_t K, bool accumulate, hipStream_t s) {
+    return sliver<TA, TB, TC>(A, lda, rows, Bcs, ldbcs, g.bc, K, C + g.n, ldc, 1, nullptr, s, accumulate);
 }
 
 }  // namespace abft

@@ -63,6 +63,21 @@ def test_layout_and_alignment_rejected():
     assert _call("abft_encode", C.byref(p), fake, fake, fake, NULL_STREAM) == abft.ABFT_E_ARG
 
 
+def test_panel_range_and_dtype_rejected():
+    fake = C.c_void_p(256)
+    p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1)
+    panel = lambda k0, k1, flags=0: _call("abft_gemm_panel", C.byref(p), fake, fake, fake, k0, k1, flags, NULL_STREAM)
+    assert panel(0, 0) == abft.ABFT_E_ARG            # empty panel
+    assert panel(128, 64) == abft.ABFT_E_ARG         # k1 < k0
+    assert panel(0, 257) == abft.ABFT_E_ARG          # beyond k
+    assert panel(-2, 64) == abft.ABFT_E_ARG
+    assert panel(1, 64) == abft.ABFT_E_ARG           # panel start not on a 16-byte boundary
+    assert panel(0, 63) == abft.ABFT_E_ARG           # panel end not on a 16-byte boundary
+    assert panel(0, 64, 4) == abft.ABFT_E_ARG        # unknown flag
+    p = abft.problem(abft.ABFT_BF16, 256, 256, 256, 1, 1)
+    assert panel(0, 64) == abft.ABFT_E_UNSUPPORTED
+
+
 def test_unrecoverable_and_bad_rects_rejected():
     fake = C.c_void_p(256)
     p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1)
