@@ -12,7 +12,11 @@ per launch with events on the launch stream (the roofline object), the plain
 product of the same kernel gives the ABFT overhead, and the CPU oracle is
 timed on a bounded sample of the same product (rank 0, N = 1 only).
 
-    python bench.py [--steps K] [--warmup W] [--workload c2|c2b1|c1|c1b64|c3|c4|c4fp8|c5] [--no-cpu-baseline]
+With --workload c2panel the product runs as a loop of panel updates
+(outer-product form) and the erasure and flip are repaired mid-loop.
+
+    python bench.py [--steps K] [--warmup W] [--workload c2|c2b1|c2panel|c1|c1b64|c3|c4|c4fp8|c5]
+                    [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -36,9 +40,13 @@ WORKLOADS = {
     "c3": ("f32", 16384, 8192, 32768, 1, False),
     "c4": ("bf16", 16384, 16384, 16384, 1, False),
     "c4fp8": ("fp8", 16384, 16384, 16384, 1, False),
+    # the same product as c2 computed as 8 rank-1024 panel updates; the block is lost, and the flip
+    # lands, half-way through the k loop and both are repaired there before the loop goes on
+    "c2panel": ("f64", 8192, 8192, 8192, 1024, True),
     # batched: 512 bfloat16 problems, m, n, k uniform on multiples of 32 in [64, 2048]
     "c5": ("bf16", 0, 0, 0, 32, True),
 }
+PANELS = {"c2panel": 8}
 BATCH = {"count": 512, "lo": 64, "hi": 2048, "step": 32, "br": 32, "bc": 1, "lam": 20.0,
          "flips": 5, "erasures": 3}
 # flip bits per C type: binary64 40..62; binary32 24..29 (exponent bits and the
@@ -47,9 +55,10 @@ BATCH = {"count": 512, "lo": 64, "hi": 2048, "step": 32, "br": 32, "bc": 1, "lam
 FLIP_BITS = {"f64": (40, 62), "f32": (24, 29), "bf16": (24, 29), "fp8": (24, 29)}
 # HBM bytes per protected-product call (read + write, all its launches), from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE on this benchmark, FETCH_SIZE scaled by 2 (a 1 GiB copy reads 0.5 GiB of FETCH_SIZE);
-# summarized in profiles/hbm_traffic_counters_c2_c4_c5.txt.  Re-measure when those kernels change.
+# summarized in profiles/hbm_traffic_counters_c2_c2panel_c4_c5.txt.  Re-measure when those kernels change.
 TRAFFIC = {
-    "c2": 28.956e9 + 0.679e9,                       # k_gemm_mfma (checksum blocks tiled with the data)
+    "c2": 28.611e9 + 0.680e9,                       # k_gemm_mfma (checksum blocks tiled with the data)
+    "c2panel": 3.305e9 + 0.679e9,                   # one accumulating panel launch of k_gemm_mfma
     "c4": 12.942e9 + 1.122e9 + 2 * 0.539e9,         # k_gemm_lowp2 + two k_sliver launches
     "c5": 5.185e9 + 2.664e9 + 0.226e9 + 0.087e9,    # kb_gemm (tuned tile) + kb_combine
 }
@@ -510,17 +519,21 @@ def main():
 
     g_events = []
 
-    def step(s):
-        if lowp:
-            abft.quantize(P.p, 0, A32, P.A, P.ws)
-            abft.quantize(P.p, 1, Bt32, P.Bt, P.ws)
-        P.encode()
+    n_panels = PANELS.get(args.workload, 0)
+
+    def timed(fn):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        P.gemm()
+        fn()
         e1.record(stream)
-        g_events.append((e0, e1))
+        return (e0, e1)
+
+    def panel(q):
+        k0, k1 = q * k // n_panels, (q + 1) * k // n_panels
+        return timed(lambda: abft.gemm_panel(P.p, P.A, P.Bt, P.C, k0, k1, abft.ABFT_ACCUMULATE if q else 0))
+
+    def repair(s):
         rect = None
         if erase:
             I, J = synth.erase_block(SEED, s, m // b, n // b)
@@ -537,6 +550,21 @@ def main():
         abft.correct(P.p, P.C, loc)
         if rect:
             abft.recover_block(P.p, P.C, rect)
+
+    def step(s):
+        if lowp:
+            abft.quantize(P.p, 0, A32, P.A, P.ws)
+            abft.quantize(P.p, 1, Bt32, P.Bt, P.ws)
+        P.encode()
+        if n_panels:
+            # rank-(k/n_panels) updates; repair half-way through the loop
+            ev = [panel(q) for q in range(n_panels // 2)]
+            repair(s)
+            ev += [panel(q) for q in range(n_panels // 2, n_panels)]
+            g_events.append(ev)
+        else:
+            g_events.append([timed(P.gemm)])
+            repair(s)
         rep = P.verify()
         if rep.n_flag_c or rep.n_flag_r:
             raise RuntimeError(f"step {s}: not clean after repair")
@@ -551,7 +579,8 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log(f"timed {args.steps} steps in {dt:.3f} s")
-    gemm_ms = sum(a.elapsed_time(c) for a, c in g_events) / len(g_events)
+    # per step: the product's launches (all panels of the loop)
+    gemm_ms = sum(sum(a.elapsed_time(c) for a, c in ev) for ev in g_events) / len(g_events)
 
     # plain product of the same kernel (no checksum rows/columns)
     pe = []
@@ -585,14 +614,17 @@ def main():
         "dtype": dt_name,
         "data": "synthetic",
         "config": {"workload": f"{dt_name.upper()} protected GEMM {args.workload}: m={m} n={n} k={k}, checksum blocks "
-                               f"{b}x{b} ({f'{m // b}x{n // b} grid, one erased block + one flip per step' if erase else 'one flip per step'})",
+                               f"{b}x{b} ({f'{m // b}x{n // b} grid, one erased block + one flip per step' if erase else 'one flip per step'})"
+                               + (f"; product as {n_panels} rank-{k // n_panels} panel updates, repaired after panel "
+                                  f"{n_panels // 2}" if n_panels else ""),
                    "m": m, "n": n, "k": k, "br": b, "bc": b, "global_batch": 1, "seq_len": 0,
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": TRAFFIC.get(args.workload),
-                     "kernel": ("k_gemm_lowp2" if lowp else "k_gemm_mfma") + " + k_sliver (thin checksum blocks)",
-                     "flops_per_launch": executed,
-                     "avg_launch_ms": round(gemm_ms, 4)},
+                     "kernel": ("k_gemm_lowp2" if lowp else "k_gemm_mfma") + " + k_sliver (thin checksum blocks)"
+                               + (f", {n_panels} accumulating panel launches per product" if n_panels else ""),
+                     "flops_per_launch": executed / max(1, n_panels),
+                     "avg_launch_ms": round(gemm_ms / max(1, n_panels), 4)},
         "pct_mfma_peak_useful": round(100 * value / peak, 2),
         "gemm_protected_ms": round(gemm_ms, 4),
         "gemm_plain_ms": round(plain_ms, 4) if plain_ms else None,
