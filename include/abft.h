@@ -347,6 +347,97 @@ int abft_batch_verify(const abft_batch_plan *plan, void *stream);
  * host_out (pinned; valid after a stream synchronisation). */
 int abft_batch_reports(const abft_batch_plan *plan, abft_report *host_out, void *stream);
 
+/*
+ * Weighted f-checksums (Sec. 2.1).  Sec. 2.1 protects p values x_g with f
+ * weighted checksums y_r = sum_g w_rg x_g and rebuilds any f lost values when
+ * every f x f submatrix of the f x p weight matrix is nonsingular.  Applied to
+ * the block product (Sec. 2.2, Eq. ABFT-GEMM with weighted checksum matrices):
+ * the values are the Gr = m/br row blocks A_g of A and the Gc = n/bc column
+ * blocks B_h of B,
+ *   A_f = [A; Y_0 .. Y_{fr-1}],  Y_r = sum_g wr[r][g] A_g   (m + fr*br rows)
+ *   B_f = [B, Z_0 .. Z_{fc-1}],  Z_c = sum_h wc[c][h] B_h   (n + fc*bc columns)
+ * and C_f = A_f B_f satisfies, for every column j < N = n + fc*bc and every
+ * row x < M = m + fr*br (corner included):
+ *   column relation (r, i, j): sum_g wr[r][g] C_f[g*br + i, j] = C_f[m + r*br + i, j]
+ *   row relation (x, c, jj):   sum_h wc[c][h] C_f[x, h*bc + jj] = C_f[x, n + c*bc + jj]
+ * The fr relations of one (i, j) form a column group, the fc relations of one
+ * (x, jj) a row group.  Binary64 only; layouts as for abft_problem with these
+ * sizes (A_f row-major, B_f column-major, C_f row-major, ldc >= N).
+ */
+#define ABFT_WMAX 4
+
+typedef struct {
+    abft_problem p;    /* dtype ABFT_F64, tau_mode ABFT_TAU_DET or ABFT_TAU_EXACT;
+                          br, bc are the block height and width */
+    int32_t fr, fc;    /* checksum block rows / columns, 1 .. ABFT_WMAX */
+    const double *wr;  /* host, fr x (m/br) row-major: wr[r*(m/br) + g] (finite) */
+    const double *wc;  /* host, fc x (n/bc) row-major */
+} abft_wproblem;
+
+/* One failed group: (a, b) = (i, j) for a column group, (x, jj) for a row
+ * group; the residual and threshold of each of its f relations. */
+typedef struct {
+    int64_t a, b;
+    double d[ABFT_WMAX];
+    double tau[ABFT_WMAX];
+} abft_wgroup;
+
+/* Result of abft_wverify.  A group fails when one of its relations has
+ * !(|D| <= tau) (NaN fails); the lists hold the first ABFT_MAX_FLAGS failed
+ * groups of each direction in no particular order (counts are exact). */
+typedef struct {
+    int64_t n_fail_c, n_fail_r;       /* failed column / row groups */
+    int64_t n_excl_c, n_excl_r;       /* groups skipped: they hold a known erased element */
+    double max_ratio_c, max_ratio_r;  /* max |D|/tau over finite relations with tau > 0 */
+    abft_wgroup col[ABFT_MAX_FLAGS];
+    abft_wgroup row[ABFT_MAX_FLAGS];
+} abft_wreport;
+
+/* Workspace bytes for p (weights, norms, partial sums, report); 0 if p is invalid. */
+size_t abft_wworkspace_size(const abft_wproblem *p);
+/* Copy the weights into ws (a blocking copy; once per problem and weight set). */
+int abft_wsetup(const abft_wproblem *p, void *ws);
+/* Checksum rows Y_r of A_f and columns Z_c of B_f (binary64 weighted sums over
+ * the blocks in increasing order, one rounding per step), then the threshold
+ * statistics: ||A_f[x, :]||_2, ||B_f[:, j]||_2 and
+ * S_r[i] = sum_g |wr[r][g]| ||A_f[g*br + i, :]||_2 (and its column analogue).
+ * ABFT_TAU_DET: tau of column relation (r, i, j) = kappa (2 gamma_k +
+ * 3 gamma_{Gr+1}) S_r[i] ||B_f[:, j]||_2, a rigorous bound on the rounding of
+ * the product, the checksums and the relation sum; rows alike with Gc. */
+int abft_wencode(const abft_wproblem *p, void *A_f, void *B_f, void *ws, void *stream);
+/* C_f = A_f B_f, all M x N entries, on the matrix cores (binary64). */
+int abft_wgemm(const abft_wproblem *p, const void *A_f, const void *B_f, void *C_f, void *stream);
+/* Every column and row group of C_f (binary64 sums); groups holding an
+ * element of a known erased rectangle (n_known <= 4) are skipped.  The report
+ * is built in ws and, if host_out is not NULL, copied there asynchronously. */
+int abft_wverify(const abft_wproblem *p, const void *C_f, const abft_rect *known, int n_known, void *ws,
+                 abft_wreport *host_out, void *stream);
+/* Locate (host only, one error per group).  When fr >= 2 each failed column
+ * group is located on its own, so errors in distinct groups are found
+ * together: a data member g with error e gives residuals wr[.][g] e (every
+ * relation of the group fails and the residual vector fits that column of
+ * the weights, for exactly one g), a checksum entry r gives one failed
+ * relation; else when fc >= 2 the row groups alike; with fr = fc = 1 one
+ * failed column group and one failed row group meet in one element.  Groups
+ * that fit no member or several, or hold a non-finite residual, give MULTI.
+ * Writes min(count, max_out) locations to out and the count to *n_out; returns
+ * ABFT_E_UNCORRECTABLE if any location is MULTI. */
+int abft_wlocate(const abft_wproblem *p, const abft_wreport *report, abft_location *out, int max_out, int *n_out);
+/* Rebuild located elements in place from their groups (never reading them):
+ * a data member from the lowest-numbered checksum relation of its group, a
+ * checksum entry as its weighted sum.  MULTI locations are refused. */
+int abft_wcorrect(const abft_wproblem *p, void *C_f, const abft_location *locs, int n, void *ws, void *stream);
+/* Sec. 2.1 recovery of lost blocks.  dir ABFT_DIR_COL: blocks[] are block-row
+ * indices (g < Gr data block rows, Gr + r checksum block row r) lost over the
+ * columns [lo, lo + len); every column group solves for the lost data members
+ * with the lowest-numbered intact checksum relations (an s x s system, s <= fr,
+ * inverted on the host in binary64 with partial pivoting), then recomputes the
+ * lost checksum entries.  ABFT_DIR_ROW: block columns over the rows
+ * [lo, lo + len).  ABFT_E_UNRECOVERABLE when more data blocks are lost than
+ * checksum blocks survive or the system's 1-norm condition number exceeds 1e12. */
+int abft_wrecover(const abft_wproblem *p, void *C_f, int dir, const int32_t *blocks, int n_blocks, int64_t lo,
+                  int64_t len, void *ws, void *stream);
+
 /* Last hipError_t seen by this thread (0 if none), and a status message. */
 int abft_last_hip_error(void);
 const char *abft_status_string(int status);

@@ -78,6 +78,33 @@ class abft_batch_plan(C.Structure):
                 ("bytes", C.c_size_t)]
 
 
+ABFT_WMAX = 4
+
+
+class abft_wproblem(C.Structure):
+    _fields_ = [("p", abft_problem), ("fr", C.c_int32), ("fc", C.c_int32),
+                ("wr", C.POINTER(C.c_double)), ("wc", C.POINTER(C.c_double))]
+
+
+class abft_wgroup(C.Structure):
+    _fields_ = [("a", C.c_int64), ("b", C.c_int64), ("d", C.c_double * ABFT_WMAX), ("tau", C.c_double * ABFT_WMAX)]
+
+
+class abft_wreport(C.Structure):
+    _fields_ = [("n_fail_c", C.c_int64), ("n_fail_r", C.c_int64),
+                ("n_excl_c", C.c_int64), ("n_excl_r", C.c_int64),
+                ("max_ratio_c", C.c_double), ("max_ratio_r", C.c_double),
+                ("col", abft_wgroup * ABFT_MAX_FLAGS), ("row", abft_wgroup * ABFT_MAX_FLAGS)]
+
+    def groups_c(self, f):
+        g = self.col[:min(self.n_fail_c, ABFT_MAX_FLAGS)]
+        return sorted((x.a, x.b, list(x.d[:f]), list(x.tau[:f])) for x in g)
+
+    def groups_r(self, f):
+        g = self.row[:min(self.n_fail_r, ABFT_MAX_FLAGS)]
+        return sorted((x.a, x.b, list(x.d[:f]), list(x.tau[:f])) for x in g)
+
+
 _lib = None
 _V = C.c_void_p
 _P = C.POINTER
@@ -115,6 +142,16 @@ def lib():
             "abft_batch_tune": (C.c_int, [_P(abft_batch_plan), _P(C.c_int), _V]),
             "abft_batch_verify": (C.c_int, [_P(abft_batch_plan), _V]),
             "abft_batch_reports": (C.c_int, [_P(abft_batch_plan), _V, _V]),
+            "abft_wworkspace_size": (C.c_size_t, [_P(abft_wproblem)]),
+            "abft_wsetup": (C.c_int, [_P(abft_wproblem), _V]),
+            "abft_wencode": (C.c_int, [_P(abft_wproblem), _V, _V, _V, _V]),
+            "abft_wgemm": (C.c_int, [_P(abft_wproblem), _V, _V, _V, _V]),
+            "abft_wverify": (C.c_int, [_P(abft_wproblem), _V, _P(abft_rect), C.c_int, _V, _V, _V]),
+            "abft_wlocate": (C.c_int, [_P(abft_wproblem), _P(abft_wreport), _P(abft_location), C.c_int,
+                                       _P(C.c_int)]),
+            "abft_wcorrect": (C.c_int, [_P(abft_wproblem), _V, _P(abft_location), C.c_int, _V, _V]),
+            "abft_wrecover": (C.c_int, [_P(abft_wproblem), _V, C.c_int, _P(C.c_int32), C.c_int, C.c_int64,
+                                        C.c_int64, _V, _V]),
             "abft_last_hip_error": (C.c_int, []),
             "abft_status_string": (C.c_char_p, [C.c_int]),
         }
@@ -374,3 +411,104 @@ class Batch:
         raw = self.rep_host.numpy().tobytes()
         sz = C.sizeof(abft_report)
         return [abft_report.from_buffer_copy(raw[q * sz:(q + 1) * sz]) for q in range(len(self.probs))]
+
+
+# ---------------------------------------------------------------- weighted f-checksums (Sec. 2.1)
+def wproblem(m, n, k, br, bc, wr, wc, lda=None, ldb=None, ldc=None, tau_mode=ABFT_TAU_DET, kappa=0.0):
+    """wr (fr x m/br), wc (fc x n/bc): float64 numpy arrays kept alive by the
+    returned structure's `_keep` attribute (the library reads them on the host)."""
+    import numpy as np
+    wr = np.ascontiguousarray(wr, dtype=np.float64)
+    wc = np.ascontiguousarray(wc, dtype=np.float64)
+    fr, fc = wr.shape[0], wc.shape[0]
+    base = problem(ABFT_F64, m, n, k, br, bc, lda, ldb, ldc if ldc is not None else n + fc * bc,
+                   tau_mode=tau_mode, kappa=kappa)
+    wp = abft_wproblem(base, fr, fc, wr.ctypes.data_as(C.POINTER(C.c_double)),
+                       wc.ctypes.data_as(C.POINTER(C.c_double)))
+    wp._keep = (wr, wc)
+    return wp
+
+
+def wworkspace_size(wp) -> int:
+    return lib().abft_wworkspace_size(C.byref(wp))
+
+
+def wsetup(wp, ws):
+    return _check("abft_wsetup", lib().abft_wsetup(C.byref(wp), _ptr(ws)))
+
+
+def wencode(wp, A_f, B_f, ws, stream=None):
+    return _check("abft_wencode", lib().abft_wencode(C.byref(wp), _ptr(A_f), _ptr(B_f), _ptr(ws), _stream(stream)))
+
+
+def wgemm(wp, A_f, B_f, C_f, stream=None):
+    return _check("abft_wgemm", lib().abft_wgemm(C.byref(wp), _ptr(A_f), _ptr(B_f), _ptr(C_f), _stream(stream)))
+
+
+def wverify(wp, C_f, ws, known=None, host_out=None, stream=None):
+    arr, nk = _rects(known)
+    hp = C.c_void_p(host_out.data_ptr()) if host_out is not None else None
+    return _check("abft_wverify", lib().abft_wverify(C.byref(wp), _ptr(C_f), arr, nk, _ptr(ws), hp, _stream(stream)))
+
+
+def new_wreport_buffer():
+    import torch
+    return torch.empty(C.sizeof(abft_wreport), dtype=torch.uint8, pin_memory=True)
+
+
+def read_wreport(host_buf) -> abft_wreport:
+    return abft_wreport.from_buffer_copy(host_buf.numpy().tobytes())
+
+
+def wlocate(wp, rep: abft_wreport, max_out=ABFT_MAX_FLAGS):
+    """-> (status, [abft_location]); status ABFT_OK or ABFT_E_UNCORRECTABLE."""
+    out = (abft_location * max(1, max_out))()
+    n = C.c_int(0)
+    st = _check("abft_wlocate", lib().abft_wlocate(C.byref(wp), C.byref(rep), out, max_out, C.byref(n)),
+                ok=(ABFT_OK, ABFT_E_UNCORRECTABLE))
+    return st, [out[q] for q in range(min(n.value, max_out))]
+
+
+def wcorrect(wp, C_f, locs, ws, stream=None):
+    arr = (abft_location * max(1, len(locs)))(*locs)
+    return _check("abft_wcorrect", lib().abft_wcorrect(C.byref(wp), _ptr(C_f), arr, len(locs), _ptr(ws),
+                                                       _stream(stream)))
+
+
+def wrecover(wp, C_f, direction, blocks, lo, length, ws, stream=None):
+    blocks = list(blocks)
+    arr = (C.c_int32 * max(1, len(blocks)))(*blocks)
+    return _check("abft_wrecover", lib().abft_wrecover(C.byref(wp), _ptr(C_f), direction, arr, len(blocks), lo,
+                                                       length, _ptr(ws), _stream(stream)))
+
+
+class WProtected:
+    """Device buffers of one weighted-checksum product (binary64): A_f
+    ((m + fr br) x k), B_f^T ((n + fc bc) x k), C_f with rows padded to 16
+    bytes, the workspace (weights copied in) and a pinned report buffer."""
+
+    def __init__(self, m, n, k, br, bc, wr, wc, device="cuda", tau_mode=ABFT_TAU_DET):
+        import torch
+        fr, fc = len(wr), len(wc)
+        self.M, self.N = m + fr * br, n + fc * bc
+        self.ldc = (self.N + 1) // 2 * 2
+        self.p = wproblem(m, n, k, br, bc, wr, wc, ldc=self.ldc, tau_mode=tau_mode)
+        self.A = torch.zeros(self.M, k, dtype=torch.float64, device=device)
+        self.Bt = torch.zeros(self.N, k, dtype=torch.float64, device=device)
+        self.Cbuf = torch.zeros(self.M, self.ldc, dtype=torch.float64, device=device)
+        self.C = self.Cbuf[:, :self.N]
+        self.ws = torch.zeros(wworkspace_size(self.p), dtype=torch.uint8, device=device)
+        wsetup(self.p, self.ws)
+        self.rep_host = new_wreport_buffer()
+
+    def encode(self):
+        wencode(self.p, self.A, self.Bt, self.ws)
+
+    def gemm(self):
+        wgemm(self.p, self.A, self.Bt, self.C)
+
+    def verify(self, known=None) -> abft_wreport:
+        import torch
+        wverify(self.p, self.C, self.ws, known=known, host_out=self.rep_host)
+        torch.cuda.current_stream().synchronize()
+        return read_wreport(self.rep_host)

@@ -210,6 +210,9 @@ void set_hip_error(hipError_t e);
 
 // ------------------------------------------------------------------ launchers (return abft_status)
 int launch_encode(const abft_problem *p, void *A_f, void *B_f, char *ws, hipStream_t s);
+// Binary64 matrix-core product C = A B^T-stored (A: M x K rows, Bt: N x K rows), all M x N entries.
+int launch_gemm_f64(const double *A, int64_t lda, const double *Bt, int64_t ldb, double *C, int64_t ldc, int64_t M,
+                    int64_t N, int64_t K, hipStream_t s);
 int launch_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, int64_t k0, int64_t k1,
                       uint32_t flags, hipStream_t s);
 int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, void *ws,

@@ -130,6 +130,14 @@ static int protected_product_lowp(const abft_problem *p, const Geom &g, const ty
     return sliver<E, float, float>(A, p->lda, g.m, Bcs, g.k, g.bc, g.k, C + g.n, p->ldc, 1, scale_exp, s);
 }
 
+int launch_gemm_f64(const double *A, int64_t lda, const double *Bt, int64_t ldb, double *C, int64_t ldc, int64_t M,
+                    int64_t N, int64_t K, hipStream_t s) {
+    int st = gemm_main(A, lda, Bt, ldb, C, ldc, M, N, K, s);
+    if (st) return st;
+    ABFT_LAUNCHED();
+    return ABFT_OK;
+}
+
 int launch_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, int64_t k0, int64_t k1,
                       uint32_t flags, hipStream_t s) {
     Geom g = geom_of(p);

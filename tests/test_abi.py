@@ -169,3 +169,96 @@ def test_batch_setup_rejects_before_any_copy():
     assert L.abft_batch_setup(probs, misaligned, 1, C.c_void_p(0x40000), need, C.byref(plan)) == abft.ABFT_E_ARG
     assert L.abft_batch_gemm(None, 0, 0, None) == abft.ABFT_E_ARG
     assert L.abft_batch_verify(None, None) == abft.ABFT_E_ARG
+
+
+# ---------------------------------------------------------------- weighted f-checksums
+def test_weighted_struct_sizes():
+    assert C.sizeof(abft.abft_wproblem) == C.sizeof(abft.abft_problem) + 4 + 4 + 8 + 8
+    assert C.sizeof(abft.abft_wgroup) == 16 + 2 * 8 * abft.ABFT_WMAX
+    assert C.sizeof(abft.abft_wreport) == 8 * 6 + 2 * 64 * C.sizeof(abft.abft_wgroup)
+
+
+def _wp(**kw):
+    args = dict(m=256, n=192, k=128, br=64, bc=64, wr=np.ones((2, 4)), wc=np.ones((2, 3)))
+    args.update(kw)
+    return abft.wproblem(**args)
+
+
+def test_weighted_bad_problems_rejected_before_launch():
+    fake = C.c_void_p(256)
+    assert abft.wworkspace_size(_wp()) > 0
+    bad = [
+        (_wp(wr=np.ones((5, 4))), abft.ABFT_E_ARG),                   # fr > ABFT_WMAX
+        (_wp(wr=np.array([[1.0, np.nan, 1.0, 1.0]])), abft.ABFT_E_ARG),  # weights must be finite
+        (_wp(k=127), abft.ABFT_E_ARG),                               # k odd: rows not 16-byte multiples
+        (_wp(ldc=200), abft.ABFT_E_ARG),                             # ldc < n + fc*bc
+        (_wp(tau_mode=abft.ABFT_TAU_STAT), abft.ABFT_E_UNSUPPORTED),
+    ]
+    for wp, want in bad:
+        assert abft.wworkspace_size(wp) == 0
+        assert _call("abft_wencode", C.byref(wp), fake, fake, fake, NULL_STREAM) == want
+    wp = _wp()
+    wp.p.dtype = abft.ABFT_BF16
+    assert _call("abft_wgemm", C.byref(wp), fake, fake, fake, NULL_STREAM) == abft.ABFT_E_UNSUPPORTED
+    wp = _wp()
+    assert _call("abft_wencode", C.byref(wp), C.c_void_p(8), fake, fake, NULL_STREAM) == abft.ABFT_E_ARG
+    assert _call("abft_wencode", C.byref(wp), fake, fake, None, NULL_STREAM) == abft.ABFT_E_WORKSPACE
+    blocks = (C.c_int32 * 3)(0, 1, 2)
+    # three data blocks lost with two checksums: refused on the host
+    assert _call("abft_wrecover", C.byref(wp), fake, abft.ABFT_DIR_COL, blocks, 3, 0, 10, fake,
+                 NULL_STREAM) == abft.ABFT_E_UNRECOVERABLE
+    # a singular system: two equal weight columns
+    ws = _wp(wr=np.array([[1.0, 1.0, 1.0, 1.0], [1.0, 2.0, 2.0, 3.0]]))
+    two = (C.c_int32 * 2)(1, 2)
+    assert _call("abft_wrecover", C.byref(ws), fake, abft.ABFT_DIR_COL, two, 2, 0, 10, fake,
+                 NULL_STREAM) == abft.ABFT_E_UNRECOVERABLE
+    assert _call("abft_wrecover", C.byref(wp), fake, abft.ABFT_DIR_COL, two, 2, 0, 1000, fake,
+                 NULL_STREAM) == abft.ABFT_E_ARG                      # beyond the columns of C_f
+
+
+def _to_wreport(orep, fr, fc):
+    rep = abft.abft_wreport()
+    rep.n_fail_c, rep.n_fail_r = len(orep["col"]), len(orep["row"])
+    # the device writes groups in arbitrary order: feed them reversed
+    for q, (a, b, d, t) in enumerate(reversed(orep["col"][:64])):
+        rep.col[q].a, rep.col[q].b = a, b
+        for r in range(fr):
+            rep.col[q].d[r], rep.col[q].tau[r] = d[r], t[r]
+    for q, (a, b, d, t) in enumerate(reversed(orep["row"][:64])):
+        rep.row[q].a, rep.row[q].b = a, b
+        for c in range(fc):
+            rep.row[q].d[c], rep.row[q].tau[c] = d[c], t[c]
+    return rep
+
+
+@pytest.mark.parametrize("fr,fc", [(2, 2), (1, 3), (3, 1), (1, 1)])
+def test_weighted_location_matches_oracle(orc, fr, fc):
+    """abft_wlocate (host C++) takes the oracle's decisions on the oracle's own
+    reports: every element of a small C_f, several exponent bits, and pairs."""
+    from oracle import weighted as wo
+    m, n, k, br, bc = 8, 6, 4, 2, 3
+    A = synth.uniform_ints(4, synth.STREAM_A, m, k, -8, 8)
+    B = synth.uniform_ints(4, synth.STREAM_B, k, n, -8, 8)
+    Wr = 0.5 + (synth.uniform(4, synth.STREAM_X, fr, m // br) + 1) / 2
+    Wc = 0.5 + (synth.uniform(4, synth.STREAM_PICK, fc, n // bc) + 1) / 2
+    Af, Bf, Cf = wo.wproduct(A, B, Wr, Wc, br, bc)
+    tc, tr = wo.wtau_det(Af, Bf, m, n, br, bc, Wr, Wc)
+    wp = abft.wproblem(m, n, k, br, bc, Wr, Wc)
+    M, N = Cf.shape
+    cases = [[(x, y, bit)] for x in range(M) for y in range(N) for bit in (45, 52, 61)]
+    cases += [[(0, 0, 60), (M - 1, N - 1, 58)], [(1, 2, 55), (3, 2, 55)], [(2, 1, 57), (2, 4, 57)]]
+    checked = 0
+    for case in cases:
+        Cx = Cf.copy()
+        for (x, y, bit) in case:
+            v = np.array([Cx[x, y]]).view(np.uint64) ^ np.uint64(1 << bit)
+            Cx[x, y] = v.view(np.float64)[0]
+        orep = wo.wverify(Cx, m, n, br, bc, Wr, Wc, tc, tr)
+        want = wo.wlocate(orep["col"], orep["row"], m, n, br, bc, Wr, Wc)
+        st, got = abft.wlocate(wp, _to_wreport(orep, fr, fc))
+        got = [(l.cls, l.dir, l.i, l.j) if l.cls != abft.ABFT_CLS_MULTI else (l.cls, l.dir) for l in got]
+        want = [w if w[0] != wo.MULTI else (w[0], w[1]) for w in want]
+        assert got == want, (case, got, want)
+        assert (st == abft.ABFT_E_UNCORRECTABLE) == any(w[0] == wo.MULTI for w in want)
+        checked += 1
+    assert checked == len(cases)
