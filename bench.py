@@ -15,7 +15,7 @@ timed on a bounded sample of the same product (rank 0, N = 1 only).
 With --workload c2panel the product runs as a loop of panel updates
 (outer-product form) and the erasure and flip are repaired mid-loop.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2|c2b1|c2panel|c1|c1b64|c3|c4|c4fp8|c5]
+    python bench.py [--steps K] [--warmup W] [--workload c2|c2b1|c2panel|c2w|c1|c1b64|c3|c4|c4fp8|c5]
                     [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -43,10 +43,14 @@ WORKLOADS = {
     # the same product as c2 computed as 8 rank-1024 panel updates; the block is lost, and the flip
     # lands, half-way through the k loop and both are repaired there before the loop goes on
     "c2panel": ("f64", 8192, 8192, 8192, 1024, True),
+    "c2w": ("f64", 8192, 8192, 8192, 512, True),
     # batched: 512 bfloat16 problems, m, n, k uniform on multiples of 32 in [64, 2048]
     "c5": ("bf16", 0, 0, 0, 32, True),
 }
 PANELS = {"c2panel": 8}
+# weighted f-checksums (Sec. 2.1): n = 8192, 512 x 512 blocks (16 x 16 grid), two weighted checksum block rows
+# and columns; per step two blocks of one block column are lost and two flips land in other column groups
+WEIGHTED = {"c2w": {"dtype": "f64", "m": 8192, "n": 8192, "k": 8192, "b": 512, "f": 2, "flips": 2}}
 BATCH = {"count": 512, "lo": 64, "hi": 2048, "step": 32, "br": 32, "bc": 1, "lam": 20.0,
          "flips": 5, "erasures": 3}
 # flip bits per C type: binary64 40..62; binary32 24..29 (exponent bits and the
@@ -287,6 +291,125 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def run_weighted(args):
+    """Weighted f-checksum step: encode (f weighted checksum block rows and
+    columns), product, f lost blocks of one block column and flips in other
+    column groups, verify with the loss known, locate the flips from the
+    weight ratios, correct, rebuild the f blocks (f x f solve), re-verify."""
+    import torch
+
+    from paper_0806_3121_amd import abft, synth
+
+    cfg = WEIGHTED[args.workload]
+    m, n, k, b, f = cfg["m"], cfg["n"], cfg["k"], cfg["b"], cfg["f"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    Gr, Gc = m // b, n // b
+    Wr = 0.5 + (synth.uniform(SEED, synth.STREAM_X, f, Gr) + 1) / 2
+    Wc = 0.5 + (synth.uniform(SEED, synth.STREAM_PICK, f, Gc) + 1) / 2
+    log(f"workload {args.workload}: f64 m={m} n={n} k={k} b={b} f={f}")
+    P = abft.WProtected(m, n, k, b, b, Wr, Wc, device=dev)
+    abft.fill_uniform(abft.ABFT_F64, m, k, k, 0, SEED, synth.STREAM_A, P.A)
+    abft.fill_uniform(abft.ABFT_F64, k, n, k, 1, SEED, synth.STREAM_B, P.Bt)
+    Cplain = torch.empty(m, n, dtype=torch.float64, device=dev)
+    pplain = abft.problem(abft.ABFT_F64, m, n, k, b, b, ldc=n)
+    torch.cuda.synchronize()
+    bit_lo, bit_hi = FLIP_BITS["f64"]
+    g_events = []
+
+    def step(s):
+        P.encode()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        P.gemm()
+        e1.record(stream)
+        g_events.append((e0, e1))
+        # f lost blocks of one block column (f failed processes of a process column)
+        I = synth.pick_distinct(SEED + s, f, Gr, stream=synth.STREAM_ERASE)
+        J = synth.randint(SEED, synth.STREAM_ERASE, 1000 + s, Gc)
+        rects = [(i * b, J * b, b, b) for i in I]
+        sites, groups, t = [], set(), 0
+        while len(sites) < cfg["flips"]:
+            x, y, bit = synth.flip_site(SEED, 4 * s + t, m, n, bit_lo, bit_hi, avoid=(0, J * b, m, b))
+            t += 1
+            if (x % b, y) not in groups:
+                groups.add((x % b, y))
+                sites.append((x, y, bit))
+        for (x, y, bit) in sites:
+            v = P.C[x, y].view(torch.int64) ^ (1 << bit)
+            P.C[x, y] = v.view(torch.float64)
+        for (i0, j0, h, w) in rects:
+            P.C[i0:i0 + h, j0:j0 + w] = float("nan")
+        rep = P.verify(known=rects)
+        st, locs = abft.wlocate(P.p, rep)
+        got = sorted((l.cls, l.i, l.j) for l in locs)
+        want = sorted((abft.ABFT_CLS_DATA, x, y) for (x, y, _) in sites)
+        if st != abft.ABFT_OK or got != want:
+            raise RuntimeError(f"step {s}: flips {sites} located as {got}")
+        abft.wcorrect(P.p, P.C, locs, P.ws)
+        abft.wrecover(P.p, P.C, abft.ABFT_DIR_COL, I, J * b, b, P.ws)
+        rep = P.verify()
+        if rep.n_fail_c or rep.n_fail_r:
+            raise RuntimeError(f"step {s}: not clean after repair")
+
+    for s in range(args.warmup):
+        step(1000 + s)
+    g_events.clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(s)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"timed {args.steps} steps in {dt:.3f} s")
+    gemm_ms = sum(a.elapsed_time(c) for a, c in g_events) / len(g_events)
+    pe = []
+    for s in range(0 if args.no_plain else max(3, min(args.steps, 10))):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        abft.gemm(pplain, P.A, P.Bt, Cplain, None, flags=abft.ABFT_PLAIN)
+        e1.record(stream)
+        pe.append((e0, e1))
+    torch.cuda.synchronize()
+    plain_ms = sum(a.elapsed_time(c) for a, c in pe[1:]) / len(pe[1:]) if pe else None
+    peak = PEAK["f64"]
+    useful = 2.0 * m * n * k
+    executed = 2.0 * (m + f * b) * (n + f * b) * k
+    ms_step = dt / args.steps * 1e3
+    value = useful / (ms_step * 1e-3) / 1e12
+    achieved = executed / (gemm_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"F64 weighted-checksum GEMM {args.workload}: m={m} n={n} k={k}, {b}x{b} blocks "
+                               f"({Gr}x{Gc} grid), {f} weighted checksum block rows and columns (weights uniform "
+                               f"in [0.5, 1.5)); per step {f} lost blocks of one block column rebuilt by an "
+                               f"{f}x{f} solve and {cfg['flips']} flips located by weight ratios",
+                   "m": m, "n": n, "k": k, "br": b, "bc": b, "f": f, "global_batch": 1, "seq_len": 0,
+                   "parallelism": "single-gpu"},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": TRAFFIC.get(args.workload),
+                     "kernel": "k_gemm_mfma (weighted-checksum product, all M x N entries)",
+                     "flops_per_launch": executed, "avg_launch_ms": round(gemm_ms, 4)},
+        "pct_mfma_peak_useful": round(100 * value / peak, 2),
+        "gemm_protected_ms": round(gemm_ms, 4),
+        "gemm_plain_ms": round(plain_ms, 4) if plain_ms else None,
+        "abft_overhead_pct": round(100 * (gemm_ms / plain_ms - 1), 2) if plain_ms else None,
+        "abft_floor_pct": round(100 * (executed / useful - 1), 2),
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        tf, thr, sec, rows = cpu_baseline("f64", m, n, k, f * b, args.cpu_seconds)
+        out["cpu_baseline"] = {"value": round(tf, 6), "unit": "TFLOP/s", "cores": thr, "kind": "oracle",
+                               "sample": f"rows 0..{rows - 1} of an encoded product ({rows} x {n + f * b} x {k}, "
+                                         f"FP64 i-l-j loops), {sec:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def run_campaign(args):
     """Reliability campaign on one workload: args.campaign clean products on
     fresh seeded inputs (every relation must pass: false positives are counted),
@@ -483,9 +606,14 @@ def main():
         sys.exit(2)
 
     if args.campaign:
+        if args.workload in WEIGHTED or args.workload in PANELS:
+            print(json.dumps({"error": f"--campaign is not defined for workload {args.workload}"}))
+            sys.exit(2)
         return run_batched_campaign(args) if args.workload == "c5" else run_campaign(args)
     if args.workload == "c5":
         return run_batched(args)
+    if args.workload in WEIGHTED:
+        return run_weighted(args)
 
     import torch
 

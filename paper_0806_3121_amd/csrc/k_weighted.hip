@@ -84,11 +84,18 @@ __device__ inline unsigned long long wsum_u(unsigned long long v) {
     for (int o = kW / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
-// One atomic per wave for the max ratio (non-negative doubles order as their bits) and the exclusions.
-__device__ inline void fold_wave(double ratio, unsigned long long excl, double *rep_ratio, int64_t *rep_excl) {
+// One atomic per block for the max ratio (non-negative doubles order as their
+// bits) and the exclusions; every thread of the block must call it.
+__device__ inline void fold_block(double ratio, unsigned long long excl, double *rep_ratio, int64_t *rep_excl) {
+    __shared__ double s_r[kT / kW];
+    __shared__ unsigned long long s_e[kT / kW];
     ratio = wmax(ratio);
     excl = wsum_u(excl);
-    if ((threadIdx.x % kW) == 0) {
+    const int lane = threadIdx.x % kW, w = threadIdx.x / kW;
+    if (lane == 0) { s_r[w] = ratio; s_e[w] = excl; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < kT / kW; ++q) { ratio = fmax(ratio, s_r[q]); excl += s_e[q]; }
         if (ratio > 0) atomicMax((unsigned long long *)rep_ratio, (unsigned long long)__double_as_longlong(ratio));
         if (excl) atomicAdd((unsigned long long *)rep_excl, excl);
     }
@@ -230,25 +237,51 @@ __device__ inline void col_finish(const VArgs &a, const double *C, int64_t i, in
     ratio = fmax(ratio, group<F>(a.rep, true, i, j, d, t));
 }
 
-// Direct: one thread per (i, j), all Gr blocks.
+// Direct: one thread per (i, column pair), all Gr blocks; the block loop is
+// unrolled so several rows are in flight.  vec: rows of C_f start on 16-byte
+// boundaries (C aligned, ldc even).
 template <int F>
-__global__ __launch_bounds__(kT) void k_wvcol(const double *__restrict__ C, VArgs a) {
-    const int64_t total = a.br * a.N;
+__global__ __launch_bounds__(kT) void k_wvcol(const double *__restrict__ C, VArgs a, int vec) {
+    const int64_t NP = (a.N + 1) / 2, total = a.br * NP;
     double ratio = 0.0;
     unsigned long long excl = 0;
     for (int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x; t < total; t += (int64_t)gridDim.x * kT) {
-        const int64_t i = t / a.N, j = t - i * a.N;
-        double s[F];
+        const int64_t i = t / NP, j = (t - i * NP) * 2;
+        const bool two = j + 1 < a.N;
+        double s[F][2];
 #pragma unroll
-        for (int r = 0; r < F; ++r) s[r] = 0.0;
-        for (int64_t g = 0; g < a.Gr; ++g) {
-            const double v = C[(g * a.br + i) * a.ldc + j];
+        for (int r = 0; r < F; ++r) s[r][0] = s[r][1] = 0.0;
+        const double *col = C + i * a.ldc + j;
+        if (two && vec) {
+#pragma unroll 4
+            for (int64_t g = 0; g < a.Gr; ++g) {
+                double v[2];
+                vec16<double>::load(col + g * a.br * a.ldc, v);
 #pragma unroll
-            for (int r = 0; r < F; ++r) s[r] += a.wr[r * a.Gr + g] * v;
+                for (int r = 0; r < F; ++r) {
+                    s[r][0] += a.wr[r * a.Gr + g] * v[0];
+                    s[r][1] += a.wr[r * a.Gr + g] * v[1];
+                }
+            }
+        } else {
+#pragma unroll 4
+            for (int64_t g = 0; g < a.Gr; ++g) {
+                const double *e = col + g * a.br * a.ldc;
+                const double v0 = e[0], v1 = two ? e[1] : 0.0;
+#pragma unroll
+                for (int r = 0; r < F; ++r) {
+                    s[r][0] += a.wr[r * a.Gr + g] * v0;
+                    s[r][1] += a.wr[r * a.Gr + g] * v1;
+                }
+            }
         }
-        col_finish<F>(a, C, i, j, s, ratio, excl);
+        double s0[F], s1[F];
+#pragma unroll
+        for (int r = 0; r < F; ++r) { s0[r] = s[r][0]; s1[r] = s[r][1]; }
+        col_finish<F>(a, C, i, j, s0, ratio, excl);
+        if (two) col_finish<F>(a, C, i, j + 1, s1, ratio, excl);
     }
-    fold_wave(ratio, excl, &a.rep->max_ratio_c, &a.rep->n_excl_c);
+    fold_block(ratio, excl, &a.rep->max_ratio_c, &a.rep->n_excl_c);
 }
 
 // Partitioned: partial sums of a run of blocks per (p, i, j), then the finish.
@@ -288,7 +321,7 @@ __global__ __launch_bounds__(kT) void k_wvcol_fin(const double *__restrict__ C, 
         }
         col_finish<F>(a, C, i, j, s, ratio, excl);
     }
-    fold_wave(ratio, excl, &a.rep->max_ratio_c, &a.rep->n_excl_c);
+    fold_block(ratio, excl, &a.rep->max_ratio_c, &a.rep->n_excl_c);
 }
 
 template <int F>
@@ -304,26 +337,41 @@ __device__ inline void row_finish(const VArgs &a, const double *C, int64_t x, in
     ratio = fmax(ratio, group<F>(a.rep, false, x, jj, d, t));
 }
 
-// Row groups, wide blocks (bc >= 64): one thread per (x, jj), consecutive jj read consecutive columns.
+// Row groups, wide blocks (bc >= 64, even): one thread per (x, residue pair),
+// consecutive pairs read consecutive columns; the block loop is unrolled.
 template <int F>
-__global__ __launch_bounds__(kT) void k_wvrow_thread(const double *__restrict__ C, VArgs a) {
-    const int64_t total = a.M * a.bc;
+__global__ __launch_bounds__(kT) void k_wvrow_thread(const double *__restrict__ C, VArgs a, int vec) {
+    const int64_t BP = a.bc / 2, total = a.M * BP;
     double ratio = 0.0;
     unsigned long long excl = 0;
     for (int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x; t < total; t += (int64_t)gridDim.x * kT) {
-        const int64_t x = t / a.bc, jj = t - x * a.bc;
+        const int64_t x = t / BP, jj = (t - x * BP) * 2;
         const double *row = C + x * a.ldc + jj;
-        double s[F];
+        double s[F][2];
 #pragma unroll
-        for (int c = 0; c < F; ++c) s[c] = 0.0;
+        for (int c = 0; c < F; ++c) s[c][0] = s[c][1] = 0.0;
+#pragma unroll 4
         for (int64_t h = 0; h < a.Gc; ++h) {
-            const double v = row[h * a.bc];
+            double v[2];
+            if (vec) {
+                vec16<double>::load(row + h * a.bc, v);
+            } else {
+                v[0] = row[h * a.bc];
+                v[1] = row[h * a.bc + 1];
+            }
 #pragma unroll
-            for (int c = 0; c < F; ++c) s[c] += a.wc[c * a.Gc + h] * v;
+            for (int c = 0; c < F; ++c) {
+                s[c][0] += a.wc[c * a.Gc + h] * v[0];
+                s[c][1] += a.wc[c * a.Gc + h] * v[1];
+            }
         }
-        row_finish<F>(a, C, x, jj, s, ratio, excl);
+        double s0[F], s1[F];
+#pragma unroll
+        for (int c = 0; c < F; ++c) { s0[c] = s[c][0]; s1[c] = s[c][1]; }
+        row_finish<F>(a, C, x, jj, s0, ratio, excl);
+        row_finish<F>(a, C, x, jj + 1, s1, ratio, excl);
     }
-    fold_wave(ratio, excl, &a.rep->max_ratio_r, &a.rep->n_excl_r);
+    fold_block(ratio, excl, &a.rep->max_ratio_r, &a.rep->n_excl_r);
 }
 
 // Row groups, narrow blocks (bc < 64): one wave per (x, jj), the lanes split
@@ -350,7 +398,7 @@ __global__ __launch_bounds__(kT) void k_wvrow_wave(const double *__restrict__ C,
         for (int c = 0; c < F; ++c) s[c] = wsum(s[c]);
         if (lane == 0) row_finish<F>(a, C, x, jj, s, ratio, excl);
     }
-    fold_wave(ratio, excl, &a.rep->max_ratio_r, &a.rep->n_excl_r);
+    fold_block(ratio, excl, &a.rep->max_ratio_r, &a.rep->n_excl_r);
 }
 
 // ------------------------------------------------------------------ recovery
@@ -420,6 +468,9 @@ __global__ __launch_bounds__(kT) void k_wrecover(double *__restrict__ C, RArgs a
 }
 
 unsigned grid(int64_t work) { return (unsigned)std::min<int64_t>(std::max<int64_t>((work + kT - 1) / kT, 1), 65536); }
+// Verification grids: enough blocks to fill the chip (8 waves per SIMD), few
+// enough that the one atomic per block stays cheap.
+unsigned vgrid(int64_t work) { return std::min<unsigned>(grid(work), 2048); }
 
 // Run STMT with the compile-time checksum count F = fv (1..ABFT_WMAX).
 #define WSWITCH(fv, STMT)                                 \
@@ -677,20 +728,22 @@ int abft_wverify(const abft_wproblem *p, const void *C_f, const abft_rect *known
     a.rep = (abft_wreport *)(w + L.report);
     const double *C = (const double *)C_f;
     k_wreport_init<<<1, kW, 0, s>>>(a.rep);
+    // 16-byte loads when every row of C_f starts on a 16-byte boundary
+    const int vec = ((uintptr_t)C_f % 16 == 0) && (g.ldc % 2 == 0);
     int64_t P = parts(g.Gr, g.br * g.N);
     if (P == 1) {
-        WSWITCH(g.fr, (k_wvcol<F><<<grid(g.br * g.N), kT, 0, s>>>(C, a)));
+        WSWITCH(g.fr, (k_wvcol<F><<<vgrid(g.br * ((g.N + 1) / 2)), kT, 0, s>>>(C, a, vec)));
     } else {
         const int64_t chunk = (g.Gr + P - 1) / P;
         P = (g.Gr + chunk - 1) / chunk;
         double *part = (double *)(w + L.part);
         WSWITCH(g.fr, (k_wvcol_part<F><<<grid(P * g.br * g.N), kT, 0, s>>>(C, a, P, chunk, part)));
-        WSWITCH(g.fr, (k_wvcol_fin<F><<<grid(g.br * g.N), kT, 0, s>>>(C, a, P, part)));
+        WSWITCH(g.fr, (k_wvcol_fin<F><<<vgrid(g.br * g.N), kT, 0, s>>>(C, a, P, part)));
     }
-    if (g.bc >= kW) {
-        WSWITCH(g.fc, (k_wvrow_thread<F><<<grid(g.M * g.bc), kT, 0, s>>>(C, a)));
+    if (g.bc >= kW && g.bc % 2 == 0) {
+        WSWITCH(g.fc, (k_wvrow_thread<F><<<vgrid(g.M * (g.bc / 2)), kT, 0, s>>>(C, a, vec)));
     } else {
-        WSWITCH(g.fc, (k_wvrow_wave<F><<<grid(g.M * g.bc * kW), kT, 0, s>>>(C, a)));
+        WSWITCH(g.fc, (k_wvrow_wave<F><<<vgrid(g.M * g.bc * kW), kT, 0, s>>>(C, a)));
     }
     ABFT_LAUNCHED();
     if (host_out) ABFT_HIP(hipMemcpyAsync(host_out, a.rep, sizeof(abft_wreport), hipMemcpyDeviceToHost, s));
