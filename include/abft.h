@@ -90,6 +90,10 @@ typedef enum { ABFT_TAU_DET = 0, ABFT_TAU_STAT = 1, ABFT_TAU_EXACT = 2 } abft_ta
                            unprotected baseline the overhead is measured against */
 #define ABFT_ACCUMULATE 2u /* abft_gemm_panel only: add the panel product to C_f
                               instead of overwriting it */
+#define ABFT_FUSED 4u      /* abft_gemm, br = bc = 1 only: the product kernel's
+                              epilogue also writes binary64 partial sums of each
+                              tile's columns and rows into ws (the fused checksum
+                              accumulation) for abft_verify_fused */
 
 /*
  * Problem descriptor.  Layouts (elements of the dtype, not bytes):
@@ -222,6 +226,30 @@ int abft_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, voi
  */
 int abft_verify(const abft_problem *p, const void *C_f, const abft_rect *known, int n_known,
                 void *ws, abft_report *host_out, void *stream);
+
+/*
+ * Fused verification (Sec. 2.2 consistency, br = bc = 1): the column
+ * relations of the data columns and the row relations of the data rows are
+ * formed from the partial sums the last abft_gemm with ABFT_FUSED on this ws
+ * wrote in its epilogue (summed over the tiles in binary64), instead of
+ * re-reading C; the carried row and column are summed from C_f.  The partials
+ * describe C as the product kernel produced it: an error made inside the
+ * computation (see abft_arm_accumulator_flip) reaches both C and the partials
+ * and is seen here, while a change of C_f in memory after the product is seen
+ * only by abft_verify.  Same report, thresholds and flags as abft_verify (no
+ * known erasures).  ABFT_E_ARG if no fused product was recorded for ws.
+ */
+int abft_verify_fused(const abft_problem *p, const void *C_f, void *ws, abft_report *host_out, void *stream);
+
+/*
+ * Test hook (fault injection inside the computation): arm a one-shot flip of
+ * bit `bit` of the accumulator of element (i, j) of C (i < m, j < n) in the
+ * next abft_gemm that uses ws; the product kernel flips it after the k loop,
+ * before its epilogue stores C and forms the fused partial sums.  bit < 64
+ * for ABFT_F64 (binary64 accumulator), < 32 otherwise (binary32).  Host only;
+ * the arming is consumed by that call.
+ */
+int abft_arm_accumulator_flip(const abft_problem *p, void *ws, int64_t i, int64_t j, int bit);
 
 /*
  * Classify a report (host only, no device work; single-error model):

@@ -18,6 +18,7 @@ ABFT_E_ARG, ABFT_E_HIP, ABFT_E_UNCORRECTABLE, ABFT_E_UNRECOVERABLE, ABFT_E_WORKS
 ABFT_TAU_DET, ABFT_TAU_STAT, ABFT_TAU_EXACT = 0, 1, 2
 ABFT_PLAIN = 1
 ABFT_ACCUMULATE = 2
+ABFT_FUSED = 4
 ABFT_CLS_CLEAN, ABFT_CLS_DATA, ABFT_CLS_CHECKSUM, ABFT_CLS_MULTI = 0, 1, 2, 3
 ABFT_DIR_COL, ABFT_DIR_ROW = 0, 1
 ABFT_MAX_FLAGS = 64
@@ -124,6 +125,8 @@ def lib():
             "abft_gemm_panel": (C.c_int, [_P(abft_problem), _V, _V, _V, C.c_int64, C.c_int64, C.c_uint32, _V]),
             "abft_quantize": (C.c_int, [_P(abft_problem), C.c_int, _V, C.c_int64, _V, _V, _V]),
             "abft_verify": (C.c_int, [_P(abft_problem), _V, _P(abft_rect), C.c_int, _V, _V, _V]),
+            "abft_verify_fused": (C.c_int, [_P(abft_problem), _V, _V, _V, _V]),
+            "abft_arm_accumulator_flip": (C.c_int, [_P(abft_problem), _V, C.c_int64, C.c_int64, C.c_int]),
             "abft_classify": (C.c_int, [_P(abft_problem), _P(abft_report), _P(abft_rect), C.c_int,
                                         _P(abft_location)]),
             "abft_correct": (C.c_int, [_P(abft_problem), _V, _P(abft_location), _V]),
@@ -231,6 +234,15 @@ def verify(p, C_f, ws, known=None, host_out=None, stream=None):
     arr, nk = _rects(known)
     hp = C.c_void_p(host_out.data_ptr()) if host_out is not None else None
     return _check("abft_verify", lib().abft_verify(C.byref(p), _ptr(C_f), arr, nk, _ptr(ws), hp, _stream(stream)))
+
+
+def verify_fused(p, C_f, ws, host_out=None, stream=None):
+    hp = C.c_void_p(host_out.data_ptr()) if host_out is not None else None
+    return _check("abft_verify_fused", lib().abft_verify_fused(C.byref(p), _ptr(C_f), _ptr(ws), hp, _stream(stream)))
+
+
+def arm_accumulator_flip(p, ws, i, j, bit):
+    return _check("abft_arm_accumulator_flip", lib().abft_arm_accumulator_flip(C.byref(p), _ptr(ws), i, j, bit))
 
 
 def new_report_buffer():
@@ -352,6 +364,12 @@ class Protected:
     def verify(self, known=None) -> abft_report:
         import torch
         verify(self.p, self.C, self.ws, known=known, host_out=self.rep_host)
+        torch.cuda.current_stream().synchronize()
+        return read_report(self.rep_host)
+
+    def verify_fused(self) -> abft_report:
+        import torch
+        verify_fused(self.p, self.C, self.ws, host_out=self.rep_host)
         torch.cuda.current_stream().synchronize()
         return read_report(self.rep_host)
 

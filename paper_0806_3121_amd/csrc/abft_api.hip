@@ -57,6 +57,11 @@ WsLayout ws_layout(const abft_problem *p) {
     L.partial_bytes = sizeof(double) * need;
     L.partial = take(L.partial_bytes > 0 ? L.partial_bytes : 8);
     L.report = take(sizeof(abft_report));
+    // fused partials (b = 1 only): column sums per tile row, row sums per tile column
+    const bool fused = g.br == 1 && g.bc == 1;
+    const int64_t tm = (g.m + kMinTileEdge - 1) / kMinTileEdge, tn = (g.n + kMinTileEdge - 1) / kMinTileEdge;
+    L.fused_c = take(fused ? sizeof(double) * tm * g.n : 8);
+    L.fused_r = take(fused ? sizeof(double) * tn * g.m : 8);
     L.total = off;
     return L;
 }
@@ -255,7 +260,12 @@ int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f
               void *stream) {
     int st = check_problem(p);
     if (st) return st;
-    if (flags & ~ABFT_PLAIN) return ABFT_E_ARG;
+    if (flags & ~(ABFT_PLAIN | ABFT_FUSED)) return ABFT_E_ARG;
+    if (flags & ABFT_FUSED) {
+        if (flags & ABFT_PLAIN) return ABFT_E_ARG;
+        if (p->br != 1 || p->bc != 1) return ABFT_E_UNSUPPORTED;
+        if (!ws) return ABFT_E_WORKSPACE;
+    }
     if ((st = check_operands(p, A_f, B_f))) return st;
     if ((st = check_c(p, C_f, flags & ABFT_PLAIN))) return st;
     if (!ws && (p->dtype == ABFT_FP8_E4M3 || (p->dtype == ABFT_BF16 && !(flags & ABFT_PLAIN)))) return ABFT_E_WORKSPACE;
@@ -273,6 +283,33 @@ int abft_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, voi
     const int64_t align = 16 / (int64_t)dtype_size(p->dtype);
     if (k0 < 0 || k1 <= k0 || k1 > p->k || k0 % align || k1 % align) return ABFT_E_ARG;
     return launch_gemm_panel(p, A_f, B_f, C_f, k0, k1, flags, (hipStream_t)stream);
+}
+
+int abft_verify_fused(const abft_problem *p, const void *C_f, void *ws, abft_report *host_out, void *stream) {
+    int st = check_problem(p);
+    if (st) return st;
+    if ((st = check_c(p, C_f, false))) return st;
+    if (!ws) return ABFT_E_WORKSPACE;
+    if (p->br != 1 || p->bc != 1) return ABFT_E_UNSUPPORTED;
+    int64_t tm = 0, tn = 0;
+    if (!fused_grid(ws, &tm, &tn)) return ABFT_E_ARG;
+    if ((st = launch_verify_fused(p, C_f, (char *)ws, tm, tn, (hipStream_t)stream))) return st;
+    if (host_out) {
+        WsLayout L = ws_layout(p);
+        ABFT_HIP(hipMemcpyAsync(host_out, (char *)ws + L.report, sizeof(abft_report), hipMemcpyDeviceToHost,
+                                (hipStream_t)stream));
+    }
+    return ABFT_OK;
+}
+
+int abft_arm_accumulator_flip(const abft_problem *p, void *ws, int64_t i, int64_t j, int bit) {
+    int st = check_problem(p);
+    if (st) return st;
+    if (!ws) return ABFT_E_WORKSPACE;
+    if (i < 0 || i >= p->m || j < 0 || j >= p->n) return ABFT_E_ARG;
+    if (bit < 0 || bit >= (p->dtype == ABFT_F64 ? 64 : 32)) return ABFT_E_ARG;
+    arm_accumulator_flip(ws, i, j, bit);
+    return ABFT_OK;
 }
 
 int abft_verify(const abft_problem *p, const void *C_f, const abft_rect *known, int n_known, void *ws,

@@ -186,6 +186,7 @@ struct WsLayout {
     size_t acs, bcs;                 // binary32 checksum rows of low-precision operands (float, br*k / bc*k)
     size_t scale;                    // FP8 per-tensor scale exponents and amax scratch (4 x int32)
     size_t partial;                  // two-level reduction partials (double)
+    size_t fused_c, fused_r;         // product-epilogue partial sums for b = 1 (double; see fused_bound)
     size_t report;                   // abft_report
     size_t total;
     size_t partial_bytes;
@@ -218,6 +219,14 @@ int launch_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, v
 int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, void *ws,
                 hipStream_t s);
 int launch_verify(const abft_problem *p, const void *C_f, const Erasures &er, char *ws, hipStream_t s);
+int launch_verify_fused(const abft_problem *p, const void *C_f, char *ws, int64_t tiles_m, int64_t tiles_n,
+                        hipStream_t s);
+// Fused partial sums of the last ABFT_FUSED product into ws (tile grid), and
+// the one-shot accumulator flip armed for the next product into ws.
+bool fused_grid(const void *ws, int64_t *tiles_m, int64_t *tiles_n);
+void arm_accumulator_flip(const void *ws, int64_t i, int64_t j, int bit);
+// Smallest tile edge of every product kernel: bounds the tile rows / columns of the fused partials.
+constexpr int64_t kMinTileEdge = 96;
 int launch_correct(const abft_problem *p, void *C_f, int64_t i, int64_t j, int dir, hipStream_t s);
 int launch_recover(const abft_problem *p, void *C_f, abft_rect e, int use_rows, hipStream_t s);
 int launch_inject_flip(const abft_problem *p, void *C_f, int64_t i, int64_t j, int bit, hipStream_t s);

@@ -22,11 +22,11 @@
 
 namespace abft {
 
-template <class Ops, int WM = 2, int GROUP_M = 8>
+template <class Ops, int WM = 2, bool FUSED = false, int GROUP_M = 8>
 __global__ __launch_bounds__(128 * WM, 1) void k_gemm_lowp2(const typename Ops::E *__restrict__ A, int64_t lda,
                                                        const typename Ops::E *__restrict__ Bt, int64_t ldb,
                                                        float *__restrict__ C, int64_t ldc, int64_t M, int64_t N,
-                                                       int64_t K, const int *__restrict__ scale_exp) {
+                                                       int64_t K, const int *__restrict__ scale_exp, EpiArgs epi) {
     typedef typename Ops::E E;
     constexpr int BM = 256, BN = 256;
     constexpr int SLAB = 128;                          // bytes of k per row and slab
@@ -117,6 +117,16 @@ __global__ __launch_bounds__(128 * WM, 1) void k_gemm_lowp2(const typename Ops::
     }
 
     const float sc = scale_exp ? __builtin_ldexpf(1.0f, -(scale_exp[0] + scale_exp[1])) : 1.0f;
+    // epilogue extras (uniform branches): the accumulator flip hook, then the
+    // store with the fused partial sums
+    auto rowof = [](int l, int v) { return 4 * (l / 16) + v; };
+    if (epi.fbit >= 0 && epi.fi >= row0 && epi.fi < row0 + BM && epi.fj >= col0 && epi.fj < col0 + BN)
+        epi_flip(acc, epi, row0 + wm * (BM / WM), col0 + wn * 128, lane, rowof);
+    if constexpr (FUSED) {
+        epi_store_fused<TMW, 8, WM, 2, BM, BN>(acc, epi, (double *)(lds + HDR), row0, col0, tm, tn, M, N, wm, wn, lane,
+                                               sc, C, ldc, false, rowof);
+        return;
+    }
     const int ccol = lane % 16;
 #pragma unroll
     for (int a = 0; a < TMW; ++a) {
@@ -134,10 +144,19 @@ __global__ __launch_bounds__(128 * WM, 1) void k_gemm_lowp2(const typename Ops::
 
 template <class Ops, int WM = 2>
 inline int launch_gemm_lowp2(const typename Ops::E *A, int64_t lda, const typename Ops::E *Bt, int64_t ldb, float *C,
-                             int64_t ldc, int64_t M, int64_t N, int64_t K, const int *scale_exp, hipStream_t s) {
+                             int64_t ldc, int64_t M, int64_t N, int64_t K, const int *scale_exp, hipStream_t s,
+                             EpiArgs *epi = nullptr) {
     int64_t tiles = ((M + 255) / 256) * ((N + 255) / 256);
     if (tiles > INT32_MAX) return ABFT_E_ARG;
-    k_gemm_lowp2<Ops, WM><<<(unsigned)tiles, 128 * WM, 0, s>>>(A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp);
+    EpiArgs e = epi ? *epi : epi_none();
+    if (epi) {
+        epi->tiles_m = (M + 255) / 256;
+        epi->tiles_n = (N + 255) / 256;
+    }
+    if (e.pc)
+        k_gemm_lowp2<Ops, WM, true><<<(unsigned)tiles, 128 * WM, 0, s>>>(A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp, e);
+    else
+        k_gemm_lowp2<Ops, WM, false><<<(unsigned)tiles, 128 * WM, 0, s>>>(A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp, e);
     return ABFT_OK;
 }
 

@@ -87,10 +87,11 @@ struct LowpTile {
 // One BM x BN tile of C at (row0, col0): the whole k loop and the epilogue.
 // lds holds 2 * T::BUF elements; the function ends with a barrier, so a
 // persistent caller may reuse lds for its next tile.
-template <class T>
+template <class T, bool FUSED>
 __device__ inline void lowp_tile(const typename T::E *__restrict__ A, int64_t lda, const typename T::E *__restrict__ Bt,
                                  int64_t ldb, float *__restrict__ C, int64_t ldc, int64_t M, int64_t N, int64_t K,
-                                 float sc, int64_t row0, int64_t col0, typename T::E *lds) {
+                                 float sc, int64_t row0, int64_t col0, typename T::E *lds, const EpiArgs &epi,
+                                 int64_t tm, int64_t tn) {
     typedef typename T::E E;
     const int tid = threadIdx.x;
     const int lane = tid % 64, wave = tid / 64;
@@ -169,6 +170,16 @@ __device__ inline void lowp_tile(const typename T::E *__restrict__ A, int64_t ld
         __syncthreads();
     }
 
+    // epilogue extras (uniform branches): the accumulator flip hook, then the
+    // store with the fused partial sums
+    auto rowof = [](int l, int v) { return 4 * (l / 16) + v; };
+    if (epi.fbit >= 0 && epi.fi >= row0 && epi.fi < row0 + T::BM && epi.fj >= col0 && epi.fj < col0 + T::BN)
+        epi_flip(acc, epi, row0 + wm * (T::BM / T::WM), col0 + wn * (T::BN / T::WN), lane, rowof);
+    if constexpr (FUSED) {
+        epi_store_fused<T::TM, T::TN, T::WM, T::WN, T::BM, T::BN>(
+            acc, epi, (double *)lds, row0, col0, tm, tn, M, N, wm, wn, lane, sc, C, ldc, false, rowof);
+        return;
+    }
     const int ccol = lane % 16;
 #pragma unroll
     for (int a = 0; a < T::TM; ++a) {
@@ -184,25 +195,35 @@ __device__ inline void lowp_tile(const typename T::E *__restrict__ A, int64_t ld
     }
 }
 
-template <class T>
+template <class T, bool FUSED>
 __global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_lowp(const typename T::E *__restrict__ A, int64_t lda,
                                                              const typename T::E *__restrict__ Bt, int64_t ldb,
                                                              float *__restrict__ C, int64_t ldc, int64_t M, int64_t N,
-                                                             int64_t K, const int *__restrict__ scale_exp) {
-    __shared__ typename T::E lds[2 * T::BUF];
+                                                             int64_t K, const int *__restrict__ scale_exp,
+                                                             EpiArgs epi) {
+    __shared__ __attribute__((aligned(16))) typename T::E lds[2 * T::BUF];
     const int64_t tiles_m = (M + T::BM - 1) / T::BM, tiles_n = (N + T::BN - 1) / T::BN;
     int64_t tm, tn;
     tile_of<T::GROUP_M>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
     const float sc = scale_exp ? __builtin_ldexpf(1.0f, -(scale_exp[0] + scale_exp[1])) : 1.0f;
-    lowp_tile<T>(A, lda, Bt, ldb, C, ldc, M, N, K, sc, tm * T::BM, tn * T::BN, lds);
+    lowp_tile<T, FUSED>(A, lda, Bt, ldb, C, ldc, M, N, K, sc, tm * T::BM, tn * T::BN, lds, epi, tm, tn);
 }
 
 template <class T>
 inline int launch_gemm_lowp_tile(const typename T::E *A, int64_t lda, const typename T::E *Bt, int64_t ldb, float *C,
-                                 int64_t ldc, int64_t M, int64_t N, int64_t K, const int *scale_exp, hipStream_t s) {
+                                 int64_t ldc, int64_t M, int64_t N, int64_t K, const int *scale_exp, hipStream_t s,
+                                 EpiArgs *epi = nullptr) {
     int64_t tiles = ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
     if (tiles > INT32_MAX) return ABFT_E_ARG;
-    k_gemm_lowp<T><<<(unsigned)tiles, T::THREADS, 0, s>>>(A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp);
+    EpiArgs e = epi ? *epi : epi_none();
+    if (epi) {
+        epi->tiles_m = (M + T::BM - 1) / T::BM;
+        epi->tiles_n = (N + T::BN - 1) / T::BN;
+    }
+    if (e.pc)
+        k_gemm_lowp<T, true><<<(unsigned)tiles, T::THREADS, 0, s>>>(A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp, e);
+    else
+        k_gemm_lowp<T, false><<<(unsigned)tiles, T::THREADS, 0, s>>>(A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp, e);
     return ABFT_OK;
 }
 

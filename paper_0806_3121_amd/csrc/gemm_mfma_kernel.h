@@ -22,6 +22,7 @@
 #pragma once
 
 #include "common.h"
+#include "epilogue.h"
 
 namespace abft {
 
@@ -80,15 +81,15 @@ __device__ inline void tile_of(int64_t wg, int64_t nwg, int64_t tiles_m, int64_t
     tn = in / gm;
 }
 
-template <class T>
+template <class T, bool FUSED>
 __global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_mfma(const typename T::E *__restrict__ A, int64_t lda,
                                                              const typename T::E *__restrict__ Bt, int64_t ldb,
                                                              typename T::E *__restrict__ C, int64_t ldc, int64_t M,
-                                                             int64_t N, int64_t K, int accumulate) {
+                                                             int64_t N, int64_t K, int accumulate, EpiArgs epi) {
     typedef typename T::E E;
     typedef MfmaOps<E> Ops;
     typedef typename Ops::vec16 v16;
-    __shared__ E lds[2 * T::BUF];
+    __shared__ __attribute__((aligned(16))) E lds[2 * T::BUF];
 
     const int64_t tiles_m = (M + T::BM - 1) / T::BM, tiles_n = (N + T::BN - 1) / T::BN;
     int64_t tm, tn;
@@ -179,6 +180,17 @@ __global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_mfma(const typenam
         __syncthreads();
     }
 
+    // epilogue extras (uniform branches): the accumulator flip hook, then the
+    // store with the fused partial sums
+    auto rowof = [](int l, int v) { return Ops::crow(l, v); };
+    if (epi.fbit >= 0 && epi.fi >= row0 && epi.fi < row0 + T::BM && epi.fj >= col0 && epi.fj < col0 + T::BN)
+        epi_flip(acc, epi, row0 + wm * (T::BM / T::WM), col0 + wn * (T::BN / T::WN), lane, rowof);
+    if constexpr (FUSED) {
+        epi_store_fused<T::TM, T::TN, T::WM, T::WN, T::BM, T::BN>(
+            acc, epi, (double *)lds, row0, col0, tm, tn, M, N, wm, wn, lane, (E)1, C, ldc, accumulate != 0, rowof);
+        return;
+    }
+
     // epilogue: lane holds row Ops::crow(lane, v), column lane % 16 of each 16 x 16 tile
     const int ccol = lane % 16;
 #pragma unroll
@@ -198,10 +210,18 @@ __global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_mfma(const typenam
 template <class T>
 inline int launch_gemm_tile(const typename T::E *A, int64_t lda, const typename T::E *Bt, int64_t ldb,
                             typename T::E *C, int64_t ldc, int64_t M, int64_t N, int64_t K, hipStream_t s,
-                            bool accumulate = false) {
+                            bool accumulate = false, EpiArgs *epi = nullptr) {
     int64_t tiles = ((M + T::BM - 1) / T::BM) * ((N + T::BN - 1) / T::BN);
     if (tiles > INT32_MAX) return ABFT_E_ARG;
-    k_gemm_mfma<T><<<(unsigned)tiles, T::THREADS, 0, s>>>(A, lda, Bt, ldb, C, ldc, M, N, K, accumulate ? 1 : 0);
+    EpiArgs e = epi ? *epi : epi_none();
+    if (epi) {
+        epi->tiles_m = (M + T::BM - 1) / T::BM;
+        epi->tiles_n = (N + T::BN - 1) / T::BN;
+    }
+    if (e.pc)
+        k_gemm_mfma<T, true><<<(unsigned)tiles, T::THREADS, 0, s>>>(A, lda, Bt, ldb, C, ldc, M, N, K, accumulate, e);
+    else
+        k_gemm_mfma<T, false><<<(unsigned)tiles, T::THREADS, 0, s>>>(A, lda, Bt, ldb, C, ldc, M, N, K, accumulate, e);
     return ABFT_OK;
 }
 

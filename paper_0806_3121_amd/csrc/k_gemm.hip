@@ -11,6 +11,9 @@
 #include "gemm_mfma_kernel.h"
 #include "sliver_kernel.h"
 
+#include <mutex>
+#include <unordered_map>
+
 namespace abft {
 
 constexpr int64_t kSliverMaxB = 8;
@@ -38,14 +41,15 @@ static const TileChoice kF64Tiles[] = {
     {0, 256, 128, 1, 0.818}, {1, 128, 128, 2, 0.787}, {2, 128, 96, 2, 0.80}, {3, 96, 96, 2, 0.76},
 };
 static int gemm_main(const double *A, int64_t lda, const double *Bt, int64_t ldb, double *C, int64_t ldc, int64_t M,
-                     int64_t N, int64_t K, hipStream_t s, bool acc = false) {
+                     int64_t N, int64_t K, hipStream_t s, bool acc = false, EpiArgs *e = nullptr) {
     switch (choose_tile(kF64Tiles, 4, M, N)) {
-    case 0: return launch_gemm_tile<MfmaTile<double, 256, 128, 16, 4, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc);
-    case 1: return launch_gemm_tile<MfmaTile<double, 128, 128, 16, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc);
+    case 0: return launch_gemm_tile<MfmaTile<double, 256, 128, 16, 4, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc, e);
+    case 1: return launch_gemm_tile<MfmaTile<double, 128, 128, 16, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc, e);
     case 2:
-        return launch_gemm_tile<MfmaTile<double, 128, 96, 16, 2, 2, 8, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc);
+        return launch_gemm_tile<MfmaTile<double, 128, 96, 16, 2, 2, 8, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc,
+                                                                          e);
     default:
-        return launch_gemm_tile<MfmaTile<double, 96, 96, 16, 2, 2, 8, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc);
+        return launch_gemm_tile<MfmaTile<double, 96, 96, 16, 2, 2, 8, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc, e);
     }
 }
 
@@ -54,24 +58,25 @@ static const TileChoice kF32Tiles[] = {
     {0, 256, 128, 1, 0.80}, {1, 128, 128, 2, 0.78},
 };
 static int gemm_main(const float *A, int64_t lda, const float *Bt, int64_t ldb, float *C, int64_t ldc, int64_t M,
-                     int64_t N, int64_t K, hipStream_t s, bool acc = false) {
+                     int64_t N, int64_t K, hipStream_t s, bool acc = false, EpiArgs *e = nullptr) {
     switch (choose_tile(kF32Tiles, 2, M, N)) {
-    case 0: return launch_gemm_tile<MfmaTile<float, 256, 128, 32, 4, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc);
-    default: return launch_gemm_tile<MfmaTile<float, 128, 128, 32, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc);
+    case 0: return launch_gemm_tile<MfmaTile<float, 256, 128, 32, 4, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc, e);
+    default: return launch_gemm_tile<MfmaTile<float, 128, 128, 32, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc, e);
     }
 }
 
 // C_f = (acc ? C_f : 0) + A_f[:, k0:k0+K) B_f[k0:k0+K, :)  (the whole product: k0 = 0, K = k).
 template <typename E>
 static int protected_product(const abft_problem *p, const Geom &g, const E *A, const E *Bt, E *C, bool plain,
-                             hipStream_t s, int64_t k0 = 0, int64_t K = -1, bool acc = false) {
+                             hipStream_t s, int64_t k0 = 0, int64_t K = -1, bool acc = false,
+                             EpiArgs *e = nullptr) {
     if (K < 0) K = g.k;
     const bool thin_r = !plain && g.S * g.br <= kSliverMaxB;
     const bool thin_c = !plain && g.S * g.bc <= kSliverMaxB;
     int64_t Mm = (plain || thin_r) ? g.m : g.M;
     int64_t Nm = (plain || thin_c) ? g.n : g.N;
     const E *Ak = A + k0, *Bk = Bt + k0;
-    int st = gemm_main(Ak, p->lda, Bk, p->ldb, C, p->ldc, Mm, Nm, K, s, acc);
+    int st = gemm_main(Ak, p->lda, Bk, p->ldb, C, p->ldc, Mm, Nm, K, s, acc, e);
     if (st) return st;
     ABFT_LAUNCHED();
     // carried row block over all N columns (corner included), then the carried
@@ -93,17 +98,18 @@ static const TileChoice kLowpTiles[] = {
 };
 template <class Ops, class Ops2>
 static int gemm_main_lowp(const typename Ops::E *A, int64_t lda, const typename Ops::E *Bt, int64_t ldb, float *C,
-                          int64_t ldc, int64_t M, int64_t N, int64_t K, const int *scale_exp, hipStream_t s) {
+                          int64_t ldc, int64_t M, int64_t N, int64_t K, const int *scale_exp, hipStream_t s,
+                          EpiArgs *e = nullptr) {
     constexpr int64_t slab = 128 / (int64_t)sizeof(typename Ops::E);
     if (K % slab == 0 && M * N >= (int64_t)256 * 256 * 256)
-        return launch_gemm_lowp2<Ops2, 4>(A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp, s);
+        return launch_gemm_lowp2<Ops2, 4>(A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp, s, e);
     switch (choose_tile(kLowpTiles, 2, M, N)) {
     case 0:
         return launch_gemm_lowp_tile<LowpTile<Ops, 256, 256, 128 / sizeof(typename Ops::E), 4, 2>>(
-            A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp, s);
+            A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp, s, e);
     default:
         return launch_gemm_lowp_tile<LowpTile<Ops, 128, 128, 64, 2, 2, 8, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K,
-                                                                              scale_exp, s);
+                                                                              scale_exp, s, e);
     }
 }
 
@@ -114,9 +120,9 @@ static int gemm_main_lowp(const typename Ops::E *A, int64_t lda, const typename 
 template <class Ops, class Ops2>
 static int protected_product_lowp(const abft_problem *p, const Geom &g, const typename Ops::E *A,
                                   const typename Ops::E *Bt, float *C, const float *Acs, const float *Bcs,
-                                  const int *scale_exp, bool plain, hipStream_t s) {
+                                  const int *scale_exp, bool plain, hipStream_t s, EpiArgs *e = nullptr) {
     typedef typename Ops::E E;
-    int st = gemm_main_lowp<Ops, Ops2>(A, p->lda, Bt, p->ldb, C, p->ldc, g.m, g.n, g.k, scale_exp, s);
+    int st = gemm_main_lowp<Ops, Ops2>(A, p->lda, Bt, p->ldb, C, p->ldc, g.m, g.n, g.k, scale_exp, s, e);
     if (st) return st;
     ABFT_LAUNCHED();
     if (plain) return ABFT_OK;
@@ -154,32 +160,97 @@ int launch_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, v
     }
 }
 
+// Host registry per workspace: the one-shot accumulator flip armed for the
+// next product, and the tile grid of the last product's fused partials.
+namespace {
+struct EpiState {
+    int64_t fi = 0, fj = 0;
+    int fbit = -1;
+    bool fused = false;
+    int64_t tiles_m = 0, tiles_n = 0;
+};
+std::mutex g_epi_mu;
+std::unordered_map<const void *, EpiState> g_epi;
+}  // namespace
+
+void arm_accumulator_flip(const void *ws, int64_t i, int64_t j, int bit) {
+    std::lock_guard<std::mutex> lk(g_epi_mu);
+    EpiState &st = g_epi[ws];
+    st.fi = i; st.fj = j; st.fbit = bit;
+}
+
+bool fused_grid(const void *ws, int64_t *tiles_m, int64_t *tiles_n) {
+    std::lock_guard<std::mutex> lk(g_epi_mu);
+    auto it = g_epi.find(ws);
+    if (it == g_epi.end() || !it->second.fused) return false;
+    *tiles_m = it->second.tiles_m;
+    *tiles_n = it->second.tiles_n;
+    return true;
+}
+
+static int product_with_extras(const abft_problem *p, const Geom &g, const void *A_f, const void *B_f, void *C_f,
+                               bool plain, void *ws, const float *Acs, const float *Bcs, const int *scale,
+                               EpiArgs *e, hipStream_t s) {
+    switch (p->dtype) {
+    case ABFT_F64:
+        return protected_product<double>(p, g, (const double *)A_f, (const double *)B_f, (double *)C_f, plain, s, 0,
+                                         -1, false, e);
+    case ABFT_F32:
+        return protected_product<float>(p, g, (const float *)A_f, (const float *)B_f, (float *)C_f, plain, s, 0, -1,
+                                        false, e);
+    case ABFT_BF16:
+        return protected_product_lowp<Bf16Ops, Bf16Ops>(p, g, (const uint16_t *)A_f, (const uint16_t *)B_f,
+                                                        (float *)C_f, Acs, Bcs, nullptr, plain, s, e);
+    case ABFT_FP8_E4M3:
+        return protected_product_lowp<Fp8Ops, Fp8x128Ops>(p, g, (const uint8_t *)A_f, (const uint8_t *)B_f,
+                                                          (float *)C_f, Acs, Bcs, scale, plain, s, e);
+    default:
+        return ABFT_E_UNSUPPORTED;
+    }
+}
+
 int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, void *ws,
                 hipStream_t s) {
     Geom g = geom_of(p);
     const bool plain = flags & ABFT_PLAIN;
-    switch (p->dtype) {
-    case ABFT_F64:
-        return protected_product<double>(p, g, (const double *)A_f, (const double *)B_f, (double *)C_f, plain, s);
-    case ABFT_F32:
-        return protected_product<float>(p, g, (const float *)A_f, (const float *)B_f, (float *)C_f, plain, s);
-    case ABFT_BF16:
-    case ABFT_FP8_E4M3: {
-        // ws may be NULL only for a plain bfloat16 product (no checksum is read)
+    // epilogue extras: an armed accumulator flip (consumed here) and the fused partial sums
+    EpiArgs e = epi_none();
+    bool extras = false;
+    if (ws) {
+        std::lock_guard<std::mutex> lk(g_epi_mu);
+        auto it = g_epi.find(ws);
+        if (it != g_epi.end()) {
+            if (it->second.fbit >= 0) {
+                e.fi = it->second.fi; e.fj = it->second.fj; e.fbit = it->second.fbit;
+                it->second.fbit = -1;
+                extras = true;
+            }
+            it->second.fused = false;
+        }
+    }
+    if (flags & ABFT_FUSED) {
         WsLayout L = ws_layout(p);
-        const char *wsc = (const char *)ws;
-        const float *Acs = ws ? (const float *)(wsc + L.acs) : nullptr;
-        const float *Bcs = ws ? (const float *)(wsc + L.bcs) : nullptr;
-        if (p->dtype == ABFT_BF16)
-            return protected_product_lowp<Bf16Ops, Bf16Ops>(p, g, (const uint16_t *)A_f, (const uint16_t *)B_f, (float *)C_f,
-                                                   Acs, Bcs, nullptr, plain, s);
-        const int *scale = ws ? (const int *)(wsc + L.scale) : nullptr;
-        return protected_product_lowp<Fp8Ops, Fp8x128Ops>(p, g, (const uint8_t *)A_f, (const uint8_t *)B_f, (float *)C_f, Acs,
-                                              Bcs, scale, plain, s);
+        e.pc = (double *)((char *)ws + L.fused_c);
+        e.pr = (double *)((char *)ws + L.fused_r);
+        e.ldpc = g.n;
+        e.ldpr = g.m;
+        extras = true;
     }
-    default:
-        return ABFT_E_UNSUPPORTED;
+    WsLayout L = ws_layout(p);
+    const char *wsc = (const char *)ws;
+    const bool lowp = p->dtype == ABFT_BF16 || p->dtype == ABFT_FP8_E4M3;
+    const float *Acs = (lowp && ws) ? (const float *)(wsc + L.acs) : nullptr;
+    const float *Bcs = (lowp && ws) ? (const float *)(wsc + L.bcs) : nullptr;
+    const int *scale = (p->dtype == ABFT_FP8_E4M3 && ws) ? (const int *)(wsc + L.scale) : nullptr;
+    int st = product_with_extras(p, g, A_f, B_f, C_f, plain, ws, Acs, Bcs, scale, extras ? &e : nullptr, s);
+    if (st == ABFT_OK && (flags & ABFT_FUSED)) {
+        std::lock_guard<std::mutex> lk(g_epi_mu);
+        EpiState &es = g_epi[ws];
+        es.fused = true;
+        es.tiles_m = e.tiles_m;
+        es.tiles_n = e.tiles_n;
     }
+    return st;
 }
 
 }  // namespace abft

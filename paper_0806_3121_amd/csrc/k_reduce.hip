@@ -598,6 +598,90 @@ static int verify_typed(const abft_problem *p, const T *C, const Erasures &er, c
     return ABFT_OK;
 }
 
+// Fused verification (b = 1): the column relations of the data columns and
+// the row relations of the data rows from the product epilogue's partial
+// sums (pc: tiles_m x n, pr: tiles_n x m, summed over the tiles in order);
+// the carried column and the carried row are summed from C_f directly.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_vfused(const T *C, VerifyArgs a, const double *pc, const double *pr,
+                                                     int64_t tiles_m, int64_t tiles_n) {
+    double rc = 0.0, rr = 0.0;
+    unsigned long long ec = 0, er = 0;
+    const int64_t total = a.n + a.m;
+    for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
+        double sum = 0.0;
+        if (t < a.n) {
+            for (int64_t q = 0; q < tiles_m; ++q) sum += pc[q * a.n + t];
+            finish_col<T>(a, C, 0, t, sum, rc, ec);
+        } else {
+            const int64_t i = t - a.n;
+            for (int64_t q = 0; q < tiles_n; ++q) sum += pr[q * a.m + i];
+            finish_row<T>(a, C, i, 0, sum, rr, er);
+        }
+    }
+    fold_block(rc, ec, &a.rep->max_ratio_c, &a.rep->n_excl_c);
+    __syncthreads();   // fold_block's shared slots are reused by the second fold
+    fold_block(rr, er, &a.rep->max_ratio_r, &a.rep->n_excl_r);
+}
+
+// Block 0: the carried column C_f[0:m, n] against the corner; block 1: the
+// carried row C_f[m, 0:n] against the corner.  Fixed-order block reductions.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_vfused_edges(const T *C, VerifyArgs a) {
+    __shared__ double sh[kThreads];
+    const bool col = blockIdx.x == 0;
+    const int64_t len = col ? a.m : a.n;
+    double s = 0.0;
+    for (int64_t t = threadIdx.x; t < len; t += kThreads)
+        s += col ? elem<T>::load(C + t * a.ldc + a.n) : elem<T>::load(C + a.m * a.ldc + t);
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    double ratio = 0.0;
+    unsigned long long excl = 0;
+    if (threadIdx.x == 0) {
+        if (col) finish_col<T>(a, C, 0, a.n, sh[0], ratio, excl);
+        else finish_row<T>(a, C, a.m, 0, sh[0], ratio, excl);
+    }
+    if (col) fold_block(ratio, excl, &a.rep->max_ratio_c, &a.rep->n_excl_c);
+    else fold_block(ratio, excl, &a.rep->max_ratio_r, &a.rep->n_excl_r);
+}
+
+template <typename T>
+static int verify_fused_typed(const abft_problem *p, const T *C, char *ws, int64_t tiles_m, int64_t tiles_n,
+                              hipStream_t s) {
+    Geom g = geom_of(p);
+    WsLayout L = ws_layout(p);
+    TauCoef tc = tau_coef(p);
+    VerifyArgs a;
+    a.m = g.m; a.n = g.n; a.br = g.br; a.bc = g.bc; a.S = g.S; a.Gr = g.Gr; a.Gc = g.Gc; a.M = g.M; a.N = g.N;
+    a.ldc = p->ldc;
+    a.mode = tc.mode; a.cc = tc.cc; a.cr = tc.cr;
+    a.na = (const double *)(ws + L.na); a.na_abs = (const double *)(ws + L.na_abs);
+    a.nb = (const double *)(ws + L.nb); a.nb_abs = (const double *)(ws + L.nb_abs);
+    a.qr = (const double *)(ws + L.qr); a.qc = (const double *)(ws + L.qc);
+    a.nv = (const double *)(ws + L.nv); a.nw = (const double *)(ws + L.nw);
+    a.scale_exp = p->dtype == ABFT_FP8_E4M3 ? (const int *)(ws + L.scale) : nullptr;
+    a.rep = (abft_report *)(ws + L.report);
+    a.er.n = 0;
+    k_report_init<<<1, kThreads, 0, s>>>(a.rep);
+    const unsigned blocks = (unsigned)std::min<int64_t>((g.n + g.m + kThreads - 1) / kThreads, 4096);
+    k_vfused<T><<<blocks, kThreads, 0, s>>>(C, a, (const double *)(ws + L.fused_c), (const double *)(ws + L.fused_r),
+                                            tiles_m, tiles_n);
+    k_vfused_edges<T><<<2, kThreads, 0, s>>>(C, a);
+    ABFT_LAUNCHED();
+    return ABFT_OK;
+}
+
+int launch_verify_fused(const abft_problem *p, const void *C_f, char *ws, int64_t tiles_m, int64_t tiles_n,
+                        hipStream_t s) {
+    if (p->dtype == ABFT_F64) return verify_fused_typed<double>(p, (const double *)C_f, ws, tiles_m, tiles_n, s);
+    return verify_fused_typed<float>(p, (const float *)C_f, ws, tiles_m, tiles_n, s);
+}
+
 int launch_verify(const abft_problem *p, const void *C_f, const Erasures &er, char *ws, hipStream_t s) {
     if (p->dtype == ABFT_F64) return verify_typed<double>(p, (const double *)C_f, er, ws, s);
     return verify_typed<float>(p, (const float *)C_f, er, ws, s);

@@ -78,6 +78,26 @@ def test_panel_range_and_dtype_rejected():
     assert panel(0, 64) == abft.ABFT_E_UNSUPPORTED
 
 
+def test_fused_flags_and_flip_hook_rejected():
+    fake = C.c_void_p(256)
+    p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1)
+    gemm = lambda q, flags, ws=fake: _call("abft_gemm", C.byref(q), fake, fake, fake, ws, flags, NULL_STREAM)
+    assert gemm(p, abft.ABFT_FUSED | abft.ABFT_PLAIN) == abft.ABFT_E_ARG
+    assert gemm(p, abft.ABFT_FUSED, None) == abft.ABFT_E_WORKSPACE
+    q = abft.problem(abft.ABFT_F64, 256, 256, 256, 64, 64)
+    assert gemm(q, abft.ABFT_FUSED) == abft.ABFT_E_UNSUPPORTED
+    # no fused product was ever recorded for this workspace
+    assert _call("abft_verify_fused", C.byref(p), fake, C.c_void_p(4096), None, NULL_STREAM) == abft.ABFT_E_ARG
+    arm = lambda q, i, j, bit, ws=fake: _call("abft_arm_accumulator_flip", C.byref(q), ws, i, j, bit)
+    assert arm(p, 256, 0, 3) == abft.ABFT_E_ARG          # rows of C only (the carried row is not the kernel's)
+    assert arm(p, 0, -1, 3) == abft.ABFT_E_ARG
+    assert arm(p, 0, 0, 64) == abft.ABFT_E_ARG
+    assert arm(p, 0, 0, 3, None) == abft.ABFT_E_WORKSPACE
+    p32 = abft.problem(abft.ABFT_F32, 256, 256, 256, 1, 1)
+    assert arm(p32, 0, 0, 32) == abft.ABFT_E_ARG
+    assert arm(p32, 0, 0, 31, C.c_void_p(8192)) == abft.ABFT_OK  # host only: arms, launches nothing
+
+
 def test_unrecoverable_and_bad_rects_rejected():
     fake = C.c_void_p(256)
     p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1)
