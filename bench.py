@@ -598,6 +598,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the unprotected-kernel timing (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--site", choices=["m", "k"], default="m",
+                    help="where the step's flip lands: m = C in memory after the product (re-reading verify), "
+                         "k = an accumulator inside the product kernel (b = 1 workloads: fused partial sums, "
+                         "fused verify)")
     ap.add_argument("--campaign", type=int, default=0,
                     help="run N clean products and N single flips instead of the benchmark, print the tallies")
     args = ap.parse_args()
@@ -649,6 +653,11 @@ def main():
     g_events = []
 
     n_panels = PANELS.get(args.workload, 0)
+    site_k = args.site == "k"
+    if site_k and (b != 1 or n_panels):
+        print(json.dumps({"error": "--site k needs a b = 1 workload (c1, c2b1, c3, c4, c4fp8)"}))
+        sys.exit(2)
+    v_events = []
 
     def timed(fn):
         e0 = torch.cuda.Event(enable_timing=True)
@@ -668,11 +677,22 @@ def main():
             I, J = synth.erase_block(SEED, s, m // b, n // b)
             rect = (I * b, J * b, b, b)
         i, j, bit = synth.flip_site(SEED, s, m, n, bit_lo, bit_hi, avoid=rect)
-        abft.inject_flip(P.p, P.C, i, j, bit)
+        if not site_k:
+            abft.inject_flip(P.p, P.C, i, j, bit)
         known = [rect] if rect else None
         if rect:
             abft.inject_erase(P.p, P.C, rect)
-        rep = P.verify(known=known)       # synchronises: the host classifies the report
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        if site_k:
+            abft.verify_fused(P.p, P.C, P.ws, host_out=P.rep_host)
+        else:
+            abft.verify(P.p, P.C, P.ws, known=known, host_out=P.rep_host)
+        e1.record(stream)
+        v_events.append((e0, e1))
+        stream.synchronize()              # the host classifies the report
+        rep = abft.read_report(P.rep_host)
         loc = abft.classify(P.p, rep, known=known)
         if (loc.cls, loc.i, loc.j) != (abft.ABFT_CLS_DATA, i, j):
             raise RuntimeError(f"step {s}: flip at ({i},{j}) bit {bit} classified as {loc.cls} ({loc.i},{loc.j})")
@@ -691,6 +711,12 @@ def main():
             repair(s)
             ev += [panel(q) for q in range(n_panels // 2, n_panels)]
             g_events.append(ev)
+        elif site_k:
+            # the step's flip happens inside the product kernel (one accumulator bit before the epilogue)
+            i, j, bit = synth.flip_site(SEED, s, m, n, bit_lo, bit_hi)
+            abft.arm_accumulator_flip(P.p, P.ws, i, j, bit)
+            g_events.append([timed(lambda: P.gemm(abft.ABFT_FUSED))])
+            repair(s)
         else:
             g_events.append([timed(P.gemm)])
             repair(s)
@@ -710,6 +736,7 @@ def main():
     log(f"timed {args.steps} steps in {dt:.3f} s")
     # per step: the product's launches (all panels of the loop)
     gemm_ms = sum(sum(a.elapsed_time(c) for a, c in ev) for ev in g_events) / len(g_events)
+    verify_ms = sum(a.elapsed_time(c) for a, c in v_events[-args.steps:]) / max(1, min(len(v_events), args.steps))
 
     # plain product of the same kernel (no checksum rows/columns)
     pe = []
@@ -745,7 +772,10 @@ def main():
         "config": {"workload": f"{dt_name.upper()} protected GEMM {args.workload}: m={m} n={n} k={k}, checksum blocks "
                                f"{b}x{b} ({f'{m // b}x{n // b} grid, one erased block + one flip per step' if erase else 'one flip per step'})"
                                + (f"; product as {n_panels} rank-{k // n_panels} panel updates, repaired after panel "
-                                  f"{n_panels // 2}" if n_panels else ""),
+                                  f"{n_panels // 2}" if n_panels else "")
+                               + ("; the flip is an accumulator bit inside the product kernel, detected from the "
+                                  "fused epilogue partial sums" if site_k else ""),
+                   "site": args.site,
                    "m": m, "n": n, "k": k, "br": b, "bc": b, "global_batch": 1, "seq_len": 0,
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
@@ -759,6 +789,7 @@ def main():
         "gemm_plain_ms": round(plain_ms, 4) if plain_ms else None,
         "abft_overhead_pct": round(100 * (gemm_ms / plain_ms - 1), 2) if plain_ms else None,
         "abft_floor_pct": round(100 * (executed / useful - 1), 2),
+        "first_verify_ms": round(verify_ms, 4),
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
