@@ -329,6 +329,56 @@ def test_mid_loop_erasure_rebuilt_then_loop_goes_on(orc, br, bc, rect, use_rows)
     assert np.array_equal(Cf, orc.gemm(Af, Bf))
 
 
+@pytest.mark.parametrize("br,bc", [(1, 1), (4, 2)])
+def test_chained_product_relations_exact_on_integers(orc, br, bc):
+    """Sec. 3.2 chained calls: the carried rows of C_f are the checksum rows of
+    C, so C_f[:, :n] can enter the next product as A_f without recomputing
+    them; every relation of the chained product holds exactly on integers."""
+    m, k1, n1, n2 = 12, 7, 10, 8
+    A1, B1 = int_problem(m, n1, k1, seed=41)
+    B2 = synth.uniform_ints(42, synth.STREAM_B, n1, n2, -8, 8)
+    _, _, C1f = orc.protected_product(A1, B1, br, bc)
+    _, B2f = orc.encode(np.zeros((m, n1)), B2, br, bc)
+    Df = orc.gemm(C1f[:, :n1], B2f)
+    Di = (A1.astype(np.int64) @ B1.astype(np.int64)) @ B2.astype(np.int64)
+    assert np.array_equal(Df[:m, :n2], Di.astype(np.float64))
+    tc, tr = np.zeros((br, n2 + bc)), np.zeros((m + br, bc))
+    rep = orc.verify(Df, m, n2, br, bc, tc, tr)[2]
+    assert rep.n_flag_c == 0 and rep.n_flag_r == 0
+
+
+def test_chained_threshold_bounds_and_needs_the_inherited_term(orc):
+    """The chained det threshold bounds the residuals of D_f on random binary64
+    data; and when the previous C_f's carried row is off by as much as its own
+    threshold allows (a legal, verified C_f), the plain threshold of the chained
+    product is exceeded while the chained one still holds."""
+    m, k1, n1, n2, b = 64, 96, 80, 48, 8
+    worst = 0.0
+    for seed in range(3):
+        A1 = synth.uniform(seed, synth.STREAM_A, m, k1)
+        B1 = synth.uniform(seed, synth.STREAM_B, k1, n1)
+        B2 = synth.uniform(seed + 7, synth.STREAM_B, n1, n2)
+        Af1, Bf1, C1f = orc.protected_product(A1, B1, b, b)
+        tc1, _ = orc.tau_det(Af1, Bf1, m, n1, b, b)
+        _, B2f = orc.encode(np.zeros((m, n1)), B2, b, b)
+        Af2 = np.ascontiguousarray(C1f[:, :n1])
+        tcc, trc = orc.tau_det_chained(Af2, B2f, m, n2, b, b, tc1)
+        Dc, Dr, rep = orc.verify(orc.gemm(Af2, B2f), m, n2, b, b, tcc, trc)
+        assert rep.n_flag_c == 0 and rep.n_flag_r == 0
+        worst = max(worst, (np.abs(Dc) / tcc).max())
+        # the carried row shifted by 0.9 of the previous threshold (sign of B2's column sums: worst case)
+        C1x = C1f.copy()
+        C1x[m:m + b, :n1] += 0.9 * tc1[:, :n1] * np.sign(B2f.sum(axis=1))[None, :]
+        assert orc.verify(C1x, m, n1, b, b, tc1, orc.tau_det(Af1, Bf1, m, n1, b, b)[1])[2].n_flag_c == 0
+        Ax = np.ascontiguousarray(C1x[:, :n1])
+        Dx = orc.gemm(Ax, B2f)
+        tcp, trp = orc.tau_det(Ax, B2f, m, n2, b, b)
+        assert orc.verify(Dx, m, n2, b, b, tcp, trp)[2].n_flag_c > 0          # the plain threshold is exceeded
+        tcx, trx = orc.tau_det_chained(Ax, B2f, m, n2, b, b, tc1)
+        assert orc.verify(Dx, m, n2, b, b, tcx, trx)[2].n_flag_c == 0        # the chained one holds
+    assert worst > 1e-6
+
+
 def test_recovery_formula_single_checksum(orc):
     """Sec. 2.1 with unit weights: x_i = y - sum_{k != i} x_k, on a 1-row C."""
     m, n, k = 1, 5, 1
