@@ -182,6 +182,26 @@ int abft_quantize(const abft_problem *p, int which, const float *X, int64_t ldx,
 int abft_encode(const abft_problem *p, void *A_f, void *B_f, void *ws, void *stream);
 
 /*
+ * Chained products (stacked fault-tolerant routines; Sec. 3.2 notes that the
+ * initial checksum is not paid again when calls are chained): the result C_f
+ * of a previous product is the A_f of the next one, D_f = C_f[:, 0:n_prev)
+ * B_f, without recomputing its checksum rows: the carried rows of C_f are
+ * already A's checksum rows.  This call encodes B_f (checksum columns as
+ * abft_encode) and fills ws for the new problem p: the threshold statistics
+ * of A_f taken over the rows that enter the product (the carried rows as they
+ * are), and the inherited threshold term.  The previous column relations hold
+ * only up to their residual, at most tau_prev(r, l); through the product it
+ * adds at most sum_l tau_prev(r, l) |B_f[l, j]| to relation (r, j), which the
+ * det threshold of p then includes.  Requirements: both problems ABFT_F64 with
+ * the same tau mode (ABFT_TAU_DET or ABFT_TAU_EXACT); p->m = prev->m,
+ * p->br = prev->br, p->k = prev->n, p->lda = prev->ldc (A_f is the previous
+ * C_f, unchanged); ws_prev is the previous product's workspace after its
+ * abft_encode (read during this call only).
+ */
+int abft_encode_chained(const abft_problem *p, const void *A_f, void *B_f, void *ws, const abft_problem *prev,
+                        const void *ws_prev, void *stream);
+
+/*
  * Protected product (Eq. ABFT-GEMM): C_f = A_f B_f over all (m+br) x (n+bc)
  * entries.  The data part and checksum blocks wider than 8 run on the matrix
  * cores with binary64 (F64) or binary32 (other dtypes) accumulation;
@@ -433,7 +453,11 @@ int abft_wsetup(const abft_wproblem *p, void *ws);
  * 3 gamma_{Gr+1}) S_r[i] ||B_f[:, j]||_2, a rigorous bound on the rounding of
  * the product, the checksums and the relation sum; rows alike with Gc. */
 int abft_wencode(const abft_wproblem *p, void *A_f, void *B_f, void *ws, void *stream);
-/* C_f = A_f B_f, all M x N entries, on the matrix cores (binary64). */
+/* C_f = A_f B_f, all M x N entries (binary64): on the matrix cores, or for
+ * N <= 8 (the matrix-vector product: n = 1, bc = 1, fc = 1) by a streaming
+ * kernel that reads A_f once.  A protected matrix-vector product y = A x is
+ * the problem with n = 1: B_f = [x, wc x], C_f = [y_f, wc y_f] with y_f the
+ * encoded result; every weighted relation, location and recovery applies. */
 int abft_wgemm(const abft_wproblem *p, const void *A_f, const void *B_f, void *C_f, void *stream);
 /* Every column and row group of C_f (binary64 sums); groups holding an
  * element of a known erased rectangle (n_known <= 4) are skipped.  The report

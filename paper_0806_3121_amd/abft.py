@@ -121,6 +121,7 @@ def lib():
         sig = {
             "abft_workspace_size": (C.c_size_t, [_P(abft_problem)]),
             "abft_encode": (C.c_int, [_P(abft_problem), _V, _V, _V, _V]),
+            "abft_encode_chained": (C.c_int, [_P(abft_problem), _V, _V, _V, _P(abft_problem), _V, _V]),
             "abft_gemm": (C.c_int, [_P(abft_problem), _V, _V, _V, _V, C.c_uint32, _V]),
             "abft_gemm_panel": (C.c_int, [_P(abft_problem), _V, _V, _V, C.c_int64, C.c_int64, C.c_uint32, _V]),
             "abft_quantize": (C.c_int, [_P(abft_problem), C.c_int, _V, C.c_int64, _V, _V, _V]),
@@ -204,6 +205,12 @@ def workspace_size(p: abft_problem) -> int:
 
 def encode(p, A_f, B_f, ws, stream=None):
     return _check("abft_encode", lib().abft_encode(C.byref(p), _ptr(A_f), _ptr(B_f), _ptr(ws), _stream(stream)))
+
+
+def encode_chained(p, A_f, B_f, ws, prev, ws_prev, stream=None):
+    """A_f: the previous product's C_f (lda = prev.ldc); B_f: the new operand."""
+    return _check("abft_encode_chained", lib().abft_encode_chained(C.byref(p), _ptr(A_f), _ptr(B_f), _ptr(ws),
+                                                                   C.byref(prev), _ptr(ws_prev), _stream(stream)))
 
 
 def gemm(p, A_f, B_f, C_f, ws=None, flags=0, stream=None):

@@ -62,6 +62,9 @@ WsLayout ws_layout(const abft_problem *p) {
     const int64_t tm = (g.m + kMinTileEdge - 1) / kMinTileEdge, tn = (g.n + kMinTileEdge - 1) / kMinTileEdge;
     L.fused_c = take(fused ? sizeof(double) * tm * g.n : 8);
     L.fused_r = take(fused ? sizeof(double) * tn * g.m : 8);
+    L.chain_a = take(sizeof(double) * g.br);
+    L.chain_w = take(sizeof(double) * g.N);
+    L.chain_cs = take(p->dtype == ABFT_F64 ? sizeof(double) * g.br * g.k : 8);
     L.total = off;
     return L;
 }
@@ -240,6 +243,21 @@ int abft_encode(const abft_problem *p, void *A_f, void *B_f, void *ws, void *str
     if ((st = check_operands(p, A_f, B_f))) return st;
     if (!ws) return ABFT_E_WORKSPACE;
     return launch_encode(p, A_f, B_f, (char *)ws, (hipStream_t)stream);
+}
+
+int abft_encode_chained(const abft_problem *p, const void *A_f, void *B_f, void *ws, const abft_problem *prev,
+                        const void *ws_prev, void *stream) {
+    int st = check_problem(p);
+    if (st) return st;
+    if ((st = check_problem(prev))) return st;
+    if (p->dtype != ABFT_F64 || prev->dtype != ABFT_F64) return ABFT_E_UNSUPPORTED;
+    if (p->tau_mode != prev->tau_mode) return ABFT_E_ARG;
+    if (p->tau_mode != ABFT_TAU_DET && p->tau_mode != ABFT_TAU_EXACT) return ABFT_E_UNSUPPORTED;
+    if (p->m != prev->m || p->br != prev->br || p->k != prev->n || p->lda != prev->ldc) return ABFT_E_ARG;
+    if ((st = check_operands(p, A_f, B_f))) return st;
+    if (!ws || !ws_prev) return ABFT_E_WORKSPACE;
+    const double cc_prev = p->tau_mode == ABFT_TAU_DET ? tau_coef(prev).cc : 0.0;
+    return launch_encode_chained(p, A_f, B_f, (char *)ws, prev, (const char *)ws_prev, cc_prev, (hipStream_t)stream);
 }
 
 int abft_quantize(const abft_problem *p, int which, const float *X, int64_t ldx, void *dst, void *ws, void *stream) {

@@ -186,7 +186,9 @@ struct WsLayout {
     size_t acs, bcs;                 // binary32 checksum rows of low-precision operands (float, br*k / bc*k)
     size_t scale;                    // FP8 per-tensor scale exponents and amax scratch (4 x int32)
     size_t partial;                  // two-level reduction partials (double)
-    size_t fused_c, fused_r;         // product-epilogue partial sums for b = 1 (double; see fused_bound)
+    size_t fused_c, fused_r;         // product-epilogue partial sums for b = 1 (double)
+    size_t chain_a, chain_w;         // chained products (binary64): inherited threshold term chain_a[r] chain_w[j]
+    size_t chain_cs;                 // chained products: the recomputed checksum rows (discarded; br x k double)
     size_t report;                   // abft_report
     size_t total;
     size_t partial_bytes;
@@ -214,11 +216,17 @@ int launch_encode(const abft_problem *p, void *A_f, void *B_f, char *ws, hipStre
 // Binary64 matrix-core product C = A B^T-stored (A: M x K rows, Bt: N x K rows), all M x N entries.
 int launch_gemm_f64(const double *A, int64_t lda, const double *Bt, int64_t ldb, double *C, int64_t ldc, int64_t M,
                     int64_t N, int64_t K, hipStream_t s);
+// Binary64 skinny product (N <= a few columns, e.g. a matrix-vector product):
+// streams A once, binary64 accumulation.  Same layouts as launch_gemm_f64.
+int launch_skinny_f64(const double *A, int64_t lda, const double *Bt, int64_t ldb, double *C, int64_t ldc,
+                      int64_t M, int64_t N, int64_t K, hipStream_t s);
 int launch_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, int64_t k0, int64_t k1,
                       uint32_t flags, hipStream_t s);
 int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, void *ws,
                 hipStream_t s);
 int launch_verify(const abft_problem *p, const void *C_f, const Erasures &er, char *ws, hipStream_t s);
+int launch_encode_chained(const abft_problem *p, const void *A_f, void *B_f, char *ws, const abft_problem *prev,
+                          const char *ws_prev, double cc_prev, hipStream_t s);
 int launch_verify_fused(const abft_problem *p, const void *C_f, char *ws, int64_t tiles_m, int64_t tiles_n,
                         hipStream_t s);
 // Fused partial sums of the last ABFT_FUSED product into ws (tile grid), and

@@ -136,6 +136,14 @@ static int protected_product_lowp(const abft_problem *p, const Geom &g, const ty
     return sliver<E, float, float>(A, p->lda, g.m, Bcs, g.k, g.bc, g.k, C + g.n, p->ldc, 1, scale_exp, s);
 }
 
+int launch_skinny_f64(const double *A, int64_t lda, const double *Bt, int64_t ldb, double *C, int64_t ldc,
+                      int64_t M, int64_t N, int64_t K, hipStream_t s) {
+    int st = sliver<double, double, double>(A, lda, M, Bt, ldb, N, K, C, ldc, 1, nullptr, s);
+    if (st) return st;
+    ABFT_LAUNCHED();
+    return ABFT_OK;
+}
+
 int launch_gemm_f64(const double *A, int64_t lda, const double *Bt, int64_t ldb, double *C, int64_t ldc, int64_t M,
                     int64_t N, int64_t K, hipStream_t s) {
     int st = gemm_main(A, lda, Bt, ldb, C, ldc, M, N, K, s);

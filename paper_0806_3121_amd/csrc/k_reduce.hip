@@ -63,6 +63,10 @@ __device__ inline double record(abft_report *rep, bool col, int64_t a, int64_t b
     return 0.0;
 }
 
+__global__ __launch_bounds__(kThreads) void k_fill_zero(double *x, int64_t n) {
+    for (int64_t t = threadIdx.x; t < n; t += kThreads) x[t] = 0.0;
+}
+
 __global__ void k_report_init(abft_report *rep) {
     uint64_t *w = (uint64_t *)rep;
     const int nw = sizeof(abft_report) / 8;
@@ -258,6 +262,70 @@ static int encode_typed(const abft_problem *p, T *A, T *Bt, TC *Acs, int64_t lda
     double *ga = (double *)(ws + (stat ? L.nv : L.na_abs)), *gb = (double *)(ws + (stat ? L.nw : L.nb_abs));
     row_stats<double>(grpA, g.k, g.br, g.k, ROW_L2, nullptr, ga, s);
     row_stats<double>(grpB, g.k, g.bc, g.k, ROW_L2, nullptr, gb, s);
+    // an operand encoded here carries no inherited residual
+    k_fill_zero<<<1, kThreads, 0, s>>>((double *)(ws + L.chain_a), g.br);
+    k_fill_zero<<<1, kThreads, 0, s>>>((double *)(ws + L.chain_w), g.N);
+    ABFT_LAUNCHED();
+    return ABFT_OK;
+}
+
+// Chained product (the result of a product fed to the next one, F64, det or
+// exact): A_f is the previous C_f, whose carried rows are used as they are.
+// Its checksum rows are recomputed only into scratch, for the group statistic;
+// the row statistics are taken over the rows that enter the product (the
+// carried ones).  B_f is encoded as usual.  The previous column relations hold
+// up to their residual, at most tau_prev(r, l) = cc_prev na_abs_prev[r]
+// nb_prev[l]; through the product it contributes at most
+// sum_l tau_prev(r, l) |B_f[l, j]| to relation (r, j): stored as
+// chain_a[r] = cc_prev na_abs_prev[r] and chain_w[j] = sum_l nb_prev[l] |B_f[l, j]|.
+__global__ __launch_bounds__(kThreads) void k_chain_a(const double *na_abs_prev, double cc_prev, int64_t br,
+                                                      double *chain_a) {
+    for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < br; r += (int64_t)gridDim.x * kThreads)
+        chain_a[r] = cc_prev * na_abs_prev[r];
+}
+
+// out[j] = sum_l w[l] |X[j, l]|: one wave per row, binary64.
+__global__ __launch_bounds__(kThreads) void k_row_absdot(const double *X, int64_t ld, int64_t rows, int64_t k,
+                                                         const double *w, double *out) {
+    const int lane = threadIdx.x % kWave;
+    const int64_t w0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kWave;
+    const int64_t nw = (int64_t)gridDim.x * kThreads / kWave;
+    for (int64_t j = w0; j < rows; j += nw) {
+        const double *row = X + j * ld;
+        double acc = 0.0;
+        for (int64_t l = 2 * lane; l < k; l += 2 * kWave) {
+            double v[2];
+            vec16<double>::load(row + l, v);
+            acc += w[l] * fabs(v[0]) + w[l + 1] * fabs(v[1]);
+        }
+        for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+        if (lane == 0) out[j] = acc;
+    }
+}
+
+int launch_encode_chained(const abft_problem *p, const void *A_f, void *B_f, char *ws, const abft_problem *prev,
+                          const char *ws_prev, double cc_prev, hipStream_t s) {
+    Geom g = geom_of(p);
+    WsLayout L = ws_layout(p), Lp = ws_layout(prev);
+    const double *A = (const double *)A_f;
+    double *Bt = (double *)B_f;
+    double *part = (double *)(ws + L.partial);
+    double *grpA = (double *)(ws + L.grpA), *grpB = (double *)(ws + L.grpB);
+    double *cs = (double *)(ws + L.chain_cs);
+    // the A side: group statistic (checksum rows into scratch), row norms of the rows that enter the product
+    encode_pass1<double, double>(const_cast<double *>(A), p->lda, g.m, g.br, g.k, cs, g.k, false, grpA, part, s);
+    encode_pass2<double, double>(A, p->lda, g.m, A + g.m * p->lda, p->lda, g.br, g.k, false, g.bc, grpB,
+                                 (double *)(ws + L.na), s);
+    // the B side as in a plain encode
+    encode_pass1<double, double>(Bt, p->ldb, g.n, g.bc, g.k, Bt + g.n * p->ldb, p->ldb, false, grpB, part, s);
+    encode_pass2<double, double>(Bt, p->ldb, g.n, Bt + g.n * p->ldb, p->ldb, g.bc, g.k, false, g.br, grpA,
+                                 (double *)(ws + L.nb), s);
+    row_stats<double>(grpA, g.k, g.br, g.k, ROW_L2, nullptr, (double *)(ws + L.na_abs), s);
+    row_stats<double>(grpB, g.k, g.bc, g.k, ROW_L2, nullptr, (double *)(ws + L.nb_abs), s);
+    // the inherited term
+    k_chain_a<<<1, kThreads, 0, s>>>((const double *)(ws_prev + Lp.na_abs), cc_prev, g.br, (double *)(ws + L.chain_a));
+    k_row_absdot<<<(unsigned)std::min<int64_t>((g.N + 3) / 4, 65536), kThreads, 0, s>>>(
+        Bt, p->ldb, g.N, g.k, (const double *)(ws_prev + Lp.nb), (double *)(ws + L.chain_w));
     ABFT_LAUNCHED();
     return ABFT_OK;
 }
@@ -387,6 +455,7 @@ struct VerifyArgs {
     int mode;
     double cc, cr;                  // det coefficients; stat: cc = lambda^2 (u^2/3)(T/2 + s)
     const double *na, *na_abs, *nb, *nb_abs;
+    const double *chain_a, *chain_w; // det: inherited term of a chained product (zero otherwise)
     const double *qr, *qc, *nv, *nw;
     const int *scale_exp;           // FP8: statistics are in the scaled domain, C is not
     abft_report *rep;
@@ -399,7 +468,7 @@ __device__ inline double tau_scale(const VerifyArgs &a) {
     return a.scale_exp ? ldexp(1.0, -(a.scale_exp[0] + a.scale_exp[1])) : 1.0;
 }
 __device__ inline double tau_col(const VerifyArgs &a, int64_t r, int64_t j) {
-    if (a.mode == ABFT_TAU_DET) return tau_scale(a) * a.cc * a.na_abs[r] * a.nb[j];
+    if (a.mode == ABFT_TAU_DET) return tau_scale(a) * a.cc * a.na_abs[r] * a.nb[j] + a.chain_a[r] * a.chain_w[j];
     if (a.mode == ABFT_TAU_STAT) return tau_scale(a) * sqrt(a.cc * (a.br == 1 ? a.qc[j] : a.nv[r] * a.qc[j]));
     return 0.0;
 }
@@ -565,6 +634,7 @@ static int verify_typed(const abft_problem *p, const T *C, const Erasures &er, c
     a.mode = tc.mode; a.cc = tc.cc; a.cr = tc.cr;
     a.na = (const double *)(ws + L.na); a.na_abs = (const double *)(ws + L.na_abs);
     a.nb = (const double *)(ws + L.nb); a.nb_abs = (const double *)(ws + L.nb_abs);
+    a.chain_a = (const double *)(ws + L.chain_a); a.chain_w = (const double *)(ws + L.chain_w);
     a.qr = (const double *)(ws + L.qr); a.qc = (const double *)(ws + L.qc);
     a.nv = (const double *)(ws + L.nv); a.nw = (const double *)(ws + L.nw);
     a.scale_exp = p->dtype == ABFT_FP8_E4M3 ? (const int *)(ws + L.scale) : nullptr;
@@ -662,6 +732,7 @@ static int verify_fused_typed(const abft_problem *p, const T *C, char *ws, int64
     a.mode = tc.mode; a.cc = tc.cc; a.cr = tc.cr;
     a.na = (const double *)(ws + L.na); a.na_abs = (const double *)(ws + L.na_abs);
     a.nb = (const double *)(ws + L.nb); a.nb_abs = (const double *)(ws + L.nb_abs);
+    a.chain_a = (const double *)(ws + L.chain_a); a.chain_w = (const double *)(ws + L.chain_w);
     a.qr = (const double *)(ws + L.qr); a.qc = (const double *)(ws + L.qc);
     a.nv = (const double *)(ws + L.nv); a.nw = (const double *)(ws + L.nw);
     a.scale_exp = p->dtype == ABFT_FP8_E4M3 ? (const int *)(ws + L.scale) : nullptr;

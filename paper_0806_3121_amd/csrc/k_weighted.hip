@@ -15,6 +15,7 @@ namespace {
 constexpr int kT = 256;
 constexpr int kW = 64;
 constexpr int FM = ABFT_WMAX;
+constexpr int64_t kSkinnyN = 8;    // products with at most this many columns stream A_f once
 
 struct WGeom {
     int64_t m, n, k, br, bc, Gr, Gc, M, N, lda, ldb, ldc;
@@ -698,6 +699,10 @@ int abft_wgemm(const abft_wproblem *p, const void *A_f, const void *B_f, void *C
     if (st) return st;
     if (!A_f || !B_f || !C_f || !aligned16(A_f) || !aligned16(B_f) || ((uintptr_t)C_f & 7u)) return ABFT_E_ARG;
     const WGeom g = wgeom(p);
+    // a few columns (the matrix-vector case n = 1): stream A_f once instead of tiling the matrix cores
+    if (g.N <= kSkinnyN)
+        return launch_skinny_f64((const double *)A_f, g.lda, (const double *)B_f, g.ldb, (double *)C_f, g.ldc, g.M,
+                                 g.N, g.k, (hipStream_t)stream);
     return launch_gemm_f64((const double *)A_f, g.lda, (const double *)B_f, g.ldb, (double *)C_f, g.ldc, g.M, g.N,
                            g.k, (hipStream_t)stream);
 }

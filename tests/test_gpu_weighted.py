@@ -278,3 +278,36 @@ def test_weighted_deterministic(dev):
         rep = P.verify()
         out.append((P.A.cpu().numpy().tobytes(), P.C.cpu().numpy().tobytes(), rep.max_ratio_c, rep.max_ratio_r))
     assert out[0] == out[1]
+
+
+def test_weighted_matrix_vector_product(dev, orc):
+    """The protected matrix-vector product (n = 1, bc = 1, fc = 1): y_f = A_f x
+    on the streaming kernel, equal to the oracle's encoded product; two flips of
+    y in distinct row residues located by the weight ratios and corrected; two
+    lost blocks of y rebuilt."""
+    m, n, k, br, bc, fr, fc = 4096, 1, 2048, 64, 1, 2, 1
+    note("weighted matrix-vector product")
+    A, B, Wr, Wc, P = make(dev, m, n, k, br, bc, fr, fc)
+    P.encode()
+    P.gemm()
+    torch.cuda.synchronize()
+    Af, Bf, Cf = wo.wproduct(A, B, Wr, Wc, br, bc)
+    clean = P.C.cpu().numpy().copy()
+    assert clean.shape == (m + fr * br, 2)
+    assert rel_err(clean, Cf) <= TOL
+    rep = P.verify()
+    assert rep.n_fail_c == 0 and rep.n_fail_r == 0
+    for (x, bit) in [(5, 57), (3 * br + 17, 54)]:
+        flip(P, x, 0, bit)
+    rep = P.verify()
+    st, locs = abft.wlocate(P.p, rep)
+    assert st == abft.ABFT_OK
+    assert sorted((l.cls, l.i, l.j) for l in locs) == [(abft.ABFT_CLS_DATA, 5, 0), (abft.ABFT_CLS_DATA, 3 * br + 17, 0)]
+    abft.wcorrect(P.p, P.C, locs, P.ws)
+    P.C[7 * br:8 * br, :] = float("nan")
+    P.C[40 * br:41 * br, :] = float("nan")
+    abft.wrecover(P.p, P.C, abft.ABFT_DIR_COL, [7, 40], 0, P.N, P.ws)
+    rep = P.verify()
+    assert rep.n_fail_c == 0 and rep.n_fail_r == 0
+    torch.cuda.synchronize()
+    assert rel_err(P.C.cpu().numpy(), clean) <= 1e-11
