@@ -15,7 +15,8 @@ timed on a bounded sample of the same product (rank 0, N = 1 only).
 With --workload c2panel the product runs as a loop of panel updates
 (outer-product form) and the erasure and flip are repaired mid-loop.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2|c2b1|c2panel|c2w|c1|c1b64|c3|c4|c4fp8|c5]
+    python bench.py [--steps K] [--warmup W]
+                    [--workload c2|c2b1|c2panel|c2w|c2chain|c2v|c1|c1b64|c3|c4|c4fp8|c5]
                     [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -44,10 +45,16 @@ WORKLOADS = {
     # lands, half-way through the k loop and both are repaired there before the loop goes on
     "c2panel": ("f64", 8192, 8192, 8192, 1024, True),
     "c2w": ("f64", 8192, 8192, 8192, 512, True),
+    "c2chain": ("f64", 8192, 8192, 8192, 1024, True),
+    "c2v": ("f64", 16384, 1, 16384, 512, True),
     # batched: 512 bfloat16 problems, m, n, k uniform on multiples of 32 in [64, 2048]
     "c5": ("bf16", 0, 0, 0, 32, True),
 }
 PANELS = {"c2panel": 8}
+# chained products (Sec. 3.2): the verified C_f of one n = 8192, b = 1024 product is the A_f of the next
+CHAINED = {"c2chain": {"m": 8192, "n": 8192, "k": 8192, "b": 1024}}
+# protected matrix-vector product (weighted checksums, n = 1): A_f streamed once per product
+GEMV = {"c2v": {"m": 16384, "k": 16384, "b": 512, "f": 2}}
 # weighted f-checksums (Sec. 2.1): n = 8192, 512 x 512 blocks (16 x 16 grid), two weighted checksum block rows
 # and columns; per step two blocks of one block column are lost and two flips land in other column groups
 WEIGHTED = {"c2w": {"dtype": "f64", "m": 8192, "n": 8192, "k": 8192, "b": 512, "f": 2, "flips": 2}}
@@ -411,6 +418,177 @@ def run_weighted(args):
     print(json.dumps(out), flush=True)
 
 
+def _timed(torch, stream, fn):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    return (e0, e1)
+
+
+def _steps(torch, args, step):
+    for s in range(args.warmup):
+        step(1000 + s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(s)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def run_chained(args):
+    """Two chained products per step: C_f = A_f B_f (encoded, verified), then
+    D_f = C_f[:, :n] B2_f with C_f's carried rows reused as checksum rows
+    (abft_encode_chained); D_f gets one flip and one erased block, is verified
+    with the erasure known, corrected, rebuilt and verified again."""
+    import torch
+
+    from paper_0806_3121_amd import abft, synth
+
+    cfg = CHAINED[args.workload]
+    m, n, k, b = cfg["m"], cfg["n"], cfg["k"], cfg["b"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    log(f"workload {args.workload}: f64 chained m={m} n={n} k={k} b={b}")
+    P1 = abft.Protected(abft.ABFT_F64, m, n, k, b, b, device=dev)
+    abft.fill_uniform(abft.ABFT_F64, m, k, k, 0, SEED, synth.STREAM_A, P1.A)
+    abft.fill_uniform(abft.ABFT_F64, k, n, k, 1, SEED, synth.STREAM_B, P1.Bt)
+    N = n + b
+    p2 = abft.problem(abft.ABFT_F64, m, n, n, b, b, lda=P1.ldc, ldb=n, ldc=P1.ldc)
+    Bt2 = torch.zeros(N, n, dtype=torch.float64, device=dev)
+    abft.fill_uniform(abft.ABFT_F64, n, n, n, 1, SEED + 1, synth.STREAM_B, Bt2)
+    ws2 = torch.zeros(abft.workspace_size(p2), dtype=torch.uint8, device=dev)
+    D = torch.zeros(m + b, P1.ldc, dtype=torch.float64, device=dev)
+    host = abft.new_report_buffer()
+    torch.cuda.synchronize()
+    ev = []
+
+    def step(s):
+        P1.encode()
+        e1 = _timed(torch, stream, P1.gemm)
+        if P1.verify().n_flag_c:
+            raise RuntimeError("first product not clean")
+        abft.encode_chained(p2, P1.Cbuf, Bt2, ws2, P1.p, P1.ws)
+        e2 = _timed(torch, stream, lambda: abft.gemm(p2, P1.Cbuf, Bt2, D, ws2))
+        ev.append((e1, e2))
+        I, J = synth.erase_block(SEED, s, m // b, n // b)
+        rect = (I * b, J * b, b, b)
+        i, j, bit = synth.flip_site(SEED, s, m, n, 40, 62, avoid=rect)
+        abft.inject_flip(p2, D, i, j, bit)
+        abft.inject_erase(p2, D, rect)
+        abft.verify(p2, D, ws2, known=[rect], host_out=host)
+        stream.synchronize()
+        loc = abft.classify(p2, abft.read_report(host), known=[rect])
+        if (loc.cls, loc.i, loc.j) != (abft.ABFT_CLS_DATA, i, j):
+            raise RuntimeError(f"step {s}: flip ({i},{j}) located as {loc.cls} ({loc.i},{loc.j})")
+        abft.correct(p2, D, loc)
+        abft.recover_block(p2, D, rect)
+        abft.verify(p2, D, ws2, host_out=host)
+        stream.synchronize()
+        rep = abft.read_report(host)
+        if rep.n_flag_c or rep.n_flag_r:
+            raise RuntimeError(f"step {s}: chained result not clean after repair")
+
+    dt = _steps(torch, args, step)
+    ev = ev[-args.steps:]
+    g1 = sum(a.elapsed_time(c) for (a, c), _ in ev) / len(ev)
+    g2 = sum(a.elapsed_time(c) for _, (a, c) in ev) / len(ev)
+    useful = 2 * 2.0 * m * n * k
+    executed = 2 * 2.0 * (m + b) * (n + b) * k
+    ms_step = dt / args.steps * 1e3
+    value = useful / (ms_step * 1e-3) / 1e12
+    achieved = executed / ((g1 + g2) * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"F64 chained protected GEMMs {args.workload}: two products m=n=k={n}, {b}x{b} blocks; "
+                               "the verified C_f of the first is the A_f of the second (carried checksum rows "
+                               "reused); the second gets one erased block and one flip per step",
+                   "m": m, "n": n, "k": k, "br": b, "bc": b, "global_batch": 1, "seq_len": 0,
+                   "parallelism": "single-gpu"},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK["f64"], 4), "traffic": None,
+                     "kernel": "k_gemm_mfma (both products)", "flops_per_launch": executed / 2,
+                     "avg_launch_ms": round((g1 + g2) / 2, 4)},
+        "gemm_first_ms": round(g1, 4), "gemm_chained_ms": round(g2, 4),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_gemv(args):
+    """Protected matrix-vector product y = A x with f weighted checksum block
+    rows (a weighted problem with n = 1): encode, product (the streaming
+    kernel reads A_f once), two flips of y located by the weight ratios and
+    corrected, then f lost blocks of y rebuilt, verify."""
+    import torch
+
+    from paper_0806_3121_amd import abft, synth
+
+    cfg = GEMV[args.workload]
+    m, k, b, f = cfg["m"], cfg["k"], cfg["b"], cfg["f"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    Gr = m // b
+    Wr = 0.5 + (synth.uniform(SEED, synth.STREAM_X, f, Gr) + 1) / 2
+    log(f"workload {args.workload}: f64 matrix-vector m={m} k={k} b={b} f={f}")
+    P = abft.WProtected(m, 1, k, b, 1, Wr, [[1.0]], device=dev)
+    abft.fill_uniform(abft.ABFT_F64, m, k, k, 0, SEED, synth.STREAM_A, P.A)
+    abft.fill_uniform(abft.ABFT_F64, k, 1, k, 1, SEED, synth.STREAM_B, P.Bt)
+    torch.cuda.synchronize()
+    ev = []
+
+    def step(s):
+        P.encode()
+        ev.append(_timed(torch, stream, P.gemm))
+        # two flips of y in distinct residues (distinct column groups): located by the weight ratios
+        r0 = synth.randint(SEED, synth.STREAM_FLIP, 4 * s, b)
+        r1 = (r0 + 1 + synth.randint(SEED, synth.STREAM_FLIP, 4 * s + 1, b - 1)) % b
+        sites = [(r0 + b * synth.randint(SEED, synth.STREAM_FLIP, 4 * s + 2, Gr), 52),
+                 (r1 + b * synth.randint(SEED, synth.STREAM_FLIP, 4 * s + 3, Gr), 57)]
+        for x, bit in sites:
+            v = P.C[x, 0].view(torch.int64) ^ (1 << bit)
+            P.C[x, 0] = v.view(torch.float64)
+        rep = P.verify()
+        st, locs = abft.wlocate(P.p, rep)
+        if st != abft.ABFT_OK or sorted((l.i, l.j) for l in locs) != sorted((x, 0) for x, _ in sites):
+            raise RuntimeError(f"step {s}: flips {sites} located as {[(l.cls, l.i, l.j) for l in locs]}")
+        abft.wcorrect(P.p, P.C, locs, P.ws)
+        # then f lost blocks of y (f failed processes), rebuilt by an f x f solve
+        lost = synth.pick_distinct(SEED + s, f, Gr, stream=synth.STREAM_ERASE)
+        for g in lost:
+            P.C[g * b:(g + 1) * b, :] = float("nan")
+        abft.wrecover(P.p, P.C, abft.ABFT_DIR_COL, lost, 0, 2, P.ws)
+        rep = P.verify()
+        if rep.n_fail_c or rep.n_fail_r:
+            raise RuntimeError(f"step {s}: not clean after repair")
+
+    dt = _steps(torch, args, step)
+    ev = ev[-args.steps:]
+    g = sum(a.elapsed_time(c) for a, c in ev) / len(ev)
+    M = m + f * b
+    bytes_read = M * k * 8.0
+    ms_step = dt / args.steps * 1e3
+    out = {
+        "metric": METRIC, "value": round(2.0 * m * k / (ms_step * 1e-3) / 1e12, 4), "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"F64 protected matrix-vector product {args.workload}: m=k={m}, {f} weighted "
+                               f"checksum block rows of {b}; per step two flips of y located by weight ratios and "
+                               f"{f} lost blocks of y rebuilt", "m": m, "n": 1, "k": k, "br": b, "bc": 1, "f": f,
+                   "global_batch": 1, "seq_len": 0, "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": round(bytes_read / (g * 1e-3) / 1e9, 1), "peak": 8000.0,
+                     "unit": "GB/s", "frac": round(bytes_read / (g * 1e-3) / 8e12, 4), "traffic": None,
+                     "kernel": "k_sliver (A_f streamed once)", "bytes_per_launch": bytes_read,
+                     "avg_launch_ms": round(g, 4)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_campaign(args):
     """Reliability campaign on one workload: args.campaign clean products on
     fresh seeded inputs (every relation must pass: false positives are counted),
@@ -611,7 +789,7 @@ def main():
         sys.exit(2)
 
     if args.campaign:
-        if args.workload in WEIGHTED or args.workload in PANELS:
+        if args.workload in WEIGHTED or args.workload in PANELS or args.workload in CHAINED or args.workload in GEMV:
             print(json.dumps({"error": f"--campaign is not defined for workload {args.workload}"}))
             sys.exit(2)
         return run_batched_campaign(args) if args.workload == "c5" else run_campaign(args)
@@ -619,6 +797,10 @@ def main():
         return run_batched(args)
     if args.workload in WEIGHTED:
         return run_weighted(args)
+    if args.workload in CHAINED:
+        return run_chained(args)
+    if args.workload in GEMV:
+        return run_gemv(args)
 
     import torch
 
