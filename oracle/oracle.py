@@ -303,3 +303,48 @@ def protected_product(A: np.ndarray, B: np.ndarray, br: int, bc: int):
     """Encode and multiply in FP64: returns (A_f, B_f, C_f)."""
     Af, Bf = encode(A, B, br, bc)
     return Af, Bf, gemm(Af, Bf)
+
+
+# ---------------------------------------------------------------- 2-D block-cyclic distribution (Sec. 4.1)
+def block_cyclic_owner(i: int, nb: int, P: int):
+    """Global index i of a dimension distributed block-cyclically with blocks
+    of nb over P processes: (process p, local index li).  Global block I = i div nb
+    belongs to process I mod P and is that process's local block I div P."""
+    I, ii = divmod(i, nb)
+    return I % P, (I // P) * nb + ii
+
+
+def block_cyclic_stack(G: np.ndarray, nb: int, P: int, Q: int) -> np.ndarray:
+    """The local arrays of a P x Q process grid, stacked: process (p, q)'s
+    local array occupies rows [p*m/P, (p+1)*m/P) and columns [q*n/Q, (q+1)*n/Q).
+    Written element by element from the owner map (m % (nb*P) == 0,
+    n % (nb*Q) == 0, so every local array has the same shape)."""
+    G = _f64(G)
+    m, n = G.shape
+    assert m % (nb * P) == 0 and n % (nb * Q) == 0
+    lm, ln = m // P, n // Q
+    rows = np.empty(m, dtype=np.int64)
+    cols = np.empty(n, dtype=np.int64)
+    for i in range(m):
+        p, li = block_cyclic_owner(i, nb, P)
+        rows[i] = p * lm + li
+    for j in range(n):
+        q, lj = block_cyclic_owner(j, nb, Q)
+        cols[j] = q * ln + lj
+    S = np.empty_like(G)
+    S[np.ix_(rows, cols)] = G
+    return S
+
+
+def block_cyclic_unstack(S: np.ndarray, nb: int, P: int, Q: int) -> np.ndarray:
+    """Inverse of block_cyclic_stack."""
+    S = _f64(S)
+    m, n = S.shape
+    lm, ln = m // P, n // Q
+    G = np.empty_like(S)
+    for i in range(m):
+        p, li = block_cyclic_owner(i, nb, P)
+        for j in range(n):
+            q, lj = block_cyclic_owner(j, nb, Q)
+            G[i, j] = S[p * lm + li, q * ln + lj]
+    return G

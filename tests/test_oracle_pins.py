@@ -521,3 +521,53 @@ def test_exponent_bit_flip_located_on_real_data(orc):
                 assert abs(v - Cf[i, j]) <= tc[i % br, j]
             found += 1
     assert found >= 50
+
+
+# ---------------------------------------------------------------- 2-D block-cyclic distribution (Sec. 4.1)
+def test_block_cyclic_owner_by_hand(orc):
+    """nb = 2 over P = 3: global blocks 0..5 go to processes 0,1,2,0,1,2; local
+    blocks 0,0,0,1,1,1."""
+    got = [orc.block_cyclic_owner(i, 2, 3) for i in range(12)]
+    assert got == [(0, 0), (0, 1), (1, 0), (1, 1), (2, 0), (2, 1),
+                   (0, 2), (0, 3), (1, 2), (1, 3), (2, 2), (2, 3)]
+
+
+def test_block_cyclic_stack_roundtrip_and_checksum_process(orc):
+    """The stacked local arrays are a permutation of the matrix; the block
+    checksum of the stacked layout with br = m/P, bc = n/Q is the checksum
+    process row / column of the grid: the sum over the process rows (columns)
+    of the local arrays, computed here from the owner map alone."""
+    nb, P, Q = 2, 3, 2
+    m, n, k = nb * P * 2, nb * Q * 3, 5
+    A, B = int_problem(m, n, k, seed=77)
+    G = A @ B
+    S = orc.block_cyclic_stack(G, nb, P, Q)
+    assert np.array_equal(orc.block_cyclic_unstack(S, nb, P, Q), G)
+    assert sorted(S.ravel().tolist()) == sorted(G.ravel().tolist())
+    lm, ln = m // P, n // Q
+    # checksum process row: for each (local row, column) the sum over p of the owners' entries
+    want_row = np.zeros((lm, n))
+    for i in range(m):
+        p, li = orc.block_cyclic_owner(i, nb, P)
+        for j in range(n):
+            q, lj = orc.block_cyclic_owner(j, nb, Q)
+            want_row[li, q * ln + lj] += G[i, j]
+    # the product in the stacked layout: rows of A and columns of B permuted as C's
+    Ar = np.empty_like(A)
+    for i in range(m):
+        p, li = orc.block_cyclic_owner(i, nb, P)
+        Ar[p * lm + li] = A[i]
+    Bc = np.empty_like(B)
+    for j in range(n):
+        q, lj = orc.block_cyclic_owner(j, nb, Q)
+        Bc[:, q * ln + lj] = B[:, j]
+    Af, Bf, Cf = orc.protected_product(Ar, Bc, lm, ln)
+    assert np.array_equal(Cf[:m, :n], S)
+    assert np.array_equal(Cf[m:, :n], want_row)
+    want_col = np.zeros((m, ln))
+    for i in range(m):
+        for j in range(n):
+            q, lj = orc.block_cyclic_owner(j, nb, Q)
+            p, li = orc.block_cyclic_owner(i, nb, P)
+            want_col[p * lm + li, lj] += G[i, j]
+    assert np.array_equal(Cf[:m, n:], want_col)
