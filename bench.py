@@ -16,7 +16,7 @@ With --workload c2panel the product runs as a loop of panel updates
 (outer-product form) and the erasure and flip are repaired mid-loop.
 
     python bench.py [--steps K] [--warmup W]
-                    [--workload c2|c2b1|c2panel|c2w|c2chain|c2v|c1|c1b64|c3|c4|c4fp8|c5]
+                    [--workload c2|c2b1|c2panel|c2w|c2chain|c2bc|c2v|c1|c1b64|c3|c4|c4fp8|c5]
                     [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -46,6 +46,7 @@ WORKLOADS = {
     "c2panel": ("f64", 8192, 8192, 8192, 1024, True),
     "c2w": ("f64", 8192, 8192, 8192, 512, True),
     "c2chain": ("f64", 8192, 8192, 8192, 1024, True),
+    "c2bc": ("f64", 8192, 8192, 8192, 1024, True),
     "c2v": ("f64", 16384, 1, 16384, 512, True),
     # batched: 512 bfloat16 problems, m, n, k uniform on multiples of 32 in [64, 2048]
     "c5": ("bf16", 0, 0, 0, 32, True),
@@ -53,6 +54,9 @@ WORKLOADS = {
 PANELS = {"c2panel": 8}
 # chained products (Sec. 3.2): the verified C_f of one n = 8192, b = 1024 product is the A_f of the next
 CHAINED = {"c2chain": {"m": 8192, "n": 8192, "k": 8192, "b": 1024}}
+# 2-D block-cyclic (Sec. 4.1): an 8 x 8 process grid with blocks of 64 over n = 8192; the local arrays are
+# stacked on the GPU, the checksum process row/column is the block checksum of height n/8
+BLOCK_CYCLIC = {"c2bc": {"n": 8192, "nb": 64, "P": 8, "Q": 8}}
 # protected matrix-vector product (weighted checksums, n = 1): A_f streamed once per product
 GEMV = {"c2v": {"m": 16384, "k": 16384, "b": 512, "f": 2}}
 # weighted f-checksums (Sec. 2.1): n = 8192, 512 x 512 blocks (16 x 16 grid), two weighted checksum block rows
@@ -519,6 +523,83 @@ def run_chained(args):
     print(json.dumps(out), flush=True)
 
 
+def run_block_cyclic(args):
+    """Step: the global A and B are stacked into the grid's local arrays (A's
+    rows over the process rows, B's columns over the process columns), encoded
+    (checksum process row and column), multiplied; one process's local array
+    of C_f is lost and one element elsewhere flipped; verify with the loss
+    known, locate, correct, rebuild the process, verify; C unstacked back to
+    the global layout."""
+    import torch
+
+    from paper_0806_3121_amd import abft, synth
+
+    cfg = BLOCK_CYCLIC[args.workload]
+    n, nb, P, Q = cfg["n"], cfg["nb"], cfg["P"], cfg["Q"]
+    m = k = n
+    br, bc = m // P, n // Q
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    log(f"workload {args.workload}: f64 n={n} nb={nb} grid {P}x{Q}")
+    Ag = torch.empty(m, k, dtype=torch.float64, device=dev)
+    Btg = torch.empty(n, k, dtype=torch.float64, device=dev)
+    abft.fill_uniform(abft.ABFT_F64, m, k, k, 0, SEED, synth.STREAM_A, Ag)
+    abft.fill_uniform(abft.ABFT_F64, k, n, k, 1, SEED, synth.STREAM_B, Btg)
+    Pr = abft.Protected(abft.ABFT_F64, m, n, k, br, bc, device=dev)
+    Cg = torch.empty(m, n, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    ev = []
+
+    def step(s):
+        e_st = _timed(torch, stream, lambda: (abft.block_cyclic_stack(Ag, m, k, nb, P, 1, Pr.A[:m]),
+                                              abft.block_cyclic_stack(Btg, n, k, nb, Q, 1, Pr.Bt[:n])))
+        Pr.encode()
+        e_g = _timed(torch, stream, Pr.gemm)
+        pq = synth.erase_block(SEED, s, P, Q)
+        rect = (pq[0] * br, pq[1] * bc, br, bc)
+        i, j, bit = synth.flip_site(SEED, s, m, n, 40, 62, avoid=rect)
+        abft.inject_flip(Pr.p, Pr.C, i, j, bit)
+        abft.inject_erase(Pr.p, Pr.C, rect)
+        rep = Pr.verify(known=[rect])
+        loc = abft.classify(Pr.p, rep, known=[rect])
+        if (loc.cls, loc.i, loc.j) != (abft.ABFT_CLS_DATA, i, j):
+            raise RuntimeError(f"step {s}: flip ({i},{j}) located as {loc.cls} ({loc.i},{loc.j})")
+        abft.correct(Pr.p, Pr.C, loc)
+        abft.recover_block(Pr.p, Pr.C, rect)
+        rep = Pr.verify()
+        if rep.n_flag_c or rep.n_flag_r:
+            raise RuntimeError(f"step {s}: not clean after repair")
+        e_un = _timed(torch, stream, lambda: abft.block_cyclic_unstack(Pr.C[:m, :n], m, n, nb, P, Q, Cg))
+        ev.append((e_st, e_g, e_un))
+
+    dt = _steps(torch, args, step)
+    ev = ev[-args.steps:]
+    st_ms = sum(a.elapsed_time(c) for (a, c), _, _ in ev) / len(ev)
+    g_ms = sum(a.elapsed_time(c) for _, (a, c), _ in ev) / len(ev)
+    un_ms = sum(a.elapsed_time(c) for _, _, (a, c) in ev) / len(ev)
+    useful = 2.0 * m * n * k
+    executed = 2.0 * (m + br) * (n + bc) * k
+    ms_step = dt / args.steps * 1e3
+    out = {
+        "metric": METRIC, "value": round(useful / (ms_step * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"F64 protected GEMM on a 2-D block-cyclic {P}x{Q} grid {args.workload}: n={n}, "
+                               f"blocks of {nb}; local arrays stacked, checksum process row and column; per step "
+                               "one process's local array of C lost and one flip elsewhere",
+                   "m": m, "n": n, "k": k, "br": br, "bc": bc, "nb": nb, "grid": [P, Q], "global_batch": 1,
+                   "seq_len": 0, "parallelism": "single-gpu"},
+        "roofline": {"bound": "mfma", "achieved": round(executed / (g_ms * 1e-3) / 1e12, 3), "peak": PEAK["f64"],
+                     "unit": "TFLOP/s", "frac": round(executed / (g_ms * 1e-3) / 1e12 / PEAK["f64"], 4),
+                     "traffic": None, "kernel": "k_gemm_mfma", "flops_per_launch": executed,
+                     "avg_launch_ms": round(g_ms, 4)},
+        "stack_ms": round(st_ms, 4), "stack_GBps": round(2 * 2 * 8.0 * n * k / (st_ms * 1e-3) / 1e9, 1),
+        "unstack_ms": round(un_ms, 4), "unstack_GBps": round(2 * 8.0 * m * n / (un_ms * 1e-3) / 1e9, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_gemv(args):
     """Protected matrix-vector product y = A x with f weighted checksum block
     rows (a weighted problem with n = 1): encode, product (the streaming
@@ -789,7 +870,8 @@ def main():
         sys.exit(2)
 
     if args.campaign:
-        if args.workload in WEIGHTED or args.workload in PANELS or args.workload in CHAINED or args.workload in GEMV:
+        if args.workload in WEIGHTED or args.workload in PANELS or args.workload in CHAINED or args.workload in GEMV \
+                or args.workload in BLOCK_CYCLIC:
             print(json.dumps({"error": f"--campaign is not defined for workload {args.workload}"}))
             sys.exit(2)
         return run_batched_campaign(args) if args.workload == "c5" else run_campaign(args)
@@ -801,6 +883,8 @@ def main():
         return run_chained(args)
     if args.workload in GEMV:
         return run_gemv(args)
+    if args.workload in BLOCK_CYCLIC:
+        return run_block_cyclic(args)
 
     import torch
 

@@ -490,6 +490,28 @@ int abft_wcorrect(const abft_wproblem *p, void *C_f, const abft_location *locs, 
 int abft_wrecover(const abft_wproblem *p, void *C_f, int dir, const int32_t *blocks, int n_blocks, int64_t lo,
                   int64_t len, void *ws, void *stream);
 
+/*
+ * 2-D block-cyclic distribution (Sec. 4.1: matrices spread over a process grid
+ * in the 2-D block-cyclic format, checksums by rows, by columns or both) on
+ * one GPU.  Over a P x Q grid with blocks of nb, global block (I, J) belongs to
+ * process (I mod P, J mod Q) as its local block (I div P, J div Q).
+ * abft_block_cyclic_stack copies a rows x cols matrix into the stacked
+ * local-array layout: process (p, q)'s local array at rows [p rows/P,
+ * (p+1) rows/P) and columns [q cols/Q, (q+1) cols/Q); unstack is the inverse.
+ * A dimension over one process (P = 1 or Q = 1) is left as it is.  With A's
+ * rows stacked over P and B's columns over Q (B_f^T's rows: stack it with
+ * P = Q_grid, Q = 1), the product in the stacked layout is C stacked, and the
+ * block checksum with br = m/P, bc = n/Q is the grid's checksum process row
+ * and column (the sum of the local arrays over the process rows / columns):
+ * losing process (p, q) is losing block (p, q) of C_f, rebuilt by
+ * abft_recover_block.  elem_size 1, 2, 4 or 8 bytes; rows % (nb P) == 0 when
+ * P > 1, cols % (nb Q) == 0 when Q > 1; source and destination distinct.
+ */
+int abft_block_cyclic_stack(const void *G, int64_t ldg, int64_t rows, int64_t cols, int32_t elem_size, int64_t nb,
+                            int32_t P, int32_t Q, void *S, int64_t lds, void *stream);
+int abft_block_cyclic_unstack(const void *S, int64_t lds, int64_t rows, int64_t cols, int32_t elem_size, int64_t nb,
+                              int32_t P, int32_t Q, void *G, int64_t ldg, void *stream);
+
 /* Last hipError_t seen by this thread (0 if none), and a status message. */
 int abft_last_hip_error(void);
 const char *abft_status_string(int status);

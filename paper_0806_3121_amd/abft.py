@@ -156,6 +156,10 @@ def lib():
             "abft_wcorrect": (C.c_int, [_P(abft_wproblem), _V, _P(abft_location), C.c_int, _V, _V]),
             "abft_wrecover": (C.c_int, [_P(abft_wproblem), _V, C.c_int, _P(C.c_int32), C.c_int, C.c_int64,
                                         C.c_int64, _V, _V]),
+            "abft_block_cyclic_stack": (C.c_int, [_V, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int64,
+                                                  C.c_int32, C.c_int32, _V, C.c_int64, _V]),
+            "abft_block_cyclic_unstack": (C.c_int, [_V, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int64,
+                                                    C.c_int32, C.c_int32, _V, C.c_int64, _V]),
             "abft_last_hip_error": (C.c_int, []),
             "abft_status_string": (C.c_char_p, [C.c_int]),
         }
@@ -537,3 +541,18 @@ class WProtected:
         wverify(self.p, self.C, self.ws, known=known, host_out=self.rep_host)
         torch.cuda.current_stream().synchronize()
         return read_wreport(self.rep_host)
+
+
+# ---------------------------------------------------------------- 2-D block-cyclic layout (Sec. 4.1)
+def block_cyclic_stack(G, rows, cols, nb, P, Q, S, stream=None):
+    """G, S: 2-D device tensors (row-major, any element size); the leading
+    dimensions are their row strides."""
+    return _check("abft_block_cyclic_stack",
+                  lib().abft_block_cyclic_stack(_ptr(G), G.stride(0), rows, cols, G.element_size(), nb, P, Q,
+                                                _ptr(S), S.stride(0), _stream(stream)))
+
+
+def block_cyclic_unstack(S, rows, cols, nb, P, Q, G, stream=None):
+    return _check("abft_block_cyclic_unstack",
+                  lib().abft_block_cyclic_unstack(_ptr(S), S.stride(0), rows, cols, S.element_size(), nb, P, Q,
+                                                  _ptr(G), G.stride(0), _stream(stream)))

@@ -1,6 +1,7 @@
 // Correction of one located element, rebuild of an erased rectangle (both the
 // unit-weight single-checksum recovery of Sec. 2.1 applied to a relation of
 // C_f), the test-only fault injectors and the synthetic-input generator.
+#include <algorithm>
 #include <cmath>
 
 #include "common.h"
@@ -194,4 +195,62 @@ int launch_fill_uniform(int32_t dtype, int64_t rows, int64_t cols, int64_t ld, i
     return ABFT_OK;
 }
 
+
+// ------------------------------------------------------------------ 2-D block-cyclic layout (Sec. 4.1)
+// One dimension of n indices over Pn processes with blocks of nb: global
+// index i is local index ((i/nb) div Pn) nb + i mod nb of process (i/nb) mod Pn;
+// its stacked position is process * (n / Pn) + local index.
+__device__ inline int64_t bc_stacked(int64_t i, int64_t nb, int64_t Pn, int64_t ln) {
+    const int64_t I = i / nb;
+    return (I % Pn) * ln + (I / Pn) * nb + (i - I * nb);
+}
+__device__ inline int64_t bc_global(int64_t r, int64_t nb, int64_t Pn, int64_t ln) {
+    const int64_t p = r / ln, li = r - p * ln, lI = li / nb;
+    return (lI * Pn + p) * nb + (li - lI * nb);
+}
+
+// Copy with the stacked <-> global permutation: destination element (r, c)
+// takes the source element its index maps to.  stack: destination stacked.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_block_cyclic(const T *__restrict__ src, int64_t lds, T *__restrict__ dst,
+                                                          int64_t ldd, int64_t rows, int64_t cols, int64_t nb,
+                                                          int64_t P, int64_t Q, int stack) {
+    const int64_t lm = rows / P, ln = cols / Q, total = rows * cols;
+    for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
+        const int64_t r = t / cols, c = t - r * cols;
+        const int64_t i = stack ? bc_global(r, nb, P, lm) : bc_stacked(r, nb, P, lm);
+        const int64_t j = stack ? bc_global(c, nb, Q, ln) : bc_stacked(c, nb, Q, ln);
+        dst[r * ldd + c] = src[i * lds + j];
+    }
+}
+
+static int block_cyclic_copy(const void *src, int64_t lds, void *dst, int64_t ldd, int64_t rows, int64_t cols,
+                             int32_t es, int64_t nb, int32_t P, int32_t Q, bool stack, hipStream_t s) {
+    if (!src || !dst || rows < 1 || cols < 1 || nb < 1 || P < 1 || Q < 1) return ABFT_E_ARG;
+    if (es != 1 && es != 2 && es != 4 && es != 8) return ABFT_E_ARG;
+    // a dimension over one process is not permuted; over several, every process gets whole blocks alike
+    if ((P > 1 && rows % (nb * P)) || (Q > 1 && cols % (nb * Q)) || lds < cols || ldd < cols) return ABFT_E_ARG;
+    if ((uintptr_t)src % es || (uintptr_t)dst % es) return ABFT_E_ARG;
+    const unsigned grid = (unsigned)std::min<int64_t>((rows * cols + kThreads - 1) / kThreads, 65536);
+    switch (es) {
+    case 1: k_block_cyclic<uint8_t><<<grid, kThreads, 0, s>>>((const uint8_t *)src, lds, (uint8_t *)dst, ldd, rows, cols, nb, P, Q, stack); break;
+    case 2: k_block_cyclic<uint16_t><<<grid, kThreads, 0, s>>>((const uint16_t *)src, lds, (uint16_t *)dst, ldd, rows, cols, nb, P, Q, stack); break;
+    case 4: k_block_cyclic<uint32_t><<<grid, kThreads, 0, s>>>((const uint32_t *)src, lds, (uint32_t *)dst, ldd, rows, cols, nb, P, Q, stack); break;
+    case 8: k_block_cyclic<uint64_t><<<grid, kThreads, 0, s>>>((const uint64_t *)src, lds, (uint64_t *)dst, ldd, rows, cols, nb, P, Q, stack); break;
+    default: return ABFT_E_ARG;
+    }
+    ABFT_LAUNCHED();
+    return ABFT_OK;
+}
+
 }  // namespace abft
+
+extern "C" int abft_block_cyclic_stack(const void *G, int64_t ldg, int64_t rows, int64_t cols, int32_t elem_size,
+                                       int64_t nb, int32_t P, int32_t Q, void *S, int64_t lds, void *stream) {
+    return abft::block_cyclic_copy(G, ldg, S, lds, rows, cols, elem_size, nb, P, Q, true, (hipStream_t)stream);
+}
+
+extern "C" int abft_block_cyclic_unstack(const void *S, int64_t lds, int64_t rows, int64_t cols, int32_t elem_size,
+                                         int64_t nb, int32_t P, int32_t Q, void *G, int64_t ldg, void *stream) {
+    return abft::block_cyclic_copy(S, lds, G, ldg, rows, cols, elem_size, nb, P, Q, false, (hipStream_t)stream);
+}

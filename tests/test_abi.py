@@ -98,6 +98,19 @@ def test_fused_flags_and_flip_hook_rejected():
     assert arm(p32, 0, 0, 31, C.c_void_p(8192)) == abft.ABFT_OK  # host only: arms, launches nothing
 
 
+def test_block_cyclic_arguments_rejected():
+    fake = C.c_void_p(256)
+    call = lambda rows, cols, es, nb, P, Q, ld=4096: _call("abft_block_cyclic_stack", fake, ld, rows, cols, es, nb,
+                                                           P, Q, fake, ld, NULL_STREAM)
+    assert call(512, 512, 3, 64, 2, 2) == abft.ABFT_E_ARG          # element size
+    assert call(500, 512, 8, 64, 2, 2) == abft.ABFT_E_ARG          # rows not whole blocks per process
+    assert call(512, 500, 8, 64, 2, 2) == abft.ABFT_E_ARG
+    assert call(512, 512, 8, 64, 0, 2) == abft.ABFT_E_ARG
+    assert call(512, 512, 8, 64, 2, 2, ld=500) == abft.ABFT_E_ARG  # leading dimension below cols
+    assert _call("abft_block_cyclic_unstack", fake, 512, 512, 512, 8, 64, 2, 2, None, 512,
+                 NULL_STREAM) == abft.ABFT_E_ARG
+
+
 def test_unrecoverable_and_bad_rects_rejected():
     fake = C.c_void_p(256)
     p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1)
