@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -694,6 +695,11 @@ def run_campaign(args):
         A32 = torch.empty(m, k, dtype=torch.float32, device=dev)
         Bt32 = torch.empty(n, k, dtype=torch.float32, device=dev)
 
+    site_k = args.site == "k"
+    if site_k and b != 1:
+        print(json.dumps({"error": "--site k needs a b = 1 workload"}))
+        sys.exit(2)
+
     def product(seed):
         if lowp:
             abft.fill_uniform(abft.ABFT_F32, m, k, k, 0, seed, synth.STREAM_A, A32)
@@ -704,13 +710,16 @@ def run_campaign(args):
             abft.fill_uniform(adt, m, k, k, 0, seed, synth.STREAM_A, P.A)
             abft.fill_uniform(adt, k, n, k, 1, seed, synth.STREAM_B, P.Bt)
         P.encode()
-        P.gemm()
+        P.gemm(abft.ABFT_FUSED if site_k else 0)
+
+    def first_verify():
+        return P.verify_fused() if site_k else P.verify()
 
     t0 = time.perf_counter()
     fp, worst = 0, 0.0
     for r in range(args.campaign):
         product(SEED + 1000 + r)
-        rep = P.verify()
+        rep = first_verify()
         if rep.n_flag_c or rep.n_flag_r:
             fp += 1
         worst = max(worst, rep.max_ratio_c, rep.max_ratio_r)
@@ -725,10 +734,16 @@ def run_campaign(args):
              "both_flagged_located": 0, "one_relation_flagged": 0, "none_flagged": 0}
     t0 = time.perf_counter()
     for r in range(args.campaign):
-        i, j, bit = synth.flip_site(SEED + 17, r, M, N, 0, nbits - 1)
-        P.C.copy_(clean)
-        abft.inject_flip(P.p, P.C, i, j, bit)
-        rep = P.verify()
+        if site_k:
+            # inside the product kernel: an accumulator of the data part, flipped before the epilogue
+            i, j, bit = synth.flip_site(SEED + 17, r, m, n, 0, nbits - 1)
+            abft.arm_accumulator_flip(P.p, P.ws, i, j, bit)
+            P.gemm(abft.ABFT_FUSED)
+        else:
+            i, j, bit = synth.flip_site(SEED + 17, r, M, N, 0, nbits - 1)
+            P.C.copy_(clean)
+            abft.inject_flip(P.p, P.C, i, j, bit)
+        rep = first_verify()
         old = clean[i, j].item()
         col_flag = [f for f in rep.flags_c() if f[0] == i % b and f[1] == j]
         row_flag = [f for f in rep.flags_r() if f[0] == i and f[1] == j % b]
@@ -753,10 +768,156 @@ def run_campaign(args):
         if r % 100 == 0:
             log(f"flip run {r}: {stats}")
     t_flip = time.perf_counter() - t0
-    out = {"campaign": args.workload, "dtype": dt_name, "m": m, "n": n, "k": k, "b": b,
-           "clean_runs": args.campaign, "false_positives": fp, "max_ratio_clean": round(worst, 4),
+    out = {"campaign": args.workload, "site": args.site, "dtype": dt_name, "m": m, "n": n, "k": k, "b": b,
+           "clean_runs": args.campaign, "false_positives": fp, "max_ratio_clean": float(f"{worst:.3g}"),
            "flip_runs": args.campaign, "flip_bits": f"0..{nbits - 1}", **stats,
            "seconds": {"clean": round(t_clean, 1), "flips": round(t_flip, 1)}}
+    print(json.dumps(out), flush=True)
+
+
+def run_weighted_campaign(args):
+    """Reliability campaign on the weighted-checksum workload: args.campaign
+    clean products on fresh seeded inputs (false positives counted), then
+    args.campaign runs with two flips (every bit position, anywhere in C_f, in
+    distinct column groups) located by the weight ratios and corrected, and
+    f lost blocks of one block column rebuilt."""
+    import torch
+
+    from paper_0806_3121_amd import abft, synth
+
+    cfg = WEIGHTED[args.workload]
+    m, n, k, b, f = cfg["m"], cfg["n"], cfg["k"], cfg["b"], cfg["f"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    Gr, Gc = m // b, n // b
+    Wr = 0.5 + (synth.uniform(SEED, synth.STREAM_X, f, Gr) + 1) / 2
+    Wc = 0.5 + (synth.uniform(SEED, synth.STREAM_PICK, f, Gc) + 1) / 2
+    P = abft.WProtected(m, n, k, b, b, Wr, Wc, device=dev)
+
+    def product(seed):
+        abft.fill_uniform(abft.ABFT_F64, m, k, k, 0, seed, synth.STREAM_A, P.A)
+        abft.fill_uniform(abft.ABFT_F64, k, n, k, 1, seed, synth.STREAM_B, P.Bt)
+        P.encode()
+        P.gemm()
+
+    t0 = time.perf_counter()
+    fp, worst = 0, 0.0
+    for r in range(args.campaign):
+        product(SEED + 3000 + r)
+        rep = P.verify()
+        fp += bool(rep.n_fail_c or rep.n_fail_r)
+        worst = max(worst, rep.max_ratio_c, rep.max_ratio_r)
+        if r % 100 == 0:
+            log(f"clean run {r}: false positives so far {fp}, max |D|/tau {worst:.3g}")
+    t_clean = time.perf_counter() - t0
+    product(SEED)
+    clean = P.C.clone()
+    M, N = P.M, P.N
+    # flips whose group failed, by size: non-finite, |delta| >= 1000 tau (clear), below that (near the
+    # threshold: one relation may fail alone, or several weight columns may fit the residuals)
+    st = {"flips": 0, "flips_group_failed": 0, "flips_located": 0, "clear": 0, "clear_located": 0, "near": 0,
+          "near_located": 0, "nonfinite": 0, "runs_all_located_and_corrected": 0, "runs_multi": 0,
+          "erasures_rebuilt": 0}
+    t0 = time.perf_counter()
+    for r in range(args.campaign):
+        P.C.copy_(clean)
+        sites = []
+        t = 0
+        while len(sites) < 2:
+            x, y, bit = synth.flip_site(SEED + 29, 4 * r + t, M, N, 0, 63)
+            t += 1
+            if all((x % b, y) != (u % b, v) for u, v, _ in sites):
+                sites.append((x, y, bit))
+        for (x, y, bit) in sites:
+            v = P.C[x, y].view(torch.int64) ^ (1 << bit)
+            P.C[x, y] = v.view(torch.float64)
+        rep = P.verify()
+        groups = {(g[0], g[1]): g[3] for g in rep.groups_c(f)}
+        status, locs = abft.wlocate(P.p, rep)
+        got = {(l.i, l.j) for l in locs if l.cls in (abft.ABFT_CLS_DATA, abft.ABFT_CLS_CHECKSUM)}
+        st["flips"] += 2
+        for (x, y, _) in sites:
+            if (x % b, y) in groups:
+                hit = (x, y) in got
+                st["flips_group_failed"] += 1
+                st["flips_located"] += hit
+                delta = P.C[x, y].item() - clean[x, y].item()
+                cls = ("nonfinite" if not math.isfinite(delta)
+                       else "clear" if abs(delta) >= 1000 * max(groups[(x % b, y)]) else "near")
+                st[cls] += 1
+                if cls != "nonfinite":
+                    st[cls + "_located"] += hit
+        st["runs_multi"] += status != abft.ABFT_OK
+        if status == abft.ABFT_OK:
+            abft.wcorrect(P.p, P.C, locs, P.ws)
+            rep = P.verify()
+            if not (rep.n_fail_c or rep.n_fail_r) and got == {(x, y) for x, y, _ in sites if (x % b, y) in groups}:
+                st["runs_all_located_and_corrected"] += 1
+        # then f lost blocks of one block column
+        P.C.copy_(clean)
+        lost = synth.pick_distinct(SEED + 5000 + r, f, Gr + f, stream=synth.STREAM_ERASE)
+        J = synth.randint(SEED, synth.STREAM_ERASE, 7000 + r, Gc + f)
+        for g in lost:
+            P.C[g * b:(g + 1) * b, J * b:(J + 1) * b] = float("nan")
+        try:
+            abft.wrecover(P.p, P.C, abft.ABFT_DIR_COL, lost, J * b, b, P.ws)
+            rep = P.verify()
+            err = (P.C - clean).abs().max().item() / clean.abs().max().item()
+            st["erasures_rebuilt"] += bool(not (rep.n_fail_c or rep.n_fail_r) and err < 1e-10)
+        except abft.AbftError:
+            pass
+        if r % 100 == 0:
+            log(f"flip/erasure run {r}: {st}")
+    out = {"campaign": args.workload, "dtype": "f64", "m": m, "n": n, "k": k, "b": b, "f": f,
+           "clean_runs": args.campaign, "false_positives": fp, "max_ratio_clean": float(f"{worst:.3g}"),
+           "runs": args.campaign, "flip_bits": "0..63", **st,
+           "seconds": {"clean": round(t_clean, 1), "faults": round(time.perf_counter() - t0, 1)}}
+    print(json.dumps(out), flush=True)
+
+
+def run_chained_campaign(args):
+    """Clean-run campaign of chained products: args.campaign pairs of chained
+    products on fresh seeded inputs; every relation of both results must pass
+    (the second's threshold carries the first's residual)."""
+    import torch
+
+    from paper_0806_3121_amd import abft, synth
+
+    cfg = CHAINED[args.workload]
+    m, n, k, b = cfg["m"], cfg["n"], cfg["k"], cfg["b"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    P1 = abft.Protected(abft.ABFT_F64, m, n, k, b, b, device=dev)
+    p2 = abft.problem(abft.ABFT_F64, m, n, n, b, b, lda=P1.ldc, ldb=n, ldc=P1.ldc)
+    Bt2 = torch.zeros(n + b, n, dtype=torch.float64, device=dev)
+    ws2 = torch.zeros(abft.workspace_size(p2), dtype=torch.uint8, device=dev)
+    D = torch.zeros(m + b, P1.ldc, dtype=torch.float64, device=dev)
+    host = abft.new_report_buffer()
+    t0 = time.perf_counter()
+    fp1 = fp2 = 0
+    w1 = w2 = 0.0
+    for r in range(args.campaign):
+        seed = SEED + 9000 + r
+        abft.fill_uniform(abft.ABFT_F64, m, k, k, 0, seed, synth.STREAM_A, P1.A)
+        abft.fill_uniform(abft.ABFT_F64, k, n, k, 1, seed, synth.STREAM_B, P1.Bt)
+        abft.fill_uniform(abft.ABFT_F64, n, n, n, 1, seed + 1, synth.STREAM_B, Bt2)
+        P1.encode()
+        P1.gemm()
+        rep = P1.verify()
+        fp1 += bool(rep.n_flag_c or rep.n_flag_r)
+        w1 = max(w1, rep.max_ratio_c, rep.max_ratio_r)
+        abft.encode_chained(p2, P1.Cbuf, Bt2, ws2, P1.p, P1.ws)
+        abft.gemm(p2, P1.Cbuf, Bt2, D, ws2)
+        abft.verify(p2, D, ws2, host_out=host)
+        torch.cuda.current_stream().synchronize()
+        rep = abft.read_report(host)
+        fp2 += bool(rep.n_flag_c or rep.n_flag_r)
+        w2 = max(w2, rep.max_ratio_c, rep.max_ratio_r)
+        if r % 100 == 0:
+            log(f"chained run {r}: false positives {fp1} / {fp2}, max |D|/tau {w1:.3g} / {w2:.3g}")
+    out = {"campaign": args.workload, "dtype": "f64", "m": m, "n": n, "k": k, "b": b, "runs": args.campaign,
+           "false_positives_first": fp1, "false_positives_chained": fp2, "max_ratio_first": float(f"{w1:.3g}"),
+           "max_ratio_chained": float(f"{w2:.3g}"), "seconds": round(time.perf_counter() - t0, 1)}
     print(json.dumps(out), flush=True)
 
 
@@ -870,8 +1031,11 @@ def main():
         sys.exit(2)
 
     if args.campaign:
-        if args.workload in WEIGHTED or args.workload in PANELS or args.workload in CHAINED or args.workload in GEMV \
-                or args.workload in BLOCK_CYCLIC:
+        if args.workload in WEIGHTED:
+            return run_weighted_campaign(args)
+        if args.workload in CHAINED:
+            return run_chained_campaign(args)
+        if args.workload in PANELS or args.workload in GEMV or args.workload in BLOCK_CYCLIC:
             print(json.dumps({"error": f"--campaign is not defined for workload {args.workload}"}))
             sys.exit(2)
         return run_batched_campaign(args) if args.workload == "c5" else run_campaign(args)
