@@ -73,9 +73,6 @@ FLIP_BITS = {"f64": (40, 62), "f32": (24, 29), "bf16": (24, 29), "fp8": (24, 29)
 # WRITE_SIZE on this benchmark, FETCH_SIZE scaled by 2 (a 1 GiB copy reads 0.5 GiB of FETCH_SIZE);
 # summarized in profiles/hbm_traffic_counters_c2_c2panel_c2w_c4_c5.txt.  Re-measure when those kernels change.
 TRAFFIC = {
-    "c2": 28.611e9 + 0.680e9,                       # k_gemm_mfma (checksum blocks tiled with the data)
-    "c2panel": 3.305e9 + 0.679e9,                   # one accumulating panel launch of k_gemm_mfma
-    "c2w": 28.160e9 + 0.680e9,                      # k_gemm_mfma over the weighted-checksum C_f
     "c4": 12.942e9 + 1.122e9 + 2 * 0.539e9,         # k_gemm_lowp2 + two k_sliver launches
     "c5": 5.185e9 + 2.664e9 + 0.226e9 + 0.087e9,    # kb_gemm (tuned tile) + kb_combine
 }
@@ -406,7 +403,7 @@ def run_weighted(args):
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": TRAFFIC.get(args.workload),
-                     "kernel": "k_gemm_mfma (weighted-checksum product, all M x N entries)",
+                     "kernel": "k_gemm_mfma2 (weighted-checksum product, all M x N entries)",
                      "flops_per_launch": executed, "avg_launch_ms": round(gemm_ms, 4)},
         "pct_mfma_peak_useful": round(100 * value / peak, 2),
         "gemm_protected_ms": round(gemm_ms, 4),
@@ -517,7 +514,7 @@ def run_chained(args):
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK["f64"], 4), "traffic": None,
-                     "kernel": "k_gemm_mfma (both products)", "flops_per_launch": executed / 2,
+                     "kernel": "k_gemm_mfma2 (both products)", "flops_per_launch": executed / 2,
                      "avg_launch_ms": round((g1 + g2) / 2, 4)},
         "gemm_first_ms": round(g1, 4), "gemm_chained_ms": round(g2, 4),
     }
@@ -593,7 +590,7 @@ def run_block_cyclic(args):
                    "seq_len": 0, "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": round(executed / (g_ms * 1e-3) / 1e12, 3), "peak": PEAK["f64"],
                      "unit": "TFLOP/s", "frac": round(executed / (g_ms * 1e-3) / 1e12 / PEAK["f64"], 4),
-                     "traffic": None, "kernel": "k_gemm_mfma", "flops_per_launch": executed,
+                     "traffic": None, "kernel": "k_gemm_mfma2", "flops_per_launch": executed,
                      "avg_launch_ms": round(g_ms, 4)},
         "stack_ms": round(st_ms, 4), "stack_GBps": round(2 * 2 * 8.0 * n * k / (st_ms * 1e-3) / 1e9, 1),
         "unstack_ms": round(un_ms, 4), "unstack_GBps": round(2 * 8.0 * m * n / (un_ms * 1e-3) / 1e9, 1),
@@ -1210,7 +1207,7 @@ def main():
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": TRAFFIC.get(args.workload),
-                     "kernel": ("k_gemm_lowp2" if lowp else "k_gemm_mfma") + " + k_sliver (thin checksum blocks)"
+                     "kernel": ("k_gemm_lowp2" if lowp else "k_gemm_mfma2") + " + k_sliver (thin checksum blocks)"
                                + (f", {n_panels} accumulating panel launches per product" if n_panels else ""),
                      "flops_per_launch": executed / max(1, n_panels),
                      "avg_launch_ms": round(gemm_ms / max(1, n_panels), 4)},

@@ -8,6 +8,7 @@
 // accumulation.
 #include "gemm_lowp2_kernel.h"
 #include "gemm_lowp_kernel.h"
+#include "gemm_mfma2_kernel.h"
 #include "gemm_mfma_kernel.h"
 #include "sliver_kernel.h"
 
@@ -36,12 +37,36 @@ static int choose_tile(const TileChoice *tab, int n, int64_t M, int64_t N) {
     return pick;
 }
 
-// binary64 candidates; efficiencies measured on MI355X at 8192^3 and 9216^2 x 8192.
+// binary64 / binary32 direct-to-LDS candidates (K a multiple of the 128-byte slab); per-tile
+// efficiencies measured on MI355X at 8192^3 and 9216^2 x 8192 (binary64).
+static const TileChoice kF64DirectTiles[] = {
+    {0, 256, 128, 1, 0.85}, {1, 128, 128, 2, 0.87}, {2, 128, 96, 2, 0.89}, {3, 96, 96, 2, 0.88},
+};
+static const TileChoice kF32DirectTiles[] = {
+    {0, 256, 128, 1, 0.85}, {1, 128, 128, 2, 0.84},
+};
+
+// binary64 candidates of the register-staged kernel (any even K); efficiencies measured on MI355X at
+// 8192^3 and 9216^2 x 8192.
 static const TileChoice kF64Tiles[] = {
     {0, 256, 128, 1, 0.818}, {1, 128, 128, 2, 0.787}, {2, 128, 96, 2, 0.80}, {3, 96, 96, 2, 0.76},
 };
 static int gemm_main(const double *A, int64_t lda, const double *Bt, int64_t ldb, double *C, int64_t ldc, int64_t M,
                      int64_t N, int64_t K, hipStream_t s, bool acc = false, EpiArgs *e = nullptr) {
+    if (K % 16 == 0) {
+        switch (choose_tile(kF64DirectTiles, 4, M, N)) {
+        case 0: return launch_gemm_mfma2<Mfma2Tile<double, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc, e);
+        case 1:
+            return launch_gemm_mfma2<Mfma2Tile<double, 2, 128, 128, 2, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s,
+                                                                             acc, e);
+        case 2:
+            return launch_gemm_mfma2<Mfma2Tile<double, 2, 128, 96, 2, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc,
+                                                                            e);
+        default:
+            return launch_gemm_mfma2<Mfma2Tile<double, 2, 96, 96, 2, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc,
+                                                                           e);
+        }
+    }
     switch (choose_tile(kF64Tiles, 4, M, N)) {
     case 0: return launch_gemm_tile<MfmaTile<double, 256, 128, 16, 4, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc, e);
     case 1: return launch_gemm_tile<MfmaTile<double, 128, 128, 16, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc, e);
@@ -59,6 +84,14 @@ static const TileChoice kF32Tiles[] = {
 };
 static int gemm_main(const float *A, int64_t lda, const float *Bt, int64_t ldb, float *C, int64_t ldc, int64_t M,
                      int64_t N, int64_t K, hipStream_t s, bool acc = false, EpiArgs *e = nullptr) {
+    if (K % 32 == 0) {
+        switch (choose_tile(kF32DirectTiles, 2, M, N)) {
+        case 0: return launch_gemm_mfma2<Mfma2Tile<float, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc, e);
+        default:
+            return launch_gemm_mfma2<Mfma2Tile<float, 2, 128, 128, 2, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc,
+                                                                            e);
+        }
+    }
     switch (choose_tile(kF32Tiles, 2, M, N)) {
     case 0: return launch_gemm_tile<MfmaTile<float, 256, 128, 32, 4, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc, e);
     default: return launch_gemm_tile<MfmaTile<float, 128, 128, 32, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc, e);
