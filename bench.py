@@ -1210,7 +1210,7 @@ def main():
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": TRAFFIC.get(args.workload),
-                     "kernel": ("k_gemm_lowp2" if lowp else "k_gemm_mfma2") + " + k_sliver (thin checksum blocks)"
+                     "kernel": abft.describe_gemm(P.p, abft.ABFT_FUSED if site_k else 0)
                                + (f", {n_panels} accumulating panel launches per product" if n_panels else ""),
                      "flops_per_launch": executed / max(1, n_panels),
                      "avg_launch_ms": round(gemm_ms / max(1, n_panels), 4)},

@@ -216,6 +216,17 @@ int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f
               void *stream);
 
 /*
+ * Diagnostic: writes to buf (len bytes, NUL-terminated) the kernels and the
+ * block tile abft_gemm would launch for p and flags, e.g.
+ * "k_gemm_mfma2 f64 96x96 on 9216x9216 k=8192" or
+ * "k_gemm_mfma2 f64 128x128 on 8192x8192 k=8192 + k_sliver carried rows + k_sliver carried columns".
+ * No device work, no allocation.  Returns ABFT_OK; ABFT_E_ARG for an invalid
+ * problem, unknown flags, a NULL buf or a len too short for the text (buf
+ * then holds a truncated string).
+ */
+int abft_describe_gemm(const abft_problem *p, uint32_t flags, char *buf, size_t len);
+
+/*
  * Panel update (outer-product form of the product, Sec. 2.2 and the rank-nb
  * updates of Sec. 3.2): C_f = A_f[:, k0:k1) B_f[k0:k1, :), or with
  * flags & ABFT_ACCUMULATE, C_f += A_f[:, k0:k1) B_f[k0:k1, :), over the same

@@ -124,6 +124,7 @@ def lib():
             "abft_encode_chained": (C.c_int, [_P(abft_problem), _V, _V, _V, _P(abft_problem), _V, _V]),
             "abft_gemm": (C.c_int, [_P(abft_problem), _V, _V, _V, _V, C.c_uint32, _V]),
             "abft_gemm_panel": (C.c_int, [_P(abft_problem), _V, _V, _V, C.c_int64, C.c_int64, C.c_uint32, _V]),
+            "abft_describe_gemm": (C.c_int, [_P(abft_problem), C.c_uint32, C.c_char_p, C.c_size_t]),
             "abft_quantize": (C.c_int, [_P(abft_problem), C.c_int, _V, C.c_int64, _V, _V, _V]),
             "abft_verify": (C.c_int, [_P(abft_problem), _V, _P(abft_rect), C.c_int, _V, _V, _V]),
             "abft_verify_fused": (C.c_int, [_P(abft_problem), _V, _V, _V, _V]),
@@ -220,6 +221,13 @@ def encode_chained(p, A_f, B_f, ws, prev, ws_prev, stream=None):
 def gemm(p, A_f, B_f, C_f, ws=None, flags=0, stream=None):
     return _check("abft_gemm", lib().abft_gemm(C.byref(p), _ptr(A_f), _ptr(B_f), _ptr(C_f), _ptr(ws), flags,
                                                _stream(stream)))
+
+
+def describe_gemm(p, flags=0) -> str:
+    """The kernels and block tile abft_gemm launches for p and flags."""
+    buf = C.create_string_buffer(256)
+    _check("abft_describe_gemm", lib().abft_describe_gemm(C.byref(p), C.c_uint32(flags), buf, C.c_size_t(256)))
+    return buf.value.decode()
 
 
 def gemm_panel(p, A_f, B_f, C_f, k0, k1, flags=0, stream=None):

@@ -290,6 +290,15 @@ int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f
     return launch_gemm(p, A_f, B_f, C_f, flags, ws, (hipStream_t)stream);
 }
 
+int abft_describe_gemm(const abft_problem *p, uint32_t flags, char *buf, size_t len) {
+    int st = check_problem(p);
+    if (st) return st;
+    if (!buf || len == 0) return ABFT_E_ARG;
+    buf[0] = 0;
+    if (flags & ~(ABFT_PLAIN | ABFT_FUSED)) return ABFT_E_ARG;
+    return describe_gemm(p, flags, buf, len);
+}
+
 int abft_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, int64_t k0, int64_t k1,
                     uint32_t flags, void *stream) {
     int st = check_problem(p);

@@ -222,6 +222,7 @@ int launch_skinny_f64(const double *A, int64_t lda, const double *Bt, int64_t ld
                       int64_t M, int64_t N, int64_t K, hipStream_t s);
 int launch_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, int64_t k0, int64_t k1,
                       uint32_t flags, hipStream_t s);
+int describe_gemm(const abft_problem *p, uint32_t flags, char *buf, size_t len);
 int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, void *ws,
                 hipStream_t s);
 int launch_verify(const abft_problem *p, const void *C_f, const Erasures &er, char *ws, hipStream_t s);

@@ -1,17 +1,21 @@
 // Protected product C_f = A_f B_f (Eq. ABFT-GEMM) dispatch.
 //
 // The data part and any thick checksum block (b > kSliverMaxB) run on the
-// matrix cores (gemm_mfma_kernel.h).  A thin checksum block (b <= kSliverMaxB,
-// e.g. the classic b = 1) would occupy a whole row or column of tiles for a
-// few useful rows, so it is computed instead by the skinny-product kernel
-// (sliver_kernel.h), which streams the other operand once with binary64
-// accumulation.
+// matrix cores (gemm_mfma2_kernel.h / gemm_mfma_kernel.h for binary64 and
+// binary32, gemm_lowp2_kernel.h / gemm_lowp_kernel.h for bfloat16 and FP8).
+// A thin checksum block (b <= kSliverMaxB, e.g. the classic b = 1) would
+// occupy a whole row or column of tiles for a few useful rows, so it is
+// computed instead by the skinny-product kernel (sliver_kernel.h), which
+// streams the other operand once with binary64 accumulation.  The tile pick
+// lives in one function per element type, used by the launch and by
+// abft_describe_gemm alike.
 #include "gemm_lowp2_kernel.h"
 #include "gemm_lowp_kernel.h"
 #include "gemm_mfma2_kernel.h"
 #include "gemm_mfma_kernel.h"
 #include "sliver_kernel.h"
 
+#include <cstdio>
 #include <mutex>
 #include <unordered_map>
 
@@ -22,25 +26,27 @@ constexpr int64_t kSliverMaxB = 8;
 struct TileChoice { int id; int bm, bn, per_cu; double eff; };
 
 // Estimated time ~ rounds of resident blocks x time per round (tile flops x
-// blocks per CU / per-tile efficiency); the smallest wins.  256 CUs.
+// blocks per CU / per-tile efficiency); the smallest wins.  256 CUs.  Returns
+// the index of the pick in tab.
 static int choose_tile(const TileChoice *tab, int n, int64_t M, int64_t N) {
     double best = 0;
-    int pick = tab[0].id;
+    int pick = 0;
     for (int q = 0; q < n; ++q) {
         const TileChoice &t = tab[q];
         int64_t tiles = ((M + t.bm - 1) / t.bm) * ((N + t.bn - 1) / t.bn);
         int64_t slots = 256 * t.per_cu;
         double rounds = (double)((tiles + slots - 1) / slots);
         double cost = rounds * (double)t.bm * t.bn * t.per_cu / t.eff;
-        if (best == 0 || cost < best) { best = cost; pick = t.id; }
+        if (best == 0 || cost < best) { best = cost; pick = q; }
     }
     return pick;
 }
 
 // binary64 / binary32 direct-to-LDS candidates (K a multiple of the 128-byte slab); per-tile
-// efficiencies measured on MI355X at 8192^3 and 9216^2 x 8192 (binary64).
+// efficiencies measured on MI355X at 8192^3 and 9216^2 x 8192 (binary64).  A 256 x 128 binary64
+// tile (0.85) is never cheaper than 128 x 128 at two blocks per CU and is not offered.
 static const TileChoice kF64DirectTiles[] = {
-    {0, 256, 128, 1, 0.85}, {1, 128, 128, 2, 0.87}, {2, 128, 96, 2, 0.89}, {3, 96, 96, 2, 0.88},
+    {1, 128, 128, 2, 0.87}, {2, 128, 96, 2, 0.89}, {3, 96, 96, 2, 0.88},
 };
 static const TileChoice kF32DirectTiles[] = {
     {0, 256, 128, 1, 0.85}, {1, 128, 128, 2, 0.84},
@@ -51,11 +57,30 @@ static const TileChoice kF32DirectTiles[] = {
 static const TileChoice kF64Tiles[] = {
     {0, 256, 128, 1, 0.818}, {1, 128, 128, 2, 0.787}, {2, 128, 96, 2, 0.80}, {3, 96, 96, 2, 0.76},
 };
+// binary32 candidates (same shapes; the f32 matrix core is twice as fast per instruction).
+static const TileChoice kF32Tiles[] = {
+    {0, 256, 128, 1, 0.80}, {1, 128, 128, 2, 0.78},
+};
+
+// The data-part kernel and tile for an M x N x K product of element type E.
+struct MainPick {
+    bool direct;            // direct-to-LDS kernel (else register-staged / padded-LDS)
+    const TileChoice *t;
+};
+static MainPick pick_main(const double *, int64_t M, int64_t N, int64_t K) {
+    if (K % 16 == 0) return {true, &kF64DirectTiles[choose_tile(kF64DirectTiles, 3, M, N)]};
+    return {false, &kF64Tiles[choose_tile(kF64Tiles, 4, M, N)]};
+}
+static MainPick pick_main(const float *, int64_t M, int64_t N, int64_t K) {
+    if (K % 32 == 0) return {true, &kF32DirectTiles[choose_tile(kF32DirectTiles, 2, M, N)]};
+    return {false, &kF32Tiles[choose_tile(kF32Tiles, 2, M, N)]};
+}
+
 static int gemm_main(const double *A, int64_t lda, const double *Bt, int64_t ldb, double *C, int64_t ldc, int64_t M,
                      int64_t N, int64_t K, hipStream_t s, bool acc = false, EpiArgs *e = nullptr) {
-    if (K % 16 == 0) {
-        switch (choose_tile(kF64DirectTiles, 4, M, N)) {
-        case 0: return launch_gemm_mfma2<Mfma2Tile<double, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc, e);
+    const MainPick pk = pick_main(A, M, N, K);
+    if (pk.direct) {
+        switch (pk.t->id) {
         case 1:
             return launch_gemm_mfma2<Mfma2Tile<double, 2, 128, 128, 2, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s,
                                                                              acc, e);
@@ -67,7 +92,7 @@ static int gemm_main(const double *A, int64_t lda, const double *Bt, int64_t ldb
                                                                            e);
         }
     }
-    switch (choose_tile(kF64Tiles, 4, M, N)) {
+    switch (pk.t->id) {
     case 0: return launch_gemm_tile<MfmaTile<double, 256, 128, 16, 4, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc, e);
     case 1: return launch_gemm_tile<MfmaTile<double, 128, 128, 16, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc, e);
     case 2:
@@ -78,21 +103,18 @@ static int gemm_main(const double *A, int64_t lda, const double *Bt, int64_t ldb
     }
 }
 
-// binary32 candidates (same shapes; the f32 matrix core is twice as fast per instruction).
-static const TileChoice kF32Tiles[] = {
-    {0, 256, 128, 1, 0.80}, {1, 128, 128, 2, 0.78},
-};
 static int gemm_main(const float *A, int64_t lda, const float *Bt, int64_t ldb, float *C, int64_t ldc, int64_t M,
                      int64_t N, int64_t K, hipStream_t s, bool acc = false, EpiArgs *e = nullptr) {
-    if (K % 32 == 0) {
-        switch (choose_tile(kF32DirectTiles, 2, M, N)) {
+    const MainPick pk = pick_main(A, M, N, K);
+    if (pk.direct) {
+        switch (pk.t->id) {
         case 0: return launch_gemm_mfma2<Mfma2Tile<float, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc, e);
         default:
             return launch_gemm_mfma2<Mfma2Tile<float, 2, 128, 128, 2, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc,
                                                                             e);
         }
     }
-    switch (choose_tile(kF32Tiles, 2, M, N)) {
+    switch (pk.t->id) {
     case 0: return launch_gemm_tile<MfmaTile<float, 256, 128, 32, 4, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc, e);
     default: return launch_gemm_tile<MfmaTile<float, 128, 128, 32, 2, 2>>(A, lda, Bt, ldb, C, ldc, M, N, K, s, acc, e);
     }
@@ -129,14 +151,18 @@ static int protected_product(const abft_problem *p, const Geom &g, const E *A, c
 static const TileChoice kLowpTiles[] = {
     {0, 256, 256, 1, 0.411}, {1, 128, 128, 2, 0.303},
 };
+static const TileChoice kLowpDirectTile = {0, 256, 256, 1, 0.49};
+static MainPick pick_main_lowp(int64_t elem_size, int64_t M, int64_t N, int64_t K) {
+    if (K % (128 / elem_size) == 0 && M * N >= (int64_t)256 * 256 * 256) return {true, &kLowpDirectTile};
+    return {false, &kLowpTiles[choose_tile(kLowpTiles, 2, M, N)]};
+}
 template <class Ops, class Ops2>
 static int gemm_main_lowp(const typename Ops::E *A, int64_t lda, const typename Ops::E *Bt, int64_t ldb, float *C,
                           int64_t ldc, int64_t M, int64_t N, int64_t K, const int *scale_exp, hipStream_t s,
                           EpiArgs *e = nullptr) {
-    constexpr int64_t slab = 128 / (int64_t)sizeof(typename Ops::E);
-    if (K % slab == 0 && M * N >= (int64_t)256 * 256 * 256)
-        return launch_gemm_lowp2<Ops2, 4>(A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp, s, e);
-    switch (choose_tile(kLowpTiles, 2, M, N)) {
+    const MainPick pk = pick_main_lowp((int64_t)sizeof(typename Ops::E), M, N, K);
+    if (pk.direct) return launch_gemm_lowp2<Ops2, 4>(A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp, s, e);
+    switch (pk.t->id) {
     case 0:
         return launch_gemm_lowp_tile<LowpTile<Ops, 256, 256, 128 / sizeof(typename Ops::E), 4, 2>>(
             A, lda, Bt, ldb, C, ldc, M, N, K, scale_exp, s, e);
@@ -199,6 +225,39 @@ int launch_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, v
     default:
         return ABFT_E_UNSUPPORTED;
     }
+}
+
+// The kernels and tiles launch_gemm runs for p and flags, as text (a
+// diagnostic: tests check that every tile is exercised, benchmarks report it).
+int describe_gemm(const abft_problem *p, uint32_t flags, char *buf, size_t len) {
+    const Geom g = geom_of(p);
+    const bool plain = flags & ABFT_PLAIN;
+    const bool lowp = p->dtype == ABFT_BF16 || p->dtype == ABFT_FP8_E4M3;
+    static const char *const kDt[] = {"f64", "f32", "bf16", "fp8"};
+    bool thin_r, thin_c;
+    int64_t Mm, Nm;
+    MainPick pk;
+    const char *kname;
+    if (lowp) {
+        thin_r = thin_c = !plain;             // every carried block from the workspace checksum rows
+        Mm = g.m;
+        Nm = g.n;
+        pk = pick_main_lowp(p->dtype == ABFT_BF16 ? 2 : 1, Mm, Nm, g.k);
+        kname = pk.direct ? "k_gemm_lowp2" : "k_gemm_lowp";
+    } else {
+        thin_r = !plain && g.S * g.br <= kSliverMaxB;
+        thin_c = !plain && g.S * g.bc <= kSliverMaxB;
+        Mm = (plain || thin_r) ? g.m : g.M;
+        Nm = (plain || thin_c) ? g.n : g.N;
+        pk = p->dtype == ABFT_F64 ? pick_main((const double *)nullptr, Mm, Nm, g.k)
+                                  : pick_main((const float *)nullptr, Mm, Nm, g.k);
+        kname = pk.direct ? "k_gemm_mfma2" : "k_gemm_mfma";
+    }
+    const int n = snprintf(buf, len, "%s %s %dx%d on %lldx%lld k=%lld%s%s%s", kname, kDt[p->dtype], pk.t->bm,
+                           pk.t->bn, (long long)Mm, (long long)Nm, (long long)g.k,
+                           thin_r ? " + k_sliver carried rows" : "", (lowp && !plain) ? " + k_sliver corner" : "",
+                           thin_c ? " + k_sliver carried columns" : "");
+    return (n < 0 || (size_t)n >= len) ? ABFT_E_ARG : ABFT_OK;
 }
 
 // Host registry per workspace: the one-shot accumulator flip armed for the

@@ -98,6 +98,29 @@ def test_fused_flags_and_flip_hook_rejected():
     assert arm(p32, 0, 0, 31, C.c_void_p(8192)) == abft.ABFT_OK  # host only: arms, launches nothing
 
 
+def test_describe_gemm_names_kernels_and_tiles():
+    """Host-only: the kernel and tile the product dispatch picks, per dtype and shape."""
+    d = lambda dt, m, n, k, b, flags=0: abft.describe_gemm(abft.problem(dt, m, n, k, b, b), flags)
+    assert d(abft.ABFT_F64, 8192, 8192, 8192, 1024) == "k_gemm_mfma2 f64 96x96 on 9216x9216 k=8192"
+    assert d(abft.ABFT_F64, 8192, 8192, 8192, 1) == ("k_gemm_mfma2 f64 128x128 on 8192x8192 k=8192"
+                                                     " + k_sliver carried rows + k_sliver carried columns")
+    assert d(abft.ABFT_F64, 8192, 8192, 8192, 1, abft.ABFT_PLAIN) == "k_gemm_mfma2 f64 128x128 on 8192x8192 k=8192"
+    assert d(abft.ABFT_F64, 256, 256, 250, 64) == "k_gemm_mfma f64 96x96 on 320x320 k=250"
+    assert d(abft.ABFT_F32, 16384, 8192, 32768, 1).startswith("k_gemm_mfma2 f32 256x128 on 16384x8192 k=32768")
+    assert d(abft.ABFT_BF16, 16384, 16384, 16384, 1) == (
+        "k_gemm_lowp2 bf16 256x256 on 16384x16384 k=16384"
+        " + k_sliver carried rows + k_sliver corner + k_sliver carried columns")
+    assert d(abft.ABFT_FP8_E4M3, 300, 260, 528, 1, abft.ABFT_PLAIN) == "k_gemm_lowp fp8 128x128 on 300x260 k=528"
+    p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1)
+    buf = C.create_string_buffer(16)
+    assert _call("abft_describe_gemm", C.byref(p), 0, buf, 16) == abft.ABFT_E_ARG      # too short
+    assert buf.value == b"k_gemm_mfma2 f6"                                             # truncated, terminated
+    assert _call("abft_describe_gemm", C.byref(p), 8, buf, 16) == abft.ABFT_E_ARG      # unknown flag
+    assert _call("abft_describe_gemm", C.byref(p), 0, None, 16) == abft.ABFT_E_ARG
+    bad = abft.problem(abft.ABFT_F64, 256, 256, 256, 3, 1)                              # br does not divide m
+    assert _call("abft_describe_gemm", C.byref(bad), 0, C.create_string_buffer(256), 256) == abft.ABFT_E_ARG
+
+
 def test_block_cyclic_arguments_rejected():
     fake = C.c_void_p(256)
     call = lambda rows, cols, es, nb, P, Q, ld=4096: _call("abft_block_cyclic_stack", fake, ld, rows, cols, es, nb,

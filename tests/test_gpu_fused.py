@@ -59,13 +59,16 @@ def fused_gemm(P):
 
 
 CASES = [
-    ("f64", 520, 392, 256),      # 128 x 96 tiles, ragged edges
-    ("f64", 2048, 2048, 512),    # 256 x 128 tiles
-    ("f32", 384, 640, 1000),     # K tail
-    ("bf16", 512, 384, 1024),    # padded-LDS kernel
-    ("bf16", 4096, 4096, 256),   # direct-to-LDS kernel
-    ("fp8", 300, 260, 528),      # padded-LDS kernel, ragged
-    ("fp8", 4096, 4096, 256),    # direct-to-LDS kernel (scaled epilogue)
+    ("f64", 520, 392, 256, "k_gemm_mfma2 f64 96x96"),       # direct-to-LDS, ragged edges
+    ("f64", 776, 5384, 32, "k_gemm_mfma2 f64 128x96"),
+    ("f64", 1032, 5384, 32, "k_gemm_mfma2 f64 128x128"),
+    ("f64", 520, 392, 250, "k_gemm_mfma f64 96x96"),        # register-staged (k % 16 != 0)
+    ("f32", 384, 640, 1024, "k_gemm_mfma2 f32 256x128"),
+    ("f32", 384, 640, 1000, "k_gemm_mfma f32 256x128"),     # K tail
+    ("bf16", 512, 384, 1024, "k_gemm_lowp bf16 128x128"),   # padded-LDS kernel
+    ("bf16", 4096, 4096, 256, "k_gemm_lowp2 bf16 256x256"),  # direct-to-LDS kernel
+    ("fp8", 300, 260, 528, "k_gemm_lowp fp8 128x128"),      # padded-LDS kernel, ragged
+    ("fp8", 4096, 4096, 256, "k_gemm_lowp2 fp8 256x256"),    # direct-to-LDS kernel (scaled epilogue)
 ]
 IDS = [f"{c[0]}-{c[1]}x{c[2]}x{c[3]}" for c in CASES]
 BITS = {"f64": (55, 60), "f32": (26, 28), "bf16": (26, 28), "fp8": (26, 28)}
@@ -73,9 +76,10 @@ BITS = {"f64": (55, 60), "f32": (26, 28), "bf16": (26, 28), "fp8": (26, 28)}
 
 @pytest.mark.parametrize("case", CASES, ids=IDS)
 def test_fused_clean_and_accumulator_flips(dev, case):
-    dt, m, n, k = case
+    dt, m, n, k, kernel = case
     note(f"fused {case}")
     P = make(dev, dt, m, n, k)
+    assert abft.describe_gemm(P.p, abft.ABFT_FUSED).startswith(kernel + " on"), abft.describe_gemm(P.p, abft.ABFT_FUSED)
     fused_gemm(P)
     torch.cuda.synchronize()
     clean = P.C.clone()
