@@ -80,6 +80,9 @@ TRAFFIC = {
     "c5": 5.185e9 + 2.664e9 + 0.226e9 + 0.087e9,    # kb_gemm (tuned tile) + kb_combine
 }
 SEED = 20080523
+# bound on max|C - C_oracle| / max|C_oracle| for the reported oracle check: binary64 as the parity tests;
+# binary32 accumulation of k products of magnitude <= 1 (rounding of the sum, stored binary32)
+TOL_VS_ORACLE = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-5, "fp8": 1e-5}
 
 
 def log(msg):
@@ -89,7 +92,7 @@ def log(msg):
 def cpu_baseline(dt_name, m, n, k, b, target_s=12.0):
     """Oracle (FP64 i-l-j loops, all host threads) on leading rows of the same
     encoded product, sized to about target_s seconds; returns (TFLOP/s,
-    threads, seconds, rows)."""
+    threads, seconds, rows, the oracle's rows of C_f)."""
     import numpy as np
 
     from oracle import oracle as orc
@@ -120,10 +123,21 @@ def cpu_baseline(dt_name, m, n, k, b, target_s=12.0):
     A = synth.uniform_rows(SEED, synth.STREAM_A, np.arange(rows), k, ndt).astype(ndt)
     t0 = time.perf_counter()
     A = quant(A)
-    orc.gemm(A, Bf)
+    Cref = orc.gemm(A, Bf)
     dt = time.perf_counter() - t0
     flops = 2.0 * rows * (n + b) * k
-    return flops / dt / 1e12, orc.num_threads(), dt, rows
+    return flops / dt / 1e12, orc.num_threads(), dt, rows, Cref
+
+
+def oracle_check(C_dev, Cref, cols):
+    """Largest |C_gpu - C_oracle| / max|C_oracle| over the oracle's rows and
+    the first cols columns of the device's final C_f."""
+    import numpy as np
+
+    rows = Cref.shape[0]
+    Cg = C_dev[:rows, :cols].double().cpu().numpy()
+    Co = Cref[:, :cols]
+    return float(np.abs(Cg - Co).max() / max(np.abs(Co).max(), 1e-300))
 
 
 def cpu_baseline_batched(shapes, br, bc, target_s=12.0):
@@ -416,7 +430,10 @@ def run_weighted(args):
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        tf, thr, sec, rows = cpu_baseline("f64", m, n, k, f * b, args.cpu_seconds)
+        tf, thr, sec, rows, Cref = cpu_baseline("f64", m, n, k, f * b, args.cpu_seconds)
+        # data columns only: the oracle's sample encodes unit-weight checksum columns
+        out["oracle_check"] = {"rows": rows, "cols": n, "max_rel_err": oracle_check(P.C, Cref, n),
+                               "bound": 1e-12}
         out["cpu_baseline"] = {"value": round(tf, 6), "unit": "TFLOP/s", "cores": thr, "kind": "oracle",
                                "sample": f"rows 0..{rows - 1} of an encoded product ({rows} x {n + f * b} x {k}, "
                                          f"FP64 i-l-j loops), {sec:.1f} s"}
@@ -1223,10 +1240,14 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        tf, thr, sec, rows = cpu_baseline(dt_name, m, n, k, b, args.cpu_seconds)
+        tf, thr, sec, rows, Cref = cpu_baseline(dt_name, m, n, k, b, args.cpu_seconds)
         out["cpu_baseline"] = {"value": round(tf, 6), "unit": "TFLOP/s", "cores": thr, "kind": "oracle",
                                "sample": f"rows 0..{rows - 1} of the encoded product C_f = A_f B_f "
                                          f"({rows} x {n + b} x {k}, FP64 i-l-j loops), {sec:.1f} s"}
+        # the last step's repaired C_f against the oracle's rows (the same seeded inputs, quantized by the
+        # oracle's own rounding for bfloat16 / FP8)
+        out["oracle_check"] = {"rows": rows, "cols": n + b, "max_rel_err": oracle_check(P.C, Cref, n + b),
+                               "bound": TOL_VS_ORACLE[dt_name]}
     print(json.dumps(out), flush=True)
 
 
