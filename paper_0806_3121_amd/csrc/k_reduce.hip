@@ -623,6 +623,74 @@ __global__ __launch_bounds__(kThreads) void k_vrow_block(const T *C, VerifyArgs 
     fold_block(ratio, excl, &a.rep->max_ratio_r, &a.rep->n_excl_r);
 }
 
+// One pass over C_f for wide checksum blocks: thread t owns residue r and the
+// V consecutive residues c0..c0+V-1 and walks the (Gr+1) x (Gc+1) grid of
+// blocks (the last block row / column is the carried one), so it holds every
+// member of the column relations (r, h*bc + c) and of the row relations
+// (g*br + r, c): both directions from one read of C_f.  Sums run over the
+// groups in increasing order with the carried term subtracted last, as in the
+// two-pass kernels, so the residuals are the same numbers.  Needs Gc < GMAX.
+constexpr int kBlockPassMaxG = 9;    // up to 8 x 8 data blocks plus the carried ones
+template <typename T, int V>
+__global__ __launch_bounds__(kThreads) void k_vblock(const T *C, VerifyArgs a) {
+    constexpr int GMAX = kBlockPassMaxG;
+    const int64_t cv = a.bc / V, total = a.br * cv;
+    double ratio_c = 0.0, ratio_r = 0.0;
+    unsigned long long excl_c = 0, excl_r = 0;
+    for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
+        const int64_t r = t / cv, c0 = (t - r * cv) * V;
+        double cs[GMAX][V];
+#pragma unroll
+        for (int h = 0; h < GMAX; ++h)
+#pragma unroll
+            for (int q = 0; q < V; ++q) cs[h][q] = 0.0;
+        for (int64_t g = 0; g <= a.Gr; ++g) {
+            const int64_t i = g * a.br + r;
+            const T *row = C + i * a.ldc + c0;
+            double rs[V], v[GMAX][V];
+#pragma unroll
+            for (int q = 0; q < V; ++q) rs[q] = 0.0;
+#pragma unroll
+            for (int h = 0; h < GMAX; ++h)
+                if (h <= a.Gc) load_c<T, V>(row + h * a.bc, v[h]);
+            double carried[V];
+#pragma unroll
+            for (int q = 0; q < V; ++q) carried[q] = 0.0;
+#pragma unroll
+            for (int h = 0; h < GMAX; ++h) {
+                if (h > a.Gc) break;
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    if (h < a.Gc) rs[q] += v[h][q];
+                    else carried[q] = v[h][q];
+                    if (g < a.Gr) cs[h][q] += v[h][q];
+                }
+            }
+            // row relations (i, c0 + q): data columns summed, the carried column last
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                if (row_rel_erased(a.er, i, c0 + q, a.bc)) excl_r++;
+                else ratio_r = fmax(ratio_r, record(a.rep, false, i, c0 + q, rs[q] - carried[q], tau_row(a, i, c0 + q)));
+            }
+            if (g < a.Gr) continue;
+            // column relations (r, j): data rows summed, the carried row last
+#pragma unroll
+            for (int h = 0; h < GMAX; ++h) {
+                if (h > a.Gc) break;
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    const int64_t j = h * a.bc + c0 + q;
+                    if (col_rel_erased(a.er, r, j, a.br)) excl_c++;
+                    else ratio_c = fmax(ratio_c, record(a.rep, true, r, j, cs[h][q] - v[h][q], tau_col(a, r, j)));
+                }
+            }
+        }
+    }
+    fold_block(ratio_c, excl_c, &a.rep->max_ratio_c, &a.rep->n_excl_c);
+    __syncthreads();   // fold_block's shared slots are reused
+    fold_block(ratio_r, excl_r, &a.rep->max_ratio_r, &a.rep->n_excl_r);
+}
+
 template <typename T>
 static int verify_typed(const abft_problem *p, const T *C, const Erasures &er, char *ws, hipStream_t s) {
     Geom g = geom_of(p);
@@ -646,6 +714,13 @@ static int verify_typed(const abft_problem *p, const T *C, const Erasures &er, c
     constexpr int VV = 16 / (int)sizeof(T);
     const bool vec = ((uintptr_t)C % 16 == 0) && (p->ldc % VV == 0);
     const int64_t V = vec ? VV : 1;
+    // wide checksum blocks with few groups per row: one pass for both directions
+    if (sizeof(T) == 8 && vec && g.bc % VV == 0 && g.bc >= 64 && g.Gc < kBlockPassMaxG &&
+        g.br * (g.bc / VV) >= 65536) {
+        k_vblock<double, 2><<<blocks(g.br * (g.bc / 2)), kThreads, 0, s>>>((const double *)C, a);
+        ABFT_LAUNCHED();
+        return ABFT_OK;
+    }
     int64_t P = group_partitions(g.Gr, g.br, (g.N + V - 1) / V);
     if (P == 1) {
         if (vec) k_vcol_direct<T, VV><<<blocks(g.br * ((g.N + VV - 1) / VV)), kThreads, 0, s>>>(C, a);

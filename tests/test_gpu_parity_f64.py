@@ -50,6 +50,7 @@ SHAPES = [
     (64, 64, 16, 64, 64),       # one group (G = 1)
     (384, 640, 1000, 3, 5),     # odd block sizes, K tail
     (130, 34, 2, 2, 2),         # tiny K
+    (1536, 1024, 64, 512, 512), # wide blocks, few groups: one-pass verify of both directions
 ]
 
 
@@ -135,7 +136,8 @@ def _oracle_decision(orc, Cf, m, n, br, bc, tc, tr, i, j, bit, known=None):
 
 
 @pytest.mark.parametrize("m,n,k,br,bc,runs", [(256, 256, 256, 1, 1, 48), (256, 256, 256, 64, 64, 24),
-                                              (200, 136, 72, 8, 4, 24), (1024, 512, 384, 128, 1, 16)])
+                                              (200, 136, 72, 8, 4, 24), (1024, 512, 384, 128, 1, 16),
+                                              (1536, 1024, 64, 512, 512, 24)])
 def test_flip_detect_locate_correct(dev, orc, m, n, k, br, bc, runs):
     """Seeded single bit flips (bits 40..62) anywhere in C_f, data and
     checksums: the GPU flags, location and class equal the oracle's; the
@@ -179,6 +181,7 @@ def test_flip_detect_locate_correct(dev, orc, m, n, k, br, bc, runs):
 @pytest.mark.parametrize("m,n,k,b,rects", [
     (256, 256, 256, 64, [(64, 128, 64, 64), (0, 0, 64, 64), (256, 192, 64, 64), (192, 256, 64, 64), (256, 256, 64, 64)]),
     (1024, 1024, 128, 128, [(384, 512, 128, 128), (1024, 0, 128, 128), (17, 33, 100, 90)]),
+    (1024, 1024, 64, 512, [(512, 0, 512, 512), (1024, 512, 512, 512), (100, 700, 300, 200)]),  # one-pass verify
 ])
 def test_erase_and_rebuild_block(dev, orc, m, n, k, b, rects):
     """Zeroed or NaN-filled blocks (data, carried row block, carried column
