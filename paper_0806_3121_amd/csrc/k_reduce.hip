@@ -623,72 +623,112 @@ __global__ __launch_bounds__(kThreads) void k_vrow_block(const T *C, VerifyArgs 
     fold_block(ratio, excl, &a.rep->max_ratio_r, &a.rep->n_excl_r);
 }
 
+// Erasure tests of the one-pass kernel: the residues of each known
+// rectangle's first row (mod br) and first column (mod bc) are taken on the
+// host, so a test is a few comparisons on kernel arguments (the same answer as
+// col_rel_erased / row_rel_erased for 0 <= r < br and 0 <= c < bc).
+struct ErasureRes {
+    int n;
+    int64_t i0[4], j0[4], h[4], w[4], ri[4], cj[4];
+};
+static ErasureRes erasure_res(const Erasures &e, int64_t br, int64_t bc) {
+    ErasureRes x{};
+    x.n = e.n;
+    for (int q = 0; q < e.n && q < 4; ++q) {
+        x.i0[q] = e.i0[q]; x.j0[q] = e.j0[q]; x.h[q] = e.h[q]; x.w[q] = e.w[q];
+        x.ri[q] = e.i0[q] % br;
+        x.cj[q] = e.j0[q] % bc;
+    }
+    return x;
+}
+__device__ inline bool col_erased_res(const ErasureRes &e, int64_t r, int64_t j, int64_t br) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q >= e.n) break;
+        if (j < e.j0[q] || j >= e.j0[q] + e.w[q]) continue;
+        if (e.h[q] >= br) return true;
+        const int64_t off = r >= e.ri[q] ? r - e.ri[q] : r - e.ri[q] + br;
+        if (off < e.h[q]) return true;
+    }
+    return false;
+}
+__device__ inline bool row_erased_res(const ErasureRes &e, int64_t i, int64_t c, int64_t bc) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q >= e.n) break;
+        if (i < e.i0[q] || i >= e.i0[q] + e.h[q]) continue;
+        if (e.w[q] >= bc) return true;
+        const int64_t off = c >= e.cj[q] ? c - e.cj[q] : c - e.cj[q] + bc;
+        if (off < e.w[q]) return true;
+    }
+    return false;
+}
+
 // One pass over C_f for wide checksum blocks: thread t owns residue r and the
 // V consecutive residues c0..c0+V-1 and walks the (Gr+1) x (Gc+1) grid of
 // blocks (the last block row / column is the carried one), so it holds every
 // member of the column relations (r, h*bc + c) and of the row relations
 // (g*br + r, c): both directions from one read of C_f.  Sums run over the
 // groups in increasing order with the carried term subtracted last, as in the
-// two-pass kernels, so the residuals are the same numbers.  Needs Gc < GMAX.
-constexpr int kBlockPassMaxG = 9;    // up to 8 x 8 data blocks plus the carried ones
-template <typename T, int V>
-__global__ __launch_bounds__(kThreads) void k_vblock(const T *C, VerifyArgs a) {
-    constexpr int GMAX = kBlockPassMaxG;
+// two-pass kernels, so the residuals are the same numbers.  GC = Gc, 1..8.
+constexpr int kBlockPassMaxG = 8;    // data block columns: up to 8 (the carried one makes 9)
+template <typename T, int V, int GC>
+__global__ __launch_bounds__(kThreads) void k_vblock(const T *C, VerifyArgs a, ErasureRes er) {
     const int64_t cv = a.bc / V, total = a.br * cv;
     double ratio_c = 0.0, ratio_r = 0.0;
     unsigned long long excl_c = 0, excl_r = 0;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
         const int64_t r = t / cv, c0 = (t - r * cv) * V;
-        double cs[GMAX][V];
+        double cs[GC + 1][V];
 #pragma unroll
-        for (int h = 0; h < GMAX; ++h)
+        for (int h = 0; h <= GC; ++h)
 #pragma unroll
             for (int q = 0; q < V; ++q) cs[h][q] = 0.0;
-        for (int64_t g = 0; g <= a.Gr; ++g) {
-            const int64_t i = g * a.br + r;
-            const T *row = C + i * a.ldc + c0;
-            double rs[V], v[GMAX][V];
-#pragma unroll
-            for (int q = 0; q < V; ++q) rs[q] = 0.0;
-#pragma unroll
-            for (int h = 0; h < GMAX; ++h)
-                if (h <= a.Gc) load_c<T, V>(row + h * a.bc, v[h]);
-            double carried[V];
-#pragma unroll
-            for (int q = 0; q < V; ++q) carried[q] = 0.0;
-#pragma unroll
-            for (int h = 0; h < GMAX; ++h) {
-                if (h > a.Gc) break;
-#pragma unroll
-                for (int q = 0; q < V; ++q) {
-                    if (h < a.Gc) rs[q] += v[h][q];
-                    else carried[q] = v[h][q];
-                    if (g < a.Gr) cs[h][q] += v[h][q];
-                }
-            }
-            // row relations (i, c0 + q): data columns summed, the carried column last
+        // row relations (i, c0 + q): data columns summed, the carried column last
+        auto rows_of = [&](int64_t i, const double (&v)[GC + 1][V]) {
 #pragma unroll
             for (int q = 0; q < V; ++q) {
-                if (row_rel_erased(a.er, i, c0 + q, a.bc)) excl_r++;
-                else ratio_r = fmax(ratio_r, record(a.rep, false, i, c0 + q, rs[q] - carried[q], tau_row(a, i, c0 + q)));
-            }
-            if (g < a.Gr) continue;
-            // column relations (r, j): data rows summed, the carried row last
+                double rs = 0.0;
 #pragma unroll
-            for (int h = 0; h < GMAX; ++h) {
-                if (h > a.Gc) break;
-#pragma unroll
-                for (int q = 0; q < V; ++q) {
-                    const int64_t j = h * a.bc + c0 + q;
-                    if (col_rel_erased(a.er, r, j, a.br)) excl_c++;
-                    else ratio_c = fmax(ratio_c, record(a.rep, true, r, j, cs[h][q] - v[h][q], tau_col(a, r, j)));
-                }
+                for (int h = 0; h < GC; ++h) rs += v[h][q];
+                if (er.n && row_erased_res(er, i, c0 + q, a.bc)) excl_r++;
+                else ratio_r = fmax(ratio_r, record(a.rep, false, i, c0 + q, rs - v[GC][q], tau_row(a, i, c0 + q)));
             }
+        };
+        for (int64_t g = 0; g < a.Gr; ++g) {
+            const int64_t i = g * a.br + r;
+            double v[GC + 1][V];
+#pragma unroll
+            for (int h = 0; h <= GC; ++h) load_c<T, V>(C + i * a.ldc + h * a.bc + c0, v[h]);
+            rows_of(i, v);
+#pragma unroll
+            for (int h = 0; h <= GC; ++h)
+#pragma unroll
+                for (int q = 0; q < V; ++q) cs[h][q] += v[h][q];
         }
+        // the carried row: its row relations, then the column relations (r, j),
+        // data rows summed, the carried row last
+        const int64_t i = a.m + r;
+        double v[GC + 1][V];
+#pragma unroll
+        for (int h = 0; h <= GC; ++h) load_c<T, V>(C + i * a.ldc + h * a.bc + c0, v[h]);
+        rows_of(i, v);
+#pragma unroll
+        for (int h = 0; h <= GC; ++h)
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                const int64_t j = h * a.bc + c0 + q;
+                if (er.n && col_erased_res(er, r, j, a.br)) excl_c++;
+                else ratio_c = fmax(ratio_c, record(a.rep, true, r, j, cs[h][q] - v[h][q], tau_col(a, r, j)));
+            }
     }
     fold_block(ratio_c, excl_c, &a.rep->max_ratio_c, &a.rep->n_excl_c);
     __syncthreads();   // fold_block's shared slots are reused
     fold_block(ratio_r, excl_r, &a.rep->max_ratio_r, &a.rep->n_excl_r);
+}
+template <int GC>
+static void launch_vblock(const double *C, const VerifyArgs &a, const ErasureRes &er, unsigned grid, hipStream_t s) {
+    k_vblock<double, 2, GC><<<grid, kThreads, 0, s>>>(C, a, er);
 }
 
 template <typename T>
@@ -715,9 +755,21 @@ static int verify_typed(const abft_problem *p, const T *C, const Erasures &er, c
     const bool vec = ((uintptr_t)C % 16 == 0) && (p->ldc % VV == 0);
     const int64_t V = vec ? VV : 1;
     // wide checksum blocks with few groups per row: one pass for both directions
-    if (sizeof(T) == 8 && vec && g.bc % VV == 0 && g.bc >= 64 && g.Gc < kBlockPassMaxG &&
+    if (sizeof(T) == 8 && vec && g.bc % VV == 0 && g.bc >= 64 && g.Gc <= kBlockPassMaxG &&
         g.br * (g.bc / VV) >= 65536) {
-        k_vblock<double, 2><<<blocks(g.br * (g.bc / 2)), kThreads, 0, s>>>((const double *)C, a);
+        const double *Cd = (const double *)C;
+        const ErasureRes ex = erasure_res(er, g.br, g.bc);
+        const unsigned grid = blocks(g.br * (g.bc / 2));
+        switch (g.Gc) {
+        case 1: launch_vblock<1>(Cd, a, ex, grid, s); break;
+        case 2: launch_vblock<2>(Cd, a, ex, grid, s); break;
+        case 3: launch_vblock<3>(Cd, a, ex, grid, s); break;
+        case 4: launch_vblock<4>(Cd, a, ex, grid, s); break;
+        case 5: launch_vblock<5>(Cd, a, ex, grid, s); break;
+        case 6: launch_vblock<6>(Cd, a, ex, grid, s); break;
+        case 7: launch_vblock<7>(Cd, a, ex, grid, s); break;
+        default: launch_vblock<8>(Cd, a, ex, grid, s); break;
+        }
         ABFT_LAUNCHED();
         return ABFT_OK;
     }
