@@ -25,6 +25,11 @@ int64_t group_partitions(int64_t G, int64_t b, int64_t cols) {
     return P;
 }
 
+bool rows_fused(const abft_problem *p) {
+    const int64_t vpe = 16 / (int64_t)dtype_size(p->dtype);
+    return p->tau_mode == ABFT_TAU_DET && (p->k / vpe) % 64 == 0;
+}
+
 WsLayout ws_layout(const abft_problem *p) {
     Geom g = geom_of(p);
     WsLayout L;
@@ -56,6 +61,8 @@ WsLayout ws_layout(const abft_problem *p) {
     if (pc > 1) need = std::max(need, (size_t)(pc * g.br * g.N));
     L.partial_bytes = sizeof(double) * need;
     L.partial = take(L.partial_bytes > 0 ? L.partial_bytes : 8);
+    // fused row statistics: the larger operand's data rows plus its checksum and group rows, k / 64 slots each
+    L.rowpart = take(rows_fused(p) ? sizeof(double) * (std::max(g.m, g.n) + 2 * std::max(g.br, g.bc)) * (g.k / 64) : 8);
     L.report = take(sizeof(abft_report));
     // fused partials (b = 1 only): column sums per tile row, row sums per tile column
     const bool fused = g.br == 1 && g.bc == 1;

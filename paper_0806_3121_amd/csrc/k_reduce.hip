@@ -86,46 +86,82 @@ template <typename TC> __device__ inline void finish_encode(double sv, double ss
     *grp = stat ? ssv + (double)c * (double)c : ssv;
 }
 
+// Row partials of the fused row statistics (det thresholds): with rp set, a
+// wave whose 64 lanes hold 64 consecutive vectors of one row also writes the
+// sum of squares of that 64-vector chunk, rp[row * rps + chunk]: data row
+// g*b + r, checksum row R + r, group-statistic row R + b + r.  The host sets
+// rp only when k / V is a multiple of 64, so every wave is whole and shares r.
+__device__ inline void row_partial(double *rp, int64_t rps, int64_t row, int64_t chunk, double q2) {
+    q2 = wave_sum(q2);
+    if (threadIdx.x % kWave == 0) rp[row * rps + chunk] = q2;
+}
+
 // Each thread owns V = 16/sizeof(T) consecutive columns l (one 16-byte load per
 // row); rows of X are 16-byte aligned and k is a multiple of V.
 template <typename T, typename TC>
 __global__ __launch_bounds__(kThreads) void k_encode_direct(const T *X, int64_t ld, int64_t b, int64_t G, int64_t k,
-                                                            TC *CS, int64_t ldcs, bool stat, double *grp) {
+                                                            TC *CS, int64_t ldcs, bool stat, double *grp, double *rp,
+                                                            int64_t rps) {
     constexpr int V = vec16<T>::N;
     const int64_t kv = k / V, total = b * kv;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
         int64_t r = t / kv, l0 = (t - r * kv) * V;
+        const int64_t chunk = l0 / (kWave * V);
         double s[V], ss[V], v[V];
 #pragma unroll
         for (int q = 0; q < V; ++q) s[q] = ss[q] = 0.0;
         const T *p = X + r * ld + l0;
         for (int64_t g = 0; g < G; ++g) {
             vec16<T>::load(p + g * b * ld, v);
+            double q2 = 0.0;
 #pragma unroll
-            for (int q = 0; q < V; ++q) { s[q] += v[q]; ss[q] += stat ? v[q] * v[q] : fabs(v[q]); }
+            for (int q = 0; q < V; ++q) {
+                s[q] += v[q];
+                ss[q] += stat ? v[q] * v[q] : fabs(v[q]);
+                q2 += v[q] * v[q];
+            }
+            if (rp) row_partial(rp, rps, g * b + r, chunk, q2);
         }
+        double c2 = 0.0, g2 = 0.0;
 #pragma unroll
-        for (int q = 0; q < V; ++q) finish_encode<TC>(s[q], ss[q], stat, CS + r * ldcs + l0 + q, grp + r * k + l0 + q);
+        for (int q = 0; q < V; ++q) {
+            finish_encode<TC>(s[q], ss[q], stat, CS + r * ldcs + l0 + q, grp + r * k + l0 + q);
+            const double c = (double)(TC)s[q], gv = stat ? ss[q] + c * c : ss[q];
+            c2 += c * c;
+            g2 += gv * gv;
+        }
+        if (rp) {
+            row_partial(rp, rps, G * b + r, chunk, c2);
+            row_partial(rp, rps, G * b + b + r, chunk, g2);
+        }
     }
 }
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_encode_partial(const T *X, int64_t ld, int64_t b, int64_t G, int64_t k,
-                                                             int64_t P, int64_t chunk, bool stat, double *part) {
+                                                             int64_t P, int64_t chunk, bool stat, double *part,
+                                                             double *rp, int64_t rps) {
     constexpr int V = vec16<T>::N;
     const int64_t kv = k / V, rel = b * k, total = P * b * kv;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
         int64_t p = t / (b * kv), q = t - p * (b * kv);
         int64_t r = q / kv, l0 = (q - r * kv) * V;
         int64_t g0 = p * chunk, g1 = min(G, g0 + chunk);
+        const int64_t lc = l0 / (kWave * V);
         double s[V], ss[V], v[V];
 #pragma unroll
         for (int e = 0; e < V; ++e) s[e] = ss[e] = 0.0;
         const T *src = X + r * ld + l0;
         for (int64_t g = g0; g < g1; ++g) {
             vec16<T>::load(src + g * b * ld, v);
+            double q2 = 0.0;
 #pragma unroll
-            for (int e = 0; e < V; ++e) { s[e] += v[e]; ss[e] += stat ? v[e] * v[e] : fabs(v[e]); }
+            for (int e = 0; e < V; ++e) {
+                s[e] += v[e];
+                ss[e] += stat ? v[e] * v[e] : fabs(v[e]);
+                q2 += v[e] * v[e];
+            }
+            if (rp) row_partial(rp, rps, g * b + r, lc, q2);
         }
 #pragma unroll
         for (int e = 0; e < V; ++e) {
@@ -137,7 +173,8 @@ __global__ __launch_bounds__(kThreads) void k_encode_partial(const T *X, int64_t
 
 template <typename TC>
 __global__ __launch_bounds__(kThreads) void k_encode_finish(int64_t b, int64_t k, TC *CS, int64_t ldcs, bool stat,
-                                                            int64_t P, const double *part, double *grp) {
+                                                            int64_t P, const double *part, double *grp, double *rp,
+                                                            int64_t rps, int64_t R) {
     const int64_t rel = b * k;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < rel; t += (int64_t)gridDim.x * kThreads) {
         int64_t r = t / k, l = t - r * k;
@@ -147,6 +184,27 @@ __global__ __launch_bounds__(kThreads) void k_encode_finish(int64_t b, int64_t k
             ssv += part[(2 * p + 1) * rel + t];
         }
         finish_encode<TC>(sv, ssv, stat, CS + r * ldcs + l, grp + t);
+        if (rp) {
+            const double c = (double)(TC)sv, gv = stat ? ssv + c * c : ssv;
+            row_partial(rp, rps, R + r, l / kWave, c * c);
+            row_partial(rp, rps, R + b + r, l / kWave, gv * gv);
+        }
+    }
+}
+
+// The fused row statistics from their partials: ||row||_2 of the R data rows
+// and b checksum rows (out[0 .. R + b)) and of the b group-statistic rows
+// (out_grp), each summing its chunks in order.
+__global__ __launch_bounds__(kThreads) void k_rows_finish(const double *rp, int64_t rps, int64_t R, int64_t b,
+                                                          int64_t n_data, int64_t n_tail, double *out,
+                                                          double *out_grp) {
+    const int64_t rows = R + 2 * b;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < rows; i += (int64_t)gridDim.x * kThreads) {
+        const int64_t nc = i < R ? n_data : n_tail;
+        double acc = 0.0;
+        for (int64_t c = 0; c < nc; ++c) acc += rp[i * rps + c];
+        if (i < R + b) out[i] = sqrt(acc);
+        else out_grp[i - R - b] = sqrt(acc);
     }
 }
 
@@ -216,21 +274,32 @@ static void row_stats(const T *X, int64_t ld, int64_t rows, int64_t k, int mode,
 static unsigned grid_for(int64_t work) { return (unsigned)std::min<int64_t>((work + kThreads - 1) / kThreads, 65536); }
 static unsigned rows_grid(int64_t rows) { return (unsigned)std::min<int64_t>(std::max<int64_t>(rows, 1), 65536); }
 
-// Pass 1 over one operand: checksum rows CS (ldcs) and grp.
+// Pass 1 over one operand: checksum rows CS (ldcs) and grp; with rp (det
+// thresholds, k / V a multiple of 64) also the row-statistic partials of the
+// data, checksum and group rows, finished into rows_out (R + b) and grp_out (b).
 template <typename T, typename TC>
 static void encode_pass1(const T *X, int64_t ld, int64_t R, int64_t b, int64_t k, TC *CS, int64_t ldcs, bool stat,
-                         double *grp, double *part, hipStream_t s) {
+                         double *grp, double *part, hipStream_t s, double *rp = nullptr, double *rows_out = nullptr,
+                         double *grp_out = nullptr) {
     constexpr int V = vec16<T>::N;
     int64_t G = R / b;
     int64_t P = group_partitions(G, b, k / V);
+    const int64_t rps = k / kWave;                 // partial slots per row (chunks of 64 columns at most)
+    int64_t n_tail;
     if (P == 1) {
-        k_encode_direct<T, TC><<<grid_for(b * k / V), kThreads, 0, s>>>(X, ld, b, G, k, CS, ldcs, stat, grp);
+        k_encode_direct<T, TC><<<grid_for(b * k / V), kThreads, 0, s>>>(X, ld, b, G, k, CS, ldcs, stat, grp, rp, rps);
+        n_tail = k / (kWave * V);
     } else {
         int64_t chunk = (G + P - 1) / P;
         P = (G + chunk - 1) / chunk;
-        k_encode_partial<T><<<grid_for(P * b * k / V), kThreads, 0, s>>>(X, ld, b, G, k, P, chunk, stat, part);
-        k_encode_finish<TC><<<grid_for(b * k), kThreads, 0, s>>>(b, k, CS, ldcs, stat, P, part, grp);
+        k_encode_partial<T><<<grid_for(P * b * k / V), kThreads, 0, s>>>(X, ld, b, G, k, P, chunk, stat, part, rp,
+                                                                          rps);
+        k_encode_finish<TC><<<grid_for(b * k), kThreads, 0, s>>>(b, k, CS, ldcs, stat, P, part, grp, rp, rps, R);
+        n_tail = k / kWave;
     }
+    if (rp)
+        k_rows_finish<<<grid_for(R + 2 * b), kThreads, 0, s>>>(rp, rps, R, b, k / (kWave * V), n_tail, rows_out,
+                                                               grp_out);
 }
 
 // Pass 2 over one operand: a statistic per row of the data rows and of the
@@ -252,6 +321,18 @@ static int encode_typed(const abft_problem *p, T *A, T *Bt, TC *Acs, int64_t lda
     double *part = (double *)(ws + L.partial);
     double *grpA = (double *)(ws + L.grpA), *grpB = (double *)(ws + L.grpB);
     const bool stat = p->tau_mode == ABFT_TAU_STAT;
+    if (rows_fused(p)) {
+        // det thresholds: every row statistic from the encode pass (no second read of A and B)
+        double *rp = (double *)(ws + L.rowpart);
+        encode_pass1<T, TC>(A, p->lda, g.m, g.br, g.k, Acs, ldacs, false, grpA, part, s, rp,
+                            (double *)(ws + L.na), (double *)(ws + L.na_abs));
+        encode_pass1<T, TC>(Bt, p->ldb, g.n, g.bc, g.k, Bcs, ldbcs, false, grpB, part, s, rp,
+                            (double *)(ws + L.nb), (double *)(ws + L.nb_abs));
+        k_fill_zero<<<1, kThreads, 0, s>>>((double *)(ws + L.chain_a), g.br);
+        k_fill_zero<<<1, kThreads, 0, s>>>((double *)(ws + L.chain_w), g.N);
+        ABFT_LAUNCHED();
+        return ABFT_OK;
+    }
     encode_pass1<T, TC>(A, p->lda, g.m, g.br, g.k, Acs, ldacs, stat, grpA, part, s);
     encode_pass1<T, TC>(Bt, p->ldb, g.n, g.bc, g.k, Bcs, ldbcs, stat, grpB, part, s);
     // row statistics (det: na, nb; stat: qr, qc) and the norms of the grp rows
