@@ -190,6 +190,7 @@ struct WsLayout {
     size_t chain_a, chain_w;         // chained products (binary64): inherited threshold term chain_a[r] chain_w[j]
     size_t chain_cs;                 // chained products: the recomputed checksum rows (discarded; br x k double)
     size_t rowpart;                  // fused row statistics (det): per-row partial sums of squares
+    size_t vpart_c, vpart_r;         // one-pass re-read verification for b = 1: tile partial sums (double)
     size_t report;                   // abft_report
     size_t total;
     size_t partial_bytes;

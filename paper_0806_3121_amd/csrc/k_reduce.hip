@@ -812,68 +812,88 @@ static void launch_vblock(const double *C, const VerifyArgs &a, const ErasureRes
     k_vblock<double, 2, GC><<<grid, kThreads, 0, s>>>(C, a, er);
 }
 
-template <typename T>
-static int verify_typed(const abft_problem *p, const T *C, const Erasures &er, char *ws, hipStream_t s) {
-    Geom g = geom_of(p);
-    WsLayout L = ws_layout(p);
-    TauCoef tc = tau_coef(p);
-    VerifyArgs a;
-    a.m = g.m; a.n = g.n; a.br = g.br; a.bc = g.bc; a.S = g.S; a.Gr = g.Gr; a.Gc = g.Gc; a.M = g.M; a.N = g.N;
-    a.ldc = p->ldc;
-    a.mode = tc.mode; a.cc = tc.cc; a.cr = tc.cr;
-    a.na = (const double *)(ws + L.na); a.na_abs = (const double *)(ws + L.na_abs);
-    a.nb = (const double *)(ws + L.nb); a.nb_abs = (const double *)(ws + L.nb_abs);
-    a.chain_a = (const double *)(ws + L.chain_a); a.chain_w = (const double *)(ws + L.chain_w);
-    a.qr = (const double *)(ws + L.qr); a.qc = (const double *)(ws + L.qc);
-    a.nv = (const double *)(ws + L.nv); a.nw = (const double *)(ws + L.nw);
-    a.scale_exp = p->dtype == ABFT_FP8_E4M3 ? (const int *)(ws + L.scale) : nullptr;
-    a.rep = (abft_report *)(ws + L.report);
-    a.er = er;
-    k_report_init<<<1, kThreads, 0, s>>>(a.rep);
-    auto blocks = [](int64_t work) { return (unsigned)std::min<int64_t>((work + kThreads - 1) / kThreads, 4096); };
-    // 16-byte loads when every row of C starts on a 16-byte boundary
-    constexpr int VV = 16 / (int)sizeof(T);
-    const bool vec = ((uintptr_t)C % 16 == 0) && (p->ldc % VV == 0);
-    const int64_t V = vec ? VV : 1;
-    // wide checksum blocks with few groups per row: one pass for both directions
-    if (sizeof(T) == 8 && vec && g.bc % VV == 0 && g.bc >= 64 && g.Gc <= kBlockPassMaxG &&
-        g.br * (g.bc / VV) >= 65536) {
-        const double *Cd = (const double *)C;
-        const ErasureRes ex = erasure_res(er, g.br, g.bc);
-        const unsigned grid = blocks(g.br * (g.bc / 2));
-        switch (g.Gc) {
-        case 1: launch_vblock<1>(Cd, a, ex, grid, s); break;
-        case 2: launch_vblock<2>(Cd, a, ex, grid, s); break;
-        case 3: launch_vblock<3>(Cd, a, ex, grid, s); break;
-        case 4: launch_vblock<4>(Cd, a, ex, grid, s); break;
-        case 5: launch_vblock<5>(Cd, a, ex, grid, s); break;
-        case 6: launch_vblock<6>(Cd, a, ex, grid, s); break;
-        case 7: launch_vblock<7>(Cd, a, ex, grid, s); break;
-        default: launch_vblock<8>(Cd, a, ex, grid, s); break;
+// Re-read verification for b = 1 in one pass over C: tile partial sums of the
+// data part, column sums of each kPartRows-row tile (pc[tile row][j]) and row
+// sums of each 64V-column tile (pr[tile column][i]), the layout the product
+// epilogue writes for the fused verification; k_vfused then finishes the
+// relations.  A wave takes rows w, w + 4, ... of its tile, four at a time.
+constexpr int64_t kPartRows = 128;
+template <typename T, int V>
+__global__ __launch_bounds__(kThreads) void k_vpartials(const T *C, int64_t ldc, int64_t m, int64_t n, double *pc,
+                                                        double *pr) {
+    constexpr int NW = kThreads / kWave;
+    constexpr int64_t TCW = (int64_t)kWave * V;
+    __shared__ double sh[NW][TCW];
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int64_t tiles_n = (n + TCW - 1) / TCW, tiles = ((m + kPartRows - 1) / kPartRows) * tiles_n;
+    for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const int64_t tm = tile / tiles_n, tn = tile - tm * tiles_n;
+        const int64_t i0 = tm * kPartRows, i1 = min(m, i0 + kPartRows), j0 = tn * TCW + lane * V;
+        double cs[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) cs[q] = 0.0;
+        // rows of C are 16-byte aligned and ldc is a multiple of V: a vector that starts before n stays
+        // inside its row; its elements at n and beyond are not summed
+        auto add_row = [&](const double (&v)[V], double &rs) {
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                const double x = j0 + q < n ? v[q] : 0.0;
+                cs[q] += x;
+                rs += x;
+            }
+        };
+        int64_t i = i0 + w;
+        for (; i + 3 * NW < i1; i += 4 * NW) {
+            double v0[V], v1[V], v2[V], v3[V];
+            if (j0 < n) {
+                load_c<T, V>(C + i * ldc + j0, v0);
+                load_c<T, V>(C + (i + NW) * ldc + j0, v1);
+                load_c<T, V>(C + (i + 2 * NW) * ldc + j0, v2);
+                load_c<T, V>(C + (i + 3 * NW) * ldc + j0, v3);
+            } else {
+#pragma unroll
+                for (int q = 0; q < V; ++q) v0[q] = v1[q] = v2[q] = v3[q] = 0.0;
+            }
+            double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+            add_row(v0, r0);
+            add_row(v1, r1);
+            add_row(v2, r2);
+            add_row(v3, r3);
+            r0 = wave_sum(r0);
+            r1 = wave_sum(r1);
+            r2 = wave_sum(r2);
+            r3 = wave_sum(r3);
+            if (lane == 0) {
+                pr[tn * m + i] = r0;
+                pr[tn * m + i + NW] = r1;
+                pr[tn * m + i + 2 * NW] = r2;
+                pr[tn * m + i + 3 * NW] = r3;
+            }
         }
-        ABFT_LAUNCHED();
-        return ABFT_OK;
+        for (; i < i1; i += NW) {
+            double v0[V];
+            if (j0 < n) load_c<T, V>(C + i * ldc + j0, v0);
+            else {
+#pragma unroll
+                for (int q = 0; q < V; ++q) v0[q] = 0.0;
+            }
+            double r0 = 0.0;
+            add_row(v0, r0);
+            r0 = wave_sum(r0);
+            if (lane == 0) pr[tn * m + i] = r0;
+        }
+#pragma unroll
+        for (int q = 0; q < V; ++q) sh[w][lane * V + q] = cs[q];
+        __syncthreads();
+        for (int64_t c = threadIdx.x; c < TCW; c += kThreads) {
+            const int64_t j = tn * TCW + c;
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) t += sh[q][c];
+            if (j < n) pc[tm * n + j] = t;
+        }
+        __syncthreads();
     }
-    int64_t P = group_partitions(g.Gr, g.br, (g.N + V - 1) / V);
-    if (P == 1) {
-        if (vec) k_vcol_direct<T, VV><<<blocks(g.br * ((g.N + VV - 1) / VV)), kThreads, 0, s>>>(C, a);
-        else k_vcol_direct<T, 1><<<blocks(g.br * g.N), kThreads, 0, s>>>(C, a);
-    } else {
-        int64_t chunk = (g.Gr + P - 1) / P;
-        P = (g.Gr + chunk - 1) / chunk;
-        double *part = (double *)(ws + L.partial);
-        if (vec) k_vcol_partial<T, VV><<<blocks(P * g.br * ((g.N + VV - 1) / VV)), kThreads, 0, s>>>(C, a, P, chunk, part);
-        else k_vcol_partial<T, 1><<<blocks(P * g.br * g.N), kThreads, 0, s>>>(C, a, P, chunk, part);
-        k_vcol_finish<T><<<blocks(g.br * g.N), kThreads, 0, s>>>(C, a, P, part);
-    }
-    if (g.bc == 1 && vec)
-        k_vrow_block<T, VV><<<(unsigned)std::min<int64_t>(g.M, 8192), kThreads, 0, s>>>(C, a);
-    else if (g.bc < 64 && (kThreads % g.bc) == 0)
-        k_vrow_block<T, 1><<<(unsigned)std::min<int64_t>(g.M, 8192), kThreads, 0, s>>>(C, a);
-    else
-        k_vrow_strided<T><<<blocks(g.M * g.bc), kThreads, 0, s>>>(C, a);
-    ABFT_LAUNCHED();
-    return ABFT_OK;
 }
 
 // Fused verification (b = 1): the column relations of the data columns and
@@ -926,6 +946,81 @@ __global__ __launch_bounds__(kThreads) void k_vfused_edges(const T *C, VerifyArg
     }
     if (col) fold_block(ratio, excl, &a.rep->max_ratio_c, &a.rep->n_excl_c);
     else fold_block(ratio, excl, &a.rep->max_ratio_r, &a.rep->n_excl_r);
+}
+
+template <typename T>
+static int verify_typed(const abft_problem *p, const T *C, const Erasures &er, char *ws, hipStream_t s) {
+    Geom g = geom_of(p);
+    WsLayout L = ws_layout(p);
+    TauCoef tc = tau_coef(p);
+    VerifyArgs a;
+    a.m = g.m; a.n = g.n; a.br = g.br; a.bc = g.bc; a.S = g.S; a.Gr = g.Gr; a.Gc = g.Gc; a.M = g.M; a.N = g.N;
+    a.ldc = p->ldc;
+    a.mode = tc.mode; a.cc = tc.cc; a.cr = tc.cr;
+    a.na = (const double *)(ws + L.na); a.na_abs = (const double *)(ws + L.na_abs);
+    a.nb = (const double *)(ws + L.nb); a.nb_abs = (const double *)(ws + L.nb_abs);
+    a.chain_a = (const double *)(ws + L.chain_a); a.chain_w = (const double *)(ws + L.chain_w);
+    a.qr = (const double *)(ws + L.qr); a.qc = (const double *)(ws + L.qc);
+    a.nv = (const double *)(ws + L.nv); a.nw = (const double *)(ws + L.nw);
+    a.scale_exp = p->dtype == ABFT_FP8_E4M3 ? (const int *)(ws + L.scale) : nullptr;
+    a.rep = (abft_report *)(ws + L.report);
+    a.er = er;
+    k_report_init<<<1, kThreads, 0, s>>>(a.rep);
+    auto blocks = [](int64_t work) { return (unsigned)std::min<int64_t>((work + kThreads - 1) / kThreads, 4096); };
+    // 16-byte loads when every row of C starts on a 16-byte boundary
+    constexpr int VV = 16 / (int)sizeof(T);
+    const bool vec = ((uintptr_t)C % 16 == 0) && (p->ldc % VV == 0);
+    const int64_t V = vec ? VV : 1;
+    // wide checksum blocks with few groups per row: one pass for both directions
+    if (sizeof(T) == 8 && vec && g.bc % VV == 0 && g.bc >= 64 && g.Gc <= kBlockPassMaxG &&
+        g.br * (g.bc / VV) >= 65536) {
+        const double *Cd = (const double *)C;
+        const ErasureRes ex = erasure_res(er, g.br, g.bc);
+        const unsigned grid = blocks(g.br * (g.bc / 2));
+        switch (g.Gc) {
+        case 1: launch_vblock<1>(Cd, a, ex, grid, s); break;
+        case 2: launch_vblock<2>(Cd, a, ex, grid, s); break;
+        case 3: launch_vblock<3>(Cd, a, ex, grid, s); break;
+        case 4: launch_vblock<4>(Cd, a, ex, grid, s); break;
+        case 5: launch_vblock<5>(Cd, a, ex, grid, s); break;
+        case 6: launch_vblock<6>(Cd, a, ex, grid, s); break;
+        case 7: launch_vblock<7>(Cd, a, ex, grid, s); break;
+        default: launch_vblock<8>(Cd, a, ex, grid, s); break;
+        }
+        ABFT_LAUNCHED();
+        return ABFT_OK;
+    }
+    // b = 1: tile partials in one pass, then the relations from them
+    if (g.br == 1 && g.bc == 1 && vec) {
+        double *pc = (double *)(ws + L.vpart_c), *pr = (double *)(ws + L.vpart_r);
+        const int64_t tiles_m = (g.m + kPartRows - 1) / kPartRows, tiles_n = (g.n + kWave * VV - 1) / (kWave * VV);
+        k_vpartials<T, VV><<<(unsigned)std::min<int64_t>(tiles_m * tiles_n, 8192), kThreads, 0, s>>>(C, p->ldc, g.m,
+                                                                                                   g.n, pc, pr);
+        k_vfused<T><<<blocks(g.n + g.m), kThreads, 0, s>>>(C, a, pc, pr, tiles_m, tiles_n);
+        k_vfused_edges<T><<<2, kThreads, 0, s>>>(C, a);
+        ABFT_LAUNCHED();
+        return ABFT_OK;
+    }
+    int64_t P = group_partitions(g.Gr, g.br, (g.N + V - 1) / V);
+    if (P == 1) {
+        if (vec) k_vcol_direct<T, VV><<<blocks(g.br * ((g.N + VV - 1) / VV)), kThreads, 0, s>>>(C, a);
+        else k_vcol_direct<T, 1><<<blocks(g.br * g.N), kThreads, 0, s>>>(C, a);
+    } else {
+        int64_t chunk = (g.Gr + P - 1) / P;
+        P = (g.Gr + chunk - 1) / chunk;
+        double *part = (double *)(ws + L.partial);
+        if (vec) k_vcol_partial<T, VV><<<blocks(P * g.br * ((g.N + VV - 1) / VV)), kThreads, 0, s>>>(C, a, P, chunk, part);
+        else k_vcol_partial<T, 1><<<blocks(P * g.br * g.N), kThreads, 0, s>>>(C, a, P, chunk, part);
+        k_vcol_finish<T><<<blocks(g.br * g.N), kThreads, 0, s>>>(C, a, P, part);
+    }
+    if (g.bc == 1 && vec)
+        k_vrow_block<T, VV><<<(unsigned)std::min<int64_t>(g.M, 8192), kThreads, 0, s>>>(C, a);
+    else if (g.bc < 64 && (kThreads % g.bc) == 0)
+        k_vrow_block<T, 1><<<(unsigned)std::min<int64_t>(g.M, 8192), kThreads, 0, s>>>(C, a);
+    else
+        k_vrow_strided<T><<<blocks(g.M * g.bc), kThreads, 0, s>>>(C, a);
+    ABFT_LAUNCHED();
+    return ABFT_OK;
 }
 
 template <typename T>
