@@ -27,7 +27,7 @@ int64_t group_partitions(int64_t G, int64_t b, int64_t cols) {
 
 bool rows_fused(const abft_problem *p) {
     const int64_t vpe = 16 / (int64_t)dtype_size(p->dtype);
-    return p->tau_mode == ABFT_TAU_DET && (p->k / vpe) % 64 == 0;
+    return (p->tau_mode == ABFT_TAU_DET || p->tau_mode == ABFT_TAU_STAT) && (p->k / vpe) % 64 == 0;
 }
 
 WsLayout ws_layout(const abft_problem *p) {

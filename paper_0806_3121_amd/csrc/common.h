@@ -189,7 +189,7 @@ struct WsLayout {
     size_t fused_c, fused_r;         // product-epilogue partial sums for b = 1 (double)
     size_t chain_a, chain_w;         // chained products (binary64): inherited threshold term chain_a[r] chain_w[j]
     size_t chain_cs;                 // chained products: the recomputed checksum rows (discarded; br x k double)
-    size_t rowpart;                  // fused row statistics (det): per-row partial sums of squares
+    size_t rowpart;                  // fused row statistics: per-row partial sums
     size_t vpart_c, vpart_r;         // one-pass re-read verification for b = 1: tile partial sums (double)
     size_t report;                   // abft_report
     size_t total;
@@ -197,8 +197,9 @@ struct WsLayout {
 };
 WsLayout ws_layout(const abft_problem *p);
 
-// Det thresholds with k / (16 / size) a multiple of 64: the encode pass also
-// produces every row statistic (rows_fused), from per-row partials in ws.
+// Det or statistical thresholds with k / (16 / size) a multiple of 64: the
+// encode pass also produces the row statistics (rows_fused), from per-row
+// partials in ws.
 bool rows_fused(const abft_problem *p);
 
 // Number of partitions used for the row-group sums of a (G groups, b residues, cols) sum.

@@ -86,11 +86,20 @@ template <typename TC> __device__ inline void finish_encode(double sv, double ss
     *grp = stat ? ssv + (double)c * (double)c : ssv;
 }
 
-// Row partials of the fused row statistics (det thresholds): with rp set, a
-// wave whose 64 lanes hold 64 consecutive vectors of one row also writes the
-// sum of squares of that 64-vector chunk, rp[row * rps + chunk]: data row
-// g*b + r, checksum row R + r, group-statistic row R + b + r.  The host sets
-// rp only when k / V is a multiple of 64, so every wave is whole and shares r.
+// Per-row statistics of the thresholds:
+//   ROW_L2:  ||x||_2              ROW_W: sum_l x_l^2 w_l          ROW_L4SQ: ||x||_4^2
+enum { ROW_L2 = 0, ROW_W = 1, ROW_L4SQ = 2 };
+__device__ inline double row_term(int mode, double x, double w) {
+    const double x2 = x * x;
+    return mode == ROW_W ? x2 * w : (mode == ROW_L4SQ ? x2 * x2 : x2);
+}
+
+// Row partials of the fused row statistics: with rp set, a wave whose 64 lanes
+// hold 64 consecutive vectors of one row also writes the sum of that 64-vector
+// chunk's terms, rp[row * rps + chunk]: data row g*b + r and checksum row R + r
+// (statistic rmode, weights rw for ROW_W), group-statistic row R + b + r
+// (ROW_L2).  The host sets rp only when k / V is a multiple of 64, so every
+// wave is whole and shares r.
 __device__ inline void row_partial(double *rp, int64_t rps, int64_t row, int64_t chunk, double q2) {
     q2 = wave_sum(q2);
     if (threadIdx.x % kWave == 0) rp[row * rps + chunk] = q2;
@@ -101,15 +110,18 @@ __device__ inline void row_partial(double *rp, int64_t rps, int64_t row, int64_t
 template <typename T, typename TC>
 __global__ __launch_bounds__(kThreads) void k_encode_direct(const T *X, int64_t ld, int64_t b, int64_t G, int64_t k,
                                                             TC *CS, int64_t ldcs, bool stat, double *grp, double *rp,
-                                                            int64_t rps) {
+                                                            int64_t rps, int rmode, const double *rw) {
     constexpr int V = vec16<T>::N;
     const int64_t kv = k / V, total = b * kv;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
         int64_t r = t / kv, l0 = (t - r * kv) * V;
         const int64_t chunk = l0 / (kWave * V);
-        double s[V], ss[V], v[V];
+        double s[V], ss[V], v[V], wv[V];
 #pragma unroll
-        for (int q = 0; q < V; ++q) s[q] = ss[q] = 0.0;
+        for (int q = 0; q < V; ++q) {
+            s[q] = ss[q] = 0.0;
+            wv[q] = (rp && rmode == ROW_W) ? rw[l0 + q] : 0.0;
+        }
         const T *p = X + r * ld + l0;
         for (int64_t g = 0; g < G; ++g) {
             vec16<T>::load(p + g * b * ld, v);
@@ -118,7 +130,7 @@ __global__ __launch_bounds__(kThreads) void k_encode_direct(const T *X, int64_t 
             for (int q = 0; q < V; ++q) {
                 s[q] += v[q];
                 ss[q] += stat ? v[q] * v[q] : fabs(v[q]);
-                q2 += v[q] * v[q];
+                q2 += row_term(rmode, v[q], wv[q]);
             }
             if (rp) row_partial(rp, rps, g * b + r, chunk, q2);
         }
@@ -127,7 +139,7 @@ __global__ __launch_bounds__(kThreads) void k_encode_direct(const T *X, int64_t 
         for (int q = 0; q < V; ++q) {
             finish_encode<TC>(s[q], ss[q], stat, CS + r * ldcs + l0 + q, grp + r * k + l0 + q);
             const double c = (double)(TC)s[q], gv = stat ? ss[q] + c * c : ss[q];
-            c2 += c * c;
+            c2 += row_term(rmode, c, wv[q]);
             g2 += gv * gv;
         }
         if (rp) {
@@ -140,7 +152,7 @@ __global__ __launch_bounds__(kThreads) void k_encode_direct(const T *X, int64_t 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_encode_partial(const T *X, int64_t ld, int64_t b, int64_t G, int64_t k,
                                                              int64_t P, int64_t chunk, bool stat, double *part,
-                                                             double *rp, int64_t rps) {
+                                                             double *rp, int64_t rps, int rmode, const double *rw) {
     constexpr int V = vec16<T>::N;
     const int64_t kv = k / V, rel = b * k, total = P * b * kv;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
@@ -148,9 +160,12 @@ __global__ __launch_bounds__(kThreads) void k_encode_partial(const T *X, int64_t
         int64_t r = q / kv, l0 = (q - r * kv) * V;
         int64_t g0 = p * chunk, g1 = min(G, g0 + chunk);
         const int64_t lc = l0 / (kWave * V);
-        double s[V], ss[V], v[V];
+        double s[V], ss[V], v[V], wv[V];
 #pragma unroll
-        for (int e = 0; e < V; ++e) s[e] = ss[e] = 0.0;
+        for (int e = 0; e < V; ++e) {
+            s[e] = ss[e] = 0.0;
+            wv[e] = (rp && rmode == ROW_W) ? rw[l0 + e] : 0.0;
+        }
         const T *src = X + r * ld + l0;
         for (int64_t g = g0; g < g1; ++g) {
             vec16<T>::load(src + g * b * ld, v);
@@ -159,7 +174,7 @@ __global__ __launch_bounds__(kThreads) void k_encode_partial(const T *X, int64_t
             for (int e = 0; e < V; ++e) {
                 s[e] += v[e];
                 ss[e] += stat ? v[e] * v[e] : fabs(v[e]);
-                q2 += v[e] * v[e];
+                q2 += row_term(rmode, v[e], wv[e]);
             }
             if (rp) row_partial(rp, rps, g * b + r, lc, q2);
         }
@@ -174,44 +189,54 @@ __global__ __launch_bounds__(kThreads) void k_encode_partial(const T *X, int64_t
 template <typename TC>
 __global__ __launch_bounds__(kThreads) void k_encode_finish(int64_t b, int64_t k, TC *CS, int64_t ldcs, bool stat,
                                                             int64_t P, const double *part, double *grp, double *rp,
-                                                            int64_t rps, int64_t R) {
+                                                            int64_t rps, int64_t R, int rmode, const double *rw) {
     const int64_t rel = b * k;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < rel; t += (int64_t)gridDim.x * kThreads) {
         int64_t r = t / k, l = t - r * k;
-        double sv = 0.0, ssv = 0.0;
-        for (int64_t p = 0; p < P; ++p) {
-            sv += part[(2 * p) * rel + t];
-            ssv += part[(2 * p + 1) * rel + t];
+        // four independent running sums (partitions p mod 4) keep eight loads in flight
+        double s4[4] = {0.0, 0.0, 0.0, 0.0}, ss4[4] = {0.0, 0.0, 0.0, 0.0};
+        int64_t p = 0;
+        for (; p + 3 < P; p += 4) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                s4[q] += part[(2 * (p + q)) * rel + t];
+                ss4[q] += part[(2 * (p + q) + 1) * rel + t];
+            }
         }
+        for (int q = 0; p < P; ++p, ++q) {
+            s4[q] += part[(2 * p) * rel + t];
+            ss4[q] += part[(2 * p + 1) * rel + t];
+        }
+        const double sv = (s4[0] + s4[1]) + (s4[2] + s4[3]), ssv = (ss4[0] + ss4[1]) + (ss4[2] + ss4[3]);
         finish_encode<TC>(sv, ssv, stat, CS + r * ldcs + l, grp + t);
         if (rp) {
             const double c = (double)(TC)sv, gv = stat ? ssv + c * c : ssv;
-            row_partial(rp, rps, R + r, l / kWave, c * c);
+            row_partial(rp, rps, R + r, l / kWave, row_term(rmode, c, rmode == ROW_W ? rw[l] : 0.0));
             row_partial(rp, rps, R + b + r, l / kWave, gv * gv);
         }
     }
 }
 
-// The fused row statistics from their partials: ||row||_2 of the R data rows
-// and b checksum rows (out[0 .. R + b)) and of the b group-statistic rows
-// (out_grp), each summing its chunks in order.
+// The fused row statistics from their partials, each row summing its chunks in
+// order: statistic rmode of the R data rows and b checksum rows (out[0 .. R + b);
+// the square root of the sum except for ROW_W) and ||row||_2 of the b
+// group-statistic rows (out_grp).
 __global__ __launch_bounds__(kThreads) void k_rows_finish(const double *rp, int64_t rps, int64_t R, int64_t b,
-                                                          int64_t n_data, int64_t n_tail, double *out,
+                                                          int64_t n_data, int64_t n_tail, int rmode, double *out,
                                                           double *out_grp) {
     const int64_t rows = R + 2 * b;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < rows; i += (int64_t)gridDim.x * kThreads) {
         const int64_t nc = i < R ? n_data : n_tail;
         double acc = 0.0;
         for (int64_t c = 0; c < nc; ++c) acc += rp[i * rps + c];
-        if (i < R + b) out[i] = sqrt(acc);
+        if (i < R + b) out[i] = rmode == ROW_W ? acc : sqrt(acc);
         else out_grp[i - R - b] = sqrt(acc);
     }
 }
 
 // Per-row statistic of X[i, 0:k), one wave per row (grid-stride over rows),
-// 16-byte loads, four in flight per lane:
-//   ROW_L2:  ||x||_2              ROW_W: sum_l x_l^2 w_l          ROW_L4SQ: ||x||_4^2
-enum { ROW_L2 = 0, ROW_W = 1, ROW_L4SQ = 2 };
+// 16-byte loads, four in flight per lane (the statistics are listed above the
+// encode kernels).
 constexpr int64_t kRowWMaxK = 16384;   // ROW_W keeps w (as binary32, 64 KB) in LDS up to this k
 constexpr int kRowThreads = 512;       // 8 waves share one copy of w
 template <typename T>
@@ -274,32 +299,35 @@ static void row_stats(const T *X, int64_t ld, int64_t rows, int64_t k, int mode,
 static unsigned grid_for(int64_t work) { return (unsigned)std::min<int64_t>((work + kThreads - 1) / kThreads, 65536); }
 static unsigned rows_grid(int64_t rows) { return (unsigned)std::min<int64_t>(std::max<int64_t>(rows, 1), 65536); }
 
-// Pass 1 over one operand: checksum rows CS (ldcs) and grp; with rp (det
-// thresholds, k / V a multiple of 64) also the row-statistic partials of the
-// data, checksum and group rows, finished into rows_out (R + b) and grp_out (b).
+// Pass 1 over one operand: checksum rows CS (ldcs) and grp; with rp (k / V a
+// multiple of 64) also the row-statistic partials of the data and checksum rows
+// (statistic rmode, weights rw) and of the group rows, finished into rows_out
+// (R + b) and grp_out (b).
 template <typename T, typename TC>
 static void encode_pass1(const T *X, int64_t ld, int64_t R, int64_t b, int64_t k, TC *CS, int64_t ldcs, bool stat,
-                         double *grp, double *part, hipStream_t s, double *rp = nullptr, double *rows_out = nullptr,
-                         double *grp_out = nullptr) {
+                         double *grp, double *part, hipStream_t s, double *rp = nullptr, int rmode = ROW_L2,
+                         const double *rw = nullptr, double *rows_out = nullptr, double *grp_out = nullptr) {
     constexpr int V = vec16<T>::N;
     int64_t G = R / b;
     int64_t P = group_partitions(G, b, k / V);
     const int64_t rps = k / kWave;                 // partial slots per row (chunks of 64 columns at most)
     int64_t n_tail;
     if (P == 1) {
-        k_encode_direct<T, TC><<<grid_for(b * k / V), kThreads, 0, s>>>(X, ld, b, G, k, CS, ldcs, stat, grp, rp, rps);
+        k_encode_direct<T, TC><<<grid_for(b * k / V), kThreads, 0, s>>>(X, ld, b, G, k, CS, ldcs, stat, grp, rp, rps,
+                                                                        rmode, rw);
         n_tail = k / (kWave * V);
     } else {
         int64_t chunk = (G + P - 1) / P;
         P = (G + chunk - 1) / chunk;
         k_encode_partial<T><<<grid_for(P * b * k / V), kThreads, 0, s>>>(X, ld, b, G, k, P, chunk, stat, part, rp,
-                                                                          rps);
-        k_encode_finish<TC><<<grid_for(b * k), kThreads, 0, s>>>(b, k, CS, ldcs, stat, P, part, grp, rp, rps, R);
+                                                                          rps, rmode, rw);
+        k_encode_finish<TC><<<grid_for(b * k), kThreads, 0, s>>>(b, k, CS, ldcs, stat, P, part, grp, rp, rps, R,
+                                                                 rmode, rw);
         n_tail = k / kWave;
     }
     if (rp)
-        k_rows_finish<<<grid_for(R + 2 * b), kThreads, 0, s>>>(rp, rps, R, b, k / (kWave * V), n_tail, rows_out,
-                                                               grp_out);
+        k_rows_finish<<<grid_for(R + 2 * b), kThreads, 0, s>>>(rp, rps, R, b, k / (kWave * V), n_tail, rmode,
+                                                               rows_out, grp_out);
 }
 
 // Pass 2 over one operand: a statistic per row of the data rows and of the
@@ -321,28 +349,30 @@ static int encode_typed(const abft_problem *p, T *A, T *Bt, TC *Acs, int64_t lda
     double *part = (double *)(ws + L.partial);
     double *grpA = (double *)(ws + L.grpA), *grpB = (double *)(ws + L.grpB);
     const bool stat = p->tau_mode == ABFT_TAU_STAT;
-    if (rows_fused(p)) {
-        // det thresholds: every row statistic from the encode pass (no second read of A and B)
-        double *rp = (double *)(ws + L.rowpart);
-        encode_pass1<T, TC>(A, p->lda, g.m, g.br, g.k, Acs, ldacs, false, grpA, part, s, rp,
-                            (double *)(ws + L.na), (double *)(ws + L.na_abs));
-        encode_pass1<T, TC>(Bt, p->ldb, g.n, g.bc, g.k, Bcs, ldbcs, false, grpB, part, s, rp,
-                            (double *)(ws + L.nb), (double *)(ws + L.nb_abs));
-        k_fill_zero<<<1, kThreads, 0, s>>>((double *)(ws + L.chain_a), g.br);
-        k_fill_zero<<<1, kThreads, 0, s>>>((double *)(ws + L.chain_w), g.N);
-        ABFT_LAUNCHED();
-        return ABFT_OK;
-    }
-    encode_pass1<T, TC>(A, p->lda, g.m, g.br, g.k, Acs, ldacs, stat, grpA, part, s);
-    encode_pass1<T, TC>(Bt, p->ldb, g.n, g.bc, g.k, Bcs, ldbcs, stat, grpB, part, s);
     // row statistics (det: na, nb; stat: qr, qc) and the norms of the grp rows
     // (det: na_abs, nb_abs; stat: nv, nw)
     double *ra = (double *)(ws + (stat ? L.qr : L.na)), *rb = (double *)(ws + (stat ? L.qc : L.nb));
-    encode_pass2<T, TC>(A, p->lda, g.m, Acs, ldacs, g.br, g.k, stat, g.bc, grpB, ra, s);
-    encode_pass2<T, TC>(Bt, p->ldb, g.n, Bcs, ldbcs, g.bc, g.k, stat, g.br, grpA, rb, s);
     double *ga = (double *)(ws + (stat ? L.nv : L.na_abs)), *gb = (double *)(ws + (stat ? L.nw : L.nb_abs));
-    row_stats<double>(grpA, g.k, g.br, g.k, ROW_L2, nullptr, ga, s);
-    row_stats<double>(grpB, g.k, g.bc, g.k, ROW_L2, nullptr, gb, s);
+    // det: ||row||_2; stat with the other side thin: sum_l row_l^2 w_l (w = the other side's grp); stat
+    // otherwise: ||row||_4^2
+    const int modeA = !stat ? ROW_L2 : (g.bc == 1 ? ROW_W : ROW_L4SQ);
+    const int modeB = !stat ? ROW_L2 : (g.br == 1 ? ROW_W : ROW_L4SQ);
+    // With rows_fused the encode pass produces the row statistics too (no second read of the operand),
+    // except A's sum_l A_il^2 w_l, whose weights (B's grp) exist only after B's encode.
+    double *rp = rows_fused(p) ? (double *)(ws + L.rowpart) : nullptr;
+    const bool fuseA = rp && modeA != ROW_W, fuseB = rp != nullptr;
+    encode_pass1<T, TC>(A, p->lda, g.m, g.br, g.k, Acs, ldacs, stat, grpA, part, s, fuseA ? rp : nullptr, modeA,
+                        nullptr, ra, ga);
+    encode_pass1<T, TC>(Bt, p->ldb, g.n, g.bc, g.k, Bcs, ldbcs, stat, grpB, part, s, fuseB ? rp : nullptr, modeB,
+                        grpA, rb, gb);
+    if (!fuseA) {
+        encode_pass2<T, TC>(A, p->lda, g.m, Acs, ldacs, g.br, g.k, stat, g.bc, grpB, ra, s);
+        row_stats<double>(grpA, g.k, g.br, g.k, ROW_L2, nullptr, ga, s);
+    }
+    if (!fuseB) {
+        encode_pass2<T, TC>(Bt, p->ldb, g.n, Bcs, ldbcs, g.bc, g.k, stat, g.br, grpA, rb, s);
+        row_stats<double>(grpB, g.k, g.bc, g.k, ROW_L2, nullptr, gb, s);
+    }
     // an operand encoded here carries no inherited residual
     k_fill_zero<<<1, kThreads, 0, s>>>((double *)(ws + L.chain_a), g.br);
     k_fill_zero<<<1, kThreads, 0, s>>>((double *)(ws + L.chain_w), g.N);
@@ -898,7 +928,8 @@ __global__ __launch_bounds__(kThreads) void k_vpartials(const T *C, int64_t ldc,
 
 // Fused verification (b = 1): the column relations of the data columns and
 // the row relations of the data rows from the product epilogue's partial
-// sums (pc: tiles_m x n, pr: tiles_n x m, summed over the tiles in order);
+// sums (pc: tiles_m x n, pr: tiles_n x m, summed over the tiles in a fixed
+// order: four running sums over tiles q mod 4, then pairwise);
 // the carried column and the carried row are summed from C_f directly.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_vfused(const T *C, VerifyArgs a, const double *pc, const double *pr,
@@ -907,14 +938,22 @@ __global__ __launch_bounds__(kThreads) void k_vfused(const T *C, VerifyArgs a, c
     unsigned long long ec = 0, er = 0;
     const int64_t total = a.n + a.m;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
-        double sum = 0.0;
+        // four independent running sums (tiles q mod 4) keep four loads in flight
+        auto sum4 = [](const double *x, int64_t stride, int64_t cnt) {
+            double s4[4] = {0.0, 0.0, 0.0, 0.0};
+            int64_t q = 0;
+            for (; q + 3 < cnt; q += 4) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) s4[e] += x[(q + e) * stride];
+            }
+            for (int e = 0; q < cnt; ++q, ++e) s4[e] += x[q * stride];
+            return (s4[0] + s4[1]) + (s4[2] + s4[3]);
+        };
         if (t < a.n) {
-            for (int64_t q = 0; q < tiles_m; ++q) sum += pc[q * a.n + t];
-            finish_col<T>(a, C, 0, t, sum, rc, ec);
+            finish_col<T>(a, C, 0, t, sum4(pc + t, a.n, tiles_m), rc, ec);
         } else {
             const int64_t i = t - a.n;
-            for (int64_t q = 0; q < tiles_n; ++q) sum += pr[q * a.m + i];
-            finish_row<T>(a, C, i, 0, sum, rr, er);
+            finish_row<T>(a, C, i, 0, sum4(pr + i, a.m, tiles_n), rr, er);
         }
     }
     fold_block(rc, ec, &a.rep->max_ratio_c, &a.rep->n_excl_c);
