@@ -41,6 +41,17 @@ __host__ __device__ inline float e4m3_to_f32(uint8_t c) {
     return (c & 0x80u) ? -v : v;
 }
 
+// The same decoding straight to binary64 (device hot loops): exponent and
+// fraction of a normal code placed at the top of a binary64 exponent and
+// fraction field, then rebiased by the exact factor 2^(1023 - 7); codes with a
+// zero exponent field are f 2^-9.  Equal to (double)e4m3_to_f32(c) for every c.
+__device__ inline double e4m3_to_f64(uint32_t c) {
+    const uint32_t a = c & 0x7Fu;
+    const double n = __longlong_as_double((long long)a << 49) * 0x1p1016;
+    const double v = (a >> 3) ? n : (double)(a & 7u) * 0x1p-9;
+    return (c & 0x80u) ? -v : v;
+}
+
 // binary32 -> E4M3, round to nearest, ties to even fraction; |x| >= 464 (the
 // midpoint above 448 and beyond) saturates to +-448; NaN -> 0x7F.
 __host__ __device__ inline uint8_t f32_to_e4m3_rne(float x) {
@@ -74,7 +85,7 @@ template <> struct elem<uint16_t> {   // bfloat16 storage
     __device__ static double load(const uint16_t *p) { return (double)bf16_to_f32(*p); }
 };
 template <> struct elem<uint8_t> {    // FP8 E4M3 storage (values in the scaled domain)
-    __device__ static double load(const uint8_t *p) { return (double)e4m3_to_f32(*p); }
+    __device__ static double load(const uint8_t *p) { return e4m3_to_f64(*p); }
 };
 
 // One 16-byte load of N elements, widened to binary64 (16-byte aligned address).
@@ -114,7 +125,7 @@ template <> struct vec16<uint8_t> {                  // FP8 E4M3
     __device__ static void load(const uint8_t *p, double *o) {
         v4u32 v = *(const v4u32 *)p;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) o[q] = (double)e4m3_to_f32((uint8_t)(v[q / 4] >> (8 * (q % 4))));
+        for (int q = 0; q < 16; ++q) o[q] = e4m3_to_f64((v[q / 4] >> (8 * (q % 4))) & 0xFFu);
     }
 };
 

@@ -495,14 +495,17 @@ __global__ __launch_bounds__(kThreads) void k_quantize_bf16(const float *X, int6
 // ws scale words: [0] = e_A, [1] = e_B, [2] = amax_A bits, [3] = amax_B bits.
 __global__ void k_amax_init(int *scale, int which) { scale[2 + which] = 0; }
 
+// 16-byte loads: rows of X are 16-byte aligned and k is a multiple of 4 (as for the quantizer).
 __global__ __launch_bounds__(kThreads) void k_amax(const float *X, int64_t ldx, int64_t rows, int64_t k, int *scale,
                                                    int which) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
     __shared__ float sh[kThreads / kWave];
     float mx = 0.0f;
-    const int64_t total = rows * k;
+    const int64_t kv = k / 4, total = rows * kv;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
-        int64_t i = t / k, l = t - i * k;
-        mx = fmaxf(mx, fabsf(X[i * ldx + l]));
+        int64_t i = t / kv, l = (t - i * kv) * 4;
+        const v4 x = *(const v4 *)(X + i * ldx + l);
+        mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x[0]), fabsf(x[1])), fmaxf(fabsf(x[2]), fabsf(x[3]))));
     }
     for (int off = kWave / 2; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, kWave));
     if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = mx;
@@ -549,7 +552,7 @@ int launch_quantize(const abft_problem *p, int which, const float *X, int64_t ld
         WsLayout L = ws_layout(p);
         int *scale = (int *)(ws + L.scale);
         k_amax_init<<<1, 1, 0, s>>>(scale, which);
-        k_amax<<<(unsigned)std::min<int64_t>((rows * p->k + kThreads - 1) / kThreads, 4096), kThreads, 0, s>>>(
+        k_amax<<<(unsigned)std::min<int64_t>((rows * p->k / 4 + kThreads - 1) / kThreads, 4096), kThreads, 0, s>>>(
             X, ldx, rows, p->k, scale, which);
         k_scale_exp<<<1, 1, 0, s>>>(scale, which);
         k_quantize_fp8<<<grid_for(rows * p->k / 4), kThreads, 0, s>>>(X, ldx, rows, p->k, (uint8_t *)dst, ldq, scale,
