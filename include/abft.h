@@ -268,7 +268,8 @@ int abft_verify(const abft_problem *p, const void *C_f, const abft_rect *known, 
  * computation (see abft_arm_accumulator_flip) reaches both C and the partials
  * and is seen here, while a change of C_f in memory after the product is seen
  * only by abft_verify.  Same report, thresholds and flags as abft_verify (no
- * known erasures).  ABFT_E_ARG if no fused product was recorded for ws.
+ * known erasures).  ABFT_E_ARG if no fused product of this same problem (dtype,
+ * sizes, ldc) was the last product recorded for ws.
  */
 int abft_verify_fused(const abft_problem *p, const void *C_f, void *ws, abft_report *host_out, void *stream);
 

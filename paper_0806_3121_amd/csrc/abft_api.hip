@@ -332,7 +332,7 @@ int abft_verify_fused(const abft_problem *p, const void *C_f, void *ws, abft_rep
     if (!ws) return ABFT_E_WORKSPACE;
     if (p->br != 1 || p->bc != 1) return ABFT_E_UNSUPPORTED;
     int64_t tm = 0, tn = 0;
-    if (!fused_grid(ws, &tm, &tn)) return ABFT_E_ARG;
+    if (!fused_grid(ws, p, &tm, &tn)) return ABFT_E_ARG;
     if ((st = launch_verify_fused(p, C_f, (char *)ws, tm, tn, (hipStream_t)stream))) return st;
     if (host_out) {
         WsLayout L = ws_layout(p);

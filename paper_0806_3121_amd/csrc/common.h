@@ -250,7 +250,7 @@ int launch_verify_fused(const abft_problem *p, const void *C_f, char *ws, int64_
                         hipStream_t s);
 // Fused partial sums of the last ABFT_FUSED product into ws (tile grid), and
 // the one-shot accumulator flip armed for the next product into ws.
-bool fused_grid(const void *ws, int64_t *tiles_m, int64_t *tiles_n);
+bool fused_grid(const void *ws, const abft_problem *p, int64_t *tiles_m, int64_t *tiles_n);
 void arm_accumulator_flip(const void *ws, int64_t i, int64_t j, int bit);
 // Smallest tile edge of every product kernel: bounds the tile rows / columns of the fused partials.
 constexpr int64_t kMinTileEdge = 96;

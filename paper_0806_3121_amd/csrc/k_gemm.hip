@@ -268,6 +268,7 @@ struct EpiState {
     int fbit = -1;
     bool fused = false;
     int64_t tiles_m = 0, tiles_n = 0;
+    abft_problem prob{};             // the problem whose fused product wrote the partials
 };
 std::mutex g_epi_mu;
 std::unordered_map<const void *, EpiState> g_epi;
@@ -279,10 +280,16 @@ void arm_accumulator_flip(const void *ws, int64_t i, int64_t j, int bit) {
     st.fi = i; st.fj = j; st.fbit = bit;
 }
 
-bool fused_grid(const void *ws, int64_t *tiles_m, int64_t *tiles_n) {
+bool fused_grid(const void *ws, const abft_problem *p, int64_t *tiles_m, int64_t *tiles_n) {
     std::lock_guard<std::mutex> lk(g_epi_mu);
     auto it = g_epi.find(ws);
     if (it == g_epi.end() || !it->second.fused) return false;
+    // the partials belong to the last fused product on this workspace: the same problem only (a workspace
+    // reused for another problem, or freed and reallocated, must not be read with the old tile grid)
+    const abft_problem &q = it->second.prob;
+    if (q.dtype != p->dtype || q.m != p->m || q.n != p->n || q.k != p->k || q.br != p->br || q.bc != p->bc ||
+        q.ldc != p->ldc)
+        return false;
     *tiles_m = it->second.tiles_m;
     *tiles_n = it->second.tiles_n;
     return true;
@@ -349,6 +356,7 @@ int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C
         es.fused = true;
         es.tiles_m = e.tiles_m;
         es.tiles_n = e.tiles_n;
+        es.prob = *p;
     }
     return st;
 }

@@ -142,6 +142,13 @@ def test_fused_state_and_refusals(dev):
     with pytest.raises(abft.AbftError) as e:
         abft.arm_accumulator_flip(P.p, P.ws, 256, 0, 3)    # carried row: not an accumulator of the data kernel
     assert e.value.status == abft.ABFT_E_ARG
+    # partials of another problem on the same workspace are refused
+    fused_gemm(P)
+    other = abft.problem(abft.ABFT_F64, 128, 256, 128, 1, 1, ldc=P.ldc)
+    with pytest.raises(abft.AbftError) as e:
+        abft.verify_fused(other, P.C, P.ws)
+    assert e.value.status == abft.ABFT_E_ARG
+    P.verify_fused()
     Q = abft.Protected(abft.ABFT_F64, 256, 256, 128, 64, 64, device=dev)
     with pytest.raises(abft.AbftError) as e:
         abft.gemm(Q.p, Q.A, Q.Bt, Q.C, Q.ws, flags=abft.ABFT_FUSED)
