@@ -125,6 +125,7 @@ def lib():
             "abft_gemm": (C.c_int, [_P(abft_problem), _V, _V, _V, _V, C.c_uint32, _V]),
             "abft_gemm_panel": (C.c_int, [_P(abft_problem), _V, _V, _V, C.c_int64, C.c_int64, C.c_uint32, _V]),
             "abft_describe_gemm": (C.c_int, [_P(abft_problem), C.c_uint32, C.c_char_p, C.c_size_t]),
+            "abft_quantize_encode": (C.c_int, [_P(abft_problem), _V, C.c_int64, _V, C.c_int64, _V, _V, _V, _V]),
             "abft_quantize": (C.c_int, [_P(abft_problem), C.c_int, _V, C.c_int64, _V, _V, _V]),
             "abft_verify": (C.c_int, [_P(abft_problem), _V, _P(abft_rect), C.c_int, _V, _V, _V]),
             "abft_verify_fused": (C.c_int, [_P(abft_problem), _V, _V, _V, _V]),
@@ -240,6 +241,13 @@ def quantize(p, which, X, dst, ws, stream=None):
     """X: float32 device tensor (A: m x k, or B^T: n x k); dst: the A_f / Bt tensor."""
     return _check("abft_quantize", lib().abft_quantize(C.byref(p), which, _ptr(X), X.stride(0), _ptr(dst), _ptr(ws),
                                                        _stream(stream)))
+
+
+def quantize_encode(p, A32, B32, A_f, B_f, ws, stream=None):
+    """Quantize A32 (m x k) and B32 (B^T, n x k) binary32 tensors into A_f, B_f and encode, in one pass."""
+    return _check("abft_quantize_encode",
+                  lib().abft_quantize_encode(C.byref(p), _ptr(A32), A32.stride(0), _ptr(B32), B32.stride(0),
+                                             _ptr(A_f), _ptr(B_f), _ptr(ws), _stream(stream)))
 
 
 def _rects(known):

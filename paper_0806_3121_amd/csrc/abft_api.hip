@@ -287,6 +287,20 @@ int abft_quantize(const abft_problem *p, int which, const float *X, int64_t ldx,
     return launch_quantize(p, which, X, ldx, dst, (char *)ws, (hipStream_t)stream);
 }
 
+int abft_quantize_encode(const abft_problem *p, const float *A32, int64_t lda32, const float *B32, int64_t ldb32,
+                         void *A_f, void *B_f, void *ws, void *stream) {
+    int st = check_problem(p);
+    if (st) return st;
+    if (!cs_in_ws(p->dtype)) return ABFT_E_UNSUPPORTED;
+    if (!A32 || !B32 || ((uintptr_t)A32 & 15u) || ((uintptr_t)B32 & 15u)) return ABFT_E_ARG;
+    if (lda32 < p->k || ldb32 < p->k || lda32 % 4 || ldb32 % 4) return ABFT_E_ARG;
+    if ((st = check_operands(p, A_f, B_f))) return st;
+    const size_t es = dtype_size(p->dtype);
+    if ((p->k * es) % 16) return ABFT_E_ARG;
+    if (!ws) return ABFT_E_WORKSPACE;
+    return launch_quantize_encode(p, A32, lda32, B32, ldb32, A_f, B_f, (char *)ws, (hipStream_t)stream);
+}
+
 int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, void *ws, uint32_t flags,
               void *stream) {
     int st = check_problem(p);

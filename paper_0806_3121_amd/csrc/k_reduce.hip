@@ -105,11 +105,70 @@ __device__ inline void row_partial(double *rp, int64_t rps, int64_t row, int64_t
     if (threadIdx.x % kWave == 0) rp[row * rps + chunk] = q2;
 }
 
+// Where the encode pass takes an operand's values from: the stored operand,
+// or binary32 values quantized on the way (bfloat16 round to nearest even, or
+// E4M3 at the operand's per-tensor scale), which are written to the operand's
+// storage and used as stored.  load(row, l0, v) fills the V values
+// X[row, l0 .. l0+V) as binary64.
+template <typename T> struct SrcStored {
+    const T *X;
+    int64_t ld;
+    __device__ void load(int64_t row, int64_t l0, double *v) const { vec16<T>::load(X + row * ld + l0, v); }
+};
+struct SrcQuantBf16 {
+    const float *X;
+    int64_t ldx;
+    uint16_t *Q;
+    int64_t ldq;
+    __device__ void load(int64_t row, int64_t l0, double *v) const {
+        typedef float v4 __attribute__((ext_vector_type(4)));
+        const v4 x0 = *(const v4 *)(X + row * ldx + l0), x1 = *(const v4 *)(X + row * ldx + l0 + 4);
+        uint16_t h[8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            h[q] = f32_to_bf16_rne(x0[q]);
+            h[4 + q] = f32_to_bf16_rne(x1[q]);
+        }
+        v4u32 o;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[q] = (uint32_t)h[2 * q] | ((uint32_t)h[2 * q + 1] << 16);
+        *(v4u32 *)(Q + row * ldq + l0) = o;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = (double)bf16_to_f32(h[q]);
+    }
+};
+struct SrcQuantFp8 {
+    const float *X;
+    int64_t ldx;
+    uint8_t *Q;
+    int64_t ldq;
+    const int *scale;      // ws scale words: the operand's exponent e (x 2^e before rounding)
+    int which;
+    __device__ void load(int64_t row, int64_t l0, double *v) const {
+        typedef float v4 __attribute__((ext_vector_type(4)));
+        const float f = __builtin_ldexpf(1.0f, scale[which]);
+        v4u32 o;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const v4 x = *(const v4 *)(X + row * ldx + l0 + 4 * w);
+            uint32_t word = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t c = f32_to_e4m3_rne(x[q] * f);
+                word |= c << (8 * q);
+                v[4 * w + q] = e4m3_to_f64(c);
+            }
+            o[w] = word;
+        }
+        *(v4u32 *)(Q + row * ldq + l0) = o;
+    }
+};
+
 // Each thread owns V = 16/sizeof(T) consecutive columns l (one 16-byte load per
 // row); rows of X are 16-byte aligned and k is a multiple of V.
-template <typename T, typename TC>
-__global__ __launch_bounds__(kThreads) void k_encode_direct(const T *X, int64_t ld, int64_t b, int64_t G, int64_t k,
-                                                            TC *CS, int64_t ldcs, bool stat, double *grp, double *rp,
+template <typename T, typename TC, class Src>
+__global__ __launch_bounds__(kThreads) void k_encode_direct(Src src, int64_t b, int64_t G, int64_t k, TC *CS,
+                                                            int64_t ldcs, bool stat, double *grp, double *rp,
                                                             int64_t rps, int rmode, const double *rw) {
     constexpr int V = vec16<T>::N;
     const int64_t kv = k / V, total = b * kv;
@@ -122,9 +181,8 @@ __global__ __launch_bounds__(kThreads) void k_encode_direct(const T *X, int64_t 
             s[q] = ss[q] = 0.0;
             wv[q] = (rp && rmode == ROW_W) ? rw[l0 + q] : 0.0;
         }
-        const T *p = X + r * ld + l0;
         for (int64_t g = 0; g < G; ++g) {
-            vec16<T>::load(p + g * b * ld, v);
+            src.load(g * b + r, l0, v);
             double q2 = 0.0;
 #pragma unroll
             for (int q = 0; q < V; ++q) {
@@ -149,10 +207,10 @@ __global__ __launch_bounds__(kThreads) void k_encode_direct(const T *X, int64_t 
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_encode_partial(const T *X, int64_t ld, int64_t b, int64_t G, int64_t k,
-                                                             int64_t P, int64_t chunk, bool stat, double *part,
-                                                             double *rp, int64_t rps, int rmode, const double *rw) {
+template <typename T, class Src>
+__global__ __launch_bounds__(kThreads) void k_encode_partial(Src src, int64_t b, int64_t G, int64_t k, int64_t P,
+                                                             int64_t chunk, bool stat, double *part, double *rp,
+                                                             int64_t rps, int rmode, const double *rw) {
     constexpr int V = vec16<T>::N;
     const int64_t kv = k / V, rel = b * k, total = P * b * kv;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
@@ -166,9 +224,8 @@ __global__ __launch_bounds__(kThreads) void k_encode_partial(const T *X, int64_t
             s[e] = ss[e] = 0.0;
             wv[e] = (rp && rmode == ROW_W) ? rw[l0 + e] : 0.0;
         }
-        const T *src = X + r * ld + l0;
         for (int64_t g = g0; g < g1; ++g) {
-            vec16<T>::load(src + g * b * ld, v);
+            src.load(g * b + r, l0, v);
             double q2 = 0.0;
 #pragma unroll
             for (int e = 0; e < V; ++e) {
@@ -303,9 +360,9 @@ static unsigned rows_grid(int64_t rows) { return (unsigned)std::min<int64_t>(std
 // multiple of 64) also the row-statistic partials of the data and checksum rows
 // (statistic rmode, weights rw) and of the group rows, finished into rows_out
 // (R + b) and grp_out (b).
-template <typename T, typename TC>
-static void encode_pass1(const T *X, int64_t ld, int64_t R, int64_t b, int64_t k, TC *CS, int64_t ldcs, bool stat,
-                         double *grp, double *part, hipStream_t s, double *rp = nullptr, int rmode = ROW_L2,
+template <typename T, typename TC, class Src>
+static void encode_pass1(Src src, int64_t R, int64_t b, int64_t k, TC *CS, int64_t ldcs, bool stat, double *grp,
+                         double *part, hipStream_t s, double *rp = nullptr, int rmode = ROW_L2,
                          const double *rw = nullptr, double *rows_out = nullptr, double *grp_out = nullptr) {
     constexpr int V = vec16<T>::N;
     int64_t G = R / b;
@@ -313,14 +370,14 @@ static void encode_pass1(const T *X, int64_t ld, int64_t R, int64_t b, int64_t k
     const int64_t rps = k / kWave;                 // partial slots per row (chunks of 64 columns at most)
     int64_t n_tail;
     if (P == 1) {
-        k_encode_direct<T, TC><<<grid_for(b * k / V), kThreads, 0, s>>>(X, ld, b, G, k, CS, ldcs, stat, grp, rp, rps,
-                                                                        rmode, rw);
+        k_encode_direct<T, TC, Src><<<grid_for(b * k / V), kThreads, 0, s>>>(src, b, G, k, CS, ldcs, stat, grp, rp,
+                                                                             rps, rmode, rw);
         n_tail = k / (kWave * V);
     } else {
         int64_t chunk = (G + P - 1) / P;
         P = (G + chunk - 1) / chunk;
-        k_encode_partial<T><<<grid_for(P * b * k / V), kThreads, 0, s>>>(X, ld, b, G, k, P, chunk, stat, part, rp,
-                                                                          rps, rmode, rw);
+        k_encode_partial<T, Src><<<grid_for(P * b * k / V), kThreads, 0, s>>>(src, b, G, k, P, chunk, stat, part,
+                                                                               rp, rps, rmode, rw);
         k_encode_finish<TC><<<grid_for(b * k), kThreads, 0, s>>>(b, k, CS, ldcs, stat, P, part, grp, rp, rps, R,
                                                                  rmode, rw);
         n_tail = k / kWave;
@@ -341,9 +398,9 @@ static void encode_pass2(const T *X, int64_t ld, int64_t R, const TC *CS, int64_
     row_stats<TC>(CS, ldcs, b, k, mode, w_other, out + R, s);
 }
 
-template <typename T, typename TC>
-static int encode_typed(const abft_problem *p, T *A, T *Bt, TC *Acs, int64_t ldacs, TC *Bcs, int64_t ldbcs, char *ws,
-                        hipStream_t s) {
+template <typename T, typename TC, class SrcA, class SrcB>
+static int encode_typed(const abft_problem *p, SrcA srcA, SrcB srcB, T *A, T *Bt, TC *Acs, int64_t ldacs, TC *Bcs,
+                        int64_t ldbcs, char *ws, hipStream_t s) {
     Geom g = geom_of(p);
     WsLayout L = ws_layout(p);
     double *part = (double *)(ws + L.partial);
@@ -361,10 +418,10 @@ static int encode_typed(const abft_problem *p, T *A, T *Bt, TC *Acs, int64_t lda
     // except A's sum_l A_il^2 w_l, whose weights (B's grp) exist only after B's encode.
     double *rp = rows_fused(p) ? (double *)(ws + L.rowpart) : nullptr;
     const bool fuseA = rp && modeA != ROW_W, fuseB = rp != nullptr;
-    encode_pass1<T, TC>(A, p->lda, g.m, g.br, g.k, Acs, ldacs, stat, grpA, part, s, fuseA ? rp : nullptr, modeA,
-                        nullptr, ra, ga);
-    encode_pass1<T, TC>(Bt, p->ldb, g.n, g.bc, g.k, Bcs, ldbcs, stat, grpB, part, s, fuseB ? rp : nullptr, modeB,
-                        grpA, rb, gb);
+    encode_pass1<T, TC>(srcA, g.m, g.br, g.k, Acs, ldacs, stat, grpA, part, s, fuseA ? rp : nullptr, modeA, nullptr,
+                        ra, ga);
+    encode_pass1<T, TC>(srcB, g.n, g.bc, g.k, Bcs, ldbcs, stat, grpB, part, s, fuseB ? rp : nullptr, modeB, grpA, rb,
+                        gb);
     if (!fuseA) {
         encode_pass2<T, TC>(A, p->lda, g.m, Acs, ldacs, g.br, g.k, stat, g.bc, grpB, ra, s);
         row_stats<double>(grpA, g.k, g.br, g.k, ROW_L2, nullptr, ga, s);
@@ -424,11 +481,12 @@ int launch_encode_chained(const abft_problem *p, const void *A_f, void *B_f, cha
     double *grpA = (double *)(ws + L.grpA), *grpB = (double *)(ws + L.grpB);
     double *cs = (double *)(ws + L.chain_cs);
     // the A side: group statistic (checksum rows into scratch), row norms of the rows that enter the product
-    encode_pass1<double, double>(const_cast<double *>(A), p->lda, g.m, g.br, g.k, cs, g.k, false, grpA, part, s);
+    encode_pass1<double, double>(SrcStored<double>{A, p->lda}, g.m, g.br, g.k, cs, g.k, false, grpA, part, s);
     encode_pass2<double, double>(A, p->lda, g.m, A + g.m * p->lda, p->lda, g.br, g.k, false, g.bc, grpB,
                                  (double *)(ws + L.na), s);
     // the B side as in a plain encode
-    encode_pass1<double, double>(Bt, p->ldb, g.n, g.bc, g.k, Bt + g.n * p->ldb, p->ldb, false, grpB, part, s);
+    encode_pass1<double, double>(SrcStored<double>{Bt, p->ldb}, g.n, g.bc, g.k, Bt + g.n * p->ldb, p->ldb, false, grpB,
+                                 part, s);
     encode_pass2<double, double>(Bt, p->ldb, g.n, Bt + g.n * p->ldb, p->ldb, g.bc, g.k, false, g.br, grpA,
                                  (double *)(ws + L.nb), s);
     row_stats<double>(grpA, g.k, g.br, g.k, ROW_L2, nullptr, (double *)(ws + L.na_abs), s);
@@ -446,23 +504,27 @@ int launch_encode(const abft_problem *p, void *A_f, void *B_f, char *ws, hipStre
     switch (p->dtype) {
     case ABFT_F64: {
         double *A = (double *)A_f, *Bt = (double *)B_f;
-        return encode_typed<double, double>(p, A, Bt, A + g.m * p->lda, p->lda, Bt + g.n * p->ldb, p->ldb, ws, s);
+        return encode_typed<double, double>(p, SrcStored<double>{A, p->lda}, SrcStored<double>{Bt, p->ldb}, A, Bt,
+                                            A + g.m * p->lda, p->lda, Bt + g.n * p->ldb, p->ldb, ws, s);
     }
     case ABFT_F32: {
         float *A = (float *)A_f, *Bt = (float *)B_f;
-        return encode_typed<float, float>(p, A, Bt, A + g.m * p->lda, p->lda, Bt + g.n * p->ldb, p->ldb, ws, s);
+        return encode_typed<float, float>(p, SrcStored<float>{A, p->lda}, SrcStored<float>{Bt, p->ldb}, A, Bt,
+                                          A + g.m * p->lda, p->lda, Bt + g.n * p->ldb, p->ldb, ws, s);
     }
     case ABFT_BF16: {
         // bfloat16 data, binary32 checksum rows in the workspace
         WsLayout L = ws_layout(p);
-        return encode_typed<uint16_t, float>(p, (uint16_t *)A_f, (uint16_t *)B_f, (float *)(ws + L.acs), g.k,
-                                             (float *)(ws + L.bcs), g.k, ws, s);
+        uint16_t *A = (uint16_t *)A_f, *Bt = (uint16_t *)B_f;
+        return encode_typed<uint16_t, float>(p, SrcStored<uint16_t>{A, p->lda}, SrcStored<uint16_t>{Bt, p->ldb}, A,
+                                             Bt, (float *)(ws + L.acs), g.k, (float *)(ws + L.bcs), g.k, ws, s);
     }
     case ABFT_FP8_E4M3: {
         // E4M3 data (scaled domain), binary32 checksum rows in the workspace
         WsLayout L = ws_layout(p);
-        return encode_typed<uint8_t, float>(p, (uint8_t *)A_f, (uint8_t *)B_f, (float *)(ws + L.acs), g.k,
-                                            (float *)(ws + L.bcs), g.k, ws, s);
+        uint8_t *A = (uint8_t *)A_f, *Bt = (uint8_t *)B_f;
+        return encode_typed<uint8_t, float>(p, SrcStored<uint8_t>{A, p->lda}, SrcStored<uint8_t>{Bt, p->ldb}, A, Bt,
+                                            (float *)(ws + L.acs), g.k, (float *)(ws + L.bcs), g.k, ws, s);
     }
     default:
         return ABFT_E_UNSUPPORTED;
@@ -559,6 +621,36 @@ int launch_quantize(const abft_problem *p, int which, const float *X, int64_t ld
                                                                       which);
         ABFT_LAUNCHED();
         return ABFT_OK;
+    }
+    return ABFT_E_UNSUPPORTED;
+}
+
+// Quantize both binary32 operands and encode them in the same pass: the
+// values abft_quantize would store are written and the encode uses them as
+// stored, so the result equals quantize + quantize + encode bit for bit.
+// FP8 takes its per-tensor scale from an absmax pass over each operand first.
+int launch_quantize_encode(const abft_problem *p, const float *A32, int64_t lda32, const float *B32, int64_t ldb32,
+                           void *A_f, void *B_f, char *ws, hipStream_t s) {
+    WsLayout L = ws_layout(p);
+    if (p->dtype == ABFT_BF16) {
+        uint16_t *A = (uint16_t *)A_f, *Bt = (uint16_t *)B_f;
+        return encode_typed<uint16_t, float>(p, SrcQuantBf16{A32, lda32, A, p->lda}, SrcQuantBf16{B32, ldb32, Bt, p->ldb},
+                                             A, Bt, (float *)(ws + L.acs), p->k, (float *)(ws + L.bcs), p->k, ws, s);
+    }
+    if (p->dtype == ABFT_FP8_E4M3) {
+        int *scale = (int *)(ws + L.scale);
+        const float *X[2] = {A32, B32};
+        const int64_t ldx[2] = {lda32, ldb32}, rows[2] = {p->m, p->n};
+        for (int which = 0; which < 2; ++which) {
+            k_amax_init<<<1, 1, 0, s>>>(scale, which);
+            k_amax<<<(unsigned)std::min<int64_t>((rows[which] * p->k / 4 + kThreads - 1) / kThreads, 4096), kThreads,
+                     0, s>>>(X[which], ldx[which], rows[which], p->k, scale, which);
+            k_scale_exp<<<1, 1, 0, s>>>(scale, which);
+        }
+        uint8_t *A = (uint8_t *)A_f, *Bt = (uint8_t *)B_f;
+        return encode_typed<uint8_t, float>(p, SrcQuantFp8{A32, lda32, A, p->lda, scale, 0},
+                                            SrcQuantFp8{B32, ldb32, Bt, p->ldb, scale, 1}, A, Bt,
+                                            (float *)(ws + L.acs), p->k, (float *)(ws + L.bcs), p->k, ws, s);
     }
     return ABFT_E_UNSUPPORTED;
 }

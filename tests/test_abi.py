@@ -121,6 +121,19 @@ def test_describe_gemm_names_kernels_and_tiles():
     assert _call("abft_describe_gemm", C.byref(bad), 0, C.create_string_buffer(256), 256) == abft.ABFT_E_ARG
 
 
+def test_quantize_encode_rejected():
+    fake = C.c_void_p(256)
+    qe = lambda q, a32=fake, lda=256, b32=fake, ldb=256, ws=fake: _call(
+        "abft_quantize_encode", C.byref(q), a32, lda, b32, ldb, fake, fake, ws, NULL_STREAM)
+    p = abft.problem(abft.ABFT_BF16, 256, 256, 256, 1, 1)
+    assert qe(abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1)) == abft.ABFT_E_UNSUPPORTED
+    assert qe(p, a32=C.c_void_p(260)) == abft.ABFT_E_ARG        # binary32 rows not 16-byte aligned
+    assert qe(p, b32=None) == abft.ABFT_E_ARG
+    assert qe(p, lda=255) == abft.ABFT_E_ARG                    # shorter than k
+    assert qe(p, ldb=258) == abft.ABFT_E_ARG                    # not a multiple of 4
+    assert qe(p, ws=None) == abft.ABFT_E_WORKSPACE
+
+
 def test_block_cyclic_arguments_rejected():
     fake = C.c_void_p(256)
     call = lambda rows, cols, es, nb, P, Q, ld=4096: _call("abft_block_cyclic_stack", fake, ld, rows, cols, es, nb,
