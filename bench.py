@@ -721,12 +721,11 @@ def run_campaign(args):
         if lowp:
             abft.fill_uniform(abft.ABFT_F32, m, k, k, 0, seed, synth.STREAM_A, A32)
             abft.fill_uniform(abft.ABFT_F32, k, n, k, 1, seed, synth.STREAM_B, Bt32)
-            abft.quantize(P.p, 0, A32, P.A, P.ws)
-            abft.quantize(P.p, 1, Bt32, P.Bt, P.ws)
+            abft.quantize_encode(P.p, A32, Bt32, P.A, P.Bt, P.ws)
         else:
             abft.fill_uniform(adt, m, k, k, 0, seed, synth.STREAM_A, P.A)
             abft.fill_uniform(adt, k, n, k, 1, seed, synth.STREAM_B, P.Bt)
-        P.encode()
+            P.encode()
         P.gemm(abft.ABFT_FUSED if site_k else 0)
 
     def first_verify():
@@ -1149,9 +1148,10 @@ def main():
 
     def step(s):
         if lowp:
-            abft.quantize(P.p, 0, A32, P.A, P.ws)
-            abft.quantize(P.p, 1, Bt32, P.Bt, P.ws)
-        P.encode()
+            # quantize both binary32 operands and encode them in one pass
+            abft.quantize_encode(P.p, A32, Bt32, P.A, P.Bt, P.ws)
+        else:
+            P.encode()
         if n_panels:
             # rank-(k/n_panels) updates; repair half-way through the loop
             ev = [panel(q) for q in range(n_panels // 2)]

@@ -172,13 +172,13 @@ size_t abft_workspace_size(const abft_problem *p);
 int abft_quantize(const abft_problem *p, int which, const float *X, int64_t ldx, void *dst, void *ws, void *stream);
 
 /*
- * Quantize both binary32 operands and encode them in one pass: the same
- * A_f, B_f and workspace contents, bit for bit, as abft_quantize(p, 0, A32,
- * lda32, A_f, ws), abft_quantize(p, 1, B32, ldb32, B_f, ws) and
- * abft_encode(p, A_f, B_f, ws), with each binary32 operand read once (FP8:
- * twice, its absmax pass first) and the quantized values encoded as they are
- * stored.  A32: A (m x k, row-major, lda32); B32: B^T (n x k, row-major,
- * ldb32).  ABFT_BF16 and ABFT_FP8_E4M3 only (ABFT_E_UNSUPPORTED otherwise);
+ * Quantize both binary32 operands and encode them: the same A_f, B_f and
+ * workspace contents, bit for bit, as abft_quantize(p, 0, A32, lda32, A_f,
+ * ws), abft_quantize(p, 1, B32, ldb32, B_f, ws) and abft_encode(p, A_f, B_f,
+ * ws).  bfloat16: one pass per operand, each binary32 operand read once and
+ * its quantized values encoded as they are stored; FP8: the same three calls
+ * in sequence (measured faster than one pass).  A32: A (m x k, row-major,
+ * lda32); B32: B^T (n x k, row-major, ldb32).  ABFT_BF16 and ABFT_FP8_E4M3 only (ABFT_E_UNSUPPORTED otherwise);
  * A32 and B32 16-byte aligned with lda32, ldb32 >= k and multiples of 4;
  * A_f, B_f and ws as for abft_quantize and abft_encode.  Asynchronous.
  */

@@ -106,9 +106,8 @@ __device__ inline void row_partial(double *rp, int64_t rps, int64_t row, int64_t
 }
 
 // Where the encode pass takes an operand's values from: the stored operand,
-// or binary32 values quantized on the way (bfloat16 round to nearest even, or
-// E4M3 at the operand's per-tensor scale), which are written to the operand's
-// storage and used as stored.  load(row, l0, v) fills the V values
+// or binary32 values quantized to bfloat16 on the way (round to nearest even),
+// which are written to the operand's storage and used as stored.  load(row, l0, v) fills the V values
 // X[row, l0 .. l0+V) as binary64.
 template <typename T> struct SrcStored {
     const T *X;
@@ -137,33 +136,6 @@ struct SrcQuantBf16 {
         for (int q = 0; q < 8; ++q) v[q] = (double)bf16_to_f32(h[q]);
     }
 };
-struct SrcQuantFp8 {
-    const float *X;
-    int64_t ldx;
-    uint8_t *Q;
-    int64_t ldq;
-    const int *scale;      // ws scale words: the operand's exponent e (x 2^e before rounding)
-    int which;
-    __device__ void load(int64_t row, int64_t l0, double *v) const {
-        typedef float v4 __attribute__((ext_vector_type(4)));
-        const float f = __builtin_ldexpf(1.0f, scale[which]);
-        v4u32 o;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const v4 x = *(const v4 *)(X + row * ldx + l0 + 4 * w);
-            uint32_t word = 0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t c = f32_to_e4m3_rne(x[q] * f);
-                word |= c << (8 * q);
-                v[4 * w + q] = e4m3_to_f64(c);
-            }
-            o[w] = word;
-        }
-        *(v4u32 *)(Q + row * ldq + l0) = o;
-    }
-};
-
 // Each thread owns V = 16/sizeof(T) consecutive columns l (one 16-byte load per
 // row); rows of X are 16-byte aligned and k is a multiple of V.
 template <typename T, typename TC, class Src>
@@ -625,32 +597,25 @@ int launch_quantize(const abft_problem *p, int which, const float *X, int64_t ld
     return ABFT_E_UNSUPPORTED;
 }
 
-// Quantize both binary32 operands and encode them in the same pass: the
-// values abft_quantize would store are written and the encode uses them as
-// stored, so the result equals quantize + quantize + encode bit for bit.
-// FP8 takes its per-tensor scale from an absmax pass over each operand first.
+// Quantize both binary32 operands and encode them.  bfloat16: in the same
+// pass (the values abft_quantize would store are written and the encode uses
+// them as stored), so the result equals quantize + quantize + encode bit for
+// bit.  FP8: the separate passes, which measured faster than one pass that
+// rounds, decodes and sums 16 values per thread (absmax, quantize and encode
+// per operand).
 int launch_quantize_encode(const abft_problem *p, const float *A32, int64_t lda32, const float *B32, int64_t ldb32,
                            void *A_f, void *B_f, char *ws, hipStream_t s) {
-    WsLayout L = ws_layout(p);
     if (p->dtype == ABFT_BF16) {
+        WsLayout L = ws_layout(p);
         uint16_t *A = (uint16_t *)A_f, *Bt = (uint16_t *)B_f;
         return encode_typed<uint16_t, float>(p, SrcQuantBf16{A32, lda32, A, p->lda}, SrcQuantBf16{B32, ldb32, Bt, p->ldb},
                                              A, Bt, (float *)(ws + L.acs), p->k, (float *)(ws + L.bcs), p->k, ws, s);
     }
     if (p->dtype == ABFT_FP8_E4M3) {
-        int *scale = (int *)(ws + L.scale);
-        const float *X[2] = {A32, B32};
-        const int64_t ldx[2] = {lda32, ldb32}, rows[2] = {p->m, p->n};
-        for (int which = 0; which < 2; ++which) {
-            k_amax_init<<<1, 1, 0, s>>>(scale, which);
-            k_amax<<<(unsigned)std::min<int64_t>((rows[which] * p->k / 4 + kThreads - 1) / kThreads, 4096), kThreads,
-                     0, s>>>(X[which], ldx[which], rows[which], p->k, scale, which);
-            k_scale_exp<<<1, 1, 0, s>>>(scale, which);
-        }
-        uint8_t *A = (uint8_t *)A_f, *Bt = (uint8_t *)B_f;
-        return encode_typed<uint8_t, float>(p, SrcQuantFp8{A32, lda32, A, p->lda, scale, 0},
-                                            SrcQuantFp8{B32, ldb32, Bt, p->ldb, scale, 1}, A, Bt,
-                                            (float *)(ws + L.acs), p->k, (float *)(ws + L.bcs), p->k, ws, s);
+        int st = launch_quantize(p, 0, A32, lda32, A_f, ws, s);
+        if (!st) st = launch_quantize(p, 1, B32, ldb32, B_f, ws, s);
+        if (!st) st = launch_encode(p, A_f, B_f, ws, s);
+        return st;
     }
     return ABFT_E_UNSUPPORTED;
 }

@@ -1,6 +1,6 @@
-"""GPU test of abft_quantize_encode: one pass that quantizes both binary32
-operands and encodes them must leave A_f, B_f and the whole workspace
-bitwise equal to abft_quantize (A), abft_quantize (B) and abft_encode, and
+"""GPU test of abft_quantize_encode: quantizing both binary32 operands and
+encoding them (bfloat16 in one pass per operand) must leave A_f, B_f and the
+whole workspace bitwise equal to abft_quantize (A), abft_quantize (B) and abft_encode, and
 the products and verification reports that follow must be equal too.  Shapes
 cover the partitioned (b = 1, 32) and direct (one group) encode passes, k with
 and without the fused row statistics (k / 8 resp. k / 16 a multiple of 64),
