@@ -129,6 +129,23 @@ def cpu_baseline(dt_name, m, n, k, b, target_s=12.0):
     return flops / dt / 1e12, orc.num_threads(), dt, rows, Cref
 
 
+def residual_rho(A_dev, Bt_dev, C_dev, m, n, k, u):
+    """The paper's residual check (Sec. 4.3) on the device's final product, in
+    the infinity norm: rho = ||C x - A (B x)|| / (k u ||C|| ||x||), x seeded
+    uniform[-1, 1]; computed on the host from the device's operands (as
+    stored, quantized ones included) and C."""
+    import numpy as np
+
+    from paper_0806_3121_amd import synth
+
+    A = A_dev[:m].double().cpu().numpy()
+    Bt = Bt_dev[:n].double().cpu().numpy()
+    C = C_dev[:m, :n].double().cpu().numpy()
+    x = synth.uniform(SEED, synth.STREAM_X, n, 1)[:, 0]
+    r = np.abs(C @ x - A @ (Bt.T @ x)).max()
+    return float(r / (k * u * np.abs(C).sum(axis=1).max() * np.abs(x).max()))
+
+
 def oracle_check(C_dev, Cref, cols):
     """Largest |C_gpu - C_oracle| / max|C_oracle| over the oracle's rows and
     the first cols columns of the device's final C_f."""
@@ -1248,6 +1265,11 @@ def main():
         # oracle's own rounding for bfloat16 / FP8)
         out["oracle_check"] = {"rows": rows, "cols": n + b, "max_rel_err": oracle_check(P.C, Cref, n + b),
                                "bound": TOL_VS_ORACLE[dt_name]}
+    if not args.no_cpu_baseline and dt_name != "fp8":
+        # FP8 results carry the operands' scale factors, which stay on the device
+        log("residual check ...")
+        out["residual_check"] = {"rho": residual_rho(P.A, P.Bt, P.C, m, n, k, 2.0 ** -53 if dt_name == "f64"
+                                                     else 2.0 ** -24), "bound": 10.0}
     print(json.dumps(out), flush=True)
 
 

@@ -134,3 +134,10 @@ def test_fullsize_pipeline(inputs, orc, b):
     diff = (P.C - clean).abs().max().item()
     assert diff / clean.abs().max().item() <= TOL64
     assert abs(P.C[i, j].item() - Af[i] @ Bf[:, j]) <= max(t_row, t_col)
+    # the paper's residual check (Sec. 4.3) on the repaired product, in the infinity norm with the unit
+    # roundoff of the accumulation: rho = ||C x - A (B x)|| / (k u ||C|| ||x||), small (<= 10)
+    x = synth.uniform(SEED, synth.STREAM_X, n, 1)[:, 0]
+    C = P.C[:m, :n].cpu().numpy()
+    rho = np.abs(C @ x - A @ (B @ x)).max() / (k * 2.0 ** -53 * np.abs(C).sum(axis=1).max() * np.abs(x).max())
+    note(f"residual rho {rho:.3e}")
+    assert rho <= 10.0
