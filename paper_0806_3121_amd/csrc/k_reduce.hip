@@ -1028,10 +1028,16 @@ __global__ __launch_bounds__(kThreads) void k_vfused_edges(const T *C, VerifyArg
     __shared__ double sh[kThreads];
     const bool col = blockIdx.x == 0;
     const int64_t len = col ? a.m : a.n;
-    double s = 0.0;
-    for (int64_t t = threadIdx.x; t < len; t += kThreads)
-        s += col ? elem<T>::load(C + t * a.ldc + a.n) : elem<T>::load(C + a.m * a.ldc + t);
-    sh[threadIdx.x] = s;
+    // element t of the carried column (row); four running sums keep four loads in flight (the tail goes to the first)
+    auto at = [&](int64_t t) { return col ? elem<T>::load(C + t * a.ldc + a.n) : elem<T>::load(C + a.m * a.ldc + t); };
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t t = threadIdx.x;
+    for (; t + 3 * kThreads < len; t += 4 * kThreads) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s4[e] += at(t + e * kThreads);
+    }
+    for (; t < len; t += kThreads) s4[0] += at(t);
+    sh[threadIdx.x] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     __syncthreads();
     for (int w = kThreads / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
