@@ -19,6 +19,7 @@
 #pragma once
 
 #include "gemm_lowp_kernel.h"
+#include "gemm_mfma2_kernel.h"
 
 namespace abft {
 
@@ -81,39 +82,123 @@ __global__ __launch_bounds__(128 * WM, 1) void k_gemm_lowp2(const typename Ops::
     const int arow = wm * (BM / WM) + lr, brow = wn * 128 + lr;
 
     const int64_t nk = K / BK;
-    issue(0, 0);
-    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
-    __syncthreads();
-    for (int64_t kt = 0; kt < nk; ++kt) {
-        const int buf = (int)(kt & 1);
-        if (kt + 1 < nk) issue(buf ^ 1, (kt + 1) * BK);
-        const uint8_t *As = lds + HDR + buf * STAGE;
-        const uint8_t *Bs = As + BM * SLAB;
-        constexpr int CPM = Ops::CPM;
+    if constexpr (Ops::CPM == 1) {
+        // Two 32-deep k groups per slab (bfloat16).  The fragments of each group
+        // are read from LDS while the previous group's MFMAs run; the one barrier
+        // per slab sits between the slab's two groups (slab kt + 1 has landed and
+        // every wave holds its fragments of slab kt, so its buffer takes slab
+        // kt + 2); and the scheduler is asked to spread the fragment reads and
+        // the slab loads evenly over the MFMAs.  Same products in the same order
+        // as one group after the other.
+        constexpr int NMF = TMW * 8, NRD = TMW + 8;
+        v4u fa0[TMW], fb0[8], fa1[TMW], fb1[8];
+        auto read = [&](int buf, int g, v4u (&fa)[TMW], v4u (&fb)[8]) {
+            const uint8_t *As = lds + HDR + buf * STAGE, *Bs = As + BM * SLAB;
+            const int kc = 4 * g + lq;
 #pragma unroll
-        for (int g = 0; g < SLAB / (64 * CPM); ++g) {
-            v4u fa[TMW][CPM], fb[8][CPM];
-#pragma unroll
-            for (int c = 0; c < CPM; ++c) {
-                const int kc = (4 * g + lq) * CPM + c;
-#pragma unroll
-                for (int a = 0; a < TMW; ++a) {
-                    int r = arow + 16 * a;
-                    fa[a][c] = *(const v4u *)(As + r * SLAB + ((kc ^ ((r >> 1) & 7)) << 4));
-                }
-#pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    int r = brow + 16 * b;
-                    fb[b][c] = *(const v4u *)(Bs + r * SLAB + ((kc ^ ((r >> 1) & 7)) << 4));
-                }
+            for (int a = 0; a < TMW; ++a) {
+                const int r = arow + 16 * a;
+                fa[a] = *(const v4u *)(As + r * SLAB + ((kc ^ ((r >> 1) & 7)) << 4));
             }
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const int r = brow + 16 * b;
+                fb[b] = *(const v4u *)(Bs + r * SLAB + ((kc ^ ((r >> 1) & 7)) << 4));
+            }
+        };
+        auto mma = [&](const v4u (&fa)[TMW], const v4u (&fb)[8]) {
 #pragma unroll
             for (int a = 0; a < TMW; ++a)
 #pragma unroll
-                for (int b = 0; b < 8; ++b) Ops::mfma_chunks(fa[a], fb[b], acc[a][b]);
+                for (int b = 0; b < 8; ++b) Ops::mfma(fa[a], fb[b], acc[a][b]);
+        };
+        // scheduling groups (masks: 0x008 MFMA, 0x020 global load, 0x100 LDS read)
+        auto spread_reads = [&]() {
+#pragma unroll
+            for (int i = 0; i < NRD; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMF / NRD, 0);
+            }
+        };
+        auto spread_loads_reads = [&]() {
+#pragma unroll
+            for (int i = 0; i < 2 * LPW; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMF / (4 * LPW), 0);
+            }
+#pragma unroll
+            for (int i = 0; i < NRD; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMF / (2 * NRD), 0);
+            }
+        };
+        issue(0, 0);
+        if (nk > 1) {
+            issue(1, BK);
+            wait_vm<2 * LPW>();
+        } else {
+            wait_vm<0>();
         }
-        __builtin_amdgcn_s_waitcnt(0x0F70);   // the next slab has landed in LDS
+        bare_barrier();
+        read(0, 0, fa0, fb0);
+        int64_t kt = 0;
+        for (; kt + 2 < nk; ++kt) {                // steady state: no branches inside
+            const int x = (int)(kt & 1);
+            read(x, 1, fa1, fb1);
+            mma(fa0, fb0);
+            spread_reads();
+            __builtin_amdgcn_s_waitcnt(0x0070);    // vmcnt(0) lgkmcnt(0)
+            bare_barrier();
+            issue(x, (kt + 2) * BK);
+            read(x ^ 1, 0, fa0, fb0);
+            mma(fa1, fb1);
+            spread_loads_reads();
+        }
+        for (; kt < nk; ++kt) {                    // the last one or two slabs
+            const int x = (int)(kt & 1);
+            read(x, 1, fa1, fb1);
+            mma(fa0, fb0);
+            __builtin_amdgcn_s_waitcnt(0x0070);
+            bare_barrier();
+            if (kt + 1 < nk) read(x ^ 1, 0, fa0, fb0);
+            mma(fa1, fb1);
+        }
+        __syncthreads();                           // LDS is reused by the epilogue
+    } else {
+        issue(0, 0);
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
         __syncthreads();
+        for (int64_t kt = 0; kt < nk; ++kt) {
+            const int buf = (int)(kt & 1);
+            if (kt + 1 < nk) issue(buf ^ 1, (kt + 1) * BK);
+            const uint8_t *As = lds + HDR + buf * STAGE;
+            const uint8_t *Bs = As + BM * SLAB;
+            constexpr int CPM = Ops::CPM;
+#pragma unroll
+            for (int g = 0; g < SLAB / (64 * CPM); ++g) {
+                v4u fa[TMW][CPM], fb[8][CPM];
+#pragma unroll
+                for (int c = 0; c < CPM; ++c) {
+                    const int kc = (4 * g + lq) * CPM + c;
+#pragma unroll
+                    for (int a = 0; a < TMW; ++a) {
+                        int r = arow + 16 * a;
+                        fa[a][c] = *(const v4u *)(As + r * SLAB + ((kc ^ ((r >> 1) & 7)) << 4));
+                    }
+#pragma unroll
+                    for (int b = 0; b < 8; ++b) {
+                        int r = brow + 16 * b;
+                        fb[b][c] = *(const v4u *)(Bs + r * SLAB + ((kc ^ ((r >> 1) & 7)) << 4));
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < TMW; ++a)
+#pragma unroll
+                    for (int b = 0; b < 8; ++b) Ops::mfma_chunks(fa[a], fb[b], acc[a][b]);
+            }
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // the next slab has landed in LDS
+            __syncthreads();
+        }
     }
 
     const float sc = scale_exp ? __builtin_ldexpf(1.0f, -(scale_exp[0] + scale_exp[1])) : 1.0f;
