@@ -71,12 +71,13 @@ BATCH = {"count": 512, "lo": 64, "hi": 2048, "step": 32, "br": 32, "bc": 1, "lam
 FLIP_BITS = {"f64": (40, 62), "f32": (24, 29), "bf16": (24, 29), "fp8": (24, 29)}
 # HBM bytes per protected-product call (read + write, all its launches), from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE on this benchmark, FETCH_SIZE scaled by 2 (a 1 GiB copy reads 0.5 GiB of FETCH_SIZE);
-# summarized in profiles/hbm_traffic_counters_c2_c2panel_c2w_c4_c5.txt.  Re-measure when those kernels change.
+# summarized in profiles/hbm_traffic_counters_c2_c2b1_c2panel_c2w_c4_c5.txt.  Re-measure when those kernels change.
 TRAFFIC = {
-    "c2": 41.247e9 + 0.680e9,                       # k_gemm_mfma2 (checksum blocks tiled with the data)
+    "c2": 41.513e9 + 0.680e9,                       # k_gemm_mfma2 (checksum blocks tiled with the data)
+    "c2b1": 40.120e9 + 0.562e9 + 2 * 0.538e9,       # k_gemm_mfma2 + two k_sliver launches
     "c2panel": 3.832e9 + 0.679e9,                   # one accumulating panel launch of k_gemm_mfma2
     "c2w": 41.595e9 + 0.680e9,                      # k_gemm_mfma2 over the weighted-checksum C_f
-    "c4": 12.942e9 + 1.122e9 + 2 * 0.539e9,         # k_gemm_lowp2 + two k_sliver launches
+    "c4": 13.728e9 + 1.121e9 + 2 * 0.539e9,         # k_gemm_lowp2 + two k_sliver launches
     "c5": 5.185e9 + 2.664e9 + 0.226e9 + 0.087e9,    # kb_gemm (tuned tile) + kb_combine
 }
 SEED = 20080523
@@ -1243,7 +1244,9 @@ def main():
                    "m": m, "n": n, "k": k, "br": b, "bc": b, "global_batch": 1, "seq_len": 0,
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": TRAFFIC.get(args.workload),
+                     "frac": round(achieved / peak, 4),
+                     # the counters were taken on the site-M product (the fused epilogue is another kernel)
+                     "traffic": None if site_k else TRAFFIC.get(args.workload),
                      "kernel": abft.describe_gemm(P.p, abft.ABFT_FUSED if site_k else 0)
                                + (f", {n_panels} accumulating panel launches per product" if n_panels else ""),
                      "flops_per_launch": executed / max(1, n_panels),
