@@ -120,6 +120,11 @@ def test_fullsize_pipeline(inputs, orc, b):
         assert not (abs(d_col) <= t_col)
     gpu_rows = [f[:2] for f in rep.flags_r()]
     gpu_cols = [f[:2] for f in rep.flags_c()]
+    # the GPU's thresholds of these relations (row statistics from the encode pass) are the oracle's
+    for f in rep.flags_r():
+        assert abs(f[3] - tr[f[0], f[1]]) <= 1e-10 * tr[f[0], f[1]]
+    for f in rep.flags_c():
+        assert abs(f[3] - tc[f[0], f[1]]) <= 1e-10 * tc[f[0], f[1]]
     assert gpu_rows == [(i, j % b)]
     assert gpu_cols == ([] if col_erased else [(i % b, j)])
     assert (loc.cls, loc.i, loc.j) == (abft.ABFT_CLS_DATA, i, j)

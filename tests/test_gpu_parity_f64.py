@@ -165,6 +165,11 @@ def test_flip_detect_locate_correct(dev, orc, m, n, k, br, bc, runs):
         assert (rep.n_flag_c, rep.n_flag_r) == (orep.n_flag_c, orep.n_flag_r)
         assert [f[:2] for f in rep.flags_c()] == [f[:2] for f in orep.flags_c()]
         assert [f[:2] for f in rep.flags_r()] == [f[:2] for f in orep.flags_r()]
+        # the GPU's thresholds (statistics from the encode pass or from their own pass) are the oracle's
+        for r, jj, _, tau in rep.flags_c():
+            assert abs(tau - tc[r, jj]) <= 1e-10 * tc[r, jj]
+        for ii, c, _, tau in rep.flags_r():
+            assert abs(tau - tr[ii, c]) <= 1e-10 * tr[ii, c]
         assert (loc.cls, loc.i, loc.j, loc.dir) == (ocls, oi, oj, od)
         if loc.cls in (abft.ABFT_CLS_DATA, abft.ABFT_CLS_CHECKSUM):
             assert (loc.i, loc.j) == (i, j)

@@ -140,6 +140,11 @@ def test_lowp_flip_decisions_match_oracle(dev, orc, m, n, k, br, bc, runs, dt):
         _, _, orep = orc.verify(Cx.astype(np.float64), m, n, br, bc, tc, tr)
         ocls, oi, oj, od = orc.classify(orep, m, n, br, bc)
         assert (rep.n_flag_c, rep.n_flag_r) == (orep.n_flag_c, orep.n_flag_r), (i, j, bit, delta)
+        # the GPU's statistical thresholds are the oracle's (binary32 weights in A's weighted row sums)
+        for r, jj, _, tau in rep.flags_c():
+            assert abs(tau - tc[r, jj]) <= 1e-6 * tc[r, jj]
+        for ii, c, _, tau in rep.flags_r():
+            assert abs(tau - tr[ii, c]) <= 1e-6 * tr[ii, c]
         assert (loc.cls, loc.i, loc.j) == (ocls, oi, oj)
         if loc.cls in (abft.ABFT_CLS_DATA, abft.ABFT_CLS_CHECKSUM):
             located += 1
