@@ -5,6 +5,9 @@
 // base + 16 L; measured on gfx950), double-buffered, with no register staging
 // and no LDS write instructions.  An MFMA group takes CPM chunks per lane:
 // chunk kc = (4 g + lane / 16) CPM + c of the slab, identical for A and B.
+// bfloat16 (two groups per slab) runs a software pipeline over the groups
+// with its barrier between them (see the main loop); FP8 (one 128-deep group
+// per slab) reads its fragments after the slab's barrier.
 //
 // LDS layout per slab and operand: row r occupies 128 bytes = 8 chunks of 16
 // bytes; chunk kc of row r is stored at slot kc ^ ((r >> 1) & 7).  The 16 lanes
