@@ -63,11 +63,11 @@ WsLayout ws_layout(const abft_problem *p) {
     L.partial = take(L.partial_bytes > 0 ? L.partial_bytes : 8);
     // fused row statistics: the larger operand's data rows plus its checksum and group rows, k / 64 slots each
     L.rowpart = take(rows_fused(p) ? sizeof(double) * (std::max(g.m, g.n) + 2 * std::max(g.br, g.bc)) * (g.k / 64) : 8);
-    // one-pass re-read verification (b = 1): column sums per 128-row tile, row sums per 128-column
+    // one-pass re-read verification (b = 1): column sums per kVerifyPartRows-row tile, row sums per 128-column
     // (binary64 C) or 256-column (binary32 C) tile
     const bool b1 = g.br == 1 && g.bc == 1;
     const int64_t vw = 64 * (16 / (p->dtype == ABFT_F64 ? 8 : 4));
-    L.vpart_c = take(b1 ? sizeof(double) * ((g.m + 127) / 128) * g.n : 8);
+    L.vpart_c = take(b1 ? sizeof(double) * ((g.m + kVerifyPartRows - 1) / kVerifyPartRows) * g.n : 8);
     L.vpart_r = take(b1 ? sizeof(double) * ((g.n + vw - 1) / vw) * g.m : 8);
     L.report = take(sizeof(abft_report));
     // fused partials (b = 1 only): column sums per tile row, row sums per tile column

@@ -254,6 +254,9 @@ bool fused_grid(const void *ws, const abft_problem *p, int64_t *tiles_m, int64_t
 void arm_accumulator_flip(const void *ws, int64_t i, int64_t j, int bit);
 // Smallest tile edge of every product kernel: bounds the tile rows / columns of the fused partials.
 constexpr int64_t kMinTileEdge = 96;
+// Row tile of the one-pass b = 1 re-read verification (column sums per tile of this many rows); its row
+// sums are per tile of 64 16-byte vectors (128 binary64 or 256 binary32 columns).
+constexpr int64_t kVerifyPartRows = 128;
 int launch_correct(const abft_problem *p, void *C_f, int64_t i, int64_t j, int dir, hipStream_t s);
 int launch_recover(const abft_problem *p, void *C_f, abft_rect e, int use_rows, hipStream_t s);
 int launch_inject_flip(const abft_problem *p, void *C_f, int64_t i, int64_t j, int bit, hipStream_t s);

@@ -907,7 +907,7 @@ static void launch_vblock(const double *C, const VerifyArgs &a, const ErasureRes
 // sums of each 64V-column tile (pr[tile column][i]), the layout the product
 // epilogue writes for the fused verification; k_vfused then finishes the
 // relations.  A wave takes rows w, w + 4, ... of its tile, four at a time.
-constexpr int64_t kPartRows = 128;
+constexpr int64_t kPartRows = kVerifyPartRows;
 template <typename T, int V>
 __global__ __launch_bounds__(kThreads) void k_vpartials(const T *C, int64_t ldc, int64_t m, int64_t n, double *pc,
                                                         double *pr) {
