@@ -110,9 +110,15 @@ def cpu_baseline(dt_name, m, n, k, b, target_s=12.0):
             return orc.e4m3_values(orc.to_e4m3_codes(X * np.float32(2.0 ** e))) * 2.0 ** -e
         return X.astype(np.float64)
 
-    B = quant(synth.uniform(SEED, synth.STREAM_B, k, n, ndt))
+    B32 = synth.uniform(SEED, synth.STREAM_B, k, n, ndt)
     probe = 32
-    A0 = quant(synth.uniform_rows(SEED, synth.STREAM_A, np.arange(probe), k, ndt).astype(ndt))
+    A32 = synth.uniform_rows(SEED, synth.STREAM_A, np.arange(probe), k, ndt).astype(ndt)
+    # low precision: the first rows of the product of the unquantized binary32 inputs (numpy, binary64),
+    # against which the quantization error of the result is reported
+    Cu = A32.astype(np.float64) @ B32.astype(np.float64) if dt_name in ("bf16", "fp8") else None
+    B = quant(B32)
+    del B32
+    A0 = quant(A32)
     Bf = np.zeros((k, n + b))
     Bf[:, :n] = B
     del B
@@ -127,7 +133,7 @@ def cpu_baseline(dt_name, m, n, k, b, target_s=12.0):
     Cref = orc.gemm(A, Bf)
     dt = time.perf_counter() - t0
     flops = 2.0 * rows * (n + b) * k
-    return flops / dt / 1e12, orc.num_threads(), dt, rows, Cref
+    return flops / dt / 1e12, orc.num_threads(), dt, rows, Cref, Cu
 
 
 def residual_rho(A_dev, Bt_dev, C_dev, m, n, k, u):
@@ -448,7 +454,7 @@ def run_weighted(args):
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        tf, thr, sec, rows, Cref = cpu_baseline("f64", m, n, k, f * b, args.cpu_seconds)
+        tf, thr, sec, rows, Cref, _ = cpu_baseline("f64", m, n, k, f * b, args.cpu_seconds)
         # data columns only: the oracle's sample encodes unit-weight checksum columns
         out["oracle_check"] = {"rows": rows, "cols": n, "max_rel_err": oracle_check(P.C, Cref, n),
                                "bound": 1e-12}
@@ -1260,7 +1266,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        tf, thr, sec, rows, Cref = cpu_baseline(dt_name, m, n, k, b, args.cpu_seconds)
+        tf, thr, sec, rows, Cref, Cu = cpu_baseline(dt_name, m, n, k, b, args.cpu_seconds)
         out["cpu_baseline"] = {"value": round(tf, 6), "unit": "TFLOP/s", "cores": thr, "kind": "oracle",
                                "sample": f"rows 0..{rows - 1} of the encoded product C_f = A_f B_f "
                                          f"({rows} x {n + b} x {k}, FP64 i-l-j loops), {sec:.1f} s"}
@@ -1268,6 +1274,10 @@ def main():
         # oracle's own rounding for bfloat16 / FP8)
         out["oracle_check"] = {"rows": rows, "cols": n + b, "max_rel_err": oracle_check(P.C, Cref, n + b),
                                "bound": TOL_VS_ORACLE[dt_name]}
+        if Cu is not None:
+            # what the quantization of the inputs costs: the result against the unquantized product
+            out["oracle_check"]["max_rel_err_vs_unquantized"] = oracle_check(P.C, Cu, n)
+            out["oracle_check"]["unquantized_rows"] = int(Cu.shape[0])
     if not args.no_cpu_baseline and dt_name != "fp8":
         # FP8 results carry the operands' scale factors, which stay on the device
         log("residual check ...")
