@@ -3,11 +3,11 @@
 // 128 x 128).  Operand slabs of 128 bytes of k per row go global -> LDS
 // directly (global_load_lds_dwordx4: lane L of a wave writes 16 bytes at
 // base + 16 L; measured on gfx950), double-buffered, with no register staging
-// and no LDS write instructions.  An MFMA group takes CPM chunks per lane:
-// chunk kc = (4 g + lane / 16) CPM + c of the slab, identical for A and B.
-// bfloat16 (two groups per slab) runs a software pipeline over the groups
-// with its barrier between them (see the main loop); FP8 (one 128-deep group
-// per slab) reads its fragments after the slab's barrier.
+// and no LDS write instructions.  Each slab is two k groups of 64 bytes, the
+// same chunks for A and B: bfloat16 (16 x 16 x 32 instruction) takes chunk
+// 4 g + lane / 16 of group g per lane, FP8 (32 x 32 x 64 instruction) chunks
+// 4 g + 2 (lane / 32) and the next.  Both run a software pipeline over the
+// groups with the slab's barrier between them (see the main loops).
 //
 // LDS layout per slab and operand: row r occupies 128 bytes = 8 chunks of 16
 // bytes; chunk kc of row r is stored at slot kc ^ ((r >> 1) & 7).  The 16 lanes
@@ -85,7 +85,140 @@ __global__ __launch_bounds__(128 * WM, 1) void k_gemm_lowp2(const typename Ops::
     const int arow = wm * (BM / WM) + lr, brow = wn * 128 + lr;
 
     const int64_t nk = K / BK;
-    if constexpr (Ops::CPM == 1) {
+    if constexpr (Ops::MT == 32) {
+        // FP8 through the 32 x 32 x 64 instruction: the pipeline of the
+        // bfloat16 branch below with two 64-deep groups per slab.  A fragment
+        // is 32 bytes of k (chunks 4 g + 2 (lane / 32) and the next) of row
+        // lane % 32 of a 32-row tile; the wave tile is TA x TB such tiles.
+        // After the k loop the accumulators are moved into the 16 x 16 layout
+        // of the other branches through LDS, so the epilogue is shared.
+        typedef typename Ops::v8i v8i;
+        constexpr int TA = (BM / WM) / 32, TB = 128 / 32;
+        static_assert(TA * TB * 16 == TMW * 8 * 4, "same accumulator count as the 16 x 16 layout");
+        constexpr int NRD = (TA + TB) * 2;             // 16-byte LDS reads per group
+        static_assert(NRD % 4 == 0 && NRD / 2 <= TA * TB && LPW + 4 <= TA * TB, "one MFMA per scheduling group");
+        v16f acc32[TA][TB];
+#pragma unroll
+        for (int a = 0; a < TA; ++a)
+#pragma unroll
+            for (int b = 0; b < TB; ++b)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc32[a][b][v] = 0.f;
+        const int lr = lane % 32, lh = lane / 32;
+        const int ar = wm * (BM / WM) + lr, br = wn * 128 + lr;
+        v8i fa0[TA], fb0[TB], fa1[TA], fb1[TB];
+        auto frag = [&](const uint8_t *S, int r, int g) {
+            const int k0 = 4 * g + 2 * lh, sw = (r >> 1) & 7;
+            typedef int v4i __attribute__((ext_vector_type(4)));
+            const v4i lo = *(const v4i *)(S + r * SLAB + ((k0 ^ sw) << 4));
+            const v4i hi = *(const v4i *)(S + r * SLAB + (((k0 + 1) ^ sw) << 4));
+            return (v8i)__builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+        };
+        auto read = [&](int buf, int g, v8i (&fa)[TA], v8i (&fb)[TB]) {
+            const uint8_t *As = lds + HDR + buf * STAGE, *Bs = As + BM * SLAB;
+#pragma unroll
+            for (int a = 0; a < TA; ++a) fa[a] = frag(As, ar + 32 * a, g);
+#pragma unroll
+            for (int b = 0; b < TB; ++b) fb[b] = frag(Bs, br + 32 * b, g);
+        };
+        auto mma = [&](const v8i (&fa)[TA], const v8i (&fb)[TB]) {
+#pragma unroll
+            for (int a = 0; a < TA; ++a)
+#pragma unroll
+                for (int b = 0; b < TB; ++b) Ops::mfma(fa[a], fb[b], acc32[a][b]);
+        };
+        // scheduling groups: two reads per MFMA; then the slab loads two per
+        // MFMA and the reads three per MFMA
+        auto spread_reads = [&]() {
+#pragma unroll
+            for (int i = 0; i < NRD / 2; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            }
+        };
+        auto spread_loads_reads = [&]() {
+#pragma unroll
+            for (int i = 0; i < LPW; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x100, NRD / 4, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            }
+        };
+        issue(0, 0);
+        if (nk > 1) {
+            issue(1, BK);
+            wait_vm<2 * LPW>();
+        } else {
+            wait_vm<0>();
+        }
+        bare_barrier();
+        read(0, 0, fa0, fb0);
+        int64_t kt = 0;
+        for (; kt + 2 < nk; ++kt) {                // steady state, as in the bfloat16 branch
+            const int x = (int)(kt & 1);
+            read(x, 1, fa1, fb1);
+            mma(fa0, fb0);
+            spread_reads();
+            __builtin_amdgcn_s_waitcnt(0x0070);    // vmcnt(0) lgkmcnt(0)
+            bare_barrier();
+            issue(x, (kt + 2) * BK);
+            read(x ^ 1, 0, fa0, fb0);
+            mma(fa1, fb1);
+            spread_loads_reads();
+        }
+        if (kt + 2 == nk) {                        // two slabs left: no more loads
+            const int x = (int)(kt & 1);
+            read(x, 1, fa1, fb1);
+            mma(fa0, fb0);
+            __builtin_amdgcn_s_waitcnt(0x0070);
+            bare_barrier();
+            read(x ^ 1, 0, fa0, fb0);
+            mma(fa1, fb1);
+            ++kt;
+        }
+        {                                          // the last slab (landed before the last barrier)
+            const int x = (int)(kt & 1);
+            read(x, 1, fa1, fb1);
+            mma(fa0, fb0);
+            mma(fa1, fb1);
+        }
+        __syncthreads();                           // LDS is reused below and by the epilogue
+        // 32 x 32 -> 16 x 16 layout, one 32 x 32 tile at a time through a
+        // wave-private column-major 32 x 36 float block placed after the
+        // epilogue's partial-sum area: lane l writes its column l % 32, rows
+        // 8 j + 4 (l / 32) + 0..3, then reads column 16 sb + l % 16, rows
+        // 16 sa + 4 (l / 16) + 0..3 of quarter (sa, sb).
+        constexpr int TLD = 36;
+        static_assert(16384 + 2 * WM * 32 * TLD * 4 <= 2 * STAGE, "conversion block inside LDS");
+        static_assert((WM * BN + 2 * BM) * 8 <= 16384, "clear of the epilogue's partial sums");
+        float *T = (float *)(lds + HDR + 16384) + wave * (32 * TLD);
+        auto lds_order = [] {
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_waitcnt(0xC07F);    // lgkmcnt(0)
+            asm volatile("" ::: "memory");
+        };
+#pragma unroll
+        for (int a = 0; a < TA; ++a)
+#pragma unroll
+            for (int b = 0; b < TB; ++b) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    *(v4f *)(T + lr * TLD + 8 * j + 4 * lh) =
+                        v4f{acc32[a][b][4 * j], acc32[a][b][4 * j + 1], acc32[a][b][4 * j + 2], acc32[a][b][4 * j + 3]};
+                lds_order();
+#pragma unroll
+                for (int sa = 0; sa < 2; ++sa)
+#pragma unroll
+                    for (int sb = 0; sb < 2; ++sb)
+                        acc[2 * a + sa][2 * b + sb] = *(const v4f *)(T + (16 * sb + lane % 16) * TLD + 16 * sa + 4 * (lane / 16));
+                lds_order();
+            }
+    } else {
+        static_assert(Ops::CPM == 1 && Ops::MT == 16, "16 x 16 instructions: one 16-byte chunk per lane");
         // Two 32-deep k groups per slab (bfloat16).  The fragments of each group
         // are read from LDS while the previous group's MFMAs run; the one barrier
         // per slab sits between the slab's two groups (slab kt + 1 has landed and
@@ -167,41 +300,6 @@ __global__ __launch_bounds__(128 * WM, 1) void k_gemm_lowp2(const typename Ops::
             mma(fa1, fb1);
         }
         __syncthreads();                           // LDS is reused by the epilogue
-    } else {
-        issue(0, 0);
-        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
-        __syncthreads();
-        for (int64_t kt = 0; kt < nk; ++kt) {
-            const int buf = (int)(kt & 1);
-            if (kt + 1 < nk) issue(buf ^ 1, (kt + 1) * BK);
-            const uint8_t *As = lds + HDR + buf * STAGE;
-            const uint8_t *Bs = As + BM * SLAB;
-            constexpr int CPM = Ops::CPM;
-#pragma unroll
-            for (int g = 0; g < SLAB / (64 * CPM); ++g) {
-                v4u fa[TMW][CPM], fb[8][CPM];
-#pragma unroll
-                for (int c = 0; c < CPM; ++c) {
-                    const int kc = (4 * g + lq) * CPM + c;
-#pragma unroll
-                    for (int a = 0; a < TMW; ++a) {
-                        int r = arow + 16 * a;
-                        fa[a][c] = *(const v4u *)(As + r * SLAB + ((kc ^ ((r >> 1) & 7)) << 4));
-                    }
-#pragma unroll
-                    for (int b = 0; b < 8; ++b) {
-                        int r = brow + 16 * b;
-                        fb[b][c] = *(const v4u *)(Bs + r * SLAB + ((kc ^ ((r >> 1) & 7)) << 4));
-                    }
-                }
-#pragma unroll
-                for (int a = 0; a < TMW; ++a)
-#pragma unroll
-                    for (int b = 0; b < 8; ++b) Ops::mfma_chunks(fa[a], fb[b], acc[a][b]);
-            }
-            __builtin_amdgcn_s_waitcnt(0x0F70);   // the next slab has landed in LDS
-            __syncthreads();
-        }
     }
 
     const float sc = scale_exp ? __builtin_ldexpf(1.0f, -(scale_exp[0] + scale_exp[1])) : 1.0f;

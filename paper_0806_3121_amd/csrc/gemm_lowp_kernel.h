@@ -31,6 +31,7 @@ struct Bf16Ops {
     typedef uint16_t E;
     static constexpr int KG = 32;       // k per fragment read across the wave's four lane groups
     static constexpr int CPM = 1;
+    static constexpr int MT = 16;       // output tile of one instruction: MT x MT
     __device__ static void mfma(const v4u &a, const v4u &b, v4f &c) {
         v8bf x, y;
         __builtin_memcpy(&x, &a, 16);
@@ -43,6 +44,7 @@ struct Fp8Ops {
     typedef uint8_t E;
     static constexpr int KG = 64;
     static constexpr int CPM = 1;
+    static constexpr int MT = 16;
     __device__ static void mfma(const v4u &a, const v4u &b, v4f &c) {
         long a0 = (long)(((uint64_t)a[1] << 32) | a[0]), a1 = (long)(((uint64_t)a[3] << 32) | a[2]);
         long b0 = (long)(((uint64_t)b[1] << 32) | b[0]), b1 = (long)(((uint64_t)b[3] << 32) | b[2]);
@@ -52,17 +54,19 @@ struct Fp8Ops {
     __device__ static void mfma_chunks(const v4u *a, const v4u *b, v4f &c) { mfma(a[0], b[0], c); }
 };
 
-// FP8 E4M3 through v_mfma_scale_f32_16x16x128_f8f6f4 (unit E8M0 scales, 127):
-// 32 bytes (two chunks) per lane and instruction, 128 products per output.
-struct Fp8x128Ops {
+// FP8 E4M3 through v_mfma_scale_f32_32x32x64_f8f6f4 (unit E8M0 scales): a 32 x 32
+// output tile over 64 k per instruction.  Lane l holds row (column) l % 32 and
+// 32 bytes of k, lanes 32-63 the second half of the 64; accumulator value v of
+// lane l is row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32 (measured on
+// gfx950 with integer-valued data, whose products and sums are exact).
+typedef float v16f __attribute__((ext_vector_type(16)));
+struct Fp8x64Ops {
     typedef uint8_t E;
     static constexpr int CPM = 2;
+    static constexpr int MT = 32;
     typedef int v8i __attribute__((ext_vector_type(8)));
-    __device__ static void mfma_chunks(const v4u *a, const v4u *b, v4f &c) {
-        v8i x, y;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) { x[q] = (int)a[0][q]; x[4 + q] = (int)a[1][q]; y[q] = (int)b[0][q]; y[4 + q] = (int)b[1][q]; }
-        c = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(x, y, c, 0, 0, 0, 127, 0, 127);
+    __device__ static void mfma(const v8i &a, const v8i &b, v16f &c) {
+        c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
     }
 };
 

@@ -145,8 +145,8 @@ static int protected_product(const abft_problem *p, const Geom &g, const E *A, c
 }
 
 // bfloat16 / FP8 candidates.  When k is a multiple of the 128-byte slab the
-// direct-to-LDS kernel runs (measured at 16384^3: bfloat16 49%, FP8 via the
-// 16x16x128 instruction); otherwise the padded-LDS kernel, on a 256 x 256
+// direct-to-LDS kernel runs (measured at 16384^3: bfloat16 53%, FP8 through
+// the 32x32x64 instruction 49%); otherwise the padded-LDS kernel, on a 256 x 256
 // or 128 x 128 tile (bfloat16 41% / 30% at 16384^3).
 static const TileChoice kLowpTiles[] = {
     {0, 256, 256, 1, 0.411}, {1, 128, 128, 2, 0.303},
@@ -309,8 +309,8 @@ static int product_with_extras(const abft_problem *p, const Geom &g, const void 
         return protected_product_lowp<Bf16Ops, Bf16Ops>(p, g, (const uint16_t *)A_f, (const uint16_t *)B_f,
                                                         (float *)C_f, Acs, Bcs, nullptr, plain, s, e);
     case ABFT_FP8_E4M3:
-        return protected_product_lowp<Fp8Ops, Fp8x128Ops>(p, g, (const uint8_t *)A_f, (const uint8_t *)B_f,
-                                                          (float *)C_f, Acs, Bcs, scale, plain, s, e);
+        return protected_product_lowp<Fp8Ops, Fp8x64Ops>(p, g, (const uint8_t *)A_f, (const uint8_t *)B_f,
+                                                         (float *)C_f, Acs, Bcs, scale, plain, s, e);
     default:
         return ABFT_E_UNSUPPORTED;
     }
