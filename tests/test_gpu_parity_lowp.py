@@ -87,6 +87,8 @@ SHAPES = [
     (300, 260, 528, 3, 5),
     (4096, 4096, 256, 1, 1),      # large enough for the direct-to-LDS kernel
     (4200, 4100, 384, 8, 4),      # same kernel, ragged tile edges
+    (4096, 4352, 128, 1, 1),      # one FP8 slab (two bfloat16 slabs): the loop's tail alone
+    (4300, 4100, 640, 1, 1),      # five FP8 slabs, ragged edges
 ]
 
 
@@ -178,3 +180,29 @@ def test_lowp_erasure_rebuild(dev, orc, dt):
             got = P.C[i0:i0 + h, j0:j0 + w].cpu().numpy().astype(np.float64)
             want = C32[i0:i0 + h, j0:j0 + w].astype(np.float64)
             assert np.abs(got - want).max() <= np.abs(tc).max()
+
+
+@pytest.mark.parametrize("dt", ["bf16", "fp8"])
+@pytest.mark.parametrize("m,n,k", [(4096, 4352, 128), (4300, 4100, 640), (300, 260, 528)])
+def test_lowp_integer_products_exact(dev, m, n, k, dt):
+    """Integer operands in [-4, 4] are exact in both element types (FP8 after its
+    scale 2^6), and every product and partial sum of the data part is an integer
+    of magnitude at most 16 k < 2^24 (times 2^12 in the FP8 domain), so the
+    matrix cores must return the exact product whatever their summation order:
+    the data part of C_f equals the integer product bit for bit.  This pins the
+    fragment and accumulator lane layouts of each kernel (direct-to-LDS with one
+    and with five FP8 slabs, padded-LDS) without any rounding tolerance."""
+    note(f"{dt} integer m={m} n={n} k={k}")
+    A = synth.uniform_ints(SEED + 3, synth.STREAM_A, m, k, -4, 4)
+    B = synth.uniform_ints(SEED + 3, synth.STREAM_B, k, n, -4, 4)
+    P = abft.Protected(DTYPES[dt], m, n, k, 1, 1, device=dev, tau_mode=abft.ABFT_TAU_STAT, lam=LAMBDA)
+    abft.quantize(P.p, 0, torch.from_numpy(A.astype(np.float32)).to(dev), P.A, P.ws)
+    abft.quantize(P.p, 1, torch.from_numpy(np.ascontiguousarray(B.T).astype(np.float32)).to(dev), P.Bt, P.ws)
+    P.encode()
+    P.gemm()
+    torch.cuda.synchronize()
+    want = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float32)
+    got = P.C[:m, :n].cpu().numpy()
+    assert np.array_equal(got, want), np.abs(got.astype(np.float64) - want).max()
+    rep = P.verify()
+    assert rep.n_flag_c == 0 and rep.n_flag_r == 0
