@@ -4,6 +4,7 @@
 // sums are binary64, and the per-block maxima/counts are folded with
 // wavefront shuffles before one atomic per block.
 #include <cmath>
+#include <type_traits>
 
 #include "common.h"
 
@@ -137,52 +138,58 @@ struct SrcQuantBf16 {
     }
 };
 // Each thread owns V = 16/sizeof(T) consecutive columns l (one 16-byte load per
-// row); rows of X are 16-byte aligned and k is a multiple of V.
-template <typename T, typename TC, class Src>
+// row); rows of X are 16-byte aligned and k is a multiple of V.  STAT: the
+// statistical group statistic (sum of squares, else sum of magnitudes); RM:
+// the row statistic of the fused row partials, kRowNone for none (rp unused).
+constexpr int kRowNone = -1;
+template <typename T, typename TC, class Src, bool STAT, int RM>
 __global__ __launch_bounds__(kThreads) void k_encode_direct(Src src, int64_t b, int64_t G, int64_t k, TC *CS,
-                                                            int64_t ldcs, bool stat, double *grp, double *rp,
-                                                            int64_t rps, int rmode, const double *rw) {
+                                                            int64_t ldcs, double *grp, double *rp, int64_t rps,
+                                                            const double *rw) {
     constexpr int V = vec16<T>::N;
     const int64_t kv = k / V, total = b * kv;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
         int64_t r = t / kv, l0 = (t - r * kv) * V;
         const int64_t chunk = l0 / (kWave * V);
-        double s[V], ss[V], v[V], wv[V];
+        double s[V], ss[V], wv[V];
 #pragma unroll
         for (int q = 0; q < V; ++q) {
             s[q] = ss[q] = 0.0;
-            wv[q] = (rp && rmode == ROW_W) ? rw[l0 + q] : 0.0;
+            wv[q] = RM == ROW_W ? rw[l0 + q] : 0.0;
         }
         for (int64_t g = 0; g < G; ++g) {
+            double v[V];
             src.load(g * b + r, l0, v);
             double q2 = 0.0;
 #pragma unroll
             for (int q = 0; q < V; ++q) {
                 s[q] += v[q];
-                ss[q] += stat ? v[q] * v[q] : fabs(v[q]);
-                q2 += row_term(rmode, v[q], wv[q]);
+                ss[q] += STAT ? v[q] * v[q] : fabs(v[q]);
+                if constexpr (RM != kRowNone) q2 += row_term(RM, v[q], wv[q]);
             }
-            if (rp) row_partial(rp, rps, g * b + r, chunk, q2);
+            if constexpr (RM != kRowNone) row_partial(rp, rps, g * b + r, chunk, q2);
         }
         double c2 = 0.0, g2 = 0.0;
 #pragma unroll
         for (int q = 0; q < V; ++q) {
-            finish_encode<TC>(s[q], ss[q], stat, CS + r * ldcs + l0 + q, grp + r * k + l0 + q);
-            const double c = (double)(TC)s[q], gv = stat ? ss[q] + c * c : ss[q];
-            c2 += row_term(rmode, c, wv[q]);
-            g2 += gv * gv;
+            finish_encode<TC>(s[q], ss[q], STAT, CS + r * ldcs + l0 + q, grp + r * k + l0 + q);
+            if constexpr (RM != kRowNone) {
+                const double c = (double)(TC)s[q], gv = STAT ? ss[q] + c * c : ss[q];
+                c2 += row_term(RM, c, wv[q]);
+                g2 += gv * gv;
+            }
         }
-        if (rp) {
+        if constexpr (RM != kRowNone) {
             row_partial(rp, rps, G * b + r, chunk, c2);
             row_partial(rp, rps, G * b + b + r, chunk, g2);
         }
     }
 }
 
-template <typename T, class Src>
+template <typename T, class Src, bool STAT, int RM>
 __global__ __launch_bounds__(kThreads) void k_encode_partial(Src src, int64_t b, int64_t G, int64_t k, int64_t P,
-                                                             int64_t chunk, bool stat, double *part, double *rp,
-                                                             int64_t rps, int rmode, const double *rw) {
+                                                             int64_t chunk, double *part, double *rp, int64_t rps,
+                                                             const double *rw) {
     constexpr int V = vec16<T>::N;
     const int64_t kv = k / V, rel = b * k, total = P * b * kv;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
@@ -190,22 +197,23 @@ __global__ __launch_bounds__(kThreads) void k_encode_partial(Src src, int64_t b,
         int64_t r = q / kv, l0 = (q - r * kv) * V;
         int64_t g0 = p * chunk, g1 = min(G, g0 + chunk);
         const int64_t lc = l0 / (kWave * V);
-        double s[V], ss[V], v[V], wv[V];
+        double s[V], ss[V], wv[V];
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             s[e] = ss[e] = 0.0;
-            wv[e] = (rp && rmode == ROW_W) ? rw[l0 + e] : 0.0;
+            wv[e] = RM == ROW_W ? rw[l0 + e] : 0.0;
         }
         for (int64_t g = g0; g < g1; ++g) {
+            double v[V];
             src.load(g * b + r, l0, v);
             double q2 = 0.0;
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 s[e] += v[e];
-                ss[e] += stat ? v[e] * v[e] : fabs(v[e]);
-                q2 += row_term(rmode, v[e], wv[e]);
+                ss[e] += STAT ? v[e] * v[e] : fabs(v[e]);
+                if constexpr (RM != kRowNone) q2 += row_term(RM, v[e], wv[e]);
             }
-            if (rp) row_partial(rp, rps, g * b + r, lc, q2);
+            if constexpr (RM != kRowNone) row_partial(rp, rps, g * b + r, lc, q2);
         }
 #pragma unroll
         for (int e = 0; e < V; ++e) {
@@ -265,33 +273,34 @@ __global__ __launch_bounds__(kThreads) void k_rows_finish(const double *rp, int6
 
 // Per-row statistic of X[i, 0:k), one wave per row (grid-stride over rows),
 // 16-byte loads, four in flight per lane (the statistics are listed above the
-// encode kernels).
+// encode kernels).  With ROW_W the weights sit in LDS as binary32, permuted so
+// that the lanes of a wave read consecutive words: lane L needs w[l0 + q] with
+// l0 = 64 V c + V L (chunk c of 64 V columns), stored at 64 V c + 64 q + L.
 constexpr int64_t kRowWMaxK = 16384;   // ROW_W keeps w (as binary32, 64 KB) in LDS up to this k
 constexpr int kRowThreads = 512;       // 8 waves share one copy of w
-template <typename T>
-__global__ __launch_bounds__(kRowThreads) void k_row_stats(const T *X, int64_t ld, int64_t rows, int64_t k, int mode,
-                                                           const double *w, double *out) {
+// The rows of one block for a statistic fixed at compile time (WLDS: ROW_W
+// with the weights in LDS, permuted as above).
+template <typename T, int MODE, bool WLDS>
+__device__ __attribute__((always_inline)) inline void row_stats_rows(const T *X, int64_t ld, int64_t rows, int64_t k,
+                                                                     const double *w, const float *wsh, double *out) {
     constexpr int V = vec16<T>::N;
     constexpr int NW = kRowThreads / kWave;
-    extern __shared__ float wsh[];                     // k floats when mode == ROW_W and k <= kRowWMaxK
-    const bool wlds = mode == ROW_W && k <= kRowWMaxK;
-    if (wlds) {
-        for (int64_t l = threadIdx.x; l < k; l += kRowThreads) wsh[l] = (float)w[l];
-        __syncthreads();
-    }
+    constexpr int64_t CH = (int64_t)kWave * V;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
     auto term = [&](const double *v, int64_t l0, double &acc) {
+        const float *wc = wsh + (l0 / CH) * CH + lane;  // this lane's weights of l0's chunk, stride kWave
 #pragma unroll
         for (int q = 0; q < V; ++q) {
             const double v2 = v[q] * v[q];
-            const double wl = mode == ROW_W ? (wlds ? (double)wsh[l0 + q] : w[l0 + q]) : 0.0;
-            acc += mode == ROW_W ? v2 * wl : (mode == ROW_L4SQ ? v2 * v2 : v2);
+            if constexpr (MODE == ROW_W) acc += v2 * (WLDS ? (double)wc[q * kWave] : w[l0 + q]);
+            else if constexpr (MODE == ROW_L4SQ) acc += v2 * v2;
+            else acc += v2;
         }
     };
     for (int64_t i = (int64_t)blockIdx.x * NW + wave; i < rows; i += (int64_t)gridDim.x * NW) {
         const T *row = X + i * ld;
         double acc = 0.0;
-        constexpr int64_t step = (int64_t)kWave * V;
+        constexpr int64_t step = CH;
         int64_t l0 = (int64_t)lane * V;
         for (; l0 + 3 * step < k; l0 += 4 * step) {
             double v0[V], v1[V], v2[V], v3[V];
@@ -310,7 +319,30 @@ __global__ __launch_bounds__(kRowThreads) void k_row_stats(const T *X, int64_t l
             term(v0, l0, acc);
         }
         acc = wave_sum(acc);
-        if (lane == 0) out[i] = mode == ROW_W ? acc : sqrt(acc);
+        if (lane == 0) out[i] = MODE == ROW_W ? acc : sqrt(acc);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRowThreads) void k_row_stats(const T *X, int64_t ld, int64_t rows, int64_t k, int mode,
+                                                           const double *w, double *out) {
+    constexpr int64_t CH = (int64_t)kWave * vec16<T>::N;   // columns per chunk (one 16-byte load per lane)
+    extern __shared__ float wsh[];                     // whole chunks of k when mode == ROW_W and k <= kRowWMaxK
+    const bool wlds = mode == ROW_W && k <= kRowWMaxK;
+    if (wlds) {
+        for (int64_t l = threadIdx.x; l < k; l += kRowThreads) {
+            const int64_t c = l / CH, e = l - c * CH;
+            wsh[c * CH + (e % vec16<T>::N) * kWave + e / vec16<T>::N] = (float)w[l];
+        }
+        __syncthreads();
+    }
+    if (mode == ROW_W) {
+        if (wlds) row_stats_rows<T, ROW_W, true>(X, ld, rows, k, w, wsh, out);
+        else row_stats_rows<T, ROW_W, false>(X, ld, rows, k, w, wsh, out);
+    } else if (mode == ROW_L4SQ) {
+        row_stats_rows<T, ROW_L4SQ, false>(X, ld, rows, k, w, wsh, out);
+    } else {
+        row_stats_rows<T, ROW_L2, false>(X, ld, rows, k, w, wsh, out);
     }
 }
 
@@ -320,7 +352,9 @@ static void row_stats(const T *X, int64_t ld, int64_t rows, int64_t k, int mode,
                       hipStream_t s) {
     if (rows <= 0) return;
     constexpr int NW = kRowThreads / kWave;
-    size_t lds = (mode == ROW_W && k <= kRowWMaxK) ? sizeof(float) * (size_t)k : 0;
+    constexpr int64_t CH = (int64_t)kWave * vec16<T>::N;   // the permuted weights fill whole chunks
+    static_assert(kRowWMaxK % CH == 0, "whole chunks within the LDS limit");
+    size_t lds = (mode == ROW_W && k <= kRowWMaxK) ? sizeof(float) * (size_t)((k + CH - 1) / CH * CH) : 0;
     unsigned grid = (unsigned)std::min<int64_t>((rows + NW - 1) / NW, lds ? 512 : 65536);
     k_row_stats<T><<<grid, kRowThreads, lds, s>>>(X, ld, rows, k, mode, w, out);
 }
@@ -341,15 +375,33 @@ static void encode_pass1(Src src, int64_t R, int64_t b, int64_t k, TC *CS, int64
     int64_t P = group_partitions(G, b, k / V);
     const int64_t rps = k / kWave;                 // partial slots per row (chunks of 64 columns at most)
     int64_t n_tail;
+    int64_t chunk = 0;
+    if (P > 1) {
+        chunk = (G + P - 1) / P;
+        P = (G + chunk - 1) / chunk;
+    }
+    // the statistic modes as template arguments (no per-element selects)
+    auto pass = [&](auto st, auto rm) {
+        constexpr bool ST = decltype(st)::value;
+        constexpr int RM = decltype(rm)::value;
+        if (P == 1)
+            k_encode_direct<T, TC, Src, ST, RM><<<grid_for(b * k / V), kThreads, 0, s>>>(src, b, G, k, CS, ldcs, grp,
+                                                                                         rp, rps, rw);
+        else
+            k_encode_partial<T, Src, ST, RM><<<grid_for(P * b * k / V), kThreads, 0, s>>>(src, b, G, k, P, chunk, part,
+                                                                                          rp, rps, rw);
+    };
+    auto by_row = [&](auto st) {
+        if (!rp) pass(st, std::integral_constant<int, kRowNone>{});
+        else if (rmode == ROW_W) pass(st, std::integral_constant<int, ROW_W>{});
+        else if (rmode == ROW_L4SQ) pass(st, std::integral_constant<int, ROW_L4SQ>{});
+        else pass(st, std::integral_constant<int, ROW_L2>{});
+    };
+    if (stat) by_row(std::true_type{});
+    else by_row(std::false_type{});
     if (P == 1) {
-        k_encode_direct<T, TC, Src><<<grid_for(b * k / V), kThreads, 0, s>>>(src, b, G, k, CS, ldcs, stat, grp, rp,
-                                                                             rps, rmode, rw);
         n_tail = k / (kWave * V);
     } else {
-        int64_t chunk = (G + P - 1) / P;
-        P = (G + chunk - 1) / chunk;
-        k_encode_partial<T, Src><<<grid_for(P * b * k / V), kThreads, 0, s>>>(src, b, G, k, P, chunk, stat, part,
-                                                                               rp, rps, rmode, rw);
         k_encode_finish<TC><<<grid_for(b * k), kThreads, 0, s>>>(b, k, CS, ldcs, stat, P, part, grp, rp, rps, R,
                                                                  rmode, rw);
         n_tail = k / kWave;
