@@ -206,3 +206,36 @@ def test_lowp_integer_products_exact(dev, m, n, k, dt):
     assert np.array_equal(got, want), np.abs(got.astype(np.float64) - want).max()
     rep = P.verify()
     assert rep.n_flag_c == 0 and rep.n_flag_r == 0
+
+
+def test_fp8_every_finite_code(dev, orc):
+    """A holds every finite E4M3 value (all 254 codes but the two NaN codes,
+    each many times; amax 448, so the per-tensor scale is 2^0 and the stored
+    codes are these values exactly).  The encode widens them with the device's
+    E4M3 conversion and the matrix core with its own decode, so one code decoded
+    wrongly on either side would break a relation: the product must meet the
+    FP8 value bound against the oracle and verify clean."""
+    m, n, k = 256, 384, 512
+    codes = np.array([c for c in range(256) if c & 0x7F != 0x7F], dtype=np.uint8)
+    vals = orc.e4m3_values(codes)
+    idx = (np.arange(m * k) * 7) % codes.size
+    A32 = vals[idx].reshape(m, k).astype(np.float32)
+    B32 = synth.uniform(SEED + 5, synth.STREAM_B, k, n, np.float32)
+    P = abft.Protected(abft.ABFT_FP8_E4M3, m, n, k, 1, 1, device=dev, tau_mode=abft.ABFT_TAU_STAT, lam=LAMBDA)
+    abft.quantize(P.p, 0, torch.from_numpy(A32).to(dev), P.A, P.ws)
+    abft.quantize(P.p, 1, torch.from_numpy(np.ascontiguousarray(B32.T)).to(dev), P.Bt, P.ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(P.A.cpu().numpy(), codes[idx].reshape(m, k))
+    Aq, A, eA = oracle_quantize(orc, "fp8", A32)
+    Bq, B, eB = oracle_quantize(orc, "fp8", B32)
+    assert eA == 0
+    P.encode()
+    P.gemm()
+    torch.cuda.synchronize()
+    Af, Bf = orc.encode(A, B, 1, 1, store_f32=True)
+    C32 = (orc.gemm(Af, Bf) * 2.0 ** -(eA + eB)).astype(np.float32)
+    Cg = P.C.cpu().numpy().astype(np.float64)
+    bound = (k * U32 + 2.0 ** -10) * (np.abs(Af) @ np.abs(Bf)) * 2.0 ** -(eA + eB) + U32 * np.abs(C32)
+    assert np.all(np.abs(Cg - C32) <= bound * 1.01 + 1e-30)
+    rep = P.verify()
+    assert rep.n_flag_c == 0 and rep.n_flag_r == 0, (rep.max_ratio_c, rep.max_ratio_r)
