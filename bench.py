@@ -1066,8 +1066,8 @@ def main():
                     help="run N clean products and N single flips instead of the benchmark, print the tallies")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the path is built and measured on one "
-                                   "MI355X (see the sharding notes in DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the path is built and measured on one "
+                                   "MI355X; sharding across GPUs is not built", "n_gpus": args.gpus}))
         sys.exit(2)
 
     if args.campaign:
