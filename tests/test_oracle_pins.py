@@ -201,8 +201,150 @@ def test_stat_model_matches_simulated_fp32_accumulation(orc):
     Dc, Dr, _ = orc.verify(Cf, m, n, 1, 1, tc, tr)
     z = np.concatenate([(Dc / tc).ravel(), (Dr / tr).ravel()])
     rms = np.sqrt(np.mean(z ** 2))
-    assert 0.3 < rms < 1.5, rms
+    assert 0.6 < rms < 1.0, rms          # T for T/2 would give ~0.53, a dropped T term ~10
     assert np.abs(z).max() < 6.0
+
+
+# Hand-worked threshold values.  The sizes are chosen so that every index of
+# the rigorous bound is visible: k = 2 products per entry (gamma_k = gamma_2),
+# G = 2 blocks, so each relation sum adds G values and subtracts the stored
+# checksum, which itself carries a (G-1)-term sum: gamma_{G+1} = gamma_3.
+_A2 = np.array([[1.0, 2.0], [3.0, 4.0]])
+_B2 = np.array([[5.0, -6.0], [7.0, 8.0]])
+_A4 = np.array([[1.0, 2.0], [3.0, -4.0], [5.0, 6.0], [-7.0, 8.0]])
+_B4 = np.array([[1.0, -2.0, 3.0, 0.0], [2.0, 1.0, -1.0, 4.0]])
+
+
+def _gamma(n, u):
+    return n * u / (1 - n * u)
+
+
+def test_det_threshold_hand_value_b1(orc):
+    """m = n = k = 2, b = 1.  By hand: A_f = [[1,2],[3,4],[4,6]],
+    B_f = [[5,-6,-1],[7,8,15]]; C_C^T|A| = [4,6] (norm sqrt 52), |B| C_R =
+    [11,15]^T (norm sqrt 346); column norms of B_f sqrt 74, 10, sqrt 226; row
+    norms of A_f sqrt 5, 5, sqrt 52.  tau = kappa (2 gamma_2 + 2 gamma_3 +
+    u_st) x (the two norms)."""
+    kappa = 1 + 2.0 ** -20
+    u = 2.0 ** -53
+    Af, Bf = orc.encode(_A2, _B2, 1, 1)
+    assert np.array_equal(Af, [[1, 2], [3, 4], [4, 6]]) and np.array_equal(Bf, [[5, -6, -1], [7, 8, 15]])
+    coef = kappa * (2 * _gamma(2, u) + 2 * _gamma(3, u))
+    want_c = coef * np.sqrt(52.0) * np.array([np.sqrt(74.0), 10.0, np.sqrt(226.0)])
+    want_r = coef * np.array([np.sqrt(5.0), 5.0, np.sqrt(52.0)]) * np.sqrt(346.0)
+    tc, tr = orc.tau_det(Af, Bf, 2, 2, 1, 1)
+    assert np.allclose(tc[0], want_c, rtol=1e-13, atol=0)
+    assert np.allclose(tr[:, 0], want_r, rtol=1e-13, atol=0)
+    # binary32 accumulation with binary32-stored checksums: gamma_2 at 2^-24,
+    # the relation sum still in binary64, plus one storage rounding u_st
+    u32 = 2.0 ** -24
+    coef32 = kappa * (2 * _gamma(2, u32) + 2 * _gamma(3, u) + u32)
+    tc, tr = orc.tau_det(Af, Bf, 2, 2, 1, 1, u_acc=u32, u_st=u32)
+    assert np.allclose(tc[0], coef32 * np.sqrt(52.0) * np.array([np.sqrt(74.0), 10.0, np.sqrt(226.0)]),
+                       rtol=1e-13, atol=0)
+
+
+def test_det_threshold_hand_value_b2(orc):
+    """m = n = 4, k = 2, br = bc = 2 (G = 2 blocks each way).  By hand:
+    C_C^T A = [[6,8],[-4,4]]; C_C^T|A| rows [6,8] and [10,12] (norms 10 and
+    sqrt 244); B C_R = [[4,-2],[1,5]]; |B| C_R columns [4,3] and [2,5] (norms 5
+    and sqrt 29); column norms of B_f sqrt 5, sqrt 5, sqrt 10, 4, sqrt 17,
+    sqrt 29; row norms of A_f sqrt 5, 5, sqrt 61, sqrt 113, 10, sqrt 32."""
+    kappa = 1 + 2.0 ** -20
+    u = 2.0 ** -53
+    Af, Bf = orc.encode(_A4, _B4, 2, 2)
+    assert np.array_equal(Af[4:], [[6, 8], [-4, 4]]) and np.array_equal(Bf[:, 4:], [[4, -2], [1, 5]])
+    coef = kappa * (2 * _gamma(2, u) + 2 * _gamma(3, u))
+    nb = np.sqrt([5.0, 5.0, 10.0, 16.0, 17.0, 29.0])
+    na = np.sqrt([5.0, 25.0, 61.0, 113.0, 100.0, 32.0])
+    want_c = coef * np.outer([10.0, np.sqrt(244.0)], nb)
+    want_r = coef * np.outer(na, [5.0, np.sqrt(29.0)])
+    tc, tr = orc.tau_det(Af, Bf, 4, 4, 2, 2)
+    assert np.allclose(tc, want_c, rtol=1e-13, atol=0)
+    assert np.allclose(tr, want_r, rtol=1e-13, atol=0)
+
+
+def test_stat_threshold_hand_value_b2(orc):
+    """The b > 1 branch of the statistical threshold, by hand on the b = 2
+    problem above.  v[r] sums the squares of the members of residue r,
+    checksum row included: v[0] = rows 0, 2, 4 = [1+25+36, 4+36+64] = [62, 104],
+    v[1] = rows 1, 3, 5 = [9+49+16, 16+64+16] = [74, 96]; likewise
+    w[:, 0] = [1+9+16, 4+1+1] = [26, 6], w[:, 1] = [4+0+4, 1+16+25] = [8, 42].
+    The Cauchy-Schwarz bound takes ||v_r||_2 and ||B_f[:, j]||_4^2 =
+    sqrt(sum b^4): sqrt 17, sqrt 17, sqrt 82, 16, sqrt 257, sqrt 641; row
+    factors ||A_f[i, :]||_4^2: sqrt 17, sqrt 337, sqrt 1921, sqrt 6497,
+    sqrt 5392, sqrt 512."""
+    u, T, s, lam = 2.0 ** -24, 8.0, 2.0, 10.0
+    Af, Bf = orc.encode(_A4, _B4, 2, 2)
+    coef = u * u / 3 * (T / 2 + s)
+    nv = np.array([np.hypot(62.0, 104.0), np.hypot(74.0, 96.0)])
+    nw = np.array([np.hypot(26.0, 6.0), np.hypot(8.0, 42.0)])
+    b4 = np.sqrt([17.0, 17.0, 82.0, 256.0, 257.0, 641.0])
+    a4 = np.sqrt([17.0, 337.0, 1921.0, 6497.0, 5392.0, 512.0])
+    tc, tr = orc.tau_stat(Af, Bf, 4, 4, 2, 2, u_acc=u, T=T, s_store=s, lam=lam)
+    assert np.allclose(tc, lam * np.sqrt(coef * np.outer(nv, b4)), rtol=1e-13, atol=0)
+    assert np.allclose(tr, lam * np.sqrt(coef * np.outer(a4, nw)), rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("br,bc", [(2, 3), (3, 2), (6, 1), (1, 3)])
+def test_stat_bound_dominates_brute_force_q(orc, br, bc):
+    """Brute force: Q of a relation is the sum over its members (checksum
+    entry included) of the squares of the k products that form each member.
+    The threshold is lambda sqrt(coef Q) exactly for b = 1 and, through
+    Cauchy-Schwarz, never below it for b > 1."""
+    m, n, k = 6, 6, 4
+    u, T, s, lam = 2.0 ** -24, 2.0, 2.0, 10.0
+    coef = u * u / 3 * (T / 2 + s)
+    for seed in range(5):
+        A, B = int_problem(m, n, k, seed=seed)
+        Af, Bf = orc.encode(A, B, br, bc)
+        tc, tr = orc.tau_stat(Af, Bf, m, n, br, bc, u_acc=u, T=T, s_store=s, lam=lam)
+        for r in range(br):
+            for j in range(n + bc):
+                members = [g * br + r for g in range(m // br + 1)]
+                q = sum((Af[i, l] * Bf[l, j]) ** 2 for i in members for l in range(k))
+                want = lam * np.sqrt(coef * q)
+                if br == 1:
+                    assert tc[r, j] == pytest.approx(want, rel=1e-13)
+                else:
+                    assert tc[r, j] >= want * (1 - 1e-13), (seed, r, j)
+        for i in range(m + br):
+            for c in range(bc):
+                members = [h * bc + c for h in range(n // bc + 1)]
+                q = sum((Af[i, l] * Bf[l, jj]) ** 2 for jj in members for l in range(k))
+                want = lam * np.sqrt(coef * q)
+                if bc == 1:
+                    assert tr[i, c] == pytest.approx(want, rel=1e-13)
+                else:
+                    assert tr[i, c] >= want * (1 - 1e-13), (seed, i, c)
+
+
+@pytest.mark.parametrize("b,lo,hi", [(4, 0.45, 0.8), (32, 0.45, 0.8)])
+def test_stat_model_block_checksums_simulated_fp32(orc, b, lo, hi):
+    """The b > 1 statistical threshold against a simulated binary32
+    accumulation (exact block of 4 products, one rounding per step, as in the
+    b = 1 test): the Cauchy-Schwarz bound makes sigma somewhat larger than the
+    exact-Q sigma, so rms(D/sigma) sits below the b = 1 value but well above
+    what a sqrt(T/2) or norm-power slip would leave, and no |D| reaches
+    lambda / 2 = 5 sigma."""
+    m, n, k = 64, 64, 1024
+    A = synth.uniform(21, 0, m, k, np.float32).astype(np.float64)
+    B = synth.uniform(21, 1, k, n, np.float32).astype(np.float64)
+    Af, Bf = orc.encode(A, B, b, b, store_f32=True)
+    step = 4
+    T = k / step
+    prods = Af[:, None, :] * Bf.T[None, :, :]
+    blocks = prods.reshape(m + b, n + b, k // step, step).sum(axis=3)
+    acc = np.zeros((m + b, n + b), dtype=np.float32)
+    for t in range(blocks.shape[2]):
+        acc = (acc.astype(np.float64) + blocks[:, :, t]).astype(np.float32)
+    Cf = acc.astype(np.float64)
+    tc, tr = orc.tau_stat(Af, Bf, m, n, b, b, u_acc=orc.U32, T=T, s_store=1.0, lam=1.0)
+    Dc, Dr, _ = orc.verify(Cf, m, n, b, b, tc, tr)
+    z = np.concatenate([(Dc / tc).ravel(), (Dr / tr).ravel()])
+    rms = np.sqrt(np.mean(z ** 2))
+    assert lo < rms < hi, rms
+    assert np.abs(z).max() < 5.0
 
 
 # ---------------------------------------------------------------- locate / correct (brute force)
@@ -249,6 +391,58 @@ def test_flip_residual_equals_delta(orc):
         sc = 1 if i < m else -1
         sr = 1 if j < n else -1
         assert abs(dc - sc * delta) <= tcq and abs(dr - sr * delta) <= trq
+
+
+def test_nonfinite_value_fails_both_relations(orc):
+    """A relation fails when !(|D| <= tau): a NaN or infinite element makes
+    both of its residuals non-finite, and both relations are flagged and
+    counted as non-finite, even with an infinite threshold budget elsewhere."""
+    m, n, k, br, bc = 8, 6, 5, 2, 3
+    A, B = int_problem(m, n, k, seed=41)
+    Af, Bf, Cf = orc.protected_product(A, B, br, bc)
+    tc = np.full((br, n + bc), 1e300)
+    tr = np.full((m + br, bc), 1e300)
+    for bad in (np.nan, np.inf, -np.inf):
+        for (i, j) in [(3, 4), (m + 1, 2), (5, n + 1)]:
+            Cx = Cf.copy()
+            Cx[i, j] = bad
+            _, _, rep = orc.verify(Cx, m, n, br, bc, tc, tr)
+            assert (rep.n_flag_c, rep.n_flag_r, rep.n_nonfinite) == (1, 1, 2), (bad, i, j)
+            assert rep.flags_c()[0][:2] == (i % br, j) and rep.flags_r()[0][:2] == (i, j % bc)
+
+
+def _hand_report(orc, flags_c, flags_r):
+    rep = orc.Report()
+    rep.n_flag_c, rep.n_flag_r = len(flags_c), len(flags_r)
+    for q, (a, b, d, t) in enumerate(flags_c):
+        rep.fc_r[q], rep.fc_j[q], rep.fc_d[q], rep.fc_t[q] = a, b, d, t
+    for q, (a, b, d, t) in enumerate(flags_r):
+        rep.fr_i[q], rep.fr_c[q], rep.fr_d[q], rep.fr_t[q] = a, b, d, t
+    return rep
+
+
+def test_classify_rules_on_hand_made_reports(orc):
+    """The single-error model on reports written by hand (m = n = 8,
+    br = 2, bc = 4): one error at (i, j) fails column relation (i mod br, j)
+    and row relation (i, j mod bc) with residuals +delta for a summand and
+    -delta for a stored total.  Flags that do not meet in one element, or
+    whose residuals disagree, are MULTI; a checksum entry is CHECKSUM."""
+    m = n = 8
+    br, bc = 2, 4
+    cls = lambda fc, fr: orc.classify(_hand_report(orc, fc, fr), m, n, br, bc)
+    assert cls([(1, 5, 3.0, 1e-3)], [(3, 1, 3.0, 1e-3)])[:3] == (orc.DATA, 3, 5)
+    # row 2 is residue 0, not 1: the two relations share no element
+    assert cls([(1, 5, 3.0, 1e-3)], [(2, 1, 3.0, 1e-3)])[0] == orc.MULTI
+    # column 6 is residue 2 of bc = 4, not 1
+    assert cls([(1, 6, 3.0, 1e-3)], [(3, 1, 3.0, 1e-3)])[0] == orc.MULTI
+    # congruent but inconsistent residuals: two errors, not one
+    assert cls([(1, 5, 3.0, 1e-3)], [(3, 1, 5.0, 1e-3)])[0] == orc.MULTI
+    # a carried row entry (i = m + 1) is the stored total of its column
+    # relation (-delta) and a summand of its row relation (+delta)
+    assert cls([(1, 5, -3.0, 1e-3)], [(m + 1, 1, 3.0, 1e-3)])[:3] == (orc.CHECKSUM, m + 1, 5)
+    assert cls([(1, 5, 3.0, 1e-3)], [(m + 1, 1, 3.0, 1e-3)])[0] == orc.MULTI
+    assert cls([], [])[0] == orc.CLEAN
+    assert cls([(1, 5, 3.0, 1e-3)], [])[0] == orc.MULTI
 
 
 def test_two_errors_are_not_miscorrected(orc):
@@ -429,6 +623,27 @@ def test_flip_with_known_erasure(orc, share):
     Cx[i, j] = orc.rebuild_value(Cx, m, n, b, b, i, j, d)
     assert orc.recover(Cx, m, n, b, b, rect) == 0
     assert np.array_equal(Cx, Cf)
+
+
+def test_known_erasure_skips_exactly_its_relations(orc):
+    """m = n = 8, br = bc = 4, erased rectangle rows 1..2, columns 2..4.  By
+    hand: the column relations that hold an erased element are residues
+    {1, 2} x columns {2, 3, 4} (6 relations), the row relations rows {1, 2} x
+    residues {2, 3, 0} (6 relations); nothing else is skipped, and a flip
+    outside them is still seen."""
+    m = n = 8
+    br = bc = 4
+    A, B = int_problem(m, n, 5, seed=8)
+    Af, Bf, Cf = orc.protected_product(A, B, br, bc)
+    Cx = Cf.copy()
+    Cx[1:3, 2:5] = 0.0
+    tc, tr = np.zeros((br, n + bc)), np.zeros((m + br, bc))
+    _, _, rep = orc.verify(Cx, m, n, br, bc, tc, tr, erasures=[(1, 2, 2, 3)])
+    assert (rep.n_excl_c, rep.n_excl_r) == (6, 6)
+    assert rep.n_flag_c == 0 and rep.n_flag_r == 0
+    Cx[3, 6] += 1.0                     # residue 3, column 6: neither relation holds an erased element
+    _, _, rep = orc.verify(Cx, m, n, br, bc, tc, tr, erasures=[(1, 2, 2, 3)])
+    assert [f[:2] for f in rep.flags_c()] == [(3, 6)] and [f[:2] for f in rep.flags_r()] == [(3, 2)]
 
 
 # ---------------------------------------------------------------- residual check (Sec. 4.3)
