@@ -777,8 +777,7 @@ def run_campaign(args):
         if site_k:
             # inside the product kernel: an accumulator of the data part, flipped before the epilogue
             i, j, bit = synth.flip_site(SEED + 17, r, m, n, 0, nbits - 1)
-            abft.arm_accumulator_flip(P.p, P.ws, i, j, bit)
-            P.gemm(abft.ABFT_FUSED)
+            P.gemm_fault(i, j, bit, abft.ABFT_FUSED)
         else:
             i, j, bit = synth.flip_site(SEED + 17, r, M, N, 0, nbits - 1)
             P.C.copy_(clean)
@@ -1185,8 +1184,7 @@ def main():
         elif site_k:
             # the step's flip happens inside the product kernel (one accumulator bit before the epilogue)
             i, j, bit = synth.flip_site(SEED, s, m, n, bit_lo, bit_hi)
-            abft.arm_accumulator_flip(P.p, P.ws, i, j, bit)
-            g_events.append([timed(lambda: P.gemm(abft.ABFT_FUSED))])
+            g_events.append([timed(lambda: P.gemm_fault(i, j, bit, abft.ABFT_FUSED))])
             repair(s)
         else:
             g_events.append([timed(P.gemm)])

@@ -34,8 +34,13 @@
  *    arguments are reported before anything is launched; no C++ exception or
  *    abort crosses this boundary.  After ABFT_E_HIP, abft_last_hip_error()
  *    gives the hipError_t.
- *  - Calls on distinct buffers are independent and reentrant; the library
- *    keeps no state besides the last HIP error (thread-local).
+ *  - Every call that takes a workspace ws also takes its size in bytes,
+ *    ws_bytes; a missing workspace, or one smaller than the problem's
+ *    workspace size, is refused with ABFT_E_WORKSPACE before any launch.
+ *  - The library keeps no state besides the last HIP error (thread-local):
+ *    whatever one call leaves for a later one (threshold statistics, the
+ *    fused partial sums and their owner) lives in the caller's workspace.
+ *    Calls on distinct buffers are independent and reentrant.
  */
 #ifndef ABFT_H
 #define ABFT_H
@@ -63,8 +68,11 @@ typedef enum {
     ABFT_E_HIP = -2,             /* a HIP runtime call failed (see abft_last_hip_error) */
     ABFT_E_UNCORRECTABLE = -3,   /* abft_correct: the flags do not name one element */
     ABFT_E_UNRECOVERABLE = -4,   /* abft_recover_block: more unknowns than relations */
-    ABFT_E_WORKSPACE = -5,       /* workspace pointer missing */
-    ABFT_E_UNSUPPORTED = -6      /* combination not implemented (e.g. dtype, tau mode) */
+    ABFT_E_WORKSPACE = -5,       /* workspace missing or smaller than the problem's workspace size */
+    ABFT_E_UNSUPPORTED = -6,     /* combination not implemented (e.g. dtype, tau mode) */
+    ABFT_E_STALE = -7            /* abft_verify_fused (reported in abft_report.status): the partial
+                                    sums in ws are not those of the last fused product of this
+                                    problem into this C_f */
 } abft_status;
 
 /* Detection threshold tau per relation (a relation fails when !(|D| <= tau),
@@ -135,12 +143,16 @@ typedef struct {
     double d, tau;
 } abft_flag;
 
-/* Result of abft_verify.  The flag lists hold the first ABFT_MAX_FLAGS failed
- * relations of each direction in no particular order (counts are exact). */
+/* Result of abft_verify.  The flag lists hold up to ABFT_MAX_FLAGS failed
+ * relations of each direction in the order the device recorded them (the
+ * counts are exact; when more fail, which ones are kept is unspecified).
+ * abft_classify sorts what it is given, and a report with more than one
+ * failed relation in a direction is MULTI whichever flags were kept. */
 typedef struct {
     int64_t n_flag_c, n_flag_r;       /* failed column / row relations */
     int64_t n_excl_c, n_excl_r;       /* relations skipped: they hold a known erased element */
     int64_t n_nonfinite;              /* failed relations with a NaN/Inf residual */
+    int64_t status;                   /* ABFT_OK; ABFT_E_STALE from abft_verify_fused, the rest then empty */
     double max_ratio_c, max_ratio_r;  /* max |D|/tau over finite, checked relations */
     abft_flag flag_c[ABFT_MAX_FLAGS];
     abft_flag flag_r[ABFT_MAX_FLAGS];
@@ -158,7 +170,8 @@ typedef struct {
 } abft_location;
 
 /* Bytes of device workspace the calls below need for problem p (threshold
- * statistics, verification partials and the device report). */
+ * statistics, verification partials, the fused partial sums and their owner
+ * tag, and the device report); 0 for an invalid problem. */
 size_t abft_workspace_size(const abft_problem *p);
 
 /*
@@ -169,7 +182,8 @@ size_t abft_workspace_size(const abft_problem *p);
  * columns of the column-major B_f (ldb).  ABFT_BF16: round to nearest even.
  * X and dst 16-byte aligned, ldx*4 a multiple of 16.  Asynchronous.
  */
-int abft_quantize(const abft_problem *p, int which, const float *X, int64_t ldx, void *dst, void *ws, void *stream);
+int abft_quantize(const abft_problem *p, int which, const float *X, int64_t ldx, void *dst, void *ws, size_t ws_bytes,
+                  void *stream);
 
 /*
  * Quantize both binary32 operands and encode them: the same A_f, B_f and
@@ -183,7 +197,7 @@ int abft_quantize(const abft_problem *p, int which, const float *X, int64_t ldx,
  * A_f, B_f and ws as for abft_quantize and abft_encode.  Asynchronous.
  */
 int abft_quantize_encode(const abft_problem *p, const float *A32, int64_t lda32, const float *B32, int64_t ldb32,
-                         void *A_f, void *B_f, void *ws, void *stream);
+                         void *A_f, void *B_f, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Encode (Eq. ABFT-GEMM, the checkpointed operands A_F and B_F): writes
@@ -191,9 +205,12 @@ int abft_quantize_encode(const abft_problem *p, const float *A32, int64_t lda32,
  * B_f (F64, F32; for BF16 / FP8 into ws, in binary32), summing in binary64
  * and rounding once, and writes the
  * per-row / per-column statistics the thresholds are built from into ws.
- * Reads A and B twice each (HBM-bound).
+ * HBM-bound: A and B are read once each when k / (16 / element size) is a
+ * multiple of 64 (the row statistics are taken in the same pass); otherwise,
+ * and for the statistical thresholds' weighted row sums of A (whose weights
+ * exist only after B's encode), a second pass reads the operand again.
  */
-int abft_encode(const abft_problem *p, void *A_f, void *B_f, void *ws, void *stream);
+int abft_encode(const abft_problem *p, void *A_f, void *B_f, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Chained products (stacked fault-tolerant routines; Sec. 3.2 notes that the
@@ -212,8 +229,8 @@ int abft_encode(const abft_problem *p, void *A_f, void *B_f, void *ws, void *str
  * C_f, unchanged); ws_prev is the previous product's workspace after its
  * abft_encode (read during this call only).
  */
-int abft_encode_chained(const abft_problem *p, const void *A_f, void *B_f, void *ws, const abft_problem *prev,
-                        const void *ws_prev, void *stream);
+int abft_encode_chained(const abft_problem *p, const void *A_f, void *B_f, void *ws, size_t ws_bytes,
+                        const abft_problem *prev, const void *ws_prev, size_t ws_prev_bytes, void *stream);
 
 /*
  * Protected product (Eq. ABFT-GEMM): C_f = A_f B_f over all (m+br) x (n+bc)
@@ -224,10 +241,29 @@ int abft_encode_chained(const abft_problem *p, const void *A_f, void *B_f, void 
  * streaming kernel with binary64 accumulation.  With flags & ABFT_PLAIN only
  * C = A B (m x n) is computed, on the matrix cores, and ws may be NULL.
  * A_f and B_f must have been encoded (unless ABFT_PLAIN); ws is the one
- * abft_encode filled (required for BF16 / FP8, unused for F64 / F32).
+ * abft_encode filled (required for BF16 / FP8 and for ABFT_FUSED; optional
+ * otherwise).  When ws is given, the product records in it whether its fused
+ * partial sums are valid and for which problem and C_f (a product without
+ * ABFT_FUSED on this ws invalidates them).
  */
-int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, void *ws, uint32_t flags,
-              void *stream);
+int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, void *ws, size_t ws_bytes,
+              uint32_t flags, void *stream);
+
+/*
+ * Test hook (a fault inside the computation): abft_gemm with one bit of one
+ * accumulator flipped.  The product kernel flips bit `fault->bit` of the
+ * accumulator of element (fault->i, fault->j) of C (i < m, j < n) after its
+ * k loop, before the epilogue stores C and forms the fused partial sums, so
+ * the flipped value reaches both.  bit < 64 for ABFT_F64 (binary64
+ * accumulator), < 32 otherwise.  fault is a host pointer (NULL: abft_gemm).
+ * Other arguments as abft_gemm.
+ */
+typedef struct {
+    int64_t i, j;
+    int32_t bit;
+} abft_fault;
+int abft_gemm_fault(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, void *ws, size_t ws_bytes,
+                    uint32_t flags, const abft_fault *fault, void *stream);
 
 /*
  * Diagnostic: writes to buf (len bytes, NUL-terminated) the kernels and the
@@ -270,7 +306,7 @@ int abft_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, voi
  * Returns ABFT_OK once queued; the outcome is in the report.
  */
 int abft_verify(const abft_problem *p, const void *C_f, const abft_rect *known, int n_known,
-                void *ws, abft_report *host_out, void *stream);
+                void *ws, size_t ws_bytes, abft_report *host_out, void *stream);
 
 /*
  * Fused verification (Sec. 2.2 consistency, br = bc = 1): the column
@@ -279,23 +315,15 @@ int abft_verify(const abft_problem *p, const void *C_f, const abft_rect *known, 
  * wrote in its epilogue (summed over the tiles in binary64), instead of
  * re-reading C; the carried row and column are summed from C_f.  The partials
  * describe C as the product kernel produced it: an error made inside the
- * computation (see abft_arm_accumulator_flip) reaches both C and the partials
+ * computation (see abft_gemm_fault) reaches both C and the partials
  * and is seen here, while a change of C_f in memory after the product is seen
  * only by abft_verify.  Same report, thresholds and flags as abft_verify (no
- * known erasures).  ABFT_E_ARG if no fused product of this same problem (dtype,
- * sizes, ldc) was the last product recorded for ws.
+ * known erasures).  The device checks that the last product recorded in ws
+ * was a fused product of this problem (dtype, sizes, ldc, tile grid) into
+ * this C_f; otherwise the report carries status ABFT_E_STALE and no flags.
  */
-int abft_verify_fused(const abft_problem *p, const void *C_f, void *ws, abft_report *host_out, void *stream);
-
-/*
- * Test hook (fault injection inside the computation): arm a one-shot flip of
- * bit `bit` of the accumulator of element (i, j) of C (i < m, j < n) in the
- * next abft_gemm that uses ws; the product kernel flips it after the k loop,
- * before its epilogue stores C and forms the fused partial sums.  bit < 64
- * for ABFT_F64 (binary64 accumulator), < 32 otherwise (binary32).  Host only;
- * the arming is consumed by that call.
- */
-int abft_arm_accumulator_flip(const abft_problem *p, void *ws, int64_t i, int64_t j, int bit);
+int abft_verify_fused(const abft_problem *p, const void *C_f, void *ws, size_t ws_bytes, abft_report *host_out,
+                      void *stream);
 
 /*
  * Classify a report (host only, no device work; single-error model):
@@ -470,7 +498,7 @@ typedef struct {
 /* Workspace bytes for p (weights, norms, partial sums, report); 0 if p is invalid. */
 size_t abft_wworkspace_size(const abft_wproblem *p);
 /* Copy the weights into ws (a blocking copy; once per problem and weight set). */
-int abft_wsetup(const abft_wproblem *p, void *ws);
+int abft_wsetup(const abft_wproblem *p, void *ws, size_t ws_bytes);
 /* Checksum rows Y_r of A_f and columns Z_c of B_f (binary64 weighted sums over
  * the blocks in increasing order, one rounding per step), then the threshold
  * statistics: ||A_f[x, :]||_2, ||B_f[:, j]||_2 and
@@ -478,7 +506,7 @@ int abft_wsetup(const abft_wproblem *p, void *ws);
  * ABFT_TAU_DET: tau of column relation (r, i, j) = kappa (2 gamma_k +
  * 3 gamma_{Gr+1}) S_r[i] ||B_f[:, j]||_2, a rigorous bound on the rounding of
  * the product, the checksums and the relation sum; rows alike with Gc. */
-int abft_wencode(const abft_wproblem *p, void *A_f, void *B_f, void *ws, void *stream);
+int abft_wencode(const abft_wproblem *p, void *A_f, void *B_f, void *ws, size_t ws_bytes, void *stream);
 /* C_f = A_f B_f, all M x N entries (binary64): on the matrix cores, or for
  * N <= 8 (the matrix-vector product: n = 1, bc = 1, fc = 1) by a streaming
  * kernel that reads A_f once.  A protected matrix-vector product y = A x is
@@ -489,7 +517,7 @@ int abft_wgemm(const abft_wproblem *p, const void *A_f, const void *B_f, void *C
  * element of a known erased rectangle (n_known <= 4) are skipped.  The report
  * is built in ws and, if host_out is not NULL, copied there asynchronously. */
 int abft_wverify(const abft_wproblem *p, const void *C_f, const abft_rect *known, int n_known, void *ws,
-                 abft_wreport *host_out, void *stream);
+                 size_t ws_bytes, abft_wreport *host_out, void *stream);
 /* Locate (host only, one error per group).  When fr >= 2 each failed column
  * group is located on its own, so errors in distinct groups are found
  * together: a data member g with error e gives residuals wr[.][g] e (every
@@ -504,7 +532,8 @@ int abft_wlocate(const abft_wproblem *p, const abft_wreport *report, abft_locati
 /* Rebuild located elements in place from their groups (never reading them):
  * a data member from the lowest-numbered checksum relation of its group, a
  * checksum entry as its weighted sum.  MULTI locations are refused. */
-int abft_wcorrect(const abft_wproblem *p, void *C_f, const abft_location *locs, int n, void *ws, void *stream);
+int abft_wcorrect(const abft_wproblem *p, void *C_f, const abft_location *locs, int n, void *ws, size_t ws_bytes,
+                  void *stream);
 /* Sec. 2.1 recovery of lost blocks.  dir ABFT_DIR_COL: blocks[] are block-row
  * indices (g < Gr data block rows, Gr + r checksum block row r) lost over the
  * columns [lo, lo + len); every column group solves for the lost data members
@@ -514,7 +543,7 @@ int abft_wcorrect(const abft_wproblem *p, void *C_f, const abft_location *locs, 
  * [lo, lo + len).  ABFT_E_UNRECOVERABLE when more data blocks are lost than
  * checksum blocks survive or the system's 1-norm condition number exceeds 1e12. */
 int abft_wrecover(const abft_wproblem *p, void *C_f, int dir, const int32_t *blocks, int n_blocks, int64_t lo,
-                  int64_t len, void *ws, void *stream);
+                  int64_t len, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * 2-D block-cyclic distribution (Sec. 4.1: matrices spread over a process grid

@@ -15,6 +15,7 @@ ABFT_F64, ABFT_F32, ABFT_BF16, ABFT_FP8_E4M3 = 0, 1, 2, 3
 ABFT_OK, ABFT_FAULT_DETECTED = 0, 1
 ABFT_E_ARG, ABFT_E_HIP, ABFT_E_UNCORRECTABLE, ABFT_E_UNRECOVERABLE, ABFT_E_WORKSPACE, ABFT_E_UNSUPPORTED = \
     -1, -2, -3, -4, -5, -6
+ABFT_E_STALE = -7
 ABFT_TAU_DET, ABFT_TAU_STAT, ABFT_TAU_EXACT = 0, 1, 2
 ABFT_PLAIN = 1
 ABFT_ACCUMULATE = 2
@@ -49,7 +50,7 @@ class abft_flag(C.Structure):
 class abft_report(C.Structure):
     _fields_ = [("n_flag_c", C.c_int64), ("n_flag_r", C.c_int64),
                 ("n_excl_c", C.c_int64), ("n_excl_r", C.c_int64),
-                ("n_nonfinite", C.c_int64),
+                ("n_nonfinite", C.c_int64), ("status", C.c_int64),
                 ("max_ratio_c", C.c_double), ("max_ratio_r", C.c_double),
                 ("flag_c", abft_flag * ABFT_MAX_FLAGS), ("flag_r", abft_flag * ABFT_MAX_FLAGS)]
 
@@ -62,6 +63,10 @@ class abft_report(C.Structure):
 
 class abft_location(C.Structure):
     _fields_ = [("cls", C.c_int32), ("dir", C.c_int32), ("i", C.c_int64), ("j", C.c_int64)]
+
+
+class abft_fault(C.Structure):
+    _fields_ = [("i", C.c_int64), ("j", C.c_int64), ("bit", C.c_int32)]
 
 
 class abft_batch_item(C.Structure):
@@ -108,6 +113,7 @@ class abft_wreport(C.Structure):
 
 _lib = None
 _V = C.c_void_p
+_Z = C.c_size_t
 _P = C.POINTER
 
 
@@ -120,16 +126,16 @@ def lib():
         L = C.CDLL(LIB_PATH)
         sig = {
             "abft_workspace_size": (C.c_size_t, [_P(abft_problem)]),
-            "abft_encode": (C.c_int, [_P(abft_problem), _V, _V, _V, _V]),
-            "abft_encode_chained": (C.c_int, [_P(abft_problem), _V, _V, _V, _P(abft_problem), _V, _V]),
-            "abft_gemm": (C.c_int, [_P(abft_problem), _V, _V, _V, _V, C.c_uint32, _V]),
+            "abft_encode": (C.c_int, [_P(abft_problem), _V, _V, _V, _Z, _V]),
+            "abft_encode_chained": (C.c_int, [_P(abft_problem), _V, _V, _V, _Z, _P(abft_problem), _V, _Z, _V]),
+            "abft_gemm": (C.c_int, [_P(abft_problem), _V, _V, _V, _V, _Z, C.c_uint32, _V]),
+            "abft_gemm_fault": (C.c_int, [_P(abft_problem), _V, _V, _V, _V, _Z, C.c_uint32, _P(abft_fault), _V]),
             "abft_gemm_panel": (C.c_int, [_P(abft_problem), _V, _V, _V, C.c_int64, C.c_int64, C.c_uint32, _V]),
             "abft_describe_gemm": (C.c_int, [_P(abft_problem), C.c_uint32, C.c_char_p, C.c_size_t]),
-            "abft_quantize_encode": (C.c_int, [_P(abft_problem), _V, C.c_int64, _V, C.c_int64, _V, _V, _V, _V]),
-            "abft_quantize": (C.c_int, [_P(abft_problem), C.c_int, _V, C.c_int64, _V, _V, _V]),
-            "abft_verify": (C.c_int, [_P(abft_problem), _V, _P(abft_rect), C.c_int, _V, _V, _V]),
-            "abft_verify_fused": (C.c_int, [_P(abft_problem), _V, _V, _V, _V]),
-            "abft_arm_accumulator_flip": (C.c_int, [_P(abft_problem), _V, C.c_int64, C.c_int64, C.c_int]),
+            "abft_quantize_encode": (C.c_int, [_P(abft_problem), _V, C.c_int64, _V, C.c_int64, _V, _V, _V, _Z, _V]),
+            "abft_quantize": (C.c_int, [_P(abft_problem), C.c_int, _V, C.c_int64, _V, _V, _Z, _V]),
+            "abft_verify": (C.c_int, [_P(abft_problem), _V, _P(abft_rect), C.c_int, _V, _Z, _V, _V]),
+            "abft_verify_fused": (C.c_int, [_P(abft_problem), _V, _V, _Z, _V, _V]),
             "abft_classify": (C.c_int, [_P(abft_problem), _P(abft_report), _P(abft_rect), C.c_int,
                                         _P(abft_location)]),
             "abft_correct": (C.c_int, [_P(abft_problem), _V, _P(abft_location), _V]),
@@ -149,15 +155,15 @@ def lib():
             "abft_batch_verify": (C.c_int, [_P(abft_batch_plan), _V]),
             "abft_batch_reports": (C.c_int, [_P(abft_batch_plan), _V, _V]),
             "abft_wworkspace_size": (C.c_size_t, [_P(abft_wproblem)]),
-            "abft_wsetup": (C.c_int, [_P(abft_wproblem), _V]),
-            "abft_wencode": (C.c_int, [_P(abft_wproblem), _V, _V, _V, _V]),
+            "abft_wsetup": (C.c_int, [_P(abft_wproblem), _V, _Z]),
+            "abft_wencode": (C.c_int, [_P(abft_wproblem), _V, _V, _V, _Z, _V]),
             "abft_wgemm": (C.c_int, [_P(abft_wproblem), _V, _V, _V, _V]),
-            "abft_wverify": (C.c_int, [_P(abft_wproblem), _V, _P(abft_rect), C.c_int, _V, _V, _V]),
+            "abft_wverify": (C.c_int, [_P(abft_wproblem), _V, _P(abft_rect), C.c_int, _V, _Z, _V, _V]),
             "abft_wlocate": (C.c_int, [_P(abft_wproblem), _P(abft_wreport), _P(abft_location), C.c_int,
                                        _P(C.c_int)]),
-            "abft_wcorrect": (C.c_int, [_P(abft_wproblem), _V, _P(abft_location), C.c_int, _V, _V]),
+            "abft_wcorrect": (C.c_int, [_P(abft_wproblem), _V, _P(abft_location), C.c_int, _V, _Z, _V]),
             "abft_wrecover": (C.c_int, [_P(abft_wproblem), _V, C.c_int, _P(C.c_int32), C.c_int, C.c_int64,
-                                        C.c_int64, _V, _V]),
+                                        C.c_int64, _V, _Z, _V]),
             "abft_block_cyclic_stack": (C.c_int, [_V, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int64,
                                                   C.c_int32, C.c_int32, _V, C.c_int64, _V]),
             "abft_block_cyclic_unstack": (C.c_int, [_V, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int64,
@@ -197,6 +203,11 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _nbytes(t) -> int:
+    """Size in bytes of a workspace tensor (0 for None)."""
+    return 0 if t is None else t.numel() * t.element_size()
+
+
 def problem(dtype, m, n, k, br, bc, lda=None, ldb=None, ldc=None, tau_mode=None, lam=0.0, kappa=0.0):
     if tau_mode is None:
         tau_mode = ABFT_TAU_DET if dtype == ABFT_F64 else ABFT_TAU_STAT
@@ -210,18 +221,27 @@ def workspace_size(p: abft_problem) -> int:
 
 
 def encode(p, A_f, B_f, ws, stream=None):
-    return _check("abft_encode", lib().abft_encode(C.byref(p), _ptr(A_f), _ptr(B_f), _ptr(ws), _stream(stream)))
+    return _check("abft_encode", lib().abft_encode(C.byref(p), _ptr(A_f), _ptr(B_f), _ptr(ws), _nbytes(ws),
+                                                   _stream(stream)))
 
 
 def encode_chained(p, A_f, B_f, ws, prev, ws_prev, stream=None):
     """A_f: the previous product's C_f (lda = prev.ldc); B_f: the new operand."""
     return _check("abft_encode_chained", lib().abft_encode_chained(C.byref(p), _ptr(A_f), _ptr(B_f), _ptr(ws),
-                                                                   C.byref(prev), _ptr(ws_prev), _stream(stream)))
+                                                                   _nbytes(ws), C.byref(prev), _ptr(ws_prev),
+                                                                   _nbytes(ws_prev), _stream(stream)))
 
 
 def gemm(p, A_f, B_f, C_f, ws=None, flags=0, stream=None):
-    return _check("abft_gemm", lib().abft_gemm(C.byref(p), _ptr(A_f), _ptr(B_f), _ptr(C_f), _ptr(ws), flags,
-                                               _stream(stream)))
+    return _check("abft_gemm", lib().abft_gemm(C.byref(p), _ptr(A_f), _ptr(B_f), _ptr(C_f), _ptr(ws), _nbytes(ws),
+                                               flags, _stream(stream)))
+
+
+def gemm_fault(p, A_f, B_f, C_f, ws, i, j, bit, flags=0, stream=None):
+    """Test hook: abft_gemm with bit `bit` of the accumulator of C[i, j] flipped inside the product kernel."""
+    f = abft_fault(i, j, bit)
+    return _check("abft_gemm_fault", lib().abft_gemm_fault(C.byref(p), _ptr(A_f), _ptr(B_f), _ptr(C_f), _ptr(ws),
+                                                           _nbytes(ws), flags, C.byref(f), _stream(stream)))
 
 
 def describe_gemm(p, flags=0) -> str:
@@ -240,14 +260,14 @@ def gemm_panel(p, A_f, B_f, C_f, k0, k1, flags=0, stream=None):
 def quantize(p, which, X, dst, ws, stream=None):
     """X: float32 device tensor (A: m x k, or B^T: n x k); dst: the A_f / Bt tensor."""
     return _check("abft_quantize", lib().abft_quantize(C.byref(p), which, _ptr(X), X.stride(0), _ptr(dst), _ptr(ws),
-                                                       _stream(stream)))
+                                                       _nbytes(ws), _stream(stream)))
 
 
 def quantize_encode(p, A32, B32, A_f, B_f, ws, stream=None):
     """Quantize A32 (m x k) and B32 (B^T, n x k) binary32 tensors into A_f, B_f and encode, in one pass."""
     return _check("abft_quantize_encode",
                   lib().abft_quantize_encode(C.byref(p), _ptr(A32), A32.stride(0), _ptr(B32), B32.stride(0),
-                                             _ptr(A_f), _ptr(B_f), _ptr(ws), _stream(stream)))
+                                             _ptr(A_f), _ptr(B_f), _ptr(ws), _nbytes(ws), _stream(stream)))
 
 
 def _rects(known):
@@ -260,16 +280,15 @@ def verify(p, C_f, ws, known=None, host_out=None, stream=None):
     """host_out: a pinned uint8 CPU tensor of sizeof(abft_report) bytes, or None."""
     arr, nk = _rects(known)
     hp = C.c_void_p(host_out.data_ptr()) if host_out is not None else None
-    return _check("abft_verify", lib().abft_verify(C.byref(p), _ptr(C_f), arr, nk, _ptr(ws), hp, _stream(stream)))
+    return _check("abft_verify", lib().abft_verify(C.byref(p), _ptr(C_f), arr, nk, _ptr(ws), _nbytes(ws), hp,
+                                                   _stream(stream)))
 
 
 def verify_fused(p, C_f, ws, host_out=None, stream=None):
+    """The report's status is ABFT_E_STALE when ws holds no fused partial sums of this problem and C_f."""
     hp = C.c_void_p(host_out.data_ptr()) if host_out is not None else None
-    return _check("abft_verify_fused", lib().abft_verify_fused(C.byref(p), _ptr(C_f), _ptr(ws), hp, _stream(stream)))
-
-
-def arm_accumulator_flip(p, ws, i, j, bit):
-    return _check("abft_arm_accumulator_flip", lib().abft_arm_accumulator_flip(C.byref(p), _ptr(ws), i, j, bit))
+    return _check("abft_verify_fused", lib().abft_verify_fused(C.byref(p), _ptr(C_f), _ptr(ws), _nbytes(ws), hp,
+                                                               _stream(stream)))
 
 
 def new_report_buffer():
@@ -388,6 +407,9 @@ class Protected:
     def gemm(self, flags=0):
         gemm(self.p, self.A, self.Bt, self.C, self.ws, flags)
 
+    def gemm_fault(self, i, j, bit, flags=0):
+        gemm_fault(self.p, self.A, self.Bt, self.C, self.ws, i, j, bit, flags)
+
     def verify(self, known=None) -> abft_report:
         import torch
         verify(self.p, self.C, self.ws, known=known, host_out=self.rep_host)
@@ -479,11 +501,12 @@ def wworkspace_size(wp) -> int:
 
 
 def wsetup(wp, ws):
-    return _check("abft_wsetup", lib().abft_wsetup(C.byref(wp), _ptr(ws)))
+    return _check("abft_wsetup", lib().abft_wsetup(C.byref(wp), _ptr(ws), _nbytes(ws)))
 
 
 def wencode(wp, A_f, B_f, ws, stream=None):
-    return _check("abft_wencode", lib().abft_wencode(C.byref(wp), _ptr(A_f), _ptr(B_f), _ptr(ws), _stream(stream)))
+    return _check("abft_wencode", lib().abft_wencode(C.byref(wp), _ptr(A_f), _ptr(B_f), _ptr(ws), _nbytes(ws),
+                                                     _stream(stream)))
 
 
 def wgemm(wp, A_f, B_f, C_f, stream=None):
@@ -493,7 +516,8 @@ def wgemm(wp, A_f, B_f, C_f, stream=None):
 def wverify(wp, C_f, ws, known=None, host_out=None, stream=None):
     arr, nk = _rects(known)
     hp = C.c_void_p(host_out.data_ptr()) if host_out is not None else None
-    return _check("abft_wverify", lib().abft_wverify(C.byref(wp), _ptr(C_f), arr, nk, _ptr(ws), hp, _stream(stream)))
+    return _check("abft_wverify", lib().abft_wverify(C.byref(wp), _ptr(C_f), arr, nk, _ptr(ws), _nbytes(ws), hp,
+                                                     _stream(stream)))
 
 
 def new_wreport_buffer():
@@ -517,14 +541,14 @@ def wlocate(wp, rep: abft_wreport, max_out=ABFT_MAX_FLAGS):
 def wcorrect(wp, C_f, locs, ws, stream=None):
     arr = (abft_location * max(1, len(locs)))(*locs)
     return _check("abft_wcorrect", lib().abft_wcorrect(C.byref(wp), _ptr(C_f), arr, len(locs), _ptr(ws),
-                                                       _stream(stream)))
+                                                       _nbytes(ws), _stream(stream)))
 
 
 def wrecover(wp, C_f, direction, blocks, lo, length, ws, stream=None):
     blocks = list(blocks)
     arr = (C.c_int32 * max(1, len(blocks)))(*blocks)
     return _check("abft_wrecover", lib().abft_wrecover(C.byref(wp), _ptr(C_f), direction, arr, len(blocks), lo,
-                                                       length, _ptr(ws), _stream(stream)))
+                                                       length, _ptr(ws), _nbytes(ws), _stream(stream)))
 
 
 class WProtected:

@@ -75,6 +75,7 @@ WsLayout ws_layout(const abft_problem *p) {
     const int64_t tm = (g.m + kMinTileEdge - 1) / kMinTileEdge, tn = (g.n + kMinTileEdge - 1) / kMinTileEdge;
     L.fused_c = take(fused ? sizeof(double) * tm * g.n : 8);
     L.fused_r = take(fused ? sizeof(double) * tn * g.m : 8);
+    L.fused_tag = take(sizeof(uint64_t));
     L.chain_a = take(sizeof(double) * g.br);
     L.chain_w = take(sizeof(double) * g.N);
     L.chain_cs = take(p->dtype == ABFT_F64 ? sizeof(double) * g.br * g.k : 8);
@@ -128,6 +129,12 @@ static int check_problem(const abft_problem *p) {
 }
 
 static bool aligned16(const void *q) { return ((uintptr_t)q & 15u) == 0; }
+
+// A workspace must be present and at least the problem's workspace size.
+static int check_ws(const abft_problem *p, const void *ws, size_t ws_bytes) {
+    if (!ws || ws_bytes < ws_layout(p).total) return ABFT_E_WORKSPACE;
+    return ABFT_OK;
+}
 
 static int check_operands(const abft_problem *p, const void *A_f, const void *B_f) {
     size_t es = dtype_size(p->dtype);
@@ -250,16 +257,16 @@ size_t abft_workspace_size(const abft_problem *p) {
     return ws_layout(p).total;
 }
 
-int abft_encode(const abft_problem *p, void *A_f, void *B_f, void *ws, void *stream) {
+int abft_encode(const abft_problem *p, void *A_f, void *B_f, void *ws, size_t ws_bytes, void *stream) {
     int st = check_problem(p);
     if (st) return st;
     if ((st = check_operands(p, A_f, B_f))) return st;
-    if (!ws) return ABFT_E_WORKSPACE;
+    if ((st = check_ws(p, ws, ws_bytes))) return st;
     return launch_encode(p, A_f, B_f, (char *)ws, (hipStream_t)stream);
 }
 
-int abft_encode_chained(const abft_problem *p, const void *A_f, void *B_f, void *ws, const abft_problem *prev,
-                        const void *ws_prev, void *stream) {
+int abft_encode_chained(const abft_problem *p, const void *A_f, void *B_f, void *ws, size_t ws_bytes,
+                        const abft_problem *prev, const void *ws_prev, size_t ws_prev_bytes, void *stream) {
     int st = check_problem(p);
     if (st) return st;
     if ((st = check_problem(prev))) return st;
@@ -268,12 +275,13 @@ int abft_encode_chained(const abft_problem *p, const void *A_f, void *B_f, void 
     if (p->tau_mode != ABFT_TAU_DET && p->tau_mode != ABFT_TAU_EXACT) return ABFT_E_UNSUPPORTED;
     if (p->m != prev->m || p->br != prev->br || p->k != prev->n || p->lda != prev->ldc) return ABFT_E_ARG;
     if ((st = check_operands(p, A_f, B_f))) return st;
-    if (!ws || !ws_prev) return ABFT_E_WORKSPACE;
+    if ((st = check_ws(p, ws, ws_bytes)) || (st = check_ws(prev, ws_prev, ws_prev_bytes))) return st;
     const double cc_prev = p->tau_mode == ABFT_TAU_DET ? tau_coef(prev).cc : 0.0;
     return launch_encode_chained(p, A_f, B_f, (char *)ws, prev, (const char *)ws_prev, cc_prev, (hipStream_t)stream);
 }
 
-int abft_quantize(const abft_problem *p, int which, const float *X, int64_t ldx, void *dst, void *ws, void *stream) {
+int abft_quantize(const abft_problem *p, int which, const float *X, int64_t ldx, void *dst, void *ws, size_t ws_bytes,
+                  void *stream) {
     int st = check_problem(p);
     if (st) return st;
     if (!cs_in_ws(p->dtype)) return ABFT_E_ARG;
@@ -283,12 +291,12 @@ int abft_quantize(const abft_problem *p, int which, const float *X, int64_t ldx,
     int64_t ldd = which == 0 ? p->lda : p->ldb;
     size_t es = dtype_size(p->dtype);
     if (ldd < p->k || (ldd * es) % 16 || (p->k * es) % 16) return ABFT_E_ARG;
-    if (!ws) return ABFT_E_WORKSPACE;
+    if ((st = check_ws(p, ws, ws_bytes))) return st;
     return launch_quantize(p, which, X, ldx, dst, (char *)ws, (hipStream_t)stream);
 }
 
 int abft_quantize_encode(const abft_problem *p, const float *A32, int64_t lda32, const float *B32, int64_t ldb32,
-                         void *A_f, void *B_f, void *ws, void *stream) {
+                         void *A_f, void *B_f, void *ws, size_t ws_bytes, void *stream) {
     int st = check_problem(p);
     if (st) return st;
     if (!cs_in_ws(p->dtype)) return ABFT_E_UNSUPPORTED;
@@ -297,12 +305,12 @@ int abft_quantize_encode(const abft_problem *p, const float *A32, int64_t lda32,
     if ((st = check_operands(p, A_f, B_f))) return st;
     const size_t es = dtype_size(p->dtype);
     if ((p->k * es) % 16) return ABFT_E_ARG;
-    if (!ws) return ABFT_E_WORKSPACE;
+    if ((st = check_ws(p, ws, ws_bytes))) return st;
     return launch_quantize_encode(p, A32, lda32, B32, ldb32, A_f, B_f, (char *)ws, (hipStream_t)stream);
 }
 
-int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, void *ws, uint32_t flags,
-              void *stream) {
+int abft_gemm_fault(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, void *ws, size_t ws_bytes,
+                    uint32_t flags, const abft_fault *fault, void *stream) {
     int st = check_problem(p);
     if (st) return st;
     if (flags & ~(ABFT_PLAIN | ABFT_FUSED)) return ABFT_E_ARG;
@@ -311,10 +319,20 @@ int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f
         if (p->br != 1 || p->bc != 1) return ABFT_E_UNSUPPORTED;
         if (!ws) return ABFT_E_WORKSPACE;
     }
+    if (fault) {
+        if (fault->i < 0 || fault->i >= p->m || fault->j < 0 || fault->j >= p->n) return ABFT_E_ARG;
+        if (fault->bit < 0 || fault->bit >= (p->dtype == ABFT_F64 ? 64 : 32)) return ABFT_E_ARG;
+    }
     if ((st = check_operands(p, A_f, B_f))) return st;
     if ((st = check_c(p, C_f, flags & ABFT_PLAIN))) return st;
     if (!ws && (p->dtype == ABFT_FP8_E4M3 || (p->dtype == ABFT_BF16 && !(flags & ABFT_PLAIN)))) return ABFT_E_WORKSPACE;
-    return launch_gemm(p, A_f, B_f, C_f, flags, ws, (hipStream_t)stream);
+    if (ws && (st = check_ws(p, ws, ws_bytes))) return st;
+    return launch_gemm(p, A_f, B_f, C_f, flags, ws, fault, (hipStream_t)stream);
+}
+
+int abft_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, void *ws, size_t ws_bytes,
+              uint32_t flags, void *stream) {
+    return abft_gemm_fault(p, A_f, B_f, C_f, ws, ws_bytes, flags, nullptr, stream);
 }
 
 int abft_describe_gemm(const abft_problem *p, uint32_t flags, char *buf, size_t len) {
@@ -339,15 +357,16 @@ int abft_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, voi
     return launch_gemm_panel(p, A_f, B_f, C_f, k0, k1, flags, (hipStream_t)stream);
 }
 
-int abft_verify_fused(const abft_problem *p, const void *C_f, void *ws, abft_report *host_out, void *stream) {
+int abft_verify_fused(const abft_problem *p, const void *C_f, void *ws, size_t ws_bytes, abft_report *host_out,
+                      void *stream) {
     int st = check_problem(p);
     if (st) return st;
     if ((st = check_c(p, C_f, false))) return st;
-    if (!ws) return ABFT_E_WORKSPACE;
+    if ((st = check_ws(p, ws, ws_bytes))) return st;
     if (p->br != 1 || p->bc != 1) return ABFT_E_UNSUPPORTED;
     int64_t tm = 0, tn = 0;
-    if (!fused_grid(ws, p, &tm, &tn)) return ABFT_E_ARG;
-    if ((st = launch_verify_fused(p, C_f, (char *)ws, tm, tn, (hipStream_t)stream))) return st;
+    const uint64_t key = fused_key(p, C_f, &tm, &tn);
+    if ((st = launch_verify_fused(p, C_f, (char *)ws, tm, tn, key, (hipStream_t)stream))) return st;
     if (host_out) {
         WsLayout L = ws_layout(p);
         ABFT_HIP(hipMemcpyAsync(host_out, (char *)ws + L.report, sizeof(abft_report), hipMemcpyDeviceToHost,
@@ -356,22 +375,12 @@ int abft_verify_fused(const abft_problem *p, const void *C_f, void *ws, abft_rep
     return ABFT_OK;
 }
 
-int abft_arm_accumulator_flip(const abft_problem *p, void *ws, int64_t i, int64_t j, int bit) {
-    int st = check_problem(p);
-    if (st) return st;
-    if (!ws) return ABFT_E_WORKSPACE;
-    if (i < 0 || i >= p->m || j < 0 || j >= p->n) return ABFT_E_ARG;
-    if (bit < 0 || bit >= (p->dtype == ABFT_F64 ? 64 : 32)) return ABFT_E_ARG;
-    arm_accumulator_flip(ws, i, j, bit);
-    return ABFT_OK;
-}
-
 int abft_verify(const abft_problem *p, const void *C_f, const abft_rect *known, int n_known, void *ws,
-                abft_report *host_out, void *stream) {
+                size_t ws_bytes, abft_report *host_out, void *stream) {
     int st = check_problem(p);
     if (st) return st;
     if ((st = check_c(p, C_f, false))) return st;
-    if (!ws) return ABFT_E_WORKSPACE;
+    if ((st = check_ws(p, ws, ws_bytes))) return st;
     Geom g = geom_of(p);
     Erasures er;
     if ((st = to_erasures(g, known, n_known, &er))) return st;
@@ -464,8 +473,9 @@ const char *abft_status_string(int s) {
     case ABFT_E_HIP: return "HIP runtime error";
     case ABFT_E_UNCORRECTABLE: return "uncorrectable: the failed relations do not name one element";
     case ABFT_E_UNRECOVERABLE: return "unrecoverable: more unknowns than checksum relations";
-    case ABFT_E_WORKSPACE: return "workspace missing";
+    case ABFT_E_WORKSPACE: return "workspace missing or too small";
     case ABFT_E_UNSUPPORTED: return "unsupported combination";
+    case ABFT_E_STALE: return "the fused partial sums in the workspace belong to another product";
     default: return "unknown status";
     }
 }

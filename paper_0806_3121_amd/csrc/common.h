@@ -193,6 +193,7 @@ struct WsLayout {
     size_t chain_cs;                 // chained products: the recomputed checksum rows (discarded; br x k double)
     size_t rowpart;                  // fused row statistics: per-row partial sums
     size_t vpart_c, vpart_r;         // one-pass re-read verification for b = 1: tile partial sums (double)
+    size_t fused_tag;                // owner of the fused partials: fused_key() of the last fused product, else 0
     size_t report;                   // abft_report
     size_t total;
     size_t partial_bytes;
@@ -232,17 +233,29 @@ int launch_skinny_f64(const double *A, int64_t lda, const double *Bt, int64_t ld
 int launch_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, int64_t k0, int64_t k1,
                       uint32_t flags, hipStream_t s);
 int describe_gemm(const abft_problem *p, uint32_t flags, char *buf, size_t len);
+// fault: a test-only accumulator flip (null: none).
 int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, void *ws,
-                hipStream_t s);
+                const abft_fault *fault, hipStream_t s);
 int launch_verify(const abft_problem *p, const void *C_f, const Erasures &er, char *ws, hipStream_t s);
+// The verification's scratch (everything it writes): the device report, the
+// tile partial sums of the one-pass b = 1 check and the two-level reduction
+// partials.  launch_verify takes them from ws; launch_verify_scratch from
+// anywhere, reading only the threshold statistics from ws.
+struct VerifyScratch {
+    abft_report *rep;
+    double *vpart_c, *vpart_r, *partial;
+};
+int launch_verify_scratch(const abft_problem *p, const void *C_f, const Erasures &er, const char *ws,
+                          const VerifyScratch &sc, hipStream_t s);
+size_t verify_scratch_layout(const abft_problem *p, const void *C_f, char *base, VerifyScratch *sc);
 int launch_encode_chained(const abft_problem *p, const void *A_f, void *B_f, char *ws, const abft_problem *prev,
                           const char *ws_prev, double cc_prev, hipStream_t s);
 int launch_verify_fused(const abft_problem *p, const void *C_f, char *ws, int64_t tiles_m, int64_t tiles_n,
-                        hipStream_t s);
-// Fused partial sums of the last ABFT_FUSED product into ws (tile grid), and
-// the one-shot accumulator flip armed for the next product into ws.
-bool fused_grid(const void *ws, const abft_problem *p, int64_t *tiles_m, int64_t *tiles_n);
-void arm_accumulator_flip(const void *ws, int64_t i, int64_t j, int bit);
+                        uint64_t key, hipStream_t s);
+// The tile grid of the fused partials an ABFT_FUSED product of p writes, and
+// the owner tag it stores in ws: a nonzero hash of the problem, the tile grid
+// and C_f.
+uint64_t fused_key(const abft_problem *p, const void *C_f, int64_t *tiles_m, int64_t *tiles_n);
 // Smallest tile edge of every product kernel: bounds the tile rows / columns of the fused partials.
 constexpr int64_t kMinTileEdge = 96;
 // Row tile of the one-pass b = 1 re-read verification (column sums per tile of this many rows); its row

@@ -16,8 +16,6 @@
 #include "sliver_kernel.h"
 
 #include <cstdio>
-#include <mutex>
-#include <unordered_map>
 
 namespace abft {
 
@@ -260,40 +258,34 @@ int describe_gemm(const abft_problem *p, uint32_t flags, char *buf, size_t len) 
     return (n < 0 || (size_t)n >= len) ? ABFT_E_ARG : ABFT_OK;
 }
 
-// Host registry per workspace: the one-shot accumulator flip armed for the
-// next product, and the tile grid of the last product's fused partials.
-namespace {
-struct EpiState {
-    int64_t fi = 0, fj = 0;
-    int fbit = -1;
-    bool fused = false;
-    int64_t tiles_m = 0, tiles_n = 0;
-    abft_problem prob{};             // the problem whose fused product wrote the partials
-};
-std::mutex g_epi_mu;
-std::unordered_map<const void *, EpiState> g_epi;
-}  // namespace
-
-void arm_accumulator_flip(const void *ws, int64_t i, int64_t j, int bit) {
-    std::lock_guard<std::mutex> lk(g_epi_mu);
-    EpiState &st = g_epi[ws];
-    st.fi = i; st.fj = j; st.fbit = bit;
+// Owner tag of the fused partial sums (the stateless stand-in for "the last
+// product on this workspace"): a 64-bit mix of the problem, its tile grid and
+// C_f, never 0 (0 marks "no valid partials").
+static uint64_t mix64(uint64_t h, uint64_t v) {
+    h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+    h ^= h >> 31;
+    h *= 0xBF58476D1CE4E5B9ull;
+    return h ^ (h >> 29);
 }
 
-bool fused_grid(const void *ws, const abft_problem *p, int64_t *tiles_m, int64_t *tiles_n) {
-    std::lock_guard<std::mutex> lk(g_epi_mu);
-    auto it = g_epi.find(ws);
-    if (it == g_epi.end() || !it->second.fused) return false;
-    // the partials belong to the last fused product on this workspace: the same problem only (a workspace
-    // reused for another problem, or freed and reallocated, must not be read with the old tile grid)
-    const abft_problem &q = it->second.prob;
-    if (q.dtype != p->dtype || q.m != p->m || q.n != p->n || q.k != p->k || q.br != p->br || q.bc != p->bc ||
-        q.ldc != p->ldc)
-        return false;
-    *tiles_m = it->second.tiles_m;
-    *tiles_n = it->second.tiles_n;
-    return true;
+uint64_t fused_key(const abft_problem *p, const void *C_f, int64_t *tiles_m, int64_t *tiles_n) {
+    const Geom g = geom_of(p);
+    const bool lowp = p->dtype == ABFT_BF16 || p->dtype == ABFT_FP8_E4M3;
+    // b = 1: the carried row and column are slivers, the main product covers m x n
+    const MainPick pk = lowp ? pick_main_lowp(p->dtype == ABFT_BF16 ? 2 : 1, g.m, g.n, g.k)
+                             : (p->dtype == ABFT_F64 ? pick_main((const double *)nullptr, g.m, g.n, g.k)
+                                                     : pick_main((const float *)nullptr, g.m, g.n, g.k));
+    *tiles_m = (g.m + pk.t->bm - 1) / pk.t->bm;
+    *tiles_n = (g.n + pk.t->bn - 1) / pk.t->bn;
+    uint64_t h = 0x6A09E667F3BCC908ull;
+    for (uint64_t v : {(uint64_t)p->dtype, (uint64_t)g.m, (uint64_t)g.n, (uint64_t)g.k, (uint64_t)g.br,
+                       (uint64_t)g.bc, (uint64_t)p->ldc, (uint64_t)(uintptr_t)C_f, (uint64_t)*tiles_m,
+                       (uint64_t)*tiles_n})
+        h = mix64(h, v);
+    return h ? h : 1;
 }
+
+__global__ void k_store_tag(uint64_t *dst, uint64_t v) { *dst = v; }
 
 static int product_with_extras(const abft_problem *p, const Geom &g, const void *A_f, const void *B_f, void *C_f,
                                bool plain, void *ws, const float *Acs, const float *Bcs, const int *scale,
@@ -317,48 +309,40 @@ static int product_with_extras(const abft_problem *p, const Geom &g, const void 
 }
 
 int launch_gemm(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, uint32_t flags, void *ws,
-                hipStream_t s) {
+                const abft_fault *fault, hipStream_t s) {
     Geom g = geom_of(p);
-    const bool plain = flags & ABFT_PLAIN;
-    // epilogue extras: an armed accumulator flip (consumed here) and the fused partial sums
+    const bool plain = flags & ABFT_PLAIN, fused = flags & ABFT_FUSED;
+    // epilogue extras: the test-only accumulator flip and the fused partial sums
     EpiArgs e = epi_none();
-    bool extras = false;
-    if (ws) {
-        std::lock_guard<std::mutex> lk(g_epi_mu);
-        auto it = g_epi.find(ws);
-        if (it != g_epi.end()) {
-            if (it->second.fbit >= 0) {
-                e.fi = it->second.fi; e.fj = it->second.fj; e.fbit = it->second.fbit;
-                it->second.fbit = -1;
-                extras = true;
-            }
-            it->second.fused = false;
-        }
+    if (fault) {
+        e.fi = fault->i; e.fj = fault->j; e.fbit = fault->bit;
     }
-    if (flags & ABFT_FUSED) {
-        WsLayout L = ws_layout(p);
+    WsLayout L = ws_layout(p);
+    if (fused) {
         e.pc = (double *)((char *)ws + L.fused_c);
         e.pr = (double *)((char *)ws + L.fused_r);
         e.ldpc = g.n;
         e.ldpr = g.m;
-        extras = true;
     }
-    WsLayout L = ws_layout(p);
     const char *wsc = (const char *)ws;
     const bool lowp = p->dtype == ABFT_BF16 || p->dtype == ABFT_FP8_E4M3;
     const float *Acs = (lowp && ws) ? (const float *)(wsc + L.acs) : nullptr;
     const float *Bcs = (lowp && ws) ? (const float *)(wsc + L.bcs) : nullptr;
     const int *scale = (p->dtype == ABFT_FP8_E4M3 && ws) ? (const int *)(wsc + L.scale) : nullptr;
-    int st = product_with_extras(p, g, A_f, B_f, C_f, plain, ws, Acs, Bcs, scale, extras ? &e : nullptr, s);
-    if (st == ABFT_OK && (flags & ABFT_FUSED)) {
-        std::lock_guard<std::mutex> lk(g_epi_mu);
-        EpiState &es = g_epi[ws];
-        es.fused = true;
-        es.tiles_m = e.tiles_m;
-        es.tiles_n = e.tiles_n;
-        es.prob = *p;
+    int st = product_with_extras(p, g, A_f, B_f, C_f, plain, ws, Acs, Bcs, scale, (fault || fused) ? &e : nullptr, s);
+    if (st) return st;
+    if (ws) {
+        // record in ws who owns the fused partials now: this product (fused) or nobody
+        uint64_t key = 0;
+        if (fused) {
+            int64_t tm = 0, tn = 0;
+            key = fused_key(p, C_f, &tm, &tn);
+            if (tm != e.tiles_m || tn != e.tiles_n) key = 0;   // a grid the fused verification would not read
+        }
+        k_store_tag<<<1, 1, 0, s>>>((uint64_t *)((char *)ws + L.fused_tag), key);
+        ABFT_LAUNCHED();
     }
-    return st;
+    return ABFT_OK;
 }
 
 }  // namespace abft

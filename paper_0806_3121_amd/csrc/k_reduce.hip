@@ -74,6 +74,17 @@ __global__ void k_report_init(abft_report *rep) {
     for (int q = threadIdx.x; q < nw; q += blockDim.x) w[q] = 0;
 }
 
+// Report of a fused verification: cleared, with status ABFT_E_STALE when the
+// owner tag in ws does not name this problem and C_f (the verify kernels then
+// record nothing).
+__global__ void k_report_init_tag(abft_report *rep, const uint64_t *tag, uint64_t key) {
+    uint64_t *w = (uint64_t *)rep;
+    const int nw = sizeof(abft_report) / 8;
+    for (int q = threadIdx.x; q < nw; q += blockDim.x) w[q] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0 && *tag != key) rep->status = ABFT_E_STALE;
+}
+
 // ------------------------------------------------------------------ encode
 // Checksum rows of an operand X (R data rows, row-major, ld; the B operand is
 // passed as its transpose, so both sides are the same row-group sum):
@@ -683,6 +694,8 @@ struct VerifyArgs {
     const int *scale_exp;           // FP8: statistics are in the scaled domain, C is not
     abft_report *rep;
     Erasures er;
+    const uint64_t *tag;            // fused verification: the owner tag the product wrote into ws (null: none)
+    uint64_t key;                   // and the value it must hold for this problem and C_f
 };
 
 // det:  tau_c = cc ||(C_C^T|A|)[r,:]||_2 ||B_f[:,j]||_2
@@ -1046,6 +1059,7 @@ __global__ __launch_bounds__(kThreads) void k_vpartials(const T *C, int64_t ldc,
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_vfused(const T *C, VerifyArgs a, const double *pc, const double *pr,
                                                      int64_t tiles_m, int64_t tiles_n) {
+    if (a.tag && *a.tag != a.key) return;     // partials of another product: nothing is recorded
     double rc = 0.0, rr = 0.0;
     unsigned long long ec = 0, er = 0;
     const int64_t total = a.n + a.m;
@@ -1077,6 +1091,7 @@ __global__ __launch_bounds__(kThreads) void k_vfused(const T *C, VerifyArgs a, c
 // carried row C_f[m, 0:n] against the corner.  Fixed-order block reductions.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_vfused_edges(const T *C, VerifyArgs a) {
+    if (a.tag && *a.tag != a.key) return;
     __shared__ double sh[kThreads];
     const bool col = blockIdx.x == 0;
     const int64_t len = col ? a.m : a.n;
@@ -1106,11 +1121,12 @@ __global__ __launch_bounds__(kThreads) void k_vfused_edges(const T *C, VerifyArg
 }
 
 template <typename T>
-static int verify_typed(const abft_problem *p, const T *C, const Erasures &er, char *ws, hipStream_t s) {
+static int verify_typed(const abft_problem *p, const T *C, const Erasures &er, const char *ws, const VerifyScratch &sc,
+                        hipStream_t s) {
     Geom g = geom_of(p);
     WsLayout L = ws_layout(p);
     TauCoef tc = tau_coef(p);
-    VerifyArgs a;
+    VerifyArgs a{};
     a.m = g.m; a.n = g.n; a.br = g.br; a.bc = g.bc; a.S = g.S; a.Gr = g.Gr; a.Gc = g.Gc; a.M = g.M; a.N = g.N;
     a.ldc = p->ldc;
     a.mode = tc.mode; a.cc = tc.cc; a.cr = tc.cr;
@@ -1120,7 +1136,7 @@ static int verify_typed(const abft_problem *p, const T *C, const Erasures &er, c
     a.qr = (const double *)(ws + L.qr); a.qc = (const double *)(ws + L.qc);
     a.nv = (const double *)(ws + L.nv); a.nw = (const double *)(ws + L.nw);
     a.scale_exp = p->dtype == ABFT_FP8_E4M3 ? (const int *)(ws + L.scale) : nullptr;
-    a.rep = (abft_report *)(ws + L.report);
+    a.rep = sc.rep;
     a.er = er;
     k_report_init<<<1, kThreads, 0, s>>>(a.rep);
     auto blocks = [](int64_t work) { return (unsigned)std::min<int64_t>((work + kThreads - 1) / kThreads, 4096); };
@@ -1149,7 +1165,7 @@ static int verify_typed(const abft_problem *p, const T *C, const Erasures &er, c
     }
     // b = 1: tile partials in one pass, then the relations from them
     if (g.br == 1 && g.bc == 1 && vec) {
-        double *pc = (double *)(ws + L.vpart_c), *pr = (double *)(ws + L.vpart_r);
+        double *pc = sc.vpart_c, *pr = sc.vpart_r;
         const int64_t tiles_m = (g.m + kPartRows - 1) / kPartRows, tiles_n = (g.n + kWave * VV - 1) / (kWave * VV);
         k_vpartials<T, VV><<<(unsigned)std::min<int64_t>(tiles_m * tiles_n, 8192), kThreads, 0, s>>>(C, p->ldc, g.m,
                                                                                                    g.n, pc, pr);
@@ -1165,7 +1181,7 @@ static int verify_typed(const abft_problem *p, const T *C, const Erasures &er, c
     } else {
         int64_t chunk = (g.Gr + P - 1) / P;
         P = (g.Gr + chunk - 1) / chunk;
-        double *part = (double *)(ws + L.partial);
+        double *part = sc.partial;
         if (vec) k_vcol_partial<T, VV><<<blocks(P * g.br * ((g.N + VV - 1) / VV)), kThreads, 0, s>>>(C, a, P, chunk, part);
         else k_vcol_partial<T, 1><<<blocks(P * g.br * g.N), kThreads, 0, s>>>(C, a, P, chunk, part);
         k_vcol_finish<T><<<blocks(g.br * g.N), kThreads, 0, s>>>(C, a, P, part);
@@ -1182,11 +1198,11 @@ static int verify_typed(const abft_problem *p, const T *C, const Erasures &er, c
 
 template <typename T>
 static int verify_fused_typed(const abft_problem *p, const T *C, char *ws, int64_t tiles_m, int64_t tiles_n,
-                              hipStream_t s) {
+                              uint64_t key, hipStream_t s) {
     Geom g = geom_of(p);
     WsLayout L = ws_layout(p);
     TauCoef tc = tau_coef(p);
-    VerifyArgs a;
+    VerifyArgs a{};
     a.m = g.m; a.n = g.n; a.br = g.br; a.bc = g.bc; a.S = g.S; a.Gr = g.Gr; a.Gc = g.Gc; a.M = g.M; a.N = g.N;
     a.ldc = p->ldc;
     a.mode = tc.mode; a.cc = tc.cc; a.cr = tc.cr;
@@ -1198,7 +1214,9 @@ static int verify_fused_typed(const abft_problem *p, const T *C, char *ws, int64
     a.scale_exp = p->dtype == ABFT_FP8_E4M3 ? (const int *)(ws + L.scale) : nullptr;
     a.rep = (abft_report *)(ws + L.report);
     a.er.n = 0;
-    k_report_init<<<1, kThreads, 0, s>>>(a.rep);
+    a.tag = (const uint64_t *)(ws + L.fused_tag);
+    a.key = key;
+    k_report_init_tag<<<1, kThreads, 0, s>>>(a.rep, a.tag, key);
     const unsigned blocks = (unsigned)std::min<int64_t>((g.n + g.m + kThreads - 1) / kThreads, 4096);
     k_vfused<T><<<blocks, kThreads, 0, s>>>(C, a, (const double *)(ws + L.fused_c), (const double *)(ws + L.fused_r),
                                             tiles_m, tiles_n);
@@ -1208,14 +1226,64 @@ static int verify_fused_typed(const abft_problem *p, const T *C, char *ws, int64
 }
 
 int launch_verify_fused(const abft_problem *p, const void *C_f, char *ws, int64_t tiles_m, int64_t tiles_n,
-                        hipStream_t s) {
-    if (p->dtype == ABFT_F64) return verify_fused_typed<double>(p, (const double *)C_f, ws, tiles_m, tiles_n, s);
-    return verify_fused_typed<float>(p, (const float *)C_f, ws, tiles_m, tiles_n, s);
+                        uint64_t key, hipStream_t s) {
+    if (p->dtype == ABFT_F64) return verify_fused_typed<double>(p, (const double *)C_f, ws, tiles_m, tiles_n, key, s);
+    return verify_fused_typed<float>(p, (const float *)C_f, ws, tiles_m, tiles_n, key, s);
 }
 
 int launch_verify(const abft_problem *p, const void *C_f, const Erasures &er, char *ws, hipStream_t s) {
-    if (p->dtype == ABFT_F64) return verify_typed<double>(p, (const double *)C_f, er, ws, s);
-    return verify_typed<float>(p, (const float *)C_f, er, ws, s);
+    const WsLayout L = ws_layout(p);
+    VerifyScratch sc;
+    sc.rep = (abft_report *)(ws + L.report);
+    sc.vpart_c = (double *)(ws + L.vpart_c);
+    sc.vpart_r = (double *)(ws + L.vpart_r);
+    sc.partial = (double *)(ws + L.partial);
+    return launch_verify_scratch(p, C_f, er, ws, sc, s);
+}
+
+// Bytes of scratch the verification of p on this C_f writes, by the path it
+// takes (as verify_typed decides it), laid out from base (256-byte aligned
+// parts; base may be null to size only).
+size_t verify_scratch_layout(const abft_problem *p, const void *C_f, char *base, VerifyScratch *sc) {
+    const Geom g = geom_of(p);
+    const bool f64 = p->dtype == ABFT_F64;
+    const int64_t VV = f64 ? 2 : 4;
+    const bool vec = ((uintptr_t)C_f % 16 == 0) && (p->ldc % VV == 0);
+    const int64_t V = vec ? VV : 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = (off + bytes + 255) & ~(size_t)255; return o; };
+    const size_t rep = take(sizeof(abft_report));
+    size_t pc = 0, pr = 0, part = 0;
+    bool use_pc = false, use_part = false;
+    const bool block_pass = f64 && vec && g.bc % VV == 0 && g.bc >= 64 && g.Gc <= kBlockPassMaxG &&
+                            g.br * (g.bc / VV) >= 65536;
+    if (!block_pass) {
+        if (g.br == 1 && g.bc == 1 && vec) {
+            const int64_t tiles_m = (g.m + kPartRows - 1) / kPartRows, tiles_n = (g.n + kWave * VV - 1) / (kWave * VV);
+            pc = take(sizeof(double) * tiles_m * g.n);
+            pr = take(sizeof(double) * tiles_n * g.m);
+            use_pc = true;
+        } else {
+            const int64_t P = group_partitions(g.Gr, g.br, (g.N + V - 1) / V);
+            if (P > 1) {
+                part = take(sizeof(double) * P * g.br * g.N);
+                use_part = true;
+            }
+        }
+    }
+    if (sc) {
+        sc->rep = (abft_report *)(base + rep);
+        sc->vpart_c = use_pc ? (double *)(base + pc) : nullptr;
+        sc->vpart_r = use_pc ? (double *)(base + pr) : nullptr;
+        sc->partial = use_part ? (double *)(base + part) : nullptr;
+    }
+    return off;
+}
+
+int launch_verify_scratch(const abft_problem *p, const void *C_f, const Erasures &er, const char *ws,
+                          const VerifyScratch &sc, hipStream_t s) {
+    if (p->dtype == ABFT_F64) return verify_typed<double>(p, (const double *)C_f, er, ws, sc, s);
+    return verify_typed<float>(p, (const float *)C_f, er, ws, sc, s);
 }
 
 }  // namespace abft

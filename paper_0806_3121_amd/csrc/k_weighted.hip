@@ -654,15 +654,21 @@ using namespace abft;
 
 extern "C" {
 
+// A workspace must be present and at least the problem's workspace size.
+static int check_wws(const abft_wproblem *p, const void *ws, size_t ws_bytes) {
+    if (!ws || ws_bytes < wlayout(wgeom(p)).total) return ABFT_E_WORKSPACE;
+    return ABFT_OK;
+}
+
 size_t abft_wworkspace_size(const abft_wproblem *p) {
     if (check_wproblem(p) != ABFT_OK) return 0;
     return wlayout(wgeom(p)).total;
 }
 
-int abft_wsetup(const abft_wproblem *p, void *ws) {
+int abft_wsetup(const abft_wproblem *p, void *ws, size_t ws_bytes) {
     int st = check_wproblem(p);
     if (st) return st;
-    if (!ws) return ABFT_E_WORKSPACE;
+    if ((st = check_wws(p, ws, ws_bytes))) return st;
     const WGeom g = wgeom(p);
     const WLayout L = wlayout(g);
     ABFT_HIP(hipMemcpy((char *)ws + L.wr, p->wr, sizeof(double) * g.fr * g.Gr, hipMemcpyHostToDevice));
@@ -670,11 +676,11 @@ int abft_wsetup(const abft_wproblem *p, void *ws) {
     return ABFT_OK;
 }
 
-int abft_wencode(const abft_wproblem *p, void *A_f, void *B_f, void *ws, void *stream) {
+int abft_wencode(const abft_wproblem *p, void *A_f, void *B_f, void *ws, size_t ws_bytes, void *stream) {
     int st = check_wproblem(p);
     if (st) return st;
     if (!A_f || !B_f || !aligned16(A_f) || !aligned16(B_f)) return ABFT_E_ARG;
-    if (!ws) return ABFT_E_WORKSPACE;
+    if ((st = check_wws(p, ws, ws_bytes))) return st;
     const WGeom g = wgeom(p);
     const WLayout L = wlayout(g);
     hipStream_t s = (hipStream_t)stream;
@@ -708,11 +714,11 @@ int abft_wgemm(const abft_wproblem *p, const void *A_f, const void *B_f, void *C
 }
 
 int abft_wverify(const abft_wproblem *p, const void *C_f, const abft_rect *known, int n_known, void *ws,
-                 abft_wreport *host_out, void *stream) {
+                 size_t ws_bytes, abft_wreport *host_out, void *stream) {
     int st = check_wproblem(p);
     if (st) return st;
     if (!C_f || ((uintptr_t)C_f & 7u)) return ABFT_E_ARG;
-    if (!ws) return ABFT_E_WORKSPACE;
+    if ((st = check_wws(p, ws, ws_bytes))) return st;
     const WGeom g = wgeom(p);
     const WLayout L = wlayout(g);
     hipStream_t s = (hipStream_t)stream;
@@ -808,11 +814,12 @@ int abft_wlocate(const abft_wproblem *p, const abft_wreport *rep, abft_location 
     return multi ? ABFT_E_UNCORRECTABLE : ABFT_OK;
 }
 
-int abft_wcorrect(const abft_wproblem *p, void *C_f, const abft_location *locs, int n, void *ws, void *stream) {
+int abft_wcorrect(const abft_wproblem *p, void *C_f, const abft_location *locs, int n, void *ws, size_t ws_bytes,
+                  void *stream) {
     int st = check_wproblem(p);
     if (st) return st;
     if (!C_f || n < 0 || (n > 0 && !locs)) return ABFT_E_ARG;
-    if (!ws) return ABFT_E_WORKSPACE;
+    if ((st = check_wws(p, ws, ws_bytes))) return st;
     const WGeom g = wgeom(p);
     const WLayout L = wlayout(g);
     for (int q = 0; q < n; ++q) {
@@ -838,12 +845,12 @@ int abft_wcorrect(const abft_wproblem *p, void *C_f, const abft_location *locs, 
 }
 
 int abft_wrecover(const abft_wproblem *p, void *C_f, int dir, const int32_t *blocks, int n_blocks, int64_t lo,
-                  int64_t len, void *ws, void *stream) {
+                  int64_t len, void *ws, size_t ws_bytes, void *stream) {
     int st = check_wproblem(p);
     if (st) return st;
     if (!C_f || n_blocks < 0 || (n_blocks > 0 && !blocks)) return ABFT_E_ARG;
     if (dir != ABFT_DIR_COL && dir != ABFT_DIR_ROW) return ABFT_E_ARG;
-    if (!ws) return ABFT_E_WORKSPACE;
+    if ((st = check_wws(p, ws, ws_bytes))) return st;
     const WGeom g = wgeom(p);
     const WLayout L = wlayout(g);
     const int64_t lines = dir == ABFT_DIR_COL ? g.N : g.M;

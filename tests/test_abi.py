@@ -31,8 +31,9 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_header_layout():
     assert C.sizeof(abft.abft_problem) == 4 + 4 + 8 * 8 + 8 * 2
     assert C.sizeof(abft.abft_flag) == 32
-    assert C.sizeof(abft.abft_report) == 8 * 5 + 8 * 2 + 2 * 64 * 32
+    assert C.sizeof(abft.abft_report) == 8 * 6 + 8 * 2 + 2 * 64 * 32
     assert C.sizeof(abft.abft_location) == 24
+    assert C.sizeof(abft.abft_fault) == 24
 
 
 def _call(name, *args):
@@ -46,21 +47,62 @@ def test_bad_problem_rejected_before_launch(field, value):
     setattr(p, field, value)
     fake = C.c_void_p(256)     # never dereferenced: the checks fail first
     assert abft.workspace_size(p) == 0
-    assert _call("abft_gemm", C.byref(p), fake, fake, fake, None, 0, NULL_STREAM) == abft.ABFT_E_ARG
+    assert _call("abft_gemm", C.byref(p), fake, fake, fake, None, 0, 0, NULL_STREAM) == abft.ABFT_E_ARG
+
+
+BIG = 1 << 40      # a workspace size no problem here exceeds (the pointers are never dereferenced)
 
 
 def test_layout_and_alignment_rejected():
     fake = C.c_void_p(256)
     p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1, lda=255)
-    assert _call("abft_encode", C.byref(p), fake, fake, fake, NULL_STREAM) == abft.ABFT_E_ARG
+    assert _call("abft_encode", C.byref(p), fake, fake, fake, BIG, NULL_STREAM) == abft.ABFT_E_ARG
     p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1, ldc=256)          # < n + bc
-    assert _call("abft_gemm", C.byref(p), fake, fake, fake, None, 0, NULL_STREAM) == abft.ABFT_E_ARG
+    assert _call("abft_gemm", C.byref(p), fake, fake, fake, None, 0, 0, NULL_STREAM) == abft.ABFT_E_ARG
     p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1)
-    assert _call("abft_gemm", C.byref(p), C.c_void_p(8), fake, fake, None, 0, NULL_STREAM) == abft.ABFT_E_ARG
-    assert _call("abft_gemm", C.byref(p), fake, fake, fake, None, 8, NULL_STREAM) == abft.ABFT_E_ARG   # unknown flag
-    assert _call("abft_encode", C.byref(p), fake, fake, None, NULL_STREAM) == abft.ABFT_E_WORKSPACE
+    assert _call("abft_gemm", C.byref(p), C.c_void_p(8), fake, fake, None, 0, 0, NULL_STREAM) == abft.ABFT_E_ARG
+    assert _call("abft_gemm", C.byref(p), fake, fake, fake, None, 0, 8, NULL_STREAM) == abft.ABFT_E_ARG  # unknown flag
+    assert _call("abft_encode", C.byref(p), fake, fake, None, BIG, NULL_STREAM) == abft.ABFT_E_WORKSPACE
     p = abft.problem(abft.ABFT_F64, 256, 256, 251, 1, 1, lda=252, ldb=252)  # k*8 not a multiple of 16
-    assert _call("abft_encode", C.byref(p), fake, fake, fake, NULL_STREAM) == abft.ABFT_E_ARG
+    assert _call("abft_encode", C.byref(p), fake, fake, fake, BIG, NULL_STREAM) == abft.ABFT_E_ARG
+
+
+@pytest.mark.parametrize("dt,b", [(abft.ABFT_F64, 1), (abft.ABFT_F64, 64), (abft.ABFT_F32, 1), (abft.ABFT_BF16, 1),
+                                  (abft.ABFT_FP8_E4M3, 4)])
+def test_short_workspace_rejected_before_launch(dt, b):
+    """Every call that takes a workspace refuses one smaller than
+    abft_workspace_size (or none) before anything is queued."""
+    fake = C.c_void_p(256)
+    p = abft.problem(dt, 256, 256, 256, b, b)
+    need = abft.workspace_size(p)
+    assert need > 0
+    rect = abft.abft_rect(0, 0, 1, 1)
+    for short in (need - 1, 0):
+        ws = None if short == 0 else fake
+        calls = {
+            "encode": lambda: _call("abft_encode", C.byref(p), fake, fake, ws, short, NULL_STREAM),
+            "gemm": lambda: _call("abft_gemm", C.byref(p), fake, fake, fake, ws, short, 0, NULL_STREAM),
+            "verify": lambda: _call("abft_verify", C.byref(p), fake, C.byref(rect), 0, ws, short, None, NULL_STREAM),
+        }
+        if b == 1:
+            calls["gemm_fused"] = lambda: _call("abft_gemm", C.byref(p), fake, fake, fake, ws, short, abft.ABFT_FUSED,
+                                                NULL_STREAM)
+            calls["verify_fused"] = lambda: _call("abft_verify_fused", C.byref(p), fake, ws, short, None, NULL_STREAM)
+        if dt in (abft.ABFT_BF16, abft.ABFT_FP8_E4M3):
+            calls["quantize"] = lambda: _call("abft_quantize", C.byref(p), 0, fake, 256, fake, ws, short, NULL_STREAM)
+            calls["quantize_encode"] = lambda: _call("abft_quantize_encode", C.byref(p), fake, 256, fake, 256, fake,
+                                                     fake, ws, short, NULL_STREAM)
+        for name, call in calls.items():
+            if dt in (abft.ABFT_F64, abft.ABFT_F32) and name == "gemm" and ws is None:
+                continue                                          # optional for these types: nothing to refuse
+            assert call() == abft.ABFT_E_WORKSPACE, (name, short)
+    if dt == abft.ABFT_F64:
+        prev = abft.problem(abft.ABFT_F64, 256, 256, 256, b, b, ldc=320)      # the next A_f is this C_f
+        q = abft.problem(abft.ABFT_F64, 256, 128, 256, b, b, lda=320)
+        chained = lambda wb, pb: _call("abft_encode_chained", C.byref(q), fake, fake, fake, wb, C.byref(prev), fake,
+                                       pb, NULL_STREAM)
+        assert chained(abft.workspace_size(q) - 1, BIG) == abft.ABFT_E_WORKSPACE
+        assert chained(BIG, abft.workspace_size(prev) - 1) == abft.ABFT_E_WORKSPACE
 
 
 def test_panel_range_and_dtype_rejected():
@@ -78,24 +120,25 @@ def test_panel_range_and_dtype_rejected():
     assert panel(0, 64) == abft.ABFT_E_UNSUPPORTED
 
 
-def test_fused_flags_and_flip_hook_rejected():
+def test_fused_flags_and_fault_hook_rejected():
     fake = C.c_void_p(256)
     p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1)
-    gemm = lambda q, flags, ws=fake: _call("abft_gemm", C.byref(q), fake, fake, fake, ws, flags, NULL_STREAM)
+    gemm = lambda q, flags, ws=fake: _call("abft_gemm", C.byref(q), fake, fake, fake, ws, BIG, flags, NULL_STREAM)
     assert gemm(p, abft.ABFT_FUSED | abft.ABFT_PLAIN) == abft.ABFT_E_ARG
     assert gemm(p, abft.ABFT_FUSED, None) == abft.ABFT_E_WORKSPACE
     q = abft.problem(abft.ABFT_F64, 256, 256, 256, 64, 64)
     assert gemm(q, abft.ABFT_FUSED) == abft.ABFT_E_UNSUPPORTED
-    # no fused product was ever recorded for this workspace
-    assert _call("abft_verify_fused", C.byref(p), fake, C.c_void_p(4096), None, NULL_STREAM) == abft.ABFT_E_ARG
-    arm = lambda q, i, j, bit, ws=fake: _call("abft_arm_accumulator_flip", C.byref(q), ws, i, j, bit)
-    assert arm(p, 256, 0, 3) == abft.ABFT_E_ARG          # rows of C only (the carried row is not the kernel's)
-    assert arm(p, 0, -1, 3) == abft.ABFT_E_ARG
-    assert arm(p, 0, 0, 64) == abft.ABFT_E_ARG
-    assert arm(p, 0, 0, 3, None) == abft.ABFT_E_WORKSPACE
+    q = abft.problem(abft.ABFT_F64, 256, 256, 256, 64, 64)
+    assert _call("abft_verify_fused", C.byref(q), fake, fake, BIG, None, NULL_STREAM) == abft.ABFT_E_UNSUPPORTED
+
+    def fault(prob, i, j, bit):
+        f = abft.abft_fault(i, j, bit)
+        return _call("abft_gemm_fault", C.byref(prob), fake, fake, fake, fake, BIG, 0, C.byref(f), NULL_STREAM)
+    assert fault(p, 256, 0, 3) == abft.ABFT_E_ARG          # rows of C only (the carried row is not the kernel's)
+    assert fault(p, 0, -1, 3) == abft.ABFT_E_ARG
+    assert fault(p, 0, 0, 64) == abft.ABFT_E_ARG
     p32 = abft.problem(abft.ABFT_F32, 256, 256, 256, 1, 1)
-    assert arm(p32, 0, 0, 32) == abft.ABFT_E_ARG
-    assert arm(p32, 0, 0, 31, C.c_void_p(8192)) == abft.ABFT_OK  # host only: arms, launches nothing
+    assert fault(p32, 0, 0, 32) == abft.ABFT_E_ARG
 
 
 def test_describe_gemm_names_kernels_and_tiles():
@@ -124,7 +167,7 @@ def test_describe_gemm_names_kernels_and_tiles():
 def test_quantize_encode_rejected():
     fake = C.c_void_p(256)
     qe = lambda q, a32=fake, lda=256, b32=fake, ldb=256, ws=fake: _call(
-        "abft_quantize_encode", C.byref(q), a32, lda, b32, ldb, fake, fake, ws, NULL_STREAM)
+        "abft_quantize_encode", C.byref(q), a32, lda, b32, ldb, fake, fake, ws, BIG, NULL_STREAM)
     p = abft.problem(abft.ABFT_BF16, 256, 256, 256, 1, 1)
     assert qe(abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1)) == abft.ABFT_E_UNSUPPORTED
     assert qe(p, a32=C.c_void_p(260)) == abft.ABFT_E_ARG        # binary32 rows not 16-byte aligned
@@ -265,23 +308,31 @@ def test_weighted_bad_problems_rejected_before_launch():
     ]
     for wp, want in bad:
         assert abft.wworkspace_size(wp) == 0
-        assert _call("abft_wencode", C.byref(wp), fake, fake, fake, NULL_STREAM) == want
+        assert _call("abft_wencode", C.byref(wp), fake, fake, fake, BIG, NULL_STREAM) == want
     wp = _wp()
     wp.p.dtype = abft.ABFT_BF16
     assert _call("abft_wgemm", C.byref(wp), fake, fake, fake, NULL_STREAM) == abft.ABFT_E_UNSUPPORTED
     wp = _wp()
-    assert _call("abft_wencode", C.byref(wp), C.c_void_p(8), fake, fake, NULL_STREAM) == abft.ABFT_E_ARG
-    assert _call("abft_wencode", C.byref(wp), fake, fake, None, NULL_STREAM) == abft.ABFT_E_WORKSPACE
+    assert _call("abft_wencode", C.byref(wp), C.c_void_p(8), fake, fake, BIG, NULL_STREAM) == abft.ABFT_E_ARG
+    assert _call("abft_wencode", C.byref(wp), fake, fake, None, BIG, NULL_STREAM) == abft.ABFT_E_WORKSPACE
+    need = abft.wworkspace_size(wp)
+    assert _call("abft_wencode", C.byref(wp), fake, fake, fake, need - 1, NULL_STREAM) == abft.ABFT_E_WORKSPACE
+    assert _call("abft_wsetup", C.byref(wp), fake, need - 1) == abft.ABFT_E_WORKSPACE
+    assert _call("abft_wverify", C.byref(wp), fake, None, 0, fake, need - 1, None, NULL_STREAM) == abft.ABFT_E_WORKSPACE
+    one = (abft.abft_location * 1)(abft.abft_location(abft.ABFT_CLS_DATA, 0, 0, 0))
+    assert _call("abft_wcorrect", C.byref(wp), fake, one, 1, fake, need - 1, NULL_STREAM) == abft.ABFT_E_WORKSPACE
     blocks = (C.c_int32 * 3)(0, 1, 2)
     # three data blocks lost with two checksums: refused on the host
-    assert _call("abft_wrecover", C.byref(wp), fake, abft.ABFT_DIR_COL, blocks, 3, 0, 10, fake,
+    assert _call("abft_wrecover", C.byref(wp), fake, abft.ABFT_DIR_COL, blocks, 3, 0, 10, fake, BIG,
                  NULL_STREAM) == abft.ABFT_E_UNRECOVERABLE
+    assert _call("abft_wrecover", C.byref(wp), fake, abft.ABFT_DIR_COL, blocks, 3, 0, 10, fake, need - 1,
+                 NULL_STREAM) == abft.ABFT_E_WORKSPACE
     # a singular system: two equal weight columns
     ws = _wp(wr=np.array([[1.0, 1.0, 1.0, 1.0], [1.0, 2.0, 2.0, 3.0]]))
     two = (C.c_int32 * 2)(1, 2)
-    assert _call("abft_wrecover", C.byref(ws), fake, abft.ABFT_DIR_COL, two, 2, 0, 10, fake,
+    assert _call("abft_wrecover", C.byref(ws), fake, abft.ABFT_DIR_COL, two, 2, 0, 10, fake, BIG,
                  NULL_STREAM) == abft.ABFT_E_UNRECOVERABLE
-    assert _call("abft_wrecover", C.byref(wp), fake, abft.ABFT_DIR_COL, two, 2, 0, 1000, fake,
+    assert _call("abft_wrecover", C.byref(wp), fake, abft.ABFT_DIR_COL, two, 2, 0, 1000, fake, BIG,
                  NULL_STREAM) == abft.ABFT_E_ARG                      # beyond the columns of C_f
 
 
