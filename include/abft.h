@@ -309,6 +309,25 @@ int abft_verify(const abft_problem *p, const void *C_f, const abft_rect *known, 
                 void *ws, size_t ws_bytes, abft_report *host_out, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): abft_verify with
+ * its scratch -- the device report, the tile partial sums and the reduction
+ * partials -- in a static device array of the library, ABFT_NOALLOC_SCRATCH_BYTES
+ * per GPU (held until the process ends), instead of ws.  ws is read only: the
+ * threshold statistics abft_encode wrote (ws_bytes as for abft_verify).  The
+ * report is copied to host_out (required; pinned host memory, valid after a
+ * stream synchronisation).  Same checks, thresholds, flags and report as
+ * abft_verify.  Allocates nothing.  ABFT_E_WORKSPACE if the problem's scratch
+ * exceeds the array (e.g. b = 1 products beyond about 16384 x 16384).  Every
+ * call on one GPU uses that GPU's one array, so calls that overlap on one GPU
+ * (other streams, other threads) race; the stream must belong to the current
+ * device.
+ */
+#define ABFT_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int abft_verify_noalloc(const abft_problem *p, const void *C_f, const abft_rect *known, int n_known,
+                        const void *ws, size_t ws_bytes, abft_report *host_out, void *stream);
+
+/*
  * Fused verification (Sec. 2.2 consistency, br = bc = 1): the column
  * relations of the data columns and the row relations of the data rows are
  * formed from the partial sums the last abft_gemm with ABFT_FUSED on this ws

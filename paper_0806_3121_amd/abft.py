@@ -136,6 +136,7 @@ def lib():
             "abft_quantize": (C.c_int, [_P(abft_problem), C.c_int, _V, C.c_int64, _V, _V, _Z, _V]),
             "abft_verify": (C.c_int, [_P(abft_problem), _V, _P(abft_rect), C.c_int, _V, _Z, _V, _V]),
             "abft_verify_fused": (C.c_int, [_P(abft_problem), _V, _V, _Z, _V, _V]),
+            "abft_verify_noalloc": (C.c_int, [_P(abft_problem), _V, _P(abft_rect), C.c_int, _V, _Z, _V, _V]),
             "abft_classify": (C.c_int, [_P(abft_problem), _P(abft_report), _P(abft_rect), C.c_int,
                                         _P(abft_location)]),
             "abft_correct": (C.c_int, [_P(abft_problem), _V, _P(abft_location), _V]),
@@ -282,6 +283,15 @@ def verify(p, C_f, ws, known=None, host_out=None, stream=None):
     hp = C.c_void_p(host_out.data_ptr()) if host_out is not None else None
     return _check("abft_verify", lib().abft_verify(C.byref(p), _ptr(C_f), arr, nk, _ptr(ws), _nbytes(ws), hp,
                                                    _stream(stream)))
+
+
+def verify_noalloc(p, C_f, ws, known=None, host_out=None, stream=None):
+    """abft_verify with the library's static scratch (allocates nothing); ws is
+    read only; host_out (a pinned buffer from new_report_buffer) is required."""
+    arr, nk = _rects(known)
+    hp = C.c_void_p(host_out.data_ptr()) if host_out is not None else None
+    return _check("abft_verify_noalloc", lib().abft_verify_noalloc(C.byref(p), _ptr(C_f), arr, nk, _ptr(ws),
+                                                                   _nbytes(ws), hp, _stream(stream)))
 
 
 def verify_fused(p, C_f, ws, host_out=None, stream=None):

@@ -1,6 +1,7 @@
 // libabft C ABI: argument checks, workspace layout, host-side classification
 // and dispatch to the gfx950 kernels.  See include/abft.h for the contract.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -236,6 +237,34 @@ static int classify(const abft_problem *p, const abft_report *rep, const abft_re
     return ABFT_OK;  // MULTI
 }
 
+// ------------------------------------------------------------------ static scratch (abft_verify_noalloc)
+// Device scratch for callers that cannot allocate: every GPU the library runs
+// on holds its own copy of this array until the process ends.  Host code
+// never passes the array's name to a kernel or a copy (on the host it is a
+// stand-in, not a device address): the device address is taken once per
+// device with hipGetSymbolAddress, with that device current, and cached here.
+// The cache only ever holds the one address of each device, so concurrent
+// first calls store the same value.
+static __device__ __align__(256) uint8_t scratch[ABFT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::atomic<char *> g_scratch_ptr[kMaxDevices];
+
+static int scratch_ptr(char **out) {
+    int dev = -1;
+    ABFT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return ABFT_E_ARG;
+    char *ptr = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (!ptr) {
+        void *addr = nullptr;
+        ABFT_HIP(hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)));
+        ptr = (char *)addr;
+        g_scratch_ptr[dev].store(ptr, std::memory_order_release);
+    }
+    *out = ptr;
+    return ABFT_OK;
+}
+
 static int to_erasures(const Geom &g, const abft_rect *known, int n_known, Erasures *er) {
     if (n_known < 0 || n_known > 4 || (n_known > 0 && !known)) return ABFT_E_ARG;
     er->n = n_known;
@@ -390,6 +419,26 @@ int abft_verify(const abft_problem *p, const void *C_f, const abft_rect *known, 
         ABFT_HIP(hipMemcpyAsync(host_out, (char *)ws + L.report, sizeof(abft_report), hipMemcpyDeviceToHost,
                                 (hipStream_t)stream));
     }
+    return ABFT_OK;
+}
+
+int abft_verify_noalloc(const abft_problem *p, const void *C_f, const abft_rect *known, int n_known,
+                        const void *ws, size_t ws_bytes, abft_report *host_out, void *stream) {
+    int st = check_problem(p);
+    if (st) return st;
+    if ((st = check_c(p, C_f, false))) return st;
+    if ((st = check_ws(p, ws, ws_bytes))) return st;
+    if (!host_out) return ABFT_E_ARG;
+    Geom g = geom_of(p);
+    Erasures er;
+    if ((st = to_erasures(g, known, n_known, &er))) return st;
+    if (verify_scratch_layout(p, C_f, nullptr, nullptr) > ABFT_NOALLOC_SCRATCH_BYTES) return ABFT_E_WORKSPACE;
+    char *base = nullptr;
+    if ((st = scratch_ptr(&base))) return st;
+    VerifyScratch sc;
+    verify_scratch_layout(p, C_f, base, &sc);
+    if ((st = launch_verify_scratch(p, C_f, er, (const char *)ws, sc, (hipStream_t)stream))) return st;
+    ABFT_HIP(hipMemcpyAsync(host_out, sc.rep, sizeof(abft_report), hipMemcpyDeviceToHost, (hipStream_t)stream));
     return ABFT_OK;
 }
 
