@@ -391,6 +391,33 @@ int abft_inject_erase(const abft_problem *p, void *C_f, abft_rect e, int nan_fil
 int abft_fill_uniform(int32_t dtype, int64_t rows, int64_t cols, int64_t ld, int transpose, uint64_t seed,
                       int32_t stream_id, void *dst, void *stream);
 
+/* Heavy-tailed binary32 inputs (the second input set of the binary32
+ * workload): N(0,1) by Box-Muller in binary64 from the splitmix64 streams 0
+ * (u1 in (0, 1]) and 1 (u2 in [0, 1)) of seed at the logical element's
+ * row-major counter, rounded to binary32, and multiplied by fl32(scale) with
+ * probability frac (stream 6).  Layout as abft_fill_uniform.  The device's
+ * log and cos may round differently from a host library's, so a value can
+ * differ from a host generator's by one binary32 rounding: for runs whose
+ * expected outcome needs no reference (clean products). */
+int abft_fill_normal(int64_t rows, int64_t cols, int64_t ld, int transpose, uint64_t seed, double frac, float scale,
+                     float *dst, void *stream);
+
+/*
+ * Peak probes (measurement aids, not part of the protected product): what the
+ * matrix cores and HBM deliver on this device, so that kernel rates can be
+ * read against measured peaks as well as datasheet ones.
+ * abft_probe_mfma launches a register-only loop of `iters` rounds of 8 (binary64: 16)
+ * independent matrix-core instructions per wave (dtype ABFT_F64:
+ * v_mfma_f64_16x16x4, ABFT_F32: v_mfma_f32_16x16x4, ABFT_BF16:
+ * v_mfma_f32_16x16x32_bf16) on 512 blocks of 4 waves, writes one value per
+ * block to sink (device, sink_len >= 512 doubles) and stores the flops it
+ * executes in *flops (host).  abft_probe_stream launches a read-only pass of
+ * 16-byte loads over buf (device, 16-byte aligned, bytes >= 16; sink_len >=
+ * 2048).  Both are asynchronous on stream; time them with events.
+ */
+int abft_probe_mfma(int32_t dtype, int64_t iters, double *sink, int64_t sink_len, double *flops, void *stream);
+int abft_probe_stream(const void *buf, size_t bytes, double *sink, int64_t sink_len, void *stream);
+
 /*
  * Batched problems: many independent protected products of uneven shapes in
  * one pass (bfloat16 inputs, binary32 C, statistical or exact thresholds).

@@ -579,10 +579,13 @@ int orc_e4m3_scale_exp(int64_t count, const float *x)
     return e;
 }
 
-/* Threads the OpenMP loops of this library run on (1 without OpenMP). */
+/* Threads the OpenMP loops of this library run on (1 without OpenMP), and a
+ * way to change it (the single-core timing of the CPU baseline). */
 #ifdef _OPENMP
 #include <omp.h>
 int orc_num_threads(void) { return omp_get_max_threads(); }
+void orc_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 #else
 int orc_num_threads(void) { return 1; }
+void orc_set_num_threads(int n) { (void)n; }
 #endif

@@ -90,6 +90,7 @@ def lib():
             "orc_to_e4m3": (None, [_I, _P, _P]),
             "orc_e4m3_scale_exp": (C.c_int, [_I, _P]),
             "orc_num_threads": (C.c_int, []),
+            "orc_set_num_threads": (None, [C.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -141,6 +142,10 @@ def gemm(A: np.ndarray, B: np.ndarray) -> np.ndarray:
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    lib().orc_set_num_threads(int(n))
 
 
 def dot(a: np.ndarray, b: np.ndarray) -> float:

@@ -169,6 +169,10 @@ def lib():
                                                   C.c_int32, C.c_int32, _V, C.c_int64, _V]),
             "abft_block_cyclic_unstack": (C.c_int, [_V, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int64,
                                                     C.c_int32, C.c_int32, _V, C.c_int64, _V]),
+            "abft_fill_normal": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_uint64, C.c_double,
+                                           C.c_float, _V, _V]),
+            "abft_probe_mfma": (C.c_int, [C.c_int32, C.c_int64, _V, C.c_int64, _P(C.c_double), _V]),
+            "abft_probe_stream": (C.c_int, [_V, _Z, _V, C.c_int64, _V]),
             "abft_last_hip_error": (C.c_int, []),
             "abft_status_string": (C.c_char_p, [C.c_int]),
         }
@@ -341,6 +345,12 @@ def fill_uniform(dtype, rows, cols, ld, transpose, seed, stream_id, dst, stream=
                                                                _ptr(dst), _stream(stream)))
 
 
+def fill_normal(rows, cols, ld, transpose, seed, dst, frac=0.01, scale=1e3, stream=None):
+    """Heavy-tailed binary32 inputs on the device (N(0,1), a fraction frac scaled by scale)."""
+    return _check("abft_fill_normal", lib().abft_fill_normal(rows, cols, ld, int(transpose), seed, frac, scale,
+                                                             _ptr(dst), _stream(stream)))
+
+
 def batch_workspace_size(probs) -> int:
     arr = (abft_problem * len(probs))(*probs)
     return lib().abft_batch_workspace_size(arr, len(probs))
@@ -385,6 +395,22 @@ def batch_reports(plan, host_out, stream=None):
     """host_out: pinned uint8 CPU tensor of count * sizeof(abft_report) bytes."""
     return _check("abft_batch_reports",
                   lib().abft_batch_reports(C.byref(plan), C.c_void_p(host_out.data_ptr()), _stream(stream)))
+
+
+def probe_mfma(dtype, iters, sink, stream=None) -> float:
+    """Launch the matrix-core peak probe (sink: float64 device tensor of >= 512
+    entries); returns the flops it executes."""
+    flops = C.c_double(0.0)
+    _check("abft_probe_mfma", lib().abft_probe_mfma(dtype, iters, _ptr(sink), sink.numel(), C.byref(flops),
+                                                    _stream(stream)))
+    return flops.value
+
+
+def probe_stream(buf, sink, stream=None):
+    """Launch the HBM read probe over the device tensor buf (sink: float64
+    device tensor of >= 2048 entries)."""
+    return _check("abft_probe_stream", lib().abft_probe_stream(_ptr(buf), _nbytes(buf), _ptr(sink), sink.numel(),
+                                                               _stream(stream)))
 
 
 # ---------------------------------------------------------------- conveniences

@@ -16,7 +16,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libabft.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["abft_api.hip", "k_reduce.hip", "k_fix.hip", "k_gemm.hip", "k_batch.hip", "k_weighted.hip"]
+SOURCES = ["abft_api.hip", "k_reduce.hip", "k_fix.hip", "k_gemm.hip", "k_batch.hip", "k_weighted.hip", "k_probe.hip"]
 
 # Packed FP32 instructions are switched off for all device code.
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

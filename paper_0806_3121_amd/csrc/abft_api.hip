@@ -512,6 +512,14 @@ int abft_fill_uniform(int32_t dtype, int64_t rows, int64_t cols, int64_t ld, int
     return launch_fill_uniform(dtype, rows, cols, ld, transpose, seed, stream_id, dst, (hipStream_t)stream);
 }
 
+int abft_fill_normal(int64_t rows, int64_t cols, int64_t ld, int transpose, uint64_t seed, double frac, float scale,
+                     float *dst, void *stream) {
+    if (rows < 1 || cols < 1 || !dst || ((uintptr_t)dst & 3u)) return ABFT_E_ARG;
+    if (ld < (transpose ? rows : cols)) return ABFT_E_ARG;
+    if (!(frac >= 0.0 && frac <= 1.0) || !std::isfinite(scale)) return ABFT_E_ARG;
+    return launch_fill_normal(rows, cols, ld, transpose, seed, frac, scale, dst, (hipStream_t)stream);
+}
+
 int abft_last_hip_error(void) { return g_last_hip_error; }
 
 const char *abft_status_string(int s) {

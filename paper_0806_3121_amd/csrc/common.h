@@ -267,6 +267,8 @@ int launch_inject_flip(const abft_problem *p, void *C_f, int64_t i, int64_t j, i
 int launch_inject_erase(const abft_problem *p, void *C_f, abft_rect e, int nan_fill, hipStream_t s);
 int launch_fill_uniform(int32_t dtype, int64_t rows, int64_t cols, int64_t ld, int transpose, uint64_t seed,
                         int32_t stream_id, void *dst, hipStream_t s);
+int launch_fill_normal(int64_t rows, int64_t cols, int64_t ld, int transpose, uint64_t seed, double frac,
+                       float scale, float *dst, hipStream_t s);
 int launch_quantize_encode(const abft_problem *p, const float *A32, int64_t lda32, const float *B32, int64_t ldb32,
                            void *A_f, void *B_f, char *ws, hipStream_t s);
 int launch_quantize(const abft_problem *p, int which, const float *X, int64_t ldx, void *dst, char *ws, hipStream_t s);

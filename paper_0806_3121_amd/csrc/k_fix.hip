@@ -195,6 +195,41 @@ int launch_fill_uniform(int32_t dtype, int64_t rows, int64_t cols, int64_t ld, i
     return ABFT_OK;
 }
 
+// Heavy-tailed binary32 inputs: N(0,1) by Box-Muller in binary64 from the
+// seed's streams A (u1 in (0, 1]) and B (u2 in [0, 1)) at the element's
+// row-major index, rounded to binary32; with probability frac (stream 6, the
+// outlier mask) the value is multiplied by fl32(scale).  The recipe of the host
+// generator; the device's log and cos may differ from the host library's in
+// the last bit, so a value can differ from the host's by one rounding (the
+// sets serve runs that need no oracle).
+__global__ __launch_bounds__(kThreads) void k_fill_normal(float *dst, int64_t rows, int64_t cols, int64_t ld,
+                                                          int transpose, uint64_t key1, uint64_t key2, uint64_t keyo,
+                                                          double frac, float scale) {
+    const int64_t total = rows * cols;
+    const uint64_t gamma = 0x9E3779B97F4A7C15ull;
+    for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
+        int64_t r, c;
+        if (transpose) { c = t / rows; r = t - c * rows; }
+        else { r = t / cols; c = t - r * cols; }
+        const uint64_t idx = (uint64_t)r * (uint64_t)cols + (uint64_t)c;
+        const uint64_t step = (idx + 1) * gamma;
+        const double u1 = ((double)(mix64(key1 + step) >> 11) + 1.0) * 0x1p-53;
+        const double u2 = (double)(mix64(key2 + step) >> 11) * 0x1p-53;
+        float z = (float)(sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2));
+        if ((double)(mix64(keyo + step) >> 11) * 0x1p-53 < frac) z = z * scale;
+        if (transpose) dst[c * ld + r] = z;
+        else dst[r * ld + c] = z;
+    }
+}
+
+int launch_fill_normal(int64_t rows, int64_t cols, int64_t ld, int transpose, uint64_t seed, double frac,
+                       float scale, float *dst, hipStream_t s) {
+    const uint64_t k1 = mix64(seed * 256ull + 0), k2 = mix64(seed * 256ull + 1), ko = mix64(seed * 256ull + 6);
+    const unsigned blocks = (unsigned)std::min<int64_t>((rows * cols + kThreads - 1) / kThreads, 65536);
+    k_fill_normal<<<blocks, kThreads, 0, s>>>(dst, rows, cols, ld, transpose, k1, k2, ko, frac, scale);
+    ABFT_LAUNCHED();
+    return ABFT_OK;
+}
 
 // ------------------------------------------------------------------ 2-D block-cyclic layout (Sec. 4.1)
 // One dimension of n indices over Pn processes with blocks of nb: global
