@@ -335,10 +335,26 @@ def run_batched(args):
     for q, (m, n, k) in enumerate(shapes):
         abft.fill_uniform(abft.ABFT_F32, m, k, k, 0, SEED + q, synth.STREAM_A, Bt.A32[q])
         abft.fill_uniform(abft.ABFT_F32, k, n, k, 1, SEED + q, synth.STREAM_B, Bt.Bt32[q])
+    abft.batch_quantize(Bt.plan)
+    # product tile shape per problem: from the tuning cache when every problem's
+    # bucket is there, else measured now (every problem under every shape) and stored
+    found, tiles = abft.batch_cache_lookup(args.tile_cache, Bt.probs)
+    tile_source = "cache"
+    if found < len(shapes):
+        costs, _ = abft.batch_tune(Bt.plan)
+        abft.batch_cache_store(args.tile_cache, Bt.probs, costs)
+        found, tiles = abft.batch_cache_lookup(args.tile_cache, Bt.probs)
+        tile_source = "tuned"
+        single = [sum(row[t] for row in costs) for t in range(abft.ABFT_BATCH_TILES)]
+        mixed = sum(row[t] for row, t in zip(costs, tiles))
+        # costs are in ticks of the 100 MHz device clock, summed over every tile (all CUs)
+        log(f"tuned: summed tile time per single shape {[round(x * 1e-5, 2) for x in single]} ms, per-problem "
+            f"shapes {mixed * 1e-5:.2f} ms")
+    Bt.set_tiles(tiles)
     plan = Bt.plan
-    abft.batch_quantize(plan)
-    tile = abft.batch_tune(plan)
-    log(f"autotuned tile shape {tile}")
+    tile = abft.ABFT_BATCH_MIXED
+    tile_counts = [tiles.count(t) for t in range(abft.ABFT_BATCH_TILES)]
+    log(f"tile shapes ({tile_source}, {args.tile_cache}): problems per shape {tile_counts}")
     torch.cuda.synchronize()
 
     side = torch.cuda.Stream()
@@ -444,7 +460,8 @@ def run_batched(args):
                                f"on multiples of {cfg['step']} in [{cfg['lo']}, {cfg['hi']}], checksum blocks "
                                f"{br}x{bc}; per step {nf} flips and {ne} erased {br}x32 blocks on distinct "
                                f"problems; graph-captured passes",
-                   "problems": len(shapes), "br": br, "bc": bc, "tile": tile, "global_batch": len(shapes),
+                   "problems": len(shapes), "br": br, "bc": bc, "tile": "per-problem",
+                   "tile_source": tile_source, "problems_per_tile_shape": tile_counts, "global_batch": len(shapes),
                    "seq_len": 0, "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": TRAFFIC["c5"],
@@ -881,13 +898,19 @@ class OracleFlips:
             self.C[r0:r1] = self._stored(orc.gemm(self.Af[r0:r1], self.Bf) * sc)
             if M * N * k > 1e10:
                 log(f"oracle C_f rows {r1} / {M}")
-        if dt_name == "f64":
+        self.stat = dt_name != "f64"
+        if not self.stat:
             self.tc, self.tr = orc.tau_det(self.Af, self.Bf, m, n, br, bc)
         else:
             T = k if dt_name == "f32" else k / 4.0
             s_store = 2.0 + (2.0 ** 18 if dt_name == "fp8" else 0.0)
-            tc, tr = orc.tau_stat(self.Af, self.Bf, m, n, br, bc, u_acc=2.0 ** -24, T=T, s_store=s_store, lam=lam)
-            self.tc, self.tr = tc * sc, tr * sc
+
+            def tau(Cf):
+                tc, tr = orc.tau_stat(self.Af, self.Bf, m, n, br, bc, u_acc=2.0 ** -24, T=T, s_store=s_store,
+                                      lam=lam, Cf=Cf / sc if sc != 1.0 else Cf)
+                return tc * sc, tr * sc
+            self._tau = tau
+            self.tc, self.tr = tau(self.C)
 
     def _stored(self, v):
         """Values of C as stored: binary64, or rounded once to binary32."""
@@ -931,6 +954,14 @@ class OracleFlips:
         with np.errstate(invalid="ignore", over="ignore"):
             dc, dr = self._residual(col), self._residual(row)
         tc, tr = self.tc[r, j], self.tr[i, c]
+        if self.stat and (i >= m or j >= n):
+            # a flip on a stored total also moves that relation's rounding term
+            self.C[i, j] = new
+            try:
+                tcs, trs = self._tau(self.C)
+            finally:
+                self.C[i, j] = old
+            tc, tr = tcs[r, j], trs[i, c]
         rep = orc.Report()
         for side, (a, bb, d, t) in (("c", (r, j, dc, tc)), ("r", (i, c, dr, tr))):
             if not abs(d) <= t:
@@ -1371,6 +1402,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the unprotected-kernel timing (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--tile-cache", default=os.path.join(ROOT, "paper_0806_3121_amd", "batch_tiles.txt"),
+                    help="batched workload: tile-shape tuning cache (read, and written after a tuning run)")
     ap.add_argument("--no-targets", action="store_true",
                     help="default workload only: skip the target-shape products (binary64 b = 1, bfloat16 and FP8 "
                          "n = 16384) and the peak probes")

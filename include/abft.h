@@ -443,17 +443,22 @@ typedef struct {
 } abft_batch_item;
 
 /* Product tile shapes of the batched kernel: 0 = 256 x 256, 1 = 256 x 128,
- * 2 = 128 x 256, 3 = 128 x 128. */
+ * 2 = 128 x 256, 3 = 128 x 128 (all eight waves, one block per CU, so one
+ * persistent launch runs tiles of every shape).  ABFT_BATCH_MIXED: every
+ * problem with its own shape (chosen at setup). */
 #define ABFT_BATCH_TILES 4
+#define ABFT_BATCH_MIXED ABFT_BATCH_TILES
 
 /* Host-side plan filled by abft_batch_setup (caller-owned, plain data). */
 typedef struct {
     void *bws;                                 /* the device batch workspace */
     int32_t count;
     int32_t dtype;
-    int64_t n_tiles[ABFT_BATCH_TILES][2];      /* product tiles per shape: [.][0] protected, [.][1] ABFT_PLAIN */
+    int64_t n_tiles[ABFT_BATCH_TILES + 1][2];  /* product tiles per shape and for the per-problem shapes:
+                                                  [.][0] protected, [.][1] ABFT_PLAIN */
     int64_t n_work[8];                         /* flattened work sizes of the other steps */
     size_t bytes;
+    size_t ttime_off;                          /* the tuner's per-tile durations in bws */
 } abft_batch_plan;
 
 /* Device bytes of the batch workspace for these problems (0 if invalid). */
@@ -467,6 +472,13 @@ size_t abft_batch_workspace_size(const abft_problem *probs, int count);
  * on a bad problem, ABFT_E_WORKSPACE if bws_bytes is too small. */
 int abft_batch_setup(const abft_problem *probs, const abft_batch_item *items, int count, void *bws, size_t bws_bytes,
                      abft_batch_plan *plan);
+/* abft_batch_setup with each problem's product tile shape for
+ * ABFT_BATCH_MIXED: tiles (host, count entries in the caller's order) holds a
+ * shape 0 .. ABFT_BATCH_TILES-1, or a negative value for the library's model
+ * (the executed tile area over a per-shape efficiency).  abft_batch_setup is
+ * this call with the model for every problem. */
+int abft_batch_setup_tiles(const abft_problem *probs, const abft_batch_item *items, int count, const int32_t *tiles,
+                           void *bws, size_t bws_bytes, abft_batch_plan *plan);
 
 /* The batched steps (asynchronous, capturable), each the single-problem
  * step of the same name applied to every problem of the plan:
@@ -476,11 +488,10 @@ int abft_batch_setup(const abft_problem *probs, const abft_batch_item *items, in
  *     kept in binary32 and as three bfloat16 rows in bws, and the statistics
  *     of the thresholds (Sec. 3);
  *   abft_batch_gemm: C_f = A_f B_f; flags 0 or ABFT_PLAIN (data block only);
- *     tile: one of the ABFT_BATCH_TILES shapes;
+ *     tile: one of the ABFT_BATCH_TILES shapes for every problem, or
+ *     ABFT_BATCH_MIXED (each problem's own);
  *   abft_batch_verify: every column and row relation of every C_f (Sec. 2),
  *     into the problem's report in bws (no erased-element exclusion).
- * abft_batch_tune runs abft_batch_gemm with every tile shape (overwriting
- * every C_f), synchronises the stream and returns the fastest in *best_tile.
  * All return ABFT_E_ARG on a NULL plan or a bad tile. */
 int abft_batch_quantize(const abft_batch_plan *plan, void *stream);
 int abft_batch_encode(const abft_batch_plan *plan, void *stream);
@@ -489,7 +500,23 @@ int abft_batch_encode(const abft_batch_plan *plan, void *stream);
  * from their bfloat16 operands as they are. */
 int abft_batch_quantize_encode(const abft_batch_plan *plan, void *stream);
 int abft_batch_gemm(const abft_batch_plan *plan, int tile, uint32_t flags, void *stream);
-int abft_batch_tune(const abft_batch_plan *plan, int *best_tile, void *stream);
+/* Tuner (synchronous; overwrites every C_f): runs the product once with each
+ * tile shape for every problem, recording each tile's duration on the device
+ * (100 MHz clock), and gives per problem (caller's order) the summed duration
+ * of its tiles for each shape in costs (host, count x ABFT_BATCH_TILES, or
+ * NULL) and the shape with the least in tiles (host, count, or NULL). */
+int abft_batch_tune(const abft_batch_plan *plan, double *costs, int32_t *tiles, void *stream);
+/* Persisted tuning results: a text file keyed by (dtype, m / 128, n / 128,
+ * log2 k rounded up, br, bc, arch) with the summed cost of each shape over the
+ * problems measured in that bucket.  abft_batch_cache_store merges the costs
+ * of these problems (from abft_batch_tune) into the file at path (a bucket
+ * measured again is replaced); abft_batch_cache_lookup fills tiles (host,
+ * count) with each problem's bucket's best shape, or -1 where the file has no
+ * entry, and returns how many were found.  arch: the device architecture name
+ * (e.g. "gfx950"), or NULL for the current device's.  Host only. */
+int abft_batch_cache_lookup(const char *path, const char *arch, const abft_problem *probs, int count, int32_t *tiles);
+int abft_batch_cache_store(const char *path, const char *arch, const abft_problem *probs, int count,
+                           const double *costs);
 int abft_batch_verify(const abft_batch_plan *plan, void *stream);
 /* Copy the count reports (verify results, in the caller's problem order) to
  * host_out (pinned; valid after a stream synchronisation). */

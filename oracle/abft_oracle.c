@@ -196,15 +196,24 @@ void orc_tau_det(int64_t m, int64_t n, int64_t k, int64_t br, int64_t bc,
  * rounding of a binary32-stored checksum.  tau = lambda * sigma.
  * For br == 1 (bc == 1) Q is computed exactly; otherwise it is replaced by
  * the Cauchy-Schwarz bound ||v[r,:]||_2 ||B_f[:,j]||_4^2.
- * A_f is (m+br) x k and B_f is k x (n+bc), both row-major and encoded.
+ * The stored total of each relation, the carried entry t = C_f[m+r, j]
+ * (C_f[i, n+c] for a row relation), is rounded once to binary32, an error of
+ * variance (u^2/3) t^2 taken with the entry's own magnitude: when C_f is
+ * given (NULL: no such term), sigma^2 += (u^2/3) t^2.  For data of one sign
+ * t is far above the root-sum-square of its products.  A non-finite t (a
+ * fault in the stored total) adds no term, so that the relation's residual,
+ * non-finite too, fails against a finite threshold.
+ * A_f is (m+br) x k and B_f is k x (n+bc), both row-major and encoded; C_f is
+ * (m+br) x (n+bc) with leading dimension ldc.
  */
 void orc_tau_stat(int64_t m, int64_t n, int64_t k, int64_t br, int64_t bc,
                   const double *Af, int64_t lda, const double *Bf, int64_t ldb,
                   double u_acc, double T, double s_store, double lambda,
-                  double *tau_c, double *tau_r)
+                  const double *Cf, int64_t ldc, double *tau_c, double *tau_r)
 {
     int64_t Gr = m / br, Gc = n / bc, N = n + bc, M = m + br;
     double coef = u_acc * u_acc / 3.0 * (T / 2.0 + s_store);
+    double cst = u_acc * u_acc / 3.0;
     double *v = (double *)calloc((size_t)(br * k), sizeof(double));
     double *w = (double *)calloc((size_t)(k * bc), sizeof(double));
     for (int64_t r = 0; r < br; ++r) {
@@ -223,7 +232,8 @@ void orc_tau_stat(int64_t m, int64_t n, int64_t k, int64_t br, int64_t bc,
         for (int64_t j = 0; j < N; ++j) {
             double q = 0.0;
             for (int64_t l = 0; l < k; ++l) q += v[l] * (Bf[l * ldb + j] * Bf[l * ldb + j]);
-            tau_c[j] = lambda * sqrt(coef * q);
+            double t = Cf && isfinite(Cf[m * ldc + j]) ? Cf[m * ldc + j] : 0.0;
+            tau_c[j] = lambda * sqrt(coef * q + cst * t * t);
         }
     } else {
         double *nv = (double *)malloc(sizeof(double) * (size_t)br);
@@ -236,7 +246,10 @@ void orc_tau_stat(int64_t m, int64_t n, int64_t k, int64_t br, int64_t bc,
             double s4 = 0.0;
             for (int64_t l = 0; l < k; ++l) { double b2 = Bf[l * ldb + j] * Bf[l * ldb + j]; s4 += b2 * b2; }
             double n4sq = sqrt(s4);
-            for (int64_t r = 0; r < br; ++r) tau_c[r * N + j] = lambda * sqrt(coef * nv[r] * n4sq);
+            for (int64_t r = 0; r < br; ++r) {
+                double t = Cf && isfinite(Cf[(m + r) * ldc + j]) ? Cf[(m + r) * ldc + j] : 0.0;
+                tau_c[r * N + j] = lambda * sqrt(coef * nv[r] * n4sq + cst * t * t);
+            }
         }
         free(nv);
     }
@@ -244,7 +257,8 @@ void orc_tau_stat(int64_t m, int64_t n, int64_t k, int64_t br, int64_t bc,
         for (int64_t i = 0; i < M; ++i) {
             double q = 0.0;
             for (int64_t l = 0; l < k; ++l) q += (Af[i * lda + l] * Af[i * lda + l]) * w[l];
-            tau_r[i] = lambda * sqrt(coef * q);
+            double t = Cf && isfinite(Cf[i * ldc + n]) ? Cf[i * ldc + n] : 0.0;
+            tau_r[i] = lambda * sqrt(coef * q + cst * t * t);
         }
     } else {
         double *nw = (double *)malloc(sizeof(double) * (size_t)bc);
@@ -257,7 +271,10 @@ void orc_tau_stat(int64_t m, int64_t n, int64_t k, int64_t br, int64_t bc,
             double s4 = 0.0;
             for (int64_t l = 0; l < k; ++l) { double a2 = Af[i * lda + l] * Af[i * lda + l]; s4 += a2 * a2; }
             double n4sq = sqrt(s4);
-            for (int64_t c = 0; c < bc; ++c) tau_r[i * bc + c] = lambda * sqrt(coef * n4sq * nw[c]);
+            for (int64_t c = 0; c < bc; ++c) {
+                double t = Cf && isfinite(Cf[i * ldc + n + c]) ? Cf[i * ldc + n + c] : 0.0;
+                tau_r[i * bc + c] = lambda * sqrt(coef * n4sq * nw[c] + cst * t * t);
+            }
         }
         free(nw);
     }

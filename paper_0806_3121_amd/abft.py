@@ -75,13 +75,14 @@ class abft_batch_item(C.Structure):
 
 
 ABFT_BATCH_TILES = 4      # product tile shapes: 256x256, 256x128, 128x256, 128x128
+ABFT_BATCH_MIXED = ABFT_BATCH_TILES   # every problem with its own shape
 
 
 class abft_batch_plan(C.Structure):
     _fields_ = [("bws", C.c_void_p), ("count", C.c_int32), ("dtype", C.c_int32),
-                ("n_tiles", (C.c_int64 * 2) * ABFT_BATCH_TILES),
+                ("n_tiles", (C.c_int64 * 2) * (ABFT_BATCH_TILES + 1)),
                 ("n_work", C.c_int64 * 8),
-                ("bytes", C.c_size_t)]
+                ("bytes", C.c_size_t), ("ttime_off", C.c_size_t)]
 
 
 ABFT_WMAX = 4
@@ -152,7 +153,12 @@ def lib():
             "abft_batch_encode": (C.c_int, [_P(abft_batch_plan), _V]),
             "abft_batch_quantize_encode": (C.c_int, [_P(abft_batch_plan), _V]),
             "abft_batch_gemm": (C.c_int, [_P(abft_batch_plan), C.c_int, C.c_uint32, _V]),
-            "abft_batch_tune": (C.c_int, [_P(abft_batch_plan), _P(C.c_int), _V]),
+            "abft_batch_setup_tiles": (C.c_int, [_P(abft_problem), _P(abft_batch_item), C.c_int, _P(C.c_int32), _V,
+                                                 C.c_size_t, _P(abft_batch_plan)]),
+            "abft_batch_tune": (C.c_int, [_P(abft_batch_plan), _P(C.c_double), _P(C.c_int32), _V]),
+            "abft_batch_cache_lookup": (C.c_int, [C.c_char_p, C.c_char_p, _P(abft_problem), C.c_int, _P(C.c_int32)]),
+            "abft_batch_cache_store": (C.c_int, [C.c_char_p, C.c_char_p, _P(abft_problem), C.c_int,
+                                                 _P(C.c_double)]),
             "abft_batch_verify": (C.c_int, [_P(abft_batch_plan), _V]),
             "abft_batch_reports": (C.c_int, [_P(abft_batch_plan), _V, _V]),
             "abft_wworkspace_size": (C.c_size_t, [_P(abft_wproblem)]),
@@ -356,12 +362,18 @@ def batch_workspace_size(probs) -> int:
     return lib().abft_batch_workspace_size(arr, len(probs))
 
 
-def batch_setup(probs, items, bws) -> abft_batch_plan:
-    """probs: abft_problem list; items: abft_batch_item list; bws: device uint8 tensor."""
+def batch_setup(probs, items, bws, tiles=None) -> abft_batch_plan:
+    """probs: abft_problem list; items: abft_batch_item list; bws: device uint8 tensor;
+    tiles: per-problem product tile shapes for ABFT_BATCH_MIXED (None or -1 entries: the library's model)."""
     pa = (abft_problem * len(probs))(*probs)
     ia = (abft_batch_item * len(items))(*items)
     plan = abft_batch_plan()
-    _check("abft_batch_setup", lib().abft_batch_setup(pa, ia, len(probs), _ptr(bws), bws.numel(), C.byref(plan)))
+    if tiles is None:
+        _check("abft_batch_setup", lib().abft_batch_setup(pa, ia, len(probs), _ptr(bws), bws.numel(), C.byref(plan)))
+    else:
+        ta = (C.c_int32 * len(probs))(*[int(t) for t in tiles])
+        _check("abft_batch_setup_tiles", lib().abft_batch_setup_tiles(pa, ia, len(probs), ta, _ptr(bws), bws.numel(),
+                                                                       C.byref(plan)))
     return plan
 
 
@@ -381,10 +393,31 @@ def batch_gemm(plan, tile=0, flags=0, stream=None):
     return _check("abft_batch_gemm", lib().abft_batch_gemm(C.byref(plan), tile, flags, _stream(stream)))
 
 
-def batch_tune(plan, stream=None) -> int:
-    best = C.c_int(-1)
-    _check("abft_batch_tune", lib().abft_batch_tune(C.byref(plan), C.byref(best), _stream(stream)))
-    return best.value
+def batch_tune(plan, stream=None):
+    """-> (per-problem costs: count x ABFT_BATCH_TILES list of lists, per-problem best shapes)."""
+    n = plan.count
+    costs = (C.c_double * (n * ABFT_BATCH_TILES))()
+    tiles = (C.c_int32 * n)()
+    _check("abft_batch_tune", lib().abft_batch_tune(C.byref(plan), costs, tiles, _stream(stream)))
+    return ([list(costs[p * ABFT_BATCH_TILES:(p + 1) * ABFT_BATCH_TILES]) for p in range(n)],
+            [int(t) for t in tiles])
+
+
+def batch_cache_lookup(path, probs, arch=None):
+    """-> (found, per-problem tile shapes or -1) from the tuning cache file."""
+    pa = (abft_problem * len(probs))(*probs)
+    tiles = (C.c_int32 * len(probs))()
+    found = lib().abft_batch_cache_lookup(path.encode(), arch.encode() if arch else None, pa, len(probs), tiles)
+    if found < 0:
+        _check("abft_batch_cache_lookup", found)
+    return found, [int(t) for t in tiles]
+
+
+def batch_cache_store(path, probs, costs, arch=None):
+    pa = (abft_problem * len(probs))(*probs)
+    flat = (C.c_double * (len(probs) * ABFT_BATCH_TILES))(*[c for row in costs for c in row])
+    return _check("abft_batch_cache_store",
+                  lib().abft_batch_cache_store(path.encode(), arch.encode() if arch else None, pa, len(probs), flat))
 
 
 def batch_verify(plan, stream=None):
@@ -465,7 +498,7 @@ class Batch:
     Bt, and C_f with rows padded to 16 bytes; one batch workspace and a pinned
     buffer for the reports.  shapes: list of (m, n, k, br, bc)."""
 
-    def __init__(self, shapes, device="cuda", tau_mode=ABFT_TAU_STAT, lam=0.0):
+    def __init__(self, shapes, device="cuda", tau_mode=ABFT_TAU_STAT, lam=0.0, tiles=None):
         import torch
         self.shapes = list(shapes)
         self.probs, self.items = [], []
@@ -488,8 +521,12 @@ class Batch:
         if nbytes == 0:
             raise AbftError("abft_batch_workspace_size", ABFT_E_ARG, "invalid batch")
         self.bws = torch.zeros(nbytes, dtype=torch.uint8, device=device)
-        self.plan = batch_setup(self.probs, self.items, self.bws)
+        self.plan = batch_setup(self.probs, self.items, self.bws, tiles)
         self.rep_host = torch.empty(len(self.probs) * C.sizeof(abft_report), dtype=torch.uint8, pin_memory=True)
+
+    def set_tiles(self, tiles):
+        """Rebuild the plan with per-problem tile shapes for ABFT_BATCH_MIXED (synchronous)."""
+        self.plan = batch_setup(self.probs, self.items, self.bws, tiles)
 
     def fetch_reports(self, stream=None):
         """Copy every report into the pinned buffer (synchronises the stream);

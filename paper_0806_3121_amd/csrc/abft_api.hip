@@ -90,6 +90,7 @@ TauCoef tau_coef(const abft_problem *p) {
     Geom g = geom_of(p);
     TauCoef t;
     t.mode = p->tau_mode;
+    t.cst = 0.0;
     t.lambda = p->lambda > 0 ? p->lambda : 10.0;
     const double u64 = std::ldexp(1.0, -53);
     const double u32 = std::ldexp(1.0, -24);
@@ -112,6 +113,12 @@ TauCoef tau_coef(const abft_problem *p) {
         double sst = 2.0;
         if (p->dtype == ABFT_FP8_E4M3) sst += std::ldexp(1.0, 2 * (24 - 15));
         t.cc = t.cr = t.lambda * t.lambda * (u * u / 3.0) * (T / 2.0 + sst);
+        // The stored total of a relation (the carried checksum entry) is rounded
+        // once to the element type: error up to u |tot|.  For data of one sign
+        // the total is far larger than the root-sum-square of its products that
+        // Q measures, so its rounding enters with its own magnitude, read from
+        // C_f at verification.
+        t.cst = t.lambda * t.lambda * (u * u / 3.0);
     } else {
         t.cc = t.cr = 0.0;
     }

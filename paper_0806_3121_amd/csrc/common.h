@@ -277,7 +277,8 @@ int launch_quantize(const abft_problem *p, int which, const float *X, int64_t ld
 struct TauCoef {
     int mode;
     double cc, cr;       // det: tau_c = cc*na_abs[r]*nb[j], tau_r = cr*na[i]*nb_abs[c];
-                         // stat: tau = sqrt(cc * Q), cc = lambda^2 (u^2/3)(T/2 + s)
+                         // stat: tau = sqrt(cc * Q + cst * tot^2), cc = lambda^2 (u^2/3)(T/2 + s)
+    double cst;          // stat: lambda^2 u^2 / 3, the binary32 storage of the relation's stored total tot
     double lambda;
 };
 TauCoef tau_coef(const abft_problem *p);

@@ -14,8 +14,12 @@
 // corner) partial products are added in binary64 and rounded once.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
 #include <numeric>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "gemm_lowp_kernel.h"
@@ -45,10 +49,12 @@ struct BatchDesc {
     double *vpart;                    // verification row partials [M][ceil(N / 1024)][bc]
     abft_report *rep;
     double cc, cr;                    // stat coefficients (lambda^2 (u^2/3)(T/2 + s))
+    double cst;                       // lambda^2 u^2 / 3: the stored total's binary32 rounding
     int mode;                         // ABFT_TAU_STAT or ABFT_TAU_EXACT
     int orig;                         // index in the caller's order
-    // starts in the flattened work spaces
-    int64_t s_tiles[ABFT_BATCH_TILES][2];
+    int tile;                         // the problem's own product tile shape (0 .. ABFT_BATCH_TILES-1)
+    // starts in the flattened work spaces: tiles of each uniform shape, then of the per-problem shapes
+    int64_t s_tiles[ABFT_BATCH_TILES + 1][2];
     int64_t s_quant, s_enc1, s_enc2, s_rows, s_comb, s_vcol, s_vrow;
 };
 
@@ -417,10 +423,17 @@ struct DCfg {
     static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "wave tile");
     static_assert(NS >= 2 && LDS <= 160 * 1024 / BPC, "LDS");
 };
+// The four tile shapes, all eight waves and one block per CU, so that one
+// persistent launch can run tiles of every shape (each problem with its own).
 typedef DCfg<256, 256, 4, 2, 1, 128, 2> Cfg0;    // 128 KB
 typedef DCfg<256, 128, 4, 2, 1, 128, 3> Cfg1;    // 144 KB
 typedef DCfg<128, 256, 2, 4, 1, 128, 3> Cfg2;    // 144 KB
-typedef DCfg<128, 128, 2, 2, 2, 64, 4> Cfg3;     // 64 KB, two blocks per CU
+typedef DCfg<128, 128, 4, 2, 1, 128, 4> Cfg3;    // 128 KB, waves of 32 x 64
+constexpr int kGemmThreads = 512;
+constexpr int kGemmLds = Cfg1::LDS > Cfg0::LDS ? (Cfg1::LDS > Cfg3::LDS ? Cfg1::LDS : Cfg3::LDS) : Cfg0::LDS;
+static_assert(Cfg0::THREADS == kGemmThreads && Cfg1::THREADS == kGemmThreads && Cfg2::THREADS == kGemmThreads &&
+              Cfg3::THREADS == kGemmThreads, "one block shape for every tile shape");
+static_assert(Cfg2::LDS <= kGemmLds && kGemmLds <= 160 * 1024, "LDS");
 
 __device__ __align__(16) uint32_t kZeroChunk[4];      // never written: the source of chunks past K
 
@@ -428,11 +441,15 @@ __device__ __align__(16) uint32_t kZeroChunk[4];      // never written: the sour
 // flattened tiles, so the tiles an XCD runs together are neighbours and share
 // operand rows in its L2.  A block takes tiles from its own XCD's queue
 // (blockIdx.x % 8), then from the others in turn.  tmap (byte offset from the
-// workspace) gives each tile's problem.
+// workspace) gives each tile's problem.  Index kMixed: every problem with its
+// own tile shape (BatchDesc::tile); 0 .. ABFT_BATCH_TILES-1: every problem
+// with that shape.
 constexpr int kXcds = 8;
+constexpr int kMixed = ABFT_BATCH_TILES;
+constexpr int kMaps = ABFT_BATCH_TILES + 1;
 struct TileQueues {
-    int64_t qb[ABFT_BATCH_TILES][2][kXcds], qe[ABFT_BATCH_TILES][2][kXcds];
-    int64_t tmap[ABFT_BATCH_TILES][2];
+    int64_t qb[kMaps][2][kXcds], qe[kMaps][2][kXcds];
+    int64_t tmap[kMaps][2];
 };
 constexpr int kCtrWords = kXcds + 1;                   // queue counters, then the exit counter
 constexpr size_t kCtlBytes = 2048;                     // counters (256 bytes) + TileQueues
@@ -459,122 +476,111 @@ __device__ inline int64_t uniform64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-template <class CF>
-__global__ __launch_bounds__(CF::THREADS, 1) void kb_gemm(const BatchDesc *__restrict__ d, int cfg, int plain,
-                                                          unsigned *ctr, const TileQueues *__restrict__ tq) {
-    // One LDS object only: with a second one the compiler cannot tell the
-    // fragment reads from the in-flight direct-to-LDS loads and waits for them.
-    __shared__ __attribute__((aligned(16))) uint8_t lds[CF::LDS];
-    int64_t &sh_next = *(int64_t *)lds;               // the header holds the next tile index
+// One tile `local` (in the problem's grouped tile order for shape CF) of
+// problem D: the k loop through the LDS ring and the epilogue.  lds: the
+// block's LDS (header first); fetch(): called by thread 0 during the last slab
+// to take the next tile.
+template <class CF, class Fetch>
+__device__ __attribute__((always_inline)) inline void gemm_tile(const BatchDesc &D, int64_t local, int plain,
+                                                                uint8_t *lds, Fetch fetch) {
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
     const int wm = wave / CF::WN, wn = wave % CF::WN;
     const int lr = lane % 16, lq = lane / 16;
-    const int home = blockIdx.x % kXcds;
-    const int64_t *qb = tq->qb[cfg][plain], *qe = tq->qe[cfg][plain];
-    const int *tmap = (const int *)((const char *)d + tq->tmap[cfg][plain]);
-    int qi = 0;                                        // thread 0: queues tried so far
-    if (tid == 0) sh_next = next_tile(ctr, qb, qe, home, qi);
-    __syncthreads();
-    int64_t t = uniform64(sh_next);
-    while (t >= 0) {
-        int64_t nx = -1;
-        const BatchDesc &D = d[tmap[t]];
-        const int64_t MV = plain ? D.m : D.MV, NV = plain ? D.n : D.NV, K = D.k;
-        const int64_t local = t - D.s_tiles[cfg][plain];
-        // grouped order: bands of GM tile rows, column by column within a band,
-        // so the tiles running together share operand rows in L2
-        const int64_t tm_count = (MV + CF::BM - 1) / CF::BM, tn_count = (NV + CF::BN - 1) / CF::BN;
-        constexpr int GM = 1024 / CF::BM;
-        const int64_t band = local / (GM * tn_count), in_band = local - band * (GM * tn_count);
-        const int64_t gsz = min((int64_t)GM, tm_count - band * GM);
-        const int64_t tm = band * GM + in_band % gsz, tn = in_band / gsz;
-        const int64_t row0 = tm * CF::BM, col0 = tn * CF::BN;
+    const int64_t MV = plain ? D.m : D.MV, NV = plain ? D.n : D.NV, K = D.k;
+    // grouped order: bands of GM tile rows, column by column within a band,
+    // so the tiles running together share operand rows in L2
+    const int64_t tm_count = (MV + CF::BM - 1) / CF::BM, tn_count = (NV + CF::BN - 1) / CF::BN;
+    constexpr int GM = 1024 / CF::BM;
+    const int64_t band = local / (GM * tn_count), in_band = local - band * (GM * tn_count);
+    const int64_t gsz = min((int64_t)GM, tm_count - band * GM);
+    const int64_t tm = band * GM + in_band % gsz, tn = in_band / gsz;
+    const int64_t row0 = tm * CF::BM, col0 = tn * CF::BN;
 
-        const uint16_t *src[CF::LPW];
+    const uint16_t *src[CF::LPW];
+#pragma unroll
+    for (int q = 0; q < CF::LPW; ++q) {
+        const int c = (wave * CF::LPW + q) * 64 + lane;
+        const int rr = c / CF::CPR, kc = (c % CF::CPR) ^ ((rr / CF::RP) % CF::CPR);
+        const uint16_t *base;
+        if (rr < CF::BM) {
+            const int64_t gr = min(row0 + rr, MV - 1);
+            base = (const uint16_t *)(gr < D.m ? gp(D.A) + gr * D.lda : gp(D.asp) + (gr - D.m) * K);
+        } else {
+            const int64_t gc = min(col0 + (rr - CF::BM), NV - 1);
+            base = (const uint16_t *)(gc < D.n ? gp(D.Bt) + gc * D.ldb : gp(D.bsp) + (gc - D.n) * K);
+        }
+        src[q] = base + kc * 8;
+    }
+    const void *zero = (const void *)kZeroChunk;
+    auto issue = [&](int stage, int64_t k0) {
+        uint8_t *dst = lds + CF::HDR + stage * CF::STAGE + wave * CF::LPW * 1024;
+        const bool full = k0 + CF::BK <= K;
 #pragma unroll
         for (int q = 0; q < CF::LPW; ++q) {
             const int c = (wave * CF::LPW + q) * 64 + lane;
             const int rr = c / CF::CPR, kc = (c % CF::CPR) ^ ((rr / CF::RP) % CF::CPR);
-            const uint16_t *base;
-            if (rr < CF::BM) {
-                const int64_t gr = min(row0 + rr, MV - 1);
-                base = (const uint16_t *)(gr < D.m ? gp(D.A) + gr * D.lda : gp(D.asp) + (gr - D.m) * K);
-            } else {
-                const int64_t gc = min(col0 + (rr - CF::BM), NV - 1);
-                base = (const uint16_t *)(gc < D.n ? gp(D.Bt) + gc * D.ldb : gp(D.bsp) + (gc - D.n) * K);
-            }
-            src[q] = base + kc * 8;
+            const void *g = (full || k0 + kc * 8 < K) ? (const void *)(src[q] + k0) : zero;
+            __builtin_amdgcn_global_load_lds(g, (void *)(dst + q * 1024), 16, 0, 0);
         }
-        const void *zero = (const void *)kZeroChunk;
-        auto issue = [&](int stage, int64_t k0) {
-            uint8_t *dst = lds + CF::HDR + stage * CF::STAGE + wave * CF::LPW * 1024;
-            const bool full = k0 + CF::BK <= K;
+    };
+
+    v4f acc[CF::TMW][CF::TNW];
 #pragma unroll
-            for (int q = 0; q < CF::LPW; ++q) {
-                const int c = (wave * CF::LPW + q) * 64 + lane;
-                const int rr = c / CF::CPR, kc = (c % CF::CPR) ^ ((rr / CF::RP) % CF::CPR);
-                const void *g = (full || k0 + kc * 8 < K) ? (const void *)(src[q] + k0) : zero;
-                __builtin_amdgcn_global_load_lds(g, (void *)(dst + q * 1024), 16, 0, 0);
+    for (int a = 0; a < CF::TMW; ++a)
+#pragma unroll
+        for (int b = 0; b < CF::TNW; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int arow = wm * (CF::BM / CF::WM) + lr, brow = CF::BM + wn * (CF::BN / CF::WN) + lr;
+
+    const int64_t nk = (K + CF::BK - 1) / CF::BK;
+#pragma unroll
+    for (int s = 0; s < CF::NS - 1; ++s)
+        if (s < nk) issue(s, (int64_t)s * CF::BK);
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        // slab kt has landed once at most the loads of the NS - 2 later slabs are pending
+        if (kt + CF::NS - 2 < nk) __builtin_amdgcn_s_waitcnt(CF::WAIT_AHEAD);
+        else __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+        // and every wave is done with slab kt - 1.  A bare barrier: the
+        // fence of __syncthreads would wait for every slab in flight.
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (kt + CF::NS - 1 < nk) issue((int)((kt + CF::NS - 1) % CF::NS), (kt + CF::NS - 1) * CF::BK);
+        // the next tile, taken during the last slab (taken earlier, it would
+        // sit reserved while idle blocks find the queues empty)
+        if (kt == nk - 1 && tid == 0) fetch();
+        const uint8_t *S = lds + CF::HDR + (int)(kt % CF::NS) * CF::STAGE;
+#pragma unroll
+        for (int g = 0; g < CF::KGS; ++g) {
+            const int kc = 4 * g + lq;
+            v4u fa[CF::TMW], fb[CF::TNW];
+#pragma unroll
+            for (int a = 0; a < CF::TMW; ++a) {
+                const int r = arow + 16 * a;
+                fa[a] = *(const v4u *)(S + r * CF::SLAB + ((kc ^ ((r / CF::RP) % CF::CPR)) << 4));
             }
-        };
-
-        v4f acc[CF::TMW][CF::TNW];
 #pragma unroll
-        for (int a = 0; a < CF::TMW; ++a)
-#pragma unroll
-            for (int b = 0; b < CF::TNW; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-        const int arow = wm * (CF::BM / CF::WM) + lr, brow = CF::BM + wn * (CF::BN / CF::WN) + lr;
-
-        const int64_t nk = (K + CF::BK - 1) / CF::BK;
-#pragma unroll
-        for (int s = 0; s < CF::NS - 1; ++s)
-            if (s < nk) issue(s, (int64_t)s * CF::BK);
-        for (int64_t kt = 0; kt < nk; ++kt) {
-            // slab kt has landed once at most the loads of the NS - 2 later slabs are pending
-            if (kt + CF::NS - 2 < nk) __builtin_amdgcn_s_waitcnt(CF::WAIT_AHEAD);
-            else __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
-            // and every wave is done with slab kt - 1.  A bare barrier: the
-            // fence of __syncthreads would wait for every slab in flight.
-            asm volatile("" ::: "memory");
-            __builtin_amdgcn_s_barrier();
-            asm volatile("" ::: "memory");
-            if (kt + CF::NS - 1 < nk) issue((int)((kt + CF::NS - 1) % CF::NS), (kt + CF::NS - 1) * CF::BK);
-            // the next tile, taken during the last slab (taken earlier, it would
-            // sit reserved while idle blocks find the queues empty)
-            if (kt == nk - 1 && tid == 0) nx = next_tile(ctr, qb, qe, home, qi);
-            const uint8_t *S = lds + CF::HDR + (int)(kt % CF::NS) * CF::STAGE;
-#pragma unroll
-            for (int g = 0; g < CF::KGS; ++g) {
-                const int kc = 4 * g + lq;
-                v4u fa[CF::TMW], fb[CF::TNW];
-#pragma unroll
-                for (int a = 0; a < CF::TMW; ++a) {
-                    const int r = arow + 16 * a;
-                    fa[a] = *(const v4u *)(S + r * CF::SLAB + ((kc ^ ((r / CF::RP) % CF::CPR)) << 4));
-                }
-#pragma unroll
-                for (int b = 0; b < CF::TNW; ++b) {
-                    const int r = brow + 16 * b;
-                    fb[b] = *(const v4u *)(S + r * CF::SLAB + ((kc ^ ((r / CF::RP) % CF::CPR)) << 4));
-                }
-#pragma unroll
-                for (int a = 0; a < CF::TMW; ++a)
-#pragma unroll
-                    for (int b = 0; b < CF::TNW; ++b) Bf16Ops::mfma(fa[a], fb[b], acc[a][b]);
+            for (int b = 0; b < CF::TNW; ++b) {
+                const int r = brow + 16 * b;
+                fb[b] = *(const v4u *)(S + r * CF::SLAB + ((kc ^ ((r / CF::RP) % CF::CPR)) << 4));
             }
-        }
-
-        // epilogue: data block -> C; rows >= m -> S1; columns >= n of data rows -> S2
-        if (row0 + CF::BM <= D.m && col0 + CF::BN <= D.n) {
-            // interior tile: every element is a data element of C
-            G<float> *Ct = gp(D.C) + (row0 + wm * (CF::BM / CF::WM) + 4 * lq) * D.ldc + col0 + wn * (CF::BN / CF::WN) + lr;
 #pragma unroll
             for (int a = 0; a < CF::TMW; ++a)
 #pragma unroll
-                for (int b = 0; b < CF::TNW; ++b)
+                for (int b = 0; b < CF::TNW; ++b) Bf16Ops::mfma(fa[a], fb[b], acc[a][b]);
+        }
+    }
+
+    // epilogue: data block -> C; rows >= m -> S1; columns >= n of data rows -> S2
+    if (row0 + CF::BM <= D.m && col0 + CF::BN <= D.n) {
+        // interior tile: every element is a data element of C
+        G<float> *Ct = gp(D.C) + (row0 + wm * (CF::BM / CF::WM) + 4 * lq) * D.ldc + col0 + wn * (CF::BN / CF::WN) + lr;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) Ct[(16 * a + v) * D.ldc + 16 * b] = acc[a][b][v];
-        } else {
+        for (int a = 0; a < CF::TMW; ++a)
+#pragma unroll
+            for (int b = 0; b < CF::TNW; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Ct[(16 * a + v) * D.ldc + 16 * b] = acc[a][b][v];
+    } else {
 #pragma unroll
         for (int a = 0; a < CF::TMW; ++a) {
 #pragma unroll
@@ -594,9 +600,49 @@ __global__ __launch_bounds__(CF::THREADS, 1) void kb_gemm(const BatchDesc *__res
                 }
             }
         }
+    }
+}
+
+// The persistent product: 256 resident blocks take tiles from the queues of
+// map `mp` (a uniform tile shape, or kMixed: each problem's own) until they
+// are empty.  ttime (null normally): the duration of every tile in ticks of
+// the constant 100 MHz clock, for the tuner.
+template <bool TIMED>
+__global__ __launch_bounds__(kGemmThreads, 1) void kb_gemm(const BatchDesc *__restrict__ d, int mp, int plain,
+                                                           unsigned *ctr, const TileQueues *__restrict__ tq,
+                                                           uint64_t *ttime) {
+    // One LDS object only: with a second one the compiler cannot tell the
+    // fragment reads from the in-flight direct-to-LDS loads and waits for them.
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kGemmLds];
+    int64_t &sh_next = *(int64_t *)lds;               // the header holds the next tile index
+    const int tid = threadIdx.x;
+    const int home = blockIdx.x % kXcds;
+    const int64_t *qb = tq->qb[mp][plain], *qe = tq->qe[mp][plain];
+    const int *tmap = (const int *)((const char *)d + tq->tmap[mp][plain]);
+    const int sidx = mp == kMixed ? ABFT_BATCH_TILES : mp;      // which tile start of the descriptor
+    int qi = 0;                                        // thread 0: queues tried so far
+    if (tid == 0) sh_next = next_tile(ctr, qb, qe, home, qi);
+    __syncthreads();
+    int64_t t = uniform64(sh_next);
+    while (t >= 0) {
+        int64_t nx = -1;
+        const BatchDesc &D = d[tmap[t]];
+        const int64_t local = t - D.s_tiles[sidx][plain];
+        const int shape = __builtin_amdgcn_readfirstlane(mp == kMixed ? D.tile : mp);
+        auto fetch = [&]() { nx = next_tile(ctr, qb, qe, home, qi); };
+        uint64_t t0 = 0;
+        if (TIMED) t0 = __builtin_amdgcn_s_memrealtime();
+        switch (shape) {
+        case 0: gemm_tile<Cfg0>(D, local, plain, lds, fetch); break;
+        case 1: gemm_tile<Cfg1>(D, local, plain, lds, fetch); break;
+        case 2: gemm_tile<Cfg2>(D, local, plain, lds, fetch); break;
+        default: gemm_tile<Cfg3>(D, local, plain, lds, fetch); break;
         }
         __syncthreads();                                // every wave is done with the last slab's stage
-        if (tid == 0) sh_next = nx;
+        if (tid == 0) {
+            if (TIMED) ttime[t] = __builtin_amdgcn_s_memrealtime() - t0;
+            sh_next = nx;
+        }
         __syncthreads();
         t = uniform64(sh_next);
     }
@@ -677,10 +723,11 @@ __device__ inline void bfold(G<abft_report> *rep, double ratio, bool col) {
     }
 }
 
-__device__ inline double btau(const BatchDesc &D, bool col, int64_t a, int64_t b) {
+__device__ inline double btau(const BatchDesc &D, bool col, int64_t a, int64_t b, double tot) {
     if (D.mode != ABFT_TAU_STAT) return 0.0;
-    if (col) return sqrt(D.cc * (D.br == 1 ? gp(D.qc)[b] : gp(D.nv)[a] * gp(D.qc)[b]));
-    return sqrt(D.cr * (D.bc == 1 ? gp(D.qr)[a] : gp(D.qr)[a] * gp(D.nw)[b]));
+    if (!isfinite(tot)) tot = 0.0;          // no rounding term: the residual is then non-finite and fails
+    if (col) return sqrt(D.cc * (D.br == 1 ? gp(D.qc)[b] : gp(D.nv)[a] * gp(D.qc)[b]) + D.cst * tot * tot);
+    return sqrt(D.cr * (D.bc == 1 ? gp(D.qr)[a] : gp(D.qr)[a] * gp(D.nw)[b]) + D.cst * tot * tot);
 }
 
 // Verification pass 1, one read of C: one wave per (residue r, strip of
@@ -731,8 +778,9 @@ __global__ __launch_bounds__(kT) void kb_verify1(const BatchDesc *__restrict__ d
         for (int e = 0; e < kVCols; ++e) {
             const int64_t j = j0 + (int64_t)e * kW;
             if (j < D.N) {
-                const double dd = cs[e] - (double)crow[j];
-                const double tau = btau(D, true, r, j);
+                const double tot = (double)crow[j];
+                const double dd = cs[e] - tot;
+                const double tau = btau(D, true, r, j, tot);
                 bflag(gp(D.rep), true, r, j, dd, tau);
                 if (isfinite(dd) && tau > 0) ratio = fmax(ratio, fabs(dd) / tau);
             }
@@ -753,8 +801,9 @@ __global__ __launch_bounds__(kT) void kb_verify2(const BatchDesc *__restrict__ d
             const int64_t i = u / D.bc, c = u - i * D.bc, nst = (D.N + kVStrip - 1) / kVStrip;
             double s = 0.0;
             for (int64_t w = 0; w < nst; ++w) s += gp(D.vpart)[(i * nst + w) * D.bc + c];
-            const double dd = s - (double)gp(D.C)[i * D.ldc + D.n + c];
-            const double tau = btau(D, false, i, c);
+            const double tot = (double)gp(D.C)[i * D.ldc + D.n + c];
+            const double dd = s - tot;
+            const double tau = btau(D, false, i, c, tot);
             bflag(gp(D.rep), false, i, c, dd, tau);
             if (isfinite(dd) && tau > 0) ratio = fabs(dd) / tau;
         }
@@ -821,7 +870,52 @@ static int64_t tiles_of(const abft_problem &q, int c, int plain) {
     const int64_t R = plain ? q.m : q.m + 3 * q.br, Cn = plain ? q.n : q.n + 3 * q.bc;
     return ((R + kTileBM[c] - 1) / kTileBM[c]) * ((Cn + kTileBN[c] - 1) / kTileBN[c]);
 }
-static size_t tmap_bytes(const abft_problem *probs, int count) {
+
+// The model's tile for a problem (used until a tuned choice is given): the
+// executed tile area over a per-shape efficiency, the smallest wins.  The
+// efficiencies are the relative rates of the shapes on large products,
+// measured on MI355X (256 x 256 = 1).
+static int model_tile(const abft_problem &q) {
+    static const double eff[ABFT_BATCH_TILES] = {1.0, 0.86, 0.86, 0.62};
+    int best = 0;
+    double cost = 0.0;
+    for (int c = 0; c < ABFT_BATCH_TILES; ++c) {
+        const double x = (double)tiles_of(q, c, 0) * kTileBM[c] * kTileBN[c] / eff[c];
+        if (c == 0 || x < cost) { cost = x; best = c; }
+    }
+    return best;
+}
+
+static int64_t max_tiles(const abft_problem *probs, int count) {
+    int64_t mx = 0;
+    for (int c = 0; c < ABFT_BATCH_TILES; ++c) {
+        int64_t n = 0;
+        for (int p = 0; p < count; ++p) n += tiles_of(probs[p], c, 0);
+        mx = std::max(mx, n);
+    }
+    return mx;
+}
+
+// per-problem tile shapes: the caller's where given (0 .. ABFT_BATCH_TILES-1), else the model's
+static int tile_choice(const abft_problem *probs, const int32_t *tiles, int p) {
+    return (tiles && tiles[p] >= 0 && tiles[p] < ABFT_BATCH_TILES) ? tiles[p] : model_tile(probs[p]);
+}
+
+static size_t tmap_bytes(const abft_problem *probs, const int32_t *tiles, int count) {
+    size_t s = 0;
+    for (int c = 0; c < kMaps; ++c)
+        for (int pl = 0; pl < 2; ++pl) {
+            int64_t n = 0;
+            for (int p = 0; p < count; ++p) n += tiles_of(probs[p], c == kMixed ? tile_choice(probs, tiles, p) : c, pl);
+            s += align256(sizeof(int) * n);
+        }
+    return s;
+}
+
+// The tile map of the mixed shapes is sized for the largest shape count any
+// choice can give (the map is rewritten when the choice changes); plus the
+// tuner's per-tile durations.
+static size_t tmap_bytes_any(const abft_problem *probs, int count) {
     size_t s = 0;
     for (int c = 0; c < ABFT_BATCH_TILES; ++c)
         for (int pl = 0; pl < 2; ++pl) {
@@ -829,17 +923,26 @@ static size_t tmap_bytes(const abft_problem *probs, int count) {
             for (int p = 0; p < count; ++p) n += tiles_of(probs[p], c, pl);
             s += align256(sizeof(int) * n);
         }
-    return s;
+    for (int pl = 0; pl < 2; ++pl) {
+        int64_t n = 0;
+        for (int p = 0; p < count; ++p) {
+            int64_t mx = 0;
+            for (int c = 0; c < ABFT_BATCH_TILES; ++c) mx = std::max(mx, tiles_of(probs[p], c, pl));
+            n += mx;
+        }
+        s += align256(sizeof(int) * n);
+    }
+    return s + align256(sizeof(uint64_t) * max_tiles(probs, count));
 }
 
 size_t batch_workspace_size(const abft_problem *probs, int count) {
-    size_t s = header_bytes(count) + tmap_bytes(probs, count);
+    size_t s = header_bytes(count) + tmap_bytes_any(probs, count);
     for (int p = 0; p < count; ++p) s += parts_of(probs[p]).total();
     return s;
 }
 
-int batch_setup(const abft_problem *probs, const abft_batch_item *items, int count, void *bws, size_t bytes,
-                abft_batch_plan *plan) {
+int batch_setup(const abft_problem *probs, const abft_batch_item *items, int count, const int32_t *tiles, void *bws,
+                size_t bytes, abft_batch_plan *plan) {
     if (count < 1 || !probs || !items || !bws || !plan) return ABFT_E_ARG;
     if ((uintptr_t)bws & 255u) return ABFT_E_ARG;
     for (int p = 0; p < count; ++p) {
@@ -864,25 +967,33 @@ int batch_setup(const abft_problem *probs, const abft_batch_item *items, int cou
     const size_t off_ctr = align256(sizeof(BatchDesc) * count);
     abft_report *reps = (abft_report *)(base + off_ctr + kCtlBytes);
     TileQueues tq;
-    for (int c = 0; c < ABFT_BATCH_TILES; ++c)
+    for (int c = 0; c < kMaps; ++c)
         for (int pl = 0; pl < 2; ++pl)
             for (int x = 0; x < kXcds; ++x) tq.qb[c][pl][x] = tq.qe[c][pl][x] = 0;
-    // per-tile problem maps, then the per-problem arrays
+    // per-tile problem maps (the uniform shapes, then the mixed one, sized for
+    // any choice), the tuner's durations, then the per-problem arrays
     size_t off = header_bytes(count);
-    std::vector<int> tmaps[ABFT_BATCH_TILES][2];
-    size_t tmap_off[ABFT_BATCH_TILES][2];
-    for (int c = 0; c < ABFT_BATCH_TILES; ++c)
+    std::vector<int> tmaps[kMaps][2];
+    size_t tmap_off[kMaps][2];
+    for (int c = 0; c < kMaps; ++c)
         for (int pl = 0; pl < 2; ++pl) {
-            int64_t n = 0;
-            for (int p = 0; p < count; ++p) n += tiles_of(probs[p], c, pl);
-            if (n >= (int64_t)INT32_MAX) return ABFT_E_ARG;
+            int64_t n = 0, cap = 0;
+            for (int p = 0; p < count; ++p) {
+                n += tiles_of(probs[p], c == kMixed ? tile_choice(probs, tiles, p) : c, pl);
+                int64_t mx = 0;
+                for (int e = 0; e < ABFT_BATCH_TILES; ++e) mx = std::max(mx, tiles_of(probs[p], e, pl));
+                cap += c == kMixed ? mx : tiles_of(probs[p], c, pl);
+            }
+            if (cap >= (int64_t)INT32_MAX) return ABFT_E_ARG;
             tmaps[c][pl].reserve(n);
             tmap_off[c][pl] = off;
             tq.tmap[c][pl] = (int64_t)off;
-            off += align256(sizeof(int) * n);
+            off += align256(sizeof(int) * cap);
         }
+    const size_t ttime_off = off;
+    off += align256(sizeof(uint64_t) * max_tiles(probs, count));
     std::vector<BatchDesc> h(count);
-    int64_t tiles[ABFT_BATCH_TILES][2] = {};
+    int64_t ntl[kMaps][2] = {};
     int64_t w[8] = {};
     for (int s = 0; s < count; ++s) {
         const int p = order[s];
@@ -913,14 +1024,15 @@ int batch_setup(const abft_problem *probs, const abft_batch_item *items, int cou
         D.vpart = (double *)(base + off); off += b.vpart;
         D.rep = reps + p;
         D.orig = p;
+        D.tile = tile_choice(probs, tiles, p);
         TauCoef tc = tau_coef(&q);
-        D.cc = tc.cc; D.cr = tc.cr; D.mode = q.tau_mode;
-        for (int c = 0; c < ABFT_BATCH_TILES; ++c) {
+        D.cc = tc.cc; D.cr = tc.cr; D.cst = tc.cst; D.mode = q.tau_mode;
+        for (int c = 0; c < kMaps; ++c) {
             for (int pl = 0; pl < 2; ++pl) {
-                D.s_tiles[c][pl] = tiles[c][pl];
-                const int64_t nt = tiles_of(q, c, pl);
+                D.s_tiles[c][pl] = ntl[c][pl];
+                const int64_t nt = tiles_of(q, c == kMixed ? D.tile : c, pl);
                 tmaps[c][pl].insert(tmaps[c][pl].end(), (size_t)nt, s);
-                tiles[c][pl] += nt;
+                ntl[c][pl] += nt;
             }
         }
         const int64_t kv = q.k / 8;
@@ -934,37 +1046,43 @@ int batch_setup(const abft_problem *probs, const abft_batch_item *items, int cou
         D.s_vcol = w[W_VCOL]; w[W_VCOL] += pad_h(q.br * ((q.n + q.bc + kVStrip - 1) / kVStrip), kT / kW);
         D.s_vrow = w[W_VROW]; w[W_VROW] += pad_h((q.m + q.br) * q.bc, kT);
     }
-    // queue cuts: equal shares of the total tile work
-    for (int c = 0; c < ABFT_BATCH_TILES; ++c)
+    // queue cuts: equal shares of the total tile work (tile area x k)
+    for (int c = 0; c < kMaps; ++c)
         for (int pl = 0; pl < 2; ++pl) {
             const std::vector<int> &tm = tmaps[c][pl];
+            auto work = [&](int v) {
+                const int sh = c == kMixed ? h[v].tile : c;
+                return (double)kTileBM[sh] * kTileBN[sh] * (double)h[v].k;
+            };
             double total = 0.0;
-            for (int v : tm) total += (double)h[v].k;
+            for (int v : tm) total += work(v);
             double acc = 0.0;
             int64_t t = 0;
             for (int x = 0; x < kXcds; ++x) {
                 tq.qb[c][pl][x] = t;
                 const double goal = total * (x + 1) / kXcds;
-                while (t < (int64_t)tm.size() && (x == kXcds - 1 || acc + 0.5 * (double)h[tm[t]].k <= goal))
-                    acc += (double)h[tm[t++]].k;
+                while (t < (int64_t)tm.size() && (x == kXcds - 1 || acc + 0.5 * work(tm[t]) <= goal))
+                    acc += work(tm[t++]);
                 tq.qe[c][pl][x] = t;
             }
         }
     ABFT_HIP(hipMemcpy(bws, h.data(), sizeof(BatchDesc) * count, hipMemcpyHostToDevice));
-    for (int c = 0; c < ABFT_BATCH_TILES; ++c)
+    for (int c = 0; c < kMaps; ++c)
         for (int pl = 0; pl < 2; ++pl)
-            ABFT_HIP(hipMemcpy(base + tmap_off[c][pl], tmaps[c][pl].data(), sizeof(int) * tmaps[c][pl].size(),
-                               hipMemcpyHostToDevice));
+            if (!tmaps[c][pl].empty())
+                ABFT_HIP(hipMemcpy(base + tmap_off[c][pl], tmaps[c][pl].data(), sizeof(int) * tmaps[c][pl].size(),
+                                   hipMemcpyHostToDevice));
     std::vector<char> ctl(kCtlBytes, 0);                // zero counters, then the queue table
     std::memcpy(ctl.data() + 256, &tq, sizeof(tq));
     ABFT_HIP(hipMemcpy(base + off_ctr, ctl.data(), kCtlBytes, hipMemcpyHostToDevice));
     plan->bws = bws;
     plan->count = count;
     plan->dtype = ABFT_BF16;
-    for (int c = 0; c < ABFT_BATCH_TILES; ++c) {
-        plan->n_tiles[c][0] = tiles[c][0];
-        plan->n_tiles[c][1] = tiles[c][1];
+    for (int c = 0; c < kMaps; ++c) {
+        plan->n_tiles[c][0] = ntl[c][0];
+        plan->n_tiles[c][1] = ntl[c][1];
     }
+    plan->ttime_off = ttime_off;
     for (int e = 0; e < 8; ++e) plan->n_work[e] = w[e];
     plan->bytes = need;
     return ABFT_OK;
@@ -995,22 +1113,17 @@ int batch_encode(const abft_batch_plan *pl, bool quantize, hipStream_t s) {
     return ABFT_OK;
 }
 
-template <class CF>
-static void launch_cfg(const abft_batch_plan *pl, int cfg, int plain, hipStream_t s) {
-    // a whole number of blocks per XCD (256 CUs, BPC blocks each)
+static void launch_gemm_map(const abft_batch_plan *pl, int mp, int plain, uint64_t *ttime, hipStream_t s) {
+    // one block per CU: a whole number of blocks per XCD
     const TileQueues *tq = (const TileQueues *)((const char *)counters(pl) + 256);
-    kb_gemm<CF><<<256 * CF::BPC, CF::THREADS, 0, s>>>(descs(pl), cfg, plain, counters(pl), tq);
+    if (ttime) kb_gemm<true><<<256, kGemmThreads, 0, s>>>(descs(pl), mp, plain, counters(pl), tq, ttime);
+    else kb_gemm<false><<<256, kGemmThreads, 0, s>>>(descs(pl), mp, plain, counters(pl), tq, nullptr);
 }
 
 int batch_gemm(const abft_batch_plan *pl, int tile, uint32_t flags, hipStream_t s) {
-    if (tile < 0 || tile >= ABFT_BATCH_TILES) return ABFT_E_ARG;
+    if (tile < 0 || tile > ABFT_BATCH_MIXED) return ABFT_E_ARG;
     const int plain = (flags & ABFT_PLAIN) ? 1 : 0;
-    switch (tile) {
-    case 0: launch_cfg<Cfg0>(pl, 0, plain, s); break;
-    case 1: launch_cfg<Cfg1>(pl, 1, plain, s); break;
-    case 2: launch_cfg<Cfg2>(pl, 2, plain, s); break;
-    default: launch_cfg<Cfg3>(pl, 3, plain, s); break;
-    }
+    launch_gemm_map(pl, tile, plain, nullptr, s);
     ABFT_LAUNCHED();
     if (!plain) {
         const int64_t n = pl->n_work[W_COMB];
@@ -1035,26 +1148,102 @@ int batch_reports(const abft_batch_plan *pl, abft_report *host, hipStream_t s) {
     return ABFT_OK;
 }
 
-int batch_tune(const abft_batch_plan *pl, int *best, hipStream_t s) {
-    float t[ABFT_BATCH_TILES];
-    hipEvent_t e0, e1;
-    ABFT_HIP(hipEventCreate(&e0));
-    ABFT_HIP(hipEventCreate(&e1));
-    int st = ABFT_OK;
-    for (int tile = 0; tile < ABFT_BATCH_TILES && st == ABFT_OK; ++tile) {
-        if ((st = batch_gemm(pl, tile, 0, s))) break;           // warm-up
-        if (hipEventRecord(e0, s) != hipSuccess) { st = ABFT_E_HIP; break; }
-        for (int r = 0; r < 3 && st == ABFT_OK; ++r) st = batch_gemm(pl, tile, 0, s);
-        if (st) break;
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&t[tile], e0, e1) != hipSuccess)
-            st = ABFT_E_HIP;
+// Tuner: each uniform tile shape runs once with the durations of its tiles
+// recorded (after a warm-up launch); a problem's cost for a shape is the sum
+// of its tiles' durations (CU time, in ticks of the 100 MHz clock).
+int batch_tune(const abft_batch_plan *pl, double *costs, int32_t *best, hipStream_t s) {
+    const int count = pl->count;
+    std::vector<BatchDesc> h(count);
+    ABFT_HIP(hipMemcpy(h.data(), pl->bws, sizeof(BatchDesc) * count, hipMemcpyDeviceToHost));
+    uint64_t *ttime = (uint64_t *)((char *)pl->bws + pl->ttime_off);
+    std::vector<uint64_t> tt;
+    std::vector<double> cost((size_t)count * ABFT_BATCH_TILES, 0.0);
+    for (int c = 0; c < ABFT_BATCH_TILES; ++c) {
+        launch_gemm_map(pl, c, 0, nullptr, s);            // warm-up
+        launch_gemm_map(pl, c, 0, ttime, s);
+        ABFT_LAUNCHED();
+        tt.resize((size_t)pl->n_tiles[c][0]);
+        ABFT_HIP(hipMemcpyAsync(tt.data(), ttime, sizeof(uint64_t) * tt.size(), hipMemcpyDeviceToHost, s));
+        ABFT_HIP(hipStreamSynchronize(s));
+        for (int v = 0; v < count; ++v) {
+            const int64_t t0 = h[v].s_tiles[c][0], t1 = v + 1 < count ? h[v + 1].s_tiles[c][0] : pl->n_tiles[c][0];
+            double sum = 0.0;
+            for (int64_t t = t0; t < t1; ++t) sum += (double)tt[(size_t)t];
+            cost[(size_t)h[v].orig * ABFT_BATCH_TILES + c] = sum;
+        }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (st) return st;
-    *best = (int)(std::min_element(t, t + ABFT_BATCH_TILES) - t);
+    for (int p = 0; p < count; ++p) {
+        const double *cp = &cost[(size_t)p * ABFT_BATCH_TILES];
+        if (costs) std::copy(cp, cp + ABFT_BATCH_TILES, costs + (size_t)p * ABFT_BATCH_TILES);
+        if (best) best[p] = (int32_t)(std::min_element(cp, cp + ABFT_BATCH_TILES) - cp);
+    }
     return ABFT_OK;
+}
+
+// ------------------------------------------------------------------ tuning cache
+// A text file, one line per bucket:
+//   <dtype> <m bucket> <n bucket> <k bucket> <br> <bc> <arch> <problems> <cost of each shape>
+// Buckets: m and n in steps of 128, k by powers of two.  The shape of a bucket
+// is the one with the least summed cost over the problems measured in it.
+struct CacheKey {
+    int dtype;
+    int64_t mb, nb, kb, br, bc;
+    std::string arch;
+    bool operator<(const CacheKey &o) const {
+        return std::tie(dtype, mb, nb, kb, br, bc, arch) < std::tie(o.dtype, o.mb, o.nb, o.kb, o.br, o.bc, o.arch);
+    }
+};
+struct CacheVal {
+    int64_t problems = 0;
+    double cost[ABFT_BATCH_TILES] = {};
+};
+static CacheKey cache_key(const abft_problem &q, const char *arch) {
+    CacheKey k;
+    k.dtype = q.dtype;
+    k.mb = (q.m + 127) / 128;
+    k.nb = (q.n + 127) / 128;
+    int64_t kb = 0;
+    while ((int64_t(1) << kb) < q.k) ++kb;
+    k.kb = kb;
+    k.br = q.br;
+    k.bc = q.bc;
+    k.arch = arch;
+    return k;
+}
+static bool read_cache(const char *path, std::map<CacheKey, CacheVal> &out) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        CacheKey k;
+        CacheVal v;
+        char dt[16], arch[64];
+        long long mb, nb, kb, br, bc, np;
+        double c[4];
+        if (std::sscanf(line, "%15s %lld %lld %lld %lld %lld %63s %lld %lf %lf %lf %lf", dt, &mb, &nb, &kb, &br, &bc,
+                        arch, &np, &c[0], &c[1], &c[2], &c[3]) != 12)
+            continue;
+        if (std::strcmp(dt, "bf16") != 0) continue;
+        k.dtype = ABFT_BF16; k.mb = mb; k.nb = nb; k.kb = kb; k.br = br; k.bc = bc; k.arch = arch;
+        v.problems = np;
+        for (int e = 0; e < ABFT_BATCH_TILES; ++e) v.cost[e] = c[e];
+        out[k] = v;
+    }
+    std::fclose(f);
+    return true;
+}
+static int best_of(const CacheVal &v) {
+    return (int)(std::min_element(v.cost, v.cost + ABFT_BATCH_TILES) - v.cost);
+}
+static bool device_arch(std::string &arch) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    return true;
 }
 
 }  // namespace abft
@@ -1071,7 +1260,11 @@ size_t abft_batch_workspace_size(const abft_problem *probs, int count) {
 }
 int abft_batch_setup(const abft_problem *probs, const abft_batch_item *items, int count, void *bws, size_t bws_bytes,
                      abft_batch_plan *plan) {
-    return batch_setup(probs, items, count, bws, bws_bytes, plan);
+    return batch_setup(probs, items, count, nullptr, bws, bws_bytes, plan);
+}
+int abft_batch_setup_tiles(const abft_problem *probs, const abft_batch_item *items, int count, const int32_t *tiles,
+                           void *bws, size_t bws_bytes, abft_batch_plan *plan) {
+    return batch_setup(probs, items, count, tiles, bws, bws_bytes, plan);
 }
 int abft_batch_quantize(const abft_batch_plan *plan, void *stream) {
     if (!plan || !plan->bws) return ABFT_E_ARG;
@@ -1089,9 +1282,53 @@ int abft_batch_gemm(const abft_batch_plan *plan, int tile, uint32_t flags, void 
     if (!plan || !plan->bws || (flags & ~ABFT_PLAIN)) return ABFT_E_ARG;
     return batch_gemm(plan, tile, flags, (hipStream_t)stream);
 }
-int abft_batch_tune(const abft_batch_plan *plan, int *best_tile, void *stream) {
-    if (!plan || !plan->bws || !best_tile) return ABFT_E_ARG;
-    return batch_tune(plan, best_tile, (hipStream_t)stream);
+int abft_batch_tune(const abft_batch_plan *plan, double *costs, int32_t *tiles, void *stream) {
+    if (!plan || !plan->bws || (!costs && !tiles)) return ABFT_E_ARG;
+    return batch_tune(plan, costs, tiles, (hipStream_t)stream);
+}
+int abft_batch_cache_lookup(const char *path, const char *arch, const abft_problem *probs, int count, int32_t *tiles) {
+    if (!path || !probs || !tiles || count < 1) return ABFT_E_ARG;
+    std::string a = arch ? arch : "";
+    if (!arch && !device_arch(a)) return ABFT_E_HIP;
+    std::map<CacheKey, CacheVal> cache;
+    read_cache(path, cache);
+    int found = 0;
+    for (int p = 0; p < count; ++p) {
+        const auto it = cache.find(cache_key(probs[p], a.c_str()));
+        tiles[p] = it == cache.end() ? -1 : best_of(it->second);
+        found += it != cache.end();
+    }
+    return found;
+}
+int abft_batch_cache_store(const char *path, const char *arch, const abft_problem *probs, int count,
+                           const double *costs) {
+    if (!path || !probs || !costs || count < 1) return ABFT_E_ARG;
+    std::string a = arch ? arch : "";
+    if (!arch && !device_arch(a)) return ABFT_E_HIP;
+    std::map<CacheKey, CacheVal> cache;
+    read_cache(path, cache);
+    std::map<CacheKey, CacheVal> fresh;
+    for (int p = 0; p < count; ++p) {
+        if (probs[p].dtype != ABFT_BF16) return ABFT_E_ARG;
+        CacheVal &v = fresh[cache_key(probs[p], a.c_str())];
+        v.problems += 1;
+        for (int e = 0; e < ABFT_BATCH_TILES; ++e) v.cost[e] += costs[(size_t)p * ABFT_BATCH_TILES + e];
+    }
+    for (const auto &kv : fresh) cache[kv.first] = kv.second;      // a new measurement replaces the old one
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return ABFT_E_ARG;
+    std::fprintf(f, "# batched product tile shapes: dtype m/128 n/128 log2(k) br bc arch problems "
+                    "cost(256x256) cost(256x128) cost(128x256) cost(128x128) (ticks of 10 ns)\n");
+    for (const auto &kv : cache) {
+        const CacheKey &k = kv.first;
+        const CacheVal &v = kv.second;
+        std::fprintf(f, "bf16 %lld %lld %lld %lld %lld %s %lld %.0f %.0f %.0f %.0f\n", (long long)k.mb, (long long)k.nb,
+                     (long long)k.kb, (long long)k.br, (long long)k.bc, k.arch.c_str(), (long long)v.problems, v.cost[0],
+                     v.cost[1], v.cost[2], v.cost[3]);
+    }
+    std::fclose(f);
+    return std::rename(tmp.c_str(), path) == 0 ? ABFT_OK : ABFT_E_ARG;
 }
 int abft_batch_verify(const abft_batch_plan *plan, void *stream) {
     if (!plan || !plan->bws) return ABFT_E_ARG;

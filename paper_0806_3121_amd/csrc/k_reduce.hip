@@ -688,6 +688,7 @@ struct VerifyArgs {
     int64_t m, n, br, bc, S, Gr, Gc, M, N, ldc;
     int mode;
     double cc, cr;                  // det coefficients; stat: cc = lambda^2 (u^2/3)(T/2 + s)
+    double cst;                     // stat: lambda^2 u^2 / 3 (the stored total's binary32 rounding)
     const double *na, *na_abs, *nb, *nb_abs;
     const double *chain_a, *chain_w; // det: inherited term of a chained product (zero otherwise)
     const double *qr, *qc, *nv, *nw;
@@ -699,18 +700,27 @@ struct VerifyArgs {
 };
 
 // det:  tau_c = cc ||(C_C^T|A|)[r,:]||_2 ||B_f[:,j]||_2
-// stat: tau_c = sqrt(cc Q_c[r,j]),  Q_c = qc[j] (br = 1, exact) or nv[r] qc[j] (Cauchy-Schwarz bound)
+// stat: tau_c = sqrt(s^2 cc Q_c[r,j] + cst tot^2),  Q_c = qc[j] (br = 1, exact) or nv[r] qc[j]
+//       (Cauchy-Schwarz bound), s the FP8 result scale (Q is in the scaled domain), tot the
+//       relation's stored total as read from C_f; a non-finite total adds no term (its
+//       residual is then non-finite and the relation fails, as it must)
 __device__ inline double tau_scale(const VerifyArgs &a) {
     return a.scale_exp ? ldexp(1.0, -(a.scale_exp[0] + a.scale_exp[1])) : 1.0;
 }
-__device__ inline double tau_col(const VerifyArgs &a, int64_t r, int64_t j) {
+__device__ inline double tau_col(const VerifyArgs &a, int64_t r, int64_t j, double tot) {
     if (a.mode == ABFT_TAU_DET) return tau_scale(a) * a.cc * a.na_abs[r] * a.nb[j] + a.chain_a[r] * a.chain_w[j];
-    if (a.mode == ABFT_TAU_STAT) return tau_scale(a) * sqrt(a.cc * (a.br == 1 ? a.qc[j] : a.nv[r] * a.qc[j]));
+    if (a.mode == ABFT_TAU_STAT) {
+        const double sc = tau_scale(a), t = isfinite(tot) ? tot : 0.0;
+        return sqrt(sc * sc * a.cc * (a.br == 1 ? a.qc[j] : a.nv[r] * a.qc[j]) + a.cst * t * t);
+    }
     return 0.0;
 }
-__device__ inline double tau_row(const VerifyArgs &a, int64_t i, int64_t c) {
+__device__ inline double tau_row(const VerifyArgs &a, int64_t i, int64_t c, double tot) {
     if (a.mode == ABFT_TAU_DET) return tau_scale(a) * a.cr * a.na[i] * a.nb_abs[c];
-    if (a.mode == ABFT_TAU_STAT) return tau_scale(a) * sqrt(a.cr * (a.bc == 1 ? a.qr[i] : a.qr[i] * a.nw[c]));
+    if (a.mode == ABFT_TAU_STAT) {
+        const double sc = tau_scale(a), t = isfinite(tot) ? tot : 0.0;
+        return sqrt(sc * sc * a.cr * (a.bc == 1 ? a.qr[i] : a.qr[i] * a.nw[c]) + a.cst * t * t);
+    }
     return 0.0;
 }
 
@@ -721,7 +731,7 @@ __device__ inline void finish_col(const VerifyArgs &a, const T *C, int64_t r, in
     double tot = 0.0;
     for (int64_t q = 0; q < a.S; ++q) tot += elem<T>::load(C + (a.m + q * a.br + r) * a.ldc + j);
     if (col_rel_erased(a.er, r, j, a.br)) { excl++; return; }
-    ratio = fmax(ratio, record(a.rep, true, r, j, s - tot, tau_col(a, r, j)));
+    ratio = fmax(ratio, record(a.rep, true, r, j, s - tot, tau_col(a, r, j, tot)));
 }
 
 // V consecutive elements of a C row: one 16-byte load (V > 1, aligned rows) or one element.
@@ -800,7 +810,7 @@ __device__ inline void finish_row(const VerifyArgs &a, const T *C, int64_t i, in
     double tot = 0.0;
     for (int64_t q = 0; q < a.S; ++q) tot += elem<T>::load(C + i * a.ldc + a.n + q * a.bc + c);
     if (row_rel_erased(a.er, i, c, a.bc)) { excl++; return; }
-    ratio = fmax(ratio, record(a.rep, false, i, c, s - tot, tau_row(a, i, c)));
+    ratio = fmax(ratio, record(a.rep, false, i, c, s - tot, tau_row(a, i, c, tot)));
 }
 
 // One thread per row relation; lanes take consecutive c (coalesced when bc >= 64).
@@ -928,7 +938,7 @@ __global__ __launch_bounds__(kThreads) void k_vblock(const T *C, VerifyArgs a, E
 #pragma unroll
                 for (int h = 0; h < GC; ++h) rs += v[h][q];
                 if (er.n && row_erased_res(er, i, c0 + q, a.bc)) excl_r++;
-                else ratio_r = fmax(ratio_r, record(a.rep, false, i, c0 + q, rs - v[GC][q], tau_row(a, i, c0 + q)));
+                else ratio_r = fmax(ratio_r, record(a.rep, false, i, c0 + q, rs - v[GC][q], tau_row(a, i, c0 + q, v[GC][q])));
             }
         };
         for (int64_t g = 0; g < a.Gr; ++g) {
@@ -955,7 +965,7 @@ __global__ __launch_bounds__(kThreads) void k_vblock(const T *C, VerifyArgs a, E
             for (int q = 0; q < V; ++q) {
                 const int64_t j = h * a.bc + c0 + q;
                 if (er.n && col_erased_res(er, r, j, a.br)) excl_c++;
-                else ratio_c = fmax(ratio_c, record(a.rep, true, r, j, cs[h][q] - v[h][q], tau_col(a, r, j)));
+                else ratio_c = fmax(ratio_c, record(a.rep, true, r, j, cs[h][q] - v[h][q], tau_col(a, r, j, v[h][q])));
             }
     }
     fold_block(ratio_c, excl_c, &a.rep->max_ratio_c, &a.rep->n_excl_c);
@@ -1129,7 +1139,7 @@ static int verify_typed(const abft_problem *p, const T *C, const Erasures &er, c
     VerifyArgs a{};
     a.m = g.m; a.n = g.n; a.br = g.br; a.bc = g.bc; a.S = g.S; a.Gr = g.Gr; a.Gc = g.Gc; a.M = g.M; a.N = g.N;
     a.ldc = p->ldc;
-    a.mode = tc.mode; a.cc = tc.cc; a.cr = tc.cr;
+    a.mode = tc.mode; a.cc = tc.cc; a.cr = tc.cr; a.cst = tc.cst;
     a.na = (const double *)(ws + L.na); a.na_abs = (const double *)(ws + L.na_abs);
     a.nb = (const double *)(ws + L.nb); a.nb_abs = (const double *)(ws + L.nb_abs);
     a.chain_a = (const double *)(ws + L.chain_a); a.chain_w = (const double *)(ws + L.chain_w);
@@ -1205,7 +1215,7 @@ static int verify_fused_typed(const abft_problem *p, const T *C, char *ws, int64
     VerifyArgs a{};
     a.m = g.m; a.n = g.n; a.br = g.br; a.bc = g.bc; a.S = g.S; a.Gr = g.Gr; a.Gc = g.Gc; a.M = g.M; a.N = g.N;
     a.ldc = p->ldc;
-    a.mode = tc.mode; a.cc = tc.cc; a.cr = tc.cr;
+    a.mode = tc.mode; a.cc = tc.cc; a.cr = tc.cr; a.cst = tc.cst;
     a.na = (const double *)(ws + L.na); a.na_abs = (const double *)(ws + L.na_abs);
     a.nb = (const double *)(ws + L.nb); a.nb_abs = (const double *)(ws + L.nb_abs);
     a.chain_a = (const double *)(ws + L.chain_a); a.chain_w = (const double *)(ws + L.chain_w);

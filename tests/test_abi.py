@@ -283,6 +283,28 @@ def test_batch_setup_rejects_before_any_copy():
     assert L.abft_batch_verify(None, None) == abft.ABFT_E_ARG
 
 
+def test_batch_tile_cache_round_trip(tmp_path):
+    """Host only: costs stored per bucket (m, n by 128, k by powers of two,
+    br, bc, arch) and looked up again; a bucket's shape is the least summed
+    cost of its problems; other architectures and unseen buckets are absent."""
+    P = lambda m, n, k: abft.problem(abft.ABFT_BF16, m, n, k, 32, 1, ldc=n + 4, tau_mode=abft.ABFT_TAU_STAT)
+    probs = [P(64, 96, 100), P(96, 128, 128), P(1024, 2048, 1024), P(640, 64, 300)]
+    costs = [[4.0, 3.0, 2.0, 1.0], [1.0, 9.0, 9.0, 9.0], [1.0, 2.0, 3.0, 4.0], [5.0, 1.0, 5.0, 5.0]]
+    path = str(tmp_path / "tiles.txt")
+    abft.batch_cache_store(path, probs, costs, arch="gfx950")
+    found, tiles = abft.batch_cache_lookup(path, probs, arch="gfx950")
+    # problems 0 and 1 share a bucket (m, n <= 128, k in (64, 128]): summed costs [5, 12, 11, 10] -> shape 0
+    assert found == 4 and tiles == [0, 0, 0, 1]
+    found, tiles = abft.batch_cache_lookup(path, probs, arch="gfx942")
+    assert found == 0 and tiles == [-1] * 4
+    found, tiles = abft.batch_cache_lookup(path, [P(2048, 2048, 2048)], arch="gfx950")
+    assert found == 0 and tiles == [-1]
+    # a new measurement of a bucket replaces the old one, other buckets stay
+    abft.batch_cache_store(path, [P(1024, 2048, 1024)], [[9.0, 9.0, 9.0, 1.0]], arch="gfx950")
+    found, tiles = abft.batch_cache_lookup(path, probs, arch="gfx950")
+    assert found == 4 and tiles == [0, 0, 3, 1]
+
+
 # ---------------------------------------------------------------- weighted f-checksums
 def test_weighted_struct_sizes():
     assert C.sizeof(abft.abft_wproblem) == C.sizeof(abft.abft_problem) + 4 + 4 + 8 + 8

@@ -60,10 +60,14 @@ class Case:
             A = orc.bf16_bits_to_f64(Aq)
             Bm = orc.bf16_bits_to_f64(Bq)
             Af, Bf = orc.encode(A, Bm, br, bc, store_f32=True)
-            C32 = orc.gemm(Af, Bf).astype(np.float32)
-            tc, tr = orc.tau_stat(Af, Bf, m, n, br, bc, u_acc=U32, T=k / 4.0, s_store=2.0, lam=LAMBDA)
+            C64 = orc.gemm(Af, Bf)
+            C32 = C64.astype(np.float32)
+            tc, tr = orc.tau_stat(Af, Bf, m, n, br, bc, u_acc=U32, T=k / 4.0, s_store=2.0, lam=LAMBDA, Cf=C64)
+            retau = (lambda Af, Bf, m, n, k, br, bc: lambda Cx: orc.tau_stat(
+                Af, Bf, m, n, br, bc, u_acc=U32, T=k / 4.0, s_store=2.0, lam=LAMBDA,
+                Cf=np.asarray(Cx, dtype=np.float64)))(Af, Bf, m, n, k, br, bc)
             bound = k * U32 * (np.abs(Af) @ np.abs(Bf)) + U32 * np.abs(C32)
-            self.ref.append(dict(Aq=Aq, Bq=Bq, C32=C32, tc=tc, tr=tr, bound=bound))
+            self.ref.append(dict(Aq=Aq, Bq=Bq, C32=C32, tc=tc, tr=tr, bound=bound, retau=retau))
         torch.cuda.synchronize()
 
     def run(self, tile):
@@ -103,17 +107,33 @@ def test_batch_product_and_clean_verify(case, tile):
     note(f"  max |D|/tau {max(max(x.max_ratio_c, x.max_ratio_r) for x in reps):.4f}")
 
 
-def test_batch_tiles_agree_and_tune(case):
+def test_batch_tiles_agree_and_tune(case, tmp_path):
+    """Every tile shape, and each problem with its own (the model's, then
+    the tuner's), gives the same C bit for bit; the tuner measures every
+    problem under every shape; its costs round-trip through the cache file."""
     case.run(0)
     C0 = [c.clone() for c in case.B.C]
-    for tile in range(1, abft.ABFT_BATCH_TILES):
+    for tile in list(range(1, abft.ABFT_BATCH_TILES)) + [abft.ABFT_BATCH_MIXED]:
         note(f"tile {tile} vs tile 0")
         case.run(tile)
         torch.cuda.synchronize()
         for q in range(len(C0)):
             assert torch.equal(C0[q], case.B.C[q]), (tile, q)
-    best = abft.batch_tune(case.B.plan)
-    assert 0 <= best < abft.ABFT_BATCH_TILES
+    costs, tiles = abft.batch_tune(case.B.plan)
+    assert len(tiles) == len(case.shapes) and all(0 <= t < abft.ABFT_BATCH_TILES for t in tiles)
+    assert all(c > 0 for row in costs for c in row)
+    assert all(row[t] == min(row) for row, t in zip(costs, tiles))
+    note(f"  tuned shapes {tiles}")
+    case.B.set_tiles(tiles)
+    reps = case.run(abft.ABFT_BATCH_MIXED)
+    torch.cuda.synchronize()
+    for q in range(len(C0)):
+        assert torch.equal(C0[q], case.B.C[q]), ("tuned", q)
+        assert reps[q].n_flag_c == 0 and reps[q].n_flag_r == 0
+    path = str(tmp_path / "batch_tiles.txt")
+    abft.batch_cache_store(path, case.B.probs, costs, arch="gfx950")
+    found, cached = abft.batch_cache_lookup(path, case.B.probs, arch="gfx950")
+    assert found == len(case.shapes) and all(0 <= t < abft.ABFT_BATCH_TILES for t in cached)
 
 
 def test_batch_fused_quantize_encode_matches_separate_steps(case):
@@ -176,7 +196,9 @@ def test_batch_flips_match_oracle(case, orc):
             case.B.C[q].copy_(clean[q])
             continue
         compared += 1
-        _, _, orep = orc.verify(Cx.astype(np.float64), m, n, br, bc, r["tc"], r["tr"])
+        # a flip on a stored total also moves that relation's rounding term
+        tcx, trx = r["retau"](Cx) if (i >= m or j >= n) else (r["tc"], r["tr"])
+        _, _, orep = orc.verify(Cx.astype(np.float64), m, n, br, bc, tcx, trx)
         ocls, oi, oj, _ = orc.classify(orep, m, n, br, bc)
         assert (rep.n_flag_c, rep.n_flag_r) == (orep.n_flag_c, orep.n_flag_r)
         loc = abft.classify(p, rep)

@@ -72,14 +72,15 @@ class Case:
             Af, Bf = orc.encode(Aq, Bq, 1, 1, store_f32=True)
             sc = 2.0 ** -(eA + eB)
         P.encode()
-        Cf = orc.gemm(Af, Bf) * sc
+        C_scaled = orc.gemm(Af, Bf)
+        Cf = C_scaled * sc
         self.C_orc = Cf if dt == "f64" else Cf.astype(np.float32).astype(np.float64)
         if dt == "f64":
             self.tc, self.tr = orc.tau_det(Af, Bf, m, n, 1, 1)
         else:
             T = k if dt == "f32" else k / 4.0
             s_store = 2.0 + (2.0 ** 18 if dt == "fp8" else 0.0)
-            tc, tr = orc.tau_stat(Af, Bf, m, n, 1, 1, u_acc=U32, T=T, s_store=s_store, lam=LAMBDA)
+            tc, tr = orc.tau_stat(Af, Bf, m, n, 1, 1, u_acc=U32, T=T, s_store=s_store, lam=LAMBDA, Cf=C_scaled)
             self.tc, self.tr = tc * sc, tr * sc
         self.absprod = (np.abs(Af) @ np.abs(Bf)) * sc if dt in ("bf16", "fp8") else None
 

@@ -45,13 +45,19 @@ def make(dev, m, n, k, br, bc, A=None, B=None):
     return A, B, P
 
 
+def thresholds(orc, Af, Bf, m, n, br, bc, Cf):
+    """The oracle's statistical thresholds; each relation's stored total is read from Cf."""
+    k = Af.shape[1]
+    return orc.tau_stat(Af, Bf, m, n, br, bc, u_acc=orc.U32, T=float(k), s_store=2.0, lam=LAMBDA,
+                        Cf=np.asarray(Cf, dtype=np.float64))
+
+
 def oracle_side(orc, A, B, br, bc):
     m, n = A.shape[0], B.shape[1]
     Af, Bf = orc.encode(A.astype(np.float64), B.astype(np.float64), br, bc, store_f32=True)
     C64 = orc.gemm(Af, Bf)
     C32 = C64.astype(np.float32)
-    k = A.shape[1]
-    tc, tr = orc.tau_stat(Af, Bf, m, n, br, bc, u_acc=orc.U32, T=float(k), s_store=2.0, lam=LAMBDA)
+    tc, tr = thresholds(orc, Af, Bf, m, n, br, bc, C64)
     return Af, Bf, C32, tc, tr
 
 
@@ -121,15 +127,17 @@ def test_f32_flip_decisions_match_oracle(dev, orc, m, n, k, br, bc, runs):
         if np.isfinite(delta) and (t1 / 2 < abs(delta) < 2 * t1 or t2 / 2 < abs(delta) < 2 * t2):
             continue
         compared += 1
-        _, _, orep = orc.verify(Cx.astype(np.float64), m, n, br, bc, tc, tr)
+        # a flip on a stored total also moves that relation's rounding term
+        tcx, trx = thresholds(orc, Af, Bf, m, n, br, bc, Cx) if (i >= m or j >= n) else (tc, tr)
+        _, _, orep = orc.verify(Cx.astype(np.float64), m, n, br, bc, tcx, trx)
         ocls, oi, oj, od = orc.classify(orep, m, n, br, bc)
         assert (rep.n_flag_c, rep.n_flag_r) == (orep.n_flag_c, orep.n_flag_r), (i, j, bit, delta)
         # the GPU's statistical thresholds are the oracle's (the weighted row sums of A take their weights
         # in binary32, 2^-24 relative)
         for r, jj, _, tau in rep.flags_c():
-            assert abs(tau - tc[r, jj]) <= 1e-6 * tc[r, jj]
+            assert abs(tau - tcx[r, jj]) <= 1e-6 * tcx[r, jj]
         for ii, c, _, tau in rep.flags_r():
-            assert abs(tau - tr[ii, c]) <= 1e-6 * tr[ii, c]
+            assert abs(tau - trx[ii, c]) <= 1e-6 * trx[ii, c]
         assert (loc.cls, loc.i, loc.j) == (ocls, oi, oj)
         if loc.cls in (abft.ABFT_CLS_DATA, abft.ABFT_CLS_CHECKSUM):
             located += 1
@@ -224,15 +232,17 @@ def test_f32_heavy_tailed_flip_decisions_match_oracle(dev, orc):
         if np.isfinite(delta) and (t1 / 2 < abs(delta) < 2 * t1 or t2 / 2 < abs(delta) < 2 * t2):
             continue
         compared += 1
-        _, _, orep = orc.verify(Cx.astype(np.float64), m, n, br, bc, tc, tr)
+        # a flip on a stored total also moves that relation's rounding term
+        tcx, trx = thresholds(orc, Af, Bf, m, n, br, bc, Cx) if (i >= m or j >= n) else (tc, tr)
+        _, _, orep = orc.verify(Cx.astype(np.float64), m, n, br, bc, tcx, trx)
         ocls, oi, oj, od = orc.classify(orep, m, n, br, bc)
         assert (rep.n_flag_c, rep.n_flag_r) == (orep.n_flag_c, orep.n_flag_r), (i, j, bit, delta)
         # the GPU's statistical thresholds are the oracle's (the weighted row sums of A take their weights
         # in binary32, 2^-24 relative)
         for r, jj, _, tau in rep.flags_c():
-            assert abs(tau - tc[r, jj]) <= 1e-6 * tc[r, jj]
+            assert abs(tau - tcx[r, jj]) <= 1e-6 * tcx[r, jj]
         for ii, c, _, tau in rep.flags_r():
-            assert abs(tau - tr[ii, c]) <= 1e-6 * tr[ii, c]
+            assert abs(tau - trx[ii, c]) <= 1e-6 * trx[ii, c]
         assert (loc.cls, loc.i, loc.j) == (ocls, oi, oj)
         if loc.cls in (abft.ABFT_CLS_DATA, abft.ABFT_CLS_CHECKSUM):
             located += 1

@@ -70,11 +70,15 @@ def make(dev, orc, m, n, k, br, bc, dt="bf16"):
     assert np.array_equal(stored_codes(P.Bt, dt), np.ascontiguousarray(Bq.T))
     Af, Bf = orc.encode(A, B, br, bc, store_f32=True)
     sc = 2.0 ** -(eA + eB)
-    C64 = orc.gemm(Af, Bf) * sc
+    C_scaled = orc.gemm(Af, Bf)
+    C64 = C_scaled * sc
     # the library's statistical model: T = k/4 accumulation steps; s = 2, plus the
-    # FP8 product-sum window (per-product error 2^-15, i.e. + (2^-15 / 2^-24)^2)
+    # FP8 product-sum window (per-product error 2^-15, i.e. + (2^-15 / 2^-24)^2); the stored totals
     s_store = 2.0 + (2.0 ** 18 if dt == "fp8" else 0.0)
-    tc, tr = orc.tau_stat(Af, Bf, m, n, br, bc, u_acc=U32, T=k / 4.0, s_store=s_store, lam=LAMBDA)
+    tc, tr = orc.tau_stat(Af, Bf, m, n, br, bc, u_acc=U32, T=k / 4.0, s_store=s_store, lam=LAMBDA, Cf=C_scaled)
+    P.retau = lambda Cx: tuple(t * sc for t in orc.tau_stat(Af, Bf, m, n, br, bc, u_acc=U32, T=k / 4.0,
+                                                             s_store=s_store, lam=LAMBDA,
+                                                             Cf=np.asarray(Cx, dtype=np.float64) / sc))
     return P, A * 2.0 ** -eA, B * 2.0 ** -eB, Af * 2.0 ** -eA, Bf * 2.0 ** -eB, C64.astype(np.float32), tc * sc, tr * sc
 
 
@@ -139,14 +143,16 @@ def test_lowp_flip_decisions_match_oracle(dev, orc, m, n, k, br, bc, runs, dt):
         if np.isfinite(delta) and (t1 / 2 < abs(delta) < 2 * t1 or t2 / 2 < abs(delta) < 2 * t2):
             continue
         compared += 1
-        _, _, orep = orc.verify(Cx.astype(np.float64), m, n, br, bc, tc, tr)
+        # a flip on a stored total also moves that relation's rounding term
+        tcx, trx = P.retau(Cx) if (i >= m or j >= n) else (tc, tr)
+        _, _, orep = orc.verify(Cx.astype(np.float64), m, n, br, bc, tcx, trx)
         ocls, oi, oj, od = orc.classify(orep, m, n, br, bc)
         assert (rep.n_flag_c, rep.n_flag_r) == (orep.n_flag_c, orep.n_flag_r), (i, j, bit, delta)
         # the GPU's statistical thresholds are the oracle's (binary32 weights in A's weighted row sums)
         for r, jj, _, tau in rep.flags_c():
-            assert abs(tau - tc[r, jj]) <= 1e-6 * tc[r, jj]
+            assert abs(tau - tcx[r, jj]) <= 1e-6 * tcx[r, jj]
         for ii, c, _, tau in rep.flags_r():
-            assert abs(tau - tr[ii, c]) <= 1e-6 * tr[ii, c]
+            assert abs(tau - trx[ii, c]) <= 1e-6 * trx[ii, c]
         assert (loc.cls, loc.i, loc.j) == (ocls, oi, oj)
         if loc.cls in (abft.ABFT_CLS_DATA, abft.ABFT_CLS_CHECKSUM):
             located += 1
@@ -239,3 +245,110 @@ def test_fp8_every_finite_code(dev, orc):
     assert np.all(np.abs(Cg - C32) <= bound * 1.01 + 1e-30)
     rep = P.verify()
     assert rep.n_flag_c == 0 and rep.n_flag_r == 0, (rep.max_ratio_c, rep.max_ratio_r)
+
+
+# ---------------------------------------------------------------- the FP8 matrix cores' product-sum window
+def _fp8_codes(orc, X):
+    return orc.to_e4m3_codes(np.asarray(X, dtype=np.float32))
+
+
+# (A row, B column) pairs over one k group: a large product 16 x 16 = 256 and
+# small ones 2^-3 x 2^-3 = 2^-6 (exact sums 256 + 31/64 and so on); the window
+# drops what lies below 2^-11 of the largest product of a group
+WINDOW_PATTERNS = [
+    ([16.0] + [0.125] * 31, [16.0] + [0.125] * 31),
+    ([-16.0] + [0.125] * 31, [16.0] + [0.125] * 31),
+    ([16.0] + [0.125] * 63, [16.0] + [0.125] * 63),
+    ([0.125] * 31 + [16.0], [0.125] * 31 + [16.0]),
+    ([16.0] + [0.0] * 63 + [0.125] * 31, [16.0] + [0.0] * 63 + [0.125] * 31),   # small ones in the next group
+]
+
+
+@pytest.mark.parametrize("m,n,k", [(64, 64, 528), (4096, 4096, 256)],
+                         ids=["padded-LDS-16x16x32", "direct-LDS-32x32x64"])
+def test_fp8_product_sum_window(dev, orc, m, n, k):
+    """Constructed E4M3 operands (scale 2^0) through each FP8 kernel: the
+    error of each product stays within 2^-11 of the largest product of its k
+    group (the measured window; the value tolerance uses w = 2^-10 of
+    (|A_q||B_q|)), it is a truncation (never above the exact sum, so it does
+    not grow the magnitude), and a group with no large product is exact."""
+    note(f"fp8 window m={m} n={n} k={k}")
+    P = abft.Protected(abft.ABFT_FP8_E4M3, m, n, k, 1, 1, device=dev, tau_mode=abft.ABFT_TAU_STAT, lam=LAMBDA)
+    A = np.zeros((m, k), np.float32)
+    Bt = np.zeros((n, k), np.float32)
+    for q, (a, b) in enumerate(WINDOW_PATTERNS):
+        A[q, :len(a)] = a
+        Bt[q, :len(b)] = b
+    P.A.copy_(torch.from_numpy(_fp8_codes(orc, A)))
+    P.Bt.copy_(torch.from_numpy(_fp8_codes(orc, Bt)))
+    C = torch.zeros(m, n, dtype=torch.float32, device=dev)
+    pp = abft.problem(abft.ABFT_FP8_E4M3, m, n, k, 1, 1, ldc=n)
+    abft.gemm(pp, P.A, P.Bt, C, P.ws, flags=abft.ABFT_PLAIN)      # ws is zero: scale exponents 0
+    torch.cuda.synchronize()
+    Cg = C.cpu().numpy().astype(np.float64)
+    Aq = orc.e4m3_values(_fp8_codes(orc, A))
+    Bq = orc.e4m3_values(_fp8_codes(orc, Bt))
+    for q in range(len(WINDOW_PATTERNS)):
+        exact = float(Aq[q] @ Bq[q])
+        err = Cg[q, q] - exact
+        largest = float(np.abs(Aq[q] * Bq[q]).max())
+        absprod = float(np.abs(Aq[q]) @ np.abs(Bq[q]))
+        note(f"  pattern {q}: exact {exact} gpu {Cg[q, q]} error {err:+.6f}")
+        assert abs(err) <= 2.0 ** -11 * largest, (q, err)
+        assert abs(err) <= 2.0 ** -10 * absprod
+        assert err <= 0.0                                        # truncated toward minus infinity
+        if q == 4:
+            assert err == 0.0                                    # small products alone in their group: exact
+    assert Cg[0, 0] != float(Aq[0] @ Bq[0])                      # the window is there (else the model is moot)
+
+
+@pytest.mark.parametrize("dt", ["fp8", "bf16"])
+@pytest.mark.parametrize("k", [4096, 16384, 16400])
+def test_same_sign_operands_verify_clean(dev, orc, dt, k):
+    """Operands of one sign (|uniform|, the truncating FP8 window then errs in
+    one direction for every product) at k = 4096 and 16384 on the
+    direct-to-LDS kernel and 16400 on the padded-LDS one: the products verify
+    clean under the statistical thresholds (no false positive)."""
+    m = n = 4096
+    note(f"same-sign {dt} m=n={m} k={k}")
+    P = abft.Protected(DTYPES[dt], m, n, k, 1, 1, device=dev, tau_mode=abft.ABFT_TAU_STAT, lam=LAMBDA)
+    A32 = torch.empty(m, k, dtype=torch.float32, device=dev)
+    Bt32 = torch.empty(n, k, dtype=torch.float32, device=dev)
+    abft.fill_uniform(abft.ABFT_F32, m, k, k, 0, SEED + 7, synth.STREAM_A, A32)
+    abft.fill_uniform(abft.ABFT_F32, k, n, k, 1, SEED + 7, synth.STREAM_B, Bt32)
+    A32.abs_()
+    Bt32.abs_()
+    abft.quantize_encode(P.p, A32, Bt32, P.A, P.Bt, P.ws)
+    P.gemm()
+    rep = P.verify()
+    note(f"  {abft.describe_gemm(P.p)}: max |D|/tau {rep.max_ratio_c:.3f} / {rep.max_ratio_r:.3f}")
+    assert rep.n_flag_c == 0 and rep.n_flag_r == 0
+    assert max(rep.max_ratio_c, rep.max_ratio_r) < 0.8
+
+
+@pytest.mark.parametrize("dt", ["bf16", "fp8"])
+def test_nonfinite_stored_total_fails_its_relations(dev, orc, dt):
+    """A stored total made infinite (a fault in the carried row) must not lift
+    its own threshold to infinity: the column relation it closes and the row
+    relation it sits in both fail, with non-finite residuals, and every other
+    threshold is as before (checked against the oracle on the same C)."""
+    m, n, k = 256, 256, 256
+    P, A, B, Af, Bf, C32, tc, tr = make(dev, orc, m, n, k, 1, 1, dt)
+    P.encode()
+    P.gemm()
+    j = 77
+    note(f"{dt} stored total C[{m}, {j}] = inf")
+    P.C[m, j] = float("inf")
+    rep = P.verify()
+    assert [(a, b) for a, b, _, _ in rep.flags_c()] == [(0, j)]
+    assert [(a, b) for a, b, _, _ in rep.flags_r()] == [(m, 0)]
+    assert rep.n_nonfinite == 2
+    Cx = C32.copy()
+    Cx[m, j] = np.inf
+    tcx, trx = P.retau(Cx)
+    assert np.isfinite(tcx).all() and np.isfinite(trx).all()
+    (_, _, _, tau_c), = rep.flags_c()
+    (_, _, _, tau_r), = rep.flags_r()
+    assert abs(tau_c - tcx[0, j]) <= 1e-6 * tcx[0, j] and abs(tau_r - trx[m, 0]) <= 1e-6 * trx[m, 0]
+    _, _, orep = orc.verify(Cx.astype(np.float64), m, n, 1, 1, tcx, trx)
+    assert (orep.n_flag_c, orep.n_flag_r, orep.n_nonfinite) == (1, 1, 2)

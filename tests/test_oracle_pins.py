@@ -284,6 +284,30 @@ def test_stat_threshold_hand_value_b2(orc):
     tc, tr = orc.tau_stat(Af, Bf, 4, 4, 2, 2, u_acc=u, T=T, s_store=s, lam=lam)
     assert np.allclose(tc, lam * np.sqrt(coef * np.outer(nv, b4)), rtol=1e-13, atol=0)
     assert np.allclose(tr, lam * np.sqrt(coef * np.outer(a4, nw)), rtol=1e-13, atol=0)
+    # with C_f, each relation's stored total t adds its own binary32 rounding,
+    # (u^2/3) t^2.  By hand: carried rows [6,8] and [-4,4] against the columns of
+    # B_f, and the rows of A_f against the carried columns [4,1] and [-2,5].
+    Cf = Af @ Bf
+    t_c = np.array([[22.0, -4.0, 10.0, 32.0, 32.0, 28.0], [4.0, 12.0, -16.0, 16.0, -12.0, 28.0]])
+    t_r = np.array([[6.0, 8.0], [8.0, -26.0], [26.0, 20.0], [-20.0, 54.0], [32.0, 28.0], [-12.0, 28.0]])
+    assert np.array_equal(Cf[4:], t_c) and np.array_equal(Cf[:, 4:], t_r)
+    tc, tr = orc.tau_stat(Af, Bf, 4, 4, 2, 2, u_acc=u, T=T, s_store=s, lam=lam, Cf=Cf)
+    assert np.allclose(tc, lam * np.sqrt(coef * np.outer(nv, b4) + u * u / 3 * t_c ** 2), rtol=1e-13, atol=0)
+    assert np.allclose(tr, lam * np.sqrt(coef * np.outer(a4, nw) + u * u / 3 * t_r ** 2), rtol=1e-13, atol=0)
+    # a fault that makes a stored total infinite adds no rounding term: the
+    # threshold stays that of the Q part alone, and the relation (residual -inf
+    # for the column, +inf for the row through the same entry) fails
+    Cx = Cf.copy()
+    Cx[5, 2] = np.inf                     # column relation (1, 2); the same entry is in row 5's data
+    tcx, trx = orc.tau_stat(Af, Bf, 4, 4, 2, 2, u_acc=u, T=T, s_store=s, lam=lam, Cf=Cx)
+    assert np.isfinite(tcx).all() and np.isfinite(trx).all()
+    assert tcx[1, 2] == pytest.approx(lam * np.sqrt(coef * nv[1] * b4[2]), rel=1e-13)
+    assert np.array_equal(np.delete(tcx.ravel(), 1 * 6 + 2), np.delete(tc.ravel(), 1 * 6 + 2))
+    assert np.array_equal(trx, tr)
+    _, _, rep = orc.verify(Cx, 4, 4, 2, 2, tcx, trx)
+    assert [(a, b) for a, b, _, _ in rep.flags_c()] == [(1, 2)]
+    assert [(a, b) for a, b, _, _ in rep.flags_r()] == [(5, 0)]
+    assert rep.n_nonfinite == 2
 
 
 @pytest.mark.parametrize("br,bc", [(2, 3), (3, 2), (6, 1), (1, 3)])
