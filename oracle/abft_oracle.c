@@ -548,14 +548,16 @@ double orc_e4m3_value(uint8_t code)
     return s ? -v : v;
 }
 
-/* binary32 -> E4M3 code, nearest value, ties to even fraction; finite inputs
- * beyond 448 saturate to +-448; NaN -> 0x7F. */
+/* binary32 -> E4M3 code, nearest value, ties to even fraction; inputs
+ * beyond 448 (the infinities too: the format has none) saturate to +-448;
+ * NaN -> 0x7F. */
 void orc_to_e4m3(int64_t count, const float *x, uint8_t *out)
 {
     for (int64_t q = 0; q < count; ++q) {
         double v = (double)x[q];
         if (isnan(v)) { out[q] = 0x7F; continue; }
         uint8_t sign = signbit(v) ? 0x80 : 0;
+        if (isinf(v)) { out[q] = (uint8_t)(sign | 0x7E); continue; }
         double a = fabs(v);
         /* spacing of the E4M3 grid around a: 2^-9 below 2^-6, else 2^(floor(log2 a) - 3) */
         int ex;
@@ -584,11 +586,13 @@ void orc_to_e4m3(int64_t count, const float *x, uint8_t *out)
 }
 
 /* Per-tensor power-of-two scale exponent: the largest e with amax * 2^e <= 448
- * (amax = max |x|); 0 when amax is 0.  Scaling by 2^e is exact. */
+ * (amax = max |x| over the finite entries: NaN and infinities cannot set a
+ * scale); 0 when amax is 0.  Scaling by 2^e is exact. */
 int orc_e4m3_scale_exp(int64_t count, const float *x)
 {
     double amax = 0.0;
-    for (int64_t q = 0; q < count; ++q) amax = fmax(amax, fabs((double)x[q]));
+    for (int64_t q = 0; q < count; ++q)
+        if (isfinite(x[q])) amax = fmax(amax, fabs((double)x[q]));
     if (amax == 0.0) return 0;
     int e = 0;
     while (ldexp(amax, e + 1) <= 448.0) ++e;

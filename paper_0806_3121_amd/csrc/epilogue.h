@@ -36,6 +36,10 @@ __device__ inline void flip_bit(double &x, int bit) {
 }
 __device__ inline void flip_bit(float &x, int bit) { x = __uint_as_float(__float_as_uint(x) ^ (1u << bit)); }
 
+// x * 2^e with one rounding (exact unless the result leaves the format's range)
+__device__ inline float scale_pow2(float x, int e) { return __builtin_ldexpf(x, e); }
+__device__ inline double scale_pow2(double x, int e) { return __builtin_ldexp(x, e); }
+
 // Flip the armed accumulator bit if this lane holds element (fi, fj): the
 // target's index in acc is found first, then one unrolled pass of selects, so
 // no register array is indexed at run time.  r0, c0: the wave tile's origin.
@@ -74,7 +78,7 @@ template <int TM, int TN, int WM, int WN, int BM, int BN, typename V4, typename 
 __device__ __attribute__((always_inline)) inline void epi_store_fused(const V4 (&acc)[TM][TN], const EpiArgs &e,
                                                                       double *sh, int64_t row0, int64_t col0,
                                                                       int64_t tm, int64_t tn, int64_t M, int64_t N,
-                                                                      int wm, int wn, int lane, TC scale, TC *C,
+                                                                      int wm, int wn, int lane, int shift, TC *C,
                                                                       int64_t ldc, bool accumulate, RowOf rowof) {
     const int wr0 = wm * (BM / WM), wc0 = wn * (BN / WN);
     const int64_t rl = M - row0 - wr0, cl = N - col0 - wc0;
@@ -91,7 +95,7 @@ __device__ __attribute__((always_inline)) inline void epi_store_fused(const V4 (
             for (int v = 0; v < 4; ++v) {
                 const int r = 16 * a + rowof(lane, v), c = 16 * b + lane % 16;
                 const bool in = r < rlim && c < clim;
-                const TC y = acc[a][b][v] * scale;
+                const TC y = scale_pow2(acc[a][b][v], shift);
                 if (in) {
                     TC *dst = C + (row0 + wr0 + r) * ldc + col0 + wc0 + c;
                     *dst = accumulate ? *dst + y : y;

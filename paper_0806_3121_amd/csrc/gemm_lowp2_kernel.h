@@ -302,7 +302,9 @@ __global__ __launch_bounds__(128 * WM, 1) void k_gemm_lowp2(const typename Ops::
         __syncthreads();                           // LDS is reused by the epilogue
     }
 
-    const float sc = scale_exp ? __builtin_ldexpf(1.0f, -(scale_exp[0] + scale_exp[1])) : 1.0f;
+    // FP8: the result is scaled back by 2^-(eA + eB) with ldexp (exact unless it leaves binary32's range;
+    // the factor itself may not be a binary32 number)
+    const int sh = scale_exp ? -(scale_exp[0] + scale_exp[1]) : 0;
     // epilogue extras (uniform branches): the accumulator flip hook, then the
     // store with the fused partial sums
     auto rowof = [](int l, int v) { return 4 * (l / 16) + v; };
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(128 * WM, 1) void k_gemm_lowp2(const typename Ops::
         epi_flip(acc, epi, row0 + wm * (BM / WM), col0 + wn * 128, lane, rowof);
     if constexpr (FUSED) {
         epi_store_fused<TMW, 8, WM, 2, BM, BN>(acc, epi, (double *)(lds + HDR), row0, col0, tm, tn, M, N, wm, wn, lane,
-                                               sc, C, ldc, false, rowof);
+                                               sh, C, ldc, false, rowof);
         return;
     }
     const int ccol = lane % 16;
@@ -322,7 +324,7 @@ __global__ __launch_bounds__(128 * WM, 1) void k_gemm_lowp2(const typename Ops::
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 int64_t gr = row0 + wm * (BM / WM) + a * 16 + 4 * (lane / 16) + v;
-                if (gr < M && gc < N) C[gr * ldc + gc] = acc[a][b][v] * sc;
+                if (gr < M && gc < N) C[gr * ldc + gc] = __builtin_ldexpf(acc[a][b][v], sh);
             }
         }
     }

@@ -94,7 +94,7 @@ struct LowpTile {
 template <class T, bool FUSED>
 __device__ inline void lowp_tile(const typename T::E *__restrict__ A, int64_t lda, const typename T::E *__restrict__ Bt,
                                  int64_t ldb, float *__restrict__ C, int64_t ldc, int64_t M, int64_t N, int64_t K,
-                                 float sc, int64_t row0, int64_t col0, typename T::E *lds, const EpiArgs &epi,
+                                 int sh, int64_t row0, int64_t col0, typename T::E *lds, const EpiArgs &epi,
                                  int64_t tm, int64_t tn) {
     typedef typename T::E E;
     const int tid = threadIdx.x;
@@ -181,7 +181,7 @@ __device__ inline void lowp_tile(const typename T::E *__restrict__ A, int64_t ld
         epi_flip(acc, epi, row0 + wm * (T::BM / T::WM), col0 + wn * (T::BN / T::WN), lane, rowof);
     if constexpr (FUSED) {
         epi_store_fused<T::TM, T::TN, T::WM, T::WN, T::BM, T::BN>(
-            acc, epi, (double *)lds, row0, col0, tm, tn, M, N, wm, wn, lane, sc, C, ldc, false, rowof);
+            acc, epi, (double *)lds, row0, col0, tm, tn, M, N, wm, wn, lane, sh, C, ldc, false, rowof);
         return;
     }
     const int ccol = lane % 16;
@@ -193,7 +193,7 @@ __device__ inline void lowp_tile(const typename T::E *__restrict__ A, int64_t ld
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 int64_t gr = row0 + wm * (T::BM / T::WM) + a * 16 + 4 * (lane / 16) + v;
-                if (gr < M && gc < N) C[gr * ldc + gc] = acc[a][b][v] * sc;
+                if (gr < M && gc < N) C[gr * ldc + gc] = __builtin_ldexpf(acc[a][b][v], sh);
             }
         }
     }
@@ -209,8 +209,8 @@ __global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_lowp(const typenam
     const int64_t tiles_m = (M + T::BM - 1) / T::BM, tiles_n = (N + T::BN - 1) / T::BN;
     int64_t tm, tn;
     tile_of<T::GROUP_M>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
-    const float sc = scale_exp ? __builtin_ldexpf(1.0f, -(scale_exp[0] + scale_exp[1])) : 1.0f;
-    lowp_tile<T, FUSED>(A, lda, Bt, ldb, C, ldc, M, N, K, sc, tm * T::BM, tn * T::BN, lds, epi, tm, tn);
+    const int sh = scale_exp ? -(scale_exp[0] + scale_exp[1]) : 0;      // scale back by 2^sh with ldexp
+    lowp_tile<T, FUSED>(A, lda, Bt, ldb, C, ldc, M, N, K, sh, tm * T::BM, tn * T::BN, lds, epi, tm, tn);
 }
 
 template <class T>

@@ -159,7 +159,7 @@ __global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_mfma2(const typena
     if constexpr (FUSED) {
         __syncthreads();
         epi_store_fused<TM, TN, T::WM, T::WN, BM, BN>(acc, epi, (double *)(lds + HDR), row0, col0, tm, tn, M, N, wm,
-                                                     wn, lane, (E)1, C, ldc, accumulate != 0, rowof);
+                                                     wn, lane, 0, C, ldc, accumulate != 0, rowof);
         return;
     }
     const int ccol = lane % 16;

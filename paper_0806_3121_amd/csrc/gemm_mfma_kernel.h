@@ -187,7 +187,7 @@ __global__ __launch_bounds__(T::THREADS, T::MINB) void k_gemm_mfma(const typenam
         epi_flip(acc, epi, row0 + wm * (T::BM / T::WM), col0 + wn * (T::BN / T::WN), lane, rowof);
     if constexpr (FUSED) {
         epi_store_fused<T::TM, T::TN, T::WM, T::WN, T::BM, T::BN>(
-            acc, epi, (double *)lds, row0, col0, tm, tn, M, N, wm, wn, lane, (E)1, C, ldc, accumulate != 0, rowof);
+            acc, epi, (double *)lds, row0, col0, tm, tn, M, N, wm, wn, lane, 0, C, ldc, accumulate != 0, rowof);
         return;
     }
 

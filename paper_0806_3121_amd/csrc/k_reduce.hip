@@ -586,13 +586,22 @@ __global__ __launch_bounds__(kThreads) void k_quantize_bf16(const float *X, int6
 }
 
 // FP8 per-tensor scaling, kept on the device (no host synchronisation):
-// amax = max |x| (binary32 bit patterns of non-negative values order like
-// unsigned integers), then the scale exponent e = the largest e with
-// amax * 2^e <= 448 (0 when amax is 0), then x * 2^e (exact) rounded to E4M3.
+// amax = max |x| over the finite entries (binary32 bit patterns of
+// non-negative values order like unsigned integers), then the scale exponent
+// e = the largest e with amax * 2^e <= 448 (0 when amax is 0), then x * 2^e
+// (ldexp: exact wherever the result can round to a non-zero code, also where
+// 2^e itself is beyond binary32) rounded to E4M3;
+// NaN stays NaN and an infinity saturates to +-448 like any |x 2^e| >= 464.
 // ws scale words: [0] = e_A, [1] = e_B, [2] = amax_A bits, [3] = amax_B bits.
 __global__ void k_amax_init(int *scale, int which) { scale[2 + which] = 0; }
 
 // 16-byte loads: rows of X are 16-byte aligned and k is a multiple of 4 (as for the quantizer).
+// |x| for finite x, else 0 (NaN and infinities take no part in the scale)
+__device__ inline float fin_abs(float x) {
+    const float a = fabsf(x);
+    return a <= 3.40282347e38f ? a : 0.0f;
+}
+
 __global__ __launch_bounds__(kThreads) void k_amax(const float *X, int64_t ldx, int64_t rows, int64_t k, int *scale,
                                                    int which) {
     typedef float v4 __attribute__((ext_vector_type(4)));
@@ -602,7 +611,7 @@ __global__ __launch_bounds__(kThreads) void k_amax(const float *X, int64_t ldx, 
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
         int64_t i = t / kv, l = (t - i * kv) * 4;
         const v4 x = *(const v4 *)(X + i * ldx + l);
-        mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x[0]), fabsf(x[1])), fmaxf(fabsf(x[2]), fabsf(x[3]))));
+        mx = fmaxf(mx, fmaxf(fmaxf(fin_abs(x[0]), fin_abs(x[1])), fmaxf(fin_abs(x[2]), fin_abs(x[3]))));
     }
     for (int off = kWave / 2; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, kWave));
     if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = mx;
@@ -616,7 +625,7 @@ __global__ __launch_bounds__(kThreads) void k_amax(const float *X, int64_t ldx, 
 __global__ void k_scale_exp(int *scale, int which) {
     double amax = (double)__uint_as_float((unsigned int)scale[2 + which]);
     int e = 0;
-    if (amax > 0.0) {
+    if (amax > 0.0 && amax <= 3.40282347e38) {        // finite by construction; both loops end within 160 steps
         while (ldexp(amax, e + 1) <= 448.0) ++e;
         while (ldexp(amax, e) > 448.0) --e;
     }
@@ -626,13 +635,15 @@ __global__ void k_scale_exp(int *scale, int which) {
 __global__ __launch_bounds__(kThreads) void k_quantize_fp8(const float *X, int64_t ldx, int64_t rows, int64_t k,
                                                            uint8_t *Q, int64_t ldq, const int *scale, int which) {
     typedef float v4 __attribute__((ext_vector_type(4)));
-    const float f = __builtin_ldexpf(1.0f, scale[which]);
+    const int e = scale[which];
     const int64_t per_row = k / 4, total = rows * per_row;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
         int64_t i = t / per_row, c = (t - i * per_row) * 4;
         v4 x = *(const v4 *)(X + i * ldx + c);
-        uint32_t o = (uint32_t)f32_to_e4m3_rne(x[0] * f) | ((uint32_t)f32_to_e4m3_rne(x[1] * f) << 8) |
-                     ((uint32_t)f32_to_e4m3_rne(x[2] * f) << 16) | ((uint32_t)f32_to_e4m3_rne(x[3] * f) << 24);
+        uint32_t o = (uint32_t)f32_to_e4m3_rne(__builtin_ldexpf(x[0], e)) |
+                     ((uint32_t)f32_to_e4m3_rne(__builtin_ldexpf(x[1], e)) << 8) |
+                     ((uint32_t)f32_to_e4m3_rne(__builtin_ldexpf(x[2], e)) << 16) |
+                     ((uint32_t)f32_to_e4m3_rne(__builtin_ldexpf(x[3], e)) << 24);
         *(uint32_t *)(Q + i * ldq + c) = o;
     }
 }

@@ -49,7 +49,7 @@ def oracle_quantize(orc, dt, X32):
         q = orc.to_bf16_bits(X32)
         return q, orc.bf16_bits_to_f64(q), 0
     e = orc.e4m3_scale_exp(X32)
-    q = orc.to_e4m3_codes(X32 * np.float32(2.0 ** e))
+    q = orc.to_e4m3_codes(np.ldexp(X32.astype(np.float64), e).astype(np.float32))   # x 2^e, exact
     return q, orc.e4m3_values(q), e
 
 

@@ -102,6 +102,8 @@ MUTATIONS = [
     ("orc_to_e4m3: ties away from zero", C,
      "if (rem > 0.5 || (rem == 0.5 && fmod(fl, 2.0) == 1.0)) qv = fl + 1.0;", "if (rem >= 0.5) qv = fl + 1.0;",
      pins.test_e4m3_rne_matches_torch_in_range, {}),
+    ("orc_to_e4m3: infinities to NaN", C, "if (isinf(v)) { out[q] = (uint8_t)(sign | 0x7E); continue; }",
+     "if (isinf(v)) { out[q] = 0x7F; continue; }", pins.test_e4m3_saturation_and_nonfinite, {}),
     ("orc_e4m3_scale_exp: one binade low", C, "while (ldexp(amax, e + 1) <= 448.0) ++e;",
      "while (ldexp(amax, e + 2) <= 448.0) ++e;", pins.test_e4m3_scale_is_largest_power_of_two, {}),
     ("oracle.tau_det_chained: |B| dropped", PY, "return tc + _f64(tau_c_prev)[:, :k] @ np.abs(Bf), tr",

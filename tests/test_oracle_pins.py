@@ -734,6 +734,24 @@ def test_e4m3_scale_is_largest_power_of_two(orc):
         a = max(0.25, float(np.float32(amax)))
         assert a * 2.0 ** e <= 448.0 < a * 2.0 ** (e + 1)
     assert orc.e4m3_scale_exp(np.zeros(4, dtype=np.float32)) == 0
+    # the scale comes from the finite entries alone; and it reaches beyond
+    # binary32's own exponent range (amax 2^-140, subnormal: e = 148)
+    x = np.array([3.0, np.inf, -np.inf, np.nan, -5.0], dtype=np.float32)
+    assert orc.e4m3_scale_exp(x) == 6                       # 5 * 2^6 = 320 <= 448 < 640
+    assert orc.e4m3_scale_exp(np.array([np.inf, np.nan], dtype=np.float32)) == 0
+    assert orc.e4m3_scale_exp(np.array([2.0 ** -140, -2.0 ** -141], dtype=np.float32)) == 148
+
+
+def test_e4m3_saturation_and_nonfinite(orc):
+    """The format has no infinities: magnitudes from the midpoint above 448
+    (464) upward, infinities included, give +-448 (codes 0x7E / 0xFE); below
+    464 they round to 448 by the ordinary rule; NaN gives 0x7F."""
+    x = np.array([448.0, 463.99, 464.0, 470.0, 1e30, np.inf], dtype=np.float32)
+    assert list(orc.to_e4m3_codes(x)) == [0x7E] * 6
+    assert list(orc.to_e4m3_codes(-x)) == [0xFE] * 6
+    assert list(orc.to_e4m3_codes(np.array([np.nan, -np.nan], dtype=np.float32))) == [0x7F, 0x7F]
+    # 432 is the midpoint of 416 and 448: ties to the even fraction (448 = 1.110b 2^8)
+    assert list(orc.to_e4m3_codes(np.array([432.0, 431.9], dtype=np.float32))) == [0x7E, 0x7D]
 
 
 def test_exponent_bit_flip_located_on_real_data(orc):
