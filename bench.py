@@ -874,6 +874,7 @@ class OracleFlips:
 
         self.orc, self.np = orc, np
         self.dt, self.br, self.bc = dt_name, br, bc
+        self.acc_exp = 0          # FP8: the product's accumulators are C scaled by 2^acc_exp
         self.m, self.k = A.shape
         self.n = B.shape[1]
         sc = 1.0
@@ -882,9 +883,10 @@ class OracleFlips:
             B = orc.bf16_bits_to_f64(orc.to_bf16_bits(B))
         elif dt_name == "fp8":
             eA, eB = orc.e4m3_scale_exp(A), orc.e4m3_scale_exp(B)
-            A = orc.e4m3_values(orc.to_e4m3_codes(A * np.float32(2.0 ** eA)))
-            B = orc.e4m3_values(orc.to_e4m3_codes(B * np.float32(2.0 ** eB)))
+            A = orc.e4m3_values(orc.to_e4m3_codes(np.ldexp(A.astype(np.float64), eA).astype(np.float32)))
+            B = orc.e4m3_values(orc.to_e4m3_codes(np.ldexp(B.astype(np.float64), eB).astype(np.float32)))
             sc = 2.0 ** -(eA + eB)
+            self.acc_exp = eA + eB
         self.sc = sc
         self.Af, self.Bf = orc.encode(np.asarray(A, dtype=np.float64), np.asarray(B, dtype=np.float64), br, bc,
                                       store_f32=(dt_name != "f64"))
@@ -935,10 +937,13 @@ class OracleFlips:
         Dc, _, _ = orc.verify(Cr, G, 1, 1, 1, np.zeros((1, 2)), np.zeros((G + 1, 1)))
         return Dc[0, 0]
 
-    def decide(self, i, j, bit):
+    def decide(self, i, j, bit, accumulator=False):
         """-> dict: delta, the two residual / threshold ratios, the class
         ('above': both relations beyond 2 tau or non-finite; 'below': both
-        within tau / 2; 'gray' otherwise) and the oracle's classification."""
+        within tau / 2; 'gray' otherwise) and the oracle's classification.
+        accumulator: the bit is flipped in the product's accumulator, before
+        the FP8 result is scaled back (an exponent bit then changes the value
+        differently than in the stored C)."""
         np, orc = self.np, self.orc
         m, n, br, bc = self.m, self.n, self.br, self.bc
         r, c = (i % br if i < m else i - m), (j % bc if j < n else j - n)
@@ -948,7 +953,12 @@ class OracleFlips:
         row = self.C[i, cols].copy()
         ic, jr = rows.index(i), cols.index(j)
         old = col[ic]
-        new = self._flip(old, bit)
+        if accumulator and self.acc_exp:
+            with np.errstate(over="ignore", invalid="ignore"):
+                acc = float(np.float32(np.ldexp(old, self.acc_exp)))       # exact: C = acc 2^-acc_exp
+                new = float(np.float32(np.ldexp(self._flip(acc, bit), -self.acc_exp)))
+        else:
+            new = self._flip(old, bit)
         col[ic] = new
         row[jr] = new
         with np.errstate(invalid="ignore", over="ignore"):
@@ -1130,7 +1140,7 @@ def run_campaign(args):
         loc = abft.classify(P.p, rep)
         located = (loc.i, loc.j) == (i, j) and loc.cls in (abft.ABFT_CLS_DATA, abft.ABFT_CLS_CHECKSUM)
         ta = time.perf_counter()
-        dec = orf.decide(i, j, bit)
+        dec = orf.decide(i, j, bit, accumulator=site_k)
         t_oracle_flips += time.perf_counter() - ta
         corrected = False
         if located:

@@ -53,6 +53,7 @@ struct BatchDesc {
     int mode;                         // ABFT_TAU_STAT or ABFT_TAU_EXACT
     int orig;                         // index in the caller's order
     int tile;                         // the problem's own product tile shape (0 .. ABFT_BATCH_TILES-1)
+    int cvec;                         // rows of C 16-byte aligned (C at 16 bytes, ldc a multiple of 4)
     // starts in the flattened work spaces: tiles of each uniform shape, then of the per-problem shapes
     int64_t s_tiles[ABFT_BATCH_TILES + 1][2];
     int64_t s_quant, s_enc1, s_enc2, s_rows, s_comb, s_vcol, s_vrow;
@@ -476,6 +477,29 @@ __device__ inline int64_t uniform64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Lanes p and p ^ 1 (p ^ 2) of each quad exchange a value: DPP quad permutations.
+__device__ inline float quad_xor1(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+__device__ inline float quad_xor2(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
+}
+// 4 x 4 transpose inside a quad of lanes: lane p holds element (v, p) of the
+// block in x[v] (a column of the matrix-core output), afterwards (p, c) in x[c]
+// (a row).  Two butterfly steps, each exchanging the two elements whose index
+// bit differs from the lane's.
+__device__ inline void quad_transpose(v4f &x, int p) {
+    const bool o1 = p & 1, o2 = p & 2;
+    float s0 = o1 ? x[0] : x[1], s1 = o1 ? x[2] : x[3];
+    float r0 = quad_xor1(s0), r1 = quad_xor1(s1);
+    if (o1) { x[0] = r0; x[2] = r1; } else { x[1] = r0; x[3] = r1; }
+    s0 = o2 ? x[0] : x[2];
+    s1 = o2 ? x[1] : x[3];
+    r0 = quad_xor2(s0);
+    r1 = quad_xor2(s1);
+    if (o2) { x[0] = r0; x[1] = r1; } else { x[2] = r0; x[3] = r1; }
+}
+
 // One tile `local` (in the problem's grouped tile order for shape CF) of
 // problem D: the k loop through the LDS ring and the epilogue.  lds: the
 // block's LDS (header first); fetch(): called by thread 0 during the last slab
@@ -571,7 +595,22 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const BatchDesc 
     }
 
     // epilogue: data block -> C; rows >= m -> S1; columns >= n of data rows -> S2
-    if (row0 + CF::BM <= D.m && col0 + CF::BN <= D.n) {
+    if (row0 + CF::BM <= D.m && col0 + CF::BN <= D.n && D.cvec) {
+        // interior tile, aligned rows: each 4 x 4 block of a quad of lanes is transposed so that a
+        // lane holds 4 consecutive columns of one row, stored with one 16-byte store (a quarter of
+        // the store instructions of the element-wise form)
+        const int p = lane & 3;
+        G<float> *Ct = gp(D.C) + (row0 + wm * (CF::BM / CF::WM) + 4 * lq + p) * D.ldc + col0 +
+                       wn * (CF::BN / CF::WN) + (lr & ~3);
+#pragma unroll
+        for (int a = 0; a < CF::TMW; ++a)
+#pragma unroll
+            for (int b = 0; b < CF::TNW; ++b) {
+                v4f x = acc[a][b];
+                quad_transpose(x, p);
+                *(G<v4f> *)(Ct + 16 * a * D.ldc + 16 * b) = x;
+            }
+    } else if (row0 + CF::BM <= D.m && col0 + CF::BN <= D.n) {
         // interior tile: every element is a data element of C
         G<float> *Ct = gp(D.C) + (row0 + wm * (CF::BM / CF::WM) + 4 * lq) * D.ldc + col0 + wn * (CF::BN / CF::WN) + lr;
 #pragma unroll
@@ -1001,6 +1040,7 @@ int batch_setup(const abft_problem *probs, const abft_batch_item *items, int cou
         BatchDesc &D = h[s];
         D.m = q.m; D.n = q.n; D.k = q.k; D.br = q.br; D.bc = q.bc;
         D.lda = q.lda; D.ldb = q.ldb; D.ldc = q.ldc;
+        D.cvec = ((uintptr_t)items[p].C_f % 16 == 0 && q.ldc % 4 == 0) ? 1 : 0;
         D.M = q.m + q.br; D.N = q.n + q.bc; D.Gr = q.m / q.br; D.Gc = q.n / q.bc;
         D.MV = q.m + 3 * q.br; D.NV = q.n + 3 * q.bc;
         D.A32 = items[p].A32; D.Bt32 = items[p].Bt32;

@@ -13,8 +13,8 @@
 namespace abft {
 namespace {
 
-// Independent accumulators per wave: the binary64 instruction needs more of
-// them than the others to keep its unit busy (8 reached 60 % of the peak).
+// Independent accumulators per wave (each chain's next instruction comes
+// after all the others: the latency is covered).
 template <int DT> constexpr int chains_of() { return DT == ABFT_F64 ? 16 : 8; }
 constexpr int kProbeThreads = 256;
 
@@ -30,10 +30,15 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_mfma(int64_t iters, dou
         v4d acc[kChains];
         for (int c = 0; c < kChains; ++c) acc[c] = v4d{(double)c, 0.0, 0.0, 0.0};
         const double a = 1.0 + lane * 0x1p-20, b = 1.0 - lane * 0x1p-21;
+        // accumulators tied in place (from the builtin, the compiler copied all
+        // of them to the accumulation registers and back on every iteration)
+        asm volatile("s_nop 7" ::: "memory");
         for (int64_t it = 0; it < iters; ++it) {
 #pragma unroll
-            for (int c = 0; c < kChains; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+            for (int c = 0; c < kChains; ++c)
+                asm volatile("v_mfma_f64_16x16x4_f64 %0, %1, %2, %0" : "+v"(acc[c]) : "v"(a), "v"(b));
         }
+        asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
         for (int c = 0; c < kChains; ++c) out += acc[c][0] + acc[c][3];
     } else if constexpr (DT == ABFT_F32) {
         v4f_p acc[kChains];
