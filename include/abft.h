@@ -411,9 +411,11 @@ int abft_fill_normal(int64_t rows, int64_t cols, int64_t ld, int transpose, uint
  * v_mfma_f64_16x16x4, ABFT_F32: v_mfma_f32_16x16x4, ABFT_BF16:
  * v_mfma_f32_16x16x32_bf16) on 512 blocks of 4 waves, writes one value per
  * block to sink (device, sink_len >= 512 doubles) and stores the flops it
- * executes in *flops (host).  abft_probe_stream launches a read-only pass of
- * 16-byte loads over buf (device, 16-byte aligned, bytes >= 16; sink_len >=
- * 2048).  Both are asynchronous on stream; time them with events.
+ * executes in *flops (host).  abft_probe_stream launches a read-only pass over
+ * buf (device, 16-byte aligned, bytes >= 16, at most 2^31 - 1 blocks of 16 KB):
+ * one block per 16 KB chunk, 16-byte non-temporal loads; sink (device,
+ * sink_len >= 1) is written only if the fold of the loaded words hits a fixed
+ * constant.  Both are asynchronous on stream; time them with events.
  */
 int abft_probe_mfma(int32_t dtype, int64_t iters, double *sink, int64_t sink_len, double *flops, void *stream);
 int abft_probe_stream(const void *buf, size_t bytes, double *sink, int64_t sink_len, void *stream);
@@ -456,7 +458,8 @@ typedef struct {
     int32_t dtype;
     int64_t n_tiles[ABFT_BATCH_TILES + 1][2];  /* product tiles per shape and for the per-problem shapes:
                                                   [.][0] protected, [.][1] ABFT_PLAIN */
-    int64_t n_work[8];                         /* flattened work sizes of the other steps */
+    int64_t n_work[8];                         /* flattened work sizes of the other steps; [7]: problems
+                                                  whose C_f rows are not 16-byte aligned */
     size_t bytes;
     size_t ttime_off;                          /* the tuner's per-tile durations in bws */
 } abft_batch_plan;

@@ -441,7 +441,7 @@ def probe_mfma(dtype, iters, sink, stream=None) -> float:
 
 def probe_stream(buf, sink, stream=None):
     """Launch the HBM read probe over the device tensor buf (sink: float64
-    device tensor of >= 2048 entries)."""
+    device tensor of >= 1 entry)."""
     return _check("abft_probe_stream", lib().abft_probe_stream(_ptr(buf), _nbytes(buf), _ptr(sink), sink.numel(),
                                                                _stream(stream)))
 
@@ -498,14 +498,16 @@ class Batch:
     Bt, and C_f with rows padded to 16 bytes; one batch workspace and a pinned
     buffer for the reports.  shapes: list of (m, n, k, br, bc)."""
 
-    def __init__(self, shapes, device="cuda", tau_mode=ABFT_TAU_STAT, lam=0.0, tiles=None):
+    def __init__(self, shapes, device="cuda", tau_mode=ABFT_TAU_STAT, lam=0.0, tiles=None, ldc_align=4):
+        """ldc_align: rows of C_f padded to a multiple of this many elements (4: 16-byte rows, the
+        vector forms of the product's store and of the verification; 1: no padding)."""
         import torch
         self.shapes = list(shapes)
         self.probs, self.items = [], []
         self.A32, self.Bt32, self.A, self.Bt, self.Cbuf, self.C = [], [], [], [], [], []
         for (m, n, k, br, bc) in self.shapes:
             N = n + bc
-            ldc = (N + 3) // 4 * 4
+            ldc = (N + ldc_align - 1) // ldc_align * ldc_align
             p = problem(ABFT_BF16, m, n, k, br, bc, ldc=ldc, tau_mode=tau_mode, lam=lam)
             a32 = torch.zeros(m, k, dtype=torch.float32, device=device)
             b32 = torch.zeros(n, k, dtype=torch.float32, device=device)

@@ -59,7 +59,7 @@ struct BatchDesc {
     int64_t s_quant, s_enc1, s_enc2, s_rows, s_comb, s_vcol, s_vrow;
 };
 
-enum { W_QUANT = 0, W_ENC1, W_ENC2, W_ROWS, W_COMB, W_VCOL, W_VROW };
+enum { W_QUANT = 0, W_ENC1, W_ENC2, W_ROWS, W_COMB, W_VCOL, W_VROW, W_UNALIGNED };
 
 // A pointer read from a descriptor, typed as global memory: offsets are added
 // in the global address space, and the result is cast back to a generic
@@ -315,16 +315,28 @@ __device__ inline int64_t pad_to(int64_t x, int64_t q) { return (x + q - 1) / q 
 // One row's statistic by a group of 16 lanes (lane16 = lane % 16).
 template <typename T, int MODE>   // MODE 0: sum x^4 -> sqrt; 1: sum x^2 w; 2: sum x^2 -> sqrt
 __device__ inline double row_stat(const G<T> *row, int64_t k, const float *wsh, const G<double> *wg, int lane16) {
-    constexpr int V = gload<T>::N;
-    double acc = 0.0, v[V];
-    for (int64_t l0 = (int64_t)lane16 * V; l0 < k; l0 += 16 * V) {
-        gload<T>::load(row + l0, v);
+    constexpr int V = gload<T>::N, U = 4;          // U 16-byte loads per lane in flight
+    double acc = 0.0;
+    for (int64_t l0 = (int64_t)lane16 * V; l0 < k; l0 += U * 16 * V) {
+        double v[U][V];
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-            double x2 = v[e] * v[e];
-            if (MODE == 1) acc += x2 * (wsh ? (double)wsh[l0 + e] : wg[l0 + e]);
-            else if (MODE == 0) acc += x2 * x2;
-            else acc += x2;
+        for (int u = 0; u < U; ++u) {
+            const int64_t l = l0 + (int64_t)u * 16 * V;
+            if (l < k) gload<T>::load(row + l, v[u]);
+        }
+        // the same order of terms per lane as one load at a time
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t l = l0 + (int64_t)u * 16 * V;
+            if (l < k) {
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    double x2 = v[u][e] * v[u][e];
+                    if (MODE == 1) acc += x2 * (wsh ? (double)wsh[l + e] : wg[l + e]);
+                    else if (MODE == 0) acc += x2 * x2;
+                    else acc += x2;
+                }
+            }
         }
     }
     for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kW);
@@ -776,16 +788,134 @@ __device__ inline double btau(const BatchDesc &D, bool col, int64_t a, int64_t b
 // part[i][strip][c].  Column relation (r, j): the sum against C[m + r, j].
 constexpr int kVCols = 16;                      // columns per lane and strip
 constexpr int kVStrip = kVCols * kW;            // 1024
+constexpr int kVStripV = 4 * kW;                // 256: the strip of the 16-byte form
+constexpr int kVRows = 8;                       // rows loaded together by the 16-byte form
+// Strips of a problem's verification (the 16-byte form when its rows are aligned).
+__host__ __device__ inline int64_t vstrips(int64_t N, bool vec) {
+    const int64_t w = vec ? kVStripV : kVStrip;
+    return (N + w - 1) / w;
+}
+
+// The same pass where the rows of C are 16-byte aligned: strips of 256
+// columns, lane l holds columns 4 l .. 4 l + 3 (one 16-byte non-temporal load
+// per row), and kVRows rows are loaded before any is summed (8 KB of a wave in
+// flight, few registers, so many waves).  Row partials: the lane's four
+// columns have residues (4 l + q) mod bc, summed across the lanes that share
+// them (bc is a power of two dividing 64).
+__device__ __attribute__((always_inline)) inline void verify1_rows_vec(const BatchDesc &D, int64_t r, int64_t st,
+                                                                       int64_t nst, int lane) {
+    const int bc = (int)D.bc;
+    const int64_t j0 = st * kVStripV + 4 * lane;       // the lane's first column
+    const bool live = j0 < D.N;                        // a chunk that starts below N lies inside the row
+    double cs[4] = {0.0, 0.0, 0.0, 0.0};
+    auto load_row = [&](int64_t i, bool ok) {
+        return (ok && live) ? __builtin_nontemporal_load((const G<v4f_> *)(gp(D.C) + i * D.ldc + j0))
+                            : v4f_{0.f, 0.f, 0.f, 0.f};
+    };
+    auto sum_row = [&](int64_t i, bool carried, v4f_ x) {
+        double y[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double v = j0 + q < D.N ? (double)x[q] : 0.0;
+            if (!carried) cs[q] += v;
+            y[q] = j0 + q < D.n ? v : 0.0;
+        }
+        if (bc >= 4) {
+            for (int off = kW / 2; off >= bc / 4; off >>= 1)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) y[q] += __shfl_xor(y[q], off, kW);
+            if (lane < bc / 4)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) gp(D.vpart)[(i * nst + st) * bc + 4 * lane + q] = y[q];
+        } else {
+            double z0 = bc == 1 ? (y[0] + y[1]) + (y[2] + y[3]) : y[0] + y[2];
+            double z1 = bc == 1 ? 0.0 : y[1] + y[3];
+            for (int off = kW / 2; off >= 1; off >>= 1) {
+                z0 += __shfl_xor(z0, off, kW);
+                if (bc == 2) z1 += __shfl_xor(z1, off, kW);
+            }
+            if (lane == 0) {
+                gp(D.vpart)[(i * nst + st) * bc] = z0;
+                if (bc == 2) gp(D.vpart)[(i * nst + st) * bc + 1] = z1;
+            }
+        }
+    };
+    static_assert(kVRows == 8, "the reduce-scatter below takes 8 rows");
+    for (int64_t g0 = 0; g0 < D.Gr; g0 += kVRows) {
+        v4f_ x[kVRows];
+#pragma unroll
+        for (int q = 0; q < kVRows; ++q) x[q] = load_row((g0 + q) * D.br + r, g0 + q < D.Gr);
+        if (bc == 1) {
+            // bc = 1: each row's partial is its strip's sum; the 8 rows' sums across
+            // the 64 lanes by a reduce-scatter (4 + 2 + 1 exchanges, then 3 within
+            // groups of 8 lanes) instead of 8 full reductions
+            double y[kVRows];
+#pragma unroll
+            for (int q = 0; q < kVRows; ++q) {
+                double s = 0.0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double v = j0 + e < D.N ? (double)x[q][e] : 0.0;
+                    cs[e] += v;
+                    if (j0 + e < D.n) s += v;
+                }
+                y[q] = s;
+            }
+            const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+            double z[4], w[2];
+#pragma unroll
+            for (int h = 0; h < 4; ++h)
+                z[h] = (b5 ? y[h + 4] : y[h]) + __shfl_xor(b5 ? y[h] : y[h + 4], 32, kW);
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                w[h] = (b4 ? z[h + 2] : z[h]) + __shfl_xor(b4 ? z[h] : z[h + 2], 16, kW);
+            double v = (b3 ? w[1] : w[0]) + __shfl_xor(b3 ? w[0] : w[1], 8, kW);
+            for (int off = 4; off >= 1; off >>= 1) v += __shfl_xor(v, off, kW);
+            const int64_t g = g0 + 4 * b5 + 2 * b4 + (b3 ? 1 : 0);    // the row this lane now holds
+            if ((lane & 7) == 0 && g < D.Gr) gp(D.vpart)[(g * D.br + r) * nst + st] = v;
+        } else {
+#pragma unroll
+            for (int q = 0; q < kVRows; ++q)
+                if (g0 + q < D.Gr) sum_row((g0 + q) * D.br + r, false, x[q]);
+        }
+    }
+    const v4f_ x = load_row(D.m + r, true);
+    sum_row(D.m + r, true, x);
+    // column relations of the strip: the carried row's entries are the stored totals
+    double ratio = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t j = j0 + q;
+        if (j < D.N) {
+            const double tot = (double)x[q];
+            const double dd = cs[q] - tot;
+            const double tau = btau(D, true, r, j, tot);
+            bflag(gp(D.rep), true, r, j, dd, tau);
+            if (isfinite(dd) && tau > 0) ratio = fmax(ratio, fabs(dd) / tau);
+        }
+    }
+    bfold(gp(D.rep), ratio, true);
+}
+
+// VEC: this launch takes the problems whose rows of C are 16-byte aligned (the
+// 16-byte form), else the others (two instantiations, so that each keeps its
+// own register count and occupancy).
+template <bool VEC>
 __global__ __launch_bounds__(kT) void kb_verify1(const BatchDesc *__restrict__ d, int count, int64_t total) {
     const int lane = threadIdx.x % kW, wave = threadIdx.x / kW;
     Walk<&BatchDesc::s_vcol, kT / kW> wk(d, count, total);
     for (int64_t b0 = wk.first; b0 < wk.last; b0 += kT / kW) {
         const BatchDesc &D = wk.at(b0);
         const int64_t u = b0 - D.s_vcol + wave;
-        const int64_t nst = (D.N + kVStrip - 1) / kVStrip;
+        if ((D.cvec != 0) != VEC) continue;           // problem-uniform: the other launch's problem
+        const int64_t nst = vstrips(D.N, D.cvec);
         if (u >= D.br * nst) continue;                // wave-uniform
         const int64_t r = u / nst, st = u - r * nst, j0 = st * kVStrip + lane;
         const int bc = (int)D.bc;
+        if constexpr (VEC) {
+            verify1_rows_vec(D, r, st, nst, lane);
+            continue;
+        }
         double cs[kVCols];
 #pragma unroll
         for (int e = 0; e < kVCols; ++e) cs[e] = 0.0;
@@ -837,7 +967,7 @@ __global__ __launch_bounds__(kT) void kb_verify2(const BatchDesc *__restrict__ d
         const int64_t u = b0 - D.s_vrow + threadIdx.x;
         double ratio = 0.0;
         if (u < D.M * D.bc) {
-            const int64_t i = u / D.bc, c = u - i * D.bc, nst = (D.N + kVStrip - 1) / kVStrip;
+            const int64_t i = u / D.bc, c = u - i * D.bc, nst = vstrips(D.N, D.cvec);
             double s = 0.0;
             for (int64_t w = 0; w < nst; ++w) s += gp(D.vpart)[(i * nst + w) * D.bc + c];
             const double tot = (double)gp(D.C)[i * D.ldc + D.n + c];
@@ -880,7 +1010,7 @@ Parts parts_of(const abft_problem &q) {
     b.qc = align256(sizeof(double) * (q.n + q.bc));
     b.nv = align256(sizeof(double) * q.br);
     b.nw = align256(sizeof(double) * q.bc);
-    b.vpart = align256(sizeof(double) * (q.m + q.br) * ((q.n + q.bc + kVStrip - 1) / kVStrip) * q.bc);
+    b.vpart = align256(sizeof(double) * (q.m + q.br) * vstrips(q.n + q.bc, true) * q.bc);   // the larger count
     return b;
 }
 
@@ -1083,8 +1213,9 @@ int batch_setup(const abft_problem *probs, const abft_batch_item *items, int cou
         w[W_ROWS] += pad_h(q.m + q.br, kRowsPerIter) + pad_h(q.n + q.bc, kRowsPerIter) +
                      pad_h(q.br + q.bc, kRowsPerIter);
         D.s_comb = w[W_COMB]; w[W_COMB] += pad_h(q.br * q.n + q.m * q.bc + q.br * q.bc, kT);
-        D.s_vcol = w[W_VCOL]; w[W_VCOL] += pad_h(q.br * ((q.n + q.bc + kVStrip - 1) / kVStrip), kT / kW);
+        D.s_vcol = w[W_VCOL]; w[W_VCOL] += pad_h(q.br * vstrips(q.n + q.bc, D.cvec), kT / kW);
         D.s_vrow = w[W_VROW]; w[W_VROW] += pad_h((q.m + q.br) * q.bc, kT);
+        if (!D.cvec) ++w[W_UNALIGNED];
     }
     // queue cuts: equal shares of the total tile work (tile area x k)
     for (int c = 0; c < kMaps; ++c)
@@ -1175,8 +1306,9 @@ int batch_gemm(const abft_batch_plan *pl, int tile, uint32_t flags, hipStream_t 
 
 int batch_verify(const abft_batch_plan *pl, hipStream_t s) {
     kb_report_init<<<(unsigned)std::min(pl->count, 1024), 64, 0, s>>>(descs(pl), pl->count);
-    const int64_t nc = pl->n_work[W_VCOL], nr = pl->n_work[W_VROW];
-    kb_verify1<<<blocks_for(nc, kT / kW), kT, 0, s>>>(descs(pl), pl->count, nc);
+    const int64_t nc = pl->n_work[W_VCOL], nr = pl->n_work[W_VROW], nu = pl->n_work[W_UNALIGNED];
+    if (nu < pl->count) kb_verify1<true><<<blocks_for(nc, kT / kW), kT, 0, s>>>(descs(pl), pl->count, nc);
+    if (nu > 0) kb_verify1<false><<<blocks_for(nc, kT / kW), kT, 0, s>>>(descs(pl), pl->count, nc);
     kb_verify2<<<blocks_for(nr, kT), kT, 0, s>>>(descs(pl), pl->count, nr);
     ABFT_LAUNCHED();
     return ABFT_OK;

@@ -39,7 +39,8 @@ def dev():
 
 def batch_shapes():
     # edge shapes (one group, minimal k, ragged tiles, one large problem) then seeded draws
-    shapes = [(32, 32, 8, 32, 1), (64, 40, 24, 32, 8), (96, 200, 72, 32, 1), (2048, 1056, 1024, 32, 32)]
+    shapes = [(32, 32, 8, 32, 1), (64, 40, 24, 32, 8), (96, 200, 72, 32, 1), (2048, 1056, 1024, 32, 32),
+              (128, 132, 64, 32, 2), (192, 1060, 128, 32, 4)]
     for q, (m, n, k) in enumerate(synth.batched_shapes(SEED, 20, lo=64, hi=640, step=32)):
         shapes.append((m, n, k, 32, 1 if q % 2 == 0 else 32))
     return shapes
@@ -268,3 +269,45 @@ def test_batch_graph_replay_matches_eager(case):
             assert reps[q].max_ratio_c == reps_eager[q].max_ratio_c
             assert reps[q].max_ratio_r == reps_eager[q].max_ratio_r
     del g
+
+
+def test_batch_unpadded_rows_match_padded(dev):
+    """C rows not 16-byte aligned (ldc = n + bc, not a multiple of 4) take the
+    element-wise store and verification; they must give the padded batch's C
+    bit for bit, a clean verification, and the same failed relations and
+    classification for the same flips (bc = 1 and 2, one and two strips)."""
+    shapes = [(256, 200, 96, 32, 1), (128, 132, 64, 32, 2), (96, 1064, 80, 32, 2), (64, 2000, 296, 32, 1)]
+    pads = [abft.Batch(shapes, device=dev, tau_mode=abft.ABFT_TAU_STAT, lam=LAMBDA, ldc_align=a) for a in (4, 1)]
+    assert all((n + bc) % 4 != 0 for (_, n, _, _, bc) in shapes)
+    for B in pads:
+        for q, (m, n, k, br, bc) in enumerate(shapes):
+            abft.fill_uniform(abft.ABFT_F32, m, k, k, 0, SEED + 50 + q, synth.STREAM_A, B.A32[q])
+            abft.fill_uniform(abft.ABFT_F32, k, n, k, 1, SEED + 50 + q, synth.STREAM_B, B.Bt32[q])
+    for tile in (0, 3):
+        note(f"unpadded vs padded rows, tile {tile}")
+        reps = []
+        for B in pads:
+            abft.batch_quantize_encode(B.plan)
+            abft.batch_gemm(B.plan, tile)
+            abft.batch_verify(B.plan)
+            reps.append(B.reports())
+        for q in range(len(shapes)):
+            assert torch.equal(pads[0].C[q], pads[1].C[q]), (tile, q)
+            for rp in reps:
+                assert rp[q].n_flag_c == 0 and rp[q].n_flag_r == 0, (tile, q)
+    clean = [[c.clone() for c in B.C] for B in pads]
+    for run, q in enumerate([0, 1, 2, 3, 2]):
+        m, n, k, br, bc = shapes[q]
+        i, j, bit = synth.flip_site(SEED + 51, run, m + br, n + bc, 24, 30)
+        note(f"flip problem {q} ({i},{j}) bit {bit}")
+        got = []
+        for B, cl in zip(pads, clean):
+            B.C[q].copy_(cl[q])
+            abft.inject_flip(B.probs[q], B.C[q], i, j, bit)
+            abft.batch_verify(B.plan)
+            rep = B.reports()[q]
+            loc = abft.classify(B.probs[q], rep)
+            got.append((sorted((a, b) for a, b, _, _ in rep.flags_c()), sorted((a, b) for a, b, _, _ in rep.flags_r()),
+                        (loc.cls, loc.i, loc.j)))
+            B.C[q].copy_(cl[q])
+        assert got[0] == got[1], (q, i, j, bit, got)
