@@ -929,54 +929,119 @@ __device__ inline bool row_erased_res(const ErasureRes &e, int64_t i, int64_t c,
 // groups in increasing order with the carried term subtracted last, as in the
 // two-pass kernels, so the residuals are the same numbers.  GC = Gc, 1..8.
 constexpr int kBlockPassMaxG = 8;    // data block columns: up to 8 (the carried one makes 9)
+// The thresholds of this pass with their row-, column- and problem-dependent
+// factors loaded ahead of the sums (the same arithmetic as tau_row / tau_col).
+struct VbFac {
+    double sc, rowc, colc;          // tau_scale; per-residue factors of the row (c) and column (r) relations
+};
+__device__ inline double vb_row_fac(const VerifyArgs &a, int64_t i) {
+    return a.mode == ABFT_TAU_DET ? a.na[i] : (a.mode == ABFT_TAU_STAT ? a.qr[i] : 0.0);
+}
+__device__ inline double vb_tau_row(const VerifyArgs &a, double sc, double fi, double fc, double tot) {
+    if (a.mode == ABFT_TAU_DET) return sc * a.cr * fi * fc;
+    if (a.mode == ABFT_TAU_STAT) {
+        const double t = isfinite(tot) ? tot : 0.0;
+        return sqrt(sc * sc * a.cr * (a.bc == 1 ? fi : fi * fc) + a.cst * t * t);
+    }
+    return 0.0;
+}
+__device__ inline double vb_tau_col(const VerifyArgs &a, double sc, double fr, double chr, double fj, double cwj,
+                                    double tot) {
+    if (a.mode == ABFT_TAU_DET) return sc * a.cc * fr * fj + chr * cwj;
+    if (a.mode == ABFT_TAU_STAT) {
+        const double t = isfinite(tot) ? tot : 0.0;
+        return sqrt(sc * sc * a.cc * (a.br == 1 ? fj : fr * fj) + a.cst * t * t);
+    }
+    return 0.0;
+}
+
 template <typename T, int V, int GC>
 __global__ __launch_bounds__(kThreads) void k_vblock(const T *C, VerifyArgs a, ErasureRes er) {
     const int64_t cv = a.bc / V, total = a.br * cv;
+    const bool det = a.mode == ABFT_TAU_DET, stat = a.mode == ABFT_TAU_STAT;
+    const double sc = (det || stat) ? tau_scale(a) : 0.0;
     double ratio_c = 0.0, ratio_r = 0.0;
     unsigned long long excl_c = 0, excl_r = 0;
     for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total; t += (int64_t)gridDim.x * kThreads) {
         const int64_t r = t / cv, c0 = (t - r * cv) * V;
+        // residue factors, loaded once: row relations (i, c0 + q), column relations (r, .)
+        double fc[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) fc[q] = det ? a.nb_abs[c0 + q] : ((stat && a.bc > 1) ? a.nw[c0 + q] : 0.0);
+        const double fr = det ? a.na_abs[r] : ((stat && a.br > 1) ? a.nv[r] : 0.0);
+        const double chr = det ? a.chain_a[r] : 0.0;
         double cs[GC + 1][V];
 #pragma unroll
         for (int h = 0; h <= GC; ++h)
 #pragma unroll
             for (int q = 0; q < V; ++q) cs[h][q] = 0.0;
         // row relations (i, c0 + q): data columns summed, the carried column last
-        auto rows_of = [&](int64_t i, const double (&v)[GC + 1][V]) {
+        auto rows_of = [&](int64_t i, double fi, const double (&v)[GC + 1][V]) {
 #pragma unroll
             for (int q = 0; q < V; ++q) {
                 double rs = 0.0;
 #pragma unroll
                 for (int h = 0; h < GC; ++h) rs += v[h][q];
                 if (er.n && row_erased_res(er, i, c0 + q, a.bc)) excl_r++;
-                else ratio_r = fmax(ratio_r, record(a.rep, false, i, c0 + q, rs - v[GC][q], tau_row(a, i, c0 + q, v[GC][q])));
+                else ratio_r = fmax(ratio_r, record(a.rep, false, i, c0 + q, rs - v[GC][q],
+                                                    vb_tau_row(a, sc, fi, fc[q], v[GC][q])));
             }
         };
-        for (int64_t g = 0; g < a.Gr; ++g) {
-            const int64_t i = g * a.br + r;
-            double v[GC + 1][V];
-#pragma unroll
-            for (int h = 0; h <= GC; ++h) load_c<T, V>(C + i * a.ldc + h * a.bc + c0, v[h]);
-            rows_of(i, v);
+        auto add_col = [&](const double (&v)[GC + 1][V]) {
 #pragma unroll
             for (int h = 0; h <= GC; ++h)
 #pragma unroll
                 for (int q = 0; q < V; ++q) cs[h][q] += v[h][q];
+        };
+        // two rows of blocks at a time: both rows' loads (and their row factors) in flight together
+        int64_t g = 0;
+        for (; g + 1 < a.Gr; g += 2) {
+            const int64_t i0 = g * a.br + r, i1 = i0 + a.br;
+            const double f0 = vb_row_fac(a, i0), f1 = vb_row_fac(a, i1);
+            double v0[GC + 1][V], v1[GC + 1][V];
+#pragma unroll
+            for (int h = 0; h <= GC; ++h) {
+                load_c<T, V>(C + i0 * a.ldc + h * a.bc + c0, v0[h]);
+                load_c<T, V>(C + i1 * a.ldc + h * a.bc + c0, v1[h]);
+            }
+            rows_of(i0, f0, v0);
+            add_col(v0);
+            rows_of(i1, f1, v1);
+            add_col(v1);
+        }
+        if (g < a.Gr) {
+            const int64_t i0 = g * a.br + r;
+            const double f0 = vb_row_fac(a, i0);
+            double v0[GC + 1][V];
+#pragma unroll
+            for (int h = 0; h <= GC; ++h) load_c<T, V>(C + i0 * a.ldc + h * a.bc + c0, v0[h]);
+            rows_of(i0, f0, v0);
+            add_col(v0);
         }
         // the carried row: its row relations, then the column relations (r, j),
         // data rows summed, the carried row last
         const int64_t i = a.m + r;
-        double v[GC + 1][V];
+        const double fi = vb_row_fac(a, i);
+        double fj[GC + 1][V], cw[GC + 1][V], v[GC + 1][V];
+#pragma unroll
+        for (int h = 0; h <= GC; ++h)
+#pragma unroll
+            for (int q = 0; q < V; ++q) {
+                const int64_t j = h * a.bc + c0 + q;
+                fj[h][q] = det ? a.nb[j] : (stat ? a.qc[j] : 0.0);
+                cw[h][q] = det ? a.chain_w[j] : 0.0;
+            }
 #pragma unroll
         for (int h = 0; h <= GC; ++h) load_c<T, V>(C + i * a.ldc + h * a.bc + c0, v[h]);
-        rows_of(i, v);
+        rows_of(i, fi, v);
 #pragma unroll
         for (int h = 0; h <= GC; ++h)
 #pragma unroll
             for (int q = 0; q < V; ++q) {
                 const int64_t j = h * a.bc + c0 + q;
                 if (er.n && col_erased_res(er, r, j, a.br)) excl_c++;
-                else ratio_c = fmax(ratio_c, record(a.rep, true, r, j, cs[h][q] - v[h][q], tau_col(a, r, j, v[h][q])));
+                else ratio_c = fmax(ratio_c, record(a.rep, true, r, j, cs[h][q] - v[h][q],
+                                                    vb_tau_col(a, sc, fr, chr, fj[h][q], cw[h][q], v[h][q])));
             }
     }
     fold_block(ratio_c, excl_c, &a.rep->max_ratio_c, &a.rep->n_excl_c);
