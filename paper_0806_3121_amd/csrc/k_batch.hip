@@ -312,17 +312,28 @@ __global__ __launch_bounds__(kT) void kb_encode2(const BatchDesc *__restrict__ d
 // Sixteen lanes per row, 16 rows per wave and block iteration.
 __device__ inline int64_t pad_to(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
-// One row's statistic by a group of 16 lanes (lane16 = lane % 16).
+// Element e of a 16-byte chunk of T, widened to binary64.
+template <typename T> __device__ inline double chunk_elem(const v4u_ &w, int e);
+template <> __device__ inline double chunk_elem<uint16_t>(const v4u_ &w, int e) {
+    return (double)bf16_to_f32((uint16_t)((w[e / 2] >> (16 * (e % 2))) & 0xFFFFu));
+}
+template <> __device__ inline double chunk_elem<float>(const v4u_ &w, int e) { return (double)__uint_as_float(w[e]); }
+template <> __device__ inline double chunk_elem<double>(const v4u_ &w, int e) {
+    return __hiloint2double((int)w[2 * e + 1], (int)w[2 * e]);
+}
+
+// One row's statistic by a group of 16 lanes (lane16 = lane % 16).  U 16-byte
+// loads per lane are in flight, kept as raw words until they are summed.
 template <typename T, int MODE>   // MODE 0: sum x^4 -> sqrt; 1: sum x^2 w; 2: sum x^2 -> sqrt
 __device__ inline double row_stat(const G<T> *row, int64_t k, const float *wsh, const G<double> *wg, int lane16) {
-    constexpr int V = gload<T>::N, U = 4;          // U 16-byte loads per lane in flight
+    constexpr int V = 16 / (int)sizeof(T), U = 8;
     double acc = 0.0;
     for (int64_t l0 = (int64_t)lane16 * V; l0 < k; l0 += U * 16 * V) {
-        double v[U][V];
+        v4u_ raw[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t l = l0 + (int64_t)u * 16 * V;
-            if (l < k) gload<T>::load(row + l, v[u]);
+            if (l < k) raw[u] = *(const G<v4u_> *)(row + l);
         }
         // the same order of terms per lane as one load at a time
 #pragma unroll
@@ -331,7 +342,8 @@ __device__ inline double row_stat(const G<T> *row, int64_t k, const float *wsh, 
             if (l < k) {
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
-                    double x2 = v[u][e] * v[u][e];
+                    const double x = chunk_elem<T>(raw[u], e);
+                    double x2 = x * x;
                     if (MODE == 1) acc += x2 * (wsh ? (double)wsh[l + e] : wg[l + e]);
                     else if (MODE == 0) acc += x2 * x2;
                     else acc += x2;

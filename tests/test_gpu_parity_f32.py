@@ -251,3 +251,29 @@ def test_f32_heavy_tailed_flip_decisions_match_oracle(dev, orc):
             assert rep2.n_flag_c == 0 and rep2.n_flag_r == 0
     note(f"  compared {compared}, located {located}")
     assert compared >= runs * 0.7 and located >= 1
+
+
+def test_same_sign_long_k_rigorous_threshold_clean(dev):
+    """Operands of one sign at long k (4096 x 4096 x 65536, |uniform|): the
+    statistical threshold's model of zero-mean product errors no longer holds
+    there (its clean residuals exceed it, measured), and the rigorous binary32
+    bound (ABFT_TAU_DET: gamma_k of the products, the checksum sums and the
+    storage) is the mode for such data: every relation passes, and a flip of
+    an exponent bit is still located."""
+    m = n = 4096
+    k = 65536
+    note(f"same-sign f32 m=n={m} k={k}, rigorous thresholds")
+    P = abft.Protected(abft.ABFT_F32, m, n, k, 1, 1, device=dev, tau_mode=abft.ABFT_TAU_DET)
+    abft.fill_uniform(abft.ABFT_F32, m, k, k, 0, SEED + 11, synth.STREAM_A, P.A)
+    abft.fill_uniform(abft.ABFT_F32, k, n, k, 1, SEED + 11, synth.STREAM_B, P.Bt)
+    P.A.abs_()
+    P.Bt.abs_()
+    P.encode()
+    P.gemm()
+    rep = P.verify()
+    note(f"  max |D|/tau {rep.max_ratio_c:.3g} / {rep.max_ratio_r:.3g}")
+    assert rep.n_flag_c == 0 and rep.n_flag_r == 0
+    abft.inject_flip(P.p, P.C, 1234, 567, 29)
+    rep = P.verify()
+    loc = abft.classify(P.p, rep)
+    assert (loc.cls, loc.i, loc.j) == (abft.ABFT_CLS_DATA, 1234, 567)
