@@ -352,9 +352,15 @@ def run_batched(args):
             f"shapes {mixed * 1e-5:.2f} ms")
     Bt.set_tiles(tiles)
     plan = Bt.plan
-    tile = abft.ABFT_BATCH_MIXED
     tile_counts = [tiles.count(t) for t in range(abft.ABFT_BATCH_TILES)]
     log(f"tile shapes ({tile_source}, {args.tile_cache}): problems per shape {tile_counts}")
+    # launch-level choice: each uniform shape and the per-problem shapes, timed whole
+    abft.batch_quantize_encode(plan)
+    choice_ms, tile = abft.batch_choose(plan, reps=3)
+    choice_names = [f"{abft.BATCH_TILE_SHAPES[t][0]}x{abft.BATCH_TILE_SHAPES[t][1]}"
+                    for t in range(abft.ABFT_BATCH_TILES)] + ["per-problem"]
+    log(f"product by launch choice (ms): {dict(zip(choice_names, [round(x, 3) for x in choice_ms]))} -> "
+        f"{choice_names[tile]}")
     torch.cuda.synchronize()
 
     side = torch.cuda.Stream()
@@ -460,8 +466,10 @@ def run_batched(args):
                                f"on multiples of {cfg['step']} in [{cfg['lo']}, {cfg['hi']}], checksum blocks "
                                f"{br}x{bc}; per step {nf} flips and {ne} erased {br}x32 blocks on distinct "
                                f"problems; graph-captured passes",
-                   "problems": len(shapes), "br": br, "bc": bc, "tile": "per-problem",
-                   "tile_source": tile_source, "problems_per_tile_shape": tile_counts, "global_batch": len(shapes),
+                   "problems": len(shapes), "br": br, "bc": bc, "tile": choice_names[tile],
+                   "tile_source": tile_source, "problems_per_tile_shape": tile_counts,
+                   "product_ms_by_choice": dict(zip(choice_names, [round(x, 4) for x in choice_ms])),
+                   "global_batch": len(shapes),
                    "seq_len": 0, "parallelism": "single-gpu"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": TRAFFIC["c5"],

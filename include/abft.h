@@ -444,10 +444,10 @@ typedef struct {
     void *C_f;          /* binary32 C_f, (m+br) x (n+bc), ldc */
 } abft_batch_item;
 
-/* Product tile shapes of the batched kernel: 0 = 256 x 256, 1 = 256 x 128,
- * 2 = 128 x 256, 3 = 128 x 128 (all eight waves, one block per CU, so one
- * persistent launch runs tiles of every shape).  ABFT_BATCH_MIXED: every
- * problem with its own shape (chosen at setup). */
+/* Product tile shapes of the batched kernel: 0 = 256 x 256 (blocks of eight
+ * waves, one per CU), 1 = 256 x 128, 2 = 128 x 256, 3 = 128 x 128 (blocks of
+ * eight waves, two per CU).  ABFT_BATCH_MIXED: every problem with its own
+ * shape (chosen at setup), in two persistent launches (shape 0, the others). */
 #define ABFT_BATCH_TILES 4
 #define ABFT_BATCH_MIXED ABFT_BATCH_TILES
 
@@ -462,6 +462,7 @@ typedef struct {
                                                   whose C_f rows are not 16-byte aligned */
     size_t bytes;
     size_t ttime_off;                          /* the tuner's per-tile durations in bws */
+    int32_t n_shape[ABFT_BATCH_TILES];         /* problems per own tile shape (ABFT_BATCH_MIXED) */
 } abft_batch_plan;
 
 /* Device bytes of the batch workspace for these problems (0 if invalid). */
@@ -505,10 +506,21 @@ int abft_batch_quantize_encode(const abft_batch_plan *plan, void *stream);
 int abft_batch_gemm(const abft_batch_plan *plan, int tile, uint32_t flags, void *stream);
 /* Tuner (synchronous; overwrites every C_f): runs the product once with each
  * tile shape for every problem, recording each tile's duration on the device
- * (100 MHz clock), and gives per problem (caller's order) the summed duration
- * of its tiles for each shape in costs (host, count x ABFT_BATCH_TILES, or
- * NULL) and the shape with the least in tiles (host, count, or NULL). */
+ * (100 MHz clock), and gives per problem (caller's order) the CU time of its
+ * tiles for each shape in costs (host, count x ABFT_BATCH_TILES, or NULL: the
+ * summed durations, halved for the shapes that run two blocks per CU, 1 .. 3)
+ * and the shape with the least in tiles (host, count, or NULL).  With
+ * ABFT_BATCH_MIXED the problems of shape 0 run in one launch (one block per
+ * CU) and the others in a second (two blocks per CU). */
 int abft_batch_tune(const abft_batch_plan *plan, double *costs, int32_t *tiles, void *stream);
+/* Launch-level choice (synchronous; overwrites every C_f): the protected
+ * product timed with device events, median of reps launches (1 .. 100) after a
+ * warm-up, with each uniform shape (0 .. ABFT_BATCH_TILES-1) and with the
+ * plan's per-problem shapes (ABFT_BATCH_MIXED); ms (host, ABFT_BATCH_TILES + 1
+ * doubles, or NULL) receives the times, *choice (host, or NULL) the fastest,
+ * the value to pass as `tile` to abft_batch_gemm.  The per-problem run is one
+ * launch per shape, so its tiles' lower summed cost need not make it faster. */
+int abft_batch_choose(const abft_batch_plan *plan, int reps, double *ms, int32_t *choice, void *stream);
 /* Persisted tuning results: a text file keyed by (dtype, m / 128, n / 128,
  * log2 k rounded up, br, bc, arch) with the summed cost of each shape over the
  * problems measured in that bucket.  abft_batch_cache_store merges the costs

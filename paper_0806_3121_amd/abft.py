@@ -76,13 +76,14 @@ class abft_batch_item(C.Structure):
 
 ABFT_BATCH_TILES = 4      # product tile shapes: 256x256, 256x128, 128x256, 128x128
 ABFT_BATCH_MIXED = ABFT_BATCH_TILES   # every problem with its own shape
+BATCH_TILE_SHAPES = [(256, 256), (256, 128), (128, 256), (128, 128)]
 
 
 class abft_batch_plan(C.Structure):
     _fields_ = [("bws", C.c_void_p), ("count", C.c_int32), ("dtype", C.c_int32),
                 ("n_tiles", (C.c_int64 * 2) * (ABFT_BATCH_TILES + 1)),
                 ("n_work", C.c_int64 * 8),
-                ("bytes", C.c_size_t), ("ttime_off", C.c_size_t)]
+                ("bytes", C.c_size_t), ("ttime_off", C.c_size_t), ("n_shape", C.c_int32 * ABFT_BATCH_TILES)]
 
 
 ABFT_WMAX = 4
@@ -156,6 +157,7 @@ def lib():
             "abft_batch_setup_tiles": (C.c_int, [_P(abft_problem), _P(abft_batch_item), C.c_int, _P(C.c_int32), _V,
                                                  C.c_size_t, _P(abft_batch_plan)]),
             "abft_batch_tune": (C.c_int, [_P(abft_batch_plan), _P(C.c_double), _P(C.c_int32), _V]),
+            "abft_batch_choose": (C.c_int, [_P(abft_batch_plan), C.c_int, _P(C.c_double), _P(C.c_int32), _V]),
             "abft_batch_cache_lookup": (C.c_int, [C.c_char_p, C.c_char_p, _P(abft_problem), C.c_int, _P(C.c_int32)]),
             "abft_batch_cache_store": (C.c_int, [C.c_char_p, C.c_char_p, _P(abft_problem), C.c_int,
                                                  _P(C.c_double)]),
@@ -401,6 +403,14 @@ def batch_tune(plan, stream=None):
     _check("abft_batch_tune", lib().abft_batch_tune(C.byref(plan), costs, tiles, _stream(stream)))
     return ([list(costs[p * ABFT_BATCH_TILES:(p + 1) * ABFT_BATCH_TILES]) for p in range(n)],
             [int(t) for t in tiles])
+
+
+def batch_choose(plan, reps=3, stream=None):
+    """-> (median ms of the protected product per choice: uniform shapes, then per-problem; fastest choice)."""
+    ms = (C.c_double * (ABFT_BATCH_TILES + 1))()
+    choice = C.c_int32(-1)
+    _check("abft_batch_choose", lib().abft_batch_choose(C.byref(plan), reps, ms, C.byref(choice), _stream(stream)))
+    return list(ms), int(choice.value)
 
 
 def batch_cache_lookup(path, probs, arch=None):

@@ -55,7 +55,7 @@ struct BatchDesc {
     int tile;                         // the problem's own product tile shape (0 .. ABFT_BATCH_TILES-1)
     int cvec;                         // rows of C 16-byte aligned (C at 16 bytes, ldc a multiple of 4)
     // starts in the flattened work spaces: tiles of each uniform shape, then of the per-problem shapes
-    int64_t s_tiles[ABFT_BATCH_TILES + 1][2];
+    int64_t s_tiles[2 * ABFT_BATCH_TILES][2];   // [map][plain]: maps of the uniform shapes, then the per-shape mixed ones
     int64_t s_quant, s_enc1, s_enc2, s_rows, s_comb, s_vcol, s_vrow;
 };
 
@@ -79,15 +79,6 @@ __device__ inline int find_problem(const BatchDesc *__restrict__ d, int count, i
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
         if (d[mid].*F <= t) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-__device__ inline int find_tile_problem(const BatchDesc *__restrict__ d, int count, int64_t t, int cfg, int plain) {
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (d[mid].s_tiles[cfg][plain] <= t) lo = mid;
         else hi = mid - 1;
     }
     return lo;
@@ -448,17 +439,21 @@ struct DCfg {
     static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "wave tile");
     static_assert(NS >= 2 && LDS <= 160 * 1024 / BPC, "LDS");
 };
-// The four tile shapes, all eight waves and one block per CU, so that one
-// persistent launch can run tiles of every shape (each problem with its own).
-typedef DCfg<256, 256, 4, 2, 1, 128, 2> Cfg0;    // 128 KB
-typedef DCfg<256, 128, 4, 2, 1, 128, 3> Cfg1;    // 144 KB
-typedef DCfg<128, 256, 2, 4, 1, 128, 3> Cfg2;    // 144 KB
-typedef DCfg<128, 128, 4, 2, 1, 128, 4> Cfg3;    // 128 KB, waves of 32 x 64
+// The four tile shapes, all blocks of eight waves.  256 x 256 (waves of
+// 64 x 128, 128 accumulators each) runs one block per CU.  The three smaller
+// shapes run two blocks per CU (waves of 64 x 64 or 32 x 64, at most 128
+// registers, at most 80 KB of LDS each), so that one block's tile start and
+// end (its first slab's latency, the drain of its stores) overlap the other's
+// k loop: measured on the 512-problem workload with one shape for every
+// problem, 2.62 -> 2.42 ms (256 x 128), 2.70 -> 2.43 (128 x 256), 2.99 -> 2.40
+// (128 x 128) against one block per CU.
+typedef DCfg<256, 256, 4, 2, 1, 128, 2> Cfg0;    // 128 KB, one block per CU
+typedef DCfg<256, 128, 4, 2, 2, 64, 3> Cfg1;     // 72 KB, two per CU
+typedef DCfg<128, 256, 2, 4, 2, 64, 3> Cfg2;     // 72 KB
+typedef DCfg<128, 128, 4, 2, 2, 128, 2> Cfg3;    // 64 KB, waves of 32 x 64
 constexpr int kGemmThreads = 512;
-constexpr int kGemmLds = Cfg1::LDS > Cfg0::LDS ? (Cfg1::LDS > Cfg3::LDS ? Cfg1::LDS : Cfg3::LDS) : Cfg0::LDS;
 static_assert(Cfg0::THREADS == kGemmThreads && Cfg1::THREADS == kGemmThreads && Cfg2::THREADS == kGemmThreads &&
               Cfg3::THREADS == kGemmThreads, "one block shape for every tile shape");
-static_assert(Cfg2::LDS <= kGemmLds && kGemmLds <= 160 * 1024, "LDS");
 
 __device__ __align__(16) uint32_t kZeroChunk[4];      // never written: the source of chunks past K
 
@@ -466,18 +461,24 @@ __device__ __align__(16) uint32_t kZeroChunk[4];      // never written: the sour
 // flattened tiles, so the tiles an XCD runs together are neighbours and share
 // operand rows in its L2.  A block takes tiles from its own XCD's queue
 // (blockIdx.x % 8), then from the others in turn.  tmap (byte offset from the
-// workspace) gives each tile's problem.  Index kMixed: every problem with its
-// own tile shape (BatchDesc::tile); 0 .. ABFT_BATCH_TILES-1: every problem
-// with that shape.
+// workspace) gives each tile's problem.  Map s (0 .. ABFT_BATCH_TILES-1): every
+// problem with shape s; map kMix + s: the problems whose own shape
+// (BatchDesc::tile) is s (the per-problem run is one launch per shape; every
+// launch runs a kernel built for its one shape, which keeps each within its
+// registers).
 constexpr int kXcds = 8;
-constexpr int kMixed = ABFT_BATCH_TILES;
-constexpr int kMaps = ABFT_BATCH_TILES + 1;
+constexpr int kMix = ABFT_BATCH_TILES;
+constexpr int kMaps = 2 * ABFT_BATCH_TILES;
+// the tile shape of map c
+__host__ __device__ inline int shape_of_map(int c) { return c < kMix ? c : c - kMix; }
+// whether a problem with own shape `own` has tiles on map c
+__host__ __device__ inline bool on_map(int c, int own) { return c < kMix || own == c - kMix; }
 struct TileQueues {
     int64_t qb[kMaps][2][kXcds], qe[kMaps][2][kXcds];
     int64_t tmap[kMaps][2];
 };
 constexpr int kCtrWords = kXcds + 1;                   // queue counters, then the exit counter
-constexpr size_t kCtlBytes = 2048;                     // counters (256 bytes) + TileQueues
+constexpr size_t kCtlBytes = 4096;                     // counters (256 bytes) + TileQueues
 static_assert(256 + sizeof(TileQueues) <= kCtlBytes, "control block");
 
 __device__ inline int64_t next_tile(unsigned *ctr, const int64_t *qb, const int64_t *qe, int home, int &qi) {
@@ -666,23 +667,23 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const BatchDesc 
     }
 }
 
-// The persistent product: 256 resident blocks take tiles from the queues of
-// map `mp` (a uniform tile shape, or kMixed: each problem's own) until they
-// are empty.  ttime (null normally): the duration of every tile in ticks of
-// the constant 100 MHz clock, for the tuner.
-template <bool TIMED>
-__global__ __launch_bounds__(kGemmThreads, 1) void kb_gemm(const BatchDesc *__restrict__ d, int mp, int plain,
-                                                           unsigned *ctr, const TileQueues *__restrict__ tq,
-                                                           uint64_t *ttime) {
+// The persistent product: resident blocks take tiles from the queues of map
+// `mp` (all of shape CF) until they are empty; BPC blocks per CU.  ttime
+// (null normally): the duration of every tile in ticks of the constant 100 MHz
+// clock, for the tuner.
+template <class CF, bool TIMED>
+__global__ __launch_bounds__(kGemmThreads, CF::BPC == 1 ? 2 : 4) void kb_gemm(const BatchDesc *__restrict__ d, int mp,
+                                                                              int plain, unsigned *ctr,
+                                                                              const TileQueues *__restrict__ tq,
+                                                                              uint64_t *ttime) {
     // One LDS object only: with a second one the compiler cannot tell the
     // fragment reads from the in-flight direct-to-LDS loads and waits for them.
-    __shared__ __attribute__((aligned(16))) uint8_t lds[kGemmLds];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[CF::LDS];
     int64_t &sh_next = *(int64_t *)lds;               // the header holds the next tile index
     const int tid = threadIdx.x;
     const int home = blockIdx.x % kXcds;
     const int64_t *qb = tq->qb[mp][plain], *qe = tq->qe[mp][plain];
     const int *tmap = (const int *)((const char *)d + tq->tmap[mp][plain]);
-    const int sidx = mp == kMixed ? ABFT_BATCH_TILES : mp;      // which tile start of the descriptor
     int qi = 0;                                        // thread 0: queues tried so far
     if (tid == 0) sh_next = next_tile(ctr, qb, qe, home, qi);
     __syncthreads();
@@ -690,17 +691,11 @@ __global__ __launch_bounds__(kGemmThreads, 1) void kb_gemm(const BatchDesc *__re
     while (t >= 0) {
         int64_t nx = -1;
         const BatchDesc &D = d[tmap[t]];
-        const int64_t local = t - D.s_tiles[sidx][plain];
-        const int shape = __builtin_amdgcn_readfirstlane(mp == kMixed ? D.tile : mp);
+        const int64_t local = t - D.s_tiles[mp][plain];
         auto fetch = [&]() { nx = next_tile(ctr, qb, qe, home, qi); };
         uint64_t t0 = 0;
         if (TIMED) t0 = __builtin_amdgcn_s_memrealtime();
-        switch (shape) {
-        case 0: gemm_tile<Cfg0>(D, local, plain, lds, fetch); break;
-        case 1: gemm_tile<Cfg1>(D, local, plain, lds, fetch); break;
-        case 2: gemm_tile<Cfg2>(D, local, plain, lds, fetch); break;
-        default: gemm_tile<Cfg3>(D, local, plain, lds, fetch); break;
-        }
+        gemm_tile<CF>(D, local, plain, lds, fetch);
         __syncthreads();                                // every wave is done with the last slab's stage
         if (tid == 0) {
             if (TIMED) ttime[t] = __builtin_amdgcn_s_memrealtime() - t0;
@@ -1082,17 +1077,6 @@ static int tile_choice(const abft_problem *probs, const int32_t *tiles, int p) {
     return (tiles && tiles[p] >= 0 && tiles[p] < ABFT_BATCH_TILES) ? tiles[p] : model_tile(probs[p]);
 }
 
-static size_t tmap_bytes(const abft_problem *probs, const int32_t *tiles, int count) {
-    size_t s = 0;
-    for (int c = 0; c < kMaps; ++c)
-        for (int pl = 0; pl < 2; ++pl) {
-            int64_t n = 0;
-            for (int p = 0; p < count; ++p) n += tiles_of(probs[p], c == kMixed ? tile_choice(probs, tiles, p) : c, pl);
-            s += align256(sizeof(int) * n);
-        }
-    return s;
-}
-
 // The tile map of the mixed shapes is sized for the largest shape count any
 // choice can give (the map is rewritten when the choice changes); plus the
 // tuner's per-tile durations.
@@ -1104,15 +1088,12 @@ static size_t tmap_bytes_any(const abft_problem *probs, int count) {
             for (int p = 0; p < count; ++p) n += tiles_of(probs[p], c, pl);
             s += align256(sizeof(int) * n);
         }
-    for (int pl = 0; pl < 2; ++pl) {
-        int64_t n = 0;
-        for (int p = 0; p < count; ++p) {
-            int64_t mx = 0;
-            for (int c = 0; c < ABFT_BATCH_TILES; ++c) mx = std::max(mx, tiles_of(probs[p], c, pl));
-            n += mx;
+    for (int c = kMix; c < kMaps; ++c)                 // each mixed map sized for any choice
+        for (int pl = 0; pl < 2; ++pl) {
+            int64_t n = 0;
+            for (int p = 0; p < count; ++p) n += tiles_of(probs[p], shape_of_map(c), pl);
+            s += align256(sizeof(int) * n);
         }
-        s += align256(sizeof(int) * n);
-    }
     return s + align256(sizeof(uint64_t) * max_tiles(probs, count));
 }
 
@@ -1160,10 +1141,9 @@ int batch_setup(const abft_problem *probs, const abft_batch_item *items, int cou
         for (int pl = 0; pl < 2; ++pl) {
             int64_t n = 0, cap = 0;
             for (int p = 0; p < count; ++p) {
-                n += tiles_of(probs[p], c == kMixed ? tile_choice(probs, tiles, p) : c, pl);
-                int64_t mx = 0;
-                for (int e = 0; e < ABFT_BATCH_TILES; ++e) mx = std::max(mx, tiles_of(probs[p], e, pl));
-                cap += c == kMixed ? mx : tiles_of(probs[p], c, pl);
+                const int own = tile_choice(probs, tiles, p);
+                if (on_map(c, own)) n += tiles_of(probs[p], shape_of_map(c), pl);
+                cap += tiles_of(probs[p], shape_of_map(c), pl);   // any choice fits
             }
             if (cap >= (int64_t)INT32_MAX) return ABFT_E_ARG;
             tmaps[c][pl].reserve(n);
@@ -1212,7 +1192,7 @@ int batch_setup(const abft_problem *probs, const abft_batch_item *items, int cou
         for (int c = 0; c < kMaps; ++c) {
             for (int pl = 0; pl < 2; ++pl) {
                 D.s_tiles[c][pl] = ntl[c][pl];
-                const int64_t nt = tiles_of(q, c == kMixed ? D.tile : c, pl);
+                const int64_t nt = on_map(c, D.tile) ? tiles_of(q, shape_of_map(c), pl) : 0;
                 tmaps[c][pl].insert(tmaps[c][pl].end(), (size_t)nt, s);
                 ntl[c][pl] += nt;
             }
@@ -1234,7 +1214,7 @@ int batch_setup(const abft_problem *probs, const abft_batch_item *items, int cou
         for (int pl = 0; pl < 2; ++pl) {
             const std::vector<int> &tm = tmaps[c][pl];
             auto work = [&](int v) {
-                const int sh = c == kMixed ? h[v].tile : c;
+                const int sh = shape_of_map(c);
                 return (double)kTileBM[sh] * kTileBN[sh] * (double)h[v].k;
             };
             double total = 0.0;
@@ -1261,9 +1241,13 @@ int batch_setup(const abft_problem *probs, const abft_batch_item *items, int cou
     plan->bws = bws;
     plan->count = count;
     plan->dtype = ABFT_BF16;
-    for (int c = 0; c < kMaps; ++c) {
-        plan->n_tiles[c][0] = ntl[c][0];
-        plan->n_tiles[c][1] = ntl[c][1];
+    for (int c = 0; c < ABFT_BATCH_TILES; ++c)
+        for (int pl = 0; pl < 2; ++pl) plan->n_tiles[c][pl] = ntl[c][pl];
+    for (int c = 0; c < ABFT_BATCH_TILES; ++c) plan->n_shape[c] = 0;
+    for (int v = 0; v < count; ++v) ++plan->n_shape[h[v].tile];
+    for (int pl = 0; pl < 2; ++pl) {
+        plan->n_tiles[ABFT_BATCH_MIXED][pl] = 0;
+        for (int c = kMix; c < kMaps; ++c) plan->n_tiles[ABFT_BATCH_MIXED][pl] += ntl[c][pl];
     }
     plan->ttime_off = ttime_off;
     for (int e = 0; e < 8; ++e) plan->n_work[e] = w[e];
@@ -1296,17 +1280,32 @@ int batch_encode(const abft_batch_plan *pl, bool quantize, hipStream_t s) {
     return ABFT_OK;
 }
 
-static void launch_gemm_map(const abft_batch_plan *pl, int mp, int plain, uint64_t *ttime, hipStream_t s) {
-    // one block per CU: a whole number of blocks per XCD
+template <class CF>
+static void launch_shape(const abft_batch_plan *pl, int mp, int plain, uint64_t *ttime, hipStream_t s) {
+    // a whole number of blocks per XCD: CF::BPC per CU
     const TileQueues *tq = (const TileQueues *)((const char *)counters(pl) + 256);
-    if (ttime) kb_gemm<true><<<256, kGemmThreads, 0, s>>>(descs(pl), mp, plain, counters(pl), tq, ttime);
-    else kb_gemm<false><<<256, kGemmThreads, 0, s>>>(descs(pl), mp, plain, counters(pl), tq, nullptr);
+    const unsigned grid = 256u * CF::BPC;
+    if (ttime) kb_gemm<CF, true><<<grid, kGemmThreads, 0, s>>>(descs(pl), mp, plain, counters(pl), tq, ttime);
+    else kb_gemm<CF, false><<<grid, kGemmThreads, 0, s>>>(descs(pl), mp, plain, counters(pl), tq, nullptr);
+}
+static void launch_gemm_map(const abft_batch_plan *pl, int mp, int plain, uint64_t *ttime, hipStream_t s) {
+    switch (shape_of_map(mp)) {
+    case 0: launch_shape<Cfg0>(pl, mp, plain, ttime, s); break;
+    case 1: launch_shape<Cfg1>(pl, mp, plain, ttime, s); break;
+    case 2: launch_shape<Cfg2>(pl, mp, plain, ttime, s); break;
+    default: launch_shape<Cfg3>(pl, mp, plain, ttime, s); break;
+    }
 }
 
 int batch_gemm(const abft_batch_plan *pl, int tile, uint32_t flags, hipStream_t s) {
     if (tile < 0 || tile > ABFT_BATCH_MIXED) return ABFT_E_ARG;
     const int plain = (flags & ABFT_PLAIN) ? 1 : 0;
-    launch_gemm_map(pl, tile, plain, nullptr, s);
+    if (tile == ABFT_BATCH_MIXED) {                    // one launch per shape that has problems
+        for (int c = kMix; c < kMaps; ++c)
+            if (pl->n_shape[c - kMix]) launch_gemm_map(pl, c, plain, nullptr, s);
+    } else {
+        launch_gemm_map(pl, tile, plain, nullptr, s);
+    }
     ABFT_LAUNCHED();
     if (!plain) {
         const int64_t n = pl->n_work[W_COMB];
@@ -1353,7 +1352,8 @@ int batch_tune(const abft_batch_plan *pl, double *costs, int32_t *best, hipStrea
             const int64_t t0 = h[v].s_tiles[c][0], t1 = v + 1 < count ? h[v + 1].s_tiles[c][0] : pl->n_tiles[c][0];
             double sum = 0.0;
             for (int64_t t = t0; t < t1; ++t) sum += (double)tt[(size_t)t];
-            cost[(size_t)h[v].orig * ABFT_BATCH_TILES + c] = sum;
+            // CU time: the shapes that run two blocks per CU count half of each tile's duration
+            cost[(size_t)h[v].orig * ABFT_BATCH_TILES + c] = c == 0 ? sum : 0.5 * sum;
         }
     }
     for (int p = 0; p < count; ++p) {
@@ -1361,6 +1361,42 @@ int batch_tune(const abft_batch_plan *pl, double *costs, int32_t *best, hipStrea
         if (costs) std::copy(cp, cp + ABFT_BATCH_TILES, costs + (size_t)p * ABFT_BATCH_TILES);
         if (best) best[p] = (int32_t)(std::min_element(cp, cp + ABFT_BATCH_TILES) - cp);
     }
+    return ABFT_OK;
+}
+
+// Launch-level choice: the whole protected product timed (device events,
+// median of `reps` launches after one warm-up) with each uniform shape and
+// with the per-problem shapes of the plan; returns the fastest.  The
+// per-problem run is one launch per shape, each with its own tail, so the
+// fastest tiles per problem need not give the fastest run.
+int batch_choose(const abft_batch_plan *pl, int reps, double *ms, int32_t *choice, hipStream_t s) {
+    hipEvent_t e0, e1;
+    ABFT_HIP(hipEventCreate(&e0));
+    ABFT_HIP(hipEventCreate(&e1));
+    double best = 0.0;
+    int arg = 0;
+    int st = ABFT_OK;
+    for (int c = 0; c <= ABFT_BATCH_MIXED && st == ABFT_OK; ++c) {
+        std::vector<float> ts;
+        for (int r = 0; r <= reps && st == ABFT_OK; ++r) {
+            if (hipEventRecord(e0, s) != hipSuccess) { st = ABFT_E_HIP; break; }
+            st = batch_gemm(pl, c, 0, s);
+            if (st) break;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { st = ABFT_E_HIP; break; }
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) { st = ABFT_E_HIP; break; }
+            if (r > 0) ts.push_back(t);                // the first launch warms up
+        }
+        if (st) break;
+        std::sort(ts.begin(), ts.end());
+        const double med = ts[ts.size() / 2];
+        if (ms) ms[c] = med;
+        if (c == 0 || med < best) { best = med; arg = c; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) return st;
+    if (choice) *choice = arg;
     return ABFT_OK;
 }
 
@@ -1469,6 +1505,10 @@ int abft_batch_gemm(const abft_batch_plan *plan, int tile, uint32_t flags, void 
 int abft_batch_tune(const abft_batch_plan *plan, double *costs, int32_t *tiles, void *stream) {
     if (!plan || !plan->bws || (!costs && !tiles)) return ABFT_E_ARG;
     return batch_tune(plan, costs, tiles, (hipStream_t)stream);
+}
+int abft_batch_choose(const abft_batch_plan *plan, int reps, double *ms, int32_t *choice, void *stream) {
+    if (!plan || !plan->bws || reps < 1 || reps > 100 || (!ms && !choice)) return ABFT_E_ARG;
+    return batch_choose(plan, reps, ms, choice, (hipStream_t)stream);
 }
 int abft_batch_cache_lookup(const char *path, const char *arch, const abft_problem *probs, int count, int32_t *tiles) {
     if (!path || !probs || !tiles || count < 1) return ABFT_E_ARG;

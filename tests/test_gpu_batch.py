@@ -131,6 +131,14 @@ def test_batch_tiles_agree_and_tune(case, tmp_path):
     for q in range(len(C0)):
         assert torch.equal(C0[q], case.B.C[q]), ("tuned", q)
         assert reps[q].n_flag_c == 0 and reps[q].n_flag_r == 0
+    ms, choice = abft.batch_choose(case.B.plan, reps=2)
+    note(f"  launch choice ms {[round(x, 3) for x in ms]} -> {choice}")
+    assert len(ms) == abft.ABFT_BATCH_TILES + 1 and all(x > 0 for x in ms)
+    assert ms[choice] == min(ms)
+    case.run(choice)
+    torch.cuda.synchronize()
+    for q in range(len(C0)):
+        assert torch.equal(C0[q], case.B.C[q]), ("chosen", q)
     path = str(tmp_path / "batch_tiles.txt")
     abft.batch_cache_store(path, case.B.probs, costs, arch="gfx950")
     found, cached = abft.batch_cache_lookup(path, case.B.probs, arch="gfx950")
