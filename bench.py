@@ -875,7 +875,9 @@ class OracleFlips:
     residual with the oracle's verification and classification.  Only the
     inputs are shared with the GPU run; no value comes from the GPU."""
 
-    def __init__(self, dt_name, A, B, br, bc, lam=10.0):
+    def __init__(self, dt_name, A, B, br, bc, lam=10.0, carried_steps=0.0):
+        """carried_steps: accumulation steps of the stored totals when the product computes them in
+        binary32 (the batched path's matrix-core checksum rows, k / 4); 0 when they are binary64 sums."""
         import numpy as np
 
         from oracle import oracle as orc
@@ -917,7 +919,7 @@ class OracleFlips:
 
             def tau(Cf):
                 tc, tr = orc.tau_stat(self.Af, self.Bf, m, n, br, bc, u_acc=2.0 ** -24, T=T, s_store=s_store,
-                                      lam=lam, Cf=Cf / sc if sc != 1.0 else Cf)
+                                      lam=lam, Cf=Cf / sc if sc != 1.0 else Cf, T_c=carried_steps)
                 return tc * sc, tr * sc
             self._tau = tau
             self.tc, self.tr = tau(self.C)
@@ -1374,7 +1376,7 @@ def run_batched_campaign(args):
             m, n, k = shapes[q]
             A = synth.uniform(SEED + q, synth.STREAM_A, m, k, np.float32)
             B = synth.uniform(SEED + q, synth.STREAM_B, k, n, np.float32)
-            oracles[q] = OracleFlips("bf16", A, B, br, bc, lam=cfg["lam"])
+            oracles[q] = OracleFlips("bf16", A, B, br, bc, lam=cfg["lam"], carried_steps=k / 4.0)
         return oracles[q]
 
     st = flip_tally(32)

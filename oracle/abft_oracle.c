@@ -203,17 +203,23 @@ void orc_tau_det(int64_t m, int64_t n, int64_t k, int64_t br, int64_t bc,
  * t is far above the root-sum-square of its products.  A non-finite t (a
  * fault in the stored total) adds no term, so that the relation's residual,
  * non-finite too, fails against a finite threshold.
+ * Where the stored totals are themselves accumulated in steps of the same
+ * precision (T_c steps, e.g. a carried checksum row computed on the matrix
+ * cores; T_c = 0 when they are summed in binary64), their running sums carry
+ * the total's own magnitude: for terms of one sign the partial sums grow
+ * linearly, sum_l s_l^2 = t^2 T_c / 3, which adds (u^2/3)(T_c/3) t^2:
+ * sigma^2 += (u^2/3) (1 + T_c/3) t^2 in all.
  * A_f is (m+br) x k and B_f is k x (n+bc), both row-major and encoded; C_f is
  * (m+br) x (n+bc) with leading dimension ldc.
  */
 void orc_tau_stat(int64_t m, int64_t n, int64_t k, int64_t br, int64_t bc,
                   const double *Af, int64_t lda, const double *Bf, int64_t ldb,
                   double u_acc, double T, double s_store, double lambda,
-                  const double *Cf, int64_t ldc, double *tau_c, double *tau_r)
+                  const double *Cf, int64_t ldc, double T_c, double *tau_c, double *tau_r)
 {
     int64_t Gr = m / br, Gc = n / bc, N = n + bc, M = m + br;
     double coef = u_acc * u_acc / 3.0 * (T / 2.0 + s_store);
-    double cst = u_acc * u_acc / 3.0;
+    double cst = u_acc * u_acc / 3.0 * (1.0 + T_c / 3.0);
     double *v = (double *)calloc((size_t)(br * k), sizeof(double));
     double *w = (double *)calloc((size_t)(k * bc), sizeof(double));
     for (int64_t r = 0; r < br; ++r) {

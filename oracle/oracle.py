@@ -78,7 +78,7 @@ def lib():
             "orc_group_abs_col_norms": (None, [_I, _I, _I, _P, _I, _P]),
             "orc_gamma": (_D, [_D, _D]),
             "orc_tau_det": (None, [_I, _I, _I, _I, _I, _P, _P, _P, _P, _D, _D, _D, _P, _P]),
-            "orc_tau_stat": (None, [_I, _I, _I, _I, _I, _P, _I, _P, _I, _D, _D, _D, _D, _P, _I, _P, _P]),
+            "orc_tau_stat": (None, [_I, _I, _I, _I, _I, _P, _I, _P, _I, _D, _D, _D, _D, _P, _I, _D, _P, _P]),
             "orc_report_size": (_I, []),
             "orc_verify": (None, [_I, _I, _I, _I, _P, _I, _P, _P, _P, C.c_int, _P, _P, _P]),
             "orc_classify": (C.c_int, [_I, _I, _I, _I, _P, _P, C.c_int, _P, _P, _P]),
@@ -195,9 +195,11 @@ def tau_det_chained(Af, Bf, m, n, br, bc, tau_c_prev, kappa=1.0 + 2.0 ** -20):
     return tc + _f64(tau_c_prev)[:, :k] @ np.abs(Bf), tr
 
 
-def tau_stat(Af, Bf, m, n, br, bc, u_acc=U32, T=None, s_store=1.0, lam=10.0, Cf=None):
+def tau_stat(Af, Bf, m, n, br, bc, u_acc=U32, T=None, s_store=1.0, lam=10.0, Cf=None, T_c=0.0):
     """Statistical thresholds; Cf (the encoded product, same domain as A_f B_f)
-    adds the binary32 rounding of each relation's stored total."""
+    adds the binary32 rounding of each relation's stored total, and T_c the
+    accumulation steps of the stored totals when they are themselves summed in
+    that precision (0: binary64)."""
     Af = _f64(Af)
     Bf = _f64(Bf)
     k = Af.shape[1]
@@ -209,7 +211,8 @@ def tau_stat(Af, Bf, m, n, br, bc, u_acc=U32, T=None, s_store=1.0, lam=10.0, Cf=
         Cf = _f64(Cf)
         assert Cf.shape[0] >= m + br and Cf.shape[1] >= n + bc
     lib().orc_tau_stat(m, n, k, br, bc, _p(Af), k, _p(Bf), n + bc, u_acc, float(T), s_store, lam,
-                       _p(Cf) if Cf is not None else None, Cf.shape[1] if Cf is not None else 0, _p(tc), _p(tr))
+                       _p(Cf) if Cf is not None else None, Cf.shape[1] if Cf is not None else 0, float(T_c),
+                       _p(tc), _p(tr))
     return tc, tr
 
 

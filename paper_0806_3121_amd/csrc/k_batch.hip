@@ -49,7 +49,7 @@ struct BatchDesc {
     double *vpart;                    // verification row partials [M][ceil(N / 1024)][bc]
     abft_report *rep;
     double cc, cr;                    // stat coefficients (lambda^2 (u^2/3)(T/2 + s))
-    double cst;                       // lambda^2 u^2 / 3: the stored total's binary32 rounding
+    double cst;                       // lambda^2 (u^2/3)(1 + T/3): the stored total's rounding and accumulation
     int mode;                         // ABFT_TAU_STAT or ABFT_TAU_EXACT
     int orig;                         // index in the caller's order
     int tile;                         // the problem's own product tile shape (0 .. ABFT_BATCH_TILES-1)
@@ -1188,7 +1188,9 @@ int batch_setup(const abft_problem *probs, const abft_batch_item *items, int cou
         D.orig = p;
         D.tile = tile_choice(probs, tiles, p);
         TauCoef tc = tau_coef(&q);
-        D.cc = tc.cc; D.cr = tc.cr; D.cst = tc.cst; D.mode = q.tau_mode;
+        // the stored totals (carried rows and columns) are accumulated on the matrix cores in binary32,
+        // k/4 steps of the hi, mid and lo parts: their running sums have the totals' own magnitude
+        D.cc = tc.cc; D.cr = tc.cr; D.cst = tc.cst * (1.0 + ((double)q.k / 4.0) / 3.0); D.mode = q.tau_mode;
         for (int c = 0; c < kMaps; ++c) {
             for (int pl = 0; pl < 2; ++pl) {
                 D.s_tiles[c][pl] = ntl[c][pl];

@@ -63,10 +63,12 @@ class Case:
             Af, Bf = orc.encode(A, Bm, br, bc, store_f32=True)
             C64 = orc.gemm(Af, Bf)
             C32 = C64.astype(np.float32)
-            tc, tr = orc.tau_stat(Af, Bf, m, n, br, bc, u_acc=U32, T=k / 4.0, s_store=2.0, lam=LAMBDA, Cf=C64)
+            # the carried totals are accumulated on the matrix cores: T_c = k / 4 steps
+            tc, tr = orc.tau_stat(Af, Bf, m, n, br, bc, u_acc=U32, T=k / 4.0, s_store=2.0, lam=LAMBDA, Cf=C64,
+                                  T_c=k / 4.0)
             retau = (lambda Af, Bf, m, n, k, br, bc: lambda Cx: orc.tau_stat(
                 Af, Bf, m, n, br, bc, u_acc=U32, T=k / 4.0, s_store=2.0, lam=LAMBDA,
-                Cf=np.asarray(Cx, dtype=np.float64)))(Af, Bf, m, n, k, br, bc)
+                Cf=np.asarray(Cx, dtype=np.float64), T_c=k / 4.0))(Af, Bf, m, n, k, br, bc)
             bound = k * U32 * (np.abs(Af) @ np.abs(Bf)) + U32 * np.abs(C32)
             self.ref.append(dict(Aq=Aq, Bq=Bq, C32=C32, tc=tc, tr=tr, bound=bound, retau=retau))
         torch.cuda.synchronize()
@@ -319,3 +321,25 @@ def test_batch_unpadded_rows_match_padded(dev):
                         (loc.cls, loc.i, loc.j)))
             B.C[q].copy_(cl[q])
         assert got[0] == got[1], (q, i, j, bit, got)
+
+
+def test_batch_same_sign_operands_verify_clean(dev):
+    """Operands of one sign (|uniform|) over the batch's shape range up to k =
+    2048: the carried checksum rows run on the matrix cores (hi + mid + lo),
+    so their accumulation errors have one sign too; every relation passes."""
+    shapes = [(2048, 2048, 2048, 32, 1), (1024, 2048, 2048, 32, 32), (512, 640, 1536, 32, 1), (96, 200, 2048, 32, 8)]
+    B = abft.Batch(shapes, device=dev, tau_mode=abft.ABFT_TAU_STAT, lam=LAMBDA)
+    for q, (m, n, k, br, bc) in enumerate(shapes):
+        abft.fill_uniform(abft.ABFT_F32, m, k, k, 0, SEED + 60 + q, synth.STREAM_A, B.A32[q])
+        abft.fill_uniform(abft.ABFT_F32, k, n, k, 1, SEED + 60 + q, synth.STREAM_B, B.Bt32[q])
+        B.A32[q].abs_()
+        B.Bt32[q].abs_()
+    abft.batch_quantize_encode(B.plan)
+    for tile in (0, 3):
+        abft.batch_gemm(B.plan, tile)
+        abft.batch_verify(B.plan)
+        reps = B.reports()
+        note(f"same-sign batch, tile {tile}: max |D|/tau " +
+             " ".join(f"{max(r.max_ratio_c, r.max_ratio_r):.3f}" for r in reps))
+        for q, r in enumerate(reps):
+            assert r.n_flag_c == 0 and r.n_flag_r == 0, (tile, q, r.max_ratio_c, r.max_ratio_r)

@@ -64,7 +64,11 @@ MUTATIONS = [
     ("orc_tau_stat: T/2 -> T", C, "double coef = u_acc * u_acc / 3.0 * (T / 2.0 + s_store);",
      "double coef = u_acc * u_acc / 3.0 * (T + s_store);", pins.test_stat_model_matches_simulated_fp32_accumulation,
      {}),
-    ("orc_tau_stat: stored-total rounding dropped", C, "double cst = u_acc * u_acc / 3.0;", "double cst = 0.0;",
+    ("orc_tau_stat: stored-total rounding dropped", C, "double cst = u_acc * u_acc / 3.0 * (1.0 + T_c / 3.0);",
+     "double cst = 0.0;",
+     pins.test_stat_threshold_hand_value_b2, {}),
+    ("orc_tau_stat: accumulated stored totals' drift dropped", C,
+     "double cst = u_acc * u_acc / 3.0 * (1.0 + T_c / 3.0);", "double cst = u_acc * u_acc / 3.0 * (1.0 + T_c / 6.0);",
      pins.test_stat_threshold_hand_value_b2, {}),
     ("orc_tau_stat: non-finite stored total kept in the rounding term", C,
      "double t = Cf && isfinite(Cf[(m + r) * ldc + j]) ? Cf[(m + r) * ldc + j] : 0.0;",

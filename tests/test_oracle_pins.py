@@ -294,6 +294,11 @@ def test_stat_threshold_hand_value_b2(orc):
     tc, tr = orc.tau_stat(Af, Bf, 4, 4, 2, 2, u_acc=u, T=T, s_store=s, lam=lam, Cf=Cf)
     assert np.allclose(tc, lam * np.sqrt(coef * np.outer(nv, b4) + u * u / 3 * t_c ** 2), rtol=1e-13, atol=0)
     assert np.allclose(tr, lam * np.sqrt(coef * np.outer(a4, nw) + u * u / 3 * t_r ** 2), rtol=1e-13, atol=0)
+    # stored totals that are themselves accumulated in T_c = 6 steps of the same
+    # precision add (u^2/3)(T_c/3) t^2: a factor 1 + 2 = 3 on the stored-total term
+    tc6, tr6 = orc.tau_stat(Af, Bf, 4, 4, 2, 2, u_acc=u, T=T, s_store=s, lam=lam, Cf=Cf, T_c=6.0)
+    assert np.allclose(tc6, lam * np.sqrt(coef * np.outer(nv, b4) + 3 * u * u / 3 * t_c ** 2), rtol=1e-13, atol=0)
+    assert np.allclose(tr6, lam * np.sqrt(coef * np.outer(a4, nw) + 3 * u * u / 3 * t_r ** 2), rtol=1e-13, atol=0)
     # a fault that makes a stored total infinite adds no rounding term: the
     # threshold stays that of the Q part alone, and the relation (residual -inf
     # for the column, +inf for the row through the same entry) fails
