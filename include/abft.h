@@ -116,7 +116,10 @@ typedef enum { ABFT_TAU_DET = 0, ABFT_TAU_STAT = 1, ABFT_TAU_EXACT = 2 } abft_ta
  * element type cannot hold, so abft_encode keeps them in the workspace.
  * Requirements: m % br == 0, n % bc == 0, k >= 1, and rows of A_f / columns
  * of B_f start on 16-byte boundaries (lda*size and ldb*size multiples of 16,
- * base pointers 16-byte aligned); k is a multiple of 16/size.  C_f only
+ * base pointers 16-byte aligned); k is a multiple of 16/size (ABFT_E_ARG
+ * otherwise: for another k, pad A_f with zero columns and B_f with zero rows
+ * up to the next multiple, which leaves the product and its checksums
+ * unchanged and the thresholds larger only through the larger k).  C_f only
  * needs its natural alignment (any ldc >= its minimum, e.g. n+1).
  */
 typedef struct {

@@ -252,3 +252,31 @@ def test_flip_and_erasure_in_one_run(dev, orc, where):
     assert rep.n_flag_c == 0 and rep.n_flag_r == 0
     Cg = P.C.cpu().numpy()
     assert rel_err(Cg, Cf) <= TOL64 and rel_err(Cg, clean) <= TOL64
+
+
+def test_odd_k_by_zero_padding(dev, orc):
+    """k = 255 is refused (rows of A_f and columns of B_f must be whole 16-byte
+    chunks); padded with one zero column of A and zero row of B it gives the
+    unpadded product (the oracle's C_f of the 255-deep problem), verifies
+    clean, and locates a flip."""
+    m, n, k, b = 512, 384, 255, 64
+    A = synth.uniform(SEED + 5, synth.STREAM_A, m, k)
+    B = synth.uniform(SEED + 5, synth.STREAM_B, k, n)
+    p_odd = abft.problem(abft.ABFT_F64, m, n, k, b, b)
+    ws = torch.zeros(abft.workspace_size(p_odd), dtype=torch.uint8, device=dev)
+    with pytest.raises(abft.AbftError):
+        abft.encode(p_odd, torch.zeros(m + b, k, dtype=torch.float64, device=dev),
+                    torch.zeros(n + b, k, dtype=torch.float64, device=dev), ws)
+    P = abft.Protected(abft.ABFT_F64, m, n, k + 1, b, b, device=dev)
+    P.A[:m, :k] = torch.from_numpy(A).to(dev)
+    P.Bt[:n, :k] = torch.from_numpy(np.ascontiguousarray(B.T)).to(dev)
+    P.encode()
+    P.gemm()
+    torch.cuda.synchronize()
+    _, _, Cf = orc.protected_product(A, B, b, b)
+    assert rel_err(P.C.cpu().numpy(), Cf) <= TOL64
+    rep = P.verify()
+    assert rep.n_flag_c == 0 and rep.n_flag_r == 0
+    abft.inject_flip(P.p, P.C, 300, 200, 55)
+    loc = abft.classify(P.p, P.verify())
+    assert (loc.cls, loc.i, loc.j) == (abft.ABFT_CLS_DATA, 300, 200)
