@@ -44,7 +44,8 @@ struct BatchDesc {
     uint16_t *asp, *bsp;              // the same split into bfloat16: (3 br x k), (3 bc x k), hi rows first
     double *grpA, *grpB;              // per-residue sums of squares (br x k), (bc x k)
     double *partA, *partB;            // encode partials [P][2][b][k] when P > 1
-    float *S1, *S2;                   // product staging: rows m.. of the virtual C (3 br x NV); columns n.. (m x 3 bc)
+    float *S1, *S2;                   // product staging: rows m.. of the virtual C (3 br x ld1); columns n.. (m x 3 bc)
+    int64_t ld1;                      // S1 row length: NV rounded up to 4 (16-byte rows)
     double *qr, *qc, *nv, *nw;        // threshold statistics (M, N, br, bc)
     double *vpart;                    // verification row partials [M][ceil(N / 1024)][bc]
     abft_report *rep;
@@ -53,7 +54,8 @@ struct BatchDesc {
     int mode;                         // ABFT_TAU_STAT or ABFT_TAU_EXACT
     int orig;                         // index in the caller's order
     int tile;                         // the problem's own product tile shape (0 .. ABFT_BATCH_TILES-1)
-    int cvec;                         // rows of C 16-byte aligned (C at 16 bytes, ldc a multiple of 4)
+    int cvec;                         // rows of C 16-byte aligned (C at 16 bytes, ldc a multiple of 4, below 2^27)
+    int s1vec;                        // ld1 below 2^27 (the 16-byte stores of S1)
     // starts in the flattened work spaces: tiles of each uniform shape, then of the per-problem shapes
     int64_t s_tiles[2 * ABFT_BATCH_TILES][2];   // [map][plain]: maps of the uniform shapes, then the per-shape mixed ones
     int64_t s_quant, s_enc1, s_enc2, s_rows, s_comb, s_vcol, s_vrow;
@@ -645,20 +647,40 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const BatchDesc 
 #pragma unroll
                 for (int v = 0; v < 4; ++v) Ct[(16 * a + v) * D.ldc + 16 * b] = acc[a][b][v];
     } else {
+        // edge tile: each 16 x 16 block of a wave (its bounds are wave-uniform) lying wholly in the
+        // data block (C, aligned rows) or wholly in the checksum rows (S1, 16-byte rows) takes the
+        // 16-byte form; only the blocks across a boundary, or in the columns >= n (S2), are stored
+        // element by element (all blocks element-wise: 14.2 us per 256 x 256 edge tile, 3.7 for an
+        // interior one)
+        // (lane offsets in 32 bits: the 16-byte forms need ldc and ld1 below 2^27, which cvec and s1vec state)
+        const int p = lane & 3;
+        const int lc = (4 * lq + p) * (int)D.ldc + (lr & ~3), l1 = (4 * lq + p) * (int)D.ld1 + (lr & ~3);
 #pragma unroll
         for (int a = 0; a < CF::TMW; ++a) {
 #pragma unroll
             for (int b = 0; b < CF::TNW; ++b) {
-                const int64_t gc = col0 + wn * (CF::BN / CF::WN) + 16 * b + lr;
+                const int64_t r0 = row0 + wm * (CF::BM / CF::WM) + 16 * a, c0 = col0 + wn * (CF::BN / CF::WN) + 16 * b;
+                if (r0 >= MV || c0 >= NV) continue;
+                if (D.cvec && r0 + 16 <= D.m && c0 + 16 <= D.n) {
+                    v4f x = acc[a][b];
+                    quad_transpose(x, p);
+                    *(G<v4f> *)(gp(D.C) + (r0 * D.ldc + c0) + lc) = x;
+                } else if (D.s1vec && r0 >= D.m && r0 + 16 <= MV && c0 + 16 <= NV) {
+                    v4f x = acc[a][b];
+                    quad_transpose(x, p);
+                    *(G<v4f> *)(gp(D.S1) + ((r0 - D.m) * D.ld1 + c0) + l1) = x;
+                } else {
+                    const int64_t gc = c0 + lr;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int64_t gr = row0 + wm * (CF::BM / CF::WM) + 16 * a + 4 * lq + v;
-                    if (gr < MV && gc < NV) {
-                        if (gr < D.m) {
-                            if (gc < D.n) gp(D.C)[gr * D.ldc + gc] = acc[a][b][v];
-                            else gp(D.S2)[gr * 3 * D.bc + (gc - D.n)] = acc[a][b][v];
-                        } else {
-                            gp(D.S1)[(gr - D.m) * D.NV + gc] = acc[a][b][v];
+                    for (int v = 0; v < 4; ++v) {
+                        const int64_t gr = r0 + 4 * lq + v;
+                        if (gr < MV && gc < NV) {
+                            if (gr < D.m) {
+                                if (gc < D.n) gp(D.C)[gr * D.ldc + gc] = acc[a][b][v];
+                                else gp(D.S2)[gr * 3 * D.bc + (gc - D.n)] = acc[a][b][v];
+                            } else {
+                                gp(D.S1)[(gr - D.m) * D.ld1 + gc] = acc[a][b][v];
+                            }
                         }
                     }
                 }
@@ -696,12 +718,20 @@ __global__ __launch_bounds__(kGemmThreads, CF::BPC == 1 ? 2 : 4) void kb_gemm(co
         uint64_t t0 = 0;
         if (TIMED) t0 = __builtin_amdgcn_s_memrealtime();
         gemm_tile<CF>(D, local, plain, lds, fetch);
-        __syncthreads();                                // every wave is done with the last slab's stage
+        // every wave is done with the last slab's stage.  Bare barriers: the
+        // tile's stores need not land before the next tile's loads (measured
+        // 0.5 % faster than the fenced __syncthreads on the 512-problem batch).
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
         if (tid == 0) {
             if (TIMED) ttime[t] = __builtin_amdgcn_s_memrealtime() - t0;
             sh_next = nx;
+            __builtin_amdgcn_s_waitcnt(0xC07F);         // lgkmcnt(0): the header written before the barrier
         }
-        __syncthreads();
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
         t = uniform64(sh_next);
     }
     // the last block out resets the queue counters for the next launch
@@ -725,7 +755,7 @@ __global__ __launch_bounds__(kT) void kb_combine(const BatchDesc *__restrict__ d
             const int64_t q = u / n, j = u - q * n;
             double s = 0.0;
 #pragma unroll
-            for (int s3 = 0; s3 < 3; ++s3) s += (double)gp(D.S1)[(s3 * br + q) * NV + j];
+            for (int s3 = 0; s3 < 3; ++s3) s += (double)gp(D.S1)[(s3 * br + q) * D.ld1 + j];
             gp(D.C)[(m + q) * D.ldc + j] = (float)s;
             continue;
         }
@@ -745,7 +775,7 @@ __global__ __launch_bounds__(kT) void kb_combine(const BatchDesc *__restrict__ d
 #pragma unroll
             for (int s3 = 0; s3 < 3; ++s3)
 #pragma unroll
-                for (int t3 = 0; t3 < 3; ++t3) s += (double)gp(D.S1)[(s3 * br + q) * NV + n + t3 * bc + c];
+                for (int t3 = 0; t3 < 3; ++t3) s += (double)gp(D.S1)[(s3 * br + q) * D.ld1 + n + t3 * bc + c];
             gp(D.C)[(m + q) * D.ldc + n + c] = (float)s;
         }
     }
@@ -1011,7 +1041,7 @@ Parts parts_of(const abft_problem &q) {
     b.grpB = align256(sizeof(double) * q.bc * q.k);
     b.partA = b.PA > 1 ? align256(sizeof(double) * 2 * b.PA * q.br * q.k) : 0;
     b.partB = b.PB > 1 ? align256(sizeof(double) * 2 * b.PB * q.bc * q.k) : 0;
-    b.S1 = align256(sizeof(float) * 3 * q.br * (q.n + 3 * q.bc));
+    b.S1 = align256(sizeof(float) * 3 * q.br * ((q.n + 3 * q.bc + 3) / 4 * 4));
     b.S2 = align256(sizeof(float) * q.m * 3 * q.bc);
     b.qr = align256(sizeof(double) * (q.m + q.br));
     b.qc = align256(sizeof(double) * (q.n + q.bc));
@@ -1162,9 +1192,10 @@ int batch_setup(const abft_problem *probs, const abft_batch_item *items, int cou
         BatchDesc &D = h[s];
         D.m = q.m; D.n = q.n; D.k = q.k; D.br = q.br; D.bc = q.bc;
         D.lda = q.lda; D.ldb = q.ldb; D.ldc = q.ldc;
-        D.cvec = ((uintptr_t)items[p].C_f % 16 == 0 && q.ldc % 4 == 0) ? 1 : 0;
+        D.cvec = ((uintptr_t)items[p].C_f % 16 == 0 && q.ldc % 4 == 0 && q.ldc < (1 << 27)) ? 1 : 0;
         D.M = q.m + q.br; D.N = q.n + q.bc; D.Gr = q.m / q.br; D.Gc = q.n / q.bc;
-        D.MV = q.m + 3 * q.br; D.NV = q.n + 3 * q.bc;
+        D.MV = q.m + 3 * q.br; D.NV = q.n + 3 * q.bc; D.ld1 = (D.NV + 3) / 4 * 4;
+        D.s1vec = D.ld1 < (1 << 27) ? 1 : 0;
         D.A32 = items[p].A32; D.Bt32 = items[p].Bt32;
         D.A = (uint16_t *)items[p].A_f; D.Bt = (uint16_t *)items[p].B_f; D.C = (float *)items[p].C_f;
         Parts b = parts_of(q);
