@@ -461,7 +461,7 @@ typedef struct {
     int32_t dtype;
     int64_t n_tiles[ABFT_BATCH_TILES + 1][2];  /* product tiles per shape and for the per-problem shapes:
                                                   [.][0] protected, [.][1] ABFT_PLAIN */
-    int64_t n_work[8];                         /* flattened work sizes of the other steps; [7]: problems
+    int64_t n_work[12];                        /* flattened work sizes of the other steps; [7]: problems
                                                   whose C_f rows are not 16-byte aligned */
     size_t bytes;
     size_t ttime_off;                          /* the tuner's per-tile durations in bws */
@@ -539,6 +539,13 @@ int abft_batch_verify(const abft_batch_plan *plan, void *stream);
 /* Copy the count reports (verify results, in the caller's problem order) to
  * host_out (pinned; valid after a stream synchronisation). */
 int abft_batch_reports(const abft_batch_plan *plan, abft_report *host_out, void *stream);
+/* Diagnostic (for tests): the thresholds the verification uses for problem
+ * `problem` (caller's order), from the threshold statistics of the last encode
+ * and the stored totals now in its C_f: tau_c (device, br x (n + bc),
+ * row-major) for the column relations (r, j), tau_r (device, (m + br) x bc)
+ * for the row relations (i, c); 0 under ABFT_TAU_EXACT.  Reads the
+ * descriptors back (synchronous copy), then launches on the stream. */
+int abft_batch_thresholds(const abft_batch_plan *plan, int problem, double *tau_c, double *tau_r, void *stream);
 
 /*
  * Weighted f-checksums (Sec. 2.1).  Sec. 2.1 protects p values x_g with f

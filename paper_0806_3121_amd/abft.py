@@ -82,7 +82,7 @@ BATCH_TILE_SHAPES = [(256, 256), (256, 128), (128, 256), (128, 128)]
 class abft_batch_plan(C.Structure):
     _fields_ = [("bws", C.c_void_p), ("count", C.c_int32), ("dtype", C.c_int32),
                 ("n_tiles", (C.c_int64 * 2) * (ABFT_BATCH_TILES + 1)),
-                ("n_work", C.c_int64 * 8),
+                ("n_work", C.c_int64 * 12),
                 ("bytes", C.c_size_t), ("ttime_off", C.c_size_t), ("n_shape", C.c_int32 * ABFT_BATCH_TILES)]
 
 
@@ -163,6 +163,7 @@ def lib():
                                                  _P(C.c_double)]),
             "abft_batch_verify": (C.c_int, [_P(abft_batch_plan), _V]),
             "abft_batch_reports": (C.c_int, [_P(abft_batch_plan), _V, _V]),
+            "abft_batch_thresholds": (C.c_int, [_P(abft_batch_plan), C.c_int, _V, _V, _V]),
             "abft_wworkspace_size": (C.c_size_t, [_P(abft_wproblem)]),
             "abft_wsetup": (C.c_int, [_P(abft_wproblem), _V, _Z]),
             "abft_wencode": (C.c_int, [_P(abft_wproblem), _V, _V, _V, _Z, _V]),
@@ -432,6 +433,12 @@ def batch_cache_store(path, probs, costs, arch=None):
 
 def batch_verify(plan, stream=None):
     return _check("abft_batch_verify", lib().abft_batch_verify(C.byref(plan), _stream(stream)))
+
+
+def batch_thresholds(plan, problem, tau_c, tau_r, stream=None):
+    """tau_c: float64 device tensor (br, n + bc); tau_r: (m + br, bc)."""
+    return _check("abft_batch_thresholds", lib().abft_batch_thresholds(C.byref(plan), problem, _ptr(tau_c),
+                                                                       _ptr(tau_r), _stream(stream)))
 
 
 def batch_reports(plan, host_out, stream=None):

@@ -47,6 +47,8 @@ struct BatchDesc {
     float *S1, *S2;                   // product staging: rows m.. of the virtual C (3 br x ld1); columns n.. (m x 3 bc)
     int64_t ld1;                      // S1 row length: NV rounded up to 4 (16-byte rows)
     double *qr, *qc, *nv, *nw;        // threshold statistics (M, N, br, bc)
+    double *rowpart;                  // strip partials of the data rows' statistics when ns > 1: A rows (m x ns), B rows (n x ns)
+    int64_t ns;                       // 128-column strips of a row: ceil(k / 128)
     double *vpart;                    // verification row partials [M][ceil(N / 1024)][bc]
     abft_report *rep;
     double cc, cr;                    // stat coefficients (lambda^2 (u^2/3)(T/2 + s))
@@ -58,10 +60,11 @@ struct BatchDesc {
     int s1vec;                        // ld1 below 2^27 (the 16-byte stores of S1)
     // starts in the flattened work spaces: tiles of each uniform shape, then of the per-problem shapes
     int64_t s_tiles[2 * ABFT_BATCH_TILES][2];   // [map][plain]: maps of the uniform shapes, then the per-shape mixed ones
-    int64_t s_quant, s_enc1, s_enc2, s_rows, s_comb, s_vcol, s_vrow;
+    int64_t s_quant, s_enc1, s_enc2, s_rows, s_comb, s_vcol, s_vrow, s_encB, s_rfin;
 };
 
-enum { W_QUANT = 0, W_ENC1, W_ENC2, W_ROWS, W_COMB, W_VCOL, W_VROW, W_UNALIGNED };
+// Flattened work spaces (plan->n_work): s_enc1 is pass 1 of A, s_encB of B.
+enum { W_QUANT = 0, W_ENC1, W_ENC2, W_ROWS, W_COMB, W_VCOL, W_VROW, W_UNALIGNED, W_ENCB, W_RFIN, W_COUNT };
 
 // A pointer read from a descriptor, typed as global memory: offsets are added
 // in the global address space, and the result is cast back to a generic
@@ -200,36 +203,61 @@ __device__ inline void enc_finish(G<float> *cs, G<uint16_t> *sp, G<double> *grp,
                  pack2(h[s3][6], h[s3][7])};
 }
 
-// Pass 1, unit = (side, partition, residue r, 8 columns): sums over the
-// partition's groups g of X[g*b + r, l] and of its square; final values when
-// the side has one partition, else partials.  QUANT: the rows are read in
-// binary32 (for the items that have them), rounded to bfloat16 and stored,
-// and the sums are taken of the rounded values (quantize and pass 1 in one
-// read of the binary32 operand).
-template <bool QUANT>
-__global__ __launch_bounds__(kT) void kb_encode1(const BatchDesc *__restrict__ d, int count, int64_t total) {
-    Walk<&BatchDesc::s_enc1, kT> wk(d, count, total);
+// Row statistic of the data rows of a side (the thresholds' Q terms): 0 none
+// here (B when br = 1: its rows are weighted by A's sums of squares, known only
+// after A's pass; the row statistics pass takes them), 1 sum x^2 w with w the
+// other side's per-column sums of squares (A when bc = 1), 2 ||x||_4^2.
+__device__ inline int side_rowstat(const BatchDesc &D, int side) {
+    return side ? (D.br == 1 ? 0 : 2) : (D.bc == 1 ? 1 : 2);
+}
+
+// Pass 1 of one side (SIDE 0: A, 1: B), unit = (partition p, residue r, strip,
+// lane16): lane16 of a strip holds columns l0 = (16 strip + lane16) * 8 ..
+// l0 + 7 (none past k).  Sums over the partition's groups g of X[g*b + r, l]
+// and of its square; final values when the side has one partition, else
+// partials.  The data rows' statistic is taken in the same read: each row's
+// 16 lane partials (added over the lane's 8 columns in order) are added by a
+// butterfly over the 16 lanes; with one strip that is the row's value, else
+// the strip's partial, added in strip order by kb_rowsfin.  QUANT: the rows
+// are read in binary32 (for the items that have them), rounded to bfloat16 and
+// stored, and every sum is taken of the rounded values (quantize, pass 1 and
+// the row statistics in one read of the binary32 operand).
+template <bool QUANT, int SIDE>
+__global__ __launch_bounds__(kT) void kb_encside(const BatchDesc *__restrict__ d, int count, int64_t total) {
+    Walk<SIDE ? &BatchDesc::s_encB : &BatchDesc::s_enc1, kT> wk(d, count, total);
+    const int lane16 = threadIdx.x % 16;
     for (int64_t b0 = wk.first; b0 < wk.last; b0 += kT) {
         const BatchDesc &D = wk.at(b0);
-        int64_t q = b0 - D.s_enc1 + threadIdx.x;
-        const int64_t kv = D.k / 8, ua = D.PA * D.br * kv;
-        if (q >= ua + D.PB * D.bc * kv) continue;
-        const bool isA = q < ua;
-        if (!isA) q -= ua;
-        const int64_t b = isA ? D.br : D.bc, NG = isA ? D.Gr : D.Gc, P = isA ? D.PA : D.PB;
-        const int64_t ld = isA ? D.lda : D.ldb;
-        const int64_t p = q / (b * kv), rem = q - p * (b * kv), r = rem / kv, l0 = (rem - r * kv) * 8;
+        const int64_t q = b0 - (SIDE ? D.s_encB : D.s_enc1) + threadIdx.x;
+        const int64_t b = SIDE ? D.bc : D.br, NG = SIDE ? D.Gc : D.Gr, P = SIDE ? D.PB : D.PA;
+        const int64_t ld = SIDE ? D.ldb : D.lda, ns = D.ns, K = D.k;
+        const int64_t grp = q / 16, strip = grp % ns, pr = grp / ns, r = pr % b, p = pr / b;
+        if (p >= P) continue;                          // whole groups of 16 lanes
+        const int64_t l0 = (strip * 16 + lane16) * 8;
+        const bool has = l0 < K;
+        const int rs = side_rowstat(D, SIDE);
         const int64_t ch = (NG + P - 1) / P, g0 = p * ch, g1 = min(NG, g0 + ch);
-        G<uint16_t> *X = (isA ? gp(D.A) : gp(D.Bt)) + r * ld + l0;
-        double s[8], ss[8], v[8];
+        double w[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) w[e] = (rs == 1 && has) ? gp(D.grpB)[l0 + e] : 0.0;
+        G<double> *rdst = rs == 0 ? nullptr
+                          : ns == 1 ? (SIDE ? gp(D.qc) : gp(D.qr))
+                                    : gp(D.rowpart) + (SIDE ? D.m * ns : 0) + strip;
+        const int64_t rstride = ns == 1 ? 1 : ns;
+        G<uint16_t> *X = (SIDE ? gp(D.Bt) : gp(D.A)) + r * ld + l0;
+        const G<const float> *X32 = QUANT ? (SIDE ? gp(D.Bt32) : gp(D.A32)) : nullptr;
+        if (X32) X32 += r * ld + l0;
+        double s[8], ss[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) s[e] = ss[e] = 0.0;
-        const G<const float> *X32 = QUANT ? (isA ? gp(D.A32) : gp(D.Bt32)) : nullptr;
-        if (X32) {
-            X32 += r * ld + l0;
-#pragma unroll 4
-            for (int64_t g = g0; g < g1; ++g) {
-                const int64_t o = g * b * ld;
+#pragma unroll 2
+        for (int64_t g = g0; g < g1; ++g) {
+            const int64_t o = g * b * ld;
+            double x[8];
+            if (!has) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) x[e] = 0.0;
+            } else if (X32) {
                 const v4f_ x0 = *(const G<v4f_> *)(X32 + o), x1 = *(const G<v4f_> *)(X32 + o + 4);
                 uint16_t h[8];
 #pragma unroll
@@ -239,25 +267,34 @@ __global__ __launch_bounds__(kT) void kb_encode1(const BatchDesc *__restrict__ d
                 }
                 *(G<v4u_> *)(X + o) = v4u_{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const double x = (double)bf16_to_f32(h[e]);
-                    s[e] += x;
-                    ss[e] += x * x;
+                for (int e = 0; e < 8; ++e) x[e] = (double)bf16_to_f32(h[e]);
+            } else {
+                gload<uint16_t>::load(X + o, x);
+            }
+            double part = 0.0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                s[e] += x[e];
+                const double x2 = x[e] * x[e];
+                ss[e] += x2;
+                part += rs == 1 ? x2 * w[e] : x2 * x2;
+            }
+            if (rs) {
+                // the 16 lanes of the strip (every lane of the group runs the same trip count)
+                for (int off = 8; off > 0; off >>= 1) part += __shfl_xor(part, off, kW);
+                if (lane16 == 0) {
+                    const double v = (ns == 1 && rs == 2) ? sqrt(part) : part;
+                    rdst[(g * b + r) * rstride] = v;
                 }
             }
-        } else {
-#pragma unroll 4
-            for (int64_t g = g0; g < g1; ++g) {
-                gload<uint16_t>::load(X + g * b * ld, v);
-#pragma unroll
-                for (int e = 0; e < 8; ++e) { s[e] += v[e]; ss[e] += v[e] * v[e]; }
-            }
         }
+        if (!has) continue;
         if (P == 1) {
-            enc_finish(isA ? gp(D.acs) : gp(D.bcs), isA ? gp(D.asp) : gp(D.bsp), isA ? gp(D.grpA) : gp(D.grpB), b, D.k, r, l0, s, ss);
+            enc_finish(SIDE ? gp(D.bcs) : gp(D.acs), SIDE ? gp(D.bsp) : gp(D.asp), SIDE ? gp(D.grpB) : gp(D.grpA), b, K,
+                       r, l0, s, ss);
         } else {
-            G<double> *part = isA ? gp(D.partA) : gp(D.partB);
-            G<double> *ps = part + ((2 * p) * b + r) * D.k + l0, *pq = part + ((2 * p + 1) * b + r) * D.k + l0;
+            G<double> *part = SIDE ? gp(D.partB) : gp(D.partA);
+            G<double> *ps = part + ((2 * p) * b + r) * K + l0, *pq = part + ((2 * p + 1) * b + r) * K + l0;
 #pragma unroll
             for (int e = 0; e < 8; e += 2) {
                 *(G<v2d_> *)(ps + e) = v2d_{s[e], s[e + 1]};
@@ -268,8 +305,8 @@ __global__ __launch_bounds__(kT) void kb_encode1(const BatchDesc *__restrict__ d
 }
 
 // Pass 1 finish for the sides with several partitions: partials added in
-// partition order.
-__global__ __launch_bounds__(kT) void kb_encode2(const BatchDesc *__restrict__ d, int count, int64_t total) {
+// partition order.  Only the units of side `side` (0: A, 1: B).
+__global__ __launch_bounds__(kT) void kb_encode2(const BatchDesc *__restrict__ d, int count, int64_t total, int side) {
     Walk<&BatchDesc::s_enc2, kT> wk(d, count, total);
     for (int64_t b0 = wk.first; b0 < wk.last; b0 += kT) {
         const BatchDesc &D = wk.at(b0);
@@ -278,6 +315,7 @@ __global__ __launch_bounds__(kT) void kb_encode2(const BatchDesc *__restrict__ d
         const int64_t ua = D.PA > 1 ? D.br * kv : 0, ub = D.PB > 1 ? D.bc * kv : 0;
         if (q >= ua + ub) continue;
         const bool isA = q < ua;
+        if (isA != (side == 0)) continue;
         if (!isA) q -= ua;
         const int64_t b = isA ? D.br : D.bc, P = isA ? D.PA : D.PB;
         const int64_t r = q / kv, l0 = (q - r * kv) * 8;
@@ -299,10 +337,11 @@ __global__ __launch_bounds__(kT) void kb_encode2(const BatchDesc *__restrict__ d
 }
 
 // ------------------------------------------------------------------ row statistics
-// Segments per problem, each padded to kRowsPerIter rows: [A rows m, acs rows br]
-// [Bt rows n, bcs rows bc] [grpA rows br, grpB rows bc].  Data and checksum rows:
-// sum x^2 w (the other side's b == 1, w = its grp) or ||x||_4^2; grp rows: ||.||_2.
-// Sixteen lanes per row, 16 rows per wave and block iteration.
+// The rows pass passes 1 do not take: segments per problem, each padded to
+// kRowsPerIter rows: [acs rows br] [B rows n when br = 1, then bcs rows bc]
+// [grpA rows br, grpB rows bc].  Data and checksum rows: sum x^2 w (the other
+// side's b == 1, w = its grp) or ||x||_4^2; grp rows: ||.||_2.  Sixteen lanes
+// per row, 16 rows per wave and block iteration.
 __device__ inline int64_t pad_to(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
 // Element e of a 16-byte chunk of T, widened to binary64.
@@ -357,7 +396,8 @@ __global__ __launch_bounds__(kT) void kb_rowstats(const BatchDesc *__restrict__ 
     for (int64_t b0 = wk.first; b0 < wk.last; b0 += kRowsPerIter) {
         const BatchDesc &D = wk.at(b0);
         const int64_t q0 = b0 - D.s_rows;
-        const int64_t pa = pad_to(D.m + D.br, kRowsPerIter), pb = pad_to(D.n + D.bc, kRowsPerIter);
+        const int64_t nb = D.br == 1 ? D.n : 0;        // B data rows taken here
+        const int64_t pa = pad_to(D.br, kRowsPerIter), pb = pad_to(nb + D.bc, kRowsPerIter);
         const int seg = q0 < pa ? 0 : (q0 < pa + pb ? 1 : 2);
         const int64_t r0 = seg == 0 ? q0 : (seg == 1 ? q0 - pa : q0 - pa - pb);
         const bool use_w = seg == 0 ? D.bc == 1 : (seg == 1 ? D.br == 1 : false);
@@ -376,28 +416,23 @@ __global__ __launch_bounds__(kT) void kb_rowstats(const BatchDesc *__restrict__ 
             double out = 0.0;
             G<double> *dst = nullptr;
             if (seg == 0) {
-                if (r < D.m) {
-                    const G<uint16_t> *row = gp(D.A) + r * D.lda;
-                    out = use_w ? row_stat<uint16_t, 1>(row, D.k, ws, wg, lane16)
-                                : row_stat<uint16_t, 0>(row, D.k, ws, wg, lane16);
-                    dst = gp(D.qr) + r;
-                } else if (r < D.m + D.br) {
-                    const G<float> *row = gp(D.acs) + (r - D.m) * D.k;
+                if (r < D.br) {
+                    const G<float> *row = gp(D.acs) + r * D.k;
                     out = use_w ? row_stat<float, 1>(row, D.k, ws, wg, lane16)
                                 : row_stat<float, 0>(row, D.k, ws, wg, lane16);
-                    dst = gp(D.qr) + r;
+                    dst = gp(D.qr) + D.m + r;
                 }
             } else if (seg == 1) {
-                if (r < D.n) {
+                if (r < nb) {
                     const G<uint16_t> *row = gp(D.Bt) + r * D.ldb;
                     out = use_w ? row_stat<uint16_t, 1>(row, D.k, ws, wg, lane16)
                                 : row_stat<uint16_t, 0>(row, D.k, ws, wg, lane16);
                     dst = gp(D.qc) + r;
-                } else if (r < D.n + D.bc) {
-                    const G<float> *row = gp(D.bcs) + (r - D.n) * D.k;
+                } else if (r < nb + D.bc) {
+                    const G<float> *row = gp(D.bcs) + (r - nb) * D.k;
                     out = use_w ? row_stat<float, 1>(row, D.k, ws, wg, lane16)
                                 : row_stat<float, 0>(row, D.k, ws, wg, lane16);
-                    dst = gp(D.qc) + r;
+                    dst = gp(D.qc) + D.n + (r - nb);
                 }
             } else {
                 if (r < D.br) {
@@ -410,6 +445,26 @@ __global__ __launch_bounds__(kT) void kb_rowstats(const BatchDesc *__restrict__ 
             }
             if (dst && lane16 == 0) *dst = out;
         }
+    }
+}
+
+// The data rows' statistics taken in strips (ns > 1): unit = a row of A (m),
+// then of B (n, when pass 1 of B takes them); the strip partials added in
+// strip order, then the square root for ||x||_4^2.
+__global__ __launch_bounds__(kT) void kb_rowsfin(const BatchDesc *__restrict__ d, int count, int64_t total) {
+    Walk<&BatchDesc::s_rfin, kT> wk(d, count, total);
+    for (int64_t b0 = wk.first; b0 < wk.last; b0 += kT) {
+        const BatchDesc &D = wk.at(b0);
+        const int64_t i = b0 - D.s_rfin + threadIdx.x;
+        const int64_t nbr = side_rowstat(D, 1) ? D.n : 0;
+        if (i >= D.m + nbr) continue;
+        const int side = i < D.m ? 0 : 1;
+        const int64_t row = side ? i - D.m : i;
+        const G<double> *pp = gp(D.rowpart) + i * D.ns;
+        double acc = 0.0;
+        for (int64_t t = 0; t < D.ns; ++t) acc += pp[t];
+        const double v = side_rowstat(D, side) == 2 ? sqrt(acc) : acc;
+        (side ? gp(D.qc) : gp(D.qr))[row] = v;
     }
 }
 
@@ -1017,17 +1072,37 @@ __global__ __launch_bounds__(kT) void kb_verify2(const BatchDesc *__restrict__ d
     }
 }
 
+// The thresholds of one problem (descriptor v), as the verification computes
+// them: column relations (r, j) into tc (br x N), row relations (i, c) into tr
+// (M x bc); the stored totals are read from C.
+__global__ __launch_bounds__(kT) void kb_thresholds(const BatchDesc *__restrict__ d, int v, double *tc, double *tr) {
+    const BatchDesc &D = d[v];
+    int64_t u = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const int64_t nc = D.br * D.N;
+    if (u < nc) {
+        const int64_t r = u / D.N, j = u - r * D.N;
+        tc[u] = btau(D, true, r, j, (double)gp(D.C)[(D.m + r) * D.ldc + j]);
+        return;
+    }
+    u -= nc;
+    if (u < D.M * D.bc) {
+        const int64_t i = u / D.bc, c = u - i * D.bc;
+        tr[u] = btau(D, false, i, c, (double)gp(D.C)[i * D.ldc + D.n + c]);
+    }
+}
+
 // ------------------------------------------------------------------ host side
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 int64_t pad_h(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
 struct Parts {
     int64_t PA, PB;
-    size_t acs, bcs, asp, bsp, grpA, grpB, partA, partB, S1, S2, qr, qc, nv, nw, vpart;
+    size_t acs, bcs, asp, bsp, grpA, grpB, partA, partB, S1, S2, qr, qc, nv, nw, vpart, rowpart;
     size_t total() const {
-        return acs + bcs + asp + bsp + grpA + grpB + partA + partB + S1 + S2 + qr + qc + nv + nw + vpart;
+        return acs + bcs + asp + bsp + grpA + grpB + partA + partB + S1 + S2 + qr + qc + nv + nw + vpart + rowpart;
     }
 };
+int64_t strips_of(const abft_problem &q) { return (q.k + 127) / 128; }
 Parts parts_of(const abft_problem &q) {
     Parts b;
     const int64_t Gr = q.m / q.br, Gc = q.n / q.bc;
@@ -1048,6 +1123,8 @@ Parts parts_of(const abft_problem &q) {
     b.nv = align256(sizeof(double) * q.br);
     b.nw = align256(sizeof(double) * q.bc);
     b.vpart = align256(sizeof(double) * (q.m + q.br) * vstrips(q.n + q.bc, true) * q.bc);   // the larger count
+    const int64_t ns = strips_of(q);
+    b.rowpart = ns > 1 ? align256(sizeof(double) * (q.m + q.n) * ns) : 0;
     return b;
 }
 
@@ -1185,7 +1262,8 @@ int batch_setup(const abft_problem *probs, const abft_batch_item *items, int cou
     off += align256(sizeof(uint64_t) * max_tiles(probs, count));
     std::vector<BatchDesc> h(count);
     int64_t ntl[kMaps][2] = {};
-    int64_t w[8] = {};
+    int64_t w[W_COUNT] = {};
+    static_assert(W_COUNT <= 12, "plan->n_work");
     for (int s = 0; s < count; ++s) {
         const int p = order[s];
         const abft_problem &q = probs[p];
@@ -1215,6 +1293,8 @@ int batch_setup(const abft_problem *probs, const abft_batch_item *items, int cou
         D.nv = (double *)(base + off); off += b.nv;
         D.nw = (double *)(base + off); off += b.nw;
         D.vpart = (double *)(base + off); off += b.vpart;
+        D.rowpart = (double *)(base + off); off += b.rowpart;
+        D.ns = strips_of(q);
         D.rep = reps + p;
         D.orig = p;
         D.tile = tile_choice(probs, tiles, p);
@@ -1232,11 +1312,14 @@ int batch_setup(const abft_problem *probs, const abft_batch_item *items, int cou
         }
         const int64_t kv = q.k / 8;
         D.s_quant = w[W_QUANT]; w[W_QUANT] += pad_h((q.m + q.n) * kv, kT);
-        D.s_enc1 = w[W_ENC1]; w[W_ENC1] += pad_h((b.PA * q.br + b.PB * q.bc) * kv, kT);
+        const int64_t ns = strips_of(q), nbr = q.br == 1 ? 0 : q.n;   // B rows of pass 1 (else of the rows pass)
+        D.s_enc1 = w[W_ENC1]; w[W_ENC1] += pad_h(b.PA * q.br * ns * 16, kT);
+        D.s_encB = w[W_ENCB]; w[W_ENCB] += pad_h(b.PB * q.bc * ns * 16, kT);
         D.s_enc2 = w[W_ENC2]; w[W_ENC2] += pad_h(((b.PA > 1 ? q.br : 0) + (b.PB > 1 ? q.bc : 0)) * kv, kT);
         D.s_rows = w[W_ROWS];
-        w[W_ROWS] += pad_h(q.m + q.br, kRowsPerIter) + pad_h(q.n + q.bc, kRowsPerIter) +
+        w[W_ROWS] += pad_h(q.br, kRowsPerIter) + pad_h((q.br == 1 ? q.n : 0) + q.bc, kRowsPerIter) +
                      pad_h(q.br + q.bc, kRowsPerIter);
+        D.s_rfin = w[W_RFIN]; w[W_RFIN] += ns > 1 ? pad_h(q.m + nbr, kT) : 0;
         D.s_comb = w[W_COMB]; w[W_COMB] += pad_h(q.br * q.n + q.m * q.bc + q.br * q.bc, kT);
         D.s_vcol = w[W_VCOL]; w[W_VCOL] += pad_h(q.br * vstrips(q.n + q.bc, D.cvec), kT / kW);
         D.s_vrow = w[W_VROW]; w[W_VROW] += pad_h((q.m + q.br) * q.bc, kT);
@@ -1283,7 +1366,7 @@ int batch_setup(const abft_problem *probs, const abft_batch_item *items, int cou
         for (int c = kMix; c < kMaps; ++c) plan->n_tiles[ABFT_BATCH_MIXED][pl] += ntl[c][pl];
     }
     plan->ttime_off = ttime_off;
-    for (int e = 0; e < 8; ++e) plan->n_work[e] = w[e];
+    for (int e = 0; e < W_COUNT; ++e) plan->n_work[e] = w[e];
     plan->bytes = need;
     return ABFT_OK;
 }
@@ -1303,12 +1386,18 @@ int batch_quantize(const abft_batch_plan *pl, hipStream_t s) {
     return ABFT_OK;
 }
 
+// B first: A's row statistics are weighted by B's sums of squares when bc = 1.
 int batch_encode(const abft_batch_plan *pl, bool quantize, hipStream_t s) {
-    const int64_t n1 = pl->n_work[W_ENC1], n2 = pl->n_work[W_ENC2], nr = pl->n_work[W_ROWS];
-    if (quantize) kb_encode1<true><<<blocks_for(n1, kT), kT, 0, s>>>(descs(pl), pl->count, n1);
-    else kb_encode1<false><<<blocks_for(n1, kT), kT, 0, s>>>(descs(pl), pl->count, n1);
-    if (n2 > 0) kb_encode2<<<blocks_for(n2, kT), kT, 0, s>>>(descs(pl), pl->count, n2);
+    const int64_t na = pl->n_work[W_ENC1], nb = pl->n_work[W_ENCB], n2 = pl->n_work[W_ENC2];
+    const int64_t nr = pl->n_work[W_ROWS], nf = pl->n_work[W_RFIN];
+    if (quantize) kb_encside<true, 1><<<blocks_for(nb, kT), kT, 0, s>>>(descs(pl), pl->count, nb);
+    else kb_encside<false, 1><<<blocks_for(nb, kT), kT, 0, s>>>(descs(pl), pl->count, nb);
+    if (n2 > 0) kb_encode2<<<blocks_for(n2, kT), kT, 0, s>>>(descs(pl), pl->count, n2, 1);
+    if (quantize) kb_encside<true, 0><<<blocks_for(na, kT), kT, 0, s>>>(descs(pl), pl->count, na);
+    else kb_encside<false, 0><<<blocks_for(na, kT), kT, 0, s>>>(descs(pl), pl->count, na);
+    if (n2 > 0) kb_encode2<<<blocks_for(n2, kT), kT, 0, s>>>(descs(pl), pl->count, n2, 0);
     kb_rowstats<<<blocks_for(nr, kRowsPerIter), kT, 0, s>>>(descs(pl), pl->count, nr);
+    if (nf > 0) kb_rowsfin<<<blocks_for(nf, kT), kT, 0, s>>>(descs(pl), pl->count, nf);
     ABFT_LAUNCHED();
     return ABFT_OK;
 }
@@ -1362,6 +1451,19 @@ int batch_reports(const abft_batch_plan *pl, abft_report *host, hipStream_t s) {
     const char *base = (const char *)pl->bws + align256(sizeof(BatchDesc) * pl->count) + kCtlBytes;
     ABFT_HIP(hipMemcpyAsync(host, base, sizeof(abft_report) * pl->count, hipMemcpyDeviceToHost, s));
     return ABFT_OK;
+}
+
+int batch_thresholds(const abft_batch_plan *pl, int problem, double *tc, double *tr, hipStream_t s) {
+    std::vector<BatchDesc> h(pl->count);
+    ABFT_HIP(hipMemcpy(h.data(), pl->bws, sizeof(BatchDesc) * pl->count, hipMemcpyDeviceToHost));
+    for (int v = 0; v < pl->count; ++v)
+        if (h[v].orig == problem) {
+            const int64_t units = h[v].br * h[v].N + h[v].M * h[v].bc;
+            kb_thresholds<<<blocks_for(units, kT), kT, 0, s>>>(descs(pl), v, tc, tr);
+            ABFT_LAUNCHED();
+            return ABFT_OK;
+        }
+    return ABFT_E_ARG;
 }
 
 // Tuner: each uniform tile shape runs once with the durations of its tiles
@@ -1594,6 +1696,10 @@ int abft_batch_verify(const abft_batch_plan *plan, void *stream) {
 int abft_batch_reports(const abft_batch_plan *plan, abft_report *host_out, void *stream) {
     if (!plan || !plan->bws || !host_out) return ABFT_E_ARG;
     return batch_reports(plan, host_out, (hipStream_t)stream);
+}
+int abft_batch_thresholds(const abft_batch_plan *plan, int problem, double *tau_c, double *tau_r, void *stream) {
+    if (!plan || !plan->bws || !tau_c || !tau_r || problem < 0 || problem >= plan->count) return ABFT_E_ARG;
+    return batch_thresholds(plan, problem, tau_c, tau_r, (hipStream_t)stream);
 }
 
 }  // extern "C"

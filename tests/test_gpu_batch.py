@@ -40,7 +40,11 @@ def dev():
 def batch_shapes():
     # edge shapes (one group, minimal k, ragged tiles, one large problem) then seeded draws
     shapes = [(32, 32, 8, 32, 1), (64, 40, 24, 32, 8), (96, 200, 72, 32, 1), (2048, 1056, 1024, 32, 32),
-              (128, 132, 64, 32, 2), (192, 1060, 128, 32, 4)]
+              (128, 132, 64, 32, 2), (192, 1060, 128, 32, 4),
+              # small br (several partitions of A's groups), br = 1 (B's rows weighted by A's sums of
+              # squares, taken after A's pass), rows in one and in several 128-column strips
+              (64, 96, 256, 1, 1), (96, 64, 200, 4, 1), (40, 48, 136, 8, 2), (33, 70, 520, 1, 2),
+              (48, 50, 1032, 1, 1)]
     for q, (m, n, k) in enumerate(synth.batched_shapes(SEED, 20, lo=64, hi=640, step=32)):
         shapes.append((m, n, k, 32, 1 if q % 2 == 0 else 32))
     return shapes
@@ -108,6 +112,38 @@ def test_batch_product_and_clean_verify(case, tile):
         assert np.all(err <= r["bound"] * 1.01 + 1e-30), (q, case.shapes[q], err.max())
         assert reps[q].n_flag_c == 0 and reps[q].n_flag_r == 0, (q, reps[q].max_ratio_c, reps[q].max_ratio_r)
     note(f"  max |D|/tau {max(max(x.max_ratio_c, x.max_ratio_r) for x in reps):.4f}")
+
+
+def test_batch_thresholds_match_oracle(case):
+    """The thresholds the verification uses (the encode's threshold statistics,
+    the product's stored totals) against the oracle's for every relation of
+    every problem, after the encode of stored bfloat16 operands; the fused
+    quantize + encode gives the same thresholds bit for bit.  Tolerance: the
+    stored totals are binary32 sums on the matrix cores (the oracle's are
+    exact), which moves a threshold by far less than 1e-4 of itself."""
+    case.run(0)
+    torch.cuda.synchronize()
+
+    def thresholds():
+        out = []
+        for q, (m, n, k, br, bc) in enumerate(case.shapes):
+            tc = torch.empty(br, n + bc, dtype=torch.float64, device=case.B.C[q].device)
+            tr = torch.empty(m + br, bc, dtype=torch.float64, device=case.B.C[q].device)
+            abft.batch_thresholds(case.B.plan, q, tc, tr)
+            out.append((tc, tr))
+        torch.cuda.synchronize()
+        return [(tc.cpu().numpy(), tr.cpu().numpy()) for tc, tr in out]
+
+    enc = thresholds()
+    for q, ((tc, tr), r) in enumerate(zip(enc, case.ref)):
+        note(f"thresholds problem {q} {case.shapes[q]}")
+        assert np.all(np.isfinite(tc)) and np.all(tc > 0) and np.all(np.isfinite(tr)) and np.all(tr > 0)
+        np.testing.assert_allclose(tc, r["tc"], rtol=1e-4, atol=0)
+        np.testing.assert_allclose(tr, r["tr"], rtol=1e-4, atol=0)
+    abft.batch_quantize_encode(case.B.plan)
+    fused = thresholds()
+    for q, (a, b) in enumerate(zip(enc, fused)):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), q
 
 
 def test_batch_tiles_agree_and_tune(case, tmp_path):
