@@ -22,9 +22,11 @@ __host__ __device__ inline float bf16_to_f32(uint16_t b) {
 __host__ __device__ inline uint16_t f32_to_bf16_rne(float f) {
     uint32_t u;
     __builtin_memcpy(&u, &f, 4);
-    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40u);
-    uint32_t rounding = 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)((u + rounding) >> 16);
+    // branch-free (a select, not a divergent branch per element): NaN keeps its
+    // sign and top payload bits and is made quiet
+    const uint32_t rounded = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+    const uint32_t quiet = (u >> 16) | 0x40u;
+    return (uint16_t)((u & 0x7FFFFFFFu) > 0x7F800000u ? quiet : rounded);
 }
 
 // OCP FP8 E4M3 (e4m3fn): bias 7, 3 fraction bits, largest finite 448, no
