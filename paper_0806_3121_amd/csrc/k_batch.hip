@@ -615,29 +615,38 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const BatchDesc 
     const int64_t tm = band * GM + in_band % gsz, tn = in_band / gsz;
     const int64_t row0 = tm * CF::BM, col0 = tn * CF::BN;
 
+    // The start of the row of A (of B) at row (column) offset rr of the tile: A or its checksum
+    // rows (both addresses formed, then one selected; as a branch, the descriptor fields were
+    // reloaded per row and the kernels spilled)
+    const uint16_t *pA = D.A, *pAs = D.asp, *pB = D.Bt, *pBs = D.bsp;
+    const int64_t dm = D.m, dn = D.n, lda = D.lda, ldb = D.ldb;
+    auto row_a = [&](int rr) -> const uint16_t * {
+        const int64_t gr = min(row0 + rr, MV - 1);
+        const uint16_t *x = pA + gr * lda, *y = pAs + (gr - dm) * K;
+        return gr < dm ? x : y;
+    };
+    auto row_b = [&](int rr) -> const uint16_t * {
+        const int64_t gc = min(col0 + rr, NV - 1);
+        const uint16_t *x = pB + gc * ldb, *y = pBs + (gc - dn) * K;
+        return gc < dn ? x : y;
+    };
+    // the 16-byte chunk of combined row rr (A rows, then B rows) that lane ln fetches at k offset 0
+    auto chunk_src = [&](int rr, int ln) -> const uint16_t * {
+        const int kc = (ln % CF::CPR) ^ ((rr / CF::RP) % CF::CPR);
+        return (rr < CF::BM ? row_a(rr) : row_b(rr - CF::BM)) + kc * 8;
+    };
+    // load instruction q of wave w fills the 1 KB of slab rows (w LPW + q) RPI ..: A rows, then B rows
     const uint16_t *src[CF::LPW];
 #pragma unroll
-    for (int q = 0; q < CF::LPW; ++q) {
-        const int c = (wave * CF::LPW + q) * 64 + lane;
-        const int rr = c / CF::CPR, kc = (c % CF::CPR) ^ ((rr / CF::RP) % CF::CPR);
-        const uint16_t *base;
-        if (rr < CF::BM) {
-            const int64_t gr = min(row0 + rr, MV - 1);
-            base = (const uint16_t *)(gr < D.m ? gp(D.A) + gr * D.lda : gp(D.asp) + (gr - D.m) * K);
-        } else {
-            const int64_t gc = min(col0 + (rr - CF::BM), NV - 1);
-            base = (const uint16_t *)(gc < D.n ? gp(D.Bt) + gc * D.ldb : gp(D.bsp) + (gc - D.n) * K);
-        }
-        src[q] = base + kc * 8;
-    }
+    for (int q = 0; q < CF::LPW; ++q) src[q] = chunk_src((wave * CF::LPW + q) * CF::RPI + lane / CF::CPR, lane);
     const void *zero = (const void *)kZeroChunk;
     auto issue = [&](int stage, int64_t k0) {
         uint8_t *dst = lds + CF::HDR + stage * CF::STAGE + wave * CF::LPW * 1024;
         const bool full = k0 + CF::BK <= K;
 #pragma unroll
         for (int q = 0; q < CF::LPW; ++q) {
-            const int c = (wave * CF::LPW + q) * 64 + lane;
-            const int rr = c / CF::CPR, kc = (c % CF::CPR) ^ ((rr / CF::RP) % CF::CPR);
+            const int rr = (wave * CF::LPW + q) * CF::RPI + lane / CF::CPR;
+            const int kc = (lane % CF::CPR) ^ ((rr / CF::RP) % CF::CPR);
             const void *g = (full || k0 + kc * 8 < K) ? (const void *)(src[q] + k0) : zero;
             __builtin_amdgcn_global_load_lds(g, (void *)(dst + q * 1024), 16, 0, 0);
         }
@@ -651,6 +660,32 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const BatchDesc 
     const int arow = wm * (CF::BM / CF::WM) + lr, brow = CF::BM + wn * (CF::BN / CF::WN) + lr;
 
     const int64_t nk = (K + CF::BK - 1) / CF::BK;
+    // fragments of k group g of the slab in stage `stage`
+    auto read = [&](int stage, int g, v4u (&fa)[CF::TMW], v4u (&fb)[CF::TNW]) {
+        const uint8_t *S = lds + CF::HDR + stage * CF::STAGE;
+        const int kc = 4 * g + lq;
+#pragma unroll
+        for (int a = 0; a < CF::TMW; ++a) {
+            const int r = arow + 16 * a;
+            fa[a] = *(const v4u *)(S + r * CF::SLAB + ((kc ^ ((r / CF::RP) % CF::CPR)) << 4));
+        }
+#pragma unroll
+        for (int b = 0; b < CF::TNW; ++b) {
+            const int r = brow + 16 * b;
+            fb[b] = *(const v4u *)(S + r * CF::SLAB + ((kc ^ ((r / CF::RP) % CF::CPR)) << 4));
+        }
+    };
+    auto mma = [&](const v4u (&fa)[CF::TMW], const v4u (&fb)[CF::TNW]) {
+#pragma unroll
+        for (int a = 0; a < CF::TMW; ++a)
+#pragma unroll
+            for (int b = 0; b < CF::TNW; ++b) Bf16Ops::mfma(fa[a], fb[b], acc[a][b]);
+    };
+    auto barrier = []() {
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    };
 #pragma unroll
     for (int s = 0; s < CF::NS - 1; ++s)
         if (s < nk) issue(s, (int64_t)s * CF::BK);
@@ -660,32 +695,16 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const BatchDesc 
         else __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
         // and every wave is done with slab kt - 1.  A bare barrier: the
         // fence of __syncthreads would wait for every slab in flight.
-        asm volatile("" ::: "memory");
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
+        barrier();
         if (kt + CF::NS - 1 < nk) issue((int)((kt + CF::NS - 1) % CF::NS), (kt + CF::NS - 1) * CF::BK);
         // the next tile, taken during the last slab (taken earlier, it would
         // sit reserved while idle blocks find the queues empty)
         if (kt == nk - 1 && tid == 0) fetch();
-        const uint8_t *S = lds + CF::HDR + (int)(kt % CF::NS) * CF::STAGE;
 #pragma unroll
         for (int g = 0; g < CF::KGS; ++g) {
-            const int kc = 4 * g + lq;
             v4u fa[CF::TMW], fb[CF::TNW];
-#pragma unroll
-            for (int a = 0; a < CF::TMW; ++a) {
-                const int r = arow + 16 * a;
-                fa[a] = *(const v4u *)(S + r * CF::SLAB + ((kc ^ ((r / CF::RP) % CF::CPR)) << 4));
-            }
-#pragma unroll
-            for (int b = 0; b < CF::TNW; ++b) {
-                const int r = brow + 16 * b;
-                fb[b] = *(const v4u *)(S + r * CF::SLAB + ((kc ^ ((r / CF::RP) % CF::CPR)) << 4));
-            }
-#pragma unroll
-            for (int a = 0; a < CF::TMW; ++a)
-#pragma unroll
-                for (int b = 0; b < CF::TNW; ++b) Bf16Ops::mfma(fa[a], fb[b], acc[a][b]);
+            read((int)(kt % CF::NS), g, fa, fb);
+            mma(fa, fb);
         }
     }
 
