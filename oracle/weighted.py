@@ -31,6 +31,7 @@ import numpy as np
 from . import oracle as _orc
 
 U64 = 2.0 ** -53
+U32 = 2.0 ** -24
 COND_MAX = 1e12            # largest 1-norm condition number of a recovery system accepted
 CLEAN, DATA, CHECKSUM, MULTI = 0, 1, 2, 3
 DIR_COL, DIR_ROW = 0, 1
@@ -107,16 +108,24 @@ def _residuals(Cf, m, n, br, bc, Wr, Wc, fr, Gr, fc, Gc, M, N):
     return Dc, Dr
 
 
-def wtau_det(Af, Bf, m: int, n: int, br: int, bc: int, Wr, Wc, kappa: float = 1.0 + 2.0 ** -20):
-    """Rigorous binary64 thresholds (tau_c (fr, br, N), tau_r (M, fc, bc)).
+def wtau_det(Af, Bf, m: int, n: int, br: int, bc: int, Wr, Wc, kappa: float = 1.0 + 2.0 ** -20,
+             u_acc: float = U64, u_st: float = 0.0):
+    """Rigorous thresholds (tau_c (fr, br, N), tau_r (M, fc, bc)).
 
     Column relation (r, i, j): every computed entry of C_f is within
-    gamma_k |a_x||b_j| <= gamma_k ||a_x||_2 ||b_j||_2 of its exact value; the
-    stored checksum row is within gamma_Gr sum_g |w_rg||a_g| of the exact
-    weighted sum; the binary64 relation sum adds gamma_{Gr+1} times the sum of
-    the magnitudes of its terms.  With S = sum_g |w_rg| ||a_{g br + i}||_2 all
-    three are bounded by (2 gamma_k + 3 gamma_{Gr+1}) S ||b_j||_2 up to
-    O(u^2) terms, which kappa covers.  Rows: the same with the roles swapped."""
+    gamma_k |a_x||b_j| <= gamma_k ||a_x||_2 ||b_j||_2 of its exact value
+    (gamma of the product's accumulation roundoff u_acc); the stored checksum
+    row is within gamma_Gr sum_g |w_rg||a_g| of the exact weighted sum (summed
+    in binary64), plus u_st sum_g |w_rg||a_g| when that sum is then rounded to
+    a narrower storage format (u_st = 2^-24 for binary32 checksum rows, 0 when
+    they keep the binary64 sum); the binary64 relation sum adds gamma_{Gr+1}
+    times the sum of the magnitudes of its terms.  With
+    S = sum_g |w_rg| ||a_{g br + i}||_2 all of them are bounded by
+    (2 gamma_k + u_st + 3 gamma_{Gr+1}) S ||b_j||_2 up to products of two
+    roundoffs, which kappa covers.  Rows: the same with the roles swapped.
+    Binary64 operands and product: u_acc = 2^-53, u_st = 0; binary32
+    operands, checksum rows and product (accumulated in binary32):
+    u_acc = u_st = 2^-24."""
     Af = np.asarray(Af, dtype=np.float64)
     Bf = np.asarray(Bf, dtype=np.float64)
     Wr = np.abs(np.asarray(Wr, dtype=np.float64))
@@ -134,8 +143,8 @@ def wtau_det(Af, Bf, m: int, n: int, br: int, bc: int, Wr, Wc, kappa: float = 1.
     for c in range(fc):
         for h in range(Gc):
             S2[c] += Wc[c, h] * nb[h * bc:(h + 1) * bc]
-    cc = kappa * (2 * gamma(k) + 3 * gamma(Gr + 1))
-    cr = kappa * (2 * gamma(k) + 3 * gamma(Gc + 1))
+    cc = kappa * (2 * gamma(k, u_acc) + u_st + 3 * gamma(Gr + 1))
+    cr = kappa * (2 * gamma(k, u_acc) + u_st + 3 * gamma(Gc + 1))
     tau_c = cc * S1[:, :, None] * nb[None, None, :]
     tau_r = cr * na[:, None, None] * S2[None, :, :]
     return tau_c, tau_r

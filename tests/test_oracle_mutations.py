@@ -120,9 +120,14 @@ MUTATIONS = [
     ("weighted.wencode: one block dropped", W, "for g in range(Gr):\n            acc += Wr[r, g] * A[g * br:(g + 1) * br]",
      "for g in range(Gr - 1):\n            acc += Wr[r, g] * A[g * br:(g + 1) * br]",
      wpins.test_section_2_1_checksums_by_hand, {}),
-    ("weighted.wtau_det: summation terms dropped", W, "cc = kappa * (2 * gamma(k) + 3 * gamma(Gr + 1))",
-     "cc = kappa * (2 * gamma(k))", wpins.test_det_threshold_needs_its_summation_term,
+    ("weighted.wtau_det: summation terms dropped", W, "cc = kappa * (2 * gamma(k, u_acc) + u_st + 3 * gamma(Gr + 1))",
+     "cc = kappa * (2 * gamma(k, u_acc) + u_st)", wpins.test_det_threshold_needs_its_summation_term,
      dict(wlo=0.5, whi=1.5)),
+    ("weighted.wtau_det: product roundoff always binary64", W,
+     "cc = kappa * (2 * gamma(k, u_acc) + u_st + 3 * gamma(Gr + 1))",
+     "cc = kappa * (2 * gamma(k) + u_st + 3 * gamma(Gr + 1))",
+     wpins.test_det_threshold_binary32_bounds_binary32_residuals,
+     dict(m=64, n=32, k=4096, br=8, bc=4, fr=2, fc=2, positive=True)),
     ("weighted.fit_group: ratio test without the threshold", W,
      "fit = all(abs(d[r] - w[r] * delta) <= t[r] + eps * (abs(d[r]) + abs(w[r] * delta)) for r in range(f))",
      "fit = all(abs(d[r] - w[r] * delta) <= 0.0 for r in range(f))",

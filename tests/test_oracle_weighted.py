@@ -150,6 +150,40 @@ def test_det_threshold_bounds_clean_residuals(orc, m, n, k, br, bc, fr, fc, sign
     assert worst > 1e-4          # the bound is not vacuous
 
 
+@pytest.mark.parametrize("m,n,k,br,bc,fr,fc,positive", [
+    (64, 48, 200, 8, 4, 2, 2, False), (40, 60, 333, 1, 1, 3, 2, False), (96, 96, 64, 32, 32, 4, 4, False),
+    (64, 32, 4096, 8, 4, 2, 2, True),
+])
+def test_det_threshold_binary32_bounds_binary32_residuals(orc, m, n, k, br, bc, fr, fc, positive):
+    """Binary32 operands, checksum rows summed in binary64 and rounded once to
+    binary32, and the product accumulated in binary32 by an independent
+    routine (numpy's single-precision matrix product): no clean relation
+    exceeds the binary32 threshold (u_acc = u_st = 2^-24), the largest
+    residual is a sizeable part of it, and the binary64 threshold of the same
+    operands is exceeded.  Positive operands at k = 4096: the accumulation
+    errors of the binary32 products are many times the storage rounding of
+    the checksum rows, so only the product term covers them."""
+    worst, over64 = 0.0, False
+    for seed in range(3):
+        A = synth.uniform(seed, synth.STREAM_A, m, k, np.float32).astype(np.float64)
+        B = synth.uniform(seed, synth.STREAM_B, k, n, np.float32).astype(np.float64)
+        if positive:                                     # in [0.5, 1.5], rounded to binary32 operands
+            A = ((A + 2.0) / 2.0).astype(np.float32).astype(np.float64)
+            B = ((B + 2.0) / 2.0).astype(np.float32).astype(np.float64)
+        Wr = 0.5 + (synth.uniform(seed, synth.STREAM_X, fr, m // br) + 1) / 2
+        Wc = -1.0 + (synth.uniform(seed, synth.STREAM_PICK, fc, n // bc) + 1)
+        Af, Bf = wo.wencode(A, B, Wr, Wc, br, bc)
+        Af32, Bf32 = Af.astype(np.float32), Bf.astype(np.float32)
+        Cf = (Af32 @ Bf32).astype(np.float64)
+        tc, tr = wo.wtau_det(Af32, Bf32, m, n, br, bc, Wr, Wc, u_acc=wo.U32, u_st=wo.U32)
+        Dc, Dr = wo.residuals(Cf, m, n, br, bc, Wr, Wc)
+        assert np.all(np.abs(Dc) <= tc) and np.all(np.abs(Dr) <= tr)
+        worst = max(worst, (np.abs(Dc) / tc).max(), (np.abs(Dr) / tr).max())
+        t64c, t64r = wo.wtau_det(Af32, Bf32, m, n, br, bc, Wr, Wc)
+        over64 |= bool(np.any(np.abs(Dc) > t64c) or np.any(np.abs(Dr) > t64r))
+    assert worst > 2e-4 and over64, worst
+
+
 @pytest.mark.parametrize("wlo,whi", [(0.5, 1.5), (100.0, 1000.0)])
 def test_det_threshold_needs_its_summation_term(orc, wlo, whi):
     """Positive data and weights, k = 1, Gr = 2048 groups: the relation sums
