@@ -561,13 +561,15 @@ int abft_batch_thresholds(const abft_batch_plan *plan, int problem, double *tau_
  *   column relation (r, i, j): sum_g wr[r][g] C_f[g*br + i, j] = C_f[m + r*br + i, j]
  *   row relation (x, c, jj):   sum_h wc[c][h] C_f[x, h*bc + jj] = C_f[x, n + c*bc + jj]
  * The fr relations of one (i, j) form a column group, the fc relations of one
- * (x, jj) a row group.  Binary64 only; layouts as for abft_problem with these
- * sizes (A_f row-major, B_f column-major, C_f row-major, ldc >= N).
+ * (x, jj) a row group.  Binary64 or binary32 operands and C_f (every sum in
+ * binary64, a stored result rounded once to the element type); layouts as for
+ * abft_problem with these sizes (A_f row-major, B_f column-major, C_f
+ * row-major, ldc >= N); k, lda and ldb multiples of 16 bytes' elements.
  */
 #define ABFT_WMAX 4
 
 typedef struct {
-    abft_problem p;    /* dtype ABFT_F64, tau_mode ABFT_TAU_DET or ABFT_TAU_EXACT;
+    abft_problem p;    /* dtype ABFT_F64 or ABFT_F32, tau_mode ABFT_TAU_DET or ABFT_TAU_EXACT;
                           br, bc are the block height and width */
     int32_t fr, fc;    /* checksum block rows / columns, 1 .. ABFT_WMAX */
     const double *wr;  /* host, fr x (m/br) row-major: wr[r*(m/br) + g] (finite) */
@@ -598,16 +600,19 @@ size_t abft_wworkspace_size(const abft_wproblem *p);
 /* Copy the weights into ws (a blocking copy; once per problem and weight set). */
 int abft_wsetup(const abft_wproblem *p, void *ws, size_t ws_bytes);
 /* Checksum rows Y_r of A_f and columns Z_c of B_f (binary64 weighted sums over
- * the blocks in increasing order, one rounding per step), then the threshold
- * statistics: ||A_f[x, :]||_2, ||B_f[:, j]||_2 and
- * S_r[i] = sum_g |wr[r][g]| ||A_f[g*br + i, :]||_2 (and its column analogue).
- * ABFT_TAU_DET: tau of column relation (r, i, j) = kappa (2 gamma_k +
+ * the blocks in increasing order, one rounding per step; binary32 problems
+ * store them rounded once to binary32), then the threshold statistics:
+ * ||A_f[x, :]||_2, ||B_f[:, j]||_2 and S_r[i] = sum_g |wr[r][g]|
+ * ||A_f[g*br + i, :]||_2 (and its column analogue).  ABFT_TAU_DET: tau of
+ * column relation (r, i, j) = kappa (2 gamma_k(u_acc) + u_st +
  * 3 gamma_{Gr+1}) S_r[i] ||B_f[:, j]||_2, a rigorous bound on the rounding of
- * the product, the checksums and the relation sum; rows alike with Gc. */
+ * the product (accumulated with unit roundoff u_acc: 2^-53, binary32 2^-24),
+ * the stored checksum rows (u_st: 0, binary32 2^-24) and the binary64
+ * relation sum; rows alike with Gc. */
 int abft_wencode(const abft_wproblem *p, void *A_f, void *B_f, void *ws, size_t ws_bytes, void *stream);
-/* C_f = A_f B_f, all M x N entries (binary64): on the matrix cores, or for
- * N <= 8 (the matrix-vector product: n = 1, bc = 1, fc = 1) by a streaming
- * kernel that reads A_f once.  A protected matrix-vector product y = A x is
+/* C_f = A_f B_f, all M x N entries: on the matrix cores (accumulated in the
+ * element type), or for N <= 8 (the matrix-vector product: n = 1, bc = 1,
+ * fc = 1) by a streaming kernel that reads A_f once (binary64 accumulation).  A protected matrix-vector product y = A x is
  * the problem with n = 1: B_f = [x, wc x], C_f = [y_f, wc y_f] with y_f the
  * encoded result; every weighted relation, location and recovery applies. */
 int abft_wgemm(const abft_wproblem *p, const void *A_f, const void *B_f, void *C_f, void *stream);

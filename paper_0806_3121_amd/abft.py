@@ -573,15 +573,17 @@ class Batch:
 
 
 # ---------------------------------------------------------------- weighted f-checksums (Sec. 2.1)
-def wproblem(m, n, k, br, bc, wr, wc, lda=None, ldb=None, ldc=None, tau_mode=ABFT_TAU_DET, kappa=0.0):
+def wproblem(m, n, k, br, bc, wr, wc, lda=None, ldb=None, ldc=None, tau_mode=ABFT_TAU_DET, kappa=0.0,
+             dtype=None):
     """wr (fr x m/br), wc (fc x n/bc): float64 numpy arrays kept alive by the
-    returned structure's `_keep` attribute (the library reads them on the host)."""
+    returned structure's `_keep` attribute (the library reads them on the host).
+    dtype: ABFT_F64 (default) or ABFT_F32."""
     import numpy as np
     wr = np.ascontiguousarray(wr, dtype=np.float64)
     wc = np.ascontiguousarray(wc, dtype=np.float64)
     fr, fc = wr.shape[0], wc.shape[0]
-    base = problem(ABFT_F64, m, n, k, br, bc, lda, ldb, ldc if ldc is not None else n + fc * bc,
-                   tau_mode=tau_mode, kappa=kappa)
+    base = problem(ABFT_F64 if dtype is None else dtype, m, n, k, br, bc, lda, ldb,
+                   ldc if ldc is not None else n + fc * bc, tau_mode=tau_mode, kappa=kappa)
     wp = abft_wproblem(base, fr, fc, wr.ctypes.data_as(C.POINTER(C.c_double)),
                        wc.ctypes.data_as(C.POINTER(C.c_double)))
     wp._keep = (wr, wc)
@@ -644,19 +646,23 @@ def wrecover(wp, C_f, direction, blocks, lo, length, ws, stream=None):
 
 
 class WProtected:
-    """Device buffers of one weighted-checksum product (binary64): A_f
-    ((m + fr br) x k), B_f^T ((n + fc bc) x k), C_f with rows padded to 16
-    bytes, the workspace (weights copied in) and a pinned report buffer."""
+    """Device buffers of one weighted-checksum product (binary64, or binary32
+    with dtype=ABFT_F32): A_f ((m + fr br) x k), B_f^T ((n + fc bc) x k), C_f
+    with rows padded to 16 bytes, the workspace (weights copied in) and a
+    pinned report buffer."""
 
-    def __init__(self, m, n, k, br, bc, wr, wc, device="cuda", tau_mode=ABFT_TAU_DET):
+    def __init__(self, m, n, k, br, bc, wr, wc, device="cuda", tau_mode=ABFT_TAU_DET, dtype=None):
         import torch
+        dtype = ABFT_F64 if dtype is None else dtype
+        tdt = torch.float64 if dtype == ABFT_F64 else torch.float32
+        per16 = 2 if dtype == ABFT_F64 else 4
         fr, fc = len(wr), len(wc)
         self.M, self.N = m + fr * br, n + fc * bc
-        self.ldc = (self.N + 1) // 2 * 2
-        self.p = wproblem(m, n, k, br, bc, wr, wc, ldc=self.ldc, tau_mode=tau_mode)
-        self.A = torch.zeros(self.M, k, dtype=torch.float64, device=device)
-        self.Bt = torch.zeros(self.N, k, dtype=torch.float64, device=device)
-        self.Cbuf = torch.zeros(self.M, self.ldc, dtype=torch.float64, device=device)
+        self.ldc = (self.N + per16 - 1) // per16 * per16
+        self.p = wproblem(m, n, k, br, bc, wr, wc, ldc=self.ldc, tau_mode=tau_mode, dtype=dtype)
+        self.A = torch.zeros(self.M, k, dtype=tdt, device=device)
+        self.Bt = torch.zeros(self.N, k, dtype=tdt, device=device)
+        self.Cbuf = torch.zeros(self.M, self.ldc, dtype=tdt, device=device)
         self.C = self.Cbuf[:, :self.N]
         self.ws = torch.zeros(wworkspace_size(self.p), dtype=torch.uint8, device=device)
         wsetup(self.p, self.ws)

@@ -232,6 +232,12 @@ int launch_gemm_f64(const double *A, int64_t lda, const double *Bt, int64_t ldb,
 // streams A once, binary64 accumulation.  Same layouts as launch_gemm_f64.
 int launch_skinny_f64(const double *A, int64_t lda, const double *Bt, int64_t ldb, double *C, int64_t ldc,
                       int64_t M, int64_t N, int64_t K, hipStream_t s);
+// The same in binary32: the matrix-core product accumulates in binary32; the
+// skinny product accumulates in binary64 and rounds each entry once.
+int launch_gemm_f32(const float *A, int64_t lda, const float *Bt, int64_t ldb, float *C, int64_t ldc, int64_t M,
+                    int64_t N, int64_t K, hipStream_t s);
+int launch_skinny_f32(const float *A, int64_t lda, const float *Bt, int64_t ldb, float *C, int64_t ldc,
+                      int64_t M, int64_t N, int64_t K, hipStream_t s);
 int launch_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, int64_t k0, int64_t k1,
                       uint32_t flags, hipStream_t s);
 int describe_gemm(const abft_problem *p, uint32_t flags, char *buf, size_t len);

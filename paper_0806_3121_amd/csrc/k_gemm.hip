@@ -209,6 +209,22 @@ int launch_gemm_f64(const double *A, int64_t lda, const double *Bt, int64_t ldb,
     return ABFT_OK;
 }
 
+int launch_skinny_f32(const float *A, int64_t lda, const float *Bt, int64_t ldb, float *C, int64_t ldc,
+                      int64_t M, int64_t N, int64_t K, hipStream_t s) {
+    int st = sliver<float, float, float>(A, lda, M, Bt, ldb, N, K, C, ldc, 1, nullptr, s);
+    if (st) return st;
+    ABFT_LAUNCHED();
+    return ABFT_OK;
+}
+
+int launch_gemm_f32(const float *A, int64_t lda, const float *Bt, int64_t ldb, float *C, int64_t ldc, int64_t M,
+                    int64_t N, int64_t K, hipStream_t s) {
+    int st = gemm_main(A, lda, Bt, ldb, C, ldc, M, N, K, s);
+    if (st) return st;
+    ABFT_LAUNCHED();
+    return ABFT_OK;
+}
+
 int launch_gemm_panel(const abft_problem *p, const void *A_f, const void *B_f, void *C_f, int64_t k0, int64_t k1,
                       uint32_t flags, hipStream_t s) {
     Geom g = geom_of(p);

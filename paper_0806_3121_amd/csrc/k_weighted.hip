@@ -20,6 +20,8 @@ constexpr int64_t kSkinnyN = 8;    // products with at most this many columns st
 struct WGeom {
     int64_t m, n, k, br, bc, Gr, Gc, M, N, lda, ldb, ldc;
     int fr, fc;
+    int dtype;        // ABFT_F64 or ABFT_F32
+    int64_t V;        // elements per 16-byte load: 2, 4
 };
 
 WGeom wgeom(const abft_wproblem *p) {
@@ -29,6 +31,8 @@ WGeom wgeom(const abft_wproblem *p) {
     g.Gr = g.m / g.br; g.Gc = g.n / g.bc;
     g.M = g.m + g.fr * g.br; g.N = g.n + g.fc * g.bc;
     g.lda = p->p.lda; g.ldb = p->p.ldb; g.ldc = p->p.ldc;
+    g.dtype = p->p.dtype;
+    g.V = g.dtype == ABFT_F64 ? 2 : 4;
     return g;
 }
 
@@ -55,7 +59,7 @@ WLayout wlayout(const WGeom &g) {
     L.nb = take(sizeof(double) * g.N);
     L.s1 = take(sizeof(double) * g.fr * g.br);
     L.s2 = take(sizeof(double) * g.fc * g.bc);
-    int64_t kv = g.k / 2;
+    int64_t kv = g.k / g.V;
     size_t pa = 0;
     int64_t P = parts(g.Gr, g.br * kv);
     if (P > 1) pa = std::max(pa, (size_t)(P * g.fr * g.br * g.k));
@@ -131,65 +135,84 @@ __device__ inline double group(abft_wreport *rep, bool col, int64_t a, int64_t b
 }
 
 // ------------------------------------------------------------------ encoding
+// Elements are binary64 or binary32 (T); every sum is taken in binary64 and a
+// stored result is rounded once to T.  V = elements per 16-byte load.
+template <typename T> __device__ inline double ld(const T *p) { return (double)*p; }
+
 // Checksum rows out[r*b + i, l] = sum_g W[r][g] X[g*b + i, l] for the blocks
-// [g0, g1); X has rows of k binary64 (16-byte aligned, k even).
-template <int F>
-__global__ __launch_bounds__(kT) void k_wenc(const double *__restrict__ X, int64_t ld, int64_t b, int64_t G,
-                                             int64_t k, const double *__restrict__ W, int64_t P, int64_t chunk,
-                                             double *__restrict__ out, int64_t ldo, int64_t rstride) {
-    const int64_t kv = k / 2, total = P * b * kv;
+// [g0, g1); X has rows of k elements (16-byte aligned, k a multiple of V).
+// P == 1: outT is the checksum rows (row r*b + i, leading dimension ldo),
+// rounded to T; P > 1: part is the binary64 partial buffer, partition p at
+// p*rstride.
+template <int F, typename T>
+__global__ __launch_bounds__(kT) void k_wenc(const T *__restrict__ X, int64_t ld_, int64_t b, int64_t G, int64_t k,
+                                             const double *__restrict__ W, int64_t P, int64_t chunk,
+                                             T *__restrict__ outT, double *__restrict__ part, int64_t ldo,
+                                             int64_t rstride) {
+    constexpr int V = vec16<T>::N;
+    const int64_t kv = k / V, total = P * b * kv;
     for (int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x; t < total; t += (int64_t)gridDim.x * kT) {
         const int64_t p = t / (b * kv), q = t - p * (b * kv);
-        const int64_t i = q / kv, l = (q - i * kv) * 2;
+        const int64_t i = q / kv, l = (q - i * kv) * V;
         const int64_t g0 = p * chunk, g1 = min(G, g0 + chunk);
-        double s[F][2];
+        double s[F][V];
 #pragma unroll
-        for (int r = 0; r < F; ++r) s[r][0] = s[r][1] = 0.0;
+        for (int r = 0; r < F; ++r)
+#pragma unroll
+            for (int e = 0; e < V; ++e) s[r][e] = 0.0;
         for (int64_t g = g0; g < g1; ++g) {
-            double v[2];
-            vec16<double>::load(X + (g * b + i) * ld + l, v);
+            double v[V];
+            vec16<T>::load(X + (g * b + i) * ld_ + l, v);
 #pragma unroll
             for (int r = 0; r < F; ++r) {
                 const double w = W[r * G + g];
-                s[r][0] += w * v[0];
-                s[r][1] += w * v[1];
+#pragma unroll
+                for (int e = 0; e < V; ++e) s[r][e] += w * v[e];
             }
         }
-        // P == 1: out is the checksum rows (row r*b + i, leading dimension ldo);
-        // P > 1: out is the partial buffer, partition p at p*rstride
-        double *o = out + p * rstride;
+        if (P == 1) {
 #pragma unroll
-        for (int r = 0; r < F; ++r) {
-            o[(r * b + i) * ldo + l] = s[r][0];
-            o[(r * b + i) * ldo + l + 1] = s[r][1];
+            for (int r = 0; r < F; ++r)
+#pragma unroll
+                for (int e = 0; e < V; ++e) outT[(r * b + i) * ldo + l + e] = (T)s[r][e];
+        } else {
+            double *o = part + p * rstride;
+#pragma unroll
+            for (int r = 0; r < F; ++r)
+#pragma unroll
+                for (int e = 0; e < V; ++e) o[(r * b + i) * k + l + e] = s[r][e];
         }
     }
 }
 
-// Sum the partitions in order: out[e] = sum_p part[p*rows*k + e], e over rows x k.
+// Sum the partitions in order: out[e] = sum_p part[p*rows*k + e], e over rows x k, rounded once to T.
+template <typename T>
 __global__ __launch_bounds__(kT) void k_wpart_sum(const double *__restrict__ part, int64_t P, int64_t rows, int64_t k,
-                                                  double *__restrict__ out, int64_t ldo) {
+                                                  T *__restrict__ out, int64_t ldo) {
     const int64_t total = rows * k;
     for (int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x; t < total; t += (int64_t)gridDim.x * kT) {
         double s = 0.0;
         for (int64_t p = 0; p < P; ++p) s += part[p * total + t];
         const int64_t x = t / k, l = t - x * k;
-        out[x * ldo + l] = s;
+        out[x * ldo + l] = (T)s;
     }
 }
 
 // ||X[x, :]||_2 for each of rows rows: one wave per row, binary64.
-__global__ __launch_bounds__(kT) void k_wnorm(const double *__restrict__ X, int64_t ld, int64_t rows, int64_t k,
+template <typename T>
+__global__ __launch_bounds__(kT) void k_wnorm(const T *__restrict__ X, int64_t ld_, int64_t rows, int64_t k,
                                               double *__restrict__ out) {
+    constexpr int V = vec16<T>::N;
     const int lane = threadIdx.x % kW;
     const int64_t w0 = ((int64_t)blockIdx.x * kT + threadIdx.x) / kW, nw = (int64_t)gridDim.x * kT / kW;
     for (int64_t x = w0; x < rows; x += nw) {
-        const double *row = X + x * ld;
+        const T *row = X + x * ld_;
         double s = 0.0;
-        for (int64_t l = 2 * lane; l < k; l += 2 * kW) {
-            double v[2];
-            vec16<double>::load(row + l, v);
-            s += v[0] * v[0] + v[1] * v[1];
+        for (int64_t l = V * lane; l < k; l += V * kW) {
+            double v[V];
+            vec16<T>::load(row + l, v);
+#pragma unroll
+            for (int e = 0; e < V; ++e) s += v[e] * v[e];
         }
         s = wsum(s);
         if (lane == 0) out[x] = sqrt(s);
@@ -225,69 +248,76 @@ __global__ void k_wreport_init(abft_wreport *rep) {
 }
 
 // Column group (i, j): s[r] = sum_g wr[r][g] C[g*br + i, j] (given), then the checksum entries.
-template <int F>
-__device__ inline void col_finish(const VArgs &a, const double *C, int64_t i, int64_t j, const double *s, double &ratio,
+template <int F, typename T>
+__device__ inline void col_finish(const VArgs &a, const T *C, int64_t i, int64_t j, const double *s, double &ratio,
                                   unsigned long long &excl) {
     if (col_rel_erased(a.er, i, j, a.br)) { excl++; return; }
     double d[F], t[F];
 #pragma unroll
     for (int r = 0; r < F; ++r) {
-        d[r] = s[r] - C[(a.m + r * a.br + i) * a.ldc + j];
+        d[r] = s[r] - ld(C + (a.m + r * a.br + i) * a.ldc + j);
         t[r] = a.cc * a.s1[r * a.br + i] * a.nb[j];
     }
     ratio = fmax(ratio, group<F>(a.rep, true, i, j, d, t));
 }
 
-// Direct: one thread per (i, column pair), all Gr blocks; the block loop is
-// unrolled so several rows are in flight.  vec: rows of C_f start on 16-byte
-// boundaries (C aligned, ldc even).
-template <int F>
-__global__ __launch_bounds__(kT) void k_wvcol(const double *__restrict__ C, VArgs a, int vec) {
-    const int64_t NP = (a.N + 1) / 2, total = a.br * NP;
+// Direct: one thread per (i, V consecutive columns), all Gr blocks; the block
+// loop is unrolled so several rows are in flight.  vec: rows of C_f start on
+// 16-byte boundaries (C aligned, ldc a multiple of V).
+template <int F, typename T>
+__global__ __launch_bounds__(kT) void k_wvcol(const T *__restrict__ C, VArgs a, int vec) {
+    constexpr int V = vec16<T>::N;
+    const int64_t NP = (a.N + V - 1) / V, total = a.br * NP;
     double ratio = 0.0;
     unsigned long long excl = 0;
     for (int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x; t < total; t += (int64_t)gridDim.x * kT) {
-        const int64_t i = t / NP, j = (t - i * NP) * 2;
-        const bool two = j + 1 < a.N;
-        double s[F][2];
+        const int64_t i = t / NP, j = (t - i * NP) * V;
+        const int cnt = (int)min((int64_t)V, a.N - j);
+        double s[F][V];
 #pragma unroll
-        for (int r = 0; r < F; ++r) s[r][0] = s[r][1] = 0.0;
-        const double *col = C + i * a.ldc + j;
-        if (two && vec) {
+        for (int r = 0; r < F; ++r)
+#pragma unroll
+            for (int e = 0; e < V; ++e) s[r][e] = 0.0;
+        const T *col = C + i * a.ldc + j;
+        if (cnt == V && vec) {
 #pragma unroll 4
             for (int64_t g = 0; g < a.Gr; ++g) {
-                double v[2];
-                vec16<double>::load(col + g * a.br * a.ldc, v);
+                double v[V];
+                vec16<T>::load(col + g * a.br * a.ldc, v);
 #pragma unroll
-                for (int r = 0; r < F; ++r) {
-                    s[r][0] += a.wr[r * a.Gr + g] * v[0];
-                    s[r][1] += a.wr[r * a.Gr + g] * v[1];
-                }
+                for (int r = 0; r < F; ++r)
+#pragma unroll
+                    for (int e = 0; e < V; ++e) s[r][e] += a.wr[r * a.Gr + g] * v[e];
             }
         } else {
 #pragma unroll 4
             for (int64_t g = 0; g < a.Gr; ++g) {
-                const double *e = col + g * a.br * a.ldc;
-                const double v0 = e[0], v1 = two ? e[1] : 0.0;
+                const T *e0 = col + g * a.br * a.ldc;
+                double v[V];
 #pragma unroll
-                for (int r = 0; r < F; ++r) {
-                    s[r][0] += a.wr[r * a.Gr + g] * v0;
-                    s[r][1] += a.wr[r * a.Gr + g] * v1;
-                }
+                for (int e = 0; e < V; ++e) v[e] = e < cnt ? ld(e0 + e) : 0.0;
+#pragma unroll
+                for (int r = 0; r < F; ++r)
+#pragma unroll
+                    for (int e = 0; e < V; ++e) s[r][e] += a.wr[r * a.Gr + g] * v[e];
             }
         }
-        double s0[F], s1[F];
 #pragma unroll
-        for (int r = 0; r < F; ++r) { s0[r] = s[r][0]; s1[r] = s[r][1]; }
-        col_finish<F>(a, C, i, j, s0, ratio, excl);
-        if (two) col_finish<F>(a, C, i, j + 1, s1, ratio, excl);
+        for (int e = 0; e < V; ++e) {
+            if (e < cnt) {
+                double se[F];
+#pragma unroll
+                for (int r = 0; r < F; ++r) se[r] = s[r][e];
+                col_finish<F, T>(a, C, i, j + e, se, ratio, excl);
+            }
+        }
     }
     fold_block(ratio, excl, &a.rep->max_ratio_c, &a.rep->n_excl_c);
 }
 
 // Partitioned: partial sums of a run of blocks per (p, i, j), then the finish.
-template <int F>
-__global__ __launch_bounds__(kT) void k_wvcol_part(const double *__restrict__ C, VArgs a, int64_t P, int64_t chunk,
+template <int F, typename T>
+__global__ __launch_bounds__(kT) void k_wvcol_part(const T *__restrict__ C, VArgs a, int64_t P, int64_t chunk,
                                                    double *__restrict__ part) {
     const int64_t rel = a.br * a.N, total = P * rel;
     for (int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x; t < total; t += (int64_t)gridDim.x * kT) {
@@ -298,7 +328,7 @@ __global__ __launch_bounds__(kT) void k_wvcol_part(const double *__restrict__ C,
 #pragma unroll
         for (int r = 0; r < F; ++r) s[r] = 0.0;
         for (int64_t g = g0; g < g1; ++g) {
-            const double v = C[(g * a.br + i) * a.ldc + j];
+            const double v = ld(C + (g * a.br + i) * a.ldc + j);
 #pragma unroll
             for (int r = 0; r < F; ++r) s[r] += a.wr[r * a.Gr + g] * v;
         }
@@ -306,8 +336,8 @@ __global__ __launch_bounds__(kT) void k_wvcol_part(const double *__restrict__ C,
         for (int r = 0; r < F; ++r) part[(p * F + r) * rel + q] = s[r];
     }
 }
-template <int F>
-__global__ __launch_bounds__(kT) void k_wvcol_fin(const double *__restrict__ C, VArgs a, int64_t P,
+template <int F, typename T>
+__global__ __launch_bounds__(kT) void k_wvcol_fin(const T *__restrict__ C, VArgs a, int64_t P,
                                                   const double *__restrict__ part) {
     const int64_t rel = a.br * a.N;
     double ratio = 0.0;
@@ -320,65 +350,70 @@ __global__ __launch_bounds__(kT) void k_wvcol_fin(const double *__restrict__ C, 
             s[r] = 0.0;
             for (int64_t p = 0; p < P; ++p) s[r] += part[(p * F + r) * rel + t];
         }
-        col_finish<F>(a, C, i, j, s, ratio, excl);
+        col_finish<F, T>(a, C, i, j, s, ratio, excl);
     }
     fold_block(ratio, excl, &a.rep->max_ratio_c, &a.rep->n_excl_c);
 }
 
-template <int F>
-__device__ inline void row_finish(const VArgs &a, const double *C, int64_t x, int64_t jj, const double *s,
+template <int F, typename T>
+__device__ inline void row_finish(const VArgs &a, const T *C, int64_t x, int64_t jj, const double *s,
                                   double &ratio, unsigned long long &excl) {
     if (row_rel_erased(a.er, x, jj, a.bc)) { excl++; return; }
     double d[F], t[F];
 #pragma unroll
     for (int c = 0; c < F; ++c) {
-        d[c] = s[c] - C[x * a.ldc + a.n + c * a.bc + jj];
+        d[c] = s[c] - ld(C + x * a.ldc + a.n + c * a.bc + jj);
         t[c] = a.cr * a.na[x] * a.s2[c * a.bc + jj];
     }
     ratio = fmax(ratio, group<F>(a.rep, false, x, jj, d, t));
 }
 
-// Row groups, wide blocks (bc >= 64, even): one thread per (x, residue pair),
-// consecutive pairs read consecutive columns; the block loop is unrolled.
-template <int F>
-__global__ __launch_bounds__(kT) void k_wvrow_thread(const double *__restrict__ C, VArgs a, int vec) {
-    const int64_t BP = a.bc / 2, total = a.M * BP;
+// Row groups, wide blocks (bc >= 64, a multiple of V): one thread per (x, V
+// consecutive residues), consecutive threads read consecutive columns; the
+// block loop is unrolled.
+template <int F, typename T>
+__global__ __launch_bounds__(kT) void k_wvrow_thread(const T *__restrict__ C, VArgs a, int vec) {
+    constexpr int V = vec16<T>::N;
+    const int64_t BP = a.bc / V, total = a.M * BP;
     double ratio = 0.0;
     unsigned long long excl = 0;
     for (int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x; t < total; t += (int64_t)gridDim.x * kT) {
-        const int64_t x = t / BP, jj = (t - x * BP) * 2;
-        const double *row = C + x * a.ldc + jj;
-        double s[F][2];
+        const int64_t x = t / BP, jj = (t - x * BP) * V;
+        const T *row = C + x * a.ldc + jj;
+        double s[F][V];
 #pragma unroll
-        for (int c = 0; c < F; ++c) s[c][0] = s[c][1] = 0.0;
+        for (int c = 0; c < F; ++c)
+#pragma unroll
+            for (int e = 0; e < V; ++e) s[c][e] = 0.0;
 #pragma unroll 4
         for (int64_t h = 0; h < a.Gc; ++h) {
-            double v[2];
+            double v[V];
             if (vec) {
-                vec16<double>::load(row + h * a.bc, v);
+                vec16<T>::load(row + h * a.bc, v);
             } else {
-                v[0] = row[h * a.bc];
-                v[1] = row[h * a.bc + 1];
+#pragma unroll
+                for (int e = 0; e < V; ++e) v[e] = ld(row + h * a.bc + e);
             }
 #pragma unroll
-            for (int c = 0; c < F; ++c) {
-                s[c][0] += a.wc[c * a.Gc + h] * v[0];
-                s[c][1] += a.wc[c * a.Gc + h] * v[1];
-            }
+            for (int c = 0; c < F; ++c)
+#pragma unroll
+                for (int e = 0; e < V; ++e) s[c][e] += a.wc[c * a.Gc + h] * v[e];
         }
-        double s0[F], s1[F];
 #pragma unroll
-        for (int c = 0; c < F; ++c) { s0[c] = s[c][0]; s1[c] = s[c][1]; }
-        row_finish<F>(a, C, x, jj, s0, ratio, excl);
-        row_finish<F>(a, C, x, jj + 1, s1, ratio, excl);
+        for (int e = 0; e < V; ++e) {
+            double se[F];
+#pragma unroll
+            for (int c = 0; c < F; ++c) se[c] = s[c][e];
+            row_finish<F, T>(a, C, x, jj + e, se, ratio, excl);
+        }
     }
     fold_block(ratio, excl, &a.rep->max_ratio_r, &a.rep->n_excl_r);
 }
 
-// Row groups, narrow blocks (bc < 64): one wave per (x, jj), the lanes split
-// the Gc blocks (lane l takes h = l, l + 64, ...), wave-tree sum.
-template <int F>
-__global__ __launch_bounds__(kT) void k_wvrow_wave(const double *__restrict__ C, VArgs a) {
+// Row groups, narrow blocks: one wave per (x, jj), the lanes split the Gc
+// blocks (lane l takes h = l, l + 64, ...), wave-tree sum.
+template <int F, typename T>
+__global__ __launch_bounds__(kT) void k_wvrow_wave(const T *__restrict__ C, VArgs a) {
     const int lane = threadIdx.x % kW;
     const int64_t total = a.M * a.bc;
     const int64_t w0 = ((int64_t)blockIdx.x * kT + threadIdx.x) / kW, nw = (int64_t)gridDim.x * kT / kW;
@@ -386,18 +421,18 @@ __global__ __launch_bounds__(kT) void k_wvrow_wave(const double *__restrict__ C,
     unsigned long long excl = 0;
     for (int64_t t = w0; t < total; t += nw) {
         const int64_t x = t / a.bc, jj = t - x * a.bc;
-        const double *row = C + x * a.ldc + jj;
+        const T *row = C + x * a.ldc + jj;
         double s[F];
 #pragma unroll
         for (int c = 0; c < F; ++c) s[c] = 0.0;
         for (int64_t h = lane; h < a.Gc; h += kW) {
-            const double v = row[h * a.bc];
+            const double v = ld(row + h * a.bc);
 #pragma unroll
             for (int c = 0; c < F; ++c) s[c] += a.wc[c * a.Gc + h] * v;
         }
 #pragma unroll
         for (int c = 0; c < F; ++c) s[c] = wsum(s[c]);
-        if (lane == 0) row_finish<F>(a, C, x, jj, s, ratio, excl);
+        if (lane == 0) row_finish<F, T>(a, C, x, jj, s, ratio, excl);
     }
     fold_block(ratio, excl, &a.rep->max_ratio_r, &a.rep->n_excl_r);
 }
@@ -409,6 +444,7 @@ __global__ __launch_bounds__(kT) void k_wvrow_wave(const double *__restrict__ C,
 // block r is member G + r, at base + r*b + i).  Lost data members U (nu of
 // them) are solved from the intact checksum relations R with the host's
 // inverse Wi of W[R][U]; then the lost checksum members Lc are recomputed.
+// Solved and recomputed values are binary64, rounded once when stored as T.
 struct RArgs {
     const double *W;          // f x G weights
     int64_t G, b, base, ldc, lo, len, i0, i1;
@@ -421,8 +457,8 @@ __device__ inline int64_t elem_at(const RArgs &a, int64_t pos, int64_t along) {
     return a.dir == ABFT_DIR_COL ? along * a.ldc + pos : pos * a.ldc + along;
 }
 
-template <int F>
-__global__ __launch_bounds__(kT) void k_wrecover(double *__restrict__ C, RArgs a) {
+template <int F, typename T>
+__global__ __launch_bounds__(kT) void k_wrecover(T *__restrict__ C, RArgs a) {
     const int64_t nres = a.i1 - a.i0, total = nres * a.len;
     for (int64_t t = (int64_t)blockIdx.x * kT + threadIdx.x; t < total; t += (int64_t)gridDim.x * kT) {
         // column direction: consecutive threads take consecutive columns; row direction: consecutive residues
@@ -436,7 +472,7 @@ __global__ __launch_bounds__(kT) void k_wrecover(double *__restrict__ C, RArgs a
             bool lost = false;
             for (int u = 0; u < a.nu; ++u) lost |= (a.U[u] == g);
             if (lost) continue;
-            const double v = C[elem_at(a, pos, g * a.b + i)];
+            const double v = ld(C + elem_at(a, pos, g * a.b + i));
 #pragma unroll
             for (int r = 0; r < F; ++r) S[r] += a.W[r * a.G + g] * v;
         }
@@ -446,7 +482,7 @@ __global__ __launch_bounds__(kT) void k_wrecover(double *__restrict__ C, RArgs a
                 double acc = 0.0;
 #pragma unroll
                 for (int r = 0; r < F; ++r) acc = (r == a.R[q]) ? S[r] : acc;
-                rhs[q] = C[elem_at(a, pos, a.base + a.R[q] * a.b + i)] - acc;
+                rhs[q] = ld(C + elem_at(a, pos, a.base + a.R[q] * a.b + i)) - acc;
             }
             for (int u = 0; u < a.nu; ++u) {
                 double v = 0.0;
@@ -454,16 +490,17 @@ __global__ __launch_bounds__(kT) void k_wrecover(double *__restrict__ C, RArgs a
                 x[u] = v;
             }
             for (int u = 0; u < a.nu; ++u) {
-                C[elem_at(a, pos, a.U[u] * a.b + i)] = x[u];
+                const T stored = (T)x[u];
+                C[elem_at(a, pos, a.U[u] * a.b + i)] = stored;
 #pragma unroll
-                for (int r = 0; r < F; ++r) S[r] += a.W[r * a.G + a.U[u]] * x[u];
+                for (int r = 0; r < F; ++r) S[r] += a.W[r * a.G + a.U[u]] * (double)stored;
             }
         }
         for (int q = 0; q < a.nl; ++q) {
             double acc = 0.0;
 #pragma unroll
             for (int r = 0; r < F; ++r) acc = (r == a.Lc[q]) ? S[r] : acc;
-            C[elem_at(a, pos, a.base + a.Lc[q] * a.b + i)] = acc;
+            C[elem_at(a, pos, a.base + a.Lc[q] * a.b + i)] = (T)acc;
         }
     }
 }
@@ -486,12 +523,13 @@ unsigned vgrid(int64_t work) { return std::min<unsigned>(grid(work), 2048); }
 int check_wproblem(const abft_wproblem *p) {
     if (!p) return ABFT_E_ARG;
     const abft_problem &q = p->p;
-    if (q.dtype != ABFT_F64) return ABFT_E_UNSUPPORTED;
+    if (q.dtype != ABFT_F64 && q.dtype != ABFT_F32) return ABFT_E_UNSUPPORTED;
     if (q.tau_mode != ABFT_TAU_DET && q.tau_mode != ABFT_TAU_EXACT) return ABFT_E_UNSUPPORTED;
     if (q.m < 1 || q.n < 1 || q.k < 1 || q.br < 1 || q.bc < 1) return ABFT_E_ARG;
     if (q.br > q.m || q.bc > q.n || q.m % q.br || q.n % q.bc) return ABFT_E_ARG;
     if (p->fr < 1 || p->fr > ABFT_WMAX || p->fc < 1 || p->fc > ABFT_WMAX) return ABFT_E_ARG;
-    if (q.k % 2 || q.lda < q.k || q.ldb < q.k || q.lda % 2 || q.ldb % 2) return ABFT_E_ARG;
+    const int64_t V = q.dtype == ABFT_F64 ? 2 : 4;     // elements per 16-byte load
+    if (q.k % V || q.lda < q.k || q.ldb < q.k || q.lda % V || q.ldb % V) return ABFT_E_ARG;
     if (q.ldc < q.n + p->fc * q.bc) return ABFT_E_ARG;
     if (!p->wr || !p->wc) return ABFT_E_ARG;
     const int64_t Gr = q.m / q.br, Gc = q.n / q.bc;
@@ -504,10 +542,7 @@ int check_wproblem(const abft_wproblem *p) {
 
 bool aligned16(const void *x) { return ((uintptr_t)x & 15u) == 0; }
 
-double gam(double n) {
-    const double u = std::ldexp(1.0, -53);
-    return n * u / (1.0 - n * u);
-}
+double gam(double n, double u = std::ldexp(1.0, -53)) { return n * u / (1.0 - n * u); }
 
 // Inverse of the s x s matrix A (row-major, s <= 4) by Gauss-Jordan with
 // partial pivoting; false if singular or its 1-norm condition number exceeds 1e12.
@@ -578,28 +613,35 @@ int recover_args(const abft_wproblem *p, const WGeom &g, const WLayout &L, char 
     return ABFT_OK;
 }
 
-int launch_recover(double *C, const RArgs &a, hipStream_t s) {
+template <typename T>
+int launch_recover(T *C, const RArgs &a, hipStream_t s) {
     const int64_t work = (a.i1 - a.i0) * a.len;
     if (work <= 0) return ABFT_OK;
-    WSWITCH(a.f, (k_wrecover<F><<<grid(work), kT, 0, s>>>(C, a)));
+    WSWITCH(a.f, (k_wrecover<F, T><<<grid(work), kT, 0, s>>>(C, a)));
     ABFT_LAUNCHED();
     return ABFT_OK;
 }
+int launch_recover_any(int dtype, void *C, const RArgs &a, hipStream_t s) {
+    return dtype == ABFT_F64 ? launch_recover((double *)C, a, s) : launch_recover((float *)C, a, s);
+}
 
 // Weighted checksum rows of one operand (rows of A_f, or rows of B_f^T):
-// out = X + G*b*ld, one pass (P == 1) or partial sums then their ordered sum.
-int encode_side(const double *X, int64_t ld, int64_t G, int64_t b, int64_t k, int f, const double *W, double *part,
+// out = X + G*b*ld, one pass (P == 1) or binary64 partial sums then their
+// ordered sum; stored rounded once to T.
+template <typename T>
+int encode_side(const T *X, int64_t ld_, int64_t G, int64_t b, int64_t k, int f, const double *W, double *part,
                 hipStream_t s) {
-    double *out = const_cast<double *>(X) + G * b * ld;
-    const int64_t kv = k / 2;
+    T *out = const_cast<T *>(X) + G * b * ld_;
+    const int64_t kv = k / vec16<T>::N;
     int64_t P = parts(G, b * kv);
     if (P == 1) {
-        WSWITCH(f, (k_wenc<F><<<grid(b * kv), kT, 0, s>>>(X, ld, b, G, k, W, 1, G, out, ld, 0)));
+        WSWITCH(f, (k_wenc<F, T><<<grid(b * kv), kT, 0, s>>>(X, ld_, b, G, k, W, 1, G, out, nullptr, ld_, 0)));
     } else {
         const int64_t chunk = (G + P - 1) / P;
         P = (G + chunk - 1) / chunk;
-        WSWITCH(f, (k_wenc<F><<<grid(P * b * kv), kT, 0, s>>>(X, ld, b, G, k, W, P, chunk, part, k, f * b * k)));
-        k_wpart_sum<<<grid(f * b * k), kT, 0, s>>>(part, P, f * b, k, out, ld);
+        WSWITCH(f, (k_wenc<F, T><<<grid(P * b * kv), kT, 0, s>>>(X, ld_, b, G, k, W, P, chunk, nullptr, part, ld_,
+                                                                  f * b * k)));
+        k_wpart_sum<T><<<grid(f * b * k), kT, 0, s>>>(part, P, f * b, k, out, ld_);
     }
     ABFT_LAUNCHED();
     return ABFT_OK;
@@ -686,12 +728,18 @@ int abft_wencode(const abft_wproblem *p, void *A_f, void *B_f, void *ws, size_t 
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
     double *part = (double *)(w + L.part);
-    if ((st = encode_side((const double *)A_f, g.lda, g.Gr, g.br, g.k, g.fr, (const double *)(w + L.wr), part, s)))
-        return st;
-    if ((st = encode_side((const double *)B_f, g.ldb, g.Gc, g.bc, g.k, g.fc, (const double *)(w + L.wc), part, s)))
-        return st;
-    k_wnorm<<<grid(g.M * kW), kT, 0, s>>>((const double *)A_f, g.lda, g.M, g.k, (double *)(w + L.na));
-    k_wnorm<<<grid(g.N * kW), kT, 0, s>>>((const double *)B_f, g.ldb, g.N, g.k, (double *)(w + L.nb));
+    const double *wr = (const double *)(w + L.wr), *wc = (const double *)(w + L.wc);
+    if (g.dtype == ABFT_F64) {
+        if ((st = encode_side((const double *)A_f, g.lda, g.Gr, g.br, g.k, g.fr, wr, part, s))) return st;
+        if ((st = encode_side((const double *)B_f, g.ldb, g.Gc, g.bc, g.k, g.fc, wc, part, s))) return st;
+        k_wnorm<double><<<grid(g.M * kW), kT, 0, s>>>((const double *)A_f, g.lda, g.M, g.k, (double *)(w + L.na));
+        k_wnorm<double><<<grid(g.N * kW), kT, 0, s>>>((const double *)B_f, g.ldb, g.N, g.k, (double *)(w + L.nb));
+    } else {
+        if ((st = encode_side((const float *)A_f, g.lda, g.Gr, g.br, g.k, g.fr, wr, part, s))) return st;
+        if ((st = encode_side((const float *)B_f, g.ldb, g.Gc, g.bc, g.k, g.fc, wc, part, s))) return st;
+        k_wnorm<float><<<grid(g.M * kW), kT, 0, s>>>((const float *)A_f, g.lda, g.M, g.k, (double *)(w + L.na));
+        k_wnorm<float><<<grid(g.N * kW), kT, 0, s>>>((const float *)B_f, g.ldb, g.N, g.k, (double *)(w + L.nb));
+    }
     k_wsumnorm<<<grid(g.fr * g.br), kT, 0, s>>>((const double *)(w + L.wr), g.fr, g.Gr, g.br,
                                                 (const double *)(w + L.na), (double *)(w + L.s1));
     k_wsumnorm<<<grid(g.fc * g.bc), kT, 0, s>>>((const double *)(w + L.wc), g.fc, g.Gc, g.bc,
@@ -703,23 +751,62 @@ int abft_wencode(const abft_wproblem *p, void *A_f, void *B_f, void *ws, size_t 
 int abft_wgemm(const abft_wproblem *p, const void *A_f, const void *B_f, void *C_f, void *stream) {
     int st = check_wproblem(p);
     if (st) return st;
-    if (!A_f || !B_f || !C_f || !aligned16(A_f) || !aligned16(B_f) || ((uintptr_t)C_f & 7u)) return ABFT_E_ARG;
     const WGeom g = wgeom(p);
+    if (!A_f || !B_f || !C_f || !aligned16(A_f) || !aligned16(B_f) || ((uintptr_t)C_f % (16 / g.V))) return ABFT_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
     // a few columns (the matrix-vector case n = 1): stream A_f once instead of tiling the matrix cores
+    if (g.dtype == ABFT_F32) {
+        if (g.N <= kSkinnyN)
+            return launch_skinny_f32((const float *)A_f, g.lda, (const float *)B_f, g.ldb, (float *)C_f, g.ldc, g.M,
+                                     g.N, g.k, s);
+        return launch_gemm_f32((const float *)A_f, g.lda, (const float *)B_f, g.ldb, (float *)C_f, g.ldc, g.M, g.N,
+                               g.k, s);
+    }
     if (g.N <= kSkinnyN)
         return launch_skinny_f64((const double *)A_f, g.lda, (const double *)B_f, g.ldb, (double *)C_f, g.ldc, g.M,
-                                 g.N, g.k, (hipStream_t)stream);
+                                 g.N, g.k, s);
     return launch_gemm_f64((const double *)A_f, g.lda, (const double *)B_f, g.ldb, (double *)C_f, g.ldc, g.M, g.N,
-                           g.k, (hipStream_t)stream);
+                           g.k, s);
 }
+
+}  // extern "C"
+
+namespace abft {
+namespace {
+// The verification kernels over C_f of element type T (16-byte loads when
+// every row of C_f starts on a 16-byte boundary).
+template <typename T>
+void launch_wverify(const WGeom &g, const WLayout &L, char *w, const T *C, const VArgs &a, int vec, hipStream_t s) {
+    constexpr int64_t V = vec16<T>::N;
+    int64_t P = parts(g.Gr, g.br * g.N);
+    if (P == 1) {
+        WSWITCH(g.fr, (k_wvcol<F, T><<<vgrid(g.br * ((g.N + V - 1) / V)), kT, 0, s>>>(C, a, vec)));
+    } else {
+        const int64_t chunk = (g.Gr + P - 1) / P;
+        P = (g.Gr + chunk - 1) / chunk;
+        double *part = (double *)(w + L.part);
+        WSWITCH(g.fr, (k_wvcol_part<F, T><<<grid(P * g.br * g.N), kT, 0, s>>>(C, a, P, chunk, part)));
+        WSWITCH(g.fr, (k_wvcol_fin<F, T><<<vgrid(g.br * g.N), kT, 0, s>>>(C, a, P, part)));
+    }
+    if (g.bc >= kW && g.bc % V == 0) {
+        WSWITCH(g.fc, (k_wvrow_thread<F, T><<<vgrid(g.M * (g.bc / V)), kT, 0, s>>>(C, a, vec)));
+    } else {
+        WSWITCH(g.fc, (k_wvrow_wave<F, T><<<vgrid(g.M * g.bc * kW), kT, 0, s>>>(C, a)));
+    }
+}
+}  // namespace
+}  // namespace abft
+
+extern "C" {
 
 int abft_wverify(const abft_wproblem *p, const void *C_f, const abft_rect *known, int n_known, void *ws,
                  size_t ws_bytes, abft_wreport *host_out, void *stream) {
     int st = check_wproblem(p);
     if (st) return st;
-    if (!C_f || ((uintptr_t)C_f & 7u)) return ABFT_E_ARG;
-    if ((st = check_wws(p, ws, ws_bytes))) return st;
     const WGeom g = wgeom(p);
+    const int64_t es = 16 / g.V;                       // element bytes
+    if (!C_f || ((uintptr_t)C_f % es)) return ABFT_E_ARG;
+    if ((st = check_wws(p, ws, ws_bytes))) return st;
     const WLayout L = wlayout(g);
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
@@ -730,32 +817,21 @@ int abft_wverify(const abft_wproblem *p, const void *C_f, const abft_rect *known
     a.s1 = (const double *)(w + L.s1); a.s2 = (const double *)(w + L.s2);
     a.m = g.m; a.n = g.n; a.br = g.br; a.bc = g.bc; a.Gr = g.Gr; a.Gc = g.Gc; a.M = g.M; a.N = g.N; a.ldc = g.ldc;
     if (p->p.tau_mode == ABFT_TAU_DET) {
+        // binary64: products accumulated in binary64, checksum rows the binary64 sums; binary32: products
+        // accumulated in binary32 (u_acc = 2^-24) and checksum rows rounded once to binary32 (u_st = 2^-24)
         const double kappa = p->p.kappa >= 1.0 ? p->p.kappa : 1.0 + std::ldexp(1.0, -20);
-        a.cc = kappa * (2 * gam((double)g.k) + 3 * gam((double)(g.Gr + 1)));
-        a.cr = kappa * (2 * gam((double)g.k) + 3 * gam((double)(g.Gc + 1)));
+        const double u_acc = std::ldexp(1.0, g.dtype == ABFT_F64 ? -53 : -24);
+        const double u_st = g.dtype == ABFT_F64 ? 0.0 : std::ldexp(1.0, -24);
+        a.cc = kappa * (2 * gam((double)g.k, u_acc) + u_st + 3 * gam((double)(g.Gr + 1)));
+        a.cr = kappa * (2 * gam((double)g.k, u_acc) + u_st + 3 * gam((double)(g.Gc + 1)));
     } else {
         a.cc = a.cr = 0.0;
     }
     a.rep = (abft_wreport *)(w + L.report);
-    const double *C = (const double *)C_f;
     k_wreport_init<<<1, kW, 0, s>>>(a.rep);
-    // 16-byte loads when every row of C_f starts on a 16-byte boundary
-    const int vec = ((uintptr_t)C_f % 16 == 0) && (g.ldc % 2 == 0);
-    int64_t P = parts(g.Gr, g.br * g.N);
-    if (P == 1) {
-        WSWITCH(g.fr, (k_wvcol<F><<<vgrid(g.br * ((g.N + 1) / 2)), kT, 0, s>>>(C, a, vec)));
-    } else {
-        const int64_t chunk = (g.Gr + P - 1) / P;
-        P = (g.Gr + chunk - 1) / chunk;
-        double *part = (double *)(w + L.part);
-        WSWITCH(g.fr, (k_wvcol_part<F><<<grid(P * g.br * g.N), kT, 0, s>>>(C, a, P, chunk, part)));
-        WSWITCH(g.fr, (k_wvcol_fin<F><<<vgrid(g.br * g.N), kT, 0, s>>>(C, a, P, part)));
-    }
-    if (g.bc >= kW && g.bc % 2 == 0) {
-        WSWITCH(g.fc, (k_wvrow_thread<F><<<vgrid(g.M * (g.bc / 2)), kT, 0, s>>>(C, a, vec)));
-    } else {
-        WSWITCH(g.fc, (k_wvrow_wave<F><<<vgrid(g.M * g.bc * kW), kT, 0, s>>>(C, a)));
-    }
+    const int vec = ((uintptr_t)C_f % 16 == 0) && (g.ldc % g.V == 0);
+    if (g.dtype == ABFT_F64) launch_wverify(g, L, w, (const double *)C_f, a, vec, s);
+    else launch_wverify(g, L, w, (const float *)C_f, a, vec, s);
     ABFT_LAUNCHED();
     if (host_out) ABFT_HIP(hipMemcpyAsync(host_out, a.rep, sizeof(abft_wreport), hipMemcpyDeviceToHost, s));
     return ABFT_OK;
@@ -839,7 +915,7 @@ int abft_wcorrect(const abft_wproblem *p, void *C_f, const abft_location *locs, 
         a.len = 1;
         a.i0 = along % b;
         a.i1 = a.i0 + 1;
-        if ((st = launch_recover((double *)C_f, a, (hipStream_t)stream))) return st;
+        if ((st = launch_recover_any(g.dtype, C_f, a, (hipStream_t)stream))) return st;
     }
     return ABFT_OK;
 }
@@ -867,7 +943,7 @@ int abft_wrecover(const abft_wproblem *p, void *C_f, int dir, const int32_t *blo
     a.len = len;
     a.i0 = 0;
     a.i1 = dir == ABFT_DIR_COL ? g.br : g.bc;
-    return launch_recover((double *)C_f, a, (hipStream_t)stream);
+    return launch_recover_any(g.dtype, C_f, a, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -321,8 +321,10 @@ def _wp(**kw):
 def test_weighted_bad_problems_rejected_before_launch():
     fake = C.c_void_p(256)
     assert abft.wworkspace_size(_wp()) > 0
+    assert abft.wworkspace_size(_wp(dtype=abft.ABFT_F32)) > 0
     bad = [
         (_wp(wr=np.ones((5, 4))), abft.ABFT_E_ARG),                   # fr > ABFT_WMAX
+        (_wp(dtype=abft.ABFT_F32, k=126), abft.ABFT_E_ARG),          # binary32 rows: k a multiple of 4
         (_wp(wr=np.array([[1.0, np.nan, 1.0, 1.0]])), abft.ABFT_E_ARG),  # weights must be finite
         (_wp(k=127), abft.ABFT_E_ARG),                               # k odd: rows not 16-byte multiples
         (_wp(ldc=200), abft.ABFT_E_ARG),                             # ldc < n + fc*bc
