@@ -226,8 +226,8 @@ int abft_encode(const abft_problem *p, void *A_f, void *B_f, void *ws, size_t ws
  * are), and the inherited threshold term.  The previous column relations hold
  * only up to their residual, at most tau_prev(r, l); through the product it
  * adds at most sum_l tau_prev(r, l) |B_f[l, j]| to relation (r, j), which the
- * det threshold of p then includes.  Requirements: both problems ABFT_F64 with
- * the same tau mode (ABFT_TAU_DET or ABFT_TAU_EXACT); p->m = prev->m,
+ * det threshold of p then includes.  Requirements: both problems ABFT_F64, or
+ * both ABFT_F32, with the same tau mode (ABFT_TAU_DET or ABFT_TAU_EXACT); p->m = prev->m,
  * p->br = prev->br, p->k = prev->n, p->lda = prev->ldc (A_f is the previous
  * C_f, unchanged); ws_prev is the previous product's workspace after its
  * abft_encode (read during this call only).

@@ -182,16 +182,17 @@ def tau_det(Af, Bf, m, n, br, bc, u_acc=U64, u_st=0.0, kappa=1.0 + 2.0 ** -20):
     return tc, tr
 
 
-def tau_det_chained(Af, Bf, m, n, br, bc, tau_c_prev, kappa=1.0 + 2.0 ** -20):
+def tau_det_chained(Af, Bf, m, n, br, bc, tau_c_prev, kappa=1.0 + 2.0 ** -20, u_acc=U64, u_st=0.0):
     """Thresholds of a chained product D_f = A_f B_f whose A_f is a previous
     product's C_f (its data columns), the carried rows used as A's checksum
     rows without recomputation (Sec. 3.2, chained calls).  Every previous
     column relation (r, l) holds up to its residual, at most tau_c_prev[r, l];
     through the product these add sum_l tau_c_prev[r, l] |B_f[l, j]| to the
-    column relation (r, j) of D_f.  Row relations are those of a plain product."""
+    column relation (r, j) of D_f.  Row relations are those of a plain product
+    (u_acc, u_st: its roundoffs, as for tau_det)."""
     Bf = _f64(Bf)
     k = Bf.shape[0]
-    tc, tr = tau_det(Af, Bf, m, n, br, bc, kappa=kappa)
+    tc, tr = tau_det(Af, Bf, m, n, br, bc, u_acc=u_acc, u_st=u_st, kappa=kappa)
     return tc + _f64(tau_c_prev)[:, :k] @ np.abs(Bf), tr
 
 

@@ -79,7 +79,7 @@ WsLayout ws_layout(const abft_problem *p) {
     L.fused_tag = take(sizeof(uint64_t));
     L.chain_a = take(sizeof(double) * g.br);
     L.chain_w = take(sizeof(double) * g.N);
-    L.chain_cs = take(p->dtype == ABFT_F64 ? sizeof(double) * g.br * g.k : 8);
+    L.chain_cs = take(p->dtype == ABFT_F64 || p->dtype == ABFT_F32 ? dtype_size(p->dtype) * g.br * g.k : 8);
     L.total = off;
     return L;
 }
@@ -306,7 +306,7 @@ int abft_encode_chained(const abft_problem *p, const void *A_f, void *B_f, void 
     int st = check_problem(p);
     if (st) return st;
     if ((st = check_problem(prev))) return st;
-    if (p->dtype != ABFT_F64 || prev->dtype != ABFT_F64) return ABFT_E_UNSUPPORTED;
+    if ((p->dtype != ABFT_F64 && p->dtype != ABFT_F32) || prev->dtype != p->dtype) return ABFT_E_UNSUPPORTED;
     if (p->tau_mode != prev->tau_mode) return ABFT_E_ARG;
     if (p->tau_mode != ABFT_TAU_DET && p->tau_mode != ABFT_TAU_EXACT) return ABFT_E_UNSUPPORTED;
     if (p->m != prev->m || p->br != prev->br || p->k != prev->n || p->lda != prev->ldc) return ABFT_E_ARG;

@@ -191,8 +191,8 @@ struct WsLayout {
     size_t scale;                    // FP8 per-tensor scale exponents and amax scratch (4 x int32)
     size_t partial;                  // two-level reduction partials (double)
     size_t fused_c, fused_r;         // product-epilogue partial sums for b = 1 (double)
-    size_t chain_a, chain_w;         // chained products (binary64): inherited threshold term chain_a[r] chain_w[j]
-    size_t chain_cs;                 // chained products: the recomputed checksum rows (discarded; br x k double)
+    size_t chain_a, chain_w;         // chained products: inherited threshold term chain_a[r] chain_w[j]
+    size_t chain_cs;                 // chained products: the recomputed checksum rows (discarded; br x k elements)
     size_t rowpart;                  // fused row statistics: per-row partial sums
     size_t vpart_c, vpart_r;         // one-pass re-read verification for b = 1: tile partial sums (double)
     size_t fused_tag;                // owner of the fused partials: fused_key() of the last fused product, else 0

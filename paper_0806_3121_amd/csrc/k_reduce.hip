@@ -472,8 +472,8 @@ static int encode_typed(const abft_problem *p, SrcA srcA, SrcB srcB, T *A, T *Bt
     return ABFT_OK;
 }
 
-// Chained product (the result of a product fed to the next one, F64, det or
-// exact): A_f is the previous C_f, whose carried rows are used as they are.
+// Chained product (the result of a product fed to the next one, F64 or F32,
+// det or exact): A_f is the previous C_f, whose carried rows are used as they are.
 // Its checksum rows are recomputed only into scratch, for the group statistic;
 // the row statistics are taken over the rows that enter the product (the
 // carried ones).  B_f is encoded as usual.  The previous column relations hold
@@ -488,50 +488,58 @@ __global__ __launch_bounds__(kThreads) void k_chain_a(const double *na_abs_prev,
 }
 
 // out[j] = sum_l w[l] |X[j, l]|: one wave per row, binary64.
-__global__ __launch_bounds__(kThreads) void k_row_absdot(const double *X, int64_t ld, int64_t rows, int64_t k,
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_row_absdot(const T *X, int64_t ld, int64_t rows, int64_t k,
                                                          const double *w, double *out) {
+    constexpr int V = vec16<T>::N;
     const int lane = threadIdx.x % kWave;
     const int64_t w0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) / kWave;
     const int64_t nw = (int64_t)gridDim.x * kThreads / kWave;
     for (int64_t j = w0; j < rows; j += nw) {
-        const double *row = X + j * ld;
+        const T *row = X + j * ld;
         double acc = 0.0;
-        for (int64_t l = 2 * lane; l < k; l += 2 * kWave) {
-            double v[2];
-            vec16<double>::load(row + l, v);
-            acc += w[l] * fabs(v[0]) + w[l + 1] * fabs(v[1]);
+        for (int64_t l = V * lane; l < k; l += V * kWave) {
+            double v[V];
+            vec16<T>::load(row + l, v);
+#pragma unroll
+            for (int e = 0; e < V; ++e) acc += w[l + e] * fabs(v[e]);
         }
         for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
         if (lane == 0) out[j] = acc;
     }
 }
 
-int launch_encode_chained(const abft_problem *p, const void *A_f, void *B_f, char *ws, const abft_problem *prev,
-                          const char *ws_prev, double cc_prev, hipStream_t s) {
+template <typename T>
+static int encode_chained_typed(const abft_problem *p, const T *A, T *Bt, char *ws, const abft_problem *prev,
+                                const char *ws_prev, double cc_prev, hipStream_t s) {
     Geom g = geom_of(p);
     WsLayout L = ws_layout(p), Lp = ws_layout(prev);
-    const double *A = (const double *)A_f;
-    double *Bt = (double *)B_f;
     double *part = (double *)(ws + L.partial);
     double *grpA = (double *)(ws + L.grpA), *grpB = (double *)(ws + L.grpB);
-    double *cs = (double *)(ws + L.chain_cs);
+    T *cs = (T *)(ws + L.chain_cs);
     // the A side: group statistic (checksum rows into scratch), row norms of the rows that enter the product
-    encode_pass1<double, double>(SrcStored<double>{A, p->lda}, g.m, g.br, g.k, cs, g.k, false, grpA, part, s);
-    encode_pass2<double, double>(A, p->lda, g.m, A + g.m * p->lda, p->lda, g.br, g.k, false, g.bc, grpB,
-                                 (double *)(ws + L.na), s);
+    encode_pass1<T, T>(SrcStored<T>{A, p->lda}, g.m, g.br, g.k, cs, g.k, false, grpA, part, s);
+    encode_pass2<T, T>(A, p->lda, g.m, A + g.m * p->lda, p->lda, g.br, g.k, false, g.bc, grpB, (double *)(ws + L.na),
+                       s);
     // the B side as in a plain encode
-    encode_pass1<double, double>(SrcStored<double>{Bt, p->ldb}, g.n, g.bc, g.k, Bt + g.n * p->ldb, p->ldb, false, grpB,
-                                 part, s);
-    encode_pass2<double, double>(Bt, p->ldb, g.n, Bt + g.n * p->ldb, p->ldb, g.bc, g.k, false, g.br, grpA,
-                                 (double *)(ws + L.nb), s);
+    encode_pass1<T, T>(SrcStored<T>{Bt, p->ldb}, g.n, g.bc, g.k, Bt + g.n * p->ldb, p->ldb, false, grpB, part, s);
+    encode_pass2<T, T>(Bt, p->ldb, g.n, Bt + g.n * p->ldb, p->ldb, g.bc, g.k, false, g.br, grpA,
+                       (double *)(ws + L.nb), s);
     row_stats<double>(grpA, g.k, g.br, g.k, ROW_L2, nullptr, (double *)(ws + L.na_abs), s);
     row_stats<double>(grpB, g.k, g.bc, g.k, ROW_L2, nullptr, (double *)(ws + L.nb_abs), s);
     // the inherited term
     k_chain_a<<<1, kThreads, 0, s>>>((const double *)(ws_prev + Lp.na_abs), cc_prev, g.br, (double *)(ws + L.chain_a));
-    k_row_absdot<<<(unsigned)std::min<int64_t>((g.N + 3) / 4, 65536), kThreads, 0, s>>>(
+    k_row_absdot<T><<<(unsigned)std::min<int64_t>((g.N + 3) / 4, 65536), kThreads, 0, s>>>(
         Bt, p->ldb, g.N, g.k, (const double *)(ws_prev + Lp.nb), (double *)(ws + L.chain_w));
     ABFT_LAUNCHED();
     return ABFT_OK;
+}
+
+int launch_encode_chained(const abft_problem *p, const void *A_f, void *B_f, char *ws, const abft_problem *prev,
+                          const char *ws_prev, double cc_prev, hipStream_t s) {
+    if (p->dtype == ABFT_F32)
+        return encode_chained_typed(p, (const float *)A_f, (float *)B_f, ws, prev, ws_prev, cc_prev, s);
+    return encode_chained_typed(p, (const double *)A_f, (double *)B_f, ws, prev, ws_prev, cc_prev, s);
 }
 
 int launch_encode(const abft_problem *p, void *A_f, void *B_f, char *ws, hipStream_t s) {

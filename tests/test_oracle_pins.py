@@ -570,6 +570,32 @@ def test_chained_product_relations_exact_on_integers(orc, br, bc):
     assert rep.n_flag_c == 0 and rep.n_flag_r == 0
 
 
+def test_chained_threshold_binary32_bounds_single_precision_products(orc):
+    """Binary32 chain: checksum rows rounded to binary32, both products
+    accumulated in binary32 by an independent routine (numpy's single-precision
+    matrix product); the first product verifies clean under the binary32 det
+    thresholds, the chained one (the first C_f as its A_f, carried rows as they
+    are) under the binary32 chained thresholds."""
+    m, k1, n1, n2, b = 64, 96, 80, 48, 8
+    worst = 0.0
+    for seed in range(3):
+        A1 = synth.uniform(seed, synth.STREAM_A, m, k1, np.float32).astype(np.float64)
+        B1 = synth.uniform(seed, synth.STREAM_B, k1, n1, np.float32).astype(np.float64)
+        B2 = synth.uniform(seed + 7, synth.STREAM_B, n1, n2, np.float32).astype(np.float64)
+        Af1, Bf1 = orc.encode(A1, B1, b, b, store_f32=True)
+        C1f = (Af1.astype(np.float32) @ Bf1.astype(np.float32)).astype(np.float64)
+        tc1, tr1 = orc.tau_det(Af1, Bf1, m, n1, b, b, u_acc=orc.U32, u_st=orc.U32)
+        assert orc.verify(C1f, m, n1, b, b, tc1, tr1)[2].n_flag_c == 0
+        _, B2f = orc.encode(np.zeros((m, n1)), B2, b, b, store_f32=True)
+        Af2 = np.ascontiguousarray(C1f[:, :n1])
+        D = (Af2.astype(np.float32) @ B2f.astype(np.float32)).astype(np.float64)
+        tcc, trc = orc.tau_det_chained(Af2, B2f, m, n2, b, b, tc1, u_acc=orc.U32, u_st=orc.U32)
+        Dc, Dr, rep = orc.verify(D, m, n2, b, b, tcc, trc)
+        assert rep.n_flag_c == 0 and rep.n_flag_r == 0
+        worst = max(worst, (np.abs(Dc) / tcc).max(), (np.abs(Dr) / trc).max())
+    assert worst > 1e-4, worst
+
+
 def test_chained_threshold_bounds_and_needs_the_inherited_term(orc):
     """The chained det threshold bounds the residuals of D_f on random binary64
     data; and when the previous C_f's carried row is off by as much as its own
