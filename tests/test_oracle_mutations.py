@@ -113,6 +113,10 @@ MUTATIONS = [
     ("oracle.tau_det_chained: |B| dropped", PY, "return tc + _f64(tau_c_prev)[:, :k] @ np.abs(Bf), tr",
      "return tc + _f64(tau_c_prev)[:, :k] @ Bf, tr", pins.test_chained_threshold_bounds_and_needs_the_inherited_term,
      {}),
+    ("oracle.tau_det_chained: roundoffs not passed on", PY,
+     "tc, tr = tau_det(Af, Bf, m, n, br, bc, u_acc=u_acc, u_st=u_st, kappa=kappa)",
+     "tc, tr = tau_det(Af, Bf, m, n, br, bc, kappa=kappa)",
+     pins.test_chained_threshold_binary32_bounds_single_precision_products, {}),
     ("oracle.outer_update: one update skipped", PY, "for l in range(k0, k1):", "for l in range(k0 + 1, k1):",
      pins.test_outer_product_does_not_transpose_or_skip, {}),
     ("oracle.block_cyclic_owner: local index", PY, "return I % P, (I // P) * nb + ii",
