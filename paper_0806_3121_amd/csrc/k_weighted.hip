@@ -1,8 +1,9 @@
-// Weighted f-checksums (Sec. 2.1) on the block product (Sec. 2.2), binary64:
-// encoding, threshold statistics, verification of every column and row group,
-// location from the weight ratios of a group, and the f x f recovery of lost
-// blocks.  Every sum is accumulated in binary64 over the blocks in increasing
-// order.
+// Weighted f-checksums (Sec. 2.1) on the block product (Sec. 2.2), binary64 or
+// binary32 operands and C_f: encoding, threshold statistics, verification of
+// every column and row group, location from the weight ratios of a group, and
+// the f x f recovery of lost blocks.  Every sum is accumulated in binary64 over
+// the blocks in increasing order; a stored result is rounded once to the
+// element type.
 #include <algorithm>
 #include <cmath>
 #include <vector>
