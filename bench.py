@@ -356,7 +356,7 @@ def run_batched(args):
     log(f"tile shapes ({tile_source}, {args.tile_cache}): problems per shape {tile_counts}")
     # launch-level choice: each uniform shape and the per-problem shapes, timed whole
     abft.batch_quantize_encode(plan)
-    choice_ms, tile = abft.batch_choose(plan, reps=3)
+    choice_ms, tile = abft.batch_choose(plan, reps=5)
     choice_names = [f"{abft.BATCH_TILE_SHAPES[t][0]}x{abft.BATCH_TILE_SHAPES[t][1]}"
                     for t in range(abft.ABFT_BATCH_TILES)] + ["per-problem"]
     log(f"product by launch choice (ms): {dict(zip(choice_names, [round(x, 3) for x in choice_ms]))} -> "

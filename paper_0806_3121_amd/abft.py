@@ -513,25 +513,34 @@ class Batch:
     """Device buffers of a batch of bfloat16 protected products: per problem
     binary32 inputs A32 (m x k) and Bt32 (n x k), their bfloat16 copies A and
     Bt, and C_f with rows padded to 16 bytes; one batch workspace and a pinned
-    buffer for the reports.  shapes: list of (m, n, k, br, bc)."""
+    buffer for the reports.  shapes: list of (m, n, k, br, bc).  A32, Bt32, A
+    and Bt are (m, k) / (n, k) views of buffers with rows of lda = ldb
+    elements (lda[q]; k unless ld_align pads them)."""
 
-    def __init__(self, shapes, device="cuda", tau_mode=ABFT_TAU_STAT, lam=0.0, tiles=None, ldc_align=4):
+    def __init__(self, shapes, device="cuda", tau_mode=ABFT_TAU_STAT, lam=0.0, tiles=None, ldc_align=4,
+                 ld_align=1):
         """ldc_align: rows of C_f padded to a multiple of this many elements (4: 16-byte rows, the
-        vector forms of the product's store and of the verification; 1: no padding)."""
+        vector forms of the product's store and of the verification; 1: no padding).  ld_align: rows
+        of the operands padded to a multiple of this many elements (a multiple of 8; 64: every
+        bfloat16 row starts on a 128-byte line, so the quantizing pass writes whole lines)."""
         import torch
+        if ld_align < 1 or (ld_align > 1 and ld_align % 8):
+            raise ValueError("ld_align: 1 or a multiple of 8")
         self.shapes = list(shapes)
-        self.probs, self.items = [], []
+        self.probs, self.items, self.lda = [], [], []
         self.A32, self.Bt32, self.A, self.Bt, self.Cbuf, self.C = [], [], [], [], [], []
         for (m, n, k, br, bc) in self.shapes:
             N = n + bc
             ldc = (N + ldc_align - 1) // ldc_align * ldc_align
-            p = problem(ABFT_BF16, m, n, k, br, bc, ldc=ldc, tau_mode=tau_mode, lam=lam)
-            a32 = torch.zeros(m, k, dtype=torch.float32, device=device)
-            b32 = torch.zeros(n, k, dtype=torch.float32, device=device)
-            a = torch.zeros(m, k, dtype=torch.bfloat16, device=device)
-            b = torch.zeros(n, k, dtype=torch.bfloat16, device=device)
+            ld = (k + ld_align - 1) // ld_align * ld_align
+            p = problem(ABFT_BF16, m, n, k, br, bc, lda=ld, ldb=ld, ldc=ldc, tau_mode=tau_mode, lam=lam)
+            a32 = torch.zeros(m, ld, dtype=torch.float32, device=device)[:, :k]
+            b32 = torch.zeros(n, ld, dtype=torch.float32, device=device)[:, :k]
+            a = torch.zeros(m, ld, dtype=torch.bfloat16, device=device)[:, :k]
+            b = torch.zeros(n, ld, dtype=torch.bfloat16, device=device)[:, :k]
             cb = torch.zeros(m + br, ldc, dtype=torch.float32, device=device)
             self.probs.append(p)
+            self.lda.append(ld)
             self.items.append(abft_batch_item(a32.data_ptr(), b32.data_ptr(), a.data_ptr(), b.data_ptr(),
                                               cb.data_ptr()))
             self.A32.append(a32); self.Bt32.append(b32); self.A.append(a); self.Bt.append(b)

@@ -1536,33 +1536,38 @@ int batch_tune(const abft_batch_plan *pl, double *costs, int32_t *best, hipStrea
 // with the per-problem shapes of the plan; returns the fastest.  The
 // per-problem run is one launch per shape, each with its own tail, so the
 // fastest tiles per problem need not give the fastest run.
+// Candidates timed in rounds (each once per round, in turn) after a warm-up
+// round: the device clock still rises during the first launches of a run, and
+// timing one candidate after another would favour the later ones.
 int batch_choose(const abft_batch_plan *pl, int reps, double *ms, int32_t *choice, hipStream_t s) {
+    constexpr int kCand = ABFT_BATCH_MIXED + 1;
     hipEvent_t e0, e1;
     ABFT_HIP(hipEventCreate(&e0));
     ABFT_HIP(hipEventCreate(&e1));
-    double best = 0.0;
-    int arg = 0;
+    std::vector<float> ts[kCand];
     int st = ABFT_OK;
-    for (int c = 0; c <= ABFT_BATCH_MIXED && st == ABFT_OK; ++c) {
-        std::vector<float> ts;
-        for (int r = 0; r <= reps && st == ABFT_OK; ++r) {
+    for (int r = 0; r <= reps && st == ABFT_OK; ++r) {
+        for (int c = 0; c < kCand && st == ABFT_OK; ++c) {
             if (hipEventRecord(e0, s) != hipSuccess) { st = ABFT_E_HIP; break; }
             st = batch_gemm(pl, c, 0, s);
             if (st) break;
             if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { st = ABFT_E_HIP; break; }
             float t = 0.f;
             if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) { st = ABFT_E_HIP; break; }
-            if (r > 0) ts.push_back(t);                // the first launch warms up
+            if (r > 0) ts[c].push_back(t);             // round 0 warms up
         }
-        if (st) break;
-        std::sort(ts.begin(), ts.end());
-        const double med = ts[ts.size() / 2];
-        if (ms) ms[c] = med;
-        if (c == 0 || med < best) { best = med; arg = c; }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (st) return st;
+    double best = 0.0;
+    int arg = 0;
+    for (int c = 0; c < kCand; ++c) {
+        std::sort(ts[c].begin(), ts[c].end());
+        const double med = ts[c][ts[c].size() / 2];
+        if (ms) ms[c] = med;
+        if (c == 0 || med < best) { best = med; arg = c; }
+    }
     if (choice) *choice = arg;
     return ABFT_OK;
 }

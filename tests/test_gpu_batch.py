@@ -379,3 +379,49 @@ def test_batch_same_sign_operands_verify_clean(dev):
              " ".join(f"{max(r.max_ratio_c, r.max_ratio_r):.3f}" for r in reps))
         for q, r in enumerate(reps):
             assert r.n_flag_c == 0 and r.n_flag_r == 0, (tile, q, r.max_ratio_c, r.max_ratio_r)
+
+
+def test_batch_padded_operand_rows(dev, orc):
+    """Operand rows padded to 64 elements (lda = ldb > k, every bfloat16 row on
+    a 128-byte line): the quantized rows are bit-exact and nothing is written
+    past k; C equals the unpadded batch's bit for bit (the same products in
+    the same k order) and lies within the oracle's bound; verification is
+    clean for the uniform and the per-problem launches."""
+    shapes = [(64, 96, 72, 32, 1), (96, 64, 200, 4, 1), (40, 48, 136, 8, 2), (128, 132, 520, 32, 2),
+              (66, 70, 1032, 1, 2), (256, 320, 64, 32, 1)]
+    note(f"padded batch of {len(shapes)} problems")
+    Bp = abft.Batch(shapes, device=dev, tau_mode=abft.ABFT_TAU_STAT, lam=LAMBDA, ld_align=64)
+    Bu = abft.Batch(shapes, device=dev, tau_mode=abft.ABFT_TAU_STAT, lam=LAMBDA)
+    refs = []
+    for q, (m, n, k, br, bc) in enumerate(shapes):
+        assert Bp.lda[q] % 64 == 0 and Bp.lda[q] >= k and Bp.A[q].stride(0) == Bp.lda[q]
+        A32 = synth.uniform(SEED + 50 + q, synth.STREAM_A, m, k, np.float32)
+        B32 = synth.uniform(SEED + 50 + q, synth.STREAM_B, k, n, np.float32)
+        for Bx in (Bp, Bu):
+            Bx.A32[q].copy_(torch.from_numpy(A32))
+            Bx.Bt32[q].copy_(torch.from_numpy(np.ascontiguousarray(B32.T)))
+        Aq, Bq = orc.to_bf16_bits(A32), orc.to_bf16_bits(B32)
+        Af, Bf = orc.encode(orc.bf16_bits_to_f64(Aq), orc.bf16_bits_to_f64(Bq), br, bc, store_f32=True)
+        C32 = orc.gemm(Af, Bf).astype(np.float32)
+        bound = k * U32 * (np.abs(Af) @ np.abs(Bf)) + U32 * np.abs(C32)
+        refs.append((Aq, Bq, C32, bound))
+    for tile in (0, abft.ABFT_BATCH_MIXED):
+        for Bx in (Bp, Bu):
+            abft.batch_quantize_encode(Bx.plan)
+            abft.batch_gemm(Bx.plan, tile)
+            abft.batch_verify(Bx.plan)
+        reps = Bp.reports()
+        for q, (m, n, k, br, bc) in enumerate(shapes):
+            note(f"padded problem {q} {shapes[q]} lda {Bp.lda[q]} tile {tile}")
+            Aq, Bq, C32, bound = refs[q]
+            a = Bp.A[q].cpu().view(torch.int16).numpy().view(np.uint16)
+            b = Bp.Bt[q].cpu().view(torch.int16).numpy().view(np.uint16)
+            assert np.array_equal(a, Aq) and np.array_equal(b, np.ascontiguousarray(Bq.T))
+            ld = Bp.lda[q]
+            for t, rows in ((Bp.A[q], m), (Bp.Bt[q], n)):
+                full = t.as_strided((rows, ld), (ld, 1))
+                assert not full[:, k:].view(torch.int16).any(), "written past k"
+            assert torch.equal(Bp.C[q], Bu.C[q]), q
+            err = np.abs(Bp.C[q].cpu().numpy().astype(np.float64) - C32)
+            assert np.all(err <= bound * 1.01 + 1e-30), (q, err.max())
+            assert reps[q].n_flag_c == 0 and reps[q].n_flag_r == 0, (q, reps[q].max_ratio_c, reps[q].max_ratio_r)
