@@ -520,7 +520,7 @@ int abft_batch_tune(const abft_batch_plan *plan, double *costs, int32_t *tiles, 
  * product timed with device events, median of reps launches (1 .. 100) after a
  * warm-up, with each uniform shape (0 .. ABFT_BATCH_TILES-1) and with the
  * plan's per-problem shapes (ABFT_BATCH_MIXED), the candidates taken in turn
- * within each round of launches (a warm-up round first); ms (host, ABFT_BATCH_TILES + 1
+ * within each sweep of launches (a warm-up sweep first); ms (host, ABFT_BATCH_TILES + 1
  * doubles, or NULL) receives the times, *choice (host, or NULL) the fastest,
  * the value to pass as `tile` to abft_batch_gemm.  The per-problem run is one
  * launch per shape, so its tiles' lower summed cost need not make it faster. */

@@ -1536,8 +1536,8 @@ int batch_tune(const abft_batch_plan *pl, double *costs, int32_t *best, hipStrea
 // with the per-problem shapes of the plan; returns the fastest.  The
 // per-problem run is one launch per shape, each with its own tail, so the
 // fastest tiles per problem need not give the fastest run.
-// Candidates timed in rounds (each once per round, in turn) after a warm-up
-// round: the device clock still rises during the first launches of a run, and
+// Candidates timed in sweeps (each once per sweep, in turn) after a warm-up
+// sweep: the device clock still rises during the first launches of a run, and
 // timing one candidate after another would favour the later ones.
 int batch_choose(const abft_batch_plan *pl, int reps, double *ms, int32_t *choice, hipStream_t s) {
     constexpr int kCand = ABFT_BATCH_MIXED + 1;
@@ -1554,7 +1554,7 @@ int batch_choose(const abft_batch_plan *pl, int reps, double *ms, int32_t *choic
             if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { st = ABFT_E_HIP; break; }
             float t = 0.f;
             if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) { st = ABFT_E_HIP; break; }
-            if (r > 0) ts[c].push_back(t);             // round 0 warms up
+            if (r > 0) ts[c].push_back(t);             // sweep 0 warms up
         }
     }
     hipEventDestroy(e0);
