@@ -830,23 +830,40 @@ __global__ __launch_bounds__(kGemmThreads, CF::BPC == 1 ? 2 : 4) void kb_gemm(co
     }
 }
 
-// Carried checksums from the staged partial products.  Unit per problem:
-// C[m+q, j] (br x n), C[i, n+c] (m x bc), corner C[m+q, n+c] (br x bc).
+// Carried checksums from the staged partial products.  Units per problem:
+// C[m+q, j0..j0+3] (br x ceil(n/4): four columns each, 16-byte loads of the
+// staged rows, whose length ld1 >= n + 3 is a multiple of 4), C[i, n+c]
+// (m x bc), corner C[m+q, n+c] (br x bc).  Each entry: its three staged terms
+// added in binary64 in order, rounded once.
+__host__ __device__ inline int64_t comb_units(int64_t m, int64_t n, int64_t br, int64_t bc) {
+    return br * ((n + 3) / 4) + m * bc + br * bc;
+}
 __global__ __launch_bounds__(kT) void kb_combine(const BatchDesc *__restrict__ d, int count, int64_t total) {
     Walk<&BatchDesc::s_comb, kT> wk(d, count, total);
     for (int64_t b0 = wk.first; b0 < wk.last; b0 += kT) {
         const BatchDesc &D = wk.at(b0);
         int64_t u = b0 - D.s_comb + threadIdx.x;
-        const int64_t br = D.br, bc = D.bc, n = D.n, m = D.m, NV = D.NV;
-        if (u < br * n) {
-            const int64_t q = u / n, j = u - q * n;
-            double s = 0.0;
+        const int64_t br = D.br, bc = D.bc, n = D.n, m = D.m, NV = D.NV, n4 = (n + 3) / 4;
+        if (u < br * n4) {
+            const int64_t q = u / n4, j0 = (u - q * n4) * 4;
+            double s[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int s3 = 0; s3 < 3; ++s3) s += (double)gp(D.S1)[(s3 * br + q) * D.ld1 + j];
-            gp(D.C)[(m + q) * D.ldc + j] = (float)s;
+            for (int s3 = 0; s3 < 3; ++s3) {
+                const v4f_ x = *(const G<v4f_> *)(gp(D.S1) + (s3 * br + q) * D.ld1 + j0);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) s[e] += (double)x[e];
+            }
+            G<float> *dst = gp(D.C) + (m + q) * D.ldc + j0;
+            if (D.cvec && j0 + 4 <= n) {
+                *(G<v4f_> *)dst = v4f_{(float)s[0], (float)s[1], (float)s[2], (float)s[3]};
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (j0 + e < n) dst[e] = (float)s[e];    // the corner columns are the third unit kind's
+            }
             continue;
         }
-        u -= br * n;
+        u -= br * n4;
         if (u < m * bc) {
             const int64_t i = u / bc, c = u - i * bc;
             double s = 0.0;
@@ -1352,7 +1369,7 @@ int batch_setup(const abft_problem *probs, const abft_batch_item *items, int cou
         w[W_ROWS] += pad_h(q.br, kRowsPerIter) + pad_h((q.br == 1 ? q.n : 0) + q.bc, kRowsPerIter) +
                      pad_h(q.br + q.bc, kRowsPerIter);
         D.s_rfin = w[W_RFIN]; w[W_RFIN] += ns > 1 ? pad_h(q.m + nbr, kT) : 0;
-        D.s_comb = w[W_COMB]; w[W_COMB] += pad_h(q.br * q.n + q.m * q.bc + q.br * q.bc, kT);
+        D.s_comb = w[W_COMB]; w[W_COMB] += pad_h(comb_units(q.m, q.n, q.br, q.bc), kT);
         D.s_vcol = w[W_VCOL]; w[W_VCOL] += pad_h(q.br * vstrips(q.n + q.bc, D.cvec), kT / kW);
         D.s_vrow = w[W_VROW]; w[W_VROW] += pad_h((q.m + q.br) * q.bc, kT);
         if (!D.cvec) ++w[W_UNALIGNED];
@@ -1557,8 +1574,8 @@ int batch_choose(const abft_batch_plan *pl, int reps, double *ms, int32_t *choic
             if (r > 0) ts[c].push_back(t);             // sweep 0 warms up
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st) return st;
     double best = 0.0;
     int arg = 0;
