@@ -91,6 +91,11 @@ template <> struct vec16<double> {
         v2 v = *(const v2 *)p;
         o[0] = v[0]; o[1] = v[1];
     }
+    // the same N values from a chunk already loaded as raw words
+    __device__ static void widen(const v4u32 &w, double *o) {
+        o[0] = __hiloint2double((int)w[1], (int)w[0]);
+        o[1] = __hiloint2double((int)w[3], (int)w[2]);
+    }
 };
 template <> struct vec16<float> {
     static constexpr int N = 4;
@@ -98,6 +103,10 @@ template <> struct vec16<float> {
         typedef float v4 __attribute__((ext_vector_type(4)));
         v4 v = *(const v4 *)p;
         o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+    }
+    __device__ static void widen(const v4u32 &w, double *o) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[q] = (double)__uint_as_float(w[q]);
     }
 };
 template <> struct vec16<uint16_t> {                 // bfloat16
@@ -111,6 +120,13 @@ template <> struct vec16<uint16_t> {                 // bfloat16
             o[2 * q + 1] = (double)bf16_to_f32((uint16_t)(v[q] >> 16));
         }
     }
+    __device__ static void widen(const v4u32 &w, double *o) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            o[2 * q] = (double)bf16_to_f32((uint16_t)(w[q] & 0xFFFFu));
+            o[2 * q + 1] = (double)bf16_to_f32((uint16_t)(w[q] >> 16));
+        }
+    }
 };
 
 template <> struct vec16<uint8_t> {                  // FP8 E4M3
@@ -119,6 +135,10 @@ template <> struct vec16<uint8_t> {                  // FP8 E4M3
         v4u32 v = *(const v4u32 *)p;
 #pragma unroll
         for (int w = 0; w < 4; ++w) e4m3x4_to_f64(v[w], o + 4 * w);
+    }
+    __device__ static void widen(const v4u32 &w, double *o) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) e4m3x4_to_f64(w[q], o + 4 * q);
     }
 };
 

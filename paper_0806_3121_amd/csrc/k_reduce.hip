@@ -288,27 +288,6 @@ __global__ __launch_bounds__(kThreads) void k_rows_finish(const double *rp, int6
 // encode kernels).  With ROW_W the weights sit in LDS as binary32, permuted so
 // that the lanes of a wave read consecutive words: lane L needs w[l0 + q] with
 // l0 = 64 V c + V L (chunk c of 64 V columns), stored at 64 V c + 64 q + L.
-// The elements of one raw 16-byte chunk of T, widened to binary64 (as vec16<T>::load).
-template <typename T> __device__ inline void widen16(const v4u32 &w, double *o);
-template <> __device__ inline void widen16<double>(const v4u32 &w, double *o) {
-    o[0] = __hiloint2double((int)w[1], (int)w[0]);
-    o[1] = __hiloint2double((int)w[3], (int)w[2]);
-}
-template <> __device__ inline void widen16<float>(const v4u32 &w, double *o) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) o[q] = (double)__uint_as_float(w[q]);
-}
-template <> __device__ inline void widen16<uint16_t>(const v4u32 &w, double *o) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        o[2 * q] = (double)bf16_to_f32((uint16_t)(w[q] & 0xFFFFu));
-        o[2 * q + 1] = (double)bf16_to_f32((uint16_t)(w[q] >> 16));
-    }
-}
-template <> __device__ inline void widen16<uint8_t>(const v4u32 &w, double *o) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) e4m3x4_to_f64(w[q], o + 4 * q);
-}
 constexpr int64_t kRowWMaxK = 16384;   // ROW_W keeps w (as binary32, 64 KB) in LDS up to this k
 constexpr int kRowThreads = 512;       // 8 waves share one copy of w
 // The rows of one block for a statistic fixed at compile time (WLDS: ROW_W
@@ -342,7 +321,7 @@ __device__ __attribute__((always_inline)) inline void row_stats_rows(const T *X,
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 double v[V];
-                widen16<T>(raw[u], v);
+                vec16<T>::widen(raw[u], v);
                 term(v, l0 + u * step, acc);
             }
         }

@@ -92,10 +92,82 @@ __global__ __launch_bounds__(kSliverThreads) void k_sliver(const TX *__restrict_
     }
 }
 
+// One checksum row (R = 1): a wave takes NR rows of X together, so that each
+// chunk of Y is read once for NR rows and NR 16-byte loads of X are in flight
+// per lane (kept raw until summed).  Per row the same sums in the same order
+// as k_sliver: each lane over its chunks in increasing k, then the butterfly.
+template <typename TX, typename TY, typename TC, int NR, int UK>
+__global__ __launch_bounds__(kSliverThreads) void k_sliver1(const TX *__restrict__ X, int64_t ldx, int64_t U,
+                                                           const TY *__restrict__ Y, int64_t K, TC *__restrict__ out,
+                                                           int64_t ou, const int *__restrict__ scale_exp,
+                                                           int accumulate) {
+    const double scale = scale_exp ? ldexp(1.0, -(scale_exp[0] + scale_exp[1])) : 1.0;
+    constexpr int VX = vec16<TX>::N, VY = vec16<TY>::N;
+    constexpr int V = VX > VY ? VX : VY;             // k per lane per step
+    const int lane = threadIdx.x % 64;
+    const int64_t wave = ((int64_t)blockIdx.x * kSliverThreads + threadIdx.x) / 64;
+    const int64_t nwaves = (int64_t)gridDim.x * kSliverThreads / 64;
+    for (int64_t u0 = wave * NR; u0 < U; u0 += nwaves * NR) {
+        double acc[NR];
+        const TX *xr[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            acc[r] = 0.0;
+            xr[r] = X + min(u0 + r, U - 1) * ldx;      // rows past U re-read the last (not stored)
+        }
+        // UK chunks of k per lane in flight (a chunk at or past K is clamped to
+        // the lane's first and not summed)
+        for (int64_t k0 = (int64_t)lane * V; k0 < K; k0 += UK * 64 * V) {
+            v4u32 xw[UK][NR][V / VX], yw[UK][V / VY];
+#pragma unroll
+            for (int c = 0; c < UK; ++c) {
+                const int64_t kc = k0 + c * 64 * V < K ? k0 + c * 64 * V : k0;
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+#pragma unroll
+                    for (int q = 0; q < V / VX; ++q) xw[c][r][q] = *(const v4u32 *)(xr[r] + kc + q * VX);
+#pragma unroll
+                for (int q = 0; q < V / VY; ++q) yw[c][q] = *(const v4u32 *)(Y + kc + q * VY);
+            }
+#pragma unroll
+            for (int c = 0; c < UK; ++c) {
+                if (k0 + c * 64 * V >= K) break;
+                double yv[V];
+#pragma unroll
+                for (int q = 0; q < V / VY; ++q) vec16<TY>::widen(yw[c][q], yv + q * VY);
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    double xv[V];
+#pragma unroll
+                    for (int q = 0; q < V / VX; ++q) vec16<TX>::widen(xw[c][r][q], xv + q * VX);
+#pragma unroll
+                    for (int q = 0; q < V; ++q) acc[r] = fma(xv[q], yv[q], acc[r]);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            double v = acc[r];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0 && u0 + r < U) store_out<TC>(out + (u0 + r) * ou, scale * v, accumulate != 0);
+        }
+    }
+}
+constexpr int kSliverRows = 4;        // rows of X per wave in k_sliver1
+constexpr int kSliverChunks = 2;      // chunks of k per lane in flight in k_sliver1
+
 template <typename TX, typename TY, typename TC>
 inline int sliver(const TX *X, int64_t ldx, int64_t U, const TY *Y, int64_t ldy, int64_t R, int64_t K, TC *out,
                   int64_t ou, int64_t os, const int *scale_exp, hipStream_t s, bool accumulate = false) {
     const int64_t waves_per_block = kSliverThreads / 64;
+    if (R == 1 && U >= 16384) {        // enough rows for a full device at kSliverRows rows per wave
+        const int64_t waves = (U + kSliverRows - 1) / kSliverRows;
+        const unsigned blocks = (unsigned)std::min<int64_t>((waves + waves_per_block - 1) / waves_per_block, 4096);
+        k_sliver1<TX, TY, TC, kSliverRows, kSliverChunks><<<blocks, kSliverThreads, 0, s>>>(X, ldx, U, Y, K, out, ou, scale_exp,
+                                                                            accumulate ? 1 : 0);
+        ABFT_LAUNCHED();
+        return ABFT_OK;
+    }
     unsigned blocks = (unsigned)std::min<int64_t>((U + waves_per_block - 1) / waves_per_block, 4096);
     for (int64_t r0 = 0; r0 < R; r0 += kSliverR) {
         int rr = (int)std::min<int64_t>(kSliverR, R - r0);
