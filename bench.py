@@ -77,7 +77,7 @@ TRAFFIC = {
     "c2b1": 40.120e9 + 0.562e9 + 2 * 0.538e9,       # k_gemm_mfma2 + two k_sliver launches
     "c2panel": 3.832e9 + 0.679e9,                   # one accumulating panel launch of k_gemm_mfma2
     "c2w": 41.595e9 + 0.680e9,                      # k_gemm_mfma2 over the weighted-checksum C_f
-    "c4": 13.728e9 + 1.121e9 + 2 * 0.539e9,         # k_gemm_lowp2 + two k_sliver launches
+    "c4": 14.040e9 + 1.120e9 + 2 * 0.538e9,         # k_gemm_lowp2 + two k_sliver1 launches
     "c5": 4.361e9 + 2.650e9 + 0.225e9 + 0.087e9,    # kb_gemm (the chosen 256 x 256 launch) + kb_combine
 }
 SEED = 20080523

@@ -267,10 +267,12 @@ int describe_gemm(const abft_problem *p, uint32_t flags, char *buf, size_t len) 
                                   : pick_main((const float *)nullptr, Mm, Nm, g.k);
         kname = pk.direct ? "k_gemm_mfma2" : "k_gemm_mfma";
     }
+    // the carried blocks' kernels: rows over the N columns (lowp: n), columns over the data rows
+    const char *sr = sliver_multirow(g.br, lowp ? g.n : g.N) ? " + k_sliver1 carried rows" : " + k_sliver carried rows";
+    const char *sc = sliver_multirow(g.bc, Mm) ? " + k_sliver1 carried columns" : " + k_sliver carried columns";
     const int n = snprintf(buf, len, "%s %s %dx%d on %lldx%lld k=%lld%s%s%s", kname, kDt[p->dtype], pk.t->bm,
-                           pk.t->bn, (long long)Mm, (long long)Nm, (long long)g.k,
-                           thin_r ? " + k_sliver carried rows" : "", (lowp && !plain) ? " + k_sliver corner" : "",
-                           thin_c ? " + k_sliver carried columns" : "");
+                           pk.t->bn, (long long)Mm, (long long)Nm, (long long)g.k, thin_r ? sr : "",
+                           (lowp && !plain) ? " + k_sliver corner" : "", thin_c ? sc : "");
     return (n < 0 || (size_t)n >= len) ? ABFT_E_ARG : ABFT_OK;
 }
 

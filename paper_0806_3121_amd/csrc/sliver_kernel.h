@@ -153,6 +153,8 @@ __global__ __launch_bounds__(kSliverThreads) void k_sliver1(const TX *__restrict
         }
     }
 }
+// k_sliver1 serves one checksum row over enough operand rows to fill the device.
+inline bool sliver_multirow(int64_t R, int64_t U) { return R == 1 && U >= 16384; }
 constexpr int kSliverRows = 4;        // rows of X per wave in k_sliver1
 constexpr int kSliverChunks = 2;      // chunks of k per lane in flight in k_sliver1
 
@@ -160,7 +162,7 @@ template <typename TX, typename TY, typename TC>
 inline int sliver(const TX *X, int64_t ldx, int64_t U, const TY *Y, int64_t ldy, int64_t R, int64_t K, TC *out,
                   int64_t ou, int64_t os, const int *scale_exp, hipStream_t s, bool accumulate = false) {
     const int64_t waves_per_block = kSliverThreads / 64;
-    if (R == 1 && U >= 16384) {        // enough rows for a full device at kSliverRows rows per wave
+    if (sliver_multirow(R, U)) {
         const int64_t waves = (U + kSliverRows - 1) / kSliverRows;
         const unsigned blocks = (unsigned)std::min<int64_t>((waves + waves_per_block - 1) / waves_per_block, 4096);
         k_sliver1<TX, TY, TC, kSliverRows, kSliverChunks><<<blocks, kSliverThreads, 0, s>>>(X, ldx, U, Y, K, out, ou, scale_exp,

@@ -149,10 +149,12 @@ def test_describe_gemm_names_kernels_and_tiles():
                                                      " + k_sliver carried rows + k_sliver carried columns")
     assert d(abft.ABFT_F64, 8192, 8192, 8192, 1, abft.ABFT_PLAIN) == "k_gemm_mfma2 f64 128x128 on 8192x8192 k=8192"
     assert d(abft.ABFT_F64, 256, 256, 250, 64) == "k_gemm_mfma f64 96x96 on 320x320 k=250"
-    assert d(abft.ABFT_F32, 16384, 8192, 32768, 1).startswith("k_gemm_mfma2 f32 256x128 on 16384x8192 k=32768")
+    # one checksum row over 16384 or more operand rows: the multi-row carried-block kernel
+    assert d(abft.ABFT_F32, 16384, 8192, 32768, 1) == ("k_gemm_mfma2 f32 256x128 on 16384x8192 k=32768"
+                                                       " + k_sliver carried rows + k_sliver1 carried columns")
     assert d(abft.ABFT_BF16, 16384, 16384, 16384, 1) == (
         "k_gemm_lowp2 bf16 256x256 on 16384x16384 k=16384"
-        " + k_sliver carried rows + k_sliver corner + k_sliver carried columns")
+        " + k_sliver1 carried rows + k_sliver corner + k_sliver1 carried columns")
     assert d(abft.ABFT_FP8_E4M3, 300, 260, 528, 1, abft.ABFT_PLAIN) == "k_gemm_lowp fp8 128x128 on 300x260 k=528"
     p = abft.problem(abft.ABFT_F64, 256, 256, 256, 1, 1)
     buf = C.create_string_buffer(16)
