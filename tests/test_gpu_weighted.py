@@ -280,6 +280,34 @@ def test_weighted_deterministic(dev):
     assert out[0] == out[1]
 
 
+def test_weighted_matrix_vector_product_many_rows(dev, orc):
+    """The matrix-vector product at the bench's row count (16384 data rows, two
+    weighted checksum block rows of 512): equal to the oracle's encoded
+    product; clean verification; one flip located and corrected."""
+    m, n, k, br, bc, fr, fc = 16384, 1, 1024, 512, 1, 2, 1
+    note("weighted matrix-vector product, 16384 rows")
+    A, B, Wr, Wc, P = make(dev, m, n, k, br, bc, fr, fc)
+    P.encode()
+    P.gemm()
+    torch.cuda.synchronize()
+    Af, Bf, Cf = wo.wproduct(A, B, Wr, Wc, br, bc)
+    clean = P.C.cpu().numpy().copy()
+    assert clean.shape == (m + fr * br, 2)
+    assert rel_err(clean, Cf) <= TOL
+    rep = P.verify()
+    assert rep.n_fail_c == 0 and rep.n_fail_r == 0
+    flip(P, 12345, 0, 57)
+    rep = P.verify()
+    st, locs = abft.wlocate(P.p, rep)
+    assert st == abft.ABFT_OK
+    assert [(l.cls, l.i, l.j) for l in locs] == [(abft.ABFT_CLS_DATA, 12345, 0)]
+    abft.wcorrect(P.p, P.C, locs, P.ws)
+    rep = P.verify()
+    assert rep.n_fail_c == 0 and rep.n_fail_r == 0
+    torch.cuda.synchronize()
+    assert rel_err(P.C.cpu().numpy(), clean) <= 1e-11
+
+
 def test_weighted_matrix_vector_product(dev, orc):
     """The protected matrix-vector product (n = 1, bc = 1, fc = 1): y_f = A_f x
     on the streaming kernel, equal to the oracle's encoded product; two flips of
